@@ -1,0 +1,235 @@
+"""Galerkin (RWG) moment matrix of the PMCHWT surface integral equation and
+plane-wave right-hand sides, written as their plain definitions.
+
+Operators (eqs. 3-7, e^{+j omega t}, G_r = exp(-j k_r R)/(4 pi R)):
+
+    L_r[m,n] = -j k_r  int int [ f_m . f_n - k_r^-2 (div f_m)(div' f_n) ] G_r dS' dS
+    K_r[m,n] =         int int   f_m(r) . [ grad G_r(r,r') x f_n(r') ]       dS' dS
+
+so that <f_m, E^scat> = eta L J - K M and <f_m, H^scat> = K J + L M / eta
+(eqs. 3-4; the printed eq. 5 has a garbled sign and the printed RWG forms
+eqs. 23-26 are not usable, so these are derived from eqs. 3-6 with the
+surface divergence theorem).  K is the principal value; its half-jump terms
+cancel in the PMCHWT sum below.
+
+PMCHWT (T-EFIE and T-MFIE of eqs. 10-11 summed over the two regions at every
+interface, with J1 = -J2, M2 = -M1 from eqs. 12-13, extended to several
+interfaces as in eq. 16): for interfaces i, j and every region r bordering
+both, with region signs s (rwg module),
+
+    Z_ij = sum_r s_ri s_rj [[ et_r L_r , -K_r ], [ K_r , L_r / et_r ]]
+
+acting on [J ; M~] with M~ = M / eta0 and et_r = eta_r / eta0 (the E-rows are
+divided by eta0, the H-rows are unchanged), so both unknowns and both rows
+carry A/m and A.  The right-hand side is b_i = -s_0i [<f, E_inc>/eta0 ;
+<f, H_inc>], non-zero only on interfaces that touch free space (region 0).
+The boundary layout is [J_1..J_E, M~_1..M~_E] in canonical edge order.
+
+Integration (the paper is silent): 7-point rule for outer and inner integrals.
+For a triangle pair that shares a vertex or whose centroids are closer than
+twice the longer of the two triangles' longest edges, (1/R - k^2 R/2)/(4 pi)
+and its gradient are integrated in closed form over the source triangle
+(potentials module) and only the remainder goes to the 7-point inner rule.
+K of a triangle with itself is zero (all three vectors lie in its plane).
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from . import potentials, quadrature
+from .rwg import RWGMesh
+
+C0 = 299792458.0
+MU0 = 4e-7 * np.pi * 1.00000000055        # CODATA 2018 magnetic constant, H/m
+ETA0 = MU0 * C0                           # free-space impedance, ohm
+
+
+def wavenumber(frequency, eps_r, mu_r):
+    """k_r = k0 sqrt(eps_r mu_r) with Im k_r <= 0 (principal branch)."""
+    k0 = 2 * np.pi * frequency / C0
+    return k0 * np.sqrt(complex(eps_r) * complex(mu_r))
+
+
+def rel_impedance(eps_r, mu_r):
+    """eta_r / eta0 = sqrt(mu_r / eps_r), principal branch."""
+    return np.sqrt(complex(mu_r) / complex(eps_r))
+
+
+def _close_pairs(mesh: RWGMesh, P: int, Qs: np.ndarray):
+    share = np.isin(mesh.triangles[Qs], mesh.triangles[P]).any(axis=1)
+    d = np.linalg.norm(mesh.centroid[Qs] - mesh.centroid[P], axis=1)
+    lim = 2.0 * np.maximum(mesh.max_edge[Qs], mesh.max_edge[P])
+    return share | (d < lim)
+
+
+def _green_remainder(k, R):
+    """G - (1/R - k^2 R/2)/(4 pi); limit -jk/(4 pi) at R = 0."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        v = (np.exp(-1j * k * R) - 1.0 + 0.5 * (k * R) ** 2) / (4 * np.pi * R)
+    return np.where(R > 0, v, -1j * k / (4 * np.pi))
+
+
+def _grad_factor_remainder(k, R):
+    """g - g_s with grad G = (r - r') g(R), g_s from (1/R - k^2 R/2)/(4 pi);
+    its product with (r - r') vanishes at R = 0."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        v = (-(1.0 + 1j * k * R) * np.exp(-1j * k * R) + 1.0 + 0.5 * (k * R) ** 2) / (4 * np.pi * R ** 3)
+    return np.where(R > 0, v, 0.0)
+
+
+def _green(k, R):
+    return np.exp(-1j * k * R) / (4 * np.pi * R)
+
+
+def _grad_factor(k, R):
+    return -(1.0 + 1j * k * R) * np.exp(-1j * k * R) / (4 * np.pi * R ** 3)
+
+
+def pair_interactions(mesh: RWGMesh, P: int, Qs: np.ndarray, k: complex):
+    """Local interactions of the three half-basis functions of test triangle P
+    with those of source triangles Qs for wavenumber k.
+
+    On triangle T the half-basis of local vertex i is (r - v_i)/(2 A_T) with
+    divergence 1/A_T; a basis function is (sign * edge length) times it.
+
+    Returns L_loc, K_loc of shape [len(Qs), 3, 3] (test local i, source local j).
+    """
+    Qs = np.asarray(Qs, dtype=np.int64)
+    w = quadrature.WEIGHTS
+    ra = mesh.qpts[P]                                    # [7, 3] outer nodes
+    rb = mesh.qpts[Qs]                                   # [nQ, 7, 3] inner nodes
+    AQ = mesh.area[Qs]
+    AP = mesh.area[P]
+    d = ra[:, None, None, :] - rb[None, :, :, :]         # [7a, nQ, 7b, 3]  r - r'
+    R = np.linalg.norm(d, axis=-1)
+    close = _close_pairs(mesh, P, Qs)
+
+    with np.errstate(divide="ignore", invalid="ignore"):
+        Gf = np.where(close[None, :, None], _green_remainder(k, R), _green(k, R))
+        gf = np.where(close[None, :, None], _grad_factor_remainder(k, R), _grad_factor(k, R))
+    wq = (w[None, None, :] * AQ[None, :, None])          # [1, nQ, 7b]
+    I_sc = np.sum(wq * Gf, axis=2)                               # [7a, nQ]
+    I_vec = np.sum((wq * Gf)[..., None] * rb[None], axis=2)      # [7a, nQ, 3]
+    g = np.sum((wq * gf)[..., None] * d, axis=2)                 # [7a, nQ, 3]
+
+    ci = np.nonzero(close)[0]
+    if len(ci):
+        V = mesh.vertices[mesh.triangles[Qs[ci]]]                # [nc, 3, 3]
+        same = (Qs[ci] == P)
+        res = potentials.triangle_integrals(ra[:, None, :], V[None, :, 0], V[None, :, 1], V[None, :, 2],
+                                            coplanar=np.broadcast_to(same[None, :], (7, len(ci))))
+        s_sc = (res["inv_r"] - 0.5 * k * k * res["r1"]) / (4 * np.pi)
+        s_vec = (res["vinv_r"] - 0.5 * k * k * res["vr1"] + res["rho"] * (res["inv_r"] - 0.5 * k * k * res["r1"])[..., None]) / (4 * np.pi)
+        s_grad = (res["grad_inv_r"] - 0.5 * k * k * res["grad_r1"]) / (4 * np.pi)
+        I_sc[:, ci] += s_sc
+        I_vec[:, ci] += s_vec
+        g[:, ci] += s_grad
+
+    pv = mesh.vertices[mesh.triangles[P]]                # [3i, 3]
+    qv = mesh.vertices[mesh.triangles[Qs]]               # [nQ, 3j, 3]
+    wa = w * AP                                          # outer weights
+    ri = ra[:, None, :] - pv[None, :, :]                 # [7a, 3i, 3] r - p_i
+    # L: (r - p_i).(I_vec - q_j I_sc) - 4/k^2 I_sc
+    vec_j = I_vec[:, :, None, :] - qv[None, :, :, :] * I_sc[:, :, None, None]   # [7a, nQ, 3j, 3]
+    dot = np.einsum("aix,aqjx->aqij", ri, vec_j)
+    integrand = dot - (4.0 / (k * k)) * I_sc[:, :, None, None]
+    L_loc = (-1j * k / (4 * AP * AQ))[:, None, None] * np.einsum("a,aqij->qij", wa, integrand)
+    # K: (r - p_i).(g x (r - q_j))
+    rj = ra[:, None, None, :] - qv[None, :, :, :]                               # [7a, nQ, 3j, 3]
+    cr = np.cross(g[:, :, None, :], rj)                                          # [7a, nQ, 3j, 3]
+    kint = np.einsum("aix,aqjx->aqij", ri, cr)
+    K_loc = (1.0 / (4 * AP * AQ))[:, None, None] * np.einsum("a,aqij->qij", wa, kint)
+    K_loc[Qs == P] = 0.0
+    return L_loc, K_loc
+
+
+def operator_rows(mesh: RWGMesh, k: complex, region: int, test_edges):
+    """Rows ``test_edges`` of L_r and K_r over all basis functions (columns in
+    canonical order), using only triangles that border ``region``."""
+    test_edges = np.asarray(test_edges, dtype=np.int64)
+    ne = mesh.n_edges
+    L = np.zeros((len(test_edges), ne), dtype=complex)
+    K = np.zeros((len(test_edges), ne), dtype=complex)
+    border = np.nonzero((mesh.tri_regions[:, 0] == region) | (mesh.tri_regions[:, 1] == region))[0]
+    edge_pos = {e: i for i, e in enumerate(test_edges)}
+    tris = sorted({int(t) for e in test_edges for t in (mesh.tri_p[e], mesh.tri_m[e])})
+    for P in tris:
+        if P not in set(border.tolist()):
+            continue
+        L_loc, K_loc = pair_interactions(mesh, P, border, k)
+        for i in range(3):
+            m = mesh.tri_edge[P, i]
+            if m not in edge_pos:
+                continue
+            sm = mesh.tri_sign[P, i] * mesh.length[m]
+            row = edge_pos[m]
+            for j in range(3):
+                n = mesh.tri_edge[border, j]
+                sn = mesh.tri_sign[border, j] * mesh.length[n]
+                np.add.at(L[row], n, sm * sn * L_loc[:, i, j])
+                np.add.at(K[row], n, sm * sn * K_loc[:, i, j])
+    return L, K
+
+
+def pmchwt_rows(mesh: RWGMesh, eps_r, mu_r, frequency, test_edges):
+    """Rows of the scaled PMCHWT matrix for the E-equations and H-equations of
+    ``test_edges``.  Returns (Z_E, Z_H), each [len(test_edges), 2 ne]."""
+    test_edges = np.asarray(test_edges, dtype=np.int64)
+    ne = mesh.n_edges
+    ZE = np.zeros((len(test_edges), 2 * ne), dtype=complex)
+    ZH = np.zeros((len(test_edges), 2 * ne), dtype=complex)
+    for r in range(len(eps_r)):
+        s = mesh.region_sign(r)
+        sm = s[test_edges]
+        if not np.any(sm) or not np.any(s):
+            continue
+        k = wavenumber(frequency, eps_r[r], mu_r[r])
+        et = rel_impedance(eps_r[r], mu_r[r])
+        L, K = operator_rows(mesh, k, r, test_edges)
+        sign = sm[:, None] * s[None, :]
+        ZE[:, :ne] += sign * et * L
+        ZE[:, ne:] += -sign * K
+        ZH[:, :ne] += sign * K
+        ZH[:, ne:] += sign * L / et
+    return ZE, ZH
+
+
+def pmchwt_dense(mesh: RWGMesh, eps_r, mu_r, frequency):
+    """The full scaled PMCHWT matrix [2 ne, 2 ne] in boundary layout."""
+    ne = mesh.n_edges
+    ZE, ZH = pmchwt_rows(mesh, eps_r, mu_r, frequency, np.arange(ne))
+    return np.concatenate([ZE, ZH], axis=0)
+
+
+def incidence(theta, phi):
+    """Propagation direction and theta-polarisation of a plane wave coming from
+    (theta, phi): k_hat = -r_hat(theta, phi), e_hat = theta_hat(theta, phi)."""
+    st, ct, sp, cp = np.sin(theta), np.cos(theta), np.sin(phi), np.cos(phi)
+    k_hat = -np.array([st * cp, st * sp, ct])
+    e_hat = np.array([ct * cp, ct * sp, -st])
+    return k_hat, e_hat
+
+
+def planewave_rhs(mesh: RWGMesh, frequency, k_hat, e_hat, E0=1.0):
+    """Scaled right-hand side [-<f,E_inc>/eta0 ; -<f,H_inc>] (eqs. 20-21 with
+    the plane wave of eq. 30 read as E_inc = e E0 exp(-j k0 k_hat.r),
+    H_inc = k_hat x E_inc / eta0), region sign of free space applied."""
+    k0 = 2 * np.pi * frequency / C0
+    k_hat = np.asarray(k_hat, dtype=float)
+    e_hat = np.asarray(e_hat, dtype=complex)
+    h_hat = np.cross(k_hat, e_hat)
+    w = quadrature.WEIGHTS
+    ne = mesh.n_edges
+    bE = np.zeros(ne, dtype=complex)
+    bH = np.zeros(ne, dtype=complex)
+    s0 = mesh.region_sign(0)
+    for side, (tri, free, sgn) in enumerate(((mesh.tri_p, mesh.free_p, 1.0), (mesh.tri_m, mesh.free_m, -1.0))):
+        pts = mesh.qpts[tri]                                           # [ne, 7, 3]
+        f = sgn * (mesh.length / (2 * mesh.area[tri]))[:, None, None] * (pts - mesh.vertices[free][:, None, :])
+        phase = E0 * np.exp(-1j * k0 * pts @ k_hat)                    # [ne, 7]
+        fe = f @ e_hat
+        fh = f @ h_hat
+        bE += mesh.area[tri] * np.sum(w * fe * phase, axis=1)
+        bH += mesh.area[tri] * np.sum(w * fh * phase, axis=1)
+    return np.concatenate([-s0 * bE / ETA0, -s0 * bH / ETA0])

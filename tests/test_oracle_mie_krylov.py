@@ -1,0 +1,101 @@
+"""Pins of the Mie series (Rayleigh limit, optical theorem, coated-sphere
+limits) and of ILU(0)/GMRES (LU limit, pattern property, direct solve)."""
+
+import numpy as np
+import pytest
+
+from oracle import krylov, mie
+
+
+def test_rayleigh_limit():
+    a, eps = 0.002, 4.0
+    k = 2 * np.pi
+    th = np.linspace(0, np.pi, 19)
+    sE, sH = mie.sphere_rcs(a, eps, th)
+    pol = abs((eps - 1) / (eps + 2)) ** 2
+    ref = 4 * np.pi * k ** 4 * a ** 6 * pol
+    assert np.allclose(sE, ref * np.cos(th) ** 2, rtol=2e-3, atol=1e-6 * ref)
+    assert np.allclose(sH, ref * np.ones_like(th), rtol=1e-3)
+
+
+def test_optical_theorem_and_angular_integral():
+    x, m = 5.0, 1.6
+    a, b = mie.coefficients_homogeneous(x, m)
+    qext, qsca = mie.efficiencies(a, b, x)
+    assert abs(qext - qsca) < 1e-10 * qext
+    g, w = np.polynomial.legendre.leggauss(400)
+    gam = np.arccos(g)
+    S1, S2 = mie.amplitudes(a, b, gam)
+    q_int = np.sum(w * (np.abs(S1) ** 2 + np.abs(S2) ** 2)) / x ** 2
+    assert abs(q_int - qsca) < 1e-9 * qsca
+    # lossy sphere absorbs
+    a, b = mie.coefficients_homogeneous(x, mie.index_from_eps(6 - 0.5j))
+    qext, qsca = mie.efficiencies(a, b, x)
+    assert qext > qsca * 1.01
+
+
+def test_coated_sphere_limits():
+    k = 2 * np.pi
+    th = np.linspace(0, np.pi, 37)
+    # transparent shell: only the core scatters
+    s1 = mie.coated_sphere_rcs(0.4, 6 - 0.5j, 0.7, 1.0, th)
+    s2 = mie.sphere_rcs(0.4, 6 - 0.5j, th)
+    assert np.allclose(s1, s2, rtol=1e-8)
+    # core of the shell material: homogeneous sphere of the outer radius
+    s1 = mie.coated_sphere_rcs(0.4, 2.56, 0.7, 2.56, th)
+    s2 = mie.sphere_rcs(0.7, 2.56, th)
+    assert np.allclose(s1, s2, rtol=1e-8)
+    # lossless coated sphere conserves energy
+    a, b = mie.coefficients_coated(k * 0.4, k * 0.7, mie.index_from_eps(6.0), mie.index_from_eps(2.56))
+    qext, qsca = mie.efficiencies(a, b, k * 0.7)
+    assert abs(qext - qsca) < 1e-9 * qext
+
+
+def _test_matrix(n, seed=3):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    return A / np.sqrt(n) + 3 * np.eye(n)
+
+
+def test_ilu0_full_pattern_is_lu_and_gmres_takes_one_step():
+    A = _test_matrix(40)
+    F = krylov.ilu0(A, np.ones_like(A, dtype=bool))
+    L = np.tril(F, -1) + np.eye(40)
+    U = np.triu(F)
+    assert np.allclose(L @ U, A, atol=1e-12)
+    b = np.arange(40) + 1j
+    x, info = krylov.gmres(lambda v: A @ v, b, lambda v: krylov.ilu_apply(F, v), restart=10, tol=1e-10)
+    assert info.converged and info.iterations == 1
+    assert np.allclose(x, np.linalg.solve(A, b), atol=1e-10)
+
+
+def test_ilu0_matches_on_pattern():
+    n = 60
+    A = _test_matrix(n)
+    rng = np.random.default_rng(7)
+    pat = rng.random((n, n)) < 0.25
+    pat |= pat.T
+    np.fill_diagonal(pat, True)
+    F = krylov.ilu0(A, pat)
+    L = np.tril(F, -1) + np.eye(n)
+    U = np.triu(F)
+    assert np.all(F[~pat] == 0)
+    assert np.allclose((L @ U)[pat], A[pat], atol=1e-12)
+
+
+def test_gmres_solves_and_reports():
+    n = 80
+    A = _test_matrix(n, seed=11)
+    b = np.exp(1j * np.arange(n))
+    x, info = krylov.gmres(lambda v: A @ v, b, restart=15, tol=1e-12, max_iters=2000)
+    assert info.converged and info.true_residual <= 1e-12
+    assert np.allclose(x, np.linalg.solve(A, b), atol=1e-10)
+    # an exact initial guess needs no iteration
+    x2, info2 = krylov.gmres(lambda v: A @ v, b, restart=15, tol=1e-10, x0=np.linalg.solve(A, b))
+    assert info2.converged and info2.iterations == 0
+    # an iteration cap reports non-convergence and the true residual
+    _, info3 = krylov.gmres(lambda v: A @ v, b, restart=5, tol=1e-14, max_iters=3)
+    assert not info3.converged and info3.iterations == 3 and info3.true_residual > 1e-14
+    # unrestarted GMRES converges in at most n steps
+    _, info4 = krylov.gmres(lambda v: A @ v, b, restart=n, tol=1e-10, max_iters=n)
+    assert info4.converged and info4.iterations <= n
