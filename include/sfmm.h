@@ -1,0 +1,192 @@
+/*
+ * sfmm.h - C interface of the MI355X (gfx950) MLFMM solver for dielectric
+ * scattering with the PMCHWT surface integral equation discretised by RWG
+ * functions in a Galerkin method of moments.
+ *
+ * Method: H. T. Chorsi, "Surface Integral Formulation with Preconditioned,
+ * Multipole-Accelerated Iterative Method Applied for the Analysis of RCS of
+ * Single and Multi-Layer Dielectric Structures", arXiv:1704.06862.
+ *   - equivalent currents J, M on every interface and their fields:   eqs. 1-7
+ *   - tangential field equations T-EFIE / T-MFIE and interface rules:  eqs. 10-13
+ *   - several interfaces / layered bodies:                              eq. 16
+ *   - RWG basis functions, Galerkin testing:                            eq. 22, "Discretization" section
+ *   - far field and RCS:                                                eqs. 27-29
+ *   - plane-wave excitation:                                            eq. 30
+ *   - MLFMM-accelerated products inside an ILU-preconditioned Krylov
+ *     solver:                                                           "Simulation Results" section
+ *
+ * Conventions (all entry points):
+ *   - time dependence exp(+j omega t); Green's function exp(-jkR)/(4 pi R);
+ *     a lossy medium has Im(eps_r) < 0.
+ *   - complex numbers are interleaved (re, im) doubles at this interface.
+ *   - unknown vectors are [n_rhs][2E] complex: E electric-current
+ *     coefficients J_1..J_E (A/m) followed by E scaled magnetic-current
+ *     coefficients M~_n = M_n / eta0 (A/m), in canonical edge order (see
+ *     sfmm_edges).  Equation vectors (right-hand sides, products) use the same
+ *     layout: the E rows hold <f_m, E>/eta0, the H rows <f_m, H>.
+ *   - canonical edges: sorted by (smaller vertex id, larger vertex id); the
+ *     basis function on edge (a, b), a < b, flows out of the triangle whose
+ *     counter-clockwise vertex order runs a -> b, into the other triangle.
+ *   - on_device = 0: vector pointers are host memory; the call copies them
+ *     and is synchronous.  on_device = 1: pointers are device memory on the
+ *     context's device, and the call is ordered on the context's stream
+ *     (sfmm_set_stream); results are ready when that stream is synchronised.
+ *   - inputs are borrowed for the duration of the call; outputs are
+ *     allocated by the caller.  A context is not thread-safe.
+ *   - every call returns an sfmm_status and never throws; on failure
+ *     sfmm_last_error(ctx) describes the error (also for a NULL ctx).
+ *   - the library owns no global GPU state except per-context allocations;
+ *     SFMM_E_DEVICE leaves the context unusable (destroy it).
+ */
+#ifndef SFMM_H
+#define SFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sfmm_ctx sfmm_ctx;
+
+typedef enum {
+    SFMM_OK = 0,
+    SFMM_E_INVALID_ARG = 1,   /* bad pointer, index, size or option          */
+    SFMM_E_MESH = 2,          /* open / non-manifold / mis-oriented mesh     */
+    SFMM_E_OOM = 3,           /* host or device allocation failed            */
+    SFMM_E_DEVICE = 4,        /* HIP error, or no usable gfx950 device       */
+    SFMM_E_NOT_CONVERGED = 5, /* iteration cap hit; best iterate returned    */
+    SFMM_E_BREAKDOWN = 6,     /* zero pivot in ILU(0) or Krylov breakdown    */
+    SFMM_E_UNSUPPORTED = 7    /* valid request outside what is implemented   */
+} sfmm_status;
+
+/* One scatterer: a closed, consistently oriented triangulated surface made
+ * of one or more interfaces between homogeneous regions (eq. 16). */
+typedef struct {
+    int32_t n_vertices;
+    const double *vertices;      /* [n_vertices][3], metres                          */
+    int32_t n_triangles;
+    const int32_t *triangles;    /* [n_triangles][3], 0-based, CCW about the normal  */
+    const int32_t *tri_regions;  /* [n_triangles][2]: region the normal points into,
+                                    region behind it; region 0 = unbounded exterior  */
+    int32_t n_regions;
+    const double *eps_r;         /* [n_regions][2] complex relative permittivity     */
+    const double *mu_r;          /* [n_regions][2] complex relative permeability     */
+    double frequency_hz;
+} sfmm_body;
+
+enum { SFMM_PREC_FP32 = 0, SFMM_PREC_BF16_SPLIT = 1, SFMM_PREC_FP64 = 2 };
+
+typedef struct {
+    double finest_box;        /* finest octree box edge in metres; 0 = 0.25 lambda0      */
+    int32_t n_levels;         /* octree levels counting the root; 0 = fewest that fit     */
+    double digits;            /* excess-bandwidth accuracy digits d0; 0 = 3              */
+    int32_t extra_multipoles; /* added to every level's truncation order                */
+    int32_t precision;        /* SFMM_PREC_*: number type of the far/near products      */
+    int32_t gmres_restart;    /* 0 = 30                                                  */
+    int32_t max_iters;        /* 0 = 1000                                                */
+    double tol;               /* relative residual target; 0 = 1e-6                      */
+    int32_t device;           /* HIP device ordinal; -1 = build host tables only        */
+    int32_t verbose;          /* 1: setup statistics to stderr; 2: also GMRES restarts  */
+    int32_t preconditioner;   /* SFMM_PRECOND_*                                          */
+} sfmm_options;
+
+/* Preconditioners of sfmm_solve: ILU(0) of the near-field matrix (default),
+ * none, or the inverses of the diagonal (same-box) blocks of the near-field
+ * matrix. */
+enum { SFMM_PRECOND_ILU0 = 0, SFMM_PRECOND_NONE = 1, SFMM_PRECOND_BLOCK_JACOBI = 2 };
+
+typedef struct {
+    int32_t converged;        /* 1 if ||b - Z x|| / ||b|| <= tol                        */
+    int32_t iterations;       /* Arnoldi steps (each one preconditioned product)        */
+    int32_t restarts;
+    double true_residual;     /* ||b - Z x|| / ||b|| at exit, recomputed explicitly     */
+    double seconds;           /* wall time of the solve                                 */
+} sfmm_solve_info;
+
+/* Fill *opt with the defaults listed above. */
+void sfmm_default_options(sfmm_options *opt);
+
+/* Validate the meshes, build RWG tables, octrees, the FP64 near-field matrix
+ * (singular terms in closed form), its ILU(0) factors and the MLFMM tables,
+ * and upload them to the device.  Bodies are independent scatterers.
+ * Errors: SFMM_E_INVALID_ARG, SFMM_E_MESH, SFMM_E_OOM, SFMM_E_DEVICE,
+ * SFMM_E_BREAKDOWN (zero ILU pivot).  On success *out owns all memory. */
+sfmm_status sfmm_setup(const sfmm_body *bodies, int32_t n_bodies, const sfmm_options *opt,
+                       sfmm_ctx **out);
+
+/* Release every host and device allocation of ctx (NULL is accepted). */
+void sfmm_destroy(sfmm_ctx *ctx);
+
+/* Message for the last failed call on ctx, or for the last failed
+ * sfmm_setup when ctx is NULL.  Valid until the next call on ctx. */
+const char *sfmm_last_error(const sfmm_ctx *ctx);
+
+/* Stream for subsequent on_device calls (hipStream_t; NULL = null stream). */
+sfmm_status sfmm_set_stream(sfmm_ctx *ctx, void *hip_stream);
+
+/* Number of unknowns 2E of a body, number of edges E. */
+sfmm_status sfmm_num_unknowns(const sfmm_ctx *ctx, int32_t body, int64_t *n_unknowns);
+
+/* Canonical edge table: [E][2] vertex ids (smaller first). */
+sfmm_status sfmm_edges(const sfmm_ctx *ctx, int32_t body, int32_t *edge_vertices);
+
+/* y = Z x for n_rhs vectors (Z: scaled PMCHWT matrix, near part exact, far
+ * part by MLFMM).  parts = 3 for the full product; 1 = near-field matrix only,
+ * 2 = far-field (MLFMM) part only (for diagnostics). */
+enum { SFMM_PART_NEAR = 1, SFMM_PART_FAR = 2, SFMM_PART_ALL = 3 };
+sfmm_status sfmm_matvec(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void *x, void *y,
+                        int32_t on_device, int32_t parts);
+
+/* y = M^-1 x with M the context's preconditioner (ILU(0) of the near-field
+ * matrix in colour ordering by default; identity for SFMM_PRECOND_NONE). */
+sfmm_status sfmm_precond(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void *x, void *y,
+                         int32_t on_device);
+
+/* Plane-wave right-hand sides (eqs. 20-21 tangential part, eq. 30): for
+ * incidence angle i, the wave arrives from direction (theta, phi) =
+ * angles[i] (radians), i.e. propagates along -r_hat(theta, phi), with
+ * E0 = 1 V/m along pol[i] * theta_hat + (1 - pol[i]) * phi_hat  (pol = 1:
+ * theta-polarised, 0: phi-polarised).  b is [n_rhs][2E] complex. */
+sfmm_status sfmm_planewave_rhs(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const double *angles,
+                               const double *pol, void *b, int32_t on_device);
+
+/* Solve Z x = b with right-preconditioned restarted GMRES(m) in FP64 and
+ * the ILU(0) preconditioner.  x0 = NULL starts from zero, otherwise from
+ * x0.  info [n_rhs] may be NULL.  Returns SFMM_E_NOT_CONVERGED (x holds the
+ * last iterate) if any right-hand side misses the tolerance. */
+sfmm_status sfmm_solve(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void *b, void *x,
+                       const void *x0, sfmm_solve_info *info, int32_t on_device);
+
+/* Bistatic RCS (eqs. 27-29): sigma[r][d] = (sigma_theta, sigma_phi) in m^2
+ * for solution r at direction theta_phi[d] (radians).  x follows on_device;
+ * theta_phi and sigma are host arrays. */
+sfmm_status sfmm_rcs(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void *x, int32_t n_dirs,
+                     const double *theta_phi, double *sigma, int32_t on_device);
+
+/* Diagnostics: rows of the FP64 near-field matrix (before the cast to the
+ * product precision), in boundary layout: out[i] = [E row; H row] of edge
+ * edges[i], each 2E complex, zero outside the near pattern.  Works on a
+ * host-only context (device = -1). */
+sfmm_status sfmm_near_rows(const sfmm_ctx *ctx, int32_t body, int32_t n_rows, const int32_t *edges,
+                           double *out);
+
+/* Diagnostics: the octree and sampling actually used. info[0..3] = levels,
+ * finest level boxes, near edge pairs, translation pairs; per region r
+ * (0 <= r < n_regions, up to 8) trunc[r*16 + l] = truncation order at level l. */
+sfmm_status sfmm_describe(const sfmm_ctx *ctx, int32_t body, int64_t *info, int32_t *trunc);
+
+/* Average GPU time in milliseconds of each stage over the products and
+ * preconditioner applications since the last reset, measured with HIP events
+ * on the context's stream: t[0] near product, t[1] aggregation, t[2] upward
+ * interpolation, t[3] translation, t[4] downward anterpolation, t[5] receive,
+ * t[6] ILU(0) solves, t[7] whole product; n[i] = number of samples.
+ * Stage timing is enabled only between sfmm_profile(ctx, 1, ...) and
+ * sfmm_profile(ctx, 0, ...); enabling resets the accumulators. */
+sfmm_status sfmm_profile(sfmm_ctx *ctx, int32_t enable, double *t, int64_t *n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFMM_H */

@@ -1,0 +1,349 @@
+// C ABI of the sfmm library (declared in include/sfmm.h).  Argument
+// validation, host setup, host <-> device staging and error capture; all
+// products, preconditioner solves and Krylov steps run in the HIP kernels.
+#include <chrono>
+#include <functional>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+
+#include "device.hpp"
+
+using namespace sfmm;
+
+struct sfmm_ctx {
+    sfmm_options opt{};
+    std::vector<std::unique_ptr<BodyHost>> bodies;
+    std::vector<std::unique_ptr<DeviceBody>> dev;
+    void *stream = nullptr;
+    std::string err;
+    bool poisoned = false;
+};
+
+namespace {
+
+thread_local std::string g_setup_error;
+
+template <typename F>
+sfmm_status guarded(sfmm_ctx *ctx, F &&fn) {
+    try {
+        if (ctx && ctx->poisoned) throw Error(SFMM_E_DEVICE, "context unusable after an earlier device error");
+        fn();
+        return SFMM_OK;
+    } catch (const Error &e) {
+        if (ctx) {
+            ctx->err = e.what();
+            if (e.code == SFMM_E_DEVICE) ctx->poisoned = true;
+        } else {
+            g_setup_error = e.what();
+        }
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        if (ctx) ctx->err = "host allocation failed";
+        else g_setup_error = "host allocation failed";
+        return SFMM_E_OOM;
+    } catch (const std::exception &e) {
+        if (ctx) ctx->err = e.what();
+        else g_setup_error = e.what();
+        return SFMM_E_INVALID_ARG;
+    }
+}
+
+const BodyHost &body_of(const sfmm_ctx *ctx, int32_t body) {
+    if (!ctx) throw Error(SFMM_E_INVALID_ARG, "NULL context");
+    if (body < 0 || body >= (int32_t)ctx->bodies.size()) throw Error(SFMM_E_INVALID_ARG, "body index out of range");
+    return *ctx->bodies[body];
+}
+
+DeviceBody &dev_of(sfmm_ctx *ctx, int32_t body) {
+    body_of(ctx, body);
+    if (ctx->dev.empty() || !ctx->dev[body])
+        throw Error(SFMM_E_INVALID_ARG, "context was built with device = -1 (host tables only)");
+    return *ctx->dev[body];
+}
+
+// RAII staging buffer for host pointers
+struct Staged {
+    void *p = nullptr;
+    explicit Staged(size_t bytes) : p(device_alloc(bytes)) {}
+    ~Staged() { device_free(p); }
+};
+
+}  // namespace
+
+extern "C" {
+
+void sfmm_default_options(sfmm_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->finest_box = 0.0;
+    o->n_levels = 0;
+    o->digits = 3.0;
+    o->extra_multipoles = 2;
+    o->precision = SFMM_PREC_FP32;
+    o->gmres_restart = 30;
+    o->max_iters = 1000;
+    o->tol = 1e-6;
+    o->device = 0;
+    o->verbose = 0;
+    o->preconditioner = SFMM_PRECOND_ILU0;
+}
+
+sfmm_status sfmm_setup(const sfmm_body *bodies, int32_t n_bodies, const sfmm_options *opt, sfmm_ctx **out) {
+    return guarded(nullptr, [&] {
+        if (!out) throw Error(SFMM_E_INVALID_ARG, "out is NULL");
+        *out = nullptr;
+        if (!bodies || n_bodies <= 0) throw Error(SFMM_E_INVALID_ARG, "no bodies");
+        auto ctx = std::make_unique<sfmm_ctx>();
+        if (opt) ctx->opt = *opt;
+        else sfmm_default_options(&ctx->opt);
+        sfmm_options &o = ctx->opt;
+        if (o.gmres_restart <= 0) o.gmres_restart = 30;
+        if (o.max_iters <= 0) o.max_iters = 1000;
+        if (!(o.tol > 0)) o.tol = 1e-6;
+        if (o.precision != SFMM_PREC_FP32 && o.precision != SFMM_PREC_FP64 && o.precision != SFMM_PREC_BF16_SPLIT)
+            throw Error(SFMM_E_INVALID_ARG, "unknown precision");
+        if (o.extra_multipoles < 0 || o.extra_multipoles > 64) throw Error(SFMM_E_INVALID_ARG, "extra_multipoles out of range");
+        if (o.preconditioner < 0 || o.preconditioner > 2) throw Error(SFMM_E_INVALID_ARG, "unknown preconditioner");
+        if (o.device >= 0) check_device(o.device);
+        for (int32_t i = 0; i < n_bodies; ++i) {
+            auto t0 = std::chrono::steady_clock::now();
+            auto bh = std::make_unique<BodyHost>();
+            bh->mesh = build_mesh(bodies[i]);
+            bh->oct = build_octree(bh->mesh, o.finest_box, o.n_levels, o.digits, o.extra_multipoles);
+            auto t1 = std::chrono::steady_clock::now();
+            bh->near = fill_near(bh->mesh, bh->oct);
+            auto t2 = std::chrono::steady_clock::now();
+            if (o.preconditioner == SFMM_PRECOND_ILU0) bh->ilu = factor_ilu(bh->mesh, bh->oct, bh->near);
+            else if (o.preconditioner == SFMM_PRECOND_BLOCK_JACOBI) bh->ilu = factor_block_jacobi(bh->mesh, bh->oct, bh->near);
+            bh->precond = o.preconditioner;
+            auto t3 = std::chrono::steady_clock::now();
+            for (const RegionTree &rt : bh->oct.regions) bh->tables.push_back(build_tables(bh->mesh, bh->oct, rt));
+            auto t4 = std::chrono::steady_clock::now();
+            if (o.verbose) {
+                auto s = [](auto a, auto b) { return std::chrono::duration<double>(b - a).count(); };
+                std::fprintf(stderr,
+                             "sfmm: body %d: %d edges, %d levels, %d finest boxes, %lld near pairs, %lld translation "
+                             "pairs; octree %.2fs near %.2fs ilu %.2fs tables %.2fs\n",
+                             i, bh->mesh.ne, bh->oct.nlev, bh->oct.nb, (long long)bh->oct.near_pairs,
+                             (long long)bh->oct.trans_pairs, s(t0, t1), s(t1, t2), s(t2, t3), s(t3, t4));
+            }
+            ctx->bodies.push_back(std::move(bh));
+        }
+        if (o.device >= 0) {
+            for (auto &bh : ctx->bodies) ctx->dev.push_back(make_device_body(*bh, o.precision, o.device, ctx->stream));
+        }
+        *out = ctx.release();
+    });
+}
+
+void sfmm_destroy(sfmm_ctx *ctx) {
+    if (!ctx) return;
+    try {
+        ctx->dev.clear();
+    } catch (...) {
+    }
+    delete ctx;
+}
+
+const char *sfmm_last_error(const sfmm_ctx *ctx) { return ctx ? ctx->err.c_str() : g_setup_error.c_str(); }
+
+sfmm_status sfmm_set_stream(sfmm_ctx *ctx, void *stream) {
+    return guarded(ctx, [&] {
+        if (!ctx) throw Error(SFMM_E_INVALID_ARG, "NULL context");
+        ctx->stream = stream;
+        for (auto &d : ctx->dev)
+            if (d) d->set_stream(stream);
+    });
+}
+
+sfmm_status sfmm_num_unknowns(const sfmm_ctx *ctx, int32_t body, int64_t *n) {
+    return guarded(const_cast<sfmm_ctx *>(ctx), [&] {
+        const BodyHost &b = body_of(ctx, body);
+        if (!n) throw Error(SFMM_E_INVALID_ARG, "NULL output");
+        *n = 2 * (int64_t)b.mesh.ne;
+    });
+}
+
+sfmm_status sfmm_edges(const sfmm_ctx *ctx, int32_t body, int32_t *ev) {
+    return guarded(const_cast<sfmm_ctx *>(ctx), [&] {
+        const BodyHost &b = body_of(ctx, body);
+        if (!ev) throw Error(SFMM_E_INVALID_ARG, "NULL output");
+        for (int e = 0; e < b.mesh.ne; ++e) {
+            ev[2 * e] = b.mesh.ev[e][0];
+            ev[2 * e + 1] = b.mesh.ev[e][1];
+        }
+    });
+}
+
+static void vector_call(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void *x, void *y, int32_t on_device,
+                        const std::function<void(DeviceBody &, const void *, void *)> &fn) {
+    DeviceBody &d = dev_of(ctx, body);
+    if (n_rhs <= 0 || !x || !y) throw Error(SFMM_E_INVALID_ARG, "bad vector arguments");
+    const size_t bytes = (size_t)n_rhs * 2 * ctx->bodies[body]->mesh.ne * 2 * sizeof(double);
+    if (on_device) {
+        fn(d, x, y);
+    } else {
+        Staged dx(bytes), dy(bytes);
+        copy_h2d(dx.p, x, bytes, ctx->stream);
+        fn(d, dx.p, dy.p);
+        copy_d2h(y, dy.p, bytes, ctx->stream);
+    }
+}
+
+sfmm_status sfmm_matvec(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void *x, void *y, int32_t on_device,
+                        int32_t parts) {
+    return guarded(ctx, [&] {
+        if (parts < 1 || parts > 3) throw Error(SFMM_E_INVALID_ARG, "parts must be 1, 2 or 3");
+        vector_call(ctx, body, n_rhs, x, y, on_device,
+                    [&](DeviceBody &d, const void *a, void *b) { d.matvec(n_rhs, a, b, parts); });
+    });
+}
+
+sfmm_status sfmm_precond(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void *x, void *y, int32_t on_device) {
+    return guarded(ctx, [&] {
+        vector_call(ctx, body, n_rhs, x, y, on_device,
+                    [&](DeviceBody &d, const void *a, void *b) { d.precond(n_rhs, a, b); });
+    });
+}
+
+sfmm_status sfmm_planewave_rhs(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const double *angles, const double *pol,
+                               void *b, int32_t on_device) {
+    return guarded(ctx, [&] {
+        DeviceBody &d = dev_of(ctx, body);
+        if (n_rhs <= 0 || !angles || !b) throw Error(SFMM_E_INVALID_ARG, "bad arguments");
+        const size_t bytes = (size_t)n_rhs * 2 * ctx->bodies[body]->mesh.ne * 2 * sizeof(double);
+        if (on_device) {
+            d.planewave_rhs(n_rhs, angles, pol, b);
+        } else {
+            Staged db(bytes);
+            d.planewave_rhs(n_rhs, angles, pol, db.p);
+            copy_d2h(b, db.p, bytes, ctx->stream);
+        }
+    });
+}
+
+sfmm_status sfmm_solve(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void *b, void *x, const void *x0,
+                       sfmm_solve_info *info, int32_t on_device) {
+    return guarded(ctx, [&] {
+        DeviceBody &d = dev_of(ctx, body);
+        if (n_rhs <= 0 || !b || !x) throw Error(SFMM_E_INVALID_ARG, "bad arguments");
+        const sfmm_options &o = ctx->opt;
+        const size_t bytes = (size_t)n_rhs * 2 * ctx->bodies[body]->mesh.ne * 2 * sizeof(double);
+        if (on_device) {
+            d.solve(n_rhs, b, x, x0, o.gmres_restart, o.max_iters, o.tol, info, o.verbose);
+        } else {
+            Staged db(bytes), dx(bytes);
+            std::unique_ptr<Staged> dx0;
+            copy_h2d(db.p, b, bytes, ctx->stream);
+            if (x0) {
+                dx0 = std::make_unique<Staged>(bytes);
+                copy_h2d(dx0->p, x0, bytes, ctx->stream);
+            }
+            try {
+                d.solve(n_rhs, db.p, dx.p, dx0 ? dx0->p : nullptr, o.gmres_restart, o.max_iters, o.tol, info,
+                        o.verbose);
+            } catch (const Error &e) {
+                if (e.code == SFMM_E_NOT_CONVERGED) copy_d2h(x, dx.p, bytes, ctx->stream);
+                throw;
+            }
+            copy_d2h(x, dx.p, bytes, ctx->stream);
+        }
+    });
+}
+
+sfmm_status sfmm_rcs(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void *x, int32_t n_dirs,
+                     const double *theta_phi, double *sigma, int32_t on_device) {
+    return guarded(ctx, [&] {
+        DeviceBody &d = dev_of(ctx, body);
+        if (n_rhs <= 0 || n_dirs <= 0 || !x || !theta_phi || !sigma) throw Error(SFMM_E_INVALID_ARG, "bad arguments");
+        const size_t bytes = (size_t)n_rhs * 2 * ctx->bodies[body]->mesh.ne * 2 * sizeof(double);
+        if (on_device) {
+            d.rcs(n_rhs, x, n_dirs, theta_phi, sigma);
+        } else {
+            Staged dx(bytes);
+            copy_h2d(dx.p, x, bytes, ctx->stream);
+            d.rcs(n_rhs, dx.p, n_dirs, theta_phi, sigma);
+        }
+    });
+}
+
+sfmm_status sfmm_near_rows(const sfmm_ctx *ctx, int32_t body, int32_t n_rows, const int32_t *edges, double *out) {
+    return guarded(const_cast<sfmm_ctx *>(ctx), [&] {
+        const BodyHost &b = body_of(ctx, body);
+        if (n_rows <= 0 || !edges || !out) throw Error(SFMM_E_INVALID_ARG, "bad arguments");
+        const int ne = b.mesh.ne;
+        const Octree &o = b.oct;
+        const size_t row_len = (size_t)2 * ne * 2;  // doubles per row
+        std::memset(out, 0, sizeof(double) * row_len * 2 * n_rows);
+        // box of every internal position
+        std::vector<int> box_of(ne);
+        for (int bx = 0; bx < o.nb; ++bx)
+            for (int p = o.bstart[bx]; p < o.bstart[bx + 1]; ++p) box_of[p] = bx;
+        for (int i = 0; i < n_rows; ++i) {
+            int e = edges[i];
+            if (e < 0 || e >= ne) throw Error(SFMM_E_INVALID_ARG, "edge index out of range");
+            int p = o.pos[e];
+            int bx = box_of[p];
+            int row = p - o.bstart[bx];
+            int ncol = b.near.col_ptr[bx + 1] - b.near.col_ptr[bx];
+            double *rE = out + (size_t)(2 * i) * row_len;
+            double *rH = out + (size_t)(2 * i + 1) * row_len;
+            for (int c = 0; c < ncol; ++c) {
+                int n = o.order[b.near.cols[b.near.col_ptr[bx] + c]];
+                int64_t idx = b.near.val_ptr[bx] + (int64_t)row * ncol + c;
+                cd A = b.near.A[idx], B = b.near.B[idx], C = b.near.C[idx];
+                rE[2 * n] = A.real();
+                rE[2 * n + 1] = A.imag();
+                rE[2 * (ne + n)] = -B.real();
+                rE[2 * (ne + n) + 1] = -B.imag();
+                rH[2 * n] = B.real();
+                rH[2 * n + 1] = B.imag();
+                rH[2 * (ne + n)] = C.real();
+                rH[2 * (ne + n) + 1] = C.imag();
+            }
+        }
+    });
+}
+
+sfmm_status sfmm_describe(const sfmm_ctx *ctx, int32_t body, int64_t *info, int32_t *trunc) {
+    return guarded(const_cast<sfmm_ctx *>(ctx), [&] {
+        const BodyHost &b = body_of(ctx, body);
+        if (info) {
+            info[0] = b.oct.nlev;
+            info[1] = b.oct.nb;
+            info[2] = b.oct.near_pairs;
+            info[3] = b.oct.trans_pairs;
+        }
+        if (trunc) {
+            for (int i = 0; i < 8 * 16; ++i) trunc[i] = 0;
+            for (const RegionTree &rt : b.oct.regions) {
+                if (rt.region >= 8) continue;
+                for (size_t l = 0; l < rt.levels_L.size() && l < 16; ++l) trunc[rt.region * 16 + l] = rt.levels_L[l];
+            }
+        }
+    });
+}
+
+sfmm_status sfmm_profile(sfmm_ctx *ctx, int32_t enable, double *t, int64_t *n) {
+    return guarded(ctx, [&] {
+        if (!ctx) throw Error(SFMM_E_INVALID_ARG, "NULL context");
+        StageTimes acc;
+        for (auto &d : ctx->dev) {
+            if (!d) continue;
+            StageTimes s = d->times();
+            for (int i = 0; i < 8; ++i) {
+                acc.ms[i] += s.ms[i];
+                acc.n[i] += s.n[i];
+            }
+            d->profile(enable != 0);
+        }
+        for (int i = 0; i < 8; ++i) {
+            if (t) t[i] = acc.n[i] ? acc.ms[i] / acc.n[i] : 0.0;
+            if (n) n[i] = acc.n[i];
+        }
+    });
+}
+
+}  // extern "C"

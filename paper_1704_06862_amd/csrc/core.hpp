@@ -1,0 +1,179 @@
+// Host-side data structures of the sfmm library: mesh and RWG table, octree,
+// FP64 near-field matrix, ILU(0) factors and MLFMM tables.  Everything here
+// is built once by sfmm_setup and then uploaded to the GPU.
+#pragma once
+
+#include <array>
+#include <complex>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/sfmm.h"
+
+namespace sfmm {
+
+using cd = std::complex<double>;
+constexpr double PI = 3.14159265358979323846;
+constexpr double C0 = 299792458.0;                       // m/s
+constexpr double MU0 = 4e-7 * PI * 1.00000000055;        // H/m (CODATA 2018)
+constexpr double ETA0 = MU0 * C0;                        // ohm
+
+struct Error : std::runtime_error {
+    sfmm_status code;
+    Error(sfmm_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+using V3 = std::array<double, 3>;
+inline V3 operator-(const V3 &a, const V3 &b) { return {a[0] - b[0], a[1] - b[1], a[2] - b[2]}; }
+inline V3 operator+(const V3 &a, const V3 &b) { return {a[0] + b[0], a[1] + b[1], a[2] + b[2]}; }
+inline V3 operator*(double s, const V3 &a) { return {s * a[0], s * a[1], s * a[2]}; }
+inline double dot(const V3 &a, const V3 &b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+inline V3 cross(const V3 &a, const V3 &b) {
+    return {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+}
+inline double norm(const V3 &a) { return std::sqrt(dot(a, a)); }
+
+// Seven-point degree-5 triangle rule (Radon): barycentric nodes and weights.
+struct TriRule {
+    double bary[7][3];
+    double w[7];
+    TriRule();
+};
+const TriRule &tri_rule();
+
+// ---------------------------------------------------------------------------
+// Mesh and RWG edges (one body).
+struct Mesh {
+    int nv = 0, nt = 0, nr = 0, ne = 0;
+    std::vector<V3> V;
+    std::vector<std::array<int, 3>> T;
+    std::vector<std::array<int, 2>> TR;   // (front region, back region)
+    std::vector<cd> eps, mu, k, eta;       // per region; eta relative to eta0
+    double freq = 0, k0 = 0;
+    // triangles
+    std::vector<double> area, maxedge;
+    std::vector<V3> normal, centroid;
+    std::vector<std::array<V3, 7>> qp;     // quadrature nodes
+    // edges, canonical order
+    std::vector<std::array<int, 2>> ev;    // (min, max) vertex ids
+    std::vector<int> tp, tm, fp, fm;       // T+, T-, free vertices
+    std::vector<double> len;
+    std::vector<std::array<int, 2>> ereg;  // (front, back) region of the interface
+    // per triangle and local vertex i: opposite edge and sign of its basis there
+    std::vector<std::array<int, 3>> tri_edge;
+    std::vector<std::array<int, 3>> tri_sign;
+    int region_sign(int e, int r) const {
+        return ereg[e][0] == r ? 1 : (ereg[e][1] == r ? -1 : 0);
+    }
+};
+
+Mesh build_mesh(const sfmm_body &b);
+
+// ---------------------------------------------------------------------------
+// Octree.  Finest boxes are stored in ILU (colour, Morton) order; the
+// internal unknown order is box by box, canonical edge order inside a box.
+struct LevelBoxes {               // boxes of one region at one level
+    double a = 0;                 // box edge
+    std::vector<std::array<int, 3>> key;
+    std::vector<int> parent;      // index into level - 1 (levels >= 3)
+    std::vector<int> child_slot;  // 0..7: octant of this box in its parent
+    // children of each box (CSR into level + 1), for the downward pass
+    std::vector<int> child_ptr, child_idx;
+    // interaction list (CSR): source box index and offset id (dx+3)*49+(dy+3)*7+(dz+3)
+    std::vector<int> il_ptr, il_src, il_off;
+};
+
+struct RegionTree {               // MLFMM structure of one region
+    int region = 0;
+    std::vector<int> levels_L;    // truncation order per level (index = level)
+    // finest level: boxes that contain edges of this region
+    std::vector<int> fbox;        // finest-box id (global) of every region box
+    std::vector<int> edge_ptr;    // CSR over region boxes -> positions in edge lists
+    std::vector<int> edge_pos;    // internal positions of the region's edges
+    std::vector<int> edge_sign;   // region sign of those edges
+    std::vector<LevelBoxes> lev;  // index = level (0, 1 unused)
+};
+
+struct Octree {
+    int nlev = 0, f = 0;          // levels counting the root, finest level index
+    double a_f = 0;
+    V3 corner{};
+    std::vector<std::array<int, 3>> ekey;    // finest key per canonical edge
+    int nb = 0;
+    std::vector<std::array<int, 3>> bkey;    // per finest box
+    std::vector<int> bcolour;
+    std::array<int, 9> colour_ptr{};
+    std::vector<int> bstart;                 // [nb + 1] internal positions
+    std::vector<int> order;                  // internal position -> canonical edge
+    std::vector<int> pos;                    // canonical edge -> internal position
+    std::vector<int> nbr_ptr, nbr_idx;       // neighbour boxes (incl. self), ascending
+    std::vector<RegionTree> regions;
+    int64_t near_pairs = 0, trans_pairs = 0;
+};
+
+Octree build_octree(const Mesh &m, double finest_box, int n_levels, double digits, int extra);
+
+// ---------------------------------------------------------------------------
+// Near-field matrix in box-ELL layout: the rows of finest box b are its edges
+// (n_b rows); its columns are the edges of its neighbour boxes in nbr order
+// (nc_b columns).  Each edge pair holds the three distinct complex entries of
+// the 2x2 PMCHWT block [[A, -B], [B, C]] (scaled system).
+struct NearMatrix {
+    std::vector<int64_t> val_ptr;   // [nb + 1] offset of box b's first entry
+    std::vector<int> col_ptr;       // [nb + 1] offset into cols
+    std::vector<int> cols;          // internal positions
+    std::vector<cd> A, B, C;
+};
+
+NearMatrix fill_near(const Mesh &m, const Octree &o);
+
+// ILU(0) of the near matrix in box-block form, folded for the solves:
+//   forward : z_I = Linv_II v_I - sum_{K<I} (Linv_II L_IK) z_K
+//   backward: w_I = Uinv_II z_I - sum_{J>I} (Uinv_II U_IJ) w_J
+// Each box row is a dense [2 n_I][2 nc] complex block over its own unknowns
+// (first) and the unknowns of the lower (forward) or upper (backward)
+// neighbour boxes; unknown 2p is J and 2p+1 is M~ of internal position p.
+struct IluFactors {
+    std::vector<int> fwd_col_ptr, fwd_cols;   // per box: internal positions (own box first)
+    std::vector<int> bwd_col_ptr, bwd_cols;
+    std::vector<int64_t> fwd_ptr, bwd_ptr;    // value offsets
+    std::vector<cd> fwd, bwd;                 // row-major [2n][2nc]
+};
+
+IluFactors factor_ilu(const Mesh &m, const Octree &o, const NearMatrix &Z);
+// Block-Jacobi: forward rows hold the inverse of each same-box diagonal block
+// of the near matrix, backward rows the identity.
+IluFactors factor_block_jacobi(const Mesh &m, const Octree &o, const NearMatrix &Z);
+
+// ---------------------------------------------------------------------------
+// MLFMM sampling and tables for one region.
+struct Sampling {
+    int L = 0, nth = 0, nph = 0, K = 0;
+    std::vector<double> x, wx;        // Gauss-Legendre nodes in cos(theta), ascending theta
+    std::vector<double> w;            // [K] quadrature weight (theta-major)
+    std::vector<V3> khat, th, ph;     // [K]
+};
+Sampling make_sampling(int L);
+
+struct RegionTables {
+    cd k, eta;                        // wavenumber, relative impedance
+    bool lossy = false;               // Im k != 0: receive patterns stored separately
+    std::vector<Sampling> samp;       // per level (2..f)
+    std::vector<cd> tx;               // [n_region_edges][2][K_f] transmit patterns (theta, phi)
+    std::vector<cd> rx;               // same for receive when lossy
+    std::vector<std::vector<cd>> trans;     // per level: [343][K] C_r * w_k * T_L(k; X)
+    std::vector<std::vector<double>> ipA, ipB, ipD;  // per level l (l -> l-1 transition, stored at child level l)
+    std::vector<std::vector<cd>> shift_up, shift_dn; // per level l: [8][K_{l-1}]
+};
+
+RegionTables build_tables(const Mesh &m, const Octree &o, const RegionTree &rt);
+
+// Incident plane-wave right-hand side in boundary layout ([2E], scaled).
+void planewave_rhs(const Mesh &m, double theta, double phi, double pol, cd *b);
+
+// Far-field transforms for RCS: F(r) for one solution in boundary layout.
+void far_field(const Mesh &m, const cd *x, double theta, double phi, cd *Fth, cd *Fph);
+
+}  // namespace sfmm

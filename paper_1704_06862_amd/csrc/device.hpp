@@ -1,0 +1,52 @@
+// Interface between the host core / C ABI and the HIP implementation.
+#pragma once
+
+#include <memory>
+
+#include "core.hpp"
+
+namespace sfmm {
+
+// Everything built on the host for one body.
+struct BodyHost {
+    Mesh mesh;
+    Octree oct;
+    NearMatrix near;
+    IluFactors ilu;
+    std::vector<RegionTables> tables;   // parallel to oct.regions
+    int precond = SFMM_PRECOND_ILU0;
+};
+
+struct StageTimes {
+    double ms[8] = {0};
+    int64_t n[8] = {0};
+};
+
+// Device-resident body.  Vectors at this interface are complex FP64 in the
+// boundary layout ([n_rhs][2E], J then M~) on the device unless noted.
+class DeviceBody {
+  public:
+    virtual ~DeviceBody() = default;
+    virtual void matvec(int n_rhs, const void *x_dev, void *y_dev, int parts) = 0;
+    virtual void precond(int n_rhs, const void *x_dev, void *y_dev) = 0;
+    virtual void solve(int n_rhs, const void *b_dev, void *x_dev, const void *x0_dev, int restart,
+                       int max_iters, double tol, sfmm_solve_info *info, int verbose) = 0;
+    virtual void planewave_rhs(int n_rhs, const double *angles_host, const double *pol_host, void *b_dev) = 0;
+    virtual void rcs(int n_rhs, const void *x_dev, int n_dirs, const double *theta_phi_host, double *sigma_host) = 0;
+    virtual void set_stream(void *stream) = 0;
+    virtual void profile(bool enable) = 0;
+    virtual StageTimes times() const = 0;
+    virtual int64_t device_bytes() const = 0;
+};
+
+std::unique_ptr<DeviceBody> make_device_body(const BodyHost &h, int precision, int device, void *stream);
+
+// HIP helpers used by the C ABI for host <-> device staging.
+void *device_alloc(size_t bytes);
+void device_free(void *p);
+void copy_h2d(void *dst, const void *src, size_t bytes, void *stream);
+void copy_d2h(void *dst, const void *src, size_t bytes, void *stream);
+void stream_sync(void *stream);
+void check_device(int device);
+
+}  // namespace sfmm

@@ -1,0 +1,145 @@
+// Mesh validation and the RWG edge table (eq. 22 and Fig. 4 of the paper).
+//
+// Basis n on edge (a, b), a < b: f_n = +l/(2A+) (r - v+) on T+ (the triangle
+// whose CCW order runs a -> b), f_n = -l/(2A-) (r - v-) on T-.  Its divergence
+// is +l/A+ and -l/A-, so every basis function carries zero net charge.
+#include <algorithm>
+#include <cmath>
+#include <map>
+
+#include "core.hpp"
+
+namespace sfmm {
+
+TriRule::TriRule() {
+    const double s15 = std::sqrt(15.0);
+    const double a1 = (6.0 - s15) / 21.0, b1 = (9.0 + 2.0 * s15) / 21.0;
+    const double a2 = (6.0 + s15) / 21.0, b2 = (9.0 - 2.0 * s15) / 21.0;
+    const double w0 = 9.0 / 40.0, w1 = (155.0 - s15) / 1200.0, w2 = (155.0 + s15) / 1200.0;
+    const double nodes[7][3] = {{1.0 / 3, 1.0 / 3, 1.0 / 3}, {a1, a1, b1}, {a1, b1, a1}, {b1, a1, a1},
+                                {a2, a2, b2}, {a2, b2, a2}, {b2, a2, a2}};
+    const double ws[7] = {w0, w1, w1, w1, w2, w2, w2};
+    for (int i = 0; i < 7; ++i) {
+        for (int j = 0; j < 3; ++j) bary[i][j] = nodes[i][j];
+        w[i] = ws[i];
+    }
+}
+
+const TriRule &tri_rule() {
+    static const TriRule r;
+    return r;
+}
+
+Mesh build_mesh(const sfmm_body &b) {
+    Mesh m;
+    if (b.n_vertices < 4 || b.n_triangles < 4 || !b.vertices || !b.triangles || !b.tri_regions)
+        throw Error(SFMM_E_INVALID_ARG, "body needs vertices, triangles and tri_regions");
+    if (b.n_regions < 2 || !b.eps_r || !b.mu_r) throw Error(SFMM_E_INVALID_ARG, "body needs >= 2 regions with eps_r, mu_r");
+    if (!(b.frequency_hz > 0)) throw Error(SFMM_E_INVALID_ARG, "frequency must be positive");
+    m.nv = b.n_vertices;
+    m.nt = b.n_triangles;
+    m.nr = b.n_regions;
+    m.freq = b.frequency_hz;
+    m.k0 = 2 * PI * m.freq / C0;
+    m.V.resize(m.nv);
+    for (int i = 0; i < m.nv; ++i)
+        for (int j = 0; j < 3; ++j) m.V[i][j] = b.vertices[3 * i + j];
+    m.T.resize(m.nt);
+    m.TR.resize(m.nt);
+    for (int t = 0; t < m.nt; ++t) {
+        for (int j = 0; j < 3; ++j) {
+            int v = b.triangles[3 * t + j];
+            if (v < 0 || v >= m.nv) throw Error(SFMM_E_MESH, "triangle references a missing vertex");
+            m.T[t][j] = v;
+        }
+        if (m.T[t][0] == m.T[t][1] || m.T[t][1] == m.T[t][2] || m.T[t][0] == m.T[t][2])
+            throw Error(SFMM_E_MESH, "triangle with repeated vertex");
+        for (int j = 0; j < 2; ++j) {
+            int r = b.tri_regions[2 * t + j];
+            if (r < 0 || r >= m.nr) throw Error(SFMM_E_MESH, "triangle region label out of range");
+            m.TR[t][j] = r;
+        }
+        if (m.TR[t][0] == m.TR[t][1]) throw Error(SFMM_E_MESH, "triangle separates a region from itself");
+    }
+    m.eps.resize(m.nr);
+    m.mu.resize(m.nr);
+    m.k.resize(m.nr);
+    m.eta.resize(m.nr);
+    for (int r = 0; r < m.nr; ++r) {
+        m.eps[r] = cd(b.eps_r[2 * r], b.eps_r[2 * r + 1]);
+        m.mu[r] = cd(b.mu_r[2 * r], b.mu_r[2 * r + 1]);
+        if (std::abs(m.eps[r]) == 0 || std::abs(m.mu[r]) == 0) throw Error(SFMM_E_INVALID_ARG, "zero eps_r or mu_r");
+        // principal square roots: Im k <= 0 for passive media under exp(+j w t)
+        m.k[r] = m.k0 * std::sqrt(m.eps[r] * m.mu[r]);
+        m.eta[r] = std::sqrt(m.mu[r] / m.eps[r]);
+    }
+
+    const TriRule &q = tri_rule();
+    m.area.resize(m.nt);
+    m.maxedge.resize(m.nt);
+    m.normal.resize(m.nt);
+    m.centroid.resize(m.nt);
+    m.qp.resize(m.nt);
+    for (int t = 0; t < m.nt; ++t) {
+        const V3 &p0 = m.V[m.T[t][0]], &p1 = m.V[m.T[t][1]], &p2 = m.V[m.T[t][2]];
+        V3 c = cross(p1 - p0, p2 - p0);
+        double n2 = norm(c);
+        if (!(n2 > 0)) throw Error(SFMM_E_MESH, "degenerate triangle");
+        m.area[t] = 0.5 * n2;
+        m.normal[t] = (1.0 / n2) * c;
+        m.centroid[t] = (1.0 / 3.0) * (p0 + p1 + p2);
+        m.maxedge[t] = std::max({norm(p1 - p0), norm(p2 - p1), norm(p0 - p2)});
+        for (int i = 0; i < 7; ++i)
+            m.qp[t][i] = q.bary[i][0] * p0 + q.bary[i][1] * p1 + q.bary[i][2] * p2;
+    }
+
+    // directed edges: local vertex i is free for the edge (i+1) -> (i+2)
+    struct Side { int tri = -1, free = -1, local = -1; };
+    std::map<std::pair<int, int>, std::pair<Side, Side>> edges;  // (plus, minus)
+    for (int t = 0; t < m.nt; ++t) {
+        for (int i = 0; i < 3; ++i) {
+            int x = m.T[t][(i + 1) % 3], y = m.T[t][(i + 2) % 3];
+            auto key = std::make_pair(std::min(x, y), std::max(x, y));
+            auto &e = edges[key];
+            Side &s = (x < y) ? e.first : e.second;
+            if (s.tri >= 0)
+                throw Error(SFMM_E_MESH, "edge traversed twice in one direction (non-manifold, mis-oriented "
+                                         "or a junction edge, which this build does not support)");
+            s.tri = t;
+            s.free = m.T[t][i];
+            s.local = i;
+        }
+    }
+    m.ne = (int)edges.size();
+    m.ev.resize(m.ne);
+    m.tp.resize(m.ne);
+    m.tm.resize(m.ne);
+    m.fp.resize(m.ne);
+    m.fm.resize(m.ne);
+    m.len.resize(m.ne);
+    m.ereg.resize(m.ne);
+    m.tri_edge.assign(m.nt, {-1, -1, -1});
+    m.tri_sign.assign(m.nt, {0, 0, 0});
+    int e = 0;
+    for (auto &kv : edges) {  // std::map iterates in (min, max) order = canonical order
+        const Side &p = kv.second.first, &n = kv.second.second;
+        if (p.tri < 0 || n.tri < 0) throw Error(SFMM_E_MESH, "open surface or inconsistent orientation");
+        if (m.TR[p.tri] != m.TR[n.tri])
+            throw Error(SFMM_E_MESH, "edge between triangles of different interfaces");
+        m.ev[e] = {kv.first.first, kv.first.second};
+        m.tp[e] = p.tri;
+        m.tm[e] = n.tri;
+        m.fp[e] = p.free;
+        m.fm[e] = n.free;
+        m.len[e] = norm(m.V[kv.first.second] - m.V[kv.first.first]);
+        m.ereg[e] = m.TR[p.tri];
+        m.tri_edge[p.tri][p.local] = e;
+        m.tri_sign[p.tri][p.local] = 1;
+        m.tri_edge[n.tri][n.local] = e;
+        m.tri_sign[n.tri][n.local] = -1;
+        ++e;
+    }
+    return m;
+}
+
+}  // namespace sfmm

@@ -1,0 +1,207 @@
+"""GPU parity of the HIP path against the oracle, through the C ABI.
+
+Tolerances: FP64 near-field products and ILU(0) solves are exact up to
+rounding (1e-11 relative); FP32 ones carry single-precision rounding of
+sums over a few hundred terms (1e-5); the full MLFMM product approximates the
+dense Galerkin matrix to the stated 1e-3 relative 2-norm error; RCS agrees
+with the oracle's LU solution within 0.2 dB above a -30 dB floor (relative to
+the cut's maximum)."""
+
+import numpy as np
+import pytest
+
+from oracle import farfield, krylov, mom, octree, rwg
+from workloads import random_complex_vector, sphere_body
+
+pytestmark = pytest.mark.gpu
+
+sfmm = pytest.importorskip("paper_1704_06862_amd.sfmm")
+
+CFG1 = dict(finest_box=0.15, n_levels=3, extra_multipoles=5)
+THETA = np.deg2rad(np.arange(181.0))
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    b = sphere_body(0.3, 4.0, 2)
+    m = rwg.from_body(b)
+    Z = mom.pmchwt_dense(m, b.eps_r, b.mu_r, b.frequency)
+    keys = octree.finest_keys(m, 0.15, 3)
+    pat = octree.near_pattern(keys)
+    x = random_complex_vector(2 * m.n_edges, 2, seed=1234)
+    return dict(body=b, mesh=m, Z=Z, pat=pat, keys=keys, x=x)
+
+
+@pytest.fixture(scope="module")
+def ctx64(cfg1):
+    print("setup cfg1 fp64", flush=True)
+    with sfmm.Context([cfg1["body"]], precision=sfmm.PREC_FP64, **CFG1) as c:
+        yield c
+
+
+@pytest.fixture(scope="module")
+def ctx32(cfg1):
+    print("setup cfg1 fp32", flush=True)
+    # FP32 at 0.15-wavelength boxes: the diagonal translation grows like
+    # h_L(kX) at small kX, so single-precision rounding is amplified; keep L
+    # at the excess-bandwidth order + 1 here (the 1e-3 FP32 gate is on the
+    # 0.25-wavelength multilevel case below)
+    # (FP32 solves stop at 1e-4, the tolerance of the FP32 workloads; the
+    # rounding noise of an FP32 product limits the attainable residual)
+    opts = dict(CFG1, extra_multipoles=1, tol=1e-4)
+    with sfmm.Context([cfg1["body"]], precision=sfmm.PREC_FP32, **opts) as c:
+        yield c
+
+
+def test_near_product_fp64(cfg1, ctx64):
+    x = cfg1["x"]
+    y = ctx64.sfmm_matvec(x, np.zeros_like(x), parts=sfmm.PART_NEAR)
+    ref = x @ np.where(cfg1["pat"], cfg1["Z"], 0).T
+    assert rel(y, ref) < 1e-11
+
+
+def test_near_product_fp32(cfg1, ctx32):
+    x = cfg1["x"]
+    y = ctx32.sfmm_matvec(x, np.zeros_like(x), parts=sfmm.PART_NEAR)
+    ref = x @ np.where(cfg1["pat"], cfg1["Z"], 0).T
+    assert rel(y, ref) < 1e-5
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_product_matches_dense(cfg1, ctx64, ctx32, prec):
+    ctx = ctx64 if prec == "fp64" else ctx32
+    x = cfg1["x"]
+    y = ctx.sfmm_matvec(x, np.zeros_like(x))
+    ref = x @ cfg1["Z"].T
+    err = rel(y, ref)
+    print(prec, "matvec rel err", err)
+    assert err < (1e-3 if prec == "fp64" else 3e-3)
+    # the far part alone is a sizeable share of the product
+    yf = ctx.sfmm_matvec(x, np.zeros_like(x), parts=sfmm.PART_FAR)
+    assert np.linalg.norm(yf) > 0.03 * np.linalg.norm(ref)
+
+
+def test_batched_rhs_equals_single(cfg1, ctx32):
+    x = cfg1["x"]
+    y2 = ctx32.sfmm_matvec(x, np.zeros_like(x))
+    y0 = ctx32.sfmm_matvec(np.ascontiguousarray(x[:1]), np.zeros_like(x[:1]))
+    y1 = ctx32.sfmm_matvec(np.ascontiguousarray(x[1:]), np.zeros_like(x[1:]))
+    assert np.array_equal(y2, np.concatenate([y0, y1]))
+
+
+def test_ilu_preconditioner_fp64(cfg1, ctx64):
+    m = cfg1["mesh"]
+    p = octree.unknown_order(cfg1["keys"])
+    F = krylov.ilu0(cfg1["Z"][np.ix_(p, p)], cfg1["pat"][np.ix_(p, p)])
+    x = cfg1["x"][0]
+    ref = np.empty_like(x)
+    ref[p] = krylov.ilu_apply(F, x[p])
+    z = ctx64.sfmm_precond(cfg1["x"][:1].copy(), np.zeros_like(cfg1["x"][:1]))[0]
+    assert rel(z, ref) < 1e-10
+
+
+def test_ilu_preconditioner_fp32(cfg1, ctx32):
+    p = octree.unknown_order(cfg1["keys"])
+    F = krylov.ilu0(cfg1["Z"][np.ix_(p, p)], cfg1["pat"][np.ix_(p, p)])
+    x = cfg1["x"][0]
+    ref = np.empty_like(x)
+    ref[p] = krylov.ilu_apply(F, x[p])
+    z = ctx32.sfmm_precond(cfg1["x"][:1].copy(), np.zeros_like(cfg1["x"][:1]))[0]
+    assert rel(z, ref) < 1e-4
+
+
+def test_planewave_rhs_matches_oracle(cfg1, ctx64):
+    m, b = cfg1["mesh"], cfg1["body"]
+    angles = np.array([[0.0, 0.0], [1.1, 0.4]])
+    rhs = ctx64.sfmm_planewave_rhs(angles, np.zeros((2, 2 * m.n_edges), dtype=complex))
+    for i, (th, ph) in enumerate(angles):
+        kh, eh = mom.incidence(th, ph)
+        ref = mom.planewave_rhs(m, b.frequency, kh, eh)
+        assert rel(rhs[i], ref) < 1e-12
+
+
+def _masked_db(s, ref):
+    floor = 1e-3 * ref.max()
+    return np.abs(10 * np.log10((s + floor) / (ref + floor)))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_solve_and_rcs_match_oracle(cfg1, ctx64, ctx32, prec):
+    ctx = ctx64 if prec == "fp64" else ctx32
+    m, b, Z = cfg1["mesh"], cfg1["body"], cfg1["Z"]
+    kh, eh = mom.incidence(0.0, 0.0)
+    rhs = mom.planewave_rhs(m, b.frequency, kh, eh)[None, :].copy()
+    x = np.zeros_like(rhs)
+    info = ctx.sfmm_solve(rhs, x)[0]
+    print(prec, info)
+    tol = 1e-6 if prec == "fp64" else 1e-4
+    assert info["converged"] and info["true_residual"] <= tol
+    # residual of the exact (dense) system is bounded by the product error
+    assert rel(Z @ x[0], rhs[0]) < (2e-3 if prec == "fp64" else 4e-3)
+    xd = np.linalg.solve(Z, rhs[0])
+    tp_e = np.stack([THETA, 0 * THETA], 1)
+    tp_h = np.stack([THETA, 0 * THETA + np.pi / 2], 1)
+    sE = ctx.sfmm_rcs(x, tp_e)[0, :, 0]
+    sH = ctx.sfmm_rcs(x, tp_h)[0, :, 1]
+    rE, _ = farfield.rcs(m, b.frequency, xd, THETA, 0 * THETA)
+    _, rH = farfield.rcs(m, b.frequency, xd, THETA, 0 * THETA + np.pi / 2)
+    assert _masked_db(sE, rE).max() < 0.2
+    assert _masked_db(sH, rH).max() < 0.2
+
+
+def test_solve_iterations_match_oracle_gmres(cfg1, ctx64):
+    m, b, Z, pat = cfg1["mesh"], cfg1["body"], cfg1["Z"], cfg1["pat"]
+    p = octree.unknown_order(cfg1["keys"])
+    F = krylov.ilu0(Z[np.ix_(p, p)], pat[np.ix_(p, p)])
+
+    def prec(v):
+        out = np.empty_like(v)
+        out[p] = krylov.ilu_apply(F, v[p])
+        return out
+
+    kh, eh = mom.incidence(0.0, 0.0)
+    rhs = mom.planewave_rhs(m, b.frequency, kh, eh)
+    _, oinfo = krylov.gmres(lambda v: Z @ v, rhs, prec, restart=30, tol=1e-6)
+    x = np.zeros((1, len(rhs)), dtype=complex)
+    info = ctx64.sfmm_solve(rhs[None, :].copy(), x)[0]
+    # the GPU solves the MLFMM-approximated system: same preconditioner,
+    # nearly the same operator, so nearly the same Krylov history
+    assert abs(info["iterations"] - oinfo.iterations) <= 3
+
+
+def test_device_pointers_match_host_path(cfg1, ctx32):
+    torch = pytest.importorskip("torch")
+    x = cfg1["x"]
+    yh = ctx32.sfmm_matvec(x, np.zeros_like(x))
+    xd = torch.from_numpy(x).to("cuda")
+    yd = torch.zeros_like(xd)
+    ctx32.sfmm_set_stream(torch.cuda.current_stream().cuda_stream)
+    ctx32.sfmm_matvec(xd, yd)
+    torch.cuda.current_stream().synchronize()
+    ctx32.sfmm_set_stream(0)
+    assert np.array_equal(yd.cpu().numpy(), yh)
+
+
+def test_multilevel_product_sampled_rows():
+    # r = 1 sphere, 3840 unknowns, 4 levels: translations at two levels with
+    # interpolation/anterpolation between them
+    b = sphere_body(1.0, 2.56, 3)
+    m = rwg.from_body(b)
+    rng = np.random.default_rng(5)
+    test = np.sort(rng.choice(m.n_edges, 60, replace=False))
+    x = random_complex_vector(2 * m.n_edges, 1, seed=99)
+    ZE, ZH = mom.pmchwt_rows(m, b.eps_r, b.mu_r, b.frequency, test)
+    ref = np.concatenate([ZE @ x[0], ZH @ x[0]])
+    for prec in (sfmm.PREC_FP64, sfmm.PREC_FP32):
+        print("setup multilevel", prec, flush=True)
+        with sfmm.Context([b], precision=prec, finest_box=0.25) as ctx:
+            assert ctx.sfmm_describe()["levels"] == 4
+            y = ctx.sfmm_matvec(x, np.zeros_like(x))[0]
+        got = np.concatenate([y[test], y[m.n_edges + test]])
+        err = rel(got, ref)
+        print("multilevel prec", prec, "sampled-row rel err", err)
+        assert err < 1e-3
