@@ -89,12 +89,20 @@ typedef struct {
     int32_t device;           /* HIP device ordinal; -1 = build host tables only        */
     int32_t verbose;          /* 1: setup statistics to stderr; 2: also GMRES restarts  */
     int32_t preconditioner;   /* SFMM_PRECOND_*                                          */
+    int32_t poly_degree;      /* degree of SFMM_PRECOND_POLY; 0 = 16                      */
 } sfmm_options;
 
-/* Preconditioners of sfmm_solve: ILU(0) of the near-field matrix (default),
- * none, or the inverses of the diagonal (same-box) blocks of the near-field
- * matrix. */
-enum { SFMM_PRECOND_ILU0 = 0, SFMM_PRECOND_NONE = 1, SFMM_PRECOND_BLOCK_JACOBI = 2 };
+/* Preconditioners of sfmm_solve, all built from the near-field matrix Z_near
+ * (the paper preconditions with an incomplete LU of it):
+ *   ILU0          ILU(0) in colour order (the paper's preconditioner);
+ *   NONE          identity;
+ *   BLOCK_JACOBI  inverses of the same-box diagonal blocks;
+ *   POLY          p(Z_near) with p the degree-d residual polynomial of GMRES on
+ *                 Z_near (roots: harmonic Ritz values from d FP64 Arnoldi
+ *                 steps from v0[i] = exp(2 pi j frac(i (sqrt5-1)/2)), Leja
+ *                 order, product form); d near-field products per
+ *                 application, no reductions.  Default. */
+enum { SFMM_PRECOND_ILU0 = 0, SFMM_PRECOND_NONE = 1, SFMM_PRECOND_BLOCK_JACOBI = 2, SFMM_PRECOND_POLY = 3 };
 
 typedef struct {
     int32_t converged;        /* 1 if ||b - Z x|| / ||b|| <= tol                        */

@@ -111,3 +111,66 @@ def gmres(matvec, b, precond=None, restart=30, tol=1e-6, max_iters=1000, x0=None
         y = solve_triangular(H[:j_end, :j_end], g[:j_end], lower=False)
         x = x + precond(V[:j_end].T @ y)
         restarts += 1
+
+
+# --- polynomial preconditioner ---------------------------------------------
+#
+# Reading adopted for the paper's near-field preconditioner when ILU(0) of the
+# PMCHWT near field is too poor an approximation of its inverse: a fixed
+# polynomial p with p(Z_near) ~ Z_near^-1, namely the residual polynomial of
+# d GMRES steps on Z_near (Loe & Morgan, Numer. Linear Algebra Appl. 2022).
+# Its roots are the harmonic Ritz values of d Arnoldi steps from the
+# deterministic start vector v0[i] = exp(2 pi j frac(i g)), g = (sqrt 5 - 1)/2,
+# and it is applied in Leja order in product form.
+
+def golden_start(n):
+    g = 0.5 * (np.sqrt(5.0) - 1.0)
+    i = np.arange(n, dtype=np.float64)
+    t = i * g - np.floor(i * g)
+    return np.exp(2j * np.pi * t)
+
+
+def harmonic_ritz(matvec, v0, d):
+    """Harmonic Ritz values of d Arnoldi steps (CGS2) from v0: eigenvalues of
+    H_d + |h_{d+1,d}|^2 H_d^-H e_d e_d^T."""
+    n = len(v0)
+    V = np.zeros((d + 1, n), dtype=complex)
+    H = np.zeros((d + 1, d), dtype=complex)
+    V[0] = v0 / np.linalg.norm(v0)
+    for j in range(d):
+        w = matvec(V[j])
+        for _ in range(2):
+            h = V[: j + 1].conj() @ w
+            w = w - V[: j + 1].T @ h
+            H[: j + 1, j] += h
+        H[j + 1, j] = np.linalg.norm(w)
+        V[j + 1] = w / H[j + 1, j]
+    Hd = H[:d, :d]
+    ed = np.zeros(d)
+    ed[-1] = 1.0
+    f = np.linalg.solve(Hd.conj().T, ed)
+    return np.linalg.eigvals(Hd + abs(H[d, d - 1]) ** 2 * np.outer(f, ed))
+
+
+def leja_order(theta):
+    """Largest modulus first, then each next root maximises the product of
+    distances to the roots already chosen."""
+    rest = list(theta)
+    first = max(rest, key=abs)
+    out = [first]
+    rest.remove(first)
+    while rest:
+        nxt = max(rest, key=lambda t: np.sum(np.log(np.abs(t - np.array(out)) + 1e-300)))
+        out.append(nxt)
+        rest.remove(nxt)
+    return np.array(out)
+
+
+def poly_apply(matvec, roots, v):
+    """y = p(A) v with 1 - z p(z) = prod_k (1 - z / roots_k)."""
+    y = np.zeros_like(v)
+    q = np.array(v, dtype=complex)
+    for t in roots:
+        y = y + q / t
+        q = q - matvec(q) / t
+    return y

@@ -172,6 +172,54 @@ def operator_rows(mesh: RWGMesh, k: complex, region: int, test_edges):
     return L, K
 
 
+def operator_near(mesh: RWGMesh, k: complex, region: int, near):
+    """L_r and K_r restricted to the boolean edge-pair pattern ``near``
+    ([ne, ne]); entries outside the pattern are zero.  Only the triangle pairs
+    that contribute to pattern entries are integrated."""
+    ne = mesh.n_edges
+    L = np.zeros((ne, ne), dtype=complex)
+    K = np.zeros((ne, ne), dtype=complex)
+    border = (mesh.tri_regions[:, 0] == region) | (mesh.tri_regions[:, 1] == region)
+    for P in np.nonzero(border)[0]:
+        edges_P = mesh.tri_edge[P]
+        cols = np.nonzero(near[edges_P].any(axis=0))[0]
+        Qs = np.unique(np.concatenate([mesh.tri_p[cols], mesh.tri_m[cols]]))
+        Qs = Qs[border[Qs]]
+        if len(Qs) == 0:
+            continue
+        L_loc, K_loc = pair_interactions(mesh, P, Qs, k)
+        for i in range(3):
+            m = edges_P[i]
+            sm = mesh.tri_sign[P, i] * mesh.length[m]
+            for j in range(3):
+                n = mesh.tri_edge[Qs, j]
+                keep = near[m, n]
+                sn = mesh.tri_sign[Qs, j] * mesh.length[n]
+                np.add.at(L[m], n[keep], (sm * sn * L_loc[:, i, j])[keep])
+                np.add.at(K[m], n[keep], (sm * sn * K_loc[:, i, j])[keep])
+    return L, K
+
+
+def pmchwt_near(mesh: RWGMesh, eps_r, mu_r, frequency, near):
+    """Scaled PMCHWT matrix [2 ne, 2 ne] restricted to the edge-pair pattern
+    ``near`` (the near-field matrix when ``near`` is the octree's near mask)."""
+    ne = mesh.n_edges
+    Z = np.zeros((2 * ne, 2 * ne), dtype=complex)
+    for r in range(len(eps_r)):
+        s = mesh.region_sign(r)
+        if not np.any(s):
+            continue
+        k = wavenumber(frequency, eps_r[r], mu_r[r])
+        et = rel_impedance(eps_r[r], mu_r[r])
+        L, K = operator_near(mesh, k, r, near)
+        sign = s[:, None] * s[None, :]
+        Z[:ne, :ne] += sign * et * L
+        Z[:ne, ne:] += -sign * K
+        Z[ne:, :ne] += sign * K
+        Z[ne:, ne:] += sign * L / et
+    return Z
+
+
 def pmchwt_rows(mesh: RWGMesh, eps_r, mu_r, frequency, test_edges):
     """Rows of the scaled PMCHWT matrix for the E-equations and H-equations of
     ``test_edges``.  Returns (Z_E, Z_H), each [len(test_edges), 2 ne]."""

@@ -13,7 +13,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsfmm.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-HOST_SOURCES = ["mesh.cpp", "octree.cpp", "nearfield.cpp", "ilu.cpp", "tables.cpp", "api.cpp"]
+HOST_SOURCES = ["mesh.cpp", "octree.cpp", "nearfield.cpp", "ilu.cpp", "poly.cpp", "tables.cpp", "api.cpp"]
 DEVICE_SOURCES = ["device.hip"]
 
 HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-fopenmp", "-ffp-contract=off", "-fcx-limited-range",

@@ -80,14 +80,15 @@ void sfmm_default_options(sfmm_options *o) {
     o->finest_box = 0.0;
     o->n_levels = 0;
     o->digits = 3.0;
-    o->extra_multipoles = 2;
+    o->extra_multipoles = 0;
     o->precision = SFMM_PREC_FP32;
     o->gmres_restart = 30;
     o->max_iters = 1000;
     o->tol = 1e-6;
     o->device = 0;
     o->verbose = 0;
-    o->preconditioner = SFMM_PRECOND_ILU0;
+    o->preconditioner = SFMM_PRECOND_POLY;
+    o->poly_degree = 16;
 }
 
 sfmm_status sfmm_setup(const sfmm_body *bodies, int32_t n_bodies, const sfmm_options *opt, sfmm_ctx **out) {
@@ -105,7 +106,9 @@ sfmm_status sfmm_setup(const sfmm_body *bodies, int32_t n_bodies, const sfmm_opt
         if (o.precision != SFMM_PREC_FP32 && o.precision != SFMM_PREC_FP64 && o.precision != SFMM_PREC_BF16_SPLIT)
             throw Error(SFMM_E_INVALID_ARG, "unknown precision");
         if (o.extra_multipoles < 0 || o.extra_multipoles > 64) throw Error(SFMM_E_INVALID_ARG, "extra_multipoles out of range");
-        if (o.preconditioner < 0 || o.preconditioner > 2) throw Error(SFMM_E_INVALID_ARG, "unknown preconditioner");
+        if (o.preconditioner < 0 || o.preconditioner > 3) throw Error(SFMM_E_INVALID_ARG, "unknown preconditioner");
+        if (o.poly_degree <= 0) o.poly_degree = 16;
+        if (o.poly_degree > 64) throw Error(SFMM_E_INVALID_ARG, "poly_degree must be at most 64");
         if (o.device >= 0) check_device(o.device);
         for (int32_t i = 0; i < n_bodies; ++i) {
             auto t0 = std::chrono::steady_clock::now();
@@ -117,6 +120,7 @@ sfmm_status sfmm_setup(const sfmm_body *bodies, int32_t n_bodies, const sfmm_opt
             auto t2 = std::chrono::steady_clock::now();
             if (o.preconditioner == SFMM_PRECOND_ILU0) bh->ilu = factor_ilu(bh->mesh, bh->oct, bh->near);
             else if (o.preconditioner == SFMM_PRECOND_BLOCK_JACOBI) bh->ilu = factor_block_jacobi(bh->mesh, bh->oct, bh->near);
+            else if (o.preconditioner == SFMM_PRECOND_POLY) bh->poly = poly_roots(bh->mesh, bh->oct, bh->near, o.poly_degree);
             bh->precond = o.preconditioner;
             auto t3 = std::chrono::steady_clock::now();
             for (const RegionTree &rt : bh->oct.regions) bh->tables.push_back(build_tables(bh->mesh, bh->oct, rt));

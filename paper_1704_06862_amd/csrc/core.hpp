@@ -147,6 +147,10 @@ IluFactors factor_ilu(const Mesh &m, const Octree &o, const NearMatrix &Z);
 // of the near matrix, backward rows the identity.
 IluFactors factor_block_jacobi(const Mesh &m, const Octree &o, const NearMatrix &Z);
 
+// Roots (Leja-ordered harmonic Ritz values) of the near-field GMRES polynomial
+// preconditioner of the given degree.
+std::vector<cd> poly_roots(const Mesh &m, const Octree &o, const NearMatrix &Z, int degree);
+
 // ---------------------------------------------------------------------------
 // MLFMM sampling and tables for one region.
 struct Sampling {

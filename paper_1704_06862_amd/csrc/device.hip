@@ -118,12 +118,15 @@ __global__ void k_zero(cx<T> *__restrict__ a, int64_t n) {
 constexpr int RW = 16;              // rows (wavefronts) per workgroup
 constexpr int RWG = RW * 64;
 
-template <typename T, bool LDS>
+// POLY = true fuses one step of the polynomial preconditioner into the
+// epilogue: with q = Z_near x,  acc += x / theta  and  y = x - q / theta.
+template <typename T, bool LDS, bool POLY = false>
 __global__ void __launch_bounds__(RWG) k_near(const int *__restrict__ bstart, const int *__restrict__ col_ptr,
                                               const int *__restrict__ cols, const int64_t *__restrict__ val_ptr,
                                               const cx<T> *__restrict__ A, const cx<T> *__restrict__ B,
                                               const cx<T> *__restrict__ C, const cx<T> *__restrict__ x,
-                                              cx<T> *__restrict__ y) {
+                                              cx<T> *__restrict__ y, cx<T> *__restrict__ acc = nullptr,
+                                              cx<T> inv_theta = {0, 0}, int write_y = 1) {
     extern __shared__ unsigned char lds_raw[];
     cx<T> *xs = reinterpret_cast<cx<T> *>(lds_raw);
     const int b = blockIdx.x;
@@ -183,8 +186,24 @@ __global__ void __launch_bounds__(RWG) k_near(const int *__restrict__ bstart, co
     aH.x = wave_sum(aH.x + bH.x);
     aH.y = wave_sum(aH.y + bH.y);
     if (lane == 0) {
-        y[2 * (r0 + row)] = aE;
-        y[2 * (r0 + row) + 1] = aH;
+        const int i = 2 * (r0 + row);
+        if (POLY) {
+            cx<T> xe = x[i], xh = x[i + 1];
+            cx<T> ae = acc[i], ah = acc[i + 1];
+            cfma(ae, xe, inv_theta);
+            cfma(ah, xh, inv_theta);
+            acc[i] = ae;
+            acc[i + 1] = ah;
+            if (write_y) {
+                cfms(xe, aE, inv_theta);
+                cfms(xh, aH, inv_theta);
+                y[i] = xe;
+                y[i + 1] = xh;
+            }
+        } else {
+            y[i] = aE;
+            y[i + 1] = aH;
+        }
     }
 }
 
@@ -394,6 +413,117 @@ __global__ void k_dn_theta(int nchild, int nth_c, int nph_c, int nth_p, const T 
         acc.y += a * g1.y + b * g2.y;
     }
     Gc[id] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// LDS-staged interpolation: one workgroup per parent box, children in turn,
+// one component at a time: child pattern -> LDS, theta stage -> LDS,
+// phi stage + shift accumulated into the parent pattern (no other workgroup
+// touches this parent).
+template <typename T>
+__global__ void __launch_bounds__(WG) k_up_box(int nth_c, int nph_c, int nth_p, int nph_p, const T *__restrict__ A,
+                                               const T *__restrict__ B, const T *__restrict__ Dt,
+                                               const int *__restrict__ child_ptr, const int *__restrict__ child_idx,
+                                               const int *__restrict__ child_slot, const cx<T> *__restrict__ shift,
+                                               const cx<T> *__restrict__ Sc, cx<T> *__restrict__ Sp) {
+    extern __shared__ unsigned char lds_raw[];
+    const int Kc = nth_c * nph_c, Kp = nth_p * nph_p;
+    cx<T> *fs = reinterpret_cast<cx<T> *>(lds_raw);      // [Kc]
+    cx<T> *ts = fs + Kc;                                   // [nth_p][nph_c]
+    const int P = blockIdx.x;
+    const int h = nph_c / 2;
+    for (int comp = 0; comp < 2; ++comp) {
+        cx<T> *out = Sp + ((size_t)P * 2 + comp) * Kp;
+        bool first = true;
+        for (int q = child_ptr[P]; q < child_ptr[P + 1]; ++q) {
+            const int c = child_idx[q];
+            const cx<T> *f = Sc + ((size_t)c * 2 + comp) * Kc;
+            __syncthreads();
+            for (int t = threadIdx.x; t < Kc; t += WG) fs[t] = f[t];
+            __syncthreads();
+            for (int t = threadIdx.x; t < nth_p * nph_c; t += WG) {
+                const int I = t / nph_c, j = t % nph_c;
+                const int j1 = j < h ? j : j - h, j2 = j1 + h;
+                const T *Pa = (j < h) ? A : B;
+                const T *Pb = (j < h) ? B : A;
+                cx<T> acc = {0, 0};
+                for (int i = 0; i < nth_c; ++i) {
+                    const T a = Pa[I * nth_c + i], b = Pb[I * nth_c + i];
+                    const cx<T> f1 = fs[i * nph_c + j1], f2 = fs[i * nph_c + j2];
+                    acc.x += a * f1.x + b * f2.x;
+                    acc.y += a * f1.y + b * f2.y;
+                }
+                ts[t] = acc;
+            }
+            __syncthreads();
+            const cx<T> *sh = shift + (size_t)child_slot[c] * Kp;
+            for (int kk = threadIdx.x; kk < Kp; kk += WG) {
+                const int I = kk / nph_p, J = kk % nph_p;
+                const cx<T> *g = ts + I * nph_c;
+                cx<T> v = {0, 0};
+                for (int j = 0; j < nph_c; ++j) {
+                    const T d = Dt[(size_t)j * nph_p + J];   // lanes read consecutive J
+                    v.x += d * g[j].x;
+                    v.y += d * g[j].y;
+                }
+                cx<T> o = first ? cx<T>{0, 0} : out[kk];
+                cfma(o, sh[kk], v);
+                out[kk] = o;
+            }
+            first = false;
+        }
+    }
+}
+
+// LDS-staged anterpolation: one workgroup per child box: shifted parent
+// pattern -> LDS, phi transpose -> LDS, theta transpose accumulated into the
+// child pattern.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_dn_box(int nth_c, int nph_c, int nth_p, int nph_p, const T *__restrict__ A,
+                                               const T *__restrict__ B, const T *__restrict__ D,
+                                               const int *__restrict__ parent, const int *__restrict__ child_slot,
+                                               const cx<T> *__restrict__ shift, const cx<T> *__restrict__ Gp,
+                                               cx<T> *__restrict__ Gc) {
+    extern __shared__ unsigned char lds_raw[];
+    const int Kc = nth_c * nph_c, Kp = nth_p * nph_p;
+    cx<T> *gs = reinterpret_cast<cx<T> *>(lds_raw);      // [Kp]
+    cx<T> *ts = gs + Kp;                                   // [nth_p][nph_c]
+    const int c = blockIdx.x;
+    const int h = nph_c / 2;
+    const cx<T> *sh = shift + (size_t)child_slot[c] * Kp;
+    for (int comp = 0; comp < 2; ++comp) {
+        const cx<T> *g = Gp + ((size_t)parent[c] * 2 + comp) * Kp;
+        __syncthreads();
+        for (int t = threadIdx.x; t < Kp; t += WG) gs[t] = cmul(sh[t], g[t]);
+        __syncthreads();
+        for (int t = threadIdx.x; t < nth_p * nph_c; t += WG) {
+            const int I = t / nph_c, j = t % nph_c;
+            const cx<T> *row = gs + I * nph_p;
+            cx<T> acc = {0, 0};
+            for (int J = 0; J < nph_p; ++J) {
+                const T d = D[(size_t)J * nph_c + j];
+                acc.x += d * row[J].x;
+                acc.y += d * row[J].y;
+            }
+            ts[t] = acc;
+        }
+        __syncthreads();
+        cx<T> *out = Gc + ((size_t)c * 2 + comp) * Kc;
+        for (int t = threadIdx.x; t < Kc; t += WG) {
+            const int i = t / nph_c, j = t % nph_c;
+            const int j1 = j < h ? j : j - h, j2 = j1 + h;
+            const T *Pa = (j < h) ? A : B;
+            const T *Pb = (j < h) ? B : A;
+            cx<T> acc = out[t];
+            for (int I = 0; I < nth_p; ++I) {
+                const T a = Pa[I * nth_c + i], b = Pb[I * nth_c + i];
+                const cx<T> g1 = ts[I * nph_c + j1], g2 = ts[I * nph_c + j2];
+                acc.x += a * g1.x + b * g2.x;
+                acc.y += a * g1.y + b * g2.y;
+            }
+            out[t] = acc;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -660,6 +790,7 @@ class DeviceBodyT final : public DeviceBody {
         max_ncol_ = 0;
         max_nrow_ = 0;
         precond_ = h.precond;
+        for (const cd &t : h.poly) inv_theta_.push_back(to_cx<T>(1.0 / t));
         for (int b = 0; b < nb_; ++b) {
             max_ncol_ = std::max(max_ncol_, h.near.col_ptr[b + 1] - h.near.col_ptr[b]);
             max_nrow_ = std::max(max_nrow_, o.bstart[b + 1] - o.bstart[b]);
@@ -714,6 +845,13 @@ class DeviceBodyT final : public DeviceBody {
                         R.ipA[l] = upload_real(tb.ipA[l]);
                         R.ipB[l] = upload_real(tb.ipB[l]);
                         R.ipD[l] = upload_real(tb.ipD[l]);
+                        {
+                            const int np_p = tb.samp[l - 1].nph, np_c = s.nph;
+                            std::vector<double> Dt((size_t)np_p * np_c);
+                            for (int J = 0; J < np_p; ++J)
+                                for (int jj = 0; jj < np_c; ++jj) Dt[(size_t)jj * np_p + J] = tb.ipD[l][(size_t)J * np_c + jj];
+                            R.ipDt[l] = upload_real(Dt);
+                        }
                         R.sup[l] = upload_cx(tb.shift_up[l]);
                         R.sdn[l] = upload_cx(tb.shift_dn[l]);
                         const Sampling &p = tb.samp[l - 1];
@@ -733,6 +871,7 @@ class DeviceBodyT final : public DeviceBody {
         yi_ = alloc_cx(N);
         zi_ = alloc_cx(N);
         wi_ = alloc_cx(N);
+        pt_ = alloc_cx(N);
         HIPCHK(hipEventCreate(&ev0_));
         HIPCHK(hipEventCreate(&ev1_));
         for (auto &e : evs_) HIPCHK(hipEventCreate(&e));
@@ -780,6 +919,15 @@ class DeviceBodyT final : public DeviceBody {
             mark(2);
             for (Reg &R : regs_) {
                 for (int l = f_; l >= 3; --l) {
+                    size_t lds = ((size_t)R.K[l] + (size_t)R.nth[l - 1] * R.nph[l]) * sizeof(cx<T>);
+                    if (lds <= LDS_LIMIT) {
+                        k_up_box<T><<<R.nbox[l - 1], WG, lds, stream_>>>(R.nth[l], R.nph[l], R.nth[l - 1], R.nph[l - 1],
+                                                                        R.ipA[l], R.ipB[l], R.ipDt[l], R.child_ptr[l - 1],
+                                                                        R.child_idx[l - 1], R.slot[l], R.sup[l], R.S[l],
+                                                                        R.S[l - 1]);
+                        LAUNCHCHK();
+                        continue;
+                    }
                     int nchild = R.nbox[l];
                     int64_t n1 = (int64_t)nchild * 2 * R.nth[l - 1] * R.nph[l];
                     k_up_theta<T><<<nblocks(n1), WG, 0, stream_>>>(nchild, R.nth[l], R.nph[l], R.nth[l - 1], R.ipA[l],
@@ -804,6 +952,14 @@ class DeviceBodyT final : public DeviceBody {
             mark(4);
             for (Reg &R : regs_) {
                 for (int l = 3; l <= f_; ++l) {
+                    size_t lds = ((size_t)R.K[l - 1] + (size_t)R.nth[l - 1] * R.nph[l]) * sizeof(cx<T>);
+                    if (lds <= LDS_LIMIT) {
+                        k_dn_box<T><<<R.nbox[l], WG, lds, stream_>>>(R.nth[l], R.nph[l], R.nth[l - 1], R.nph[l - 1],
+                                                                    R.ipA[l], R.ipB[l], R.ipD[l], R.parent[l], R.slot[l],
+                                                                    R.sdn[l], R.G[l - 1], R.G[l]);
+                        LAUNCHCHK();
+                        continue;
+                    }
                     int nchild = R.nbox[l];
                     int64_t n1 = (int64_t)nchild * 2 * R.nth[l - 1] * R.nph[l];
                     k_dn_phi<T><<<nblocks(n1), WG, 0, stream_>>>(nchild, R.nth[l - 1], R.nph[l - 1], R.nph[l], R.ipD[l],
@@ -850,7 +1006,27 @@ class DeviceBodyT final : public DeviceBody {
                 k_ilu<T, false><<<grid, RWG, 0, stream_>>>(box0, bstart_, cp, cl, vp, W, own, other, out);
             LAUNCHCHK();
         };
-        if (precond_ == SFMM_PRECOND_BLOCK_JACOBI) {
+        if (precond_ == SFMM_PRECOND_POLY) {
+            // w = p(Z_near) v, product form over the Leja-ordered roots
+            k_zero<T><<<nblocks(2 * ne_), WG, 0, stream_>>>(w, 2 * ne_);
+            LAUNCHCHK();
+            size_t lds_n = (size_t)max_ncol_ * 2 * sizeof(cx<T>);
+            dim3 grid(nb_, (max_nrow_ + RW - 1) / RW);
+            const cx<T> *cur = v;
+            const int d = (int)inv_theta_.size();
+            for (int k = 0; k < d; ++k) {
+                cx<T> *next = (k % 2 == 0) ? z : pt_;
+                const int last = (k == d - 1);
+                if (lds_n <= LDS_LIMIT)
+                    k_near<T, true, true><<<grid, RWG, lds_n, stream_>>>(bstart_, near_col_ptr_, near_cols_, near_val_ptr_,
+                                                                        nA_, nB_, nC_, cur, next, w, inv_theta_[k], !last);
+                else
+                    k_near<T, false, true><<<grid, RWG, 0, stream_>>>(bstart_, near_col_ptr_, near_cols_, near_val_ptr_,
+                                                                     nA_, nB_, nC_, cur, next, w, inv_theta_[k], !last);
+                LAUNCHCHK();
+                cur = next;
+            }
+        } else if (precond_ == SFMM_PRECOND_BLOCK_JACOBI) {
             sweep(0, nb_, fcol_ptr_, fcols_, fptr_, fval_, v, v, w);
         } else {
             for (int c = 0; c < 8; ++c)
@@ -900,7 +1076,9 @@ class DeviceBodyT final : public DeviceBody {
     }
 
     // FP64 internal helpers for GMRES
-    void op_apply(const double2 *in, double2 *out, bool precondition, bool product) {
+    // out = A M^-1 in (or A in, or M^-1 in); if zout is given, it receives
+    // M^-1 in exactly as the product saw it (flexible GMRES keeps it).
+    void op_apply(const double2 *in, double2 *out, bool precondition, bool product, double2 *zout = nullptr) {
         const int N = 2 * ne_;
         k_cast<double, T><<<nblocks(N), WG, 0, stream_>>>((const cx<double> *)in, xi_, N);
         LAUNCHCHK();
@@ -908,6 +1086,10 @@ class DeviceBodyT final : public DeviceBody {
         if (precondition && precond_ != SFMM_PRECOND_NONE) {
             ilu_internal(xi_, zi_, wi_);
             cur = wi_;
+        }
+        if (zout) {
+            k_cast<T, double><<<nblocks(N), WG, 0, stream_>>>(cur, (cx<double> *)zout, N);
+            LAUNCHCHK();
         }
         if (product) {
             matvec_internal(cur, yi_, SFMM_PART_ALL);
@@ -985,7 +1167,7 @@ class DeviceBodyT final : public DeviceBody {
                 for (int j = 0; j < m; ++j) {
                     double2 *Vj = kV_ + (size_t)j * N;
                     double2 *w = kV_ + (size_t)(j + 1) * N;
-                    op_apply(Vj, w, true, true);
+                    op_apply(Vj, w, true, true, kZ_ + (size_t)j * N);
                     ++its;
                     // classical Gram-Schmidt, twice
                     std::vector<cd> h(j + 1, 0.0);
@@ -1046,9 +1228,9 @@ class DeviceBodyT final : public DeviceBody {
                 std::vector<double2> yd(jend);
                 for (int i = 0; i < jend; ++i) yd[i] = make_double2(y[i].real(), y[i].imag());
                 HIPCHK(hipMemcpyAsync(dh_, yd.data(), sizeof(double2) * jend, hipMemcpyHostToDevice, stream_));
-                k_lincomb<<<nblocks(N), WG, 0, stream_>>>(kV_, N, jend, N, dh_, ku_);
+                // flexible form: x += Z y with z_j = M^-1 v_j as used in the products
+                k_lincomb<<<nblocks(N), WG, 0, stream_>>>(kZ_, N, jend, N, dh_, kt_);
                 LAUNCHCHK();
-                op_apply(ku_, kt_, true, false);
                 k_add<<<nblocks(N), WG, 0, stream_>>>(kt_, N, kx_);
                 LAUNCHCHK();
                 ++restarts;
@@ -1105,7 +1287,7 @@ class DeviceBodyT final : public DeviceBody {
         int *il_ptr[MAXLEV] = {nullptr}, *il_src[MAXLEV] = {nullptr}, *il_off[MAXLEV] = {nullptr};
         int *parent[MAXLEV] = {nullptr}, *slot[MAXLEV] = {nullptr};
         int *child_ptr[MAXLEV] = {nullptr}, *child_idx[MAXLEV] = {nullptr};
-        T *ipA[MAXLEV] = {nullptr}, *ipB[MAXLEV] = {nullptr}, *ipD[MAXLEV] = {nullptr};
+        T *ipA[MAXLEV] = {nullptr}, *ipB[MAXLEV] = {nullptr}, *ipD[MAXLEV] = {nullptr}, *ipDt[MAXLEV] = {nullptr};
         cx<T> *sup[MAXLEV] = {nullptr}, *sdn[MAXLEV] = {nullptr};
     };
 
@@ -1145,6 +1327,7 @@ class DeviceBodyT final : public DeviceBody {
         if (m <= kM_) return;
         kM_ = m;
         kV_ = alloc_raw<double2>((size_t)(m + 1) * N);
+        kZ_ = alloc_raw<double2>((size_t)m * N);
         kb_ = alloc_raw<double2>(N);
         kx_ = alloc_raw<double2>(N);
         ku_ = alloc_raw<double2>(N);
@@ -1186,10 +1369,11 @@ class DeviceBodyT final : public DeviceBody {
     int64_t *fptr_ = nullptr, *bptr_ = nullptr;
     cx<T> *fval_ = nullptr, *bval_ = nullptr;
     std::vector<Reg> regs_;
-    cx<T> *xi_ = nullptr, *yi_ = nullptr, *zi_ = nullptr, *wi_ = nullptr;
+    cx<T> *xi_ = nullptr, *yi_ = nullptr, *zi_ = nullptr, *wi_ = nullptr, *pt_ = nullptr;
+    std::vector<cx<T>> inv_theta_;
     // Krylov workspace
     int kM_ = 0, red_blocks_ = 1;
-    double2 *kV_ = nullptr, *kb_ = nullptr, *kx_ = nullptr, *ku_ = nullptr, *kt_ = nullptr;
+    double2 *kV_ = nullptr, *kZ_ = nullptr, *kb_ = nullptr, *kx_ = nullptr, *ku_ = nullptr, *kt_ = nullptr;
     double2 *dpartc_ = nullptr, *dh_ = nullptr;
     double *dpart_ = nullptr, *dscal_ = nullptr;
     std::vector<void *> allocs_;

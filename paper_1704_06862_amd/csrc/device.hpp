@@ -15,6 +15,7 @@ struct BodyHost {
     IluFactors ilu;
     std::vector<RegionTables> tables;   // parallel to oct.regions
     int precond = SFMM_PRECOND_ILU0;
+    std::vector<cd> poly;               // roots of the polynomial preconditioner
 };
 
 struct StageTimes {

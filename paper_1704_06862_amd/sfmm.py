@@ -22,7 +22,7 @@ STATUS = {0: "SFMM_OK", 1: "SFMM_E_INVALID_ARG", 2: "SFMM_E_MESH", 3: "SFMM_E_OO
           5: "SFMM_E_NOT_CONVERGED", 6: "SFMM_E_BREAKDOWN", 7: "SFMM_E_UNSUPPORTED"}
 PREC_FP32, PREC_BF16_SPLIT, PREC_FP64 = 0, 1, 2
 PART_NEAR, PART_FAR, PART_ALL = 1, 2, 3
-PRECOND_ILU0, PRECOND_NONE, PRECOND_BLOCK_JACOBI = 0, 1, 2
+PRECOND_ILU0, PRECOND_NONE, PRECOND_BLOCK_JACOBI, PRECOND_POLY = 0, 1, 2, 3
 
 EXPORTED = ["sfmm_default_options", "sfmm_setup", "sfmm_destroy", "sfmm_last_error", "sfmm_set_stream",
             "sfmm_num_unknowns", "sfmm_edges", "sfmm_matvec", "sfmm_precond", "sfmm_planewave_rhs",
@@ -41,7 +41,8 @@ class sfmm_options(ctypes.Structure):
     _fields_ = [("finest_box", ctypes.c_double), ("n_levels", ctypes.c_int32), ("digits", ctypes.c_double),
                 ("extra_multipoles", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("gmres_restart", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("device", ctypes.c_int32), ("verbose", ctypes.c_int32), ("preconditioner", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("verbose", ctypes.c_int32), ("preconditioner", ctypes.c_int32),
+                ("poly_degree", ctypes.c_int32)]
 
 
 class sfmm_solve_info(ctypes.Structure):

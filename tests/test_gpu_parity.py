@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 sfmm = pytest.importorskip("paper_1704_06862_amd.sfmm")
 
-CFG1 = dict(finest_box=0.15, n_levels=3, extra_multipoles=5)
+CFG1 = dict(finest_box=0.15, n_levels=3, extra_multipoles=5, preconditioner=0)
 THETA = np.deg2rad(np.arange(181.0))
 
 
@@ -198,10 +198,44 @@ def test_multilevel_product_sampled_rows():
     ref = np.concatenate([ZE @ x[0], ZH @ x[0]])
     for prec in (sfmm.PREC_FP64, sfmm.PREC_FP32):
         print("setup multilevel", prec, flush=True)
-        with sfmm.Context([b], precision=prec, finest_box=0.25) as ctx:
+        with sfmm.Context([b], precision=prec, finest_box=0.25, extra_multipoles=2) as ctx:
             assert ctx.sfmm_describe()["levels"] == 4
             y = ctx.sfmm_matvec(x, np.zeros_like(x))[0]
         got = np.concatenate([y[test], y[m.n_edges + test]])
         err = rel(got, ref)
         print("multilevel prec", prec, "sampled-row rel err", err)
         assert err < 1e-3
+
+
+def _oracle_poly(cfg1, degree):
+    near = cfg1["pat"]
+    Zn = np.where(near, cfg1["Z"], 0)
+    th = krylov.leja_order(krylov.harmonic_ritz(lambda v: Zn @ v, krylov.golden_start(len(Zn)), degree))
+    return Zn, th
+
+
+def test_polynomial_preconditioner_fp64(cfg1):
+    Zn, th = _oracle_poly(cfg1, 16)
+    x = cfg1["x"][:1].copy()
+    ref = krylov.poly_apply(lambda v: Zn @ v, th, x[0])
+    with sfmm.Context([cfg1["body"]], precision=sfmm.PREC_FP64, finest_box=0.15, n_levels=3,
+                      preconditioner=sfmm.PRECOND_POLY, poly_degree=16) as ctx:
+        z = ctx.sfmm_precond(x, np.zeros_like(x))[0]
+    print("poly precond rel err", rel(z, ref))
+    assert rel(z, ref) < 1e-9
+
+
+def test_polynomial_preconditioned_solve_matches_oracle(cfg1):
+    Zn, th = _oracle_poly(cfg1, 16)
+    m, b, Z = cfg1["mesh"], cfg1["body"], cfg1["Z"]
+    kh, eh = mom.incidence(0.0, 0.0)
+    rhs = mom.planewave_rhs(m, b.frequency, kh, eh)
+    _, oinfo = krylov.gmres(lambda v: Z @ v, rhs, lambda v: krylov.poly_apply(lambda u: Zn @ u, th, v),
+                            restart=30, tol=1e-6)
+    x = np.zeros((1, len(rhs)), dtype=complex)
+    with sfmm.Context([b], precision=sfmm.PREC_FP64, finest_box=0.15, n_levels=3, extra_multipoles=5,
+                      preconditioner=sfmm.PRECOND_POLY, poly_degree=16) as ctx:
+        info = ctx.sfmm_solve(rhs[None, :].copy(), x)[0]
+    print("poly solve", info, "oracle its", oinfo.iterations)
+    assert info["converged"] and abs(info["iterations"] - oinfo.iterations) <= 2
+    assert rel(Z @ x[0], rhs) < 2e-3

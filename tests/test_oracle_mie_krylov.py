@@ -99,3 +99,39 @@ def test_gmres_solves_and_reports():
     # unrestarted GMRES converges in at most n steps
     _, info4 = krylov.gmres(lambda v: A @ v, b, restart=n, tol=1e-10, max_iters=n)
     assert info4.converged and info4.iterations <= n
+
+
+def test_full_degree_polynomial_is_the_inverse():
+    # the residual polynomial of n GMRES steps vanishes on the whole spectrum
+    n = 12
+    A = _test_matrix(n, seed=21)
+    th = krylov.leja_order(krylov.harmonic_ritz(lambda v: A @ v, krylov.golden_start(n), n))
+    assert np.allclose(np.sort_complex(th), np.sort_complex(np.linalg.eigvals(A)), atol=1e-8)
+    v = np.cos(np.arange(n)) + 1j
+    y = krylov.poly_apply(lambda u: A @ u, th, v)
+    assert np.allclose(y, np.linalg.solve(A, v), atol=1e-8)
+
+
+def test_polynomial_preconditioner_reduces_iterations():
+    n = 120
+    rng = np.random.default_rng(5)
+    A = np.diag(np.linspace(1, 50, n) * np.exp(0.3j * rng.standard_normal(n))) + \
+        0.05 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    b = np.ones(n, dtype=complex)
+    th = krylov.leja_order(krylov.harmonic_ritz(lambda v: A @ v, krylov.golden_start(n), 10))
+    _, i0 = krylov.gmres(lambda v: A @ v, b, restart=20, tol=1e-8, max_iters=2000)
+    _, i1 = krylov.gmres(lambda v: A @ v, b, lambda v: krylov.poly_apply(lambda u: A @ u, th, v),
+                         restart=20, tol=1e-8, max_iters=2000)
+    assert i1.converged and i1.iterations * 3 < i0.iterations
+    # order of the roots does not change the operator
+    v = np.sin(np.arange(n)) + 0j
+    y1 = krylov.poly_apply(lambda u: A @ u, th, v)
+    y2 = krylov.poly_apply(lambda u: A @ u, th[::-1], v)
+    assert np.allclose(y1, y2, rtol=1e-8)
+
+
+def test_golden_start_is_unit_modulus_and_deterministic():
+    v = krylov.golden_start(5)
+    assert np.allclose(np.abs(v), 1) and v[0] == 1
+    g = (np.sqrt(5) - 1) / 2
+    assert np.isclose(np.angle(v[1]), 2 * np.pi * g - 2 * np.pi)
