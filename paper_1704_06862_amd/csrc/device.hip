@@ -256,22 +256,24 @@ __global__ void __launch_bounds__(RWG) k_ilu(int box0, const int *__restrict__ b
 }
 
 // ---------------------------------------------------------------------------
-// Finest-level aggregation: S_b = sum_n s_n [et F_n J_n + ... ] (theta, phi)
+// Finest-level aggregation: S_b = sum_n s_n [et F_n J_n + ...] (theta, phi).
+// One workgroup per box, blockDim = K rounded up to a wavefront (<= 1024,
+// directions beyond it loop), the box's scaled excitations staged in LDS.
 template <typename T>
-__global__ void __launch_bounds__(WG) k_aggregate(int K, const int *__restrict__ edge_ptr,
-                                                  const int *__restrict__ edge_pos, const int *__restrict__ edge_sign,
-                                                  const cx<T> *__restrict__ tx, cx<T> et,
-                                                  const cx<T> *__restrict__ x, cx<T> *__restrict__ S) {
+__global__ void __launch_bounds__(1024) k_aggregate(int K, const int *__restrict__ edge_ptr,
+                                                    const int *__restrict__ edge_pos, const int *__restrict__ edge_sign,
+                                                    const cx<T> *__restrict__ tx, cx<T> et,
+                                                    const cx<T> *__restrict__ x, cx<T> *__restrict__ S) {
     __shared__ cx<T> js[128], ms[128];
     const int b = blockIdx.x;
     const int e0 = edge_ptr[b], e1 = edge_ptr[b + 1];
-    for (int k0 = 0; k0 < K; k0 += WG) {
+    for (int k0 = 0; k0 < K; k0 += blockDim.x) {
         const int k = k0 + threadIdx.x;
-        cx<T> st = {0, 0}, sp = {0, 0};
+        cx<T> st = {0, 0}, sp = {0, 0}, st2 = {0, 0}, sp2 = {0, 0};
         for (int c0 = e0; c0 < e1; c0 += 128) {
             const int cnt = min(128, e1 - c0);
             __syncthreads();
-            for (int t = threadIdx.x; t < cnt; t += WG) {
+            for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
                 int p = edge_pos[c0 + t];
                 T s = (T)edge_sign[c0 + t];
                 cx<T> xj = x[2 * p], xm = x[2 * p + 1];
@@ -281,20 +283,32 @@ __global__ void __launch_bounds__(WG) k_aggregate(int K, const int *__restrict__
             }
             __syncthreads();
             if (k < K) {
-                for (int t = 0; t < cnt; ++t) {
-                    const cx<T> *F = tx + (size_t)(c0 + t) * 2 * K;
-                    cx<T> ft = F[k], fp = F[K + k];
-                    cx<T> j = js[t], m = ms[t];
-                    cfma(st, ft, j);
-                    cfma(st, fp, m);
-                    cfma(sp, fp, j);
-                    cfms(sp, ft, m);
+                const cx<T> *F = tx + (size_t)c0 * 2 * K + k;
+                int t = 0;
+                for (; t + 1 < cnt; t += 2) {
+                    const cx<T> ft = F[(size_t)t * 2 * K], fp = F[(size_t)t * 2 * K + K];
+                    const cx<T> gt = F[(size_t)(t + 1) * 2 * K], gp = F[(size_t)(t + 1) * 2 * K + K];
+                    cfma(st, ft, js[t]);
+                    cfma(st, fp, ms[t]);
+                    cfma(sp, fp, js[t]);
+                    cfms(sp, ft, ms[t]);
+                    cfma(st2, gt, js[t + 1]);
+                    cfma(st2, gp, ms[t + 1]);
+                    cfma(sp2, gp, js[t + 1]);
+                    cfms(sp2, gt, ms[t + 1]);
+                }
+                if (t < cnt) {
+                    const cx<T> ft = F[(size_t)t * 2 * K], fp = F[(size_t)t * 2 * K + K];
+                    cfma(st, ft, js[t]);
+                    cfma(st, fp, ms[t]);
+                    cfma(sp, fp, js[t]);
+                    cfms(sp, ft, ms[t]);
                 }
             }
         }
         if (k < K) {
-            S[(size_t)b * 2 * K + k] = st;
-            S[(size_t)b * 2 * K + K + k] = sp;
+            S[(size_t)b * 2 * K + k] = {st.x + st2.x, st.y + st2.y};
+            S[(size_t)b * 2 * K + K + k] = {sp.x + sp2.x, sp.y + sp2.y};
         }
     }
 }
@@ -416,10 +430,13 @@ __global__ void k_dn_theta(int nchild, int nth_c, int nph_c, int nth_p, const T 
 }
 
 // ---------------------------------------------------------------------------
-// LDS-staged interpolation: one workgroup per parent box, children in turn,
-// one component at a time: child pattern -> LDS, theta stage -> LDS,
-// phi stage + shift accumulated into the parent pattern (no other workgroup
-// touches this parent).
+// LDS-staged interpolation.  One workgroup per (parent box, component, chunk
+// of UPR parent theta rows): for every child in turn the child pattern is
+// staged in LDS, the theta stage computes only the chunk's rows into LDS, and
+// the phi stage + shift accumulates the chunk's outputs in registers.
+constexpr int UPR = 4;      // parent theta rows per workgroup
+constexpr int UPMAX = 8;    // outputs per thread: UPR * nph_p <= WG * UPMAX
+
 template <typename T>
 __global__ void __launch_bounds__(WG) k_up_box(int nth_c, int nph_c, int nth_p, int nph_p, const T *__restrict__ A,
                                                const T *__restrict__ B, const T *__restrict__ Dt,
@@ -429,49 +446,60 @@ __global__ void __launch_bounds__(WG) k_up_box(int nth_c, int nph_c, int nth_p, 
     extern __shared__ unsigned char lds_raw[];
     const int Kc = nth_c * nph_c, Kp = nth_p * nph_p;
     cx<T> *fs = reinterpret_cast<cx<T> *>(lds_raw);      // [Kc]
-    cx<T> *ts = fs + Kc;                                   // [nth_p][nph_c]
-    const int P = blockIdx.x;
+    cx<T> *ts = fs + Kc;                                   // [UPR][nph_c]
+    const int nchunk = (nth_p + UPR - 1) / UPR;
+    const int P = blockIdx.x / (2 * nchunk);
+    const int comp = (blockIdx.x / nchunk) % 2;
+    const int I0 = (blockIdx.x % nchunk) * UPR;
+    const int nI = min(UPR, nth_p - I0);
+    const int nout = nI * nph_p;
     const int h = nph_c / 2;
-    for (int comp = 0; comp < 2; ++comp) {
-        cx<T> *out = Sp + ((size_t)P * 2 + comp) * Kp;
-        bool first = true;
-        for (int q = child_ptr[P]; q < child_ptr[P + 1]; ++q) {
-            const int c = child_idx[q];
-            const cx<T> *f = Sc + ((size_t)c * 2 + comp) * Kc;
-            __syncthreads();
-            for (int t = threadIdx.x; t < Kc; t += WG) fs[t] = f[t];
-            __syncthreads();
-            for (int t = threadIdx.x; t < nth_p * nph_c; t += WG) {
-                const int I = t / nph_c, j = t % nph_c;
-                const int j1 = j < h ? j : j - h, j2 = j1 + h;
-                const T *Pa = (j < h) ? A : B;
-                const T *Pb = (j < h) ? B : A;
-                cx<T> acc = {0, 0};
-                for (int i = 0; i < nth_c; ++i) {
-                    const T a = Pa[I * nth_c + i], b = Pb[I * nth_c + i];
-                    const cx<T> f1 = fs[i * nph_c + j1], f2 = fs[i * nph_c + j2];
-                    acc.x += a * f1.x + b * f2.x;
-                    acc.y += a * f1.y + b * f2.y;
-                }
-                ts[t] = acc;
+    cx<T> acc[UPMAX];
+#pragma unroll
+    for (int u = 0; u < UPMAX; ++u) acc[u] = {0, 0};
+    for (int q = child_ptr[P]; q < child_ptr[P + 1]; ++q) {
+        const int c = child_idx[q];
+        const cx<T> *f = Sc + ((size_t)c * 2 + comp) * Kc;
+        __syncthreads();
+        for (int t = threadIdx.x; t < Kc; t += WG) fs[t] = f[t];
+        __syncthreads();
+        for (int t = threadIdx.x; t < nI * nph_c; t += WG) {
+            const int I = I0 + t / nph_c, j = t % nph_c;
+            const int j1 = j < h ? j : j - h, j2 = j1 + h;
+            const T *Pa = (j < h) ? A : B;
+            const T *Pb = (j < h) ? B : A;
+            cx<T> a2 = {0, 0};
+            for (int i = 0; i < nth_c; ++i) {
+                const T a = Pa[I * nth_c + i], b = Pb[I * nth_c + i];
+                const cx<T> f1 = fs[i * nph_c + j1], f2 = fs[i * nph_c + j2];
+                a2.x += a * f1.x + b * f2.x;
+                a2.y += a * f1.y + b * f2.y;
             }
-            __syncthreads();
-            const cx<T> *sh = shift + (size_t)child_slot[c] * Kp;
-            for (int kk = threadIdx.x; kk < Kp; kk += WG) {
-                const int I = kk / nph_p, J = kk % nph_p;
-                const cx<T> *g = ts + I * nph_c;
+            ts[t] = a2;
+        }
+        __syncthreads();
+        const cx<T> *sh = shift + (size_t)child_slot[c] * Kp + I0 * nph_p;
+#pragma unroll
+        for (int u = 0; u < UPMAX; ++u) {
+            const int o = threadIdx.x + u * WG;
+            if (o < nout) {
+                const int Il = o / nph_p, J = o % nph_p;
+                const cx<T> *g = ts + Il * nph_c;
                 cx<T> v = {0, 0};
                 for (int j = 0; j < nph_c; ++j) {
-                    const T d = Dt[(size_t)j * nph_p + J];   // lanes read consecutive J
+                    const T d = Dt[(size_t)j * nph_p + J];
                     v.x += d * g[j].x;
                     v.y += d * g[j].y;
                 }
-                cx<T> o = first ? cx<T>{0, 0} : out[kk];
-                cfma(o, sh[kk], v);
-                out[kk] = o;
+                cfma(acc[u], sh[o], v);
             }
-            first = false;
         }
+    }
+    cx<T> *out = Sp + ((size_t)P * 2 + comp) * Kp + I0 * nph_p;
+#pragma unroll
+    for (int u = 0; u < UPMAX; ++u) {
+        const int o = threadIdx.x + u * WG;
+        if (o < nout) out[o] = acc[u];
     }
 }
 
@@ -528,20 +556,33 @@ __global__ void __launch_bounds__(WG) k_dn_box(int nth_c, int nph_c, int nth_p, 
 
 // ---------------------------------------------------------------------------
 // Diagonal translation over the interaction lists: G_b = sum T(X_bb') S_b'.
+// Threads are flattened over (box, direction) so no lane idles on short K.
 template <typename T>
-__global__ void __launch_bounds__(WG) k_translate(int K, const int *__restrict__ il_ptr,
+__global__ void __launch_bounds__(WG) k_translate(int nbox, int K, const int *__restrict__ il_ptr,
                                                   const int *__restrict__ il_src, const int *__restrict__ il_off,
                                                   const cx<T> *__restrict__ trans, const cx<T> *__restrict__ S,
                                                   cx<T> *__restrict__ G) {
-    const int b = blockIdx.y;
-    const int k = blockIdx.x * WG + threadIdx.x;
-    if (k >= K) return;
+    const int64_t id = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (id >= (int64_t)nbox * K) return;
+    const int b = (int)(id / K), k = (int)(id % K);
     cx<T> gt = {0, 0}, gp = {0, 0};
-    for (int q = il_ptr[b]; q < il_ptr[b + 1]; ++q) {
-        const int s = il_src[q];
-        const cx<T> t = trans[(size_t)il_off[q] * K + k];
-        cfma(gt, t, S[(size_t)s * 2 * K + k]);
-        cfma(gp, t, S[(size_t)s * 2 * K + K + k]);
+    const int q1 = il_ptr[b + 1];
+    int q = il_ptr[b];
+    for (; q + 1 < q1; q += 2) {
+        const int s0 = il_src[q], s1 = il_src[q + 1];
+        const cx<T> t0 = trans[(size_t)il_off[q] * K + k], t1 = trans[(size_t)il_off[q + 1] * K + k];
+        const cx<T> a0 = S[(size_t)s0 * 2 * K + k], b0 = S[(size_t)s0 * 2 * K + K + k];
+        const cx<T> a1 = S[(size_t)s1 * 2 * K + k], b1 = S[(size_t)s1 * 2 * K + K + k];
+        cfma(gt, t0, a0);
+        cfma(gp, t0, b0);
+        cfma(gt, t1, a1);
+        cfma(gp, t1, b1);
+    }
+    if (q < q1) {
+        const int s0 = il_src[q];
+        const cx<T> t0 = trans[(size_t)il_off[q] * K + k];
+        cfma(gt, t0, S[(size_t)s0 * 2 * K + k]);
+        cfma(gp, t0, S[(size_t)s0 * 2 * K + K + k]);
     }
     G[(size_t)b * 2 * K + k] = gt;
     G[(size_t)b * 2 * K + K + k] = gp;
@@ -913,15 +954,17 @@ class DeviceBodyT final : public DeviceBody {
         if ((parts & SFMM_PART_FAR) && f_ >= 2) {
             for (Reg &R : regs_) {
                 const int f = f_;
-                k_aggregate<T><<<R.nbf, WG, 0, stream_>>>(R.K[f], R.edge_ptr, R.edge_pos, R.edge_sign, R.tx, R.et, x, R.S[f]);
+                const int bs = std::min(1024, ((R.K[f] + 63) / 64) * 64);
+                k_aggregate<T><<<R.nbf, bs, 0, stream_>>>(R.K[f], R.edge_ptr, R.edge_pos, R.edge_sign, R.tx, R.et, x, R.S[f]);
                 LAUNCHCHK();
             }
             mark(2);
             for (Reg &R : regs_) {
                 for (int l = f_; l >= 3; --l) {
-                    size_t lds = ((size_t)R.K[l] + (size_t)R.nth[l - 1] * R.nph[l]) * sizeof(cx<T>);
-                    if (lds <= LDS_LIMIT) {
-                        k_up_box<T><<<R.nbox[l - 1], WG, lds, stream_>>>(R.nth[l], R.nph[l], R.nth[l - 1], R.nph[l - 1],
+                    size_t lds = ((size_t)R.K[l] + (size_t)UPR * R.nph[l]) * sizeof(cx<T>);
+                    if (lds <= LDS_LIMIT && UPR * R.nph[l - 1] <= WG * UPMAX) {
+                        const int nchunk = (R.nth[l - 1] + UPR - 1) / UPR;
+                        k_up_box<T><<<R.nbox[l - 1] * 2 * nchunk, WG, lds, stream_>>>(R.nth[l], R.nph[l], R.nth[l - 1], R.nph[l - 1],
                                                                         R.ipA[l], R.ipB[l], R.ipDt[l], R.child_ptr[l - 1],
                                                                         R.child_idx[l - 1], R.slot[l], R.sup[l], R.S[l],
                                                                         R.S[l - 1]);
@@ -943,9 +986,8 @@ class DeviceBodyT final : public DeviceBody {
             mark(3);
             for (Reg &R : regs_) {
                 for (int l = 2; l <= f_; ++l) {
-                    dim3 grid(nblocks(R.K[l]), R.nbox[l]);
-                    k_translate<T><<<grid, WG, 0, stream_>>>(R.K[l], R.il_ptr[l], R.il_src[l], R.il_off[l], R.trans[l],
-                                                             R.S[l], R.G[l]);
+                    k_translate<T><<<nblocks((int64_t)R.nbox[l] * R.K[l]), WG, 0, stream_>>>(
+                        R.nbox[l], R.K[l], R.il_ptr[l], R.il_src[l], R.il_off[l], R.trans[l], R.S[l], R.G[l]);
                     LAUNCHCHK();
                 }
             }
