@@ -42,6 +42,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-solve", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--batch", type=str, default="8,64",
+                   help="extra right-hand-side batch sizes measured outside the timed region")
     return p.parse_args()
 
 
@@ -108,6 +110,22 @@ def main():
     value = n * args.steps / dt
     print(f"matvec {ms:.3f} ms", file=sys.stderr, flush=True)
 
+    # batched products (outside the timed region): unknowns x RHS per second
+    batched = {}
+    for R in [int(v) for v in args.batch.split(",") if v]:
+        xr = torch.from_numpy(random_complex_vector(n, R, seed=99)).to("cuda")
+        yr = torch.zeros_like(xr)
+        ctx.sfmm_matvec(xr, yr)
+        torch.cuda.synchronize()
+        reps = max(2, 20 // R)
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            ctx.sfmm_matvec(xr, yr)
+        torch.cuda.synchronize()
+        batched[str(R)] = n * R * reps / (time.perf_counter() - t1)
+        del xr, yr
+    print("batched", batched, file=sys.stderr, flush=True)
+
     # per-stage HIP-event times (outside the timed region)
     ctx.sfmm_profile(1)
     for _ in range(10):
@@ -137,7 +155,8 @@ def main():
               "vs_baseline": None, "dtype": "f32", "data": "synthetic",
               "config": {"workload": "dielectric sphere r=2 lambda0, eps_r=2.56, icosphere s=5, 61,440 unknowns, "
                                      "5-level MLFMM, 0.25 lambda0 boxes, 3 digits, FP32, 1 RHS"},
-              "setup_s": round(setup_s, 2), "stages_ms": stages, "roofline": roofline}
+              "setup_s": round(setup_s, 2), "stages_ms": stages, "roofline": roofline,
+              "batched_unknowns_rhs_per_s": batched}
 
     if not args.no_solve:
         b = torch.zeros_like(x)

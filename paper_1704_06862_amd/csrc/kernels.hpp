@@ -1,0 +1,816 @@
+// gfx950 kernels of the MLFMM-accelerated PMCHWT product, its preconditioners
+// and the batched FP64 Krylov solver.
+//
+// Internal layout (right-hand-side minor): position p of the internal edge
+// order holds J_p and M~_p; unknown u = 2p + h (h = 0 for J, 1 for M~) of
+// right-hand side r lives at index u * R + r.  Level patterns are
+// [box][component][direction][r].  T is float or double; Krylov vectors are
+// complex FP64 and right-hand-side major.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sfmm {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ void cfma(cx<T> &acc, cx<T> a, cx<T> b) {
+    acc.x += a.x * b.x - a.y * b.y;
+    acc.y += a.x * b.y + a.y * b.x;
+}
+template <typename T>
+__device__ __forceinline__ void cfms(cx<T> &acc, cx<T> a, cx<T> b) {  // acc -= a b
+    acc.x -= a.x * b.x - a.y * b.y;
+    acc.y -= a.x * b.y + a.y * b.x;
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cconj(cx<T> a) {
+    return {a.x, -a.y};
+}
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+// sum over the lanes that share lane % RT (the other lane bits)
+template <int RT, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+    for (int o = 32; o >= RT; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+constexpr int WG = 256;
+constexpr int WAVES = WG / 64;
+constexpr int RW = 16;              // rows (wavefronts) per near/ILU workgroup
+constexpr int RWG = RW * 64;
+constexpr int UPR = 4;              // parent theta rows per upward workgroup
+constexpr int UPMAX = 8;            // outputs per thread in the upward kernel
+
+// ---------------------------------------------------------------------------
+// Layout conversions.
+
+// boundary FP64 [R][J(ne); M~(ne)] -> internal T
+template <typename T>
+__global__ void k_to_internal(const double2 *__restrict__ xb, const int *__restrict__ pos, int ne, int R,
+                              cx<T> *__restrict__ xi) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)ne * R) return;
+    const int e = (int)(id / R), r = (int)(id % R);
+    const int p = pos[e];
+    const double2 j = xb[(int64_t)r * 2 * ne + e], m = xb[(int64_t)r * 2 * ne + ne + e];
+    xi[(int64_t)(2 * p) * R + r] = {(T)j.x, (T)j.y};
+    xi[(int64_t)(2 * p + 1) * R + r] = {(T)m.x, (T)m.y};
+}
+
+template <typename T>
+__global__ void k_to_boundary(const cx<T> *__restrict__ yi, const int *__restrict__ pos, int ne, int R,
+                              double2 *__restrict__ yb) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)ne * R) return;
+    const int e = (int)(id / R), r = (int)(id % R);
+    const int p = pos[e];
+    const cx<T> j = yi[(int64_t)(2 * p) * R + r], m = yi[(int64_t)(2 * p + 1) * R + r];
+    yb[(int64_t)r * 2 * ne + e] = make_double2((double)j.x, (double)j.y);
+    yb[(int64_t)r * 2 * ne + ne + e] = make_double2((double)m.x, (double)m.y);
+}
+
+// Krylov FP64 vectors (slot s at base + act[s] * lds, internal order) <-> T [N][R]
+template <typename T>
+__global__ void k_gather(const double2 *__restrict__ base, int64_t lds, const int *__restrict__ act, int N, int R,
+                         cx<T> *__restrict__ out) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)N * R) return;
+    const int i = (int)(id / R), s = (int)(id % R);
+    const double2 v = base[(int64_t)act[s] * lds + i];
+    out[id] = {(T)v.x, (T)v.y};
+}
+
+template <typename T>
+__global__ void k_scatter(const cx<T> *__restrict__ in, int N, int R, const int *__restrict__ act, int64_t lds,
+                          double2 *__restrict__ base) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)N * R) return;
+    const int i = (int)(id / R), s = (int)(id % R);
+    const cx<T> v = in[id];
+    base[(int64_t)act[s] * lds + i] = make_double2((double)v.x, (double)v.y);
+}
+
+template <typename T>
+__global__ void k_zero(cx<T> *__restrict__ a, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = {0, 0};
+}
+
+// ---------------------------------------------------------------------------
+// Near-field product Y = Z_near X for a tile of RT right-hand sides.
+// Grid: (finest boxes, row groups of RW rows, RHS tiles).  The box's input
+// columns (both halves, RT right-hand sides) are staged in LDS; one wavefront
+// per row; lane = rr + RT * cg (cg: column group), so the RT lanes of a
+// column group share the matrix entries (one load serves RT products).
+// POLY = true fuses one product-form step of the polynomial preconditioner:
+// with Q = Z_near X,  acc += X / theta  and  Y = X - Q / theta.
+template <typename T, int RT, bool LDS, bool POLY>
+__global__ void __launch_bounds__(RWG) k_near(int R, const int *__restrict__ bstart, const int *__restrict__ col_ptr,
+                                              const int *__restrict__ cols, const int64_t *__restrict__ val_ptr,
+                                              const cx<T> *__restrict__ A, const cx<T> *__restrict__ B,
+                                              const cx<T> *__restrict__ C, const cx<T> *__restrict__ x,
+                                              cx<T> *__restrict__ y, cx<T> *__restrict__ acc, cx<T> inv_theta,
+                                              int write_y) {
+    extern __shared__ unsigned char lds_raw[];
+    cx<T> *xs = reinterpret_cast<cx<T> *>(lds_raw);     // [ncol][2][RT]
+    constexpr int NCG = 64 / RT;
+    const int b = blockIdx.x;
+    const int r0 = bstart[b], nrow = bstart[b + 1] - r0;
+    if ((int)blockIdx.y * RW >= nrow) return;            // uniform over the workgroup
+    const int c0 = col_ptr[b], ncol = col_ptr[b + 1] - c0;
+    const int rhs0 = blockIdx.z * RT;
+    if (LDS) {
+        for (int t = threadIdx.x; t < ncol * 2 * RT; t += RWG) {
+            const int c = t / (2 * RT), hr = t % (2 * RT);
+            const int p = cols[c0 + c];
+            xs[t] = x[(int64_t)(2 * p + hr / RT) * R + rhs0 + hr % RT];
+        }
+        __syncthreads();
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row = blockIdx.y * RW + wave;
+    if (row >= nrow) return;
+    const int rr = lane % RT, cg = lane / RT;
+    const int64_t rb = val_ptr[b] + (int64_t)row * ncol;
+    auto xin = [&](int c, cx<T> &xj, cx<T> &xm) {
+        if (LDS) {
+            xj = xs[(2 * c) * RT + rr];
+            xm = xs[(2 * c + 1) * RT + rr];
+        } else {
+            const int p = cols[c0 + c];
+            xj = x[(int64_t)(2 * p) * R + rhs0 + rr];
+            xm = x[(int64_t)(2 * p + 1) * R + rhs0 + rr];
+        }
+    };
+    cx<T> aE = {0, 0}, aH = {0, 0}, bE = {0, 0}, bH = {0, 0};
+    int c = cg;
+    for (; c + NCG < ncol; c += 2 * NCG) {
+        const cx<T> a0 = A[rb + c], b0 = B[rb + c], c0v = C[rb + c];
+        const cx<T> a1 = A[rb + c + NCG], b1 = B[rb + c + NCG], c1v = C[rb + c + NCG];
+        cx<T> xj0, xm0, xj1, xm1;
+        xin(c, xj0, xm0);
+        xin(c + NCG, xj1, xm1);
+        cfma(aE, a0, xj0);
+        cfms(aE, b0, xm0);
+        cfma(aH, b0, xj0);
+        cfma(aH, c0v, xm0);
+        cfma(bE, a1, xj1);
+        cfms(bE, b1, xm1);
+        cfma(bH, b1, xj1);
+        cfma(bH, c1v, xm1);
+    }
+    if (c < ncol) {
+        const cx<T> a0 = A[rb + c], b0 = B[rb + c], c0v = C[rb + c];
+        cx<T> xj0, xm0;
+        xin(c, xj0, xm0);
+        cfma(aE, a0, xj0);
+        cfms(aE, b0, xm0);
+        cfma(aH, b0, xj0);
+        cfma(aH, c0v, xm0);
+    }
+    aE.x = group_sum<RT>(aE.x + bE.x);
+    aE.y = group_sum<RT>(aE.y + bE.y);
+    aH.x = group_sum<RT>(aH.x + bH.x);
+    aH.y = group_sum<RT>(aH.y + bH.y);
+    if (lane < RT) {
+        const int64_t iE = (int64_t)(2 * (r0 + row)) * R + rhs0 + rr;
+        const int64_t iH = iE + R;
+        if (POLY) {
+            cx<T> xe = x[iE], xh = x[iH];
+            cx<T> ae = acc[iE], ah = acc[iH];
+            cfma(ae, xe, inv_theta);
+            cfma(ah, xh, inv_theta);
+            acc[iE] = ae;
+            acc[iH] = ah;
+            if (write_y) {
+                cfms(xe, aE, inv_theta);
+                cfms(xh, aH, inv_theta);
+                y[iE] = xe;
+                y[iH] = xh;
+            }
+        } else {
+            y[iE] = aE;
+            y[iH] = aH;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// ILU(0) sweep over a range of boxes (one colour, or all boxes for the
+// block-Jacobi variant): out_I = W_I [own_I ; other_K ...] for RT right-hand
+// sides; grid = boxes x row groups x RHS tiles, one wavefront per unknown row.
+template <typename T, int RT, bool LDS>
+__global__ void __launch_bounds__(RWG) k_ilu(int R, int box0, const int *__restrict__ bstart,
+                                             const int *__restrict__ col_ptr, const int *__restrict__ cols,
+                                             const int64_t *__restrict__ val_ptr, const cx<T> *__restrict__ W,
+                                             const cx<T> *__restrict__ own, const cx<T> *__restrict__ other,
+                                             cx<T> *__restrict__ out) {
+    extern __shared__ unsigned char lds_raw[];
+    cx<T> *us = reinterpret_cast<cx<T> *>(lds_raw);     // [2 nc][RT]
+    constexpr int NCG = 64 / RT;
+    const int I = box0 + blockIdx.x;
+    const int r0 = bstart[I], nI = bstart[I + 1] - r0;
+    if ((int)blockIdx.y * RW >= 2 * nI) return;
+    const int c0 = col_ptr[I], nc = col_ptr[I + 1] - c0;
+    const int nu = 2 * nc;
+    const int rhs0 = blockIdx.z * RT;
+    auto src_of = [&](int t) { return (t < nI) ? own : other; };
+    if (LDS) {
+        for (int t = threadIdx.x; t < nu * RT; t += RWG) {
+            const int cc = t / RT, rr = t % RT;
+            const int e = cc >> 1;
+            us[t] = src_of(e)[(int64_t)(2 * cols[c0 + e] + (cc & 1)) * R + rhs0 + rr];
+        }
+        __syncthreads();
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row = blockIdx.y * RW + wave;
+    if (row >= 2 * nI) return;
+    const int rr = lane % RT, cg = lane / RT;
+    const int64_t rb = val_ptr[I] + (int64_t)row * nu;
+    auto uin = [&](int cc) -> cx<T> {
+        if (LDS) return us[cc * RT + rr];
+        const int e = cc >> 1;
+        return src_of(e)[(int64_t)(2 * cols[c0 + e] + (cc & 1)) * R + rhs0 + rr];
+    };
+    cx<T> a0 = {0, 0}, a1 = {0, 0};
+    int cc = cg;
+    for (; cc + NCG < nu; cc += 2 * NCG) {
+        cfma(a0, W[rb + cc], uin(cc));
+        cfma(a1, W[rb + cc + NCG], uin(cc + NCG));
+    }
+    if (cc < nu) cfma(a0, W[rb + cc], uin(cc));
+    a0.x = group_sum<RT>(a0.x + a1.x);
+    a0.y = group_sum<RT>(a0.y + a1.y);
+    if (lane < RT) out[(int64_t)(2 * r0 + row) * R + rhs0 + rr] = a0;
+}
+
+// ---------------------------------------------------------------------------
+// Finest-level aggregation: S_b[c][k][r] = sum_n s_n (...)(theta, phi).
+// One workgroup per region box; threads over (direction, rhs) with rhs
+// fastest, so the R threads of a direction share each pattern load; the
+// box's scaled excitations are staged in LDS in chunks of ech edges.
+template <typename T>
+__global__ void __launch_bounds__(1024) k_aggregate(int K, int R, int ech, const int *__restrict__ edge_ptr,
+                                                    const int *__restrict__ edge_pos,
+                                                    const int *__restrict__ edge_sign, const cx<T> *__restrict__ tx,
+                                                    cx<T> et, const cx<T> *__restrict__ x, cx<T> *__restrict__ S) {
+    extern __shared__ unsigned char lds_raw[];
+    cx<T> *js = reinterpret_cast<cx<T> *>(lds_raw);      // [ech][R]
+    cx<T> *ms = js + (size_t)ech * R;
+    const int b = blockIdx.x;
+    const int e0 = edge_ptr[b], e1 = edge_ptr[b + 1];
+    const int KR = K * R;
+    for (int q0 = 0; q0 < KR; q0 += blockDim.x) {
+        const int q = q0 + threadIdx.x;
+        const int k = q / R, r = q % R;
+        cx<T> st = {0, 0}, sp = {0, 0}, st2 = {0, 0}, sp2 = {0, 0};
+        for (int c0 = e0; c0 < e1; c0 += ech) {
+            const int cnt = min(ech, e1 - c0);
+            __syncthreads();
+            for (int t = threadIdx.x; t < cnt * R; t += blockDim.x) {
+                const int te = t / R, tr = t % R;
+                const int p = edge_pos[c0 + te];
+                const T s = (T)edge_sign[c0 + te];
+                const cx<T> xj = x[(int64_t)(2 * p) * R + tr], xm = x[(int64_t)(2 * p + 1) * R + tr];
+                const cx<T> j = cmul(et, xj);
+                js[t] = {s * j.x, s * j.y};
+                ms[t] = {s * xm.x, s * xm.y};
+            }
+            __syncthreads();
+            if (q < KR) {
+                const cx<T> *F = tx + (size_t)c0 * 2 * K + k;
+                int t = 0;
+                for (; t + 1 < cnt; t += 2) {
+                    const cx<T> ft = F[(size_t)t * 2 * K], fp = F[(size_t)t * 2 * K + K];
+                    const cx<T> gt = F[(size_t)(t + 1) * 2 * K], gp = F[(size_t)(t + 1) * 2 * K + K];
+                    const cx<T> j0 = js[t * R + r], m0 = ms[t * R + r];
+                    const cx<T> j1 = js[(t + 1) * R + r], m1 = ms[(t + 1) * R + r];
+                    cfma(st, ft, j0);
+                    cfma(st, fp, m0);
+                    cfma(sp, fp, j0);
+                    cfms(sp, ft, m0);
+                    cfma(st2, gt, j1);
+                    cfma(st2, gp, m1);
+                    cfma(sp2, gp, j1);
+                    cfms(sp2, gt, m1);
+                }
+                if (t < cnt) {
+                    const cx<T> ft = F[(size_t)t * 2 * K], fp = F[(size_t)t * 2 * K + K];
+                    const cx<T> j0 = js[t * R + r], m0 = ms[t * R + r];
+                    cfma(st, ft, j0);
+                    cfma(st, fp, m0);
+                    cfma(sp, fp, j0);
+                    cfms(sp, ft, m0);
+                }
+            }
+        }
+        if (q < KR) {
+            S[((size_t)b * 2 * K + k) * R + r] = {st.x + st2.x, st.y + st2.y};
+            S[((size_t)b * 2 * K + K + k) * R + r] = {sp.x + sp2.x, sp.y + sp2.y};
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Upward pass.  One workgroup per (parent box, component, chunk of UPR parent
+// theta rows, tile of RT right-hand sides): for every child in turn its
+// pattern is staged in LDS, the theta stage computes the chunk's rows into LDS
+// (even/odd azimuthal parts paired through phi and phi + pi), and the phi
+// stage (transposed matrix, coalesced) plus the child shift accumulates the
+// chunk's outputs in registers.
+template <typename T, int RT>
+__global__ void __launch_bounds__(WG) k_up_box(int R, int nth_c, int nph_c, int nth_p, int nph_p,
+                                               const T *__restrict__ A, const T *__restrict__ B,
+                                               const T *__restrict__ Dt, const int *__restrict__ child_ptr,
+                                               const int *__restrict__ child_idx, const int *__restrict__ child_slot,
+                                               const cx<T> *__restrict__ shift, const cx<T> *__restrict__ Sc,
+                                               cx<T> *__restrict__ Sp) {
+    extern __shared__ unsigned char lds_raw[];
+    const int Kc = nth_c * nph_c, Kp = nth_p * nph_p;
+    cx<T> *fs = reinterpret_cast<cx<T> *>(lds_raw);      // [Kc][RT]
+    cx<T> *ts = fs + (size_t)Kc * RT;                     // [UPR][nph_c][RT]
+    const int nchunk = (nth_p + UPR - 1) / UPR;
+    const int ntile = R / RT;
+    int bid = blockIdx.x;
+    const int tile = bid % ntile;
+    bid /= ntile;
+    const int chunk = bid % nchunk;
+    bid /= nchunk;
+    const int comp = bid % 2;
+    const int P = bid / 2;
+    const int I0 = chunk * UPR;
+    const int nI = min(UPR, nth_p - I0);
+    const int nout = nI * nph_p * RT;
+    const int h = nph_c / 2;
+    const int rhs0 = tile * RT;
+    cx<T> acc[UPMAX];
+#pragma unroll
+    for (int u = 0; u < UPMAX; ++u) acc[u] = {0, 0};
+    for (int q = child_ptr[P]; q < child_ptr[P + 1]; ++q) {
+        const int c = child_idx[q];
+        const cx<T> *f = Sc + ((size_t)c * 2 + comp) * Kc * R;
+        __syncthreads();
+        for (int t = threadIdx.x; t < Kc * RT; t += WG) fs[t] = f[(size_t)(t / RT) * R + rhs0 + t % RT];
+        __syncthreads();
+        for (int t = threadIdx.x; t < nI * nph_c * RT; t += WG) {
+            const int rr = t % RT, tj = t / RT;
+            const int I = I0 + tj / nph_c, j = tj % nph_c;
+            const int j1 = j < h ? j : j - h, j2 = j1 + h;
+            const T *Pa = (j < h) ? A : B;
+            const T *Pb = (j < h) ? B : A;
+            cx<T> a2 = {0, 0};
+            for (int i = 0; i < nth_c; ++i) {
+                const T a = Pa[I * nth_c + i], b = Pb[I * nth_c + i];
+                const cx<T> f1 = fs[(i * nph_c + j1) * RT + rr], f2 = fs[(i * nph_c + j2) * RT + rr];
+                a2.x += a * f1.x + b * f2.x;
+                a2.y += a * f1.y + b * f2.y;
+            }
+            ts[t] = a2;
+        }
+        __syncthreads();
+        const cx<T> *sh = shift + (size_t)child_slot[c] * Kp + I0 * nph_p;
+#pragma unroll
+        for (int u = 0; u < UPMAX; ++u) {
+            const int o = threadIdx.x + u * WG;
+            if (o < nout) {
+                const int rr = o % RT, oj = o / RT;
+                const int Il = oj / nph_p, J = oj % nph_p;
+                const cx<T> *g = ts + (size_t)Il * nph_c * RT + rr;
+                cx<T> v = {0, 0};
+                for (int j = 0; j < nph_c; ++j) {
+                    const T d = Dt[(size_t)j * nph_p + J];
+                    v.x += d * g[j * RT].x;
+                    v.y += d * g[j * RT].y;
+                }
+                cfma(acc[u], sh[oj], v);
+            }
+        }
+    }
+    cx<T> *out = Sp + (((size_t)P * 2 + comp) * Kp + I0 * nph_p) * R + rhs0;
+#pragma unroll
+    for (int u = 0; u < UPMAX; ++u) {
+        const int o = threadIdx.x + u * WG;
+        if (o < nout) out[(size_t)(o / RT) * R + o % RT] = acc[u];
+    }
+}
+
+// Downward pass (transpose of the upward pass), one workgroup per (child box,
+// RHS tile): shifted parent pattern -> LDS, phi transpose -> LDS, theta
+// transpose accumulated into the child pattern.
+template <typename T, int RT>
+__global__ void __launch_bounds__(WG) k_dn_box(int R, int nth_c, int nph_c, int nth_p, int nph_p,
+                                               const T *__restrict__ A, const T *__restrict__ B,
+                                               const T *__restrict__ D, const int *__restrict__ parent,
+                                               const int *__restrict__ child_slot, const cx<T> *__restrict__ shift,
+                                               const cx<T> *__restrict__ Gp, cx<T> *__restrict__ Gc) {
+    extern __shared__ unsigned char lds_raw[];
+    const int Kc = nth_c * nph_c, Kp = nth_p * nph_p;
+    cx<T> *gs = reinterpret_cast<cx<T> *>(lds_raw);      // [Kp][RT]
+    cx<T> *ts = gs + (size_t)Kp * RT;                     // [nth_p][nph_c][RT]
+    const int ntile = R / RT;
+    const int c = blockIdx.x / ntile, tile = blockIdx.x % ntile;
+    const int rhs0 = tile * RT;
+    const int h = nph_c / 2;
+    const cx<T> *sh = shift + (size_t)child_slot[c] * Kp;
+    for (int comp = 0; comp < 2; ++comp) {
+        const cx<T> *g = Gp + ((size_t)parent[c] * 2 + comp) * Kp * R;
+        __syncthreads();
+        for (int t = threadIdx.x; t < Kp * RT; t += WG)
+            gs[t] = cmul(sh[t / RT], g[(size_t)(t / RT) * R + rhs0 + t % RT]);
+        __syncthreads();
+        for (int t = threadIdx.x; t < nth_p * nph_c * RT; t += WG) {
+            const int rr = t % RT, tj = t / RT;
+            const int I = tj / nph_c, j = tj % nph_c;
+            const cx<T> *row = gs + (size_t)I * nph_p * RT + rr;
+            cx<T> a2 = {0, 0};
+            for (int J = 0; J < nph_p; ++J) {
+                const T d = D[(size_t)J * nph_c + j];
+                a2.x += d * row[J * RT].x;
+                a2.y += d * row[J * RT].y;
+            }
+            ts[t] = a2;
+        }
+        __syncthreads();
+        cx<T> *out = Gc + ((size_t)c * 2 + comp) * Kc * R + rhs0;
+        for (int t = threadIdx.x; t < Kc * RT; t += WG) {
+            const int rr = t % RT, tk = t / RT;
+            const int i = tk / nph_c, j = tk % nph_c;
+            const int j1 = j < h ? j : j - h, j2 = j1 + h;
+            const T *Pa = (j < h) ? A : B;
+            const T *Pb = (j < h) ? B : A;
+            cx<T> a2 = out[(size_t)tk * R + rr];
+            for (int I = 0; I < nth_p; ++I) {
+                const T a = Pa[I * nth_c + i], b = Pb[I * nth_c + i];
+                const cx<T> g1 = ts[(I * nph_c + j1) * RT + rr], g2 = ts[(I * nph_c + j2) * RT + rr];
+                a2.x += a * g1.x + b * g2.x;
+                a2.y += a * g1.y + b * g2.y;
+            }
+            out[(size_t)tk * R + rr] = a2;
+        }
+    }
+}
+
+// Element-wise fallbacks for levels whose box patterns exceed the LDS budget.
+// theta stage: tmp[c][comp][I][j][r]
+template <typename T>
+__global__ void k_up_theta(int R, int nchild, int nth_c, int nph_c, int nth_p, const T *__restrict__ A,
+                           const T *__restrict__ B, const cx<T> *__restrict__ S, cx<T> *__restrict__ tmp) {
+    const int64_t total = (int64_t)nchild * 2 * nth_p * nph_c * R;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= total) return;
+    const int r = id % R;
+    int64_t q = id / R;
+    const int j = q % nph_c;
+    q /= nph_c;
+    const int I = q % nth_p;
+    const int64_t cc = q / nth_p;
+    const int h = nph_c / 2;
+    const int j1 = j < h ? j : j - h, j2 = j1 + h;
+    const T *Pa = (j < h) ? A : B;
+    const T *Pb = (j < h) ? B : A;
+    const cx<T> *f = S + cc * nth_c * nph_c * R + r;
+    cx<T> acc = {0, 0};
+    for (int i = 0; i < nth_c; ++i) {
+        const T a = Pa[I * nth_c + i], b = Pb[I * nth_c + i];
+        const cx<T> f1 = f[(size_t)(i * nph_c + j1) * R], f2 = f[(size_t)(i * nph_c + j2) * R];
+        acc.x += a * f1.x + b * f2.x;
+        acc.y += a * f1.y + b * f2.y;
+    }
+    tmp[id] = acc;
+}
+
+// phi stage + shift + sum over the children of every parent
+template <typename T>
+__global__ void k_up_phi(int R, int nparent, int nth_p, int nph_p, int nph_c, const T *__restrict__ Dt,
+                         const int *__restrict__ child_ptr, const int *__restrict__ child_idx,
+                         const int *__restrict__ child_slot, const cx<T> *__restrict__ shift,
+                         const cx<T> *__restrict__ tmp, cx<T> *__restrict__ Sp) {
+    const int Kp = nth_p * nph_p;
+    const int64_t total = (int64_t)nparent * 2 * Kp * R;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= total) return;
+    const int r = id % R;
+    int64_t q = id / R;
+    const int kk = q % Kp;
+    q /= Kp;
+    const int comp = q % 2;
+    const int P = q / 2;
+    const int I = kk / nph_p, J = kk % nph_p;
+    cx<T> out = {0, 0};
+    for (int qq = child_ptr[P]; qq < child_ptr[P + 1]; ++qq) {
+        const int c = child_idx[qq];
+        const cx<T> *g = tmp + ((((int64_t)c * 2 + comp) * nth_p + I) * nph_c) * R + r;
+        cx<T> v = {0, 0};
+        for (int j = 0; j < nph_c; ++j) {
+            const T d = Dt[(size_t)j * nph_p + J];
+            v.x += d * g[(size_t)j * R].x;
+            v.y += d * g[(size_t)j * R].y;
+        }
+        cfma(out, shift[child_slot[c] * Kp + kk], v);
+    }
+    Sp[id] = out;
+}
+
+// downward phi stage: tmp[c][comp][I][j][r] = sum_J D[J][j] shift_dn G_parent
+template <typename T>
+__global__ void k_dn_phi(int R, int nchild, int nth_p, int nph_p, int nph_c, const T *__restrict__ D,
+                         const int *__restrict__ parent, const int *__restrict__ child_slot,
+                         const cx<T> *__restrict__ shift, const cx<T> *__restrict__ Gp, cx<T> *__restrict__ tmp) {
+    const int Kp = nth_p * nph_p;
+    const int64_t total = (int64_t)nchild * 2 * nth_p * nph_c * R;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= total) return;
+    const int r = id % R;
+    int64_t q = id / R;
+    const int j = q % nph_c;
+    q /= nph_c;
+    const int I = q % nth_p;
+    q /= nth_p;
+    const int comp = q % 2;
+    const int c = q / 2;
+    const cx<T> *g = Gp + (((int64_t)parent[c] * 2 + comp) * Kp + I * nph_p) * R + r;
+    const cx<T> *sh = shift + child_slot[c] * Kp + I * nph_p;
+    cx<T> acc = {0, 0};
+    for (int J = 0; J < nph_p; ++J) {
+        const cx<T> v = cmul(sh[J], g[(size_t)J * R]);
+        const T d = D[J * nph_c + j];
+        acc.x += d * v.x;
+        acc.y += d * v.y;
+    }
+    tmp[id] = acc;
+}
+
+// downward theta stage, accumulated into G_child[c][comp][i][j][r]
+template <typename T>
+__global__ void k_dn_theta(int R, int nchild, int nth_c, int nph_c, int nth_p, const T *__restrict__ A,
+                           const T *__restrict__ B, const cx<T> *__restrict__ tmp, cx<T> *__restrict__ Gc) {
+    const int64_t total = (int64_t)nchild * 2 * nth_c * nph_c * R;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= total) return;
+    const int r = id % R;
+    int64_t q = id / R;
+    const int j = q % nph_c;
+    q /= nph_c;
+    const int i = q % nth_c;
+    const int64_t cc = q / nth_c;
+    const int h = nph_c / 2;
+    const int j1 = j < h ? j : j - h, j2 = j1 + h;
+    const T *Pa = (j < h) ? A : B;
+    const T *Pb = (j < h) ? B : A;
+    const cx<T> *g = tmp + cc * nth_p * nph_c * R + r;
+    cx<T> acc = Gc[id];
+    for (int I = 0; I < nth_p; ++I) {
+        const T a = Pa[I * nth_c + i], b = Pb[I * nth_c + i];
+        const cx<T> g1 = g[(size_t)(I * nph_c + j1) * R], g2 = g[(size_t)(I * nph_c + j2) * R];
+        acc.x += a * g1.x + b * g2.x;
+        acc.y += a * g1.y + b * g2.y;
+    }
+    Gc[id] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Diagonal translation over the interaction lists: G_b = sum T(X_bb') S_b'.
+// Threads are flattened over (box, direction, rhs), rhs fastest: the R
+// threads of a direction share every translation-table load.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_translate(int nbox, int K, int R, const int *__restrict__ il_ptr,
+                                                  const int *__restrict__ il_src, const int *__restrict__ il_off,
+                                                  const cx<T> *__restrict__ trans, const cx<T> *__restrict__ S,
+                                                  cx<T> *__restrict__ G) {
+    const int64_t id = (int64_t)blockIdx.x * WG + threadIdx.x;
+    const int64_t KR = (int64_t)K * R;
+    if (id >= (int64_t)nbox * KR) return;
+    const int b = (int)(id / KR);
+    const int kr = (int)(id % KR);
+    const int k = kr / R;
+    cx<T> gt = {0, 0}, gp = {0, 0};
+    const int q1 = il_ptr[b + 1];
+    int q = il_ptr[b];
+    for (; q + 1 < q1; q += 2) {
+        const int s0 = il_src[q], s1 = il_src[q + 1];
+        const cx<T> t0 = trans[(size_t)il_off[q] * K + k], t1 = trans[(size_t)il_off[q + 1] * K + k];
+        const cx<T> a0 = S[(size_t)s0 * 2 * KR + kr], b0 = S[(size_t)s0 * 2 * KR + KR + kr];
+        const cx<T> a1 = S[(size_t)s1 * 2 * KR + kr], b1 = S[(size_t)s1 * 2 * KR + KR + kr];
+        cfma(gt, t0, a0);
+        cfma(gp, t0, b0);
+        cfma(gt, t1, a1);
+        cfma(gp, t1, b1);
+    }
+    if (q < q1) {
+        const int s0 = il_src[q];
+        const cx<T> t0 = trans[(size_t)il_off[q] * K + k];
+        cfma(gt, t0, S[(size_t)s0 * 2 * KR + kr]);
+        cfma(gp, t0, S[(size_t)s0 * 2 * KR + KR + kr]);
+    }
+    G[(size_t)b * 2 * KR + kr] = gt;
+    G[(size_t)b * 2 * KR + KR + kr] = gp;
+}
+
+// ---------------------------------------------------------------------------
+// Receive at the finest level: y_E += s sum_k R.G, y_H += (s/et) sum_k R.(k x G)
+// for a tile of RT right-hand sides; one wavefront per edge, lane = rr + RT kg
+// (kg: direction group), reduction over the direction groups.
+template <typename T, int RT, bool LOSSY>
+__global__ void __launch_bounds__(WG) k_receive(int K, int R, const int *__restrict__ edge_ptr,
+                                                const int *__restrict__ edge_pos, const int *__restrict__ edge_sign,
+                                                const cx<T> *__restrict__ tx, const cx<T> *__restrict__ rx,
+                                                cx<T> inv_et, const cx<T> *__restrict__ G, cx<T> *__restrict__ y) {
+    constexpr int NKG = 64 / RT;
+    const int b = blockIdx.x;
+    const int rhs0 = blockIdx.y * RT;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int rr = lane % RT, kg = lane / RT;
+    const int64_t KR = (int64_t)K * R;
+    const cx<T> *g = G + (size_t)b * 2 * KR + rhs0 + rr;
+    for (int ie = edge_ptr[b] + wave; ie < edge_ptr[b + 1]; ie += WAVES) {
+        const cx<T> *Rp = (LOSSY ? rx : tx) + (size_t)ie * 2 * K;
+        cx<T> aE = {0, 0}, aH = {0, 0};
+        for (int k = kg; k < K; k += NKG) {
+            cx<T> rt = Rp[k], rp = Rp[K + k];
+            if (!LOSSY) {
+                rt = cconj(rt);
+                rp = cconj(rp);
+            }
+            const cx<T> gt = g[(size_t)k * R], gp = g[KR + (size_t)k * R];
+            cfma(aE, rt, gt);
+            cfma(aE, rp, gp);
+            cfms(aH, rt, gp);
+            cfma(aH, rp, gt);
+        }
+        aE.x = group_sum<RT>(aE.x);
+        aE.y = group_sum<RT>(aE.y);
+        aH.x = group_sum<RT>(aH.x);
+        aH.y = group_sum<RT>(aH.y);
+        if (lane < RT) {
+            const int p = edge_pos[ie];
+            const T s = (T)edge_sign[ie];
+            const cx<T> hh = cmul(aH, inv_et);
+            const int64_t iE = (int64_t)(2 * p) * R + rhs0 + rr, iH = iE + R;
+            cx<T> ye = y[iE], yh = y[iH];
+            ye.x += s * aE.x;
+            ye.y += s * aE.y;
+            yh.x += s * hh.x;
+            yh.y += s * hh.y;
+            y[iE] = ye;
+            y[iH] = yh;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Batched FP64 Krylov kernels.  Vector of slot s and basis index j is at
+// base + j * ldj + act[s] * lds (complex FP64, N entries, internal order).
+
+// partial[(s * nv + j) * nblk + blk] = sum over chunk of conj(V_j[s]) w[s]
+__global__ void __launch_bounds__(WG) k_bdots(const double2 *__restrict__ V, int64_t ldj, int64_t lds,
+                                              const double2 *__restrict__ W, const int *__restrict__ act, int N,
+                                              int nv, double2 *__restrict__ partial) {
+    __shared__ double2 red[WAVES];
+    const int j = blockIdx.y, s = blockIdx.z;
+    const double2 *v = V + (int64_t)j * ldj + (int64_t)act[s] * lds;
+    const double2 *w = W + (int64_t)act[s] * lds;
+    double sx = 0, sy = 0;
+    for (int i = blockIdx.x * WG + threadIdx.x; i < N; i += gridDim.x * WG) {
+        const double2 a = v[i], b = w[i];
+        sx += a.x * b.x + a.y * b.y;
+        sy += a.x * b.y - a.y * b.x;
+    }
+    sx = wave_sum(sx);
+    sy = wave_sum(sy);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = make_double2(sx, sy);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double2 t = red[0];
+        for (int q = 1; q < WAVES; ++q) {
+            t.x += red[q].x;
+            t.y += red[q].y;
+        }
+        partial[((int64_t)s * nv + j) * gridDim.x + blockIdx.x] = t;
+    }
+}
+
+// out[i] = sum_b partial[i][b]   (one wavefront per i, fixed order)
+__global__ void k_sum_partials(const double2 *__restrict__ partial, int nblk, double2 *__restrict__ out) {
+    const int i = blockIdx.x, lane = threadIdx.x;
+    double sx = 0, sy = 0;
+    for (int b = lane; b < nblk; b += 64) {
+        sx += partial[(int64_t)i * nblk + b].x;
+        sy += partial[(int64_t)i * nblk + b].y;
+    }
+    sx = wave_sum(sx);
+    sy = wave_sum(sy);
+    if (lane == 0) out[i] = make_double2(sx, sy);
+}
+
+// w[s] -= sum_j V_j[s] h[s][j]
+__global__ void k_bsub(const double2 *__restrict__ V, int64_t ldj, int64_t lds, int nv, const int *__restrict__ act,
+                       int N, const double2 *__restrict__ h, double2 *__restrict__ W) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, s = blockIdx.y;
+    if (i >= N) return;
+    double2 *w = W + (int64_t)act[s] * lds;
+    double2 acc = w[i];
+    for (int j = 0; j < nv; ++j) {
+        const double2 v = V[(int64_t)j * ldj + (int64_t)act[s] * lds + i], c = h[(int64_t)s * nv + j];
+        acc.x -= v.x * c.x - v.y * c.y;
+        acc.y -= v.x * c.y + v.y * c.x;
+    }
+    w[i] = acc;
+}
+
+// x[s] += sum_{j < cnt[s]} Z_j[s] y[s][j]   (y has stride nv per slot)
+__global__ void k_bupdate(const double2 *__restrict__ Z, int64_t ldj, int64_t lds, int nv, const int *__restrict__ cnt,
+                          const int *__restrict__ act, int N, const double2 *__restrict__ y, double2 *__restrict__ X) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, s = blockIdx.y;
+    if (i >= N) return;
+    double2 *x = X + (int64_t)act[s] * lds;
+    double2 acc = x[i];
+    for (int j = 0; j < cnt[s]; ++j) {
+        const double2 v = Z[(int64_t)j * ldj + (int64_t)act[s] * lds + i], c = y[(int64_t)s * nv + j];
+        acc.x += v.x * c.x - v.y * c.y;
+        acc.y += v.x * c.y + v.y * c.x;
+    }
+    x[i] = acc;
+}
+
+// partial[s][blk] = sum |w[s]|^2
+__global__ void __launch_bounds__(WG) k_bnorm2(const double2 *__restrict__ W, int64_t lds, const int *__restrict__ act,
+                                               int N, double *__restrict__ partial) {
+    __shared__ double red[WAVES];
+    const int s = blockIdx.y;
+    const double2 *w = W + (int64_t)act[s] * lds;
+    double acc = 0;
+    for (int i = blockIdx.x * WG + threadIdx.x; i < N; i += gridDim.x * WG) acc += w[i].x * w[i].x + w[i].y * w[i].y;
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0;
+        for (int q = 0; q < WAVES; ++q) t += red[q];
+        partial[(int64_t)s * gridDim.x + blockIdx.x] = t;
+    }
+}
+
+__global__ void k_sum_real(const double *__restrict__ partial, int nblk, double *__restrict__ out) {
+    const int i = blockIdx.x, lane = threadIdx.x;
+    double acc = 0;
+    for (int b = lane; b < nblk; b += 64) acc += partial[(int64_t)i * nblk + b];
+    acc = wave_sum(acc);
+    if (lane == 0) out[i] = acc;
+}
+
+// w[s] *= a[s]
+__global__ void k_bscale(const double *__restrict__ a, const int *__restrict__ act, int64_t lds, int N,
+                         double2 *__restrict__ W) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, s = blockIdx.y;
+    if (i >= N) return;
+    double2 *w = W + (int64_t)act[s] * lds;
+    w[i] = make_double2(a[s] * w[i].x, a[s] * w[i].y);
+}
+
+// y[s] = b[s] - y[s]
+__global__ void k_brsub(const double2 *__restrict__ Bv, const int *__restrict__ act, int64_t lds, int N,
+                        double2 *__restrict__ Y) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, s = blockIdx.y;
+    if (i >= N) return;
+    const double2 b = Bv[(int64_t)act[s] * lds + i];
+    double2 *y = Y + (int64_t)act[s] * lds;
+    y[i] = make_double2(b.x - y[i].x, b.y - y[i].y);
+}
+
+// boundary FP64 [2E] <-> internal FP64 [2E] for one vector
+__global__ void k_perm_in(const double2 *__restrict__ xb, const int *__restrict__ pos, int ne,
+                          double2 *__restrict__ xi) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    const int p = pos[e];
+    xi[2 * p] = xb[e];
+    xi[2 * p + 1] = xb[ne + e];
+}
+__global__ void k_perm_out(const double2 *__restrict__ xi, const int *__restrict__ pos, int ne,
+                           double2 *__restrict__ xb) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    const int p = pos[e];
+    xb[e] = xi[2 * p];
+    xb[ne + e] = xi[2 * p + 1];
+}
+
+}  // namespace sfmm

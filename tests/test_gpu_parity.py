@@ -85,12 +85,32 @@ def test_full_product_matches_dense(cfg1, ctx64, ctx32, prec):
     assert np.linalg.norm(yf) > 0.03 * np.linalg.norm(ref)
 
 
-def test_batched_rhs_equals_single(cfg1, ctx32):
-    x = cfg1["x"]
-    y2 = ctx32.sfmm_matvec(x, np.zeros_like(x))
-    y0 = ctx32.sfmm_matvec(np.ascontiguousarray(x[:1]), np.zeros_like(x[:1]))
-    y1 = ctx32.sfmm_matvec(np.ascontiguousarray(x[1:]), np.zeros_like(x[1:]))
-    assert np.array_equal(y2, np.concatenate([y0, y1]))
+def test_batched_rhs_equals_single(cfg1, ctx32, ctx64):
+    # a batch runs the same arithmetic per right-hand side; only the order of
+    # the partial sums across lanes differs (in FP32 at these 0.15-wavelength
+    # boxes the finest translations amplify that reordering to ~1e-5)
+    rng = np.random.default_rng(3)
+    xb = random_complex_vector(cfg1["x"].shape[1], 8, seed=21)
+    for ctx, tol in ((ctx32, 3e-5), (ctx64, 1e-13)):
+        yb = ctx.sfmm_matvec(xb, np.zeros_like(xb))
+        zb = ctx.sfmm_precond(xb, np.zeros_like(xb))
+        for r in rng.choice(8, 3, replace=False):
+            y1 = ctx.sfmm_matvec(np.ascontiguousarray(xb[r:r + 1]), np.zeros_like(xb[:1]))[0]
+            z1 = ctx.sfmm_precond(np.ascontiguousarray(xb[r:r + 1]), np.zeros_like(xb[:1]))[0]
+            assert rel(yb[r], y1) < tol and rel(zb[r], z1) < tol
+
+
+def test_batched_solve_matches_single_solves(cfg1, ctx64):
+    m, b = cfg1["mesh"], cfg1["body"]
+    angles = np.array([[0.0, 0.0], [0.7, 0.3], [2.0, 1.0]])
+    rhs = ctx64.sfmm_planewave_rhs(angles, np.zeros((3, 2 * m.n_edges), dtype=complex))
+    xb = np.zeros_like(rhs)
+    infos = ctx64.sfmm_solve(rhs, xb)
+    for r in range(3):
+        x1 = np.zeros_like(rhs[:1])
+        i1 = ctx64.sfmm_solve(np.ascontiguousarray(rhs[r:r + 1]), x1)[0]
+        assert infos[r]["converged"] and abs(infos[r]["iterations"] - i1["iterations"]) <= 1
+        assert rel(xb[r], x1[0]) < 1e-5
 
 
 def test_ilu_preconditioner_fp64(cfg1, ctx64):
