@@ -108,7 +108,9 @@ typedef struct {
     int32_t converged;        /* 1 if ||b - Z x|| / ||b|| <= tol                        */
     int32_t iterations;       /* Arnoldi steps (each one preconditioned product)        */
     int32_t restarts;
+    int32_t guess_used;       /* 1 if the supplied x0 was kept (see sfmm_solve)         */
     double true_residual;     /* ||b - Z x|| / ||b|| at exit, recomputed explicitly     */
+    double initial_residual;  /* ||b - Z x0|| / ||b|| of the supplied x0 (1 if none)    */
     double seconds;           /* wall time of the solve                                 */
 } sfmm_solve_info;
 
@@ -159,10 +161,18 @@ sfmm_status sfmm_precond(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void 
 sfmm_status sfmm_planewave_rhs(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const double *angles,
                                const double *pol, void *b, int32_t on_device);
 
-/* Solve Z x = b with right-preconditioned restarted GMRES(m) in FP64 and
- * the ILU(0) preconditioner.  x0 = NULL starts from zero, otherwise from
- * x0.  info [n_rhs] may be NULL.  Returns SFMM_E_NOT_CONVERGED (x holds the
- * last iterate) if any right-hand side misses the tolerance. */
+/* Solve Z x = b with restarted flexible GMRES(m) (Saad 1993): Arnoldi with
+ * classical Gram-Schmidt applied twice, Givens rotations and the
+ * least-squares update in FP64, the preconditioner of sfmm_options applied on
+ * the right in the product precision.  Right-hand sides are iterated in
+ * lockstep, up to 64 at a time; converged ones leave the batch.  Convergence
+ * is declared only on the explicitly recomputed residual ||b - Z x|| / ||b||
+ * <= tol.  x0 = NULL starts from zero.  A supplied x0 (for instance from
+ * sfmm_guess_predict) is judged by its true residual: if ||b - Z x0|| is not
+ * below ||b|| the right-hand side starts from zero instead, so a poor guess
+ * never costs more than one product.  info [n_rhs] may be NULL.  Returns
+ * SFMM_E_NOT_CONVERGED (x holds the last iterate) if any right-hand side
+ * misses the tolerance. */
 sfmm_status sfmm_solve(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void *b, void *x,
                        const void *x0, sfmm_solve_info *info, int32_t on_device);
 
@@ -171,6 +181,51 @@ sfmm_status sfmm_solve(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void *b
  * theta_phi and sigma are host arrays. */
 sfmm_status sfmm_rcs(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void *x, int32_t n_dirs,
                      const double *theta_phi, double *sigma, int32_t on_device);
+
+/* Learned GMRES initial guess (an addition to the paper's method; the paper
+ * starts GMRES from zero).  sfmm_guess_fit trains, on the device, a network
+ * that maps an incidence to the currents:
+ *   POD basis U: the r leading left singular vectors of the n training
+ *     solutions x (Gram matrix on the device, Hermitian Jacobi on the host);
+ *   features: cos/sin(m theta), cos/sin(m phi) for m = 1..M and
+ *     Re/Im(U^H b) / ||b||, b the plane-wave right-hand side of the angle;
+ *   network: two tanh hidden layers and a linear output of the standardised
+ *     Re/Im(U^H x) / ||b||; mean-squared error, Adam with a cosine decay;
+ *     GEMM operands rounded to bfloat16 with FP32 accumulation, FP32 weights.
+ * sfmm_guess_predict returns x0 = U c ||b|| for new incidences, to be passed
+ * to sfmm_solve, which keeps it only if it lowers the true residual.
+ * angles [n][2] (theta, phi) and pol [n] follow sfmm_planewave_rhs; x and x0
+ * are [n][2E] complex in boundary order, on the device if on_device.
+ * fit: 1 <= n <= 512; *final_loss (may be NULL) receives the training loss.
+ * Errors: SFMM_E_INVALID_ARG (sizes, options, predict before fit). */
+typedef struct {
+    int32_t rank;       /* POD basis size r (clamped to n and to the resolved rank) */
+    int32_t harmonics;  /* M angle harmonics                                        */
+    int32_t hidden;     /* width of both tanh hidden layers                         */
+    int32_t epochs;     /* full-batch Adam steps                                    */
+    double lr;          /* peak Adam step size                                      */
+    uint64_t seed;      /* SplitMix64 seed of the uniform weight initialisation     */
+} sfmm_guess_options;
+
+void sfmm_guess_default_options(sfmm_guess_options *opt);
+sfmm_status sfmm_guess_fit(sfmm_ctx *ctx, int32_t body, int32_t n, const double *angles, const double *pol,
+                           const void *x, const sfmm_guess_options *opt, double *final_loss, int32_t on_device);
+sfmm_status sfmm_guess_predict(sfmm_ctx *ctx, int32_t body, int32_t n, const double *angles, const double *pol,
+                               void *x0, int32_t on_device);
+
+/* The network kernels of the learned guess on their own, for checking: an
+ * MLP with layer sizes sizes[0..n_sizes-1] (tanh hidden layers, linear
+ * output) and parameters params (host; per layer W [in][out] row-major then
+ * b [out], FP32) on a batch X [batch][sizes[0]] with targets
+ * Y [batch][sizes[n_sizes-1]].  Computes, on GPU `device`, the output out
+ * (may be NULL) and the loss 0.5/batch sum ||f(X) - Y||^2 with its gradient
+ * grads (may be NULL) at the given parameters, then takes `steps` Adam steps
+ * (beta1 0.9, beta2 0.999, eps 1e-8, step size lr) and writes the new
+ * parameters back into params.  loss [steps + 1] receives the loss before
+ * each step and after the last.  Errors: SFMM_E_INVALID_ARG, SFMM_E_DEVICE. */
+sfmm_status sfmm_mlp_train(int32_t device, int32_t n_sizes, const int32_t *sizes, float *params, int32_t batch,
+                           const float *X, const float *Y, int32_t steps, double lr, double *loss, float *grads,
+                           float *out);
 
 /* Diagnostics: rows of the FP64 near-field matrix (before the cast to the
  * product precision), in boundary layout: out[i] = [E row; H row] of edge

@@ -9,6 +9,7 @@
 #include <string>
 
 #include "device.hpp"
+#include "guess.hpp"
 
 using namespace sfmm;
 
@@ -16,6 +17,7 @@ struct sfmm_ctx {
     sfmm_options opt{};
     std::vector<std::unique_ptr<BodyHost>> bodies;
     std::vector<std::unique_ptr<DeviceBody>> dev;
+    std::vector<std::unique_ptr<Guess>> guess;
     void *stream = nullptr;
     std::string err;
     bool poisoned = false;
@@ -145,6 +147,7 @@ sfmm_status sfmm_setup(const sfmm_body *bodies, int32_t n_bodies, const sfmm_opt
 void sfmm_destroy(sfmm_ctx *ctx) {
     if (!ctx) return;
     try {
+        ctx->guess.clear();
         ctx->dev.clear();
     } catch (...) {
     }
@@ -159,6 +162,8 @@ sfmm_status sfmm_set_stream(sfmm_ctx *ctx, void *stream) {
         ctx->stream = stream;
         for (auto &d : ctx->dev)
             if (d) d->set_stream(stream);
+        for (auto &g : ctx->guess)
+            if (g) g->set_stream(stream);
     });
 }
 
@@ -347,6 +352,99 @@ sfmm_status sfmm_profile(sfmm_ctx *ctx, int32_t enable, double *t, int64_t *n) {
             if (t) t[i] = acc.n[i] ? acc.ms[i] / acc.n[i] : 0.0;
             if (n) n[i] = acc.n[i];
         }
+    });
+}
+
+void sfmm_guess_default_options(sfmm_guess_options *o) {
+    if (!o) return;
+    const GuessOptions d{};
+    o->rank = d.rank;
+    o->harmonics = d.harmonics;
+    o->hidden = d.hidden;
+    o->epochs = d.epochs;
+    o->lr = d.lr;
+    o->seed = d.seed;
+}
+
+sfmm_status sfmm_guess_fit(sfmm_ctx *ctx, int32_t body, int32_t n, const double *angles, const double *pol,
+                           const void *x, const sfmm_guess_options *opt, double *final_loss, int32_t on_device) {
+    return guarded(ctx, [&] {
+        DeviceBody &d = dev_of(ctx, body);
+        if (n <= 0 || !angles || !x) throw Error(SFMM_E_INVALID_ARG, "bad arguments");
+        sfmm_guess_options go;
+        sfmm_guess_default_options(&go);
+        if (opt) go = *opt;
+        GuessOptions g;
+        g.rank = go.rank;
+        g.harmonics = go.harmonics;
+        g.hidden = go.hidden;
+        g.epochs = go.epochs;
+        g.lr = go.lr;
+        g.seed = go.seed;
+        const int N = 2 * ctx->bodies[body]->mesh.ne;
+        const size_t bytes = (size_t)n * N * 2 * sizeof(double);
+        Staged db(bytes);
+        d.planewave_rhs(n, angles, pol, db.p);
+        std::unique_ptr<Staged> dx;
+        const void *xd = x;
+        if (!on_device) {
+            dx = std::make_unique<Staged>(bytes);
+            copy_h2d(dx->p, x, bytes, ctx->stream);
+            xd = dx->p;
+        }
+        if (ctx->guess.size() < ctx->bodies.size()) ctx->guess.resize(ctx->bodies.size());
+        auto gs = std::make_unique<Guess>(N, ctx->stream);
+        const double loss = gs->fit(n, angles, db.p, xd, g);
+        ctx->guess[body] = std::move(gs);
+        if (final_loss) *final_loss = loss;
+    });
+}
+
+sfmm_status sfmm_guess_predict(sfmm_ctx *ctx, int32_t body, int32_t n, const double *angles, const double *pol,
+                               void *x0, int32_t on_device) {
+    return guarded(ctx, [&] {
+        DeviceBody &d = dev_of(ctx, body);
+        if (n <= 0 || !angles || !x0) throw Error(SFMM_E_INVALID_ARG, "bad arguments");
+        if ((int)ctx->guess.size() <= body || !ctx->guess[body])
+            throw Error(SFMM_E_INVALID_ARG, "learned guess is not trained for this body (call sfmm_guess_fit)");
+        const int N = 2 * ctx->bodies[body]->mesh.ne;
+        const size_t bytes = (size_t)n * N * 2 * sizeof(double);
+        Staged db(bytes);
+        d.planewave_rhs(n, angles, pol, db.p);
+        if (on_device) {
+            ctx->guess[body]->predict(n, angles, db.p, x0);
+        } else {
+            Staged dx(bytes);
+            ctx->guess[body]->predict(n, angles, db.p, dx.p);
+            copy_d2h(x0, dx.p, bytes, ctx->stream);
+        }
+    });
+}
+
+sfmm_status sfmm_mlp_train(int32_t device, int32_t n_sizes, const int32_t *sizes, float *params, int32_t batch,
+                           const float *X, const float *Y, int32_t steps, double lr, double *loss, float *grads,
+                           float *out) {
+    return guarded(nullptr, [&] {
+        if (n_sizes < 2 || n_sizes > 16 || !sizes || !params || batch <= 0 || !X || !Y || steps < 0)
+            throw Error(SFMM_E_INVALID_ARG, "bad arguments");
+        std::vector<int> sz(sizes, sizes + n_sizes);
+        check_device(device);
+        use_device(device);
+        Mlp net(sz, nullptr);
+        net.set_params(params);
+        const size_t nin = (size_t)batch * sz.front(), nout = (size_t)batch * sz.back();
+        Staged dX(sizeof(float) * nin), dY(sizeof(float) * nout);
+        copy_h2d(dX.p, X, sizeof(float) * nin, nullptr);
+        copy_h2d(dY.p, Y, sizeof(float) * nout, nullptr);
+        const float *fx = (const float *)dX.p, *fy = (const float *)dY.p;
+        if (out) copy_d2h(out, net.forward(batch, fx), sizeof(float) * nout, nullptr);
+        for (int32_t t = 0; t <= steps; ++t) {
+            const double l = net.loss_grad(batch, fx, fy, loss != nullptr);
+            if (loss) loss[t] = l;
+            if (t == 0 && grads) net.get_grads(grads);
+            if (t < steps) net.adam_step(lr);
+        }
+        if (steps > 0) net.get_params(params);
     });
 }
 

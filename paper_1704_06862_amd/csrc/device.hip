@@ -501,8 +501,8 @@ class DeviceBodyT final : public DeviceBody {
             for (int s = 0; s < R; ++s) all[s] = s;
             upload_act(all);
             std::vector<double> nb = norms(kb_, R);
-            std::vector<int> its(R, 0), restarts(R, 0);
-            std::vector<double> rel(R, 0.0);
+            std::vector<int> its(R, 0), restarts(R, 0), used(R, 0);
+            std::vector<double> rel(R, 0.0), rel0(R, 1.0);
             std::vector<char> conv(R, 0);
             for (int s = 0; s < R; ++s)
                 if (nb[s] == 0.0) conv[s] = 1;
@@ -526,8 +526,25 @@ class DeviceBodyT final : public DeviceBody {
                     k_brsub<<<dim3(nblocks(N), Ra), WG, 0, stream_>>>(kb_, dact_, N, N, V0);
                     LAUNCHCHK();
                 }
+                const bool judge = first && x0_dev;
                 first = false;
                 std::vector<double> beta = norms(V0, Ra);
+                if (judge) {
+                    // the true residual judges a supplied guess: one that is no
+                    // better than zero is dropped and the slot starts from zero
+                    for (int a = 0; a < Ra; ++a) {
+                        const int s = act[a];
+                        rel0[s] = beta[a] / nb[s];
+                        if (rel0[s] < 1.0) {
+                            used[s] = 1;
+                            continue;
+                        }
+                        HIPCHK(hipMemsetAsync(kx_ + (size_t)s * N, 0, sizeof(double2) * N, stream_));
+                        HIPCHK(hipMemcpyAsync(V0 + (size_t)s * N, kb_ + (size_t)s * N, sizeof(double2) * N,
+                                              hipMemcpyDeviceToDevice, stream_));
+                        beta[a] = nb[s];
+                    }
+                }
                 std::vector<int> next;
                 for (int a = 0; a < Ra; ++a) {
                     const int s = act[a];
@@ -655,7 +672,9 @@ class DeviceBodyT final : public DeviceBody {
                     info[c0 + s].converged = conv[s] ? 1 : 0;
                     info[c0 + s].iterations = its[s];
                     info[c0 + s].restarts = restarts[s];
+                    info[c0 + s].guess_used = used[s];
                     info[c0 + s].true_residual = rel[s];
+                    info[c0 + s].initial_residual = rel0[s];
                     info[c0 + s].seconds = secs;
                 }
                 all_ok = all_ok && conv[s];

@@ -1,0 +1,102 @@
+// Learned initial guess: device MLP with hand-written kernels, POD helpers.
+#pragma once
+
+#include <cstdint>
+#include <memory>
+#include <vector>
+
+#include "core.hpp"
+
+namespace sfmm {
+
+int64_t mlp_param_count(const std::vector<int> &sizes);
+
+// make `device` current for the calling thread
+void use_device(int device);
+
+// Multilayer perceptron with tanh hidden layers and a linear output layer.
+// Parameters: for every layer W [in][out] row-major, then b [out] (FP32).
+class Mlp {
+  public:
+    Mlp(const std::vector<int> &sizes, void *stream);
+    ~Mlp();
+    Mlp(const Mlp &) = delete;
+    Mlp &operator=(const Mlp &) = delete;
+    int64_t n_params() const { return np_; }
+    const std::vector<int> &sizes() const { return sizes_; }
+    void set_stream(void *s) { stream_ = s; }
+    void init_uniform(uint64_t seed);
+    void set_params(const float *host);
+    void get_params(float *host) const;
+    void get_grads(float *host) const;
+    // X: device [B][in]; returns device pointer to the [B][out] output
+    const float *forward(int B, const float *X);
+    // 0.5/B sum ||f(X) - Y||^2 and the gradients (kept on the device); with
+    // want_loss = false the loss is not read back (no host synchronisation)
+    // and NaN is returned
+    double loss_grad(int B, const float *X, const float *Y, bool want_loss = true);
+    void adam_step(double lr, double b1 = 0.9, double b2 = 0.999, double eps = 1e-8);
+
+  private:
+    void ensure(int B);
+    std::vector<int> sizes_;
+    void *stream_;
+    int64_t np_ = 0;
+    float *p_ = nullptr, *g_ = nullptr, *m_ = nullptr, *v_ = nullptr;
+    std::vector<float *> acts_;
+    float *delta_ = nullptr, *delta2_ = nullptr;
+    double *partial_ = nullptr;
+    int cap_ = 0;
+    int t_ = 0;
+};
+
+// Eigen-decomposition of a Hermitian n x n matrix (row-major, overwritten);
+// eigenvalues w (unsorted) and eigenvectors as the columns of V.
+void hermitian_eig(int n, std::vector<cd> &A, std::vector<double> &w, std::vector<cd> &V);
+
+// out[i][j] = <a_i, b_j> = sum conj(a_i) b_j  (FP64 device vectors of length N)
+void cross_dots(const void *A, int64_t lda, int na, const void *B, int64_t ldb, int nbv, int N, cd *out_host,
+                void *stream);
+// out[i] = ||a_i||
+void self_norms(const void *A, int64_t lda, int n, int N, double *out_host, void *stream);
+// out_s = sum_j coef[s][j] v_j   (FP64 device vectors of length N)
+void lincomb(const void *vecs, int64_t ld, int nv, const cd *coef_host, int ns, int N, void *out, int64_t ldo,
+             void *stream);
+
+struct GuessOptions {
+    int rank = 16;        // POD basis size r (clamped to the training count)
+    int harmonics = 4;    // M angle harmonics
+    int hidden = 64;      // width of both tanh hidden layers
+    int epochs = 6000;    // full-batch Adam steps
+    double lr = 3e-3;     // peak Adam step, cosine decay to zero
+    uint64_t seed = 0;    // weight initialisation
+};
+
+// Learned GMRES initial guess for one body (boundary unknown order).
+class Guess {
+  public:
+    Guess(int N, void *stream) : N_(N), stream_(stream) {}
+    ~Guess();
+    Guess(const Guess &) = delete;
+    Guess &operator=(const Guess &) = delete;
+    void set_stream(void *s);
+    bool trained() const { return net_ != nullptr; }
+    int rank() const { return r_; }
+    // angles [n][2]; B, X device [n][N] complex (right-hand sides and their
+    // solutions).  Returns the final training loss.
+    double fit(int n, const double *angles, const void *B, const void *X, const GuessOptions &o);
+    // X0 device [n][N] complex
+    void predict(int n, const double *angles, const void *B, void *X0);
+
+  private:
+    void features(int n, const double *angles, const void *B, std::vector<float> &F, std::vector<double> &nb);
+    int N_;
+    void *stream_;
+    GuessOptions o_{};
+    int r_ = 0;
+    void *U_ = nullptr;            // [r][N] complex FP64, orthonormal rows
+    std::vector<double> mu_, sd_;  // target standardisation
+    std::unique_ptr<Mlp> net_;
+};
+
+}  // namespace sfmm

@@ -26,7 +26,8 @@ PRECOND_ILU0, PRECOND_NONE, PRECOND_BLOCK_JACOBI, PRECOND_POLY = 0, 1, 2, 3
 
 EXPORTED = ["sfmm_default_options", "sfmm_setup", "sfmm_destroy", "sfmm_last_error", "sfmm_set_stream",
             "sfmm_num_unknowns", "sfmm_edges", "sfmm_matvec", "sfmm_precond", "sfmm_planewave_rhs",
-            "sfmm_solve", "sfmm_rcs", "sfmm_near_rows", "sfmm_describe", "sfmm_profile"]
+            "sfmm_solve", "sfmm_rcs", "sfmm_near_rows", "sfmm_describe", "sfmm_profile",
+            "sfmm_guess_default_options", "sfmm_guess_fit", "sfmm_guess_predict", "sfmm_mlp_train"]
 
 
 class sfmm_body(ctypes.Structure):
@@ -47,7 +48,13 @@ class sfmm_options(ctypes.Structure):
 
 class sfmm_solve_info(ctypes.Structure):
     _fields_ = [("converged", ctypes.c_int32), ("iterations", ctypes.c_int32), ("restarts", ctypes.c_int32),
-                ("true_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("guess_used", ctypes.c_int32), ("true_residual", ctypes.c_double),
+                ("initial_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+class sfmm_guess_options(ctypes.Structure):
+    _fields_ = [("rank", ctypes.c_int32), ("harmonics", ctypes.c_int32), ("hidden", ctypes.c_int32),
+                ("epochs", ctypes.c_int32), ("lr", ctypes.c_double), ("seed", ctypes.c_uint64)]
 
 
 class SfmmError(RuntimeError):
@@ -86,8 +93,13 @@ def load():
     lib.sfmm_near_rows.argtypes = [P, I32, I32, P, P]
     lib.sfmm_describe.argtypes = [P, I32, P, P]
     lib.sfmm_profile.argtypes = [P, I32, P, P]
+    lib.sfmm_guess_default_options.argtypes = [ctypes.POINTER(sfmm_guess_options)]
+    lib.sfmm_guess_default_options.restype = None
+    lib.sfmm_guess_fit.argtypes = [P, I32, I32, P, P, P, ctypes.POINTER(sfmm_guess_options), P, I32]
+    lib.sfmm_guess_predict.argtypes = [P, I32, I32, P, P, P, I32]
+    lib.sfmm_mlp_train.argtypes = [I32, I32, P, P, I32, P, P, I32, D, P, P, P]
     for name in EXPORTED:
-        if name not in ("sfmm_default_options", "sfmm_destroy", "sfmm_last_error"):
+        if name not in ("sfmm_default_options", "sfmm_destroy", "sfmm_last_error", "sfmm_guess_default_options"):
             getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -127,6 +139,32 @@ def sfmm_default_options(**overrides):
     for k, v in overrides.items():
         setattr(o, k, v)
     return o
+
+
+def sfmm_guess_default_options(**overrides):
+    o = sfmm_guess_options()
+    lib().sfmm_guess_default_options(ctypes.byref(o))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+def sfmm_mlp_train(sizes, params, X, Y, steps=0, lr=1e-3, device=0):
+    """Network kernels on their own.  params: float32 host array (updated in
+    place when steps > 0).  Returns (loss history [steps + 1], gradient at the
+    initial parameters, output at the initial parameters)."""
+    sizes = np.ascontiguousarray(sizes, dtype=np.int32)
+    if params.dtype != np.float32 or not params.flags["C_CONTIGUOUS"]:
+        raise ValueError("params must be a contiguous float32 array (updated in place)")
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    Y = np.ascontiguousarray(Y, dtype=np.float32)
+    loss = np.zeros(steps + 1)
+    grads = np.zeros_like(params)
+    out = np.zeros((X.shape[0], int(sizes[-1])), dtype=np.float32)
+    _check(lib().sfmm_mlp_train(device, len(sizes), sizes.ctypes.data, params.ctypes.data, X.shape[0],
+                                X.ctypes.data, Y.ctypes.data, steps, lr, loss.ctypes.data, grads.ctypes.data,
+                                out.ctypes.data))
+    return loss, grads, out
 
 
 class Context:
@@ -223,7 +261,29 @@ class Context:
         if st != SFMM_OK and (st != 5 or raise_on_nonconvergence):
             _check(st, self.ctx)
         return [dict(converged=bool(i.converged), iterations=i.iterations, restarts=i.restarts,
-                     true_residual=i.true_residual, seconds=i.seconds) for i in info]
+                     guess_used=bool(i.guess_used), true_residual=i.true_residual,
+                     initial_residual=i.initial_residual, seconds=i.seconds) for i in info]
+
+    def sfmm_guess_fit(self, angles, x, pol=None, body=0, **options):
+        """Train the learned initial guess on solutions x [n][2E] of the
+        incidences angles [n][2]; returns the final training loss."""
+        angles = np.ascontiguousarray(angles, dtype=np.float64).reshape(-1, 2)
+        polv = None if pol is None else np.ascontiguousarray(pol, dtype=np.float64)
+        px, dev = _ptr(x)
+        go = sfmm_guess_default_options(**options)
+        loss = ctypes.c_double(0.0)
+        _check(lib().sfmm_guess_fit(self.ctx, body, len(angles), angles.ctypes.data,
+                                    None if polv is None else polv.ctypes.data, px, ctypes.byref(go),
+                                    ctypes.byref(loss), dev), self.ctx)
+        return loss.value
+
+    def sfmm_guess_predict(self, angles, x0, pol=None, body=0):
+        angles = np.ascontiguousarray(angles, dtype=np.float64).reshape(-1, 2)
+        polv = None if pol is None else np.ascontiguousarray(pol, dtype=np.float64)
+        px, dev = _ptr(x0)
+        _check(lib().sfmm_guess_predict(self.ctx, body, len(angles), angles.ctypes.data,
+                                        None if polv is None else polv.ctypes.data, px, dev), self.ctx)
+        return x0
 
     def sfmm_rcs(self, x, theta_phi, body=0):
         px, dev = _ptr(x)

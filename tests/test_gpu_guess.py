@@ -1,0 +1,180 @@
+"""GPU checks of the learned initial guess.
+
+* The network kernels (bfloat16-rounded GEMM operands, FP32 accumulation)
+  against the FP64 oracle MLP on the same parameters: outputs and loss within
+  1e-2 relative, gradients per tensor with cosine >= 0.999 and relative error
+  <= 2e-2; Adam steps and a short training run follow the oracle's.
+* The trained guess on a theta sweep of a dielectric ellipsoid: it lies in the
+  span of the training solutions, it cuts GMRES iterations against the zero
+  start, and every solve still meets the tolerance on its true residual.
+* The solver's judge: a guess worse than zero is dropped.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import mlp
+from workloads import Body, icosphere, random_complex_vector, theta_sweep
+
+pytestmark = pytest.mark.gpu
+
+sfmm = pytest.importorskip("paper_1704_06862_amd.sfmm")
+
+SIZES = [20, 48, 48, 10]
+
+
+def flatten(params):
+    return np.concatenate([np.concatenate([W.ravel(), b]) for W, b in params]).astype(np.float32)
+
+
+def unflatten(vec, sizes):
+    out, off = [], 0
+    for a, b in zip(sizes[:-1], sizes[1:]):
+        W = vec[off:off + a * b].reshape(a, b).astype(np.float64)
+        off += a * b
+        out.append([W, vec[off:off + b].astype(np.float64)])
+        off += b
+    return out
+
+
+def problem(seed=0):
+    rng = np.random.default_rng(seed)
+    params = mlp.init(SIZES, seed=seed + 1)
+    for layer in params:
+        layer[1] = 0.1 * rng.standard_normal(layer[1].shape)
+    p32 = flatten(params)
+    X = rng.standard_normal((37, SIZES[0])).astype(np.float32)
+    Y = rng.standard_normal((37, SIZES[-1])).astype(np.float32)
+    return p32, X, Y
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def test_forward_and_gradients_match_oracle():
+    print("mlp forward/backward parity", flush=True)
+    p32, X, Y = problem()
+    loss, grads, out = sfmm.sfmm_mlp_train(SIZES, p32.copy(), X, Y, steps=0)
+    ref_params = unflatten(p32, SIZES)
+    ref_out, _ = mlp.forward(ref_params, X.astype(np.float64))
+    ref_loss, ref_grads = mlp.loss_and_grads(ref_params, X.astype(np.float64), Y.astype(np.float64))
+    assert rel(out, ref_out) < 1e-2
+    assert abs(loss[0] - ref_loss) < 1e-2 * ref_loss
+    g = unflatten(grads, SIZES)
+    for li in range(len(g)):
+        for k in range(2):
+            a, b = g[li][k].ravel(), ref_grads[li][k].ravel()
+            cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b))
+            assert cos >= 0.999, (li, k, cos)
+            assert rel(a, b) <= 2e-2, (li, k, rel(a, b))
+
+
+def test_adam_steps_follow_oracle():
+    print("mlp adam parity", flush=True)
+    p32, X, Y = problem(1)
+    p = p32.copy()
+    loss, _, _ = sfmm.sfmm_mlp_train(SIZES, p, X, Y, steps=20, lr=1e-3)
+    ref = unflatten(p32, SIZES)
+    state, ref_loss = {}, []
+    for _ in range(20):
+        l, g = mlp.loss_and_grads(ref, X.astype(np.float64), Y.astype(np.float64))
+        ref_loss.append(l)
+        mlp.adam(ref, g, state, lr=1e-3)
+    ref_loss.append(mlp.loss_and_grads(ref, X.astype(np.float64), Y.astype(np.float64))[0])
+    d_gpu = p.astype(np.float64) - p32
+    d_ref = flatten(ref).astype(np.float64) - p32
+    cos = d_gpu @ d_ref / (np.linalg.norm(d_gpu) * np.linalg.norm(d_ref))
+    assert cos >= 0.99, cos
+    assert np.allclose(loss, ref_loss, rtol=2e-2)
+
+
+def test_training_reduces_loss_like_oracle():
+    print("mlp training", flush=True)
+    p32, X, _ = problem(2)
+    Xd = X.astype(np.float64)
+    Y = np.stack([np.sin(Xd[:, 0]) * Xd[:, 1], np.cos(Xd[:, 2]), Xd[:, 3] ** 2 - 1] + [0.5 * Xd[:, i] for i in range(7)],
+                 axis=1).astype(np.float32)
+    loss, _, _ = sfmm.sfmm_mlp_train(SIZES, p32.copy(), X, Y, steps=300, lr=3e-3)
+    ref = unflatten(p32, SIZES)
+    state = {}
+    for _ in range(300):
+        _, g = mlp.loss_and_grads(ref, Xd, Y.astype(np.float64))
+        mlp.adam(ref, g, state, lr=3e-3)
+    ref_final = mlp.loss_and_grads(ref, Xd, Y.astype(np.float64))[0]
+    assert loss[-1] < 0.1 * loss[0]
+    assert loss[-1] < 3.0 * ref_final + 1e-3
+
+
+def ellipsoid():
+    v, t = icosphere(3, 1.0)
+    v = v * np.array([0.5, 0.35, 0.25])
+    reg = np.tile(np.array([[0, 1]], dtype=np.int32), (len(t), 1))
+    return Body(v, t, reg, np.array([1.0, 4.0], dtype=complex), np.ones(2, dtype=complex),
+                name="ellipsoid 0.5 x 0.35 x 0.25 wavelengths, eps 4")
+
+
+@pytest.fixture(scope="module")
+def ectx():
+    print("setup ellipsoid fp32", flush=True)
+    with sfmm.Context([ellipsoid()], precision=sfmm.PREC_FP32, finest_box=0.25, tol=1e-4, gmres_restart=50,
+                      max_iters=600) as c:
+        yield c
+
+
+def test_learned_guess_cuts_iterations(ectx):
+    print("learned guess sweep", flush=True)
+    n = ectx.sfmm_num_unknowns()
+    ang = theta_sweep(91)
+    tr = np.arange(0, 91, 3)
+    te = np.setdiff1d(np.arange(91), tr)
+    b = ectx.sfmm_planewave_rhs(ang, np.zeros((91, n), dtype=complex))
+    x_tr = np.zeros((len(tr), n), dtype=complex)
+    info_tr = ectx.sfmm_solve(b[tr].copy(), x_tr)
+    assert all(i["converged"] for i in info_tr)
+    loss = ectx.sfmm_guess_fit(ang[tr], x_tr)
+    assert np.isfinite(loss)
+    x0 = ectx.sfmm_guess_predict(ang[te], np.zeros((len(te), n), dtype=complex))
+    # x0 = U c lies in the span of the training solutions
+    coef = np.linalg.lstsq(x_tr.T, x0.T, rcond=None)[0]
+    assert rel(x_tr.T @ coef, x0.T) < 1e-6
+    # at the training angles the guess is close to the training solutions
+    x0_tr = ectx.sfmm_guess_predict(ang[tr], np.zeros((len(tr), n), dtype=complex))
+    assert rel(x0_tr, x_tr) < 0.1
+    x_zero = np.zeros((len(te), n), dtype=complex)
+    x_lrn = np.zeros((len(te), n), dtype=complex)
+    info0 = ectx.sfmm_solve(b[te].copy(), x_zero)
+    info1 = ectx.sfmm_solve(b[te].copy(), x_lrn, x0=x0)
+    its0 = np.array([i["iterations"] for i in info0])
+    its1 = np.array([i["iterations"] for i in info1])
+    r0 = np.array([i["initial_residual"] for i in info1])
+    print(f"zero-guess iterations {its0.mean():.1f}, learned {its1.mean():.1f}, "
+          f"guess residual median {np.median(r0):.3e} max {r0.max():.3e}, loss {loss:.3e}", flush=True)
+    for i0, i1 in zip(info0, info1):
+        assert i0["converged"] and i1["converged"]
+        assert i0["true_residual"] <= 1e-4 and i1["true_residual"] <= 1e-4
+    assert np.mean([i["guess_used"] for i in info1]) >= 0.9
+    assert np.median(r0) < 0.1
+    assert its1.mean() < 0.75 * its0.mean()
+    # both solutions agree to the solver tolerance
+    assert rel(x_lrn, x_zero) < 1e-2
+
+
+def test_judge_drops_a_bad_guess(ectx):
+    print("judge of the initial guess", flush=True)
+    n = ectx.sfmm_num_unknowns()
+    ang = theta_sweep(3)
+    b = ectx.sfmm_planewave_rhs(ang, np.zeros((3, n), dtype=complex))
+    x_ref = np.zeros_like(b)
+    info_ref = ectx.sfmm_solve(b.copy(), x_ref)
+    bad = 1e3 * random_complex_vector(n, 3, seed=7)
+    x = np.zeros_like(b)
+    info = ectx.sfmm_solve(b.copy(), x, x0=bad)
+    for i, r in zip(info, info_ref):
+        assert not i["guess_used"] and i["initial_residual"] > 1.0
+        assert i["converged"] and i["iterations"] == r["iterations"]
+    # a converged solution as the guess needs no iteration
+    x2 = np.zeros_like(b)
+    info2 = ectx.sfmm_solve(b.copy(), x2, x0=x_ref)
+    for i in info2:
+        assert i["guess_used"] and i["converged"] and i["iterations"] == 0

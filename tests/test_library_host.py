@@ -108,3 +108,23 @@ def test_invalid_arguments():
         assert e.value.status == 1
         with pytest.raises(sfmm.SfmmError):
             ctx.sfmm_near_rows([10 ** 6])
+
+
+def test_guess_entry_points_refuse_bad_use():
+    b = sphere_body(0.3, 4.0, 1)
+    with sfmm.Context([b], device=-1) as ctx:
+        n = ctx.sfmm_num_unknowns()
+        ang = np.zeros((1, 2))
+        with pytest.raises(sfmm.SfmmError) as e:
+            ctx.sfmm_guess_fit(ang, np.zeros((1, n), dtype=complex))
+        assert e.value.status == 1
+        with pytest.raises(sfmm.SfmmError) as e:
+            ctx.sfmm_guess_predict(ang, np.zeros((1, n), dtype=complex))
+        assert e.value.status == 1
+    with pytest.raises(sfmm.SfmmError) as e:
+        sfmm.sfmm_mlp_train([4], np.zeros(4, dtype=np.float32), np.zeros((1, 4)), np.zeros((1, 4)))
+    assert e.value.status == 1
+    with pytest.raises(ValueError):
+        sfmm.sfmm_mlp_train([4, 2], np.zeros(10), np.zeros((1, 4)), np.zeros((1, 2)))
+    o = sfmm.sfmm_guess_default_options()
+    assert o.rank > 0 and o.hidden > 0 and o.epochs > 0 and o.lr > 0
