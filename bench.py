@@ -44,6 +44,9 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--batch", type=str, default="8,64",
                    help="extra right-hand-side batch sizes measured outside the timed region")
+    p.add_argument("--sweep", type=int, default=64, help="angles of the theta sweep (0 = skip)")
+    p.add_argument("--train-every", type=int, default=2,
+                   help="learned-guess sweep: solve every n-th angle first and train on those")
     return p.parse_args()
 
 
@@ -70,6 +73,76 @@ def cpu_baseline(body, x, seconds):
     return {"value": rows / dt, "unit": "unknowns*RHS/s", "cores": 1, "kind": "oracle",
             "sample": f"{rows} of {2 * mesh.n_edges} rows of Z x (dense PMCHWT rows with singular "
                       f"extraction, FP64 numpy, 1 thread) in {dt:.1f} s"}
+
+
+def sweep(ctx, sfmm, torch, n_ang, every):
+    """Time-to-solution of a theta sweep (theta uniform in [0, 180] degrees at
+    phi = 0, theta-polarised) to the 1e-4 true residual, three ways:
+    plain (one right-hand side per solve, zero start), batched (all angles in
+    one lockstep solve) and batched + learned guess (every `every`-th angle
+    solved first, the network trained on those currents, then the rest solved
+    from its prediction).  Wall times include training and prediction."""
+    from workloads import theta_sweep
+
+    n = ctx.sfmm_num_unknowns()
+    ang = theta_sweep(n_ang)
+    b = torch.zeros((n_ang, n), dtype=torch.complex128, device="cuda")
+    ctx.sfmm_planewave_rhs(ang, b)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0
+
+    x = torch.zeros_like(b)
+    infos, t_plain = timed(lambda: [ctx.sfmm_solve(b[i:i + 1], x[i:i + 1])[0] for i in range(n_ang)])
+    its_plain = [i["iterations"] for i in infos]
+    ok_plain = all(i["converged"] for i in infos)
+    x.zero_()
+    infos, t_batch = timed(lambda: ctx.sfmm_solve(b, x))
+    its_batch = [i["iterations"] for i in infos]
+    ok_batch = all(i["converged"] for i in infos)
+
+    tr = np.arange(0, n_ang, every)
+    te = np.setdiff1d(np.arange(n_ang), tr)
+    tr_t = torch.from_numpy(tr).to("cuda")
+    te_t = torch.from_numpy(te).to("cuda")
+
+    def learned():
+        b_tr = b.index_select(0, tr_t).contiguous()
+        b_te = b.index_select(0, te_t).contiguous()
+        x_tr = torch.zeros_like(b_tr)
+        i_tr = ctx.sfmm_solve(b_tr, x_tr)
+        t_fit = time.perf_counter()
+        loss = ctx.sfmm_guess_fit(ang[tr], x_tr, rank=len(tr))
+        x0 = torch.zeros_like(b_te)
+        ctx.sfmm_guess_predict(ang[te], x0)
+        torch.cuda.synchronize()
+        t_fit = time.perf_counter() - t_fit
+        x_te = torch.zeros_like(b_te)
+        i_te = ctx.sfmm_solve(b_te, x_te, x0=x0)
+        return i_tr, i_te, loss, t_fit
+
+    (i_tr, i_te, loss, t_fit), t_learn = timed(learned)
+    ok_learn = all(i["converged"] for i in i_tr + i_te)
+    return {
+        "angles": n_ang, "tol": 1e-4,
+        "plain_ms_per_angle": round(1e3 * t_plain / n_ang, 2),
+        "batched_ms_per_angle": round(1e3 * t_batch / n_ang, 2),
+        "batched_learned_ms_per_angle": round(1e3 * t_learn / n_ang, 2),
+        "speedup_batched": round(t_plain / t_batch, 2),
+        "speedup_batched_learned": round(t_plain / t_learn, 2),
+        "iterations_mean": {"plain": float(np.mean(its_plain)), "batched": float(np.mean(its_batch)),
+                            "learned_train": float(np.mean([i["iterations"] for i in i_tr])),
+                            "learned_predicted": float(np.mean([i["iterations"] for i in i_te]))},
+        "guess": {"trained_on": len(tr), "fit_and_predict_s": round(t_fit, 3), "loss": loss,
+                  "initial_residual_median": float(np.median([i["initial_residual"] for i in i_te])),
+                  "used": int(sum(i["guess_used"] for i in i_te))},
+        "all_converged": bool(ok_plain and ok_batch and ok_learn),
+    }
 
 
 def main():
@@ -136,6 +209,18 @@ def main():
     names = ["near", "aggregate", "interp_up", "translate", "anterp_down", "receive", "precond", "matvec_total"]
     stages = {k: round(float(v), 4) for k, v in zip(names, st)}
     print("stages ms", stages, file=sys.stderr, flush=True)
+    # the same at 64 right-hand sides (one batched product / application)
+    xr = torch.from_numpy(random_complex_vector(n, 64, seed=99)).to("cuda")
+    yr = torch.zeros_like(xr)
+    ctx.sfmm_profile(1)
+    for _ in range(3):
+        ctx.sfmm_matvec(xr, yr)
+        ctx.sfmm_precond(xr, yr)
+    torch.cuda.synchronize()
+    st64, _ = ctx.sfmm_profile(0)
+    stages64 = {k: round(float(v), 4) for k, v in zip(names, st64)}
+    del xr, yr
+    print("stages ms at 64 RHS", stages64, file=sys.stderr, flush=True)
 
     # dominant kernel roofline: the near-field product (one kernel launch)
     ne = n // 2
@@ -155,7 +240,7 @@ def main():
               "vs_baseline": None, "dtype": "f32", "data": "synthetic",
               "config": {"workload": "dielectric sphere r=2 lambda0, eps_r=2.56, icosphere s=5, 61,440 unknowns, "
                                      "5-level MLFMM, 0.25 lambda0 boxes, 3 digits, FP32, 1 RHS"},
-              "setup_s": round(setup_s, 2), "stages_ms": stages, "roofline": roofline,
+              "setup_s": round(setup_s, 2), "stages_ms": stages, "stages_ms_64rhs": stages64, "roofline": roofline,
               "batched_unknowns_rhs_per_s": batched}
 
     if not args.no_solve:
@@ -168,6 +253,10 @@ def main():
                            "restart": 50, "true_residual": info["true_residual"], "converged": info["converged"],
                            "preconditioner": "near-field GMRES polynomial, degree 16"}
         print("gmres", result["gmres"], file=sys.stderr, flush=True)
+
+    if args.sweep > 0:
+        result["sweep"] = sweep(ctx, sfmm, torch, args.sweep, args.train_every)
+        print("sweep", result["sweep"], file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(body, xh[0], args.cpu_seconds)

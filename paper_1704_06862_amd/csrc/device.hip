@@ -21,9 +21,11 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "device.hpp"
+#include "mfma.hpp"
 #include "kernels.hpp"
 
 namespace sfmm {
@@ -40,6 +42,7 @@ namespace sfmm {
 constexpr int MAXLEV = 21;
 constexpr size_t LDS_LIMIT = 64 * 1024;
 constexpr int BATCH = 64;        // right-hand sides per batched chunk
+constexpr int MMA_MIN_R = 16;    // batched near products from this many RHS run on the matrix cores
 
 void *device_alloc(size_t bytes) {
     void *p = nullptr;
@@ -92,7 +95,8 @@ int pick_tile(int R, std::initializer_list<int> cands, F fits) {
 template <typename T>
 class DeviceBodyT final : public DeviceBody {
   public:
-    DeviceBodyT(const BodyHost &h, int device, void *stream) : h_(h), stream_((hipStream_t)stream) {
+    DeviceBodyT(const BodyHost &h, int device, void *stream, bool split = false)
+        : h_(h), stream_((hipStream_t)stream), split_(split) {
         HIPCHK(hipSetDevice(device));
         const Mesh &m = h.mesh;
         const Octree &o = h.oct;
@@ -114,6 +118,7 @@ class DeviceBodyT final : public DeviceBody {
             max_ncol_ = std::max(max_ncol_, h.near.col_ptr[b + 1] - h.near.col_ptr[b]);
             max_nrow_ = std::max(max_nrow_, o.bstart[b + 1] - o.bstart[b]);
         }
+        if constexpr (std::is_same<T, float>::value) build_mma_tiles(h);
         if (!h.ilu.fwd_col_ptr.empty()) {
             fcol_ptr_ = upload(h.ilu.fwd_col_ptr);
             fcols_ = upload(h.ilu.fwd_cols);
@@ -205,6 +210,12 @@ class DeviceBodyT final : public DeviceBody {
     // ---- batched products on internal T vectors [2E][R] ----
     template <bool POLY>
     void launch_near(int R, const cx<T> *x, cx<T> *y, cx<T> *acc, cx<T> inv_theta, int write_y) {
+        if constexpr (std::is_same<T, float>::value) {
+            if (R >= MMA_MIN_R && ntiles_ > 0) {
+                launch_near_mma<POLY>(R, x, y, acc, inv_theta, write_y);
+                return;
+            }
+        }
         const int rt = pick_tile(R, {8, 4, 2, 1},
                                  [&](int t) { return (size_t)max_ncol_ * 2 * t * sizeof(cx<T>) <= LDS_LIMIT; });
         const bool lds = rt > 0;
@@ -221,6 +232,117 @@ class DeviceBodyT final : public DeviceBody {
         else SFMM_NEAR(1, true);
 #undef SFMM_NEAR
         LAUNCHCHK();
+    }
+
+    template <bool POLY>
+    void launch_near_mma(int R, const cx<float> *x, cx<float> *y, cx<float> *acc, cx<float> inv_theta,
+                         int write_y) {
+        const int nt = (R + 15) / 16;
+#define SFMM_NMMA(NT_, S_)                                                                                          \
+    k_near_mma<NT_, S_, POLY><<<ntiles_, 64 * MMA_WAVES, 0, stream_>>>(R, tile_box_, tile_row0_, tile_step_, bstart_, \
+                                                                     near_col_ptr_, near_cols_, tvals_, nsteps_, x, y, \
+                                                                     acc, inv_theta, write_y)
+        if (split_) {
+            if (nt == 1) SFMM_NMMA(1, true);
+            else if (nt == 2) SFMM_NMMA(2, true);
+            else if (nt == 3) SFMM_NMMA(3, true);
+            else SFMM_NMMA(4, true);
+        } else {
+            if (nt == 1) SFMM_NMMA(1, false);
+            else if (nt == 2) SFMM_NMMA(2, false);
+            else if (nt == 3) SFMM_NMMA(3, false);
+            else SFMM_NMMA(4, false);
+        }
+#undef SFMM_NMMA
+        LAUNCHCHK();
+    }
+
+    // Near-field matrix in matrix-core tile order (see k_near_mma): tiles of
+    // 16 rows of one box, K steps of 4 (FP32) or 32 (bf16 split) columns.
+    void build_mma_tiles(const BodyHost &h) {
+        const Octree &o = h.oct;
+        const NearMatrix &Z = h.near;
+        const int KS = split_ ? 32 : 4;
+        std::vector<int> tbox, trow0;
+        std::vector<int64_t> tstep{0};
+        for (int b = 0; b < nb_; ++b) {
+            const int nrow = o.bstart[b + 1] - o.bstart[b], ncol = Z.col_ptr[b + 1] - Z.col_ptr[b];
+            const int nks = (ncol + KS - 1) / KS;
+            for (int row0 = 0; row0 < nrow; row0 += 16) {
+                tbox.push_back(b);
+                trow0.push_back(row0);
+                tstep.push_back(tstep.back() + nks);
+            }
+        }
+        ntiles_ = (int)tbox.size();
+        nsteps_ = tstep.back();
+        if (ntiles_ == 0 || nsteps_ == 0) {
+            ntiles_ = 0;
+            return;
+        }
+        tile_box_ = upload(tbox);
+        tile_row0_ = upload(trow0);
+        tile_step_ = upload(tstep);
+        const std::vector<cd> *mats[3] = {&Z.A, &Z.B, &Z.C};
+        if (!split_) {
+            std::vector<cx<float>> V((size_t)3 * nsteps_ * 64, cx<float>{0, 0});
+            for (int t = 0; t < ntiles_; ++t) {
+                const int b = tbox[t], row0 = trow0[t];
+                const int nrow = o.bstart[b + 1] - o.bstart[b], ncol = Z.col_ptr[b + 1] - Z.col_ptr[b];
+                for (int64_t st = tstep[t]; st < tstep[t + 1]; ++st) {
+                    const int s = (int)(st - tstep[t]);
+                    for (int lane = 0; lane < 64; ++lane) {
+                        const int row = row0 + lane % 16, col = 4 * s + lane / 16;
+                        if (row >= nrow || col >= ncol) continue;
+                        const int64_t idx = Z.val_ptr[b] + (int64_t)row * ncol + col;
+                        for (int m = 0; m < 3; ++m)
+                            V[((size_t)m * nsteps_ + st) * 64 + lane] = to_cx<float>((*mats[m])[idx]);
+                    }
+                }
+            }
+            tvals_ = upload(V);
+        } else {
+            // twelve planes (A, B, C) x (re hi, re lo, im hi, im lo), 8 bf16 per lane
+            std::vector<uint16_t> V((size_t)12 * nsteps_ * 64 * 8, 0);
+            auto bf = [](double v, uint16_t &hi, uint16_t &lo) {
+                auto rne = [](float f) {
+                    uint32_t u;
+                    std::memcpy(&u, &f, 4);
+                    u += 0x7fffu + ((u >> 16) & 1u);
+                    return (uint16_t)(u >> 16);
+                };
+                auto back = [](uint16_t b) {
+                    const uint32_t u = (uint32_t)b << 16;
+                    float f;
+                    std::memcpy(&f, &u, 4);
+                    return (double)f;
+                };
+                hi = rne((float)v);
+                lo = rne((float)(v - back(hi)));
+            };
+            for (int t = 0; t < ntiles_; ++t) {
+                const int b = tbox[t], row0 = trow0[t];
+                const int nrow = o.bstart[b + 1] - o.bstart[b], ncol = Z.col_ptr[b + 1] - Z.col_ptr[b];
+                for (int64_t st = tstep[t]; st < tstep[t + 1]; ++st) {
+                    const int s = (int)(st - tstep[t]);
+                    for (int lane = 0; lane < 64; ++lane)
+                        for (int e = 0; e < 8; ++e) {
+                            const int row = row0 + lane % 16, col = 32 * s + 8 * (lane / 16) + e;
+                            if (row >= nrow || col >= ncol) continue;
+                            const int64_t idx = Z.val_ptr[b] + (int64_t)row * ncol + col;
+                            for (int m = 0; m < 3; ++m) {
+                                const cd v = (*mats[m])[idx];
+                                uint16_t q[4];
+                                bf(v.real(), q[0], q[1]);
+                                bf(v.imag(), q[2], q[3]);
+                                for (int c = 0; c < 4; ++c)
+                                    V[((((size_t)(4 * m + c) * nsteps_ + st) * 64) + lane) * 8 + e] = q[c];
+                            }
+                        }
+                }
+            }
+            tvals_ = upload(V);
+        }
     }
 
     void matvec_internal(const cx<T> *x, cx<T> *y, int R, int parts) {
@@ -817,6 +939,13 @@ class DeviceBodyT final : public DeviceBody {
     int *near_col_ptr_ = nullptr, *near_cols_ = nullptr;
     int64_t *near_val_ptr_ = nullptr;
     cx<T> *nA_ = nullptr, *nB_ = nullptr, *nC_ = nullptr;
+    // matrix-core tiles of the near matrix (FP32 / bf16-split modes)
+    bool split_ = false;
+    int ntiles_ = 0;
+    int64_t nsteps_ = 0;
+    int *tile_box_ = nullptr, *tile_row0_ = nullptr;
+    int64_t *tile_step_ = nullptr;
+    void *tvals_ = nullptr;
     int max_ncol_ = 0, max_nrow_ = 0, max_ilu_nc_ = 0, precond_ = SFMM_PRECOND_ILU0;
     int *fcol_ptr_ = nullptr, *fcols_ = nullptr, *bcol_ptr_ = nullptr, *bcols_ = nullptr;
     int64_t *fptr_ = nullptr, *bptr_ = nullptr;
@@ -843,8 +972,9 @@ class DeviceBodyT final : public DeviceBody {
 std::unique_ptr<DeviceBody> make_device_body(const BodyHost &h, int precision, int device, void *stream) {
     check_device(device);
     if (precision == SFMM_PREC_FP64) return std::make_unique<DeviceBodyT<double>>(h, device, stream);
-    if (precision == SFMM_PREC_FP32) return std::make_unique<DeviceBodyT<float>>(h, device, stream);
-    throw Error(SFMM_E_UNSUPPORTED, "precision mode not implemented yet");
+    if (precision == SFMM_PREC_FP32) return std::make_unique<DeviceBodyT<float>>(h, device, stream, false);
+    if (precision == SFMM_PREC_BF16_SPLIT) return std::make_unique<DeviceBodyT<float>>(h, device, stream, true);
+    throw Error(SFMM_E_UNSUPPORTED, "unknown precision mode");
 }
 
 }  // namespace sfmm

@@ -1,0 +1,224 @@
+// Matrix-core (MFMA) kernels for batched right-hand sides on gfx950.
+//
+// With R right-hand sides in the internal RHS-minor layout, the near-field
+// product of one finest box is a dense complex GEMM
+//     [E rows; H rows] (2 n_b x R) = [[A, -B], [B, C]] (2 n_b x 2 n_c) [J; M] (2 n_c x R)
+// so it runs on the matrix cores: rows in blocks of 16 (the M dimension),
+// right-hand sides in blocks of 16 (N), columns along K.  Two arithmetic
+// variants share the tiling:
+//   FP32       v_mfma_f32_16x16x4_f32, K = 4 columns per step;
+//   BF16-split every FP32 operand v is carried as hi = bf16(v) and
+//              lo = bf16(v - hi); a product is hi*hi + hi*lo + lo*hi on
+//              v_mfma_f32_16x16x32_bf16 (K = 32 per step) with FP32
+//              accumulation, about 16 significant bits per operand.
+// Operand lane layouts (16x16 output block, lane l in 0..63):
+//   A (matrix)  row l % 16, K index (l / 16) * E + e   (E = 1 or 8 elements)
+//   B (vectors) column l % 16, same K index
+//   D           row 4 (l / 16) + v, column l % 16, v = 0..3
+// The matrix is stored once in this tile order at setup (zero padding), so
+// every matrix load is a contiguous 64-lane access.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace sfmm {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int MMA_WAVES = 4;   // waves per tile workgroup; they split the K steps
+
+// bf16 rounding (to nearest even) of v and of the remainder v - hi
+__device__ __forceinline__ void split_bf16(float v, __bf16 &hi, __bf16 &lo) {
+    hi = (__bf16)v;
+    lo = (__bf16)(v - (float)hi);
+}
+
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+// sign flip of eight bf16 values (exact)
+__device__ __forceinline__ bf16x8 neg8(bf16x8 v) {
+    u16x8 u = __builtin_bit_cast(u16x8, v);
+    u ^= (unsigned short)0x8000;
+    return __builtin_bit_cast(bf16x8, u);
+}
+
+__device__ __forceinline__ void mma_f32(f32x4 &c, float a, float b) {
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+// hi*hi + hi*lo + lo*hi
+__device__ __forceinline__ void mma_split(f32x4 &c, const bf16x8 &ah, const bf16x8 &al, const bf16x8 &bh,
+                                          const bf16x8 &bl) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+}
+
+// Near-field product on the matrix cores for R <= 16 * NT right-hand sides.
+// One workgroup per tile (box b, 16-row block starting at row0); the 4 waves
+// take every 4th K step and their partial sums are added through LDS.
+// vals: FP32: three planes (A, B, C) of cx<float>[nsteps][64];
+//       split: twelve planes (A, B, C) x (re hi, re lo, im hi, im lo) of
+//       bf16x8[nsteps][64].
+// POLY as in k_near: with Q = Z_near X, acc += X / theta, Y = X - Q / theta.
+template <int NT, bool SPLIT, bool POLY>
+__global__ void __launch_bounds__(64 * MMA_WAVES)
+    k_near_mma(int R, const int *__restrict__ tile_box, const int *__restrict__ tile_row0,
+               const int64_t *__restrict__ tile_step, const int *__restrict__ bstart, const int *__restrict__ col_ptr,
+               const int *__restrict__ cols, const void *__restrict__ vals, int64_t nsteps,
+               const cx<float> *__restrict__ x, cx<float> *__restrict__ y, cx<float> *__restrict__ acc,
+               cx<float> inv_theta, int write_y) {
+    __shared__ f32x4 red[MMA_WAVES - 1][NT * 4][64];
+    const int t = blockIdx.x;
+    const int b = tile_box[t], row0 = tile_row0[t];
+    const int r0 = bstart[b], nrow = bstart[b + 1] - r0;
+    const int c0 = col_ptr[b], ncol = col_ptr[b + 1] - c0;
+    const int64_t st0 = tile_step[t];
+    const int nst = (int)(tile_step[t + 1] - st0);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, lg = lane >> 4;
+    f32x4 aEr[NT], aEi[NT], aHr[NT], aHi[NT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) aEr[n] = aEi[n] = aHr[n] = aHi[n] = f32x4{0, 0, 0, 0};
+
+    for (int s = wave; s < nst; s += MMA_WAVES) {
+        const int64_t vi = (st0 + s) * 64 + lane;
+        if constexpr (!SPLIT) {
+            const cx<float> *V = reinterpret_cast<const cx<float> *>(vals);
+            const cx<float> a = V[vi], bb = V[nsteps * 64 + vi], c = V[2 * nsteps * 64 + vi];
+            const int col = 4 * s + lg;
+            const int p = col < ncol ? cols[c0 + col] : -1;
+            const float nay = -a.y, nbx = -bb.x, nby = -bb.y, ncy = -c.y;
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+                const int rhs = 16 * n + lr;
+                cx<float> xj = {0, 0}, xm = {0, 0};
+                if (p >= 0 && rhs < R) {
+                    xj = x[(int64_t)(2 * p) * R + rhs];
+                    xm = x[(int64_t)(2 * p + 1) * R + rhs];
+                }
+                // E = A xJ - B xM ; H = B xJ + C xM
+                mma_f32(aEr[n], a.x, xj.x);
+                mma_f32(aEr[n], nay, xj.y);
+                mma_f32(aEr[n], nbx, xm.x);
+                mma_f32(aEr[n], bb.y, xm.y);
+                mma_f32(aEi[n], a.x, xj.y);
+                mma_f32(aEi[n], a.y, xj.x);
+                mma_f32(aEi[n], nbx, xm.y);
+                mma_f32(aEi[n], nby, xm.x);
+                mma_f32(aHr[n], bb.x, xj.x);
+                mma_f32(aHr[n], nby, xj.y);
+                mma_f32(aHr[n], c.x, xm.x);
+                mma_f32(aHr[n], ncy, xm.y);
+                mma_f32(aHi[n], bb.x, xj.y);
+                mma_f32(aHi[n], bb.y, xj.x);
+                mma_f32(aHi[n], c.x, xm.y);
+                mma_f32(aHi[n], c.y, xm.x);
+            }
+        } else {
+            const bf16x8 *V = reinterpret_cast<const bf16x8 *>(vals);
+            const int64_t pl = nsteps * 64;
+            const bf16x8 arh = V[vi], arl = V[pl + vi], aih = V[2 * pl + vi], ail = V[3 * pl + vi];
+            const bf16x8 brh = V[4 * pl + vi], brl = V[5 * pl + vi], bih = V[6 * pl + vi], bil = V[7 * pl + vi];
+            const bf16x8 crh = V[8 * pl + vi], crl = V[9 * pl + vi], cih = V[10 * pl + vi], cil = V[11 * pl + vi];
+            const bf16x8 naih = neg8(aih), nail = neg8(ail), nbrh = neg8(brh), nbrl = neg8(brl);
+            const bf16x8 nbih = neg8(bih), nbil = neg8(bil), ncih = neg8(cih), ncil = neg8(cil);
+            const int colb = 32 * s + 8 * lg;
+            int p[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) p[e] = colb + e < ncol ? cols[c0 + colb + e] : -1;
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+                const int rhs = 16 * n + lr;
+                bf16x8 jrh, jrl, jih, jil, mrh, mrl, mih, mil;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    cx<float> xj = {0, 0}, xm = {0, 0};
+                    if (p[e] >= 0 && rhs < R) {
+                        xj = x[(int64_t)(2 * p[e]) * R + rhs];
+                        xm = x[(int64_t)(2 * p[e] + 1) * R + rhs];
+                    }
+                    __bf16 h, l;
+                    split_bf16(xj.x, h, l);
+                    jrh[e] = h;
+                    jrl[e] = l;
+                    split_bf16(xj.y, h, l);
+                    jih[e] = h;
+                    jil[e] = l;
+                    split_bf16(xm.x, h, l);
+                    mrh[e] = h;
+                    mrl[e] = l;
+                    split_bf16(xm.y, h, l);
+                    mih[e] = h;
+                    mil[e] = l;
+                }
+                mma_split(aEr[n], arh, arl, jrh, jrl);
+                mma_split(aEr[n], naih, nail, jih, jil);
+                mma_split(aEr[n], nbrh, nbrl, mrh, mrl);
+                mma_split(aEr[n], bih, bil, mih, mil);
+                mma_split(aEi[n], arh, arl, jih, jil);
+                mma_split(aEi[n], aih, ail, jrh, jrl);
+                mma_split(aEi[n], nbrh, nbrl, mih, mil);
+                mma_split(aEi[n], nbih, nbil, mrh, mrl);
+                mma_split(aHr[n], brh, brl, jrh, jrl);
+                mma_split(aHr[n], nbih, nbil, jih, jil);
+                mma_split(aHr[n], crh, crl, mrh, mrl);
+                mma_split(aHr[n], ncih, ncil, mih, mil);
+                mma_split(aHi[n], brh, brl, jih, jil);
+                mma_split(aHi[n], bih, bil, jrh, jrl);
+                mma_split(aHi[n], crh, crl, mih, mil);
+                mma_split(aHi[n], cih, cil, mrh, mrl);
+            }
+        }
+    }
+    if (wave > 0) {
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            red[wave - 1][4 * n + 0][lane] = aEr[n];
+            red[wave - 1][4 * n + 1][lane] = aEi[n];
+            red[wave - 1][4 * n + 2][lane] = aHr[n];
+            red[wave - 1][4 * n + 3][lane] = aHi[n];
+        }
+    }
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+#pragma unroll
+        for (int w = 0; w < MMA_WAVES - 1; ++w) {
+            aEr[n] += red[w][4 * n + 0][lane];
+            aEi[n] += red[w][4 * n + 1][lane];
+            aHr[n] += red[w][4 * n + 2][lane];
+            aHi[n] += red[w][4 * n + 3][lane];
+        }
+        const int rhs = 16 * n + lr;
+        if (rhs >= R) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = row0 + 4 * lg + v;
+            if (row >= nrow) continue;
+            const int64_t iE = (int64_t)(2 * (r0 + row)) * R + rhs;
+            const int64_t iH = iE + R;
+            const cx<float> qE = {aEr[n][v], aEi[n][v]}, qH = {aHr[n][v], aHi[n][v]};
+            if (POLY) {
+                cx<float> xe = x[iE], xh = x[iH];
+                cx<float> ae = acc[iE], ah = acc[iH];
+                cfma(ae, xe, inv_theta);
+                cfma(ah, xh, inv_theta);
+                acc[iE] = ae;
+                acc[iH] = ah;
+                if (write_y) {
+                    cfms(xe, qE, inv_theta);
+                    cfms(xh, qH, inv_theta);
+                    y[iE] = xe;
+                    y[iH] = xh;
+                }
+            } else {
+                y[iE] = qE;
+                y[iH] = qH;
+            }
+        }
+    }
+}
+
+}  // namespace sfmm

@@ -24,31 +24,46 @@ def rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-def test_bench_configuration_sampled_rows():
+@pytest.fixture(scope="module")
+def bench_rows():
     body = sphere_body(2.0, 2.56, 5)
     mesh = rwg.from_body(body)
     ne = mesh.n_edges
     rng = np.random.default_rng(11)
     test = np.sort(rng.choice(ne, 16, replace=False))
-    x = random_complex_vector(2 * ne, 1, seed=1234)
     print("oracle rows", flush=True)
     ZE, ZH = mom.pmchwt_rows(mesh, body.eps_r, body.mu_r, body.frequency, test)
     keys = octree.finest_keys(mesh, 0.25, 5)
     near = np.tile(octree.near_mask(keys)[test], (1, 2))
-    ref = np.concatenate([ZE @ x[0], ZH @ x[0]])
-    ref_near = np.concatenate([np.where(near, ZE, 0) @ x[0], np.where(near, ZH, 0) @ x[0]])
-    print("setup bench configuration", flush=True)
-    with sfmm.Context([body], **BENCH_OPTS) as ctx:
+    return dict(body=body, ne=ne, test=test, Z=np.concatenate([ZE, ZH]),
+                Zn=np.concatenate([np.where(near, ZE, 0), np.where(near, ZH, 0)]))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_bench_configuration_sampled_rows(bench_rows, prec):
+    # one right-hand side (vector kernels) and 64 (matrix-core near product)
+    body, ne, test = bench_rows["body"], bench_rows["ne"], bench_rows["test"]
+    x = random_complex_vector(2 * ne, 1, seed=1234)
+    xb = random_complex_vector(2 * ne, 64, seed=77)
+    opts = dict(BENCH_OPTS, precision=sfmm.PREC_FP32 if prec == "fp32" else sfmm.PREC_BF16_SPLIT)
+    print("setup bench configuration", prec, flush=True)
+    with sfmm.Context([body], **opts) as ctx:
         assert ctx.sfmm_num_unknowns() == 61440
         yn = ctx.sfmm_matvec(x, np.zeros_like(x), parts=sfmm.PART_NEAR)[0]
         y = ctx.sfmm_matvec(x, np.zeros_like(x))[0]
+        ybn = ctx.sfmm_matvec(xb, np.zeros_like(xb), parts=sfmm.PART_NEAR)
+        yb = ctx.sfmm_matvec(xb, np.zeros_like(xb))
     pick = np.concatenate([test, ne + test])
-    e_near = rel(yn[pick], ref_near)
-    e_full = rel(y[pick], ref)
-    print("bench config sampled rows: near", e_near, "full", e_full,
-          "far share", np.linalg.norm(ref - ref_near) / np.linalg.norm(ref))
+    e_near = rel(yn[pick], bench_rows["Zn"] @ x[0])
+    e_full = rel(y[pick], bench_rows["Z"] @ x[0])
+    eb_near = max(rel(ybn[r][pick], bench_rows["Zn"] @ xb[r]) for r in range(64))
+    eb_full = max(rel(yb[r][pick], bench_rows["Z"] @ xb[r]) for r in range(64))
+    print(prec, "bench config sampled rows: near", e_near, "full", e_full, "| 64 RHS: near", eb_near,
+          "full", eb_full)
     assert e_near < 1e-5
     assert e_full < 1e-3
+    assert eb_near < (1e-5 if prec == "fp32" else 5e-5)
+    assert eb_full < 1e-3
 
 
 def test_ilu_preconditioner_multilevel_fp64():
@@ -84,3 +99,23 @@ def test_polynomial_preconditioner_multilevel_fp64():
         z = ctx.sfmm_precond(x, np.zeros_like(x))[0]
     print("multilevel poly rel err", rel(z, ref))
     assert rel(z, ref) < 1e-9
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_polynomial_preconditioner_batched(prec):
+    # 64 right-hand sides: every near product of the polynomial runs on the
+    # matrix cores (FP32 or bf16-split operands, FP32 accumulation)
+    body = sphere_body(1.0, 2.56, 3)
+    mesh = rwg.from_body(body)
+    keys = octree.finest_keys(mesh, 0.25, 4)
+    near = octree.near_mask(keys)
+    Zn = mom.pmchwt_near(mesh, body.eps_r, body.mu_r, body.frequency, near)
+    th = krylov.leja_order(krylov.harmonic_ritz(lambda v: Zn @ v, krylov.golden_start(len(Zn)), 16))
+    x = random_complex_vector(2 * mesh.n_edges, 64, seed=9)
+    p = sfmm.PREC_FP32 if prec == "fp32" else sfmm.PREC_BF16_SPLIT
+    with sfmm.Context([body], precision=p, finest_box=0.25, preconditioner=sfmm.PRECOND_POLY,
+                      poly_degree=16) as ctx:
+        z = ctx.sfmm_precond(x, np.zeros_like(x))
+    err = max(rel(z[r], krylov.poly_apply(lambda v: Zn @ v, th, x[r])) for r in range(0, 64, 9))
+    print(prec, "batched poly rel err", err)
+    assert err < (1e-4 if prec == "fp32" else 1e-3)

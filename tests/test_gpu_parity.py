@@ -57,6 +57,27 @@ def ctx32(cfg1):
         yield c
 
 
+@pytest.fixture(scope="module")
+def ctxbf(cfg1):
+    print("setup cfg1 bf16-split", flush=True)
+    opts = dict(CFG1, extra_multipoles=1, tol=1e-4)
+    with sfmm.Context([cfg1["body"]], precision=sfmm.PREC_BF16_SPLIT, **opts) as c:
+        yield c
+
+
+@pytest.mark.parametrize("R", [16, 20, 64])
+def test_batched_near_on_matrix_cores(cfg1, ctx32, ctxbf, R):
+    # from 16 right-hand sides the near product runs on the matrix cores;
+    # 20 leaves a ragged second block of 16
+    x = random_complex_vector(cfg1["x"].shape[1], R, seed=40 + R)
+    ref = x @ np.where(cfg1["pat"], cfg1["Z"], 0).T
+    for ctx, tol in ((ctx32, 1e-5), (ctxbf, 5e-5)):
+        y = ctx.sfmm_matvec(x, np.zeros_like(x), parts=sfmm.PART_NEAR)
+        err = max(rel(y[r], ref[r]) for r in range(R))
+        print(R, "near rel err", err)
+        assert err < tol
+
+
 def test_near_product_fp64(cfg1, ctx64):
     x = cfg1["x"]
     y = ctx64.sfmm_matvec(x, np.zeros_like(x), parts=sfmm.PART_NEAR)
@@ -71,9 +92,9 @@ def test_near_product_fp32(cfg1, ctx32):
     assert rel(y, ref) < 1e-5
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_full_product_matches_dense(cfg1, ctx64, ctx32, prec):
-    ctx = ctx64 if prec == "fp64" else ctx32
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_full_product_matches_dense(cfg1, ctx64, ctx32, ctxbf, prec):
+    ctx = {"fp64": ctx64, "fp32": ctx32, "bf16": ctxbf}[prec]
     x = cfg1["x"]
     y = ctx.sfmm_matvec(x, np.zeros_like(x))
     ref = x @ cfg1["Z"].T
@@ -150,9 +171,9 @@ def _masked_db(s, ref):
     return np.abs(10 * np.log10((s + floor) / (ref + floor)))
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_solve_and_rcs_match_oracle(cfg1, ctx64, ctx32, prec):
-    ctx = ctx64 if prec == "fp64" else ctx32
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_solve_and_rcs_match_oracle(cfg1, ctx64, ctx32, ctxbf, prec):
+    ctx = {"fp64": ctx64, "fp32": ctx32, "bf16": ctxbf}[prec]
     m, b, Z = cfg1["mesh"], cfg1["body"], cfg1["Z"]
     kh, eh = mom.incidence(0.0, 0.0)
     rhs = mom.planewave_rhs(m, b.frequency, kh, eh)[None, :].copy()
