@@ -75,13 +75,16 @@ def cpu_baseline(body, x, seconds):
                       f"extraction, FP64 numpy, 1 thread) in {dt:.1f} s"}
 
 
-def sweep(ctx, sfmm, torch, n_ang, every):
+def sweep(ctx, ctx_mixed, torch, n_ang, every):
     """Time-to-solution of a theta sweep (theta uniform in [0, 180] degrees at
-    phi = 0, theta-polarised) to the 1e-4 true residual, three ways:
-    plain (one right-hand side per solve, zero start), batched (all angles in
-    one lockstep solve) and batched + learned guess (every `every`-th angle
-    solved first, the network trained on those currents, then the rest solved
-    from its prediction).  Wall times include training and prediction."""
+    phi = 0, theta-polarised) to the 1e-4 true residual:
+      plain          FP32, one right-hand side per solve, zero start;
+      batched        FP32, all angles in one lockstep solve;
+      mixed          bf16-split matrix-core products, all angles at once;
+      mixed_learned  bf16-split: every `every`-th angle solved first, the
+                     network trained on those currents, the rest solved from
+                     its prediction (wall time includes training/prediction).
+    """
     from workloads import theta_sweep
 
     n = ctx.sfmm_num_unknowns()
@@ -97,14 +100,15 @@ def sweep(ctx, sfmm, torch, n_ang, every):
         torch.cuda.synchronize()
         return out, time.perf_counter() - t0
 
+    def its(infos):
+        return float(np.mean([i["iterations"] for i in infos]))
+
     x = torch.zeros_like(b)
-    infos, t_plain = timed(lambda: [ctx.sfmm_solve(b[i:i + 1], x[i:i + 1])[0] for i in range(n_ang)])
-    its_plain = [i["iterations"] for i in infos]
-    ok_plain = all(i["converged"] for i in infos)
+    i_plain, t_plain = timed(lambda: [ctx.sfmm_solve(b[i:i + 1], x[i:i + 1])[0] for i in range(n_ang)])
     x.zero_()
-    infos, t_batch = timed(lambda: ctx.sfmm_solve(b, x))
-    its_batch = [i["iterations"] for i in infos]
-    ok_batch = all(i["converged"] for i in infos)
+    i_batch, t_batch = timed(lambda: ctx.sfmm_solve(b, x))
+    x.zero_()
+    i_mixed, t_mixed = timed(lambda: ctx_mixed.sfmm_solve(b, x))
 
     tr = np.arange(0, n_ang, every)
     te = np.setdiff1d(np.arange(n_ang), tr)
@@ -115,33 +119,35 @@ def sweep(ctx, sfmm, torch, n_ang, every):
         b_tr = b.index_select(0, tr_t).contiguous()
         b_te = b.index_select(0, te_t).contiguous()
         x_tr = torch.zeros_like(b_tr)
-        i_tr = ctx.sfmm_solve(b_tr, x_tr)
+        i_tr = ctx_mixed.sfmm_solve(b_tr, x_tr)
         t_fit = time.perf_counter()
-        loss = ctx.sfmm_guess_fit(ang[tr], x_tr, rank=len(tr))
+        loss = ctx_mixed.sfmm_guess_fit(ang[tr], x_tr, rank=len(tr))
         x0 = torch.zeros_like(b_te)
-        ctx.sfmm_guess_predict(ang[te], x0)
+        ctx_mixed.sfmm_guess_predict(ang[te], x0)
         torch.cuda.synchronize()
         t_fit = time.perf_counter() - t_fit
         x_te = torch.zeros_like(b_te)
-        i_te = ctx.sfmm_solve(b_te, x_te, x0=x0)
+        i_te = ctx_mixed.sfmm_solve(b_te, x_te, x0=x0)
         return i_tr, i_te, loss, t_fit
 
     (i_tr, i_te, loss, t_fit), t_learn = timed(learned)
-    ok_learn = all(i["converged"] for i in i_tr + i_te)
+    ok = all(i["converged"] for i in i_plain + i_batch + i_mixed + i_tr + i_te)
+    ms = lambda t: round(1e3 * t / n_ang, 2)  # noqa: E731
     return {
         "angles": n_ang, "tol": 1e-4,
-        "plain_ms_per_angle": round(1e3 * t_plain / n_ang, 2),
-        "batched_ms_per_angle": round(1e3 * t_batch / n_ang, 2),
-        "batched_learned_ms_per_angle": round(1e3 * t_learn / n_ang, 2),
-        "speedup_batched": round(t_plain / t_batch, 2),
-        "speedup_batched_learned": round(t_plain / t_learn, 2),
-        "iterations_mean": {"plain": float(np.mean(its_plain)), "batched": float(np.mean(its_batch)),
-                            "learned_train": float(np.mean([i["iterations"] for i in i_tr])),
-                            "learned_predicted": float(np.mean([i["iterations"] for i in i_te]))},
+        "ms_per_angle": {"plain_fp32": ms(t_plain), "batched_fp32": ms(t_batch), "batched_bf16split": ms(t_mixed),
+                         "batched_bf16split_learned": ms(t_learn)},
+        "speedup_vs_plain": {"batched_fp32": round(t_plain / t_batch, 2),
+                             "batched_bf16split": round(t_plain / t_mixed, 2),
+                             "batched_bf16split_learned": round(t_plain / t_learn, 2)},
+        "iterations_mean": {"plain_fp32": its(i_plain), "batched_fp32": its(i_batch),
+                            "batched_bf16split": its(i_mixed), "learned_training_angles": its(i_tr),
+                            "learned_predicted_angles": its(i_te)},
+        "true_residual_max": max(i["true_residual"] for i in i_plain + i_batch + i_mixed + i_tr + i_te),
         "guess": {"trained_on": len(tr), "fit_and_predict_s": round(t_fit, 3), "loss": loss,
                   "initial_residual_median": float(np.median([i["initial_residual"] for i in i_te])),
                   "used": int(sum(i["guess_used"] for i in i_te))},
-        "all_converged": bool(ok_plain and ok_batch and ok_learn),
+        "all_converged": bool(ok),
     }
 
 
@@ -255,7 +261,10 @@ def main():
         print("gmres", result["gmres"], file=sys.stderr, flush=True)
 
     if args.sweep > 0:
-        result["sweep"] = sweep(ctx, sfmm, torch, args.sweep, args.train_every)
+        ctx_mixed = sfmm.Context([body], **dict(opts, precision=sfmm.PREC_BF16_SPLIT))
+        ctx_mixed.sfmm_set_stream(stream.cuda_stream)
+        result["sweep"] = sweep(ctx, ctx_mixed, torch, args.sweep, args.train_every)
+        ctx_mixed.close()
         print("sweep", result["sweep"], file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:

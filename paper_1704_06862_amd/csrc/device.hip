@@ -42,6 +42,7 @@ namespace sfmm {
 constexpr int MAXLEV = 21;
 constexpr size_t LDS_LIMIT = 64 * 1024;
 constexpr int BATCH = 64;        // right-hand sides per batched chunk
+constexpr int TRANS_GRP_MIN_R = 33;  // sibling-grouped translation from this many RHS
 constexpr int MMA_MIN_R = 16;    // batched near products from this many RHS run on the matrix cores
 
 void *device_alloc(size_t bytes) {
@@ -146,6 +147,8 @@ class DeviceBodyT final : public DeviceBody {
             R.edge_ptr = upload(rt.edge_ptr);
             R.edge_pos = upload(rt.edge_pos);
             R.edge_sign = upload(rt.edge_sign);
+            for (int b = 0; b + 1 < (int)rt.edge_ptr.size(); ++b)
+                R.max_ebox = std::max(R.max_ebox, rt.edge_ptr[b + 1] - rt.edge_ptr[b]);
             if (f_ >= 2) {
                 R.tx = upload_cx(tb.tx);
                 if (tb.lossy) R.rx = upload_cx(tb.rx);
@@ -159,6 +162,7 @@ class DeviceBodyT final : public DeviceBody {
                     R.il_ptr[l] = upload(lv.il_ptr);
                     R.il_src[l] = upload(lv.il_src);
                     R.il_off[l] = upload(lv.il_off);
+                    build_translation_groups(R, l, lv);
                     R.trans[l] = upload_cx(tb.trans[l]);
                     if (l >= 3) {
                         R.parent[l] = upload(lv.parent);
@@ -358,6 +362,12 @@ class DeviceBodyT final : public DeviceBody {
         if ((parts & SFMM_PART_FAR) && f_ >= 2) {
             const int f = f_;
             for (Reg &G : regs_) {
+                if constexpr (std::is_same<T, float>::value) {
+                    if (R >= MMA_MIN_R) {
+                        aggregate_mma(G, R, x);
+                        continue;
+                    }
+                }
                 const int ech = std::max(1, 2048 / R);
                 const int bs = (int)std::min<int64_t>(1024, (((int64_t)G.K[f] * R + 63) / 64) * 64);
                 const size_t shm = (size_t)2 * ech * R * sizeof(cx<T>);
@@ -370,16 +380,18 @@ class DeviceBodyT final : public DeviceBody {
                 for (int l = f; l >= 3; --l) upward(G, l, R);
             mark(3);
             for (Reg &G : regs_)
-                for (int l = 2; l <= f; ++l) {
-                    k_translate<T><<<nblocks((int64_t)G.nbox[l] * G.K[l] * R), WG, 0, stream_>>>(
-                        G.nbox[l], G.K[l], R, G.il_ptr[l], G.il_src[l], G.il_off[l], G.trans[l], G.S[l], G.G[l]);
-                    LAUNCHCHK();
-                }
+                for (int l = 2; l <= f; ++l) translate(G, l, R);
             mark(4);
             for (Reg &G : regs_)
                 for (int l = 3; l <= f; ++l) downward(G, l, R);
             mark(5);
             for (Reg &G : regs_) {
+                if constexpr (std::is_same<T, float>::value) {
+                    if (R >= MMA_MIN_R) {
+                        receive_mma(G, R, y);
+                        continue;
+                    }
+                }
                 const int rt = pick_tile(R, {8, 4, 2, 1}, [](int) { return true; });
                 dim3 grid(G.nbf, R / rt);
 #define SFMM_RECV(RT_)                                                                                           \
@@ -410,6 +422,112 @@ class DeviceBodyT final : public DeviceBody {
     struct Reg;
 
   public:
+    // Sibling groups for k_translate_grp: boxes sharing a parent key, the union
+    // of their interaction lists as candidates, and per (candidate, octant)
+    // the translation offset id or -1 when the pair is not in that list.
+    void build_translation_groups(Reg &R, int l, const LevelBoxes &lv) {
+        const int nbox = (int)lv.key.size();
+        std::vector<std::array<int, 4>> order(nbox);   // parent key, box
+        for (int b = 0; b < nbox; ++b) order[b] = {lv.key[b][0] >> 1, lv.key[b][1] >> 1, lv.key[b][2] >> 1, b};
+        std::sort(order.begin(), order.end());
+        std::vector<int> dst, cptr{0}, csrc;
+        std::vector<int> coff;
+        for (int i = 0; i < nbox;) {
+            int j = i;
+            while (j < nbox && order[j][0] == order[i][0] && order[j][1] == order[i][1] && order[j][2] == order[i][2])
+                ++j;
+            int d8[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+            std::vector<int> cand;
+            for (int q = i; q < j; ++q) {
+                const int b = order[q][3];
+                const auto &kk = lv.key[b];
+                d8[(kk[0] & 1) * 4 + (kk[1] & 1) * 2 + (kk[2] & 1)] = b;
+                for (int e = lv.il_ptr[b]; e < lv.il_ptr[b + 1]; ++e) cand.push_back(lv.il_src[e]);
+            }
+            std::sort(cand.begin(), cand.end());
+            cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+            const size_t base = coff.size();
+            coff.resize(base + cand.size() * 8, -1);
+            for (int slot = 0; slot < 8; ++slot) {
+                const int b = d8[slot];
+                if (b < 0) continue;
+                for (int e = lv.il_ptr[b]; e < lv.il_ptr[b + 1]; ++e) {
+                    const size_t ci = std::lower_bound(cand.begin(), cand.end(), lv.il_src[e]) - cand.begin();
+                    coff[base + ci * 8 + slot] = lv.il_off[e];
+                }
+            }
+            for (int slot = 0; slot < 8; ++slot) dst.push_back(d8[slot]);
+            csrc.insert(csrc.end(), cand.begin(), cand.end());
+            cptr.push_back((int)csrc.size());
+            i = j;
+        }
+        R.ngrp[l] = (int)cptr.size() - 1;
+        R.grp_dst[l] = upload(dst);
+        R.cand_ptr[l] = upload(cptr);
+        R.cand_src[l] = upload(csrc);
+        R.cand_off[l] = upload(coff);
+    }
+
+    void aggregate_mma(Reg &G, int R, const cx<float> *x) {
+        const int f = f_, K = G.K[f], nmt = (K + 15) / 16, nt = (R + 15) / 16;
+        dim3 grid(G.nbf, (nmt + 3) / 4);
+#define SFMM_AGG(NT_)                                                                                               \
+    k_aggregate_mma<NT_><<<grid, 256, 0, stream_>>>(K, R, nmt, G.edge_ptr, G.edge_pos, G.edge_sign, G.tx, G.et, x, \
+                                                    G.S[f])
+        if (nt == 1) SFMM_AGG(1);
+        else if (nt == 2) SFMM_AGG(2);
+        else if (nt == 3) SFMM_AGG(3);
+        else SFMM_AGG(4);
+#undef SFMM_AGG
+        LAUNCHCHK();
+    }
+
+    void receive_mma(Reg &G, int R, cx<float> *y) {
+        const int f = f_, K = G.K[f], nt = (R + 15) / 16;
+        dim3 grid(G.nbf, (G.max_ebox + 15) / 16);
+#define SFMM_RCV(NT_, L_)                                                                                              \
+    k_receive_mma<NT_, L_><<<grid, 64 * MMA_WAVES, 0, stream_>>>(K, R, G.edge_ptr, G.edge_pos, G.edge_sign, G.tx, G.rx, \
+                                                                 G.inv_et, G.G[f], y)
+        if (G.lossy) {
+            if (nt == 1) SFMM_RCV(1, true);
+            else if (nt == 2) SFMM_RCV(2, true);
+            else if (nt == 3) SFMM_RCV(3, true);
+            else SFMM_RCV(4, true);
+        } else {
+            if (nt == 1) SFMM_RCV(1, false);
+            else if (nt == 2) SFMM_RCV(2, false);
+            else if (nt == 3) SFMM_RCV(3, false);
+            else SFMM_RCV(4, false);
+        }
+#undef SFMM_RCV
+        LAUNCHCHK();
+    }
+
+    void translate(Reg &G, int l, int R) {
+        if (R < TRANS_GRP_MIN_R) {
+            k_translate<T><<<nblocks((int64_t)G.nbox[l] * G.K[l] * R), WG, 0, stream_>>>(
+                G.nbox[l], G.K[l], R, G.il_ptr[l], G.il_src[l], G.il_off[l], G.trans[l], G.S[l], G.G[l]);
+            LAUNCHCHK();
+            return;
+        }
+        int rp = 1;
+        while (rp < R) rp <<= 1;
+        const int dpw = WG / rp;
+        dim3 grid(G.ngrp[l], (G.K[l] + dpw - 1) / dpw);
+#define SFMM_TG(RP_)                                                                                             \
+    k_translate_grp<T, RP_><<<grid, WG, 0, stream_>>>(G.K[l], R, G.grp_dst[l], G.cand_ptr[l], G.cand_src[l], \
+                                                      G.cand_off[l], G.trans[l], G.S[l], G.G[l])
+        if (rp == 64) SFMM_TG(64);
+        else if (rp == 32) SFMM_TG(32);
+        else if (rp == 16) SFMM_TG(16);
+        else if (rp == 8) SFMM_TG(8);
+        else if (rp == 4) SFMM_TG(4);
+        else if (rp == 2) SFMM_TG(2);
+        else SFMM_TG(1);
+#undef SFMM_TG
+        LAUNCHCHK();
+    }
+
     void upward(Reg &G, int l, int R) {
         const int nth_c = G.nth[l], nph_c = G.nph[l], nth_p = G.nth[l - 1], nph_p = G.nph[l - 1];
         const int rt = pick_tile(R, {4, 2, 1}, [&](int t) {
@@ -833,12 +951,16 @@ class DeviceBodyT final : public DeviceBody {
     struct Reg {
         cx<T> et{}, inv_et{};
         bool lossy = false;
-        int nbf = 0;
+        int nbf = 0, max_ebox = 0;
         int *edge_ptr = nullptr, *edge_pos = nullptr, *edge_sign = nullptr;
         cx<T> *tx = nullptr, *rx = nullptr, *tmp = nullptr;
         int K[MAXLEV] = {0}, nth[MAXLEV] = {0}, nph[MAXLEV] = {0}, nbox[MAXLEV] = {0};
         cx<T> *S[MAXLEV] = {nullptr}, *G[MAXLEV] = {nullptr}, *trans[MAXLEV] = {nullptr};
         int *il_ptr[MAXLEV] = {nullptr}, *il_src[MAXLEV] = {nullptr}, *il_off[MAXLEV] = {nullptr};
+        // translation groups (siblings of one parent): dst[g][octant], candidate sources, offsets
+        int ngrp[MAXLEV] = {0};
+        int *grp_dst[MAXLEV] = {nullptr}, *cand_ptr[MAXLEV] = {nullptr}, *cand_src[MAXLEV] = {nullptr};
+        int *cand_off[MAXLEV] = {nullptr};
         int *parent[MAXLEV] = {nullptr}, *slot[MAXLEV] = {nullptr};
         int *child_ptr[MAXLEV] = {nullptr}, *child_idx[MAXLEV] = {nullptr};
         T *ipA[MAXLEV] = {nullptr}, *ipB[MAXLEV] = {nullptr}, *ipD[MAXLEV] = {nullptr}, *ipDt[MAXLEV] = {nullptr};

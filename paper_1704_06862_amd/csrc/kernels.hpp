@@ -24,14 +24,24 @@ __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
     return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
 template <typename T>
+__device__ __forceinline__ T fmad(T a, T b, T c) {
+    if constexpr (sizeof(T) == 4) return __builtin_fmaf(a, b, c);
+    else return __builtin_fma(a, b, c);
+}
+// acc += a b and acc -= a b as four fused multiply-adds
+template <typename T>
 __device__ __forceinline__ void cfma(cx<T> &acc, cx<T> a, cx<T> b) {
-    acc.x += a.x * b.x - a.y * b.y;
-    acc.y += a.x * b.y + a.y * b.x;
+    acc.x = fmad(a.x, b.x, acc.x);
+    acc.x = fmad(-a.y, b.y, acc.x);
+    acc.y = fmad(a.x, b.y, acc.y);
+    acc.y = fmad(a.y, b.x, acc.y);
 }
 template <typename T>
-__device__ __forceinline__ void cfms(cx<T> &acc, cx<T> a, cx<T> b) {  // acc -= a b
-    acc.x -= a.x * b.x - a.y * b.y;
-    acc.y -= a.x * b.y + a.y * b.x;
+__device__ __forceinline__ void cfms(cx<T> &acc, cx<T> a, cx<T> b) {
+    acc.x = fmad(-a.x, b.x, acc.x);
+    acc.x = fmad(a.y, b.y, acc.x);
+    acc.y = fmad(-a.x, b.y, acc.y);
+    acc.y = fmad(-a.y, b.x, acc.y);
 }
 template <typename T>
 __device__ __forceinline__ cx<T> cconj(cx<T> a) {
@@ -622,6 +632,69 @@ __global__ void __launch_bounds__(WG) k_translate(int nbox, int K, int R, const 
     }
     G[(size_t)b * 2 * KR + kr] = gt;
     G[(size_t)b * 2 * KR + KR + kr] = gp;
+}
+
+// Translation for batched right-hand sides, grouped by parent: the (up to 8)
+// boxes of one parent share most of their interaction lists, so each source
+// pattern sample is loaded once per group and applied to every sibling whose
+// list holds it (offset id >= 0 in cand_off[c][slot]).  Lanes: rr = lane % RP
+// (right-hand side, RP = R rounded up to a power of two), the rest of the
+// workgroup runs over directions; blockIdx.x = group, blockIdx.y = direction
+// chunk, so concurrent workgroups share a slab of directions in cache.
+template <typename T, int RP>
+__global__ void __launch_bounds__(WG) k_translate_grp(int K, int R, const int *__restrict__ grp_dst,
+                                                      const int *__restrict__ cand_ptr,
+                                                      const int *__restrict__ cand_src,
+                                                      const int *__restrict__ cand_off,
+                                                      const cx<T> *__restrict__ trans, const cx<T> *__restrict__ S,
+                                                      cx<T> *__restrict__ G) {
+    constexpr int DPW = WG / RP;   // directions per workgroup
+    const int g = blockIdx.x;
+    const int rr = threadIdx.x % RP;
+    int k = blockIdx.y * DPW + threadIdx.x / RP;
+    if (RP == 64) k = __builtin_amdgcn_readfirstlane(k);
+    if (k >= K || rr >= R) return;
+    const int64_t KR = (int64_t)K * R;
+    const int64_t kr = (int64_t)k * R + rr;
+    cx<T> acc[8][2];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j][0] = acc[j][1] = cx<T>{0, 0};
+    const int c1 = cand_ptr[g + 1];
+    int c = cand_ptr[g];
+    cx<T> s0 = {0, 0}, s1 = {0, 0};
+    if (c < c1) {
+        const int64_t base = (int64_t)cand_src[c] * 2 * KR + kr;
+        s0 = S[base];
+        s1 = S[base + KR];
+    }
+    for (; c < c1; ++c) {
+        // the next candidate's samples are in flight while this one is applied
+        cx<T> n0 = {0, 0}, n1 = {0, 0};
+        if (c + 1 < c1) {
+            const int64_t base = (int64_t)cand_src[c + 1] * 2 * KR + kr;
+            n0 = S[base];
+            n1 = S[base + KR];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int o = cand_off[(int64_t)c * 8 + j];
+            if (o >= 0) {
+                const cx<T> t = trans[(int64_t)o * K + k];
+                cfma(acc[j][0], t, s0);
+                cfma(acc[j][1], t, s1);
+            }
+        }
+        s0 = n0;
+        s1 = n1;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int d = grp_dst[g * 8 + j];
+        if (d >= 0) {
+            G[(int64_t)d * 2 * KR + kr] = acc[j][0];
+            G[(int64_t)d * 2 * KR + KR + kr] = acc[j][1];
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------

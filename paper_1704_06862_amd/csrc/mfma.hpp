@@ -221,4 +221,185 @@ __global__ void __launch_bounds__(64 * MMA_WAVES)
     }
 }
 
+
+// Finest-level aggregation on the matrix cores (FP32):
+//   S_t(k) += F_t(k) j + F_p(k) m,   S_p(k) += F_p(k) j - F_t(k) m,
+// j = et s x_J, m = s x_M for the edges n of region box b.  Rows (M) are
+// directions k, K runs over the box's edges, N over right-hand sides.  Grid
+// (box, groups of 4 direction tiles); each wave owns one 16-direction tile.
+template <int NT>
+__global__ void __launch_bounds__(256) k_aggregate_mma(int K, int R, int nmt, const int *__restrict__ edge_ptr,
+                                                       const int *__restrict__ edge_pos,
+                                                       const int *__restrict__ edge_sign,
+                                                       const cx<float> *__restrict__ tx, cx<float> et,
+                                                       const cx<float> *__restrict__ x, cx<float> *__restrict__ S) {
+    const int b = blockIdx.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int mt = blockIdx.y * 4 + wave;
+    if (mt >= nmt) return;
+    const int lr = lane & 15, lg = lane >> 4;
+    const int e0 = edge_ptr[b], n = edge_ptr[b + 1] - e0;
+    const int k = 16 * mt + lr;
+    f32x4 tr[NT], ti[NT], pr[NT], pi[NT];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) tr[q] = ti[q] = pr[q] = pi[q] = f32x4{0, 0, 0, 0};
+    for (int s = 0; s < (n + 3) / 4; ++s) {
+        const int e = 4 * s + lg;
+        cx<float> ft = {0, 0}, fp = {0, 0};
+        int p = -1;
+        float sg = 0;
+        if (e < n) {
+            if (k < K) {
+                ft = tx[(int64_t)(e0 + e) * 2 * K + k];
+                fp = tx[(int64_t)(e0 + e) * 2 * K + K + k];
+            }
+            p = edge_pos[e0 + e];
+            sg = (float)edge_sign[e0 + e];
+        }
+        const float nfti = -ft.y, nftr = -ft.x, nfpi = -fp.y;
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+            const int rhs = 16 * q + lr;
+            cx<float> j = {0, 0}, m = {0, 0};
+            if (p >= 0 && rhs < R) {
+                const cx<float> xj = x[(int64_t)(2 * p) * R + rhs], xm = x[(int64_t)(2 * p + 1) * R + rhs];
+                j = cmul(et, cx<float>{sg * xj.x, sg * xj.y});
+                m = {sg * xm.x, sg * xm.y};
+            }
+            mma_f32(tr[q], ft.x, j.x);
+            mma_f32(tr[q], nfti, j.y);
+            mma_f32(tr[q], fp.x, m.x);
+            mma_f32(tr[q], nfpi, m.y);
+            mma_f32(ti[q], ft.x, j.y);
+            mma_f32(ti[q], ft.y, j.x);
+            mma_f32(ti[q], fp.x, m.y);
+            mma_f32(ti[q], fp.y, m.x);
+            mma_f32(pr[q], fp.x, j.x);
+            mma_f32(pr[q], nfpi, j.y);
+            mma_f32(pr[q], nftr, m.x);
+            mma_f32(pr[q], ft.y, m.y);
+            mma_f32(pi[q], fp.x, j.y);
+            mma_f32(pi[q], fp.y, j.x);
+            mma_f32(pi[q], nftr, m.y);
+            mma_f32(pi[q], nfti, m.x);
+        }
+    }
+    const int64_t KR = (int64_t)K * R;
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+        const int rhs = 16 * q + lr;
+        if (rhs >= R) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int kk = 16 * mt + 4 * lg + v;
+            if (kk >= K) continue;
+            S[(int64_t)b * 2 * KR + (int64_t)kk * R + rhs] = {tr[q][v], ti[q][v]};
+            S[(int64_t)b * 2 * KR + KR + (int64_t)kk * R + rhs] = {pr[q][v], pi[q][v]};
+        }
+    }
+}
+
+// Finest-level receive on the matrix cores (FP32):
+//   y_E += s sum_k (R_t G_t + R_p G_p),  y_H += (s / et) sum_k (R_p G_t - R_t G_p)
+// with R = conj(F) (real wavenumber) or the separate receive table.  Rows are
+// the box's edges (16 per tile), K runs over directions (4 waves take every
+// 4th step, partial sums added through LDS), N over right-hand sides.
+template <int NT, bool LOSSY>
+__global__ void __launch_bounds__(64 * MMA_WAVES)
+    k_receive_mma(int K, int R, const int *__restrict__ edge_ptr, const int *__restrict__ edge_pos,
+                  const int *__restrict__ edge_sign, const cx<float> *__restrict__ tx,
+                  const cx<float> *__restrict__ rx, cx<float> inv_et, const cx<float> *__restrict__ G,
+                  cx<float> *__restrict__ y) {
+    __shared__ f32x4 red[MMA_WAVES - 1][NT * 4][64];
+    const int b = blockIdx.x, mt = blockIdx.y;
+    const int e0 = edge_ptr[b], n = edge_ptr[b + 1] - e0;
+    if (16 * mt >= n) return;   // uniform over the workgroup
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, lg = lane >> 4;
+    const int row = 16 * mt + lr;
+    const cx<float> *tab = LOSSY ? rx : tx;
+    const int64_t KR = (int64_t)K * R;
+    const cx<float> *g = G + (int64_t)b * 2 * KR;
+    f32x4 er[NT], ei[NT], hr[NT], hi[NT];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) er[q] = ei[q] = hr[q] = hi[q] = f32x4{0, 0, 0, 0};
+    for (int s = wave; s < (K + 3) / 4; s += MMA_WAVES) {
+        const int k = 4 * s + lg;
+        cx<float> rt = {0, 0}, rp = {0, 0};
+        if (row < n && k < K) {
+            rt = tab[(int64_t)(e0 + row) * 2 * K + k];
+            rp = tab[(int64_t)(e0 + row) * 2 * K + K + k];
+            if (!LOSSY) {
+                rt.y = -rt.y;
+                rp.y = -rp.y;
+            }
+        }
+        const float nrti = -rt.y, nrtr = -rt.x, nrpi = -rp.y;
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+            const int rhs = 16 * q + lr;
+            cx<float> gt = {0, 0}, gp = {0, 0};
+            if (k < K && rhs < R) {
+                gt = g[(int64_t)k * R + rhs];
+                gp = g[KR + (int64_t)k * R + rhs];
+            }
+            mma_f32(er[q], rt.x, gt.x);
+            mma_f32(er[q], nrti, gt.y);
+            mma_f32(er[q], rp.x, gp.x);
+            mma_f32(er[q], nrpi, gp.y);
+            mma_f32(ei[q], rt.x, gt.y);
+            mma_f32(ei[q], rt.y, gt.x);
+            mma_f32(ei[q], rp.x, gp.y);
+            mma_f32(ei[q], rp.y, gp.x);
+            mma_f32(hr[q], nrtr, gp.x);
+            mma_f32(hr[q], rt.y, gp.y);
+            mma_f32(hr[q], rp.x, gt.x);
+            mma_f32(hr[q], nrpi, gt.y);
+            mma_f32(hi[q], nrtr, gp.y);
+            mma_f32(hi[q], nrti, gp.x);
+            mma_f32(hi[q], rp.x, gt.y);
+            mma_f32(hi[q], rp.y, gt.x);
+        }
+    }
+    if (wave > 0) {
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+            red[wave - 1][4 * q + 0][lane] = er[q];
+            red[wave - 1][4 * q + 1][lane] = ei[q];
+            red[wave - 1][4 * q + 2][lane] = hr[q];
+            red[wave - 1][4 * q + 3][lane] = hi[q];
+        }
+    }
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+#pragma unroll
+        for (int w = 0; w < MMA_WAVES - 1; ++w) {
+            er[q] += red[w][4 * q + 0][lane];
+            ei[q] += red[w][4 * q + 1][lane];
+            hr[q] += red[w][4 * q + 2][lane];
+            hi[q] += red[w][4 * q + 3][lane];
+        }
+        const int rhs = 16 * q + lr;
+        if (rhs >= R) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int ed = 16 * mt + 4 * lg + v;
+            if (ed >= n) continue;
+            const int p = edge_pos[e0 + ed];
+            const float sg = (float)edge_sign[e0 + ed];
+            const cx<float> hh = cmul(cx<float>{hr[q][v], hi[q][v]}, inv_et);
+            const int64_t iE = (int64_t)(2 * p) * R + rhs, iH = iE + R;
+            cx<float> ye = y[iE], yh = y[iH];
+            ye.x += sg * er[q][v];
+            ye.y += sg * ei[q][v];
+            yh.x += sg * hh.x;
+            yh.y += sg * hh.y;
+            y[iE] = ye;
+            y[iH] = yh;
+        }
+    }
+}
+
 }  // namespace sfmm

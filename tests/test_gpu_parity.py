@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 from oracle import farfield, krylov, mom, octree, rwg
-from workloads import random_complex_vector, sphere_body
+from workloads import coated_sphere_body, random_complex_vector, sphere_body
 
 pytestmark = pytest.mark.gpu
 
@@ -76,6 +76,59 @@ def test_batched_near_on_matrix_cores(cfg1, ctx32, ctxbf, R):
         err = max(rel(y[r], ref[r]) for r in range(R))
         print(R, "near rel err", err)
         assert err < tol
+
+
+@pytest.mark.parametrize("R", [16, 64])
+def test_batched_full_product_on_matrix_cores(cfg1, ctx32, ctxbf, R):
+    # aggregation, receive (and, from 33 RHS, the sibling-grouped translation)
+    # switch to their batched kernels
+    x = random_complex_vector(cfg1["x"].shape[1], R, seed=60 + R)
+    ref = x @ cfg1["Z"].T
+    for ctx in (ctx32, ctxbf):
+        y = ctx.sfmm_matvec(x, np.zeros_like(x))
+        err = max(rel(y[r], ref[r]) for r in range(R))
+        y1 = ctx.sfmm_matvec(np.ascontiguousarray(x[:1]), np.zeros_like(x[:1]))[0]
+        print(R, "batched full rel err", err, "vs single", rel(y[0], y1))
+        assert err < 3e-3
+        assert rel(y[0], y1) < 1e-4
+
+
+@pytest.fixture(scope="module")
+def coated():
+    # lossy core (complex wavenumber: separate receive table) inside a shell
+    b = coated_sphere_body(0.15, 6 - 0.5j, 1, 0.3, 2.56, 2)
+    m = rwg.from_body(b)
+    print("oracle dense coated sphere", flush=True)
+    Z = mom.pmchwt_dense(m, b.eps_r, b.mu_r, b.frequency)
+    return dict(body=b, mesh=m, Z=Z)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_coated_lossy_sphere_product_and_rcs(coated, prec):
+    b, m, Z = coated["body"], coated["mesh"], coated["Z"]
+    p = sfmm.PREC_FP64 if prec == "fp64" else sfmm.PREC_FP32
+    opts = dict(finest_box=0.15, n_levels=3, extra_multipoles=5 if prec == "fp64" else 1,
+                tol=1e-6 if prec == "fp64" else 1e-4)
+    with sfmm.Context([b], precision=p, **opts) as ctx:
+        assert ctx.sfmm_num_unknowns() == 2 * m.n_edges
+        for R in (1, 16):
+            x = random_complex_vector(2 * m.n_edges, R, seed=90 + R)
+            y = ctx.sfmm_matvec(x, np.zeros_like(x))
+            ref = x @ Z.T
+            err = max(rel(y[r], ref[r]) for r in range(R))
+            print(prec, R, "coated product rel err", err)
+            assert err < (1e-3 if prec == "fp64" else 3e-3)
+        kh, eh = mom.incidence(0.0, 0.0)
+        rhs = mom.planewave_rhs(m, b.frequency, kh, eh)[None, :].copy()
+        xs = np.zeros_like(rhs)
+        info = ctx.sfmm_solve(rhs, xs)[0]
+        assert info["converged"]
+        xd = np.linalg.solve(Z, rhs[0])
+        tp = np.stack([THETA, 0 * THETA], 1)
+        sE = ctx.sfmm_rcs(xs, tp)[0, :, 0]
+        rE, _ = farfield.rcs(m, b.frequency, xd, THETA, 0 * THETA)
+        print(prec, "coated RCS max dB diff", _masked_db(sE, rE).max(), info)
+        assert _masked_db(sE, rE).max() < 0.2
 
 
 def test_near_product_fp64(cfg1, ctx64):
