@@ -178,6 +178,23 @@ class DeviceBodyT final : public DeviceBody {
                         R.ipDt[l] = upload_real(Dt);
                         R.sup[l] = upload_cx(tb.shift_up[l]);
                         R.sdn[l] = upload_cx(tb.shift_dn[l]);
+                        if constexpr (std::is_same<T, float>::value) {
+                            // phi stage with the child shift folded in, per (octant, parent theta row)
+                            const int nt_p = tb.samp[l - 1].nth;
+                            const size_t Kp = (size_t)nt_p * np_p;
+                            std::vector<cd> up((size_t)8 * nt_p * np_p * np_c), dn(up.size());
+                            for (int sl = 0; sl < 8; ++sl)
+                                for (int I = 0; I < nt_p; ++I)
+                                    for (int J = 0; J < np_p; ++J)
+                                        for (int jj = 0; jj < np_c; ++jj) {
+                                            const double d = tb.ipD[l][(size_t)J * np_c + jj];
+                                            const size_t q = (size_t)sl * Kp + (size_t)I * np_p + J;
+                                            up[(((size_t)sl * nt_p + I) * np_p + J) * np_c + jj] = d * tb.shift_up[l][q];
+                                            dn[(((size_t)sl * nt_p + I) * np_c + jj) * np_p + J] = d * tb.shift_dn[l][q];
+                                        }
+                            R.Dup[l] = upload_cx(up);
+                            R.Ddn[l] = upload_cx(dn);
+                        }
                     }
                     if (l < f_) {
                         R.child_ptr[l] = upload(lv.child_ptr);
@@ -503,6 +520,46 @@ class DeviceBodyT final : public DeviceBody {
         LAUNCHCHK();
     }
 
+    // matrix-core interpolation: sizes within 4 tiles of 16 (theta pairs and phi)
+    bool interp_mma_ok(const Reg &G, int l, int R) const {
+        return R >= MMA_MIN_R && G.Dup[l] && 2 * G.nth[l - 1] <= 64 && 2 * G.nth[l] <= 64 && G.nph[l - 1] <= 64 &&
+               G.nph[l] <= 64;
+    }
+
+    void upward_mma(Reg &G, int l, int R) {
+        const int nt = (R + 15) / 16;
+        const int nth_c = G.nth[l], nph_c = G.nph[l], nth_p = G.nth[l - 1], nph_p = G.nph[l - 1];
+        const unsigned g1 = (unsigned)G.nbox[l] * 2, g2 = (unsigned)G.nbox[l - 1] * 2 * nth_p;
+#define SFMM_UPM(NT_)                                                                                                \
+    k_up_theta_mma<NT_><<<g1, 256, 0, stream_>>>(R, nth_c, nph_c, nth_p, G.ipA[l], G.ipB[l], G.S[l], G.tmp);         \
+    LAUNCHCHK();                                                                                                     \
+    k_up_phi_mma<NT_><<<g2, 256, 0, stream_>>>(R, nth_p, nph_p, nph_c, G.Dup[l], G.child_ptr[l - 1],                \
+                                               G.child_idx[l - 1], G.slot[l], G.tmp, G.S[l - 1]);                    \
+    LAUNCHCHK()
+        if (nt == 1) { SFMM_UPM(1); }
+        else if (nt == 2) { SFMM_UPM(2); }
+        else if (nt == 3) { SFMM_UPM(3); }
+        else { SFMM_UPM(4); }
+#undef SFMM_UPM
+    }
+
+    void downward_mma(Reg &G, int l, int R) {
+        const int nt = (R + 15) / 16;
+        const int nth_c = G.nth[l], nph_c = G.nph[l], nth_p = G.nth[l - 1], nph_p = G.nph[l - 1];
+        const unsigned g1 = (unsigned)G.nbox[l] * 2 * nth_p, g2 = (unsigned)G.nbox[l] * 2;
+#define SFMM_DNM(NT_)                                                                                              \
+    k_dn_phi_mma<NT_><<<g1, 256, 0, stream_>>>(R, nth_p, nph_p, nph_c, G.Ddn[l], G.parent[l], G.slot[l],            \
+                                               G.G[l - 1], G.tmp);                                                 \
+    LAUNCHCHK();                                                                                                   \
+    k_dn_theta_mma<NT_><<<g2, 256, 0, stream_>>>(R, nth_c, nph_c, nth_p, G.ipA[l], G.ipB[l], G.tmp, G.G[l]);        \
+    LAUNCHCHK()
+        if (nt == 1) { SFMM_DNM(1); }
+        else if (nt == 2) { SFMM_DNM(2); }
+        else if (nt == 3) { SFMM_DNM(3); }
+        else { SFMM_DNM(4); }
+#undef SFMM_DNM
+    }
+
     void translate(Reg &G, int l, int R) {
         if (R < TRANS_GRP_MIN_R) {
             k_translate<T><<<nblocks((int64_t)G.nbox[l] * G.K[l] * R), WG, 0, stream_>>>(
@@ -530,6 +587,12 @@ class DeviceBodyT final : public DeviceBody {
 
     void upward(Reg &G, int l, int R) {
         const int nth_c = G.nth[l], nph_c = G.nph[l], nth_p = G.nth[l - 1], nph_p = G.nph[l - 1];
+        if constexpr (std::is_same<T, float>::value) {
+            if (interp_mma_ok(G, l, R)) {
+                upward_mma(G, l, R);
+                return;
+            }
+        }
         const int rt = pick_tile(R, {4, 2, 1}, [&](int t) {
             return ((size_t)G.K[l] + (size_t)UPR * nph_c) * t * sizeof(cx<T>) <= LDS_LIMIT &&
                    UPR * nph_p * t <= WG * UPMAX;
@@ -562,6 +625,12 @@ class DeviceBodyT final : public DeviceBody {
 
     void downward(Reg &G, int l, int R) {
         const int nth_c = G.nth[l], nph_c = G.nph[l], nth_p = G.nth[l - 1], nph_p = G.nph[l - 1];
+        if constexpr (std::is_same<T, float>::value) {
+            if (interp_mma_ok(G, l, R)) {
+                downward_mma(G, l, R);
+                return;
+            }
+        }
         const int rt = pick_tile(R, {4, 2, 1}, [&](int t) {
             return ((size_t)G.K[l - 1] + (size_t)nth_p * nph_c) * t * sizeof(cx<T>) <= LDS_LIMIT;
         });
@@ -965,6 +1034,7 @@ class DeviceBodyT final : public DeviceBody {
         int *child_ptr[MAXLEV] = {nullptr}, *child_idx[MAXLEV] = {nullptr};
         T *ipA[MAXLEV] = {nullptr}, *ipB[MAXLEV] = {nullptr}, *ipD[MAXLEV] = {nullptr}, *ipDt[MAXLEV] = {nullptr};
         cx<T> *sup[MAXLEV] = {nullptr}, *sdn[MAXLEV] = {nullptr};
+        cx<T> *Dup[MAXLEV] = {nullptr}, *Ddn[MAXLEV] = {nullptr};   // shift-folded phi stages
     };
 
     template <typename U>

@@ -402,4 +402,253 @@ __global__ void __launch_bounds__(64 * MMA_WAVES)
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Interpolation (upward) and anterpolation (downward) on the matrix cores.
+// The theta stage of a child pattern is, for every phi pair (j, j + h),
+//   [T(:, j); T(:, j+h)] = W [f(:, j); f(:, j+h)],   W = [[A, B], [B, A]]
+// (2 nth_p x 2 nth_c, real), and the phi stage with the child shift folded in
+// is, for every parent theta row I, a complex matrix Dsh[slot][I] applied to
+// T(I, :).  The intermediate T goes through HBM (tmp[c][comp][I][j][R]).
+// Limits: 2 nth <= 64 and nph <= 64 (4 tiles of 16), checked by the host.
+constexpr int IMT = 4;    // max 16-row tiles
+constexpr int IKS = 16;   // max 4-column steps
+
+// W (or its transpose) entry for the theta stage: row r, column k over
+// [top/bottom half][theta index] blocks of sizes (nr, nk)
+__device__ __forceinline__ float theta_w(const float *A, const float *B, int row, int col, int nr, int nk,
+                                         int ldA, bool transpose) {
+    if (row >= 2 * nr || col >= 2 * nk) return 0.f;
+    const int hr = row >= nr, hc = col >= nk;
+    const int r = row - hr * nr, c = col - hc * nk;
+    // W[(hr, I)][(hc, i)] = A[I][i] if hr == hc else B[I][i]; transpose swaps roles
+    const int I = transpose ? c : r, i = transpose ? r : c;
+    return (hr == hc) ? A[I * ldA + i] : B[I * ldA + i];
+}
+
+// theta stage, upward: grid = children x 2 components.  W is staged in LDS in
+// operand order; each wave takes (phi pair, 16-RHS tile) column blocks.
+template <int NT>
+__global__ void __launch_bounds__(256) k_up_theta_mma(int R, int nth_c, int nph_c, int nth_p,
+                                                      const float *__restrict__ A, const float *__restrict__ B,
+                                                      const cx<float> *__restrict__ Sc, cx<float> *__restrict__ tmp) {
+    __shared__ float Wop[IMT * IKS * 64];
+    const int c = blockIdx.x >> 1, comp = blockIdx.x & 1;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+    const int h = nph_c / 2, Kc = nth_c * nph_c;
+    const int nmt = (2 * nth_p + 15) / 16, nks = (2 * nth_c + 3) / 4;
+    for (int t = threadIdx.x; t < IMT * IKS * 64; t += 256) {
+        const int l = t & 63, ms = t >> 6, mt = ms / IKS, st = ms % IKS;
+        Wop[t] = theta_w(A, B, 16 * mt + (l & 15), 4 * st + (l >> 4), nth_p, nth_c, nth_c, false);
+    }
+    __syncthreads();
+    const cx<float> *f = Sc + ((int64_t)c * 2 + comp) * Kc * R;
+    cx<float> *out = tmp + ((int64_t)c * 2 + comp) * nth_p * nph_c * R;
+    for (int ct = wave; ct < h * NT; ct += 4) {
+        const int jp = ct / NT, n = ct % NT;
+        const int rhs = 16 * n + lr;
+        f32x4 re[IMT], im[IMT];
+#pragma unroll
+        for (int mt = 0; mt < IMT; ++mt) re[mt] = im[mt] = f32x4{0, 0, 0, 0};
+        for (int st = 0; st < nks; ++st) {
+            const int k = 4 * st + lg;
+            const int hk = k >= nth_c, i = k - hk * nth_c;
+            cx<float> fv = {0, 0};
+            if (k < 2 * nth_c && rhs < R) fv = f[(int64_t)(i * nph_c + jp + hk * h) * R + rhs];
+#pragma unroll
+            for (int mt = 0; mt < IMT; ++mt) {
+                if (mt < nmt) {
+                    const float w = Wop[(mt * IKS + st) * 64 + lane];
+                    mma_f32(re[mt], w, fv.x);
+                    mma_f32(im[mt], w, fv.y);
+                }
+            }
+        }
+        if (rhs >= R) continue;
+#pragma unroll
+        for (int mt = 0; mt < IMT; ++mt) {
+            if (mt >= nmt) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * mt + 4 * lg + v;
+                if (row >= 2 * nth_p) continue;
+                const int hr = row >= nth_p, I = row - hr * nth_p;
+                out[(int64_t)(I * nph_c + jp + hr * h) * R + rhs] = {re[mt][v], im[mt][v]};
+            }
+        }
+    }
+}
+
+// phi stage + shift, upward: grid = parents x 2 x nth_p; wave w = 16-row
+// tile of parent phi samples J; K runs over the children's phi samples, so
+// the sum over children accumulates inside the matrix-core accumulators.
+// Dsh[slot][I][J][j] = D[J][j] shift_up[slot][I nph_p + J] (complex).
+template <int NT>
+__global__ void __launch_bounds__(256) k_up_phi_mma(int R, int nth_p, int nph_p, int nph_c,
+                                                    const cx<float> *__restrict__ Dsh,
+                                                    const int *__restrict__ child_ptr,
+                                                    const int *__restrict__ child_idx,
+                                                    const int *__restrict__ child_slot,
+                                                    const cx<float> *__restrict__ tmp, cx<float> *__restrict__ Sp) {
+    int bid = blockIdx.x;
+    const int I = bid % nth_p;
+    bid /= nth_p;
+    const int comp = bid % 2, P = bid / 2;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+    if (16 * wave >= nph_p) return;
+    const int J = 16 * wave + lr;
+    f32x4 re[NT], im[NT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) re[n] = im[n] = f32x4{0, 0, 0, 0};
+    for (int q = child_ptr[P]; q < child_ptr[P + 1]; ++q) {
+        const int c = child_idx[q];
+        const cx<float> *a_row = Dsh + (((int64_t)child_slot[c] * nth_p + I) * nph_p + J) * nph_c;
+        const cx<float> *t = tmp + (((int64_t)c * 2 + comp) * nth_p + I) * nph_c * R;
+        for (int st = 0; st < (nph_c + 3) / 4; ++st) {
+            const int j = 4 * st + lg;
+            cx<float> a = {0, 0};
+            if (J < nph_p && j < nph_c) a = a_row[j];
+            const float nay = -a.y;
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+                const int rhs = 16 * n + lr;
+                cx<float> b = {0, 0};
+                if (j < nph_c && rhs < R) b = t[(int64_t)j * R + rhs];
+                mma_f32(re[n], a.x, b.x);
+                mma_f32(re[n], nay, b.y);
+                mma_f32(im[n], a.x, b.y);
+                mma_f32(im[n], a.y, b.x);
+            }
+        }
+    }
+    cx<float> *out = Sp + (((int64_t)P * 2 + comp) * nth_p * nph_p + (int64_t)I * nph_p) * R;
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+        const int rhs = 16 * n + lr;
+        if (rhs >= R) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int JJ = 16 * wave + 4 * lg + v;
+            if (JJ < nph_p) out[(int64_t)JJ * R + rhs] = {re[n][v], im[n][v]};
+        }
+    }
+}
+
+// phi stage (transpose) + shift, downward: grid = children x 2 x nth_p;
+// wave w = 16-row tile of child phi samples j; K runs over parent phi samples.
+// Dsh[slot][I][j][J] = D[J][j] shift_dn[slot][I nph_p + J] (complex).
+template <int NT>
+__global__ void __launch_bounds__(256) k_dn_phi_mma(int R, int nth_p, int nph_p, int nph_c,
+                                                    const cx<float> *__restrict__ Dsh,
+                                                    const int *__restrict__ parent,
+                                                    const int *__restrict__ child_slot,
+                                                    const cx<float> *__restrict__ Gp, cx<float> *__restrict__ tmp) {
+    int bid = blockIdx.x;
+    const int I = bid % nth_p;
+    bid /= nth_p;
+    const int comp = bid % 2, c = bid / 2;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+    if (16 * wave >= nph_c) return;
+    const int j = 16 * wave + lr;
+    const cx<float> *a_row = Dsh + (((int64_t)child_slot[c] * nth_p + I) * nph_c + j) * nph_p;
+    const cx<float> *g = Gp + (((int64_t)parent[c] * 2 + comp) * nth_p * nph_p + (int64_t)I * nph_p) * R;
+    f32x4 re[NT], im[NT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) re[n] = im[n] = f32x4{0, 0, 0, 0};
+    for (int st = 0; st < (nph_p + 3) / 4; ++st) {
+        const int J = 4 * st + lg;
+        cx<float> a = {0, 0};
+        if (j < nph_c && J < nph_p) a = a_row[J];
+        const float nay = -a.y;
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            const int rhs = 16 * n + lr;
+            cx<float> b = {0, 0};
+            if (J < nph_p && rhs < R) b = g[(int64_t)J * R + rhs];
+            mma_f32(re[n], a.x, b.x);
+            mma_f32(re[n], nay, b.y);
+            mma_f32(im[n], a.x, b.y);
+            mma_f32(im[n], a.y, b.x);
+        }
+    }
+    cx<float> *out = tmp + (((int64_t)c * 2 + comp) * nth_p + I) * nph_c * R;
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+        const int rhs = 16 * n + lr;
+        if (rhs >= R) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int jj = 16 * wave + 4 * lg + v;
+            if (jj < nph_c) out[(int64_t)jj * R + rhs] = {re[n][v], im[n][v]};
+        }
+    }
+}
+
+// theta stage (transpose), downward: grid = children x 2; adds
+// W^T [T(:, j); T(:, j+h)] into the child pattern (same blocking as upward).
+template <int NT>
+__global__ void __launch_bounds__(256) k_dn_theta_mma(int R, int nth_c, int nph_c, int nth_p,
+                                                      const float *__restrict__ A, const float *__restrict__ B,
+                                                      const cx<float> *__restrict__ tmp, cx<float> *__restrict__ Gc) {
+    __shared__ float Wop[IMT * IKS * 64];
+    const int c = blockIdx.x >> 1, comp = blockIdx.x & 1;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+    const int h = nph_c / 2, Kc = nth_c * nph_c;
+    const int nmt = (2 * nth_c + 15) / 16, nks = (2 * nth_p + 3) / 4;
+    for (int t = threadIdx.x; t < IMT * IKS * 64; t += 256) {
+        const int l = t & 63, ms = t >> 6, mt = ms / IKS, st = ms % IKS;
+        Wop[t] = theta_w(A, B, 16 * mt + (l & 15), 4 * st + (l >> 4), nth_c, nth_p, nth_c, true);
+    }
+    __syncthreads();
+    const cx<float> *t = tmp + ((int64_t)c * 2 + comp) * nth_p * nph_c * R;
+    cx<float> *out = Gc + ((int64_t)c * 2 + comp) * Kc * R;
+    for (int ct = wave; ct < h * NT; ct += 4) {
+        const int jp = ct / NT, n = ct % NT;
+        const int rhs = 16 * n + lr;
+        f32x4 re[IMT], im[IMT];
+#pragma unroll
+        for (int mt = 0; mt < IMT; ++mt) re[mt] = im[mt] = f32x4{0, 0, 0, 0};
+        for (int st = 0; st < nks; ++st) {
+            const int k = 4 * st + lg;
+            const int hk = k >= nth_p, I = k - hk * nth_p;
+            cx<float> tv = {0, 0};
+            if (k < 2 * nth_p && rhs < R) tv = t[(int64_t)(I * nph_c + jp + hk * h) * R + rhs];
+#pragma unroll
+            for (int mt = 0; mt < IMT; ++mt) {
+                if (mt < nmt) {
+                    const float w = Wop[(mt * IKS + st) * 64 + lane];
+                    mma_f32(re[mt], w, tv.x);
+                    mma_f32(im[mt], w, tv.y);
+                }
+            }
+        }
+        if (rhs >= R) continue;
+        // read all current values first, then add and store (no serialised
+        // load-store chains)
+        cx<float> cur[IMT][4];
+#pragma unroll
+        for (int mt = 0; mt < IMT; ++mt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * mt + 4 * lg + v;
+                cur[mt][v] = {0, 0};
+                if (mt < nmt && row < 2 * nth_c) {
+                    const int hr = row >= nth_c, i = row - hr * nth_c;
+                    cur[mt][v] = out[(int64_t)(i * nph_c + jp + hr * h) * R + rhs];
+                }
+            }
+#pragma unroll
+        for (int mt = 0; mt < IMT; ++mt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * mt + 4 * lg + v;
+                if (mt < nmt && row < 2 * nth_c) {
+                    const int hr = row >= nth_c, i = row - hr * nth_c;
+                    out[(int64_t)(i * nph_c + jp + hr * h) * R + rhs] = {cur[mt][v].x + re[mt][v],
+                                                                         cur[mt][v].y + im[mt][v]};
+                }
+            }
+    }
+}
+
 }  // namespace sfmm

@@ -53,6 +53,8 @@ def test_bench_configuration_sampled_rows(bench_rows, prec):
         y = ctx.sfmm_matvec(x, np.zeros_like(x))[0]
         ybn = ctx.sfmm_matvec(xb, np.zeros_like(xb), parts=sfmm.PART_NEAR)
         yb = ctx.sfmm_matvec(xb, np.zeros_like(xb))
+        # the batched kernels against the single-RHS ones on the same inputs
+        y1 = [ctx.sfmm_matvec(np.ascontiguousarray(xb[r:r + 1]), np.zeros_like(xb[:1]))[0] for r in (0, 37, 63)]
     pick = np.concatenate([test, ne + test])
     e_near = rel(yn[pick], bench_rows["Zn"] @ x[0])
     e_full = rel(y[pick], bench_rows["Z"] @ x[0])
@@ -62,8 +64,11 @@ def test_bench_configuration_sampled_rows(bench_rows, prec):
           "full", eb_full)
     assert e_near < 1e-5
     assert e_full < 1e-3
+    e_bs = max(rel(yb[r], y) for r, y in zip((0, 37, 63), y1))
+    print(prec, "64-RHS batch vs single", e_bs)
     assert eb_near < (1e-5 if prec == "fp32" else 5e-5)
     assert eb_full < 1e-3
+    assert e_bs < (1e-5 if prec == "fp32" else 5e-5)
 
 
 def test_ilu_preconditioner_multilevel_fp64():
