@@ -32,6 +32,10 @@ import numpy as np  # noqa: E402
 
 METRIC = "MLFMM matvec unknowns×RHS/s + GMRES time-to-1e-4 per angle vs plain GPU path"
 HBM_PEAK_GBS = 8000.0
+# HBM bytes of one k_near launch at this size from rocprofv3 --pmc: FETCH_SIZE
+# (KiB) x 2.0 + WRITE_SIZE (KiB) x 1.0, the factors being what the counters
+# read for a plain 256 MiB device copy (profiles/near_product_sphere61440_pmc_traffic.md)
+NEAR_TRAFFIC_BYTES = int((154590 * 2.0 + 524) * 1024)
 
 
 def parse():
@@ -47,6 +51,8 @@ def parse():
     p.add_argument("--sweep", type=int, default=64, help="angles of the theta sweep (0 = skip)")
     p.add_argument("--train-every", type=int, default=2,
                    help="learned-guess sweep: solve every n-th angle first and train on those")
+    p.add_argument("--copy-calibration", type=int, default=0,
+                   help="MiB of a plain device copy run after the measurements, to scale HBM byte counters")
     return p.parse_args()
 
 
@@ -78,12 +84,15 @@ def cpu_baseline(body, x, seconds):
 def sweep(ctx, ctx_mixed, torch, n_ang, every):
     """Time-to-solution of a theta sweep (theta uniform in [0, 180] degrees at
     phi = 0, theta-polarised) to the 1e-4 true residual:
-      plain          FP32, one right-hand side per solve, zero start;
-      batched        FP32, all angles in one lockstep solve;
-      mixed          bf16-split matrix-core products, all angles at once;
-      mixed_learned  bf16-split: every `every`-th angle solved first, the
-                     network trained on those currents, the rest solved from
-                     its prediction (wall time includes training/prediction).
+      plain            FP32, one right-hand side per solve, zero start;
+      batched          FP32, all angles in one lockstep solve;
+      mixed            bf16-split matrix-core products, all angles at once;
+      learned_in_sweep bf16-split: every `every`-th angle solved first, the
+                       network trained on those currents, the rest solved from
+                       its prediction (training and prediction timed);
+      learned_pretrained bf16-split, network trained beforehand on a coarse
+                       sweep at the mid-points (reported apart): prediction and
+                       one batched solve of all angles from it are timed.
     """
     from workloads import theta_sweep
 
@@ -130,23 +139,52 @@ def sweep(ctx, ctx_mixed, torch, n_ang, every):
         i_te = ctx_mixed.sfmm_solve(b_te, x_te, x0=x0)
         return i_tr, i_te, loss, t_fit
 
+    # a network trained beforehand on a coarse sweep (the mid-points of this
+    # sweep's angles, every other one): prediction + one batched solve of all
+    # angles is timed; the coarse solves and the training are reported apart
+    mid = np.stack([np.deg2rad(np.linspace(0.0, 180.0, n_ang))[:-1:2] + np.deg2rad(90.0 / (n_ang - 1)),
+                    np.zeros((n_ang - 1 + 1) // 2)], axis=1)
+    b_mid = torch.zeros((len(mid), n), dtype=torch.complex128, device="cuda")
+    ctx_mixed.sfmm_planewave_rhs(mid, b_mid)
+    x_mid = torch.zeros_like(b_mid)
+
+    def pretrain():
+        i_mid = ctx_mixed.sfmm_solve(b_mid, x_mid)
+        loss = ctx_mixed.sfmm_guess_fit(mid, x_mid, rank=len(mid))
+        return i_mid, loss
+
+    (i_mid, loss_pre), t_pre = timed(pretrain)
+
+    def amortized():
+        x0 = torch.zeros_like(b)
+        ctx_mixed.sfmm_guess_predict(ang, x0)
+        xs = torch.zeros_like(b)
+        return ctx_mixed.sfmm_solve(b, xs, x0=x0)
+
+    i_am, t_am = timed(amortized)
+
     (i_tr, i_te, loss, t_fit), t_learn = timed(learned)
-    ok = all(i["converged"] for i in i_plain + i_batch + i_mixed + i_tr + i_te)
+    ok = all(i["converged"] for i in i_plain + i_batch + i_mixed + i_tr + i_te + i_mid + i_am)
     ms = lambda t: round(1e3 * t / n_ang, 2)  # noqa: E731
     return {
         "angles": n_ang, "tol": 1e-4,
         "ms_per_angle": {"plain_fp32": ms(t_plain), "batched_fp32": ms(t_batch), "batched_bf16split": ms(t_mixed),
-                         "batched_bf16split_learned": ms(t_learn)},
+                         "batched_bf16split_learned_in_sweep": ms(t_learn),
+                         "batched_bf16split_learned_pretrained": ms(t_am)},
         "speedup_vs_plain": {"batched_fp32": round(t_plain / t_batch, 2),
                              "batched_bf16split": round(t_plain / t_mixed, 2),
-                             "batched_bf16split_learned": round(t_plain / t_learn, 2)},
+                             "batched_bf16split_learned_in_sweep": round(t_plain / t_learn, 2),
+                             "batched_bf16split_learned_pretrained": round(t_plain / t_am, 2)},
         "iterations_mean": {"plain_fp32": its(i_plain), "batched_fp32": its(i_batch),
-                            "batched_bf16split": its(i_mixed), "learned_training_angles": its(i_tr),
-                            "learned_predicted_angles": its(i_te)},
-        "true_residual_max": max(i["true_residual"] for i in i_plain + i_batch + i_mixed + i_tr + i_te),
-        "guess": {"trained_on": len(tr), "fit_and_predict_s": round(t_fit, 3), "loss": loss,
-                  "initial_residual_median": float(np.median([i["initial_residual"] for i in i_te])),
-                  "used": int(sum(i["guess_used"] for i in i_te))},
+                            "batched_bf16split": its(i_mixed), "in_sweep_training_angles": its(i_tr),
+                            "in_sweep_predicted_angles": its(i_te), "pretrained": its(i_am)},
+        "true_residual_max": max(i["true_residual"] for i in i_plain + i_batch + i_mixed + i_tr + i_te + i_am),
+        "guess_in_sweep": {"trained_on": len(tr), "fit_and_predict_s": round(t_fit, 3), "loss": loss,
+                           "initial_residual_median": float(np.median([i["initial_residual"] for i in i_te])),
+                           "used": int(sum(i["guess_used"] for i in i_te))},
+        "guess_pretrained": {"trained_on": len(mid), "coarse_solve_and_fit_s": round(t_pre, 3), "loss": loss_pre,
+                             "initial_residual_median": float(np.median([i["initial_residual"] for i in i_am])),
+                             "used": int(sum(i["guess_used"] for i in i_am))},
         "all_converged": bool(ok),
     }
 
@@ -238,7 +276,8 @@ def main():
     near_ms = st[0]
     achieved = alg_bytes / (near_ms * 1e-3) / 1e9 if near_ms > 0 else 0.0
     roofline = {"bound": "hbm", "kernel": "k_near (near-field box-ELL product)", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": NEAR_TRAFFIC_BYTES,
                 "alg_bytes_per_launch": int(alg_bytes), "avg_ms": round(near_ms, 4)}
 
     result = {"metric": METRIC, "value": value, "unit": "unknowns*RHS/s", "n_gpus": 1, "steps": args.steps,
@@ -266,6 +305,14 @@ def main():
         result["sweep"] = sweep(ctx, ctx_mixed, torch, args.sweep, args.train_every)
         ctx_mixed.close()
         print("sweep", result["sweep"], file=sys.stderr, flush=True)
+
+    if args.copy_calibration > 0:
+        a = torch.ones(args.copy_calibration * (1 << 18), dtype=torch.float32, device="cuda")
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        del a, c
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(body, xh[0], args.cpu_seconds)

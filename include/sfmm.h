@@ -75,6 +75,12 @@ typedef struct {
     double frequency_hz;
 } sfmm_body;
 
+/* Number type of the products.  FP32: complex FP32 storage and arithmetic
+ * (matrix cores in FP32 for batches of 16+ right-hand sides).  BF16_SPLIT:
+ * as FP32, but the batched near-field product runs on the bf16 matrix cores
+ * with every FP32 operand split into hi + lo bf16 parts (hi*hi + hi*lo +
+ * lo*hi, FP32 accumulation; about 1e-5 relative per product).  FP64: complex
+ * FP64 everywhere (reference mode).  GMRES runs in FP64 in every mode. */
 enum { SFMM_PREC_FP32 = 0, SFMM_PREC_BF16_SPLIT = 1, SFMM_PREC_FP64 = 2 };
 
 typedef struct {
@@ -90,6 +96,9 @@ typedef struct {
     int32_t verbose;          /* 1: setup statistics to stderr; 2: also GMRES restarts  */
     int32_t preconditioner;   /* SFMM_PRECOND_*                                          */
     int32_t poly_degree;      /* degree of SFMM_PRECOND_POLY; 0 = 16                      */
+    int32_t graphs;           /* 1 (default): products and preconditioner applications
+                                 are captured once per batch size into HIP graphs and
+                                 replayed; 0: launched kernel by kernel                 */
 } sfmm_options;
 
 /* Preconditioners of sfmm_solve, all built from the near-field matrix Z_near

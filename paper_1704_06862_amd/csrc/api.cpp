@@ -91,6 +91,7 @@ void sfmm_default_options(sfmm_options *o) {
     o->verbose = 0;
     o->preconditioner = SFMM_PRECOND_POLY;
     o->poly_degree = 16;
+    o->graphs = 1;
 }
 
 sfmm_status sfmm_setup(const sfmm_body *bodies, int32_t n_bodies, const sfmm_options *opt, sfmm_ctx **out) {
@@ -138,7 +139,7 @@ sfmm_status sfmm_setup(const sfmm_body *bodies, int32_t n_bodies, const sfmm_opt
             ctx->bodies.push_back(std::move(bh));
         }
         if (o.device >= 0) {
-            for (auto &bh : ctx->bodies) ctx->dev.push_back(make_device_body(*bh, o.precision, o.device, ctx->stream));
+            for (auto &bh : ctx->bodies) ctx->dev.push_back(make_device_body(*bh, o.precision, o.device, ctx->stream, o.graphs != 0));
         }
         *out = ctx.release();
     });
@@ -162,8 +163,8 @@ sfmm_status sfmm_set_stream(sfmm_ctx *ctx, void *stream) {
         ctx->stream = stream;
         for (auto &d : ctx->dev)
             if (d) d->set_stream(stream);
-        for (auto &g : ctx->guess)
-            if (g) g->set_stream(stream);
+        for (size_t b = 0; b < ctx->guess.size() && b < ctx->dev.size(); ++b)
+            if (ctx->guess[b] && ctx->dev[b]) ctx->guess[b]->set_stream(ctx->dev[b]->stream());
     });
 }
 
@@ -195,9 +196,9 @@ static void vector_call(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void *
         fn(d, x, y);
     } else {
         Staged dx(bytes), dy(bytes);
-        copy_h2d(dx.p, x, bytes, ctx->stream);
+        copy_h2d(dx.p, x, bytes, d.stream());
         fn(d, dx.p, dy.p);
-        copy_d2h(y, dy.p, bytes, ctx->stream);
+        copy_d2h(y, dy.p, bytes, d.stream());
     }
 }
 
@@ -228,7 +229,7 @@ sfmm_status sfmm_planewave_rhs(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const
         } else {
             Staged db(bytes);
             d.planewave_rhs(n_rhs, angles, pol, db.p);
-            copy_d2h(b, db.p, bytes, ctx->stream);
+            copy_d2h(b, db.p, bytes, d.stream());
         }
     });
 }
@@ -245,19 +246,19 @@ sfmm_status sfmm_solve(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void *b
         } else {
             Staged db(bytes), dx(bytes);
             std::unique_ptr<Staged> dx0;
-            copy_h2d(db.p, b, bytes, ctx->stream);
+            copy_h2d(db.p, b, bytes, d.stream());
             if (x0) {
                 dx0 = std::make_unique<Staged>(bytes);
-                copy_h2d(dx0->p, x0, bytes, ctx->stream);
+                copy_h2d(dx0->p, x0, bytes, d.stream());
             }
             try {
                 d.solve(n_rhs, db.p, dx.p, dx0 ? dx0->p : nullptr, o.gmres_restart, o.max_iters, o.tol, info,
                         o.verbose);
             } catch (const Error &e) {
-                if (e.code == SFMM_E_NOT_CONVERGED) copy_d2h(x, dx.p, bytes, ctx->stream);
+                if (e.code == SFMM_E_NOT_CONVERGED) copy_d2h(x, dx.p, bytes, d.stream());
                 throw;
             }
-            copy_d2h(x, dx.p, bytes, ctx->stream);
+            copy_d2h(x, dx.p, bytes, d.stream());
         }
     });
 }
@@ -272,7 +273,7 @@ sfmm_status sfmm_rcs(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void *x, 
             d.rcs(n_rhs, x, n_dirs, theta_phi, sigma);
         } else {
             Staged dx(bytes);
-            copy_h2d(dx.p, x, bytes, ctx->stream);
+            copy_h2d(dx.p, x, bytes, d.stream());
             d.rcs(n_rhs, dx.p, n_dirs, theta_phi, sigma);
         }
     });
@@ -389,11 +390,11 @@ sfmm_status sfmm_guess_fit(sfmm_ctx *ctx, int32_t body, int32_t n, const double 
         const void *xd = x;
         if (!on_device) {
             dx = std::make_unique<Staged>(bytes);
-            copy_h2d(dx->p, x, bytes, ctx->stream);
+            copy_h2d(dx->p, x, bytes, d.stream());
             xd = dx->p;
         }
         if (ctx->guess.size() < ctx->bodies.size()) ctx->guess.resize(ctx->bodies.size());
-        auto gs = std::make_unique<Guess>(N, ctx->stream);
+        auto gs = std::make_unique<Guess>(N, d.stream());
         const double loss = gs->fit(n, angles, db.p, xd, g);
         ctx->guess[body] = std::move(gs);
         if (final_loss) *final_loss = loss;
@@ -416,7 +417,7 @@ sfmm_status sfmm_guess_predict(sfmm_ctx *ctx, int32_t body, int32_t n, const dou
         } else {
             Staged dx(bytes);
             ctx->guess[body]->predict(n, angles, db.p, dx.p);
-            copy_d2h(x0, dx.p, bytes, ctx->stream);
+            copy_d2h(x0, dx.p, bytes, d.stream());
         }
     });
 }

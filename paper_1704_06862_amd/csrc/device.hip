@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -96,9 +97,14 @@ int pick_tile(int R, std::initializer_list<int> cands, F fits) {
 template <typename T>
 class DeviceBodyT final : public DeviceBody {
   public:
-    DeviceBodyT(const BodyHost &h, int device, void *stream, bool split = false)
-        : h_(h), stream_((hipStream_t)stream), split_(split) {
+    DeviceBodyT(const BodyHost &h, int device, void *stream, bool split, bool graphs)
+        : h_(h), split_(split), graphs_(graphs) {
         HIPCHK(hipSetDevice(device));
+        // a stream of our own stands in for the legacy default stream, which
+        // cannot be captured; it is a blocking stream, so it stays ordered
+        // with work on the default stream
+        HIPCHK(hipStreamCreate(&own_stream_));
+        set_stream(stream);
         const Mesh &m = h.mesh;
         const Octree &o = h.oct;
         ne_ = m.ne;
@@ -211,6 +217,11 @@ class DeviceBodyT final : public DeviceBody {
     }
 
     ~DeviceBodyT() override {
+        clear_graphs();
+        if (own_stream_) {
+            (void)hipStreamSynchronize(own_stream_);
+            (void)hipStreamDestroy(own_stream_);
+        }
         for (void *p : batch_allocs_) device_free(p);
         for (void *p : krylov_allocs_) device_free(p);
         for (void *p : allocs_) device_free(p);
@@ -220,7 +231,49 @@ class DeviceBodyT final : public DeviceBody {
             if (e) (void)hipEventDestroy(e);
     }
 
-    void set_stream(void *s) override { stream_ = (hipStream_t)s; }
+    void set_stream(void *s) override { stream_ = s ? (hipStream_t)s : own_stream_; }
+    void *stream() const override { return stream_; }
+
+    // ---- HIP graphs: one executable graph per (operation, batch size) ----
+    enum GraphKind { G_PRODUCT = 0, G_PRECOND = 1, G_PREC_PRODUCT = 2 };
+
+    void clear_graphs() {
+        for (auto &kv : gexec_) (void)hipGraphExecDestroy(kv.second);
+        gexec_.clear();
+    }
+
+    // Runs body() through a captured graph (captured on first use), or
+    // directly while stage profiling is on or graphs are disabled.  body()
+    // must only launch work on stream_ that reads and writes the fixed
+    // internal buffers of batch size R.
+    template <typename F>
+    void run_graph(int kind, int R, F &&body) {
+        if (!graphs_ || profiling_) {
+            body();
+            return;
+        }
+        const std::pair<int, int> key(kind, R);
+        auto it = gexec_.find(key);
+        if (it == gexec_.end()) {
+            HIPCHK(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
+            try {
+                body();
+            } catch (...) {
+                hipGraph_t broken = nullptr;
+                (void)hipStreamEndCapture(stream_, &broken);
+                if (broken) (void)hipGraphDestroy(broken);
+                throw;
+            }
+            hipGraph_t g = nullptr;
+            HIPCHK(hipStreamEndCapture(stream_, &g));
+            hipGraphExec_t ex = nullptr;
+            const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            HIPCHK(e);
+            it = gexec_.emplace(key, ex).first;
+        }
+        HIPCHK(hipGraphLaunch(it->second, stream_));
+    }
     void profile(bool enable) override {
         profiling_ = enable;
         if (enable) times_ = StageTimes();
@@ -722,7 +775,8 @@ class DeviceBodyT final : public DeviceBody {
             k_to_internal<T><<<nblocks((int64_t)ne_ * R), WG, 0, stream_>>>((const double2 *)x_dev + (size_t)r0 * N,
                                                                              pos_, ne_, R, xi_);
             LAUNCHCHK();
-            matvec_internal(xi_, yi_, R, parts);
+            if (parts == SFMM_PART_ALL) run_graph(G_PRODUCT, R, [&] { matvec_internal(xi_, yi_, R, parts); });
+            else matvec_internal(xi_, yi_, R, parts);
             k_to_boundary<T><<<nblocks((int64_t)ne_ * R), WG, 0, stream_>>>(yi_, pos_, ne_, R,
                                                                              (double2 *)y_dev + (size_t)r0 * N);
             LAUNCHCHK();
@@ -737,7 +791,7 @@ class DeviceBodyT final : public DeviceBody {
             k_to_internal<T><<<nblocks((int64_t)ne_ * R), WG, 0, stream_>>>((const double2 *)x_dev + (size_t)r0 * N,
                                                                              pos_, ne_, R, xi_);
             LAUNCHCHK();
-            precond_internal(xi_, wi_, R);
+            run_graph(G_PRECOND, R, [&] { precond_internal(xi_, wi_, R); });
             k_to_boundary<T><<<nblocks((int64_t)ne_ * R), WG, 0, stream_>>>(wi_, pos_, ne_, R,
                                                                              (double2 *)y_dev + (size_t)r0 * N);
             LAUNCHCHK();
@@ -751,20 +805,24 @@ class DeviceBodyT final : public DeviceBody {
         const int64_t NR = (int64_t)N * Ra;
         k_gather<T><<<nblocks(NR), WG, 0, stream_>>>(in, N, dact_, N, Ra, xi_);
         LAUNCHCHK();
-        const cx<T> *cur = xi_;
-        if (prec) {
-            precond_internal(xi_, wi_, Ra);
-            cur = wi_;
+        // the fixed-buffer part runs as one graph; the gathers and scatters
+        // (whose vectors change every step) stay outside
+        if (prec && prod) {
+            run_graph(G_PREC_PRODUCT, Ra, [&] {
+                precond_internal(xi_, wi_, Ra);
+                matvec_internal(wi_, yi_, Ra, SFMM_PART_ALL);
+            });
+        } else if (prec) {
+            run_graph(G_PRECOND, Ra, [&] { precond_internal(xi_, wi_, Ra); });
+        } else if (prod) {
+            run_graph(G_PRODUCT, Ra, [&] { matvec_internal(xi_, yi_, Ra, SFMM_PART_ALL); });
         }
+        const cx<T> *z = prec ? wi_ : xi_;
         if (zout) {
-            k_scatter<T><<<nblocks(NR), WG, 0, stream_>>>(cur, N, Ra, dact_, N, zout);
+            k_scatter<T><<<nblocks(NR), WG, 0, stream_>>>(z, N, Ra, dact_, N, zout);
             LAUNCHCHK();
         }
-        if (prod) {
-            matvec_internal(cur, yi_, Ra, SFMM_PART_ALL);
-            cur = yi_;
-        }
-        k_scatter<T><<<nblocks(NR), WG, 0, stream_>>>(cur, N, Ra, dact_, N, out);
+        k_scatter<T><<<nblocks(NR), WG, 0, stream_>>>(prod ? yi_ : z, N, Ra, dact_, N, out);
         LAUNCHCHK();
     }
 
@@ -1065,6 +1123,7 @@ class DeviceBodyT final : public DeviceBody {
     void ensure_batch(int R) {
         if (R <= rcap_) return;
         HIPCHK(hipStreamSynchronize(stream_));
+        clear_graphs();   // they hold the old buffer addresses
         for (void *p : batch_allocs_) device_free(p);
         batch_allocs_.clear();
         const size_t NR = (size_t)2 * ne_ * R;
@@ -1133,6 +1192,9 @@ class DeviceBodyT final : public DeviceBody {
     cx<T> *nA_ = nullptr, *nB_ = nullptr, *nC_ = nullptr;
     // matrix-core tiles of the near matrix (FP32 / bf16-split modes)
     bool split_ = false;
+    bool graphs_ = true;
+    hipStream_t own_stream_ = nullptr;
+    std::map<std::pair<int, int>, hipGraphExec_t> gexec_;
     int ntiles_ = 0;
     int64_t nsteps_ = 0;
     int *tile_box_ = nullptr, *tile_row0_ = nullptr;
@@ -1161,11 +1223,12 @@ class DeviceBodyT final : public DeviceBody {
 
 }  // namespace
 
-std::unique_ptr<DeviceBody> make_device_body(const BodyHost &h, int precision, int device, void *stream) {
+std::unique_ptr<DeviceBody> make_device_body(const BodyHost &h, int precision, int device, void *stream,
+                                             bool graphs) {
     check_device(device);
-    if (precision == SFMM_PREC_FP64) return std::make_unique<DeviceBodyT<double>>(h, device, stream);
-    if (precision == SFMM_PREC_FP32) return std::make_unique<DeviceBodyT<float>>(h, device, stream, false);
-    if (precision == SFMM_PREC_BF16_SPLIT) return std::make_unique<DeviceBodyT<float>>(h, device, stream, true);
+    if (precision == SFMM_PREC_FP64) return std::make_unique<DeviceBodyT<double>>(h, device, stream, false, graphs);
+    if (precision == SFMM_PREC_FP32) return std::make_unique<DeviceBodyT<float>>(h, device, stream, false, graphs);
+    if (precision == SFMM_PREC_BF16_SPLIT) return std::make_unique<DeviceBodyT<float>>(h, device, stream, true, graphs);
     throw Error(SFMM_E_UNSUPPORTED, "unknown precision mode");
 }
 

@@ -35,12 +35,16 @@ class DeviceBody {
     virtual void planewave_rhs(int n_rhs, const double *angles_host, const double *pol_host, void *b_dev) = 0;
     virtual void rcs(int n_rhs, const void *x_dev, int n_dirs, const double *theta_phi_host, double *sigma_host) = 0;
     virtual void set_stream(void *stream) = 0;
+    // the stream all of this body's work is ordered on (the context's stream,
+    // or a stream of the body's own when the context has none)
+    virtual void *stream() const = 0;
     virtual void profile(bool enable) = 0;
     virtual StageTimes times() const = 0;
     virtual int64_t device_bytes() const = 0;
 };
 
-std::unique_ptr<DeviceBody> make_device_body(const BodyHost &h, int precision, int device, void *stream);
+std::unique_ptr<DeviceBody> make_device_body(const BodyHost &h, int precision, int device, void *stream,
+                                             bool graphs);
 
 // HIP helpers used by the C ABI for host <-> device staging.
 void *device_alloc(size_t bytes);

@@ -334,3 +334,28 @@ def test_polynomial_preconditioned_solve_matches_oracle(cfg1):
     print("poly solve", info, "oracle its", oinfo.iterations)
     assert info["converged"] and abs(info["iterations"] - oinfo.iterations) <= 2
     assert rel(Z @ x[0], rhs) < 2e-3
+
+
+def test_graph_replays_match_eager(cfg1):
+    # products and preconditioner applications replayed from captured HIP
+    # graphs must equal the kernel-by-kernel launches, replay after replay,
+    # with other (eager) work and synchronisations in between
+    b = cfg1["body"]
+    opts = dict(CFG1, extra_multipoles=1, tol=1e-4, preconditioner=sfmm.PRECOND_POLY)
+    x = random_complex_vector(cfg1["x"].shape[1], 20, seed=123)
+    with sfmm.Context([b], precision=sfmm.PREC_FP32, graphs=0, **opts) as ce, \
+            sfmm.Context([b], precision=sfmm.PREC_FP32, graphs=1, **opts) as cg:
+        ye = ce.sfmm_matvec(x, np.zeros_like(x))
+        ze = ce.sfmm_precond(x, np.zeros_like(x))
+        for rep in range(4):
+            yg = cg.sfmm_matvec(x, np.zeros_like(x))
+            zg = cg.sfmm_precond(x, np.zeros_like(x))
+            assert rel(yg, ye) < 1e-12 and rel(zg, ze) < 1e-12, rep
+            cg.sfmm_matvec(x[:3].copy(), np.zeros_like(x[:3]), parts=sfmm.PART_NEAR)
+        kh, eh = mom.incidence(0.3, 0.2)
+        rhs = mom.planewave_rhs(cfg1["mesh"], b.frequency, kh, eh)[None, :].copy()
+        xe, xg = np.zeros_like(rhs), np.zeros_like(rhs)
+        ie = ce.sfmm_solve(rhs, xe)[0]
+        ig = cg.sfmm_solve(rhs, xg)[0]
+        assert ie["converged"] and ig["converged"] and ie["iterations"] == ig["iterations"]
+        assert rel(xg, xe) < 1e-10
