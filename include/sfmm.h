@@ -166,7 +166,9 @@ sfmm_status sfmm_precond(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void 
  * incidence angle i, the wave arrives from direction (theta, phi) =
  * angles[i] (radians), i.e. propagates along -r_hat(theta, phi), with
  * E0 = 1 V/m along pol[i] * theta_hat + (1 - pol[i]) * phi_hat  (pol = 1:
- * theta-polarised, 0: phi-polarised).  b is [n_rhs][2E] complex. */
+ * theta-polarised, 0: phi-polarised; pol = NULL: all theta-polarised).
+ * b is [n_rhs][2E] complex.  Computed on the device in FP64 (7-point rule on
+ * both triangles of every edge that faces the exterior region). */
 sfmm_status sfmm_planewave_rhs(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const double *angles,
                                const double *pol, void *b, int32_t on_device);
 
@@ -187,7 +189,8 @@ sfmm_status sfmm_solve(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void *b
 
 /* Bistatic RCS (eqs. 27-29): sigma[r][d] = (sigma_theta, sigma_phi) in m^2
  * for solution r at direction theta_phi[d] (radians).  x follows on_device;
- * theta_phi and sigma are host arrays. */
+ * theta_phi and sigma are host arrays.  The far-field sums run on the device
+ * in FP64 over the exterior-facing edges. */
 sfmm_status sfmm_rcs(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void *x, int32_t n_dirs,
                      const double *theta_phi, double *sigma, int32_t on_device);
 

@@ -174,10 +174,4 @@ struct RegionTables {
 
 RegionTables build_tables(const Mesh &m, const Octree &o, const RegionTree &rt);
 
-// Incident plane-wave right-hand side in boundary layout ([2E], scaled).
-void planewave_rhs(const Mesh &m, double theta, double phi, double pol, cd *b);
-
-// Far-field transforms for RCS: F(r) for one solution in boundary layout.
-void far_field(const Mesh &m, const cd *x, double theta, double phi, cd *Fth, cd *Fph);
-
 }  // namespace sfmm

@@ -126,6 +126,7 @@ class DeviceBodyT final : public DeviceBody {
             max_nrow_ = std::max(max_nrow_, o.bstart[b + 1] - o.bstart[b]);
         }
         if constexpr (std::is_same<T, float>::value) build_mma_tiles(h);
+        upload_edge_quadrature(m);
         if (!h.ilu.fwd_col_ptr.empty()) {
             fcol_ptr_ = upload(h.ilu.fwd_col_ptr);
             fcols_ = upload(h.ilu.fwd_cols);
@@ -1051,27 +1052,68 @@ class DeviceBodyT final : public DeviceBody {
     }
 
     void planewave_rhs(int n_rhs, const double *angles, const double *pol, void *b_dev) override {
-        const int N = 2 * ne_;
-        std::vector<cd> b(N);
-        for (int r = 0; r < n_rhs; ++r) {
-            sfmm::planewave_rhs(h_.mesh, angles[2 * r], angles[2 * r + 1], pol ? pol[r] : 1.0, b.data());
-            copy_h2d((double2 *)b_dev + (size_t)r * N, b.data(), sizeof(cd) * N, stream_);
+        double *da = (double *)device_alloc(sizeof(double) * 3 * n_rhs);
+        try {
+            HIPCHK(hipMemcpyAsync(da, angles, sizeof(double) * 2 * n_rhs, hipMemcpyHostToDevice, stream_));
+            if (pol) HIPCHK(hipMemcpyAsync(da + 2 * n_rhs, pol, sizeof(double) * n_rhs, hipMemcpyHostToDevice, stream_));
+            k_planewave_rhs<<<nblocks((int64_t)ne_ * n_rhs), WG, 0, stream_>>>(
+                ne_, n_rhs, gs0_, gqr_, gqf_, h_.mesh.k0, 1.0 / ETA0, da, pol ? da + 2 * n_rhs : nullptr,
+                (double2 *)b_dev);
+            LAUNCHCHK();
             HIPCHK(hipStreamSynchronize(stream_));
+        } catch (...) {
+            device_free(da);
+            throw;
         }
+        device_free(da);
     }
 
     void rcs(int n_rhs, const void *x_dev, int n_dirs, const double *tp, double *sigma) override {
-        const int N = 2 * ne_;
-        std::vector<cd> x(N);
-        for (int r = 0; r < n_rhs; ++r) {
-            copy_d2h(x.data(), (const double2 *)x_dev + (size_t)r * N, sizeof(cd) * N, stream_);
-            for (int d = 0; d < n_dirs; ++d) {
-                cd Ft, Fp;
-                far_field(h_.mesh, x.data(), tp[2 * d], tp[2 * d + 1], &Ft, &Fp);
-                sigma[((size_t)r * n_dirs + d) * 2] = 4 * PI * std::norm(Ft);
-                sigma[((size_t)r * n_dirs + d) * 2 + 1] = 4 * PI * std::norm(Fp);
+        double *dd = (double *)device_alloc(sizeof(double) * 2 * n_dirs);
+        double *ds = (double *)device_alloc(sizeof(double) * 2 * (size_t)n_dirs * n_rhs);
+        try {
+            HIPCHK(hipMemcpyAsync(dd, tp, sizeof(double) * 2 * n_dirs, hipMemcpyHostToDevice, stream_));
+            dim3 grid(n_dirs, (n_rhs + RCS_RT - 1) / RCS_RT);
+            k_far_field<<<grid, 256, 0, stream_>>>(ne_, n_rhs, gs0_, gqr_, gqf_, h_.mesh.k0, ETA0, dd,
+                                                   (const double2 *)x_dev, ds, n_dirs);
+            LAUNCHCHK();
+            HIPCHK(hipMemcpyAsync(sigma, ds, sizeof(double) * 2 * (size_t)n_dirs * n_rhs, hipMemcpyDeviceToHost,
+                                  stream_));
+            HIPCHK(hipStreamSynchronize(stream_));
+        } catch (...) {
+            device_free(dd);
+            device_free(ds);
+            throw;
+        }
+        device_free(dd);
+        device_free(ds);
+    }
+
+    // quadrature geometry of every edge for the excitation and far-field kernels
+    void upload_edge_quadrature(const Mesh &m) {
+        const TriRule &q = tri_rule();
+        const int ne = m.ne;
+        std::vector<double> qr((size_t)14 * 3 * ne), qf(qr.size());
+        std::vector<int> s0(ne);
+        for (int e = 0; e < ne; ++e) {
+            s0[e] = m.region_sign(e, 0);
+            for (int side = 0; side < 2; ++side) {
+                const int tri = side ? m.tm[e] : m.tp[e], fv = side ? m.fm[e] : m.fp[e];
+                const double coef = (side ? -1.0 : 1.0) * m.len[e] / (2.0 * m.area[tri]);
+                for (int a = 0; a < 7; ++a) {
+                    const V3 &r = m.qp[tri][a];
+                    const double w = q.w[a] * m.area[tri];
+                    const int qi = side * 7 + a;
+                    for (int c = 0; c < 3; ++c) {
+                        qr[((size_t)qi * 3 + c) * ne + e] = r[c];
+                        qf[((size_t)qi * 3 + c) * ne + e] = coef * (r[c] - m.V[fv][c]) * w;
+                    }
+                }
             }
         }
+        gs0_ = upload(s0);
+        gqr_ = upload(qr);
+        gqf_ = upload(qf);
     }
 
   private:
@@ -1200,6 +1242,9 @@ class DeviceBodyT final : public DeviceBody {
     int *tile_box_ = nullptr, *tile_row0_ = nullptr;
     int64_t *tile_step_ = nullptr;
     void *tvals_ = nullptr;
+    // edge quadrature for the plane-wave and far-field kernels
+    int *gs0_ = nullptr;
+    double *gqr_ = nullptr, *gqf_ = nullptr;
     int max_ncol_ = 0, max_nrow_ = 0, max_ilu_nc_ = 0, precond_ = SFMM_PRECOND_ILU0;
     int *fcol_ptr_ = nullptr, *fcols_ = nullptr, *bcol_ptr_ = nullptr, *bcols_ = nullptr;
     int64_t *fptr_ = nullptr, *bptr_ = nullptr;

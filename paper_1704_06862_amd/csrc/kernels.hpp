@@ -749,6 +749,130 @@ __global__ void __launch_bounds__(WG) k_receive(int K, int R, const int *__restr
 }
 
 // ---------------------------------------------------------------------------
+// Plane-wave excitation and far field on the device (FP64).  Every edge e has
+// 14 quadrature points (7 on T+, 7 on T-) with position r and weighted basis
+// value w f(r) stored structure-of-arrays: qr[(q * 3 + c) * ne + e].  s0[e] is
+// the edge's sign with respect to region 0 (0: interior interface).
+
+// b[r][e] = -s0 <f_e, E_inc> / eta0, b[r][ne + e] = -s0 <f_e, H_inc> eta0 / eta0
+// for the wave arriving from angles[r] = (theta, phi), polarisation pol[r].
+__global__ void k_planewave_rhs(int ne, int R, const int *__restrict__ s0, const double *__restrict__ qr,
+                                const double *__restrict__ qf, double k0, double inv_eta0,
+                                const double *__restrict__ angles, const double *__restrict__ pol,
+                                double2 *__restrict__ b) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)ne * R) return;
+    const int e = (int)(id % ne), r = (int)(id / ne);
+    double2 bE = make_double2(0, 0), bH = make_double2(0, 0);
+    const int sg = s0[e];
+    if (sg != 0) {
+        double st, ct, sp, cp;
+        sincos(angles[2 * r], &st, &ct);
+        sincos(angles[2 * r + 1], &sp, &cp);
+        const double kh[3] = {-st * cp, -st * sp, -ct};
+        const double pv = pol ? pol[r] : 1.0;
+        const double ev[3] = {pv * ct * cp - (1.0 - pv) * sp, pv * ct * sp + (1.0 - pv) * cp, -pv * st};
+        const double hv[3] = {kh[1] * ev[2] - kh[2] * ev[1], kh[2] * ev[0] - kh[0] * ev[2],
+                              kh[0] * ev[1] - kh[1] * ev[0]};
+        for (int q = 0; q < 14; ++q) {
+            const double x = qr[(q * 3 + 0) * (int64_t)ne + e], y = qr[(q * 3 + 1) * (int64_t)ne + e],
+                         z = qr[(q * 3 + 2) * (int64_t)ne + e];
+            const double fx = qf[(q * 3 + 0) * (int64_t)ne + e], fy = qf[(q * 3 + 1) * (int64_t)ne + e],
+                         fz = qf[(q * 3 + 2) * (int64_t)ne + e];
+            double sn, cs;
+            sincos(-k0 * (kh[0] * x + kh[1] * y + kh[2] * z), &sn, &cs);
+            const double fe = fx * ev[0] + fy * ev[1] + fz * ev[2];
+            const double fh = fx * hv[0] + fy * hv[1] + fz * hv[2];
+            bE.x += fe * cs;
+            bE.y += fe * sn;
+            bH.x += fh * cs;
+            bH.y += fh * sn;
+        }
+    }
+    const double c = -(double)sg * inv_eta0;
+    b[(int64_t)r * 2 * ne + e] = make_double2(c * bE.x, c * bE.y);
+    b[(int64_t)r * 2 * ne + ne + e] = make_double2(c * bH.x, c * bH.y);
+}
+
+// Bistatic RCS: for direction d (theta, phi) and the FP64 currents x[r]
+// (boundary layout), F = (-j k0 eta0 / 4 pi) [(I - rr) J^ - r x M~^] with
+// J^ = sum_e s0 J_e Int f_e exp(+j k0 r.r'); sigma = 4 pi (|F_theta|^2,
+// |F_phi|^2).  Grid: (directions, tiles of RCS_RT right-hand sides).
+constexpr int RCS_RT = 4;
+__global__ void __launch_bounds__(256) k_far_field(int ne, int R, const int *__restrict__ s0,
+                                                   const double *__restrict__ qr, const double *__restrict__ qf,
+                                                   double k0, double eta0, const double *__restrict__ dirs,
+                                                   const double2 *__restrict__ x, double *__restrict__ sigma,
+                                                   int n_dirs) {
+    __shared__ double red[4][RCS_RT * 8];
+    const int d = blockIdx.x, r0 = blockIdx.y * RCS_RT;
+    double st, ct, sp, cp;
+    sincos(dirs[2 * d], &st, &ct);
+    sincos(dirs[2 * d + 1], &sp, &cp);
+    const double rh[3] = {st * cp, st * sp, ct}, th[3] = {ct * cp, ct * sp, -st}, ph[3] = {-sp, cp, 0.0};
+    double acc[RCS_RT][8];   // Jt, Jp, Mt, Mp (re, im)
+#pragma unroll
+    for (int t = 0; t < RCS_RT; ++t)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[t][u] = 0.0;
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+        const int sg = s0[e];
+        if (sg == 0) continue;
+        double ftr = 0, fti = 0, fpr = 0, fpi = 0;
+        for (int q = 0; q < 14; ++q) {
+            const double px = qr[(q * 3 + 0) * (int64_t)ne + e], py = qr[(q * 3 + 1) * (int64_t)ne + e],
+                         pz = qr[(q * 3 + 2) * (int64_t)ne + e];
+            const double fx = qf[(q * 3 + 0) * (int64_t)ne + e], fy = qf[(q * 3 + 1) * (int64_t)ne + e],
+                         fz = qf[(q * 3 + 2) * (int64_t)ne + e];
+            double sn, cs;
+            sincos(k0 * (rh[0] * px + rh[1] * py + rh[2] * pz), &sn, &cs);
+            const double a = fx * th[0] + fy * th[1] + fz * th[2];
+            const double b = fx * ph[0] + fy * ph[1] + fz * ph[2];
+            ftr += a * cs;
+            fti += a * sn;
+            fpr += b * cs;
+            fpi += b * sn;
+        }
+#pragma unroll
+        for (int t = 0; t < RCS_RT; ++t) {
+            if (r0 + t >= R) continue;
+            const double2 J = x[(int64_t)(r0 + t) * 2 * ne + e], M = x[(int64_t)(r0 + t) * 2 * ne + ne + e];
+            const double jr = sg * J.x, ji = sg * J.y, mr = sg * M.x, mi = sg * M.y;
+            acc[t][0] += jr * ftr - ji * fti;
+            acc[t][1] += jr * fti + ji * ftr;
+            acc[t][2] += jr * fpr - ji * fpi;
+            acc[t][3] += jr * fpi + ji * fpr;
+            acc[t][4] += mr * ftr - mi * fti;
+            acc[t][5] += mr * fti + mi * ftr;
+            acc[t][6] += mr * fpr - mi * fpi;
+            acc[t][7] += mr * fpi + mi * fpr;
+        }
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int t = 0; t < RCS_RT; ++t)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double v = wave_sum(acc[t][u]);
+            if (lane == 0) red[wave][t * 8 + u] = v;
+        }
+    __syncthreads();
+    if (threadIdx.x >= RCS_RT) return;
+    const int t = threadIdx.x;
+    if (r0 + t >= R) return;
+    double v[8];
+    for (int u = 0; u < 8; ++u) v[u] = red[0][t * 8 + u] + red[1][t * 8 + u] + red[2][t * 8 + u] + red[3][t * 8 + u];
+    // F_theta = pre (Jt + Mp), F_phi = pre (Jp - Mt), pre = -j k0 eta0 / 4 pi
+    const double pre = k0 * eta0 / (4.0 * 3.14159265358979323846);
+    const double ar = v[0] + v[6], ai = v[1] + v[7];
+    const double br = v[2] - v[4], bi = v[3] - v[5];
+    // |pre * (a)|^2 = pre^2 |a|^2 (the -j factor has unit modulus)
+    const double s = 4.0 * 3.14159265358979323846 * pre * pre;
+    sigma[((int64_t)(r0 + t) * n_dirs + d) * 2] = s * (ar * ar + ai * ai);
+    sigma[((int64_t)(r0 + t) * n_dirs + d) * 2 + 1] = s * (br * br + bi * bi);
+}
+
+// ---------------------------------------------------------------------------
 // Batched FP64 Krylov kernels.  Vector of slot s and basis index j is at
 // base + j * ldj + act[s] * lds (complex FP64, N entries, internal order).
 

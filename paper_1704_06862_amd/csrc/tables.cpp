@@ -260,77 +260,4 @@ RegionTables build_tables(const Mesh &m, const Octree &o, const RegionTree &rt) 
     return t;
 }
 
-// ---------------------------------------------------------------------------
-// Plane-wave right-hand side (eqs. 20-21, tangential part; eq. 30 with the
-// wave arriving from (theta, phi): k = -r(theta, phi), E = e exp(-jk0 k.r),
-// H = k x E / eta0), scaled like the system: b = [-<f,E>/eta0 ; -<f,H>],
-// weighted by the region-0 sign of each edge.
-void planewave_rhs(const Mesh &m, double theta, double phi, double pol, cd *b) {
-    const TriRule &q = tri_rule();
-    const cd j(0.0, 1.0);
-    double st = std::sin(theta), ct = std::cos(theta), sp = std::sin(phi), cp = std::cos(phi);
-    V3 kh = {-st * cp, -st * sp, -ct};
-    V3 th = {ct * cp, ct * sp, -st}, ph = {-sp, cp, 0.0};
-    V3 e = pol * th + (1.0 - pol) * ph;
-    V3 h = cross(kh, e);
-#pragma omp parallel for schedule(static)
-    for (int ed = 0; ed < m.ne; ++ed) {
-        cd bE = 0, bH = 0;
-        int s0 = m.region_sign(ed, 0);
-        if (s0 != 0) {
-            for (int side = 0; side < 2; ++side) {
-                int tri = side ? m.tm[ed] : m.tp[ed];
-                int fvtx = side ? m.fm[ed] : m.fp[ed];
-                double coef = (side ? -1.0 : 1.0) * m.len[ed] / (2.0 * m.area[tri]);
-                for (int a = 0; a < 7; ++a) {
-                    const V3 &r = m.qp[tri][a];
-                    V3 fv = coef * (r - m.V[fvtx]);
-                    cd phs = std::exp(-j * m.k0 * dot(kh, r)) * (q.w[a] * m.area[tri]);
-                    bE += dot(fv, e) * phs;
-                    bH += dot(fv, h) * phs;
-                }
-            }
-        }
-        b[ed] = -double(s0) * bE / ETA0;
-        b[m.ne + ed] = -double(s0) * bH / ETA0;
-    }
-}
-
-// Far field F(theta, phi) of the currents x (eqs. 27-28 with the transverse
-// projection): F = (-j k0 eta0 / 4 pi) [(I - rr) J^ - r x M~^],
-// J^ = sum_n s0_n J_n Int f_n exp(+j k0 r.r').
-void far_field(const Mesh &m, const cd *x, double theta, double phi, cd *Fth, cd *Fph) {
-    const TriRule &q = tri_rule();
-    const cd j(0.0, 1.0);
-    double st = std::sin(theta), ct = std::cos(theta), sp = std::sin(phi), cp = std::cos(phi);
-    V3 rh = {st * cp, st * sp, ct}, th = {ct * cp, ct * sp, -st}, ph = {-sp, cp, 0.0};
-    cd Jt = 0, Jp = 0, Mt = 0, Mp = 0;
-    for (int ed = 0; ed < m.ne; ++ed) {
-        int s0 = m.region_sign(ed, 0);
-        if (!s0) continue;
-        cd ft = 0, fp = 0;
-        for (int side = 0; side < 2; ++side) {
-            int tri = side ? m.tm[ed] : m.tp[ed];
-            int fvtx = side ? m.fm[ed] : m.fp[ed];
-            double coef = (side ? -1.0 : 1.0) * m.len[ed] / (2.0 * m.area[tri]);
-            for (int a = 0; a < 7; ++a) {
-                const V3 &r = m.qp[tri][a];
-                V3 fv = coef * (r - m.V[fvtx]);
-                cd phs = std::exp(j * m.k0 * dot(rh, r)) * (q.w[a] * m.area[tri]);
-                ft += dot(fv, th) * phs;
-                fp += dot(fv, ph) * phs;
-            }
-        }
-        cd Jn = double(s0) * x[ed], Mn = double(s0) * x[m.ne + ed];
-        Jt += Jn * ft;
-        Jp += Jn * fp;
-        Mt += Mn * ft;
-        Mp += Mn * fp;
-    }
-    // r x (Mt th + Mp ph) = Mt ph - Mp th
-    cd pre = -j * m.k0 * ETA0 / (4.0 * PI);
-    *Fth = pre * (Jt + Mp);
-    *Fph = pre * (Jp - Mt);
-}
-
 }  // namespace sfmm

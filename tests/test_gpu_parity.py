@@ -359,3 +359,34 @@ def test_graph_replays_match_eager(cfg1):
         ig = cg.sfmm_solve(rhs, xg)[0]
         assert ie["converged"] and ig["converged"] and ie["iterations"] == ig["iterations"]
         assert rel(xg, xe) < 1e-10
+
+
+def test_planewave_rhs_kernel_polarisations(cfg1, ctx32):
+    # the excitation kernel is FP64 in every precision mode
+    m, b = cfg1["mesh"], cfg1["body"]
+    angles = np.array([[0.0, 0.0], [0.4, 1.3], [2.2, -0.7], [np.pi, 0.5], [1.0, 2.0]])
+    pol = np.array([1.0, 0.0, 1.0, 0.0, 0.3])
+    rhs = ctx32.sfmm_planewave_rhs(angles, np.zeros((5, 2 * m.n_edges), dtype=complex), pol=pol)
+    for i, (th, ph) in enumerate(angles):
+        kh, et = mom.incidence(th, ph)
+        ep = np.array([-np.sin(ph), np.cos(ph), 0.0])
+        ref = mom.planewave_rhs(m, b.frequency, kh, pol[i] * et + (1 - pol[i]) * ep)
+        assert rel(rhs[i], ref) < 1e-12, i
+
+
+def test_rcs_kernel_matches_oracle_far_field(cfg1, ctx32):
+    # same currents on both sides: the oracle's dense solutions for 5
+    # incidences (a full tile of 4 and a ragged one)
+    m, b, Z = cfg1["mesh"], cfg1["body"], cfg1["Z"]
+    cur = []
+    for th in (0.0, 0.5, 1.1, 2.0, 3.0):
+        kh, eh = mom.incidence(th, 0.3)
+        cur.append(np.linalg.solve(Z, mom.planewave_rhs(m, b.frequency, kh, eh)))
+    cur = np.array(cur)
+    th = np.deg2rad(np.arange(0.0, 181.0, 7.0))
+    for phi in (0.0, 1.0):
+        tp = np.stack([th, 0 * th + phi], 1)
+        s = ctx32.sfmm_rcs(cur, tp)
+        for r in range(5):
+            rE, rH = farfield.rcs(m, b.frequency, cur[r], th, 0 * th + phi)
+            assert rel(s[r, :, 0], rE) < 1e-10 and rel(s[r, :, 1], rH) < 1e-10
