@@ -99,6 +99,11 @@ typedef struct {
     int32_t graphs;           /* 1 (default): products and preconditioner applications
                                  are captured once per batch size into HIP graphs and
                                  replayed; 0: launched kernel by kernel                 */
+    int32_t autotune;         /* 1: on the first batch of each size, time the vector and
+                                 the matrix-core / grouped variant of every stage that
+                                 has both and keep the faster; 0 (default): fixed
+                                 thresholds (matrix cores from 16 RHS, grouped
+                                 translation from 33 RHS)                               */
 } sfmm_options;
 
 /* Preconditioners of sfmm_solve, all built from the near-field matrix Z_near

@@ -92,6 +92,7 @@ void sfmm_default_options(sfmm_options *o) {
     o->preconditioner = SFMM_PRECOND_POLY;
     o->poly_degree = 16;
     o->graphs = 1;
+    o->autotune = 0;
 }
 
 sfmm_status sfmm_setup(const sfmm_body *bodies, int32_t n_bodies, const sfmm_options *opt, sfmm_ctx **out) {
@@ -139,7 +140,8 @@ sfmm_status sfmm_setup(const sfmm_body *bodies, int32_t n_bodies, const sfmm_opt
             ctx->bodies.push_back(std::move(bh));
         }
         if (o.device >= 0) {
-            for (auto &bh : ctx->bodies) ctx->dev.push_back(make_device_body(*bh, o.precision, o.device, ctx->stream, o.graphs != 0));
+            for (auto &bh : ctx->bodies) ctx->dev.push_back(make_device_body(*bh, o.precision, o.device, ctx->stream, o.graphs != 0,
+                                                                         o.autotune != 0, o.verbose));
         }
         *out = ctx.release();
     });

@@ -97,8 +97,8 @@ int pick_tile(int R, std::initializer_list<int> cands, F fits) {
 template <typename T>
 class DeviceBodyT final : public DeviceBody {
   public:
-    DeviceBodyT(const BodyHost &h, int device, void *stream, bool split, bool graphs)
-        : h_(h), split_(split), graphs_(graphs) {
+    DeviceBodyT(const BodyHost &h, int device, void *stream, bool split, bool graphs, bool autotune, int verbose)
+        : h_(h), split_(split), graphs_(graphs), autotune_(autotune), verbose_(verbose) {
         HIPCHK(hipSetDevice(device));
         // a stream of our own stands in for the legacy default stream, which
         // cannot be captured; it is a blocking stream, so it stays ordered
@@ -282,11 +282,79 @@ class DeviceBodyT final : public DeviceBody {
     StageTimes times() const override { return times_; }
     int64_t device_bytes() const override { return bytes_; }
 
+    // ---- kernel choice per batch size ----
+    // Each stage with two implementations (vector kernel / matrix-core or
+    // grouped kernel) is chosen per batch size R: by fixed thresholds, or,
+    // with autotuning on, by timing both on the first batch of that size
+    // (one stage at a time, the others at their current best).
+    struct Plan {
+        bool near_mma = false, agg_mma = false, interp_mma = false, trans_grp = false;
+    };
+    static Plan default_plan(int R) {
+        Plan p;
+        p.near_mma = p.agg_mma = p.interp_mma = R >= MMA_MIN_R && std::is_same<T, float>::value;
+        p.trans_grp = R >= TRANS_GRP_MIN_R;
+        return p;
+    }
+    void use_plan(int R) {
+        if (!autotune_) {
+            plan_ = default_plan(R);
+            return;
+        }
+        // one tuned plan per size class (exact below 16, multiples of 16 above)
+        const int cls = R < 16 ? R : (R + 15) / 16 * 16;
+        auto it = plans_.find(cls);
+        if (it == plans_.end()) it = plans_.emplace(cls, tune(R)).first;
+        plan_ = it->second;
+    }
+    float time_product(int R) {
+        float best = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            HIPCHK(hipEventRecord(ev0_, stream_));
+            matvec_internal(xi_, yi_, R, SFMM_PART_ALL);
+            HIPCHK(hipEventRecord(ev1_, stream_));
+            HIPCHK(hipEventSynchronize(ev1_));
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, ev0_, ev1_));
+            best = std::min(best, ms);
+        }
+        return best;
+    }
+    Plan tune(int R) {
+        ensure_batch(R);
+        const bool prof = profiling_;
+        profiling_ = false;
+        k_zero<T><<<nblocks((int64_t)2 * ne_ * R), WG, 0, stream_>>>(xi_, (int64_t)2 * ne_ * R);
+        LAUNCHCHK();
+        Plan best = default_plan(R);
+        plan_ = best;
+        float tbest = time_product(R);
+        bool Plan::*fields[4] = {&Plan::near_mma, &Plan::agg_mma, &Plan::interp_mma, &Plan::trans_grp};
+        for (bool Plan::*f : fields) {
+            if (f != &Plan::trans_grp && !std::is_same<T, float>::value) continue;
+            if (f != &Plan::trans_grp && R < MMA_MIN_R) continue;
+            plan_ = best;
+            plan_.*f = !(best.*f);
+            const float t = time_product(R);
+            if (t < tbest) {
+                tbest = t;
+                best = plan_;
+            }
+        }
+        profiling_ = prof;
+        if (verbose_)
+            std::fprintf(stderr, "sfmm autotune R=%d: near %s, aggregate/receive %s, interpolation %s, translation %s "
+                                 "(%.3f ms)\n",
+                         R, best.near_mma ? "mfma" : "vector", best.agg_mma ? "mfma" : "vector",
+                         best.interp_mma ? "mfma" : "vector", best.trans_grp ? "grouped" : "flat", tbest);
+        return best;
+    }
+
     // ---- batched products on internal T vectors [2E][R] ----
     template <bool POLY>
     void launch_near(int R, const cx<T> *x, cx<T> *y, cx<T> *acc, cx<T> inv_theta, int write_y) {
         if constexpr (std::is_same<T, float>::value) {
-            if (R >= MMA_MIN_R && ntiles_ > 0) {
+            if (plan_.near_mma && R >= MMA_MIN_R && ntiles_ > 0) {
                 launch_near_mma<POLY>(R, x, y, acc, inv_theta, write_y);
                 return;
             }
@@ -434,7 +502,7 @@ class DeviceBodyT final : public DeviceBody {
             const int f = f_;
             for (Reg &G : regs_) {
                 if constexpr (std::is_same<T, float>::value) {
-                    if (R >= MMA_MIN_R) {
+                    if (plan_.agg_mma && R >= MMA_MIN_R) {
                         aggregate_mma(G, R, x);
                         continue;
                     }
@@ -458,7 +526,7 @@ class DeviceBodyT final : public DeviceBody {
             mark(5);
             for (Reg &G : regs_) {
                 if constexpr (std::is_same<T, float>::value) {
-                    if (R >= MMA_MIN_R) {
+                    if (plan_.agg_mma && R >= MMA_MIN_R) {
                         receive_mma(G, R, y);
                         continue;
                     }
@@ -576,7 +644,7 @@ class DeviceBodyT final : public DeviceBody {
 
     // matrix-core interpolation: sizes within 4 tiles of 16 (theta pairs and phi)
     bool interp_mma_ok(const Reg &G, int l, int R) const {
-        return R >= MMA_MIN_R && G.Dup[l] && 2 * G.nth[l - 1] <= 64 && 2 * G.nth[l] <= 64 && G.nph[l - 1] <= 64 &&
+        return plan_.interp_mma && R >= MMA_MIN_R && G.Dup[l] && 2 * G.nth[l - 1] <= 64 && 2 * G.nth[l] <= 64 && G.nph[l - 1] <= 64 &&
                G.nph[l] <= 64;
     }
 
@@ -615,7 +683,7 @@ class DeviceBodyT final : public DeviceBody {
     }
 
     void translate(Reg &G, int l, int R) {
-        if (R < TRANS_GRP_MIN_R) {
+        if (!plan_.trans_grp) {
             k_translate<T><<<nblocks((int64_t)G.nbox[l] * G.K[l] * R), WG, 0, stream_>>>(
                 G.nbox[l], G.K[l], R, G.il_ptr[l], G.il_src[l], G.il_off[l], G.trans[l], G.S[l], G.G[l]);
             LAUNCHCHK();
@@ -773,6 +841,7 @@ class DeviceBodyT final : public DeviceBody {
         for (int r0 = 0; r0 < n_rhs; r0 += BATCH) {
             const int R = std::min(BATCH, n_rhs - r0);
             ensure_batch(R);
+            use_plan(R);
             k_to_internal<T><<<nblocks((int64_t)ne_ * R), WG, 0, stream_>>>((const double2 *)x_dev + (size_t)r0 * N,
                                                                              pos_, ne_, R, xi_);
             LAUNCHCHK();
@@ -789,6 +858,7 @@ class DeviceBodyT final : public DeviceBody {
         for (int r0 = 0; r0 < n_rhs; r0 += BATCH) {
             const int R = std::min(BATCH, n_rhs - r0);
             ensure_batch(R);
+            use_plan(R);
             k_to_internal<T><<<nblocks((int64_t)ne_ * R), WG, 0, stream_>>>((const double2 *)x_dev + (size_t)r0 * N,
                                                                              pos_, ne_, R, xi_);
             LAUNCHCHK();
@@ -804,6 +874,7 @@ class DeviceBodyT final : public DeviceBody {
     void op_apply(const double2 *in, double2 *out, double2 *zout, int Ra, bool prec, bool prod) {
         const int N = 2 * ne_;
         const int64_t NR = (int64_t)N * Ra;
+        use_plan(Ra);
         k_gather<T><<<nblocks(NR), WG, 0, stream_>>>(in, N, dact_, N, Ra, xi_);
         LAUNCHCHK();
         // the fixed-buffer part runs as one graph; the gathers and scatters
@@ -1235,6 +1306,10 @@ class DeviceBodyT final : public DeviceBody {
     // matrix-core tiles of the near matrix (FP32 / bf16-split modes)
     bool split_ = false;
     bool graphs_ = true;
+    bool autotune_ = false;
+    int verbose_ = 0;
+    Plan plan_{};
+    std::map<int, Plan> plans_;
     hipStream_t own_stream_ = nullptr;
     std::map<std::pair<int, int>, hipGraphExec_t> gexec_;
     int ntiles_ = 0;
@@ -1269,11 +1344,14 @@ class DeviceBodyT final : public DeviceBody {
 }  // namespace
 
 std::unique_ptr<DeviceBody> make_device_body(const BodyHost &h, int precision, int device, void *stream,
-                                             bool graphs) {
+                                             bool graphs, bool autotune, int verbose) {
     check_device(device);
-    if (precision == SFMM_PREC_FP64) return std::make_unique<DeviceBodyT<double>>(h, device, stream, false, graphs);
-    if (precision == SFMM_PREC_FP32) return std::make_unique<DeviceBodyT<float>>(h, device, stream, false, graphs);
-    if (precision == SFMM_PREC_BF16_SPLIT) return std::make_unique<DeviceBodyT<float>>(h, device, stream, true, graphs);
+    if (precision == SFMM_PREC_FP64)
+        return std::make_unique<DeviceBodyT<double>>(h, device, stream, false, graphs, autotune, verbose);
+    if (precision == SFMM_PREC_FP32)
+        return std::make_unique<DeviceBodyT<float>>(h, device, stream, false, graphs, autotune, verbose);
+    if (precision == SFMM_PREC_BF16_SPLIT)
+        return std::make_unique<DeviceBodyT<float>>(h, device, stream, true, graphs, autotune, verbose);
     throw Error(SFMM_E_UNSUPPORTED, "unknown precision mode");
 }
 

@@ -44,7 +44,7 @@ class DeviceBody {
 };
 
 std::unique_ptr<DeviceBody> make_device_body(const BodyHost &h, int precision, int device, void *stream,
-                                             bool graphs);
+                                             bool graphs, bool autotune, int verbose);
 
 // HIP helpers used by the C ABI for host <-> device staging.
 void *device_alloc(size_t bytes);

@@ -390,3 +390,16 @@ def test_rcs_kernel_matches_oracle_far_field(cfg1, ctx32):
         for r in range(5):
             rE, rH = farfield.rcs(m, b.frequency, cur[r], th, 0 * th + phi)
             assert rel(s[r, :, 0], rE) < 1e-10 and rel(s[r, :, 1], rH) < 1e-10
+
+
+def test_autotuned_batched_product(cfg1):
+    # whatever the autotuner picks per batch size, the products stay within
+    # the MLFMM tolerance of the dense matrix
+    b = cfg1["body"]
+    opts = dict(CFG1, extra_multipoles=1, tol=1e-4, autotune=1)
+    with sfmm.Context([b], precision=sfmm.PREC_FP32, **opts) as ctx:
+        for R in (3, 24, 48):
+            x = random_complex_vector(cfg1["x"].shape[1], R, seed=200 + R)
+            y = ctx.sfmm_matvec(x, np.zeros_like(x))
+            ref = x @ cfg1["Z"].T
+            assert max(rel(y[r], ref[r]) for r in range(R)) < 3e-3, R
