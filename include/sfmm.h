@@ -111,11 +111,15 @@ typedef struct {
  *   ILU0          ILU(0) in colour order (the paper's preconditioner);
  *   NONE          identity;
  *   BLOCK_JACOBI  inverses of the same-box diagonal blocks;
- *   POLY          p(Z_near) with p the degree-d residual polynomial of GMRES on
- *                 Z_near (roots: harmonic Ritz values from d FP64 Arnoldi
- *                 steps from v0[i] = exp(2 pi j frac(i (sqrt5-1)/2)), Leja
- *                 order, product form); d near-field products per
- *                 application, no reductions.  Default. */
+ *   POLY          p(D^-1 Z_near) D^-1 with D the edges' 2x2 self blocks
+ *                 [[A_mm, -B_mm], [B_mm, C_mm]] and p the degree-d residual
+ *                 polynomial of GMRES on D^-1 Z_near (roots: harmonic Ritz
+ *                 values from d FP64 Arnoldi steps from v0[i] =
+ *                 exp(2 pi j frac(i (sqrt5-1)/2)), Leja order, product form);
+ *                 d near-field products per application (D^-1 fused into
+ *                 their epilogue), no reductions.  Default; several
+ *                 interfaces with high-contrast or lossy media may need a
+ *                 higher degree (poly_degree). */
 enum { SFMM_PRECOND_ILU0 = 0, SFMM_PRECOND_NONE = 1, SFMM_PRECOND_BLOCK_JACOBI = 2, SFMM_PRECOND_POLY = 3 };
 
 typedef struct {

@@ -174,3 +174,40 @@ def poly_apply(matvec, roots, v):
         y = y + q / t
         q = q - matvec(q) / t
     return y
+
+
+# ---------------------------------------------------------------------------
+# Edge-block scaling of the polynomial preconditioner.  Every RWG edge m owns
+# the 2x2 self block D_m = [[Z_EJ(m,m), Z_EM(m,m)], [Z_HJ(m,m), Z_HM(m,m)]] of
+# the near matrix (boundary layout: J/E rows 0..E-1, M/H rows E..2E-1).  The
+# polynomial is built for D^-1 Z_near, which puts the J and M unknowns of
+# every interface on a common scale, and applied as p(D^-1 Z_near) D^-1.
+
+def edge_blocks_inverse(Zn):
+    """[E, 2, 2] inverses of the edge self blocks of Zn (boundary layout)."""
+    ne = Zn.shape[0] // 2
+    i = np.arange(ne)
+    D = np.empty((ne, 2, 2), dtype=complex)
+    D[:, 0, 0] = Zn[i, i]
+    D[:, 0, 1] = Zn[i, ne + i]
+    D[:, 1, 0] = Zn[ne + i, i]
+    D[:, 1, 1] = Zn[ne + i, ne + i]
+    return np.linalg.inv(D)
+
+
+def edge_blocks_apply(Dinv, v):
+    ne = Dinv.shape[0]
+    a, c = v[:ne], v[ne:]
+    return np.concatenate([Dinv[:, 0, 0] * a + Dinv[:, 0, 1] * c, Dinv[:, 1, 0] * a + Dinv[:, 1, 1] * c])
+
+
+def near_poly_preconditioner(Zn, degree):
+    """v -> p(D^-1 Zn) D^-1 v with p the degree-d GMRES residual polynomial
+    of D^-1 Zn (roots: harmonic Ritz values from golden_start, Leja order)."""
+    Dinv = edge_blocks_inverse(Zn)
+
+    def op(u):
+        return edge_blocks_apply(Dinv, Zn @ u)
+
+    th = leja_order(harmonic_ritz(op, golden_start(Zn.shape[0]), degree))
+    return lambda v: poly_apply(op, th, edge_blocks_apply(Dinv, v))

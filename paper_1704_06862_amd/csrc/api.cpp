@@ -124,7 +124,10 @@ sfmm_status sfmm_setup(const sfmm_body *bodies, int32_t n_bodies, const sfmm_opt
             auto t2 = std::chrono::steady_clock::now();
             if (o.preconditioner == SFMM_PRECOND_ILU0) bh->ilu = factor_ilu(bh->mesh, bh->oct, bh->near);
             else if (o.preconditioner == SFMM_PRECOND_BLOCK_JACOBI) bh->ilu = factor_block_jacobi(bh->mesh, bh->oct, bh->near);
-            else if (o.preconditioner == SFMM_PRECOND_POLY) bh->poly = poly_roots(bh->mesh, bh->oct, bh->near, o.poly_degree);
+            else if (o.preconditioner == SFMM_PRECOND_POLY) {
+                bh->poly_dinv = edge_block_inverse(bh->oct, bh->near);
+                bh->poly = poly_roots(bh->mesh, bh->oct, bh->near, o.poly_degree, bh->poly_dinv);
+            }
             bh->precond = o.preconditioner;
             auto t3 = std::chrono::steady_clock::now();
             for (const RegionTree &rt : bh->oct.regions) bh->tables.push_back(build_tables(bh->mesh, bh->oct, rt));

@@ -149,7 +149,12 @@ IluFactors factor_block_jacobi(const Mesh &m, const Octree &o, const NearMatrix 
 
 // Roots (Leja-ordered harmonic Ritz values) of the near-field GMRES polynomial
 // preconditioner of the given degree.
-std::vector<cd> poly_roots(const Mesh &m, const Octree &o, const NearMatrix &Z, int degree);
+// Inverses of the edges' 2x2 near self blocks, [position][4] row-major.
+std::vector<cd> edge_block_inverse(const Octree &o, const NearMatrix &Z);
+// Roots (Leja order) of the GMRES residual polynomial of D^-1 Z_near
+// (D^-1 = dinv; empty dinv: of Z_near itself).
+std::vector<cd> poly_roots(const Mesh &m, const Octree &o, const NearMatrix &Z, int degree,
+                           const std::vector<cd> &dinv);
 
 // ---------------------------------------------------------------------------
 // MLFMM sampling and tables for one region.

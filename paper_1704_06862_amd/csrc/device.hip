@@ -121,6 +121,7 @@ class DeviceBodyT final : public DeviceBody {
         nC_ = upload_cx(h.near.C);
         precond_ = h.precond;
         for (const cd &t : h.poly) inv_theta_.push_back(to_cx<T>(1.0 / t));
+        if (!h.poly_dinv.empty()) dinv_ = upload_cx(h.poly_dinv);
         for (int b = 0; b < nb_; ++b) {
             max_ncol_ = std::max(max_ncol_, h.near.col_ptr[b + 1] - h.near.col_ptr[b]);
             max_nrow_ = std::max(max_nrow_, o.bstart[b + 1] - o.bstart[b]);
@@ -367,7 +368,8 @@ class DeviceBodyT final : public DeviceBody {
         const size_t shm = lds ? (size_t)max_ncol_ * 2 * t * sizeof(cx<T>) : 0;
 #define SFMM_NEAR(RT_, L_)                                                                                      \
     k_near<T, RT_, L_, POLY><<<grid, RWG, shm, stream_>>>(R, bstart_, near_col_ptr_, near_cols_, near_val_ptr_, \
-                                                          nA_, nB_, nC_, x, y, acc, inv_theta, write_y)
+                                                          nA_, nB_, nC_, x, y, acc, inv_theta, write_y,           \
+                                                          POLY ? dinv_ : nullptr)
         if (!lds) SFMM_NEAR(1, false);
         else if (t == 8) SFMM_NEAR(8, true);
         else if (t == 4) SFMM_NEAR(4, true);
@@ -384,7 +386,7 @@ class DeviceBodyT final : public DeviceBody {
 #define SFMM_NMMA(NT_, S_)                                                                                          \
     k_near_mma<NT_, S_, POLY><<<ntiles_, 64 * MMA_WAVES, 0, stream_>>>(R, tile_box_, tile_row0_, tile_step_, bstart_, \
                                                                      near_col_ptr_, near_cols_, tvals_, nsteps_, x, y, \
-                                                                     acc, inv_theta, write_y)
+                                                                     acc, inv_theta, write_y, POLY ? dinv_ : nullptr)
         if (split_) {
             if (nt == 1) SFMM_NMMA(1, true);
             else if (nt == 2) SFMM_NMMA(2, true);
@@ -808,10 +810,17 @@ class DeviceBodyT final : public DeviceBody {
         } else if (precond_ == SFMM_PRECOND_POLY) {
             k_zero<T><<<nblocks(NR), WG, 0, stream_>>>(w, NR);
             LAUNCHCHK();
+            // p(D^-1 Z_near) D^-1 v in product form; every step's D^-1 is
+            // applied in the near kernel's epilogue
             const cx<T> *cur = v;
+            if (dinv_) {
+                k_edge_block<T><<<nblocks((int64_t)ne_ * R), WG, 0, stream_>>>(ne_, R, dinv_, v, zi_);
+                LAUNCHCHK();
+                cur = zi_;
+            }
             const int d = (int)inv_theta_.size();
             for (int k = 0; k < d; ++k) {
-                cx<T> *next = (k % 2 == 0) ? zi_ : pt_;
+                cx<T> *next = (cur == zi_) ? pt_ : zi_;
                 launch_near<true>(R, cur, next, w, inv_theta_[k], k < d - 1);
                 cur = next;
             }
@@ -1325,6 +1334,7 @@ class DeviceBodyT final : public DeviceBody {
     int64_t *fptr_ = nullptr, *bptr_ = nullptr;
     cx<T> *fval_ = nullptr, *bval_ = nullptr;
     std::vector<cx<T>> inv_theta_;
+    cx<T> *dinv_ = nullptr;   // edge-block scaling of the polynomial preconditioner
     std::vector<Reg> regs_;
     int rcap_ = 0;
     cx<T> *xi_ = nullptr, *yi_ = nullptr, *zi_ = nullptr, *wi_ = nullptr, *pt_ = nullptr;

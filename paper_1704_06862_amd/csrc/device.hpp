@@ -16,6 +16,7 @@ struct BodyHost {
     std::vector<RegionTables> tables;   // parallel to oct.regions
     int precond = SFMM_PRECOND_ILU0;
     std::vector<cd> poly;               // roots of the polynomial preconditioner
+    std::vector<cd> poly_dinv;          // its edge-block scaling D^-1, [position][4]
 };
 
 struct StageTimes {

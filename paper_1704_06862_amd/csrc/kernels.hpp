@@ -61,6 +61,17 @@ __device__ __forceinline__ T group_sum(T v) {
     return v;
 }
 
+// (e, h) <- D (e, h) for one edge's 2x2 block d[0..3] (row-major)
+template <typename T>
+__device__ __forceinline__ void edge_block(const cx<T> *__restrict__ d, cx<T> &e, cx<T> &h) {
+    const cx<T> d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3];
+    cx<T> e2 = cmul(d0, e), h2 = cmul(d2, e);
+    cfma(e2, d1, h);
+    cfma(h2, d3, h);
+    e = e2;
+    h = h2;
+}
+
 constexpr int WG = 256;
 constexpr int WAVES = WG / 64;
 constexpr int RW = 16;              // rows (wavefronts) per near/ILU workgroup
@@ -117,6 +128,19 @@ __global__ void k_scatter(const cx<T> *__restrict__ in, int N, int R, const int 
     base[(int64_t)act[s] * lds + i] = make_double2((double)v.x, (double)v.y);
 }
 
+// y = D x per edge (2x2 blocks dinv[4p..4p+3]) for R right-hand sides
+template <typename T>
+__global__ void k_edge_block(int ne, int R, const cx<T> *__restrict__ dinv, const cx<T> *__restrict__ x,
+                             cx<T> *__restrict__ y) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)ne * R) return;
+    const int64_t p = id / R, r = id % R;
+    cx<T> e = x[2 * p * R + r], h = x[(2 * p + 1) * R + r];
+    edge_block(dinv + 4 * p, e, h);
+    y[2 * p * R + r] = e;
+    y[(2 * p + 1) * R + r] = h;
+}
+
 template <typename T>
 __global__ void k_zero(cx<T> *__restrict__ a, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -137,7 +161,7 @@ __global__ void __launch_bounds__(RWG) k_near(int R, const int *__restrict__ bst
                                               const cx<T> *__restrict__ A, const cx<T> *__restrict__ B,
                                               const cx<T> *__restrict__ C, const cx<T> *__restrict__ x,
                                               cx<T> *__restrict__ y, cx<T> *__restrict__ acc, cx<T> inv_theta,
-                                              int write_y) {
+                                              int write_y, const cx<T> *__restrict__ dinv) {
     extern __shared__ unsigned char lds_raw[];
     cx<T> *xs = reinterpret_cast<cx<T> *>(lds_raw);     // [ncol][2][RT]
     constexpr int NCG = 64 / RT;
@@ -210,6 +234,7 @@ __global__ void __launch_bounds__(RWG) k_near(int R, const int *__restrict__ bst
             acc[iE] = ae;
             acc[iH] = ah;
             if (write_y) {
+                if (dinv) edge_block(dinv + 4 * (int64_t)(r0 + row), aE, aH);
                 cfms(xe, aE, inv_theta);
                 cfms(xh, aH, inv_theta);
                 y[iE] = xe;

@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(64 * MMA_WAVES)
                const int64_t *__restrict__ tile_step, const int *__restrict__ bstart, const int *__restrict__ col_ptr,
                const int *__restrict__ cols, const void *__restrict__ vals, int64_t nsteps,
                const cx<float> *__restrict__ x, cx<float> *__restrict__ y, cx<float> *__restrict__ acc,
-               cx<float> inv_theta, int write_y) {
+               cx<float> inv_theta, int write_y, const cx<float> *__restrict__ dinv) {
     __shared__ f32x4 red[MMA_WAVES - 1][NT * 4][64];
     const int t = blockIdx.x;
     const int b = tile_box[t], row0 = tile_row0[t];
@@ -199,8 +199,9 @@ __global__ void __launch_bounds__(64 * MMA_WAVES)
             if (row >= nrow) continue;
             const int64_t iE = (int64_t)(2 * (r0 + row)) * R + rhs;
             const int64_t iH = iE + R;
-            const cx<float> qE = {aEr[n][v], aEi[n][v]}, qH = {aHr[n][v], aHi[n][v]};
+            cx<float> qE = {aEr[n][v], aEi[n][v]}, qH = {aHr[n][v], aHi[n][v]};
             if (POLY) {
+                if (dinv) edge_block(dinv + 4 * (int64_t)(r0 + row), qE, qH);
                 cx<float> xe = x[iE], xh = x[iH];
                 cx<float> ae = acc[iE], ah = acc[iH];
                 cfma(ae, xe, inv_theta);

@@ -16,6 +16,11 @@
 //   * Leja ordering, applied in product form
 //       y = 0, q = v;  for k: y += q / theta_k;  q -= Z_near q / theta_k
 //     which gives y = p(Z_near) v with 1 - z p(z) = prod_k (1 - z / theta_k).
+// The operator is scaled by the inverses of the edges' 2x2 self blocks
+// D_m = [[A_mm, -B_mm], [B_mm, C_mm]]: the polynomial is built for
+// D^-1 Z_near and applied as p(D^-1 Z_near) D^-1, which puts the J and M
+// unknowns of every interface on one scale (with several interfaces and
+// high-contrast or lossy media the unscaled polynomial can stall GMRES).
 #include <algorithm>
 #include <cmath>
 
@@ -43,6 +48,17 @@ void near_apply(const Octree &o, const NearMatrix &Z, const std::vector<cd> &x, 
             y[2 * (o.bstart[b] + r)] = e;
             y[2 * (o.bstart[b] + r) + 1] = h;
         }
+    }
+}
+
+// y <- D^-1 y, per internal position p (dinv[4p..4p+3] row-major 2x2)
+void block_apply(const std::vector<cd> &dinv, std::vector<cd> &y) {
+    const int64_t ne = (int64_t)dinv.size() / 4;
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < ne; ++p) {
+        const cd e = y[2 * p], h = y[2 * p + 1];
+        y[2 * p] = dinv[4 * p] * e + dinv[4 * p + 1] * h;
+        y[2 * p + 1] = dinv[4 * p + 2] * e + dinv[4 * p + 3] * h;
     }
 }
 
@@ -125,7 +141,33 @@ std::vector<cd> hessenberg_eigenvalues(std::vector<cd> H, int n) {
 
 }  // namespace
 
-std::vector<cd> poly_roots(const Mesh &m, const Octree &o, const NearMatrix &Z, int degree) {
+std::vector<cd> edge_block_inverse(const Octree &o, const NearMatrix &Z) {
+    std::vector<cd> dinv((size_t)4 * o.bstart[o.nb]);
+    for (int b = 0; b < o.nb; ++b) {
+        const int nrow = o.bstart[b + 1] - o.bstart[b];
+        const int ncol = Z.col_ptr[b + 1] - Z.col_ptr[b];
+        for (int r = 0; r < nrow; ++r) {
+            const int p = o.bstart[b] + r;
+            int c = -1;
+            for (int q = 0; q < ncol; ++q)
+                if (Z.cols[Z.col_ptr[b] + q] == p) c = q;
+            if (c < 0) throw Error(SFMM_E_BREAKDOWN, "edge missing from its own near-field row");
+            const int64_t idx = Z.val_ptr[b] + (int64_t)r * ncol + c;
+            const cd A = Z.A[idx], B = Z.B[idx], C = Z.C[idx];
+            // [[A, -B], [B, C]]^-1 = [[C, B], [-B, A]] / (A C + B^2)
+            const cd det = A * C + B * B;
+            if (!(std::abs(det) > 0)) throw Error(SFMM_E_BREAKDOWN, "singular edge self block");
+            dinv[4 * (size_t)p] = C / det;
+            dinv[4 * (size_t)p + 1] = B / det;
+            dinv[4 * (size_t)p + 2] = -B / det;
+            dinv[4 * (size_t)p + 3] = A / det;
+        }
+    }
+    return dinv;
+}
+
+std::vector<cd> poly_roots(const Mesh &m, const Octree &o, const NearMatrix &Z, int degree,
+                           const std::vector<cd> &dinv) {
     const int ne = m.ne;
     const int N = 2 * ne;
     const int d = degree;
@@ -145,6 +187,7 @@ std::vector<cd> poly_roots(const Mesh &m, const Octree &o, const NearMatrix &Z, 
     std::vector<cd> w(N);
     for (int j = 0; j < d; ++j) {
         near_apply(o, Z, V[j], w);
+        if (!dinv.empty()) block_apply(dinv, w);
         for (int pass = 0; pass < 2; ++pass)
             for (int i = 0; i <= j; ++i) {
                 cd h = vdot(V[i], w);

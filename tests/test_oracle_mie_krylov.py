@@ -135,3 +135,27 @@ def test_golden_start_is_unit_modulus_and_deterministic():
     assert np.allclose(np.abs(v), 1) and v[0] == 1
     g = (np.sqrt(5) - 1) / 2
     assert np.isclose(np.angle(v[1]), 2 * np.pi * g - 2 * np.pi)
+
+
+def test_edge_block_scaling_pins():
+    rng = np.random.default_rng(12)
+    ne = 40
+    # a matrix made of 2x2 edge blocks only: the scaled operator is I and the
+    # degree-1 polynomial is exact
+    D = rng.standard_normal((ne, 2, 2)) + 1j * rng.standard_normal((ne, 2, 2)) + 3 * np.eye(2)
+    Zb = np.zeros((2 * ne, 2 * ne), dtype=complex)
+    i = np.arange(ne)
+    Zb[i, i], Zb[i, ne + i], Zb[ne + i, i], Zb[ne + i, ne + i] = D[:, 0, 0], D[:, 0, 1], D[:, 1, 0], D[:, 1, 1]
+    Dinv = krylov.edge_blocks_inverse(Zb)
+    v = rng.standard_normal(2 * ne) + 1j * rng.standard_normal(2 * ne)
+    assert np.allclose(Zb @ krylov.edge_blocks_apply(Dinv, v), v, atol=1e-12)
+    assert np.allclose(krylov.near_poly_preconditioner(Zb, 1)(v), np.linalg.solve(Zb, v), atol=1e-12)
+    # badly scaled J/M halves plus a weak coupling: the scaled polynomial is
+    # far closer to the inverse than the unscaled one of the same degree
+    s = np.concatenate([np.full(ne, 1e-2), np.full(ne, 1e2)])
+    Zs = s[:, None] * (Zb + 0.05 * (rng.standard_normal((2 * ne, 2 * ne)) + 1j * rng.standard_normal((2 * ne, 2 * ne))) / np.sqrt(2 * ne))
+    ref = np.linalg.solve(Zs, v)
+    e_scaled = np.linalg.norm(krylov.near_poly_preconditioner(Zs, 8)(v) - ref) / np.linalg.norm(ref)
+    th = krylov.leja_order(krylov.harmonic_ritz(lambda u: Zs @ u, krylov.golden_start(2 * ne), 8))
+    e_plain = np.linalg.norm(krylov.poly_apply(lambda u: Zs @ u, th, v) - ref) / np.linalg.norm(ref)
+    assert e_scaled < 1e-3 and e_scaled < 1e-2 * e_plain
