@@ -103,7 +103,7 @@ typedef struct {
                                  the matrix-core / grouped variant of every stage that
                                  has both and keep the faster; 0 (default): fixed
                                  thresholds (matrix cores from 16 RHS, grouped
-                                 translation from 33 RHS)                               */
+                                 translation from 16 RHS)                               */
 } sfmm_options;
 
 /* Preconditioners of sfmm_solve, all built from the near-field matrix Z_near
@@ -195,6 +195,19 @@ sfmm_status sfmm_planewave_rhs(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const
  * misses the tolerance. */
 sfmm_status sfmm_solve(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void *b, void *x,
                        const void *x0, sfmm_solve_info *info, int32_t on_device);
+
+/* Solve several bodies of the context at once: body bodies[i] with n_rhs[i]
+ * right-hand sides b[i] -> x[i] ([n_rhs[i]][2E_i] each, host or device per
+ * on_device), zero initial guess.  The bodies are taken largest-first from a
+ * work list by up to 8 host threads, each body on a HIP stream of its own, so
+ * uneven bodies overlap on the GPU.  info (may be NULL) is [sum n_rhs] in the
+ * order of the list.  Work queued on the context stream before the call is
+ * complete before any body starts; the call returns when every body is done.
+ * A body may be listed once.  Status: the first hard error of any body, else
+ * SFMM_E_NOT_CONVERGED if any right-hand side missed the tolerance.  Must not
+ * overlap with other calls on the same context. */
+sfmm_status sfmm_solve_bodies(sfmm_ctx *ctx, int32_t n, const int32_t *bodies, const int32_t *n_rhs,
+                              const void *const *b, void *const *x, sfmm_solve_info *info, int32_t on_device);
 
 /* Bistatic RCS (eqs. 27-29): sigma[r][d] = (sigma_theta, sigma_phi) in m^2
  * for solution r at direction theta_phi[d] (radians).  x follows on_device;

@@ -1,12 +1,15 @@
 // C ABI of the sfmm library (declared in include/sfmm.h).  Argument
 // validation, host setup, host <-> device staging and error capture; all
 // products, preconditioner solves and Krylov steps run in the HIP kernels.
+#include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <functional>
 #include <cstdio>
 #include <cstring>
 #include <memory>
 #include <string>
+#include <thread>
 
 #include "device.hpp"
 #include "guess.hpp"
@@ -71,6 +74,32 @@ struct Staged {
     explicit Staged(size_t bytes) : p(device_alloc(bytes)) {}
     ~Staged() { device_free(p); }
 };
+
+void solve_one(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void *b, void *x, const void *x0,
+               sfmm_solve_info *info, int32_t on_device) {
+    DeviceBody &d = dev_of(ctx, body);
+    if (n_rhs <= 0 || !b || !x) throw Error(SFMM_E_INVALID_ARG, "bad arguments");
+    const sfmm_options &o = ctx->opt;
+    const size_t bytes = (size_t)n_rhs * 2 * ctx->bodies[body]->mesh.ne * 2 * sizeof(double);
+    if (on_device) {
+        d.solve(n_rhs, b, x, x0, o.gmres_restart, o.max_iters, o.tol, info, o.verbose);
+        return;
+    }
+    Staged db(bytes), dx(bytes);
+    std::unique_ptr<Staged> dx0;
+    copy_h2d(db.p, b, bytes, d.stream());
+    if (x0) {
+        dx0 = std::make_unique<Staged>(bytes);
+        copy_h2d(dx0->p, x0, bytes, d.stream());
+    }
+    try {
+        d.solve(n_rhs, db.p, dx.p, dx0 ? dx0->p : nullptr, o.gmres_restart, o.max_iters, o.tol, info, o.verbose);
+    } catch (const Error &e) {
+        if (e.code == SFMM_E_NOT_CONVERGED) copy_d2h(x, dx.p, bytes, d.stream());
+        throw;
+    }
+    copy_d2h(x, dx.p, bytes, d.stream());
+}
 
 }  // namespace
 
@@ -241,30 +270,72 @@ sfmm_status sfmm_planewave_rhs(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const
 
 sfmm_status sfmm_solve(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void *b, void *x, const void *x0,
                        sfmm_solve_info *info, int32_t on_device) {
+    return guarded(ctx, [&] { solve_one(ctx, body, n_rhs, b, x, x0, info, on_device); });
+}
+
+sfmm_status sfmm_solve_bodies(sfmm_ctx *ctx, int32_t n, const int32_t *bodies, const int32_t *n_rhs,
+                              const void *const *b, void *const *x, sfmm_solve_info *info, int32_t on_device) {
     return guarded(ctx, [&] {
-        DeviceBody &d = dev_of(ctx, body);
-        if (n_rhs <= 0 || !b || !x) throw Error(SFMM_E_INVALID_ARG, "bad arguments");
-        const sfmm_options &o = ctx->opt;
-        const size_t bytes = (size_t)n_rhs * 2 * ctx->bodies[body]->mesh.ne * 2 * sizeof(double);
-        if (on_device) {
-            d.solve(n_rhs, b, x, x0, o.gmres_restart, o.max_iters, o.tol, info, o.verbose);
-        } else {
-            Staged db(bytes), dx(bytes);
-            std::unique_ptr<Staged> dx0;
-            copy_h2d(db.p, b, bytes, d.stream());
-            if (x0) {
-                dx0 = std::make_unique<Staged>(bytes);
-                copy_h2d(dx0->p, x0, bytes, d.stream());
-            }
-            try {
-                d.solve(n_rhs, db.p, dx.p, dx0 ? dx0->p : nullptr, o.gmres_restart, o.max_iters, o.tol, info,
-                        o.verbose);
-            } catch (const Error &e) {
-                if (e.code == SFMM_E_NOT_CONVERGED) copy_d2h(x, dx.p, bytes, d.stream());
-                throw;
-            }
-            copy_d2h(x, dx.p, bytes, d.stream());
+        if (!ctx || n <= 0 || !bodies || !n_rhs || !b || !x) throw Error(SFMM_E_INVALID_ARG, "bad arguments");
+        std::vector<int64_t> off(n + 1, 0);
+        std::vector<char> seen(ctx->bodies.size(), 0);
+        for (int i = 0; i < n; ++i) {
+            dev_of(ctx, bodies[i]);
+            if (n_rhs[i] <= 0 || !b[i] || !x[i]) throw Error(SFMM_E_INVALID_ARG, "bad arguments for one body");
+            if (seen[bodies[i]]) throw Error(SFMM_E_INVALID_ARG, "a body is listed twice");
+            seen[bodies[i]] = 1;
+            off[i + 1] = off[i] + n_rhs[i];
         }
+        // largest work first, so uneven bodies finish close together
+        std::vector<int> order(n);
+        for (int i = 0; i < n; ++i) order[i] = i;
+        std::sort(order.begin(), order.end(), [&](int a, int c) {
+            return (int64_t)ctx->bodies[bodies[a]]->mesh.ne * n_rhs[a] > (int64_t)ctx->bodies[bodies[c]]->mesh.ne * n_rhs[c];
+        });
+        if (ctx->stream) stream_sync(ctx->stream);   // inputs made on the context stream are complete
+        std::vector<sfmm_status> codes(n, SFMM_OK);
+        std::vector<std::string> msgs(n);
+        std::atomic<int> next{0};
+        auto worker = [&] {
+            try {
+                use_device(ctx->opt.device);
+            } catch (const Error &e) {
+                next = n;
+                codes[0] = e.code;
+                msgs[0] = e.what();
+                return;
+            }
+            for (;;) {
+                const int k = next++;
+                if (k >= n) break;
+                const int i = order[k];
+                DeviceBody &d = *ctx->dev[bodies[i]];
+                // each body runs on a stream of its own while this call lasts
+                d.set_stream(nullptr);
+                try {
+                    solve_one(ctx, bodies[i], n_rhs[i], b[i], x[i], nullptr, info ? info + off[i] : nullptr,
+                              on_device);
+                    d.stream_synchronize();
+                } catch (const Error &e) {
+                    codes[i] = e.code;
+                    msgs[i] = e.what();
+                } catch (const std::exception &e) {
+                    codes[i] = SFMM_E_INVALID_ARG;
+                    msgs[i] = e.what();
+                }
+                d.set_stream(ctx->stream);
+            }
+        };
+        const int nw = std::min(n, 8);
+        std::vector<std::thread> pool;
+        for (int w = 0; w < nw; ++w) pool.emplace_back(worker);
+        for (std::thread &t : pool) t.join();
+        int worst = -1;
+        for (int i = 0; i < n; ++i) {
+            if (codes[i] == SFMM_OK) continue;
+            if (worst < 0 || (codes[worst] == SFMM_E_NOT_CONVERGED && codes[i] != SFMM_E_NOT_CONVERGED)) worst = i;
+        }
+        if (worst >= 0) throw Error(codes[worst], "body " + std::to_string(bodies[worst]) + ": " + msgs[worst]);
     });
 }
 

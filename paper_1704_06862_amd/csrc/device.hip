@@ -43,7 +43,7 @@ namespace sfmm {
 constexpr int MAXLEV = 21;
 constexpr size_t LDS_LIMIT = 64 * 1024;
 constexpr int BATCH = 64;        // right-hand sides per batched chunk
-constexpr int TRANS_GRP_MIN_R = 33;  // sibling-grouped translation from this many RHS
+constexpr int TRANS_GRP_MIN_R = 16;  // sibling-grouped translation from this many RHS
 constexpr int MMA_MIN_R = 16;    // batched near products from this many RHS run on the matrix cores
 
 void *device_alloc(size_t bytes) {
@@ -235,6 +235,7 @@ class DeviceBodyT final : public DeviceBody {
 
     void set_stream(void *s) override { stream_ = s ? (hipStream_t)s : own_stream_; }
     void *stream() const override { return stream_; }
+    void stream_synchronize() override { HIPCHK(hipStreamSynchronize(stream_)); }
 
     // ---- HIP graphs: one executable graph per (operation, batch size) ----
     enum GraphKind { G_PRODUCT = 0, G_PRECOND = 1, G_PREC_PRODUCT = 2 };

@@ -27,7 +27,8 @@ PRECOND_ILU0, PRECOND_NONE, PRECOND_BLOCK_JACOBI, PRECOND_POLY = 0, 1, 2, 3
 EXPORTED = ["sfmm_default_options", "sfmm_setup", "sfmm_destroy", "sfmm_last_error", "sfmm_set_stream",
             "sfmm_num_unknowns", "sfmm_edges", "sfmm_matvec", "sfmm_precond", "sfmm_planewave_rhs",
             "sfmm_solve", "sfmm_rcs", "sfmm_near_rows", "sfmm_describe", "sfmm_profile",
-            "sfmm_guess_default_options", "sfmm_guess_fit", "sfmm_guess_predict", "sfmm_mlp_train"]
+            "sfmm_guess_default_options", "sfmm_guess_fit", "sfmm_guess_predict", "sfmm_mlp_train",
+            "sfmm_solve_bodies"]
 
 
 class sfmm_body(ctypes.Structure):
@@ -98,6 +99,7 @@ def load():
     lib.sfmm_guess_fit.argtypes = [P, I32, I32, P, P, P, ctypes.POINTER(sfmm_guess_options), P, I32]
     lib.sfmm_guess_predict.argtypes = [P, I32, I32, P, P, P, I32]
     lib.sfmm_mlp_train.argtypes = [I32, I32, P, P, I32, P, P, I32, D, P, P, P]
+    lib.sfmm_solve_bodies.argtypes = [P, I32, P, P, P, P, P, I32]
     for name in EXPORTED:
         if name not in ("sfmm_default_options", "sfmm_destroy", "sfmm_last_error", "sfmm_guess_default_options"):
             getattr(lib, name).restype = ctypes.c_int
@@ -263,6 +265,32 @@ class Context:
         return [dict(converged=bool(i.converged), iterations=i.iterations, restarts=i.restarts,
                      guess_used=bool(i.guess_used), true_residual=i.true_residual,
                      initial_residual=i.initial_residual, seconds=i.seconds) for i in info]
+
+    def sfmm_solve_bodies(self, problems, raise_on_nonconvergence=False):
+        """problems: list of (body, b, x); all host or all device arrays.
+        Returns one list of info dicts per problem."""
+        n = len(problems)
+        bodies = np.array([p[0] for p in problems], dtype=np.int32)
+        n_rhs = np.array([p[1].shape[0] if p[1].ndim == 2 else 1 for p in problems], dtype=np.int32)
+        devs = set()
+        pb, px = (ctypes.c_void_p * n)(), (ctypes.c_void_p * n)()
+        for i, (_, b, x) in enumerate(problems):
+            pb[i], d1 = _ptr(b)
+            px[i], d2 = _ptr(x)
+            devs.update((d1, d2))
+        if len(devs) != 1:
+            raise ValueError("all vectors must be host arrays or all device arrays")
+        info = (sfmm_solve_info * int(n_rhs.sum()))()
+        st = lib().sfmm_solve_bodies(self.ctx, n, bodies.ctypes.data, n_rhs.ctypes.data, pb, px, info, devs.pop())
+        if st != SFMM_OK and (st != 5 or raise_on_nonconvergence):
+            _check(st, self.ctx)
+        out, k = [], 0
+        for r in n_rhs:
+            out.append([dict(converged=bool(i.converged), iterations=i.iterations, restarts=i.restarts,
+                             guess_used=bool(i.guess_used), true_residual=i.true_residual,
+                             initial_residual=i.initial_residual, seconds=i.seconds) for i in info[k:k + r]])
+            k += r
+        return out
 
     def sfmm_guess_fit(self, angles, x, pol=None, body=0, **options):
         """Train the learned initial guess on solutions x [n][2E] of the

@@ -62,3 +62,43 @@ def test_coated_sphere_307200_unknowns_rcs_vs_mie():
     print(info, "E-plane RMS/max dB", rE, xE, "H-plane", rH, xH)
     assert info["converged"] and info["true_residual"] <= 1e-4
     assert rE < 0.5 and rH < 0.5 and xE < 3.0 and xH < 3.0
+
+
+def test_uneven_bodies_solved_concurrently():
+    # a slice of the seeded 48-ellipsoid batch (semi-axes U[0.3, 1.5] wavelengths,
+    # eps_r U[2, 10]; 15,360 unknowns each, 58 to 1,210 GMRES iterations), 8
+    # incidence angles each: solved body by body and all at once (one stream
+    # per body); the results must not depend on the schedule
+    torch = pytest.importorskip("torch")
+    import time
+
+    from workloads import ellipsoid_batch, theta_sweep
+
+    bodies = ellipsoid_batch(48)[:8]
+    print("setup", [len(b.triangles) for b in bodies], flush=True)
+    with sfmm.Context(bodies, finest_box=0.25, digits=3.0, precision=sfmm.PREC_FP32, gmres_restart=50,
+                      tol=1e-4, max_iters=2000) as ctx:
+        ang = theta_sweep(8)
+        bs, xs, xc = [], [], []
+        for i in range(len(bodies)):
+            n = ctx.sfmm_num_unknowns(i)
+            b = torch.zeros((8, n), dtype=torch.complex128, device="cuda")
+            ctx.sfmm_planewave_rhs(ang, b, body=i)
+            bs.append(b)
+            xs.append(torch.zeros_like(b))
+            xc.append(torch.zeros_like(b))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        seq = [ctx.sfmm_solve(bs[i], xs[i], body=i) for i in range(len(bodies))]
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        conc = ctx.sfmm_solve_bodies([(i, bs[i], xc[i]) for i in range(len(bodies))])
+        torch.cuda.synchronize()
+        t_conc = time.perf_counter() - t0
+    print(f"8 bodies x 8 angles: one after another {t_seq:.3f} s, concurrently {t_conc:.3f} s "
+          f"({t_seq / t_conc:.2f}x)", [max(i["iterations"] for i in s) for s in seq])
+    for i in range(len(bodies)):
+        assert all(a["converged"] for a in conc[i])
+        assert [a["iterations"] for a in conc[i]] == [a["iterations"] for a in seq[i]]
+        assert float(torch.linalg.norm(xc[i] - xs[i]) / torch.linalg.norm(xs[i])) < 1e-10
