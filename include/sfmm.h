@@ -181,6 +181,10 @@ sfmm_status sfmm_precond(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void 
 sfmm_status sfmm_planewave_rhs(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const double *angles,
                                const double *pol, void *b, int32_t on_device);
 
+/* Change the GMRES settings of later sfmm_solve calls (0 keeps a value):
+ * restart length (1..1000), iteration cap, relative tolerance. */
+sfmm_status sfmm_set_solver(sfmm_ctx *ctx, int32_t gmres_restart, int32_t max_iters, double tol);
+
 /* Solve Z x = b with restarted flexible GMRES(m) (Saad 1993): Arnoldi with
  * classical Gram-Schmidt applied twice, Givens rotations and the
  * least-squares update in FP64, the preconditioner of sfmm_options applied on

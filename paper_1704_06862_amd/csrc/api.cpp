@@ -202,6 +202,17 @@ sfmm_status sfmm_set_stream(sfmm_ctx *ctx, void *stream) {
     });
 }
 
+sfmm_status sfmm_set_solver(sfmm_ctx *ctx, int32_t gmres_restart, int32_t max_iters, double tol) {
+    return guarded(ctx, [&] {
+        if (!ctx) throw Error(SFMM_E_INVALID_ARG, "NULL context");
+        if (gmres_restart < 0 || gmres_restart > 1000 || max_iters < 0 || !(tol >= 0))
+            throw Error(SFMM_E_INVALID_ARG, "bad solver settings");
+        if (gmres_restart > 0) ctx->opt.gmres_restart = gmres_restart;
+        if (max_iters > 0) ctx->opt.max_iters = max_iters;
+        if (tol > 0) ctx->opt.tol = tol;
+    });
+}
+
 sfmm_status sfmm_num_unknowns(const sfmm_ctx *ctx, int32_t body, int64_t *n) {
     return guarded(const_cast<sfmm_ctx *>(ctx), [&] {
         const BodyHost &b = body_of(ctx, body);

@@ -116,6 +116,29 @@ __global__ void k_adam(int64_t n, float lr, float b1, float b2, float eps, float
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// Adam step whose step count lives on the device (so that a captured graph
+// can replay it): t = *step + 1, step size lr0 (1 + cos(pi (t - 1) / E)) / 2
+// for t <= E, bias corrections 1 - b^t.
+__global__ void k_adam_sched(int64_t n, float lr0, int E, float b1, float b2, float eps,
+                             const int *__restrict__ step, const float *__restrict__ g, float *__restrict__ m,
+                             float *__restrict__ v, float *__restrict__ p) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int t = *step + 1;
+    const float lr = lr0 * 0.5f * (1.f + cosf(3.14159265358979f * (float)(t - 1) / (float)E));
+    const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void k_step_inc(int *step) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *step += 1;
+}
+
 inline unsigned nb(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 void gemm(hipStream_t s, int M, int N, int K, const float *A, int64_t a0, int64_t a1, const float *B, int64_t b0,
@@ -194,7 +217,7 @@ void Mlp::init_uniform(uint64_t seed) {
     t_ = 0;
 }
 
-void Mlp::ensure(int B) {
+void Mlp::ensure_batch(int B) {
     if (B <= cap_) return;
     for (float *q : acts_) (void)hipFree(q);
     acts_.assign(sizes_.size(), nullptr);
@@ -213,7 +236,7 @@ void Mlp::ensure(int B) {
 }
 
 const float *Mlp::forward(int B, const float *X) {
-    ensure(B);
+    ensure_batch(B);
     hipStream_t s = (hipStream_t)stream_;
     GHIPCHK(hipMemcpyAsync(acts_[0], X, sizeof(float) * (size_t)B * sizes_[0], hipMemcpyDeviceToDevice, s));
     int64_t off = 0;
@@ -263,6 +286,14 @@ double Mlp::loss_grad(int B, const float *X, const float *Y, bool want_loss) {
     double loss = 0;
     for (double v : part) loss += v;
     return loss / B;
+}
+
+void Mlp::adam_scheduled(const int *step, double lr0, int epochs, double b1, double b2, double eps) {
+    k_adam_sched<<<nb(np_, 256), 256, 0, (hipStream_t)stream_>>>(np_, (float)lr0, epochs, (float)b1, (float)b2,
+                                                                 (float)eps, step, g_, m_, v_, p_);
+    GHIPCHK(hipGetLastError());
+    k_step_inc<<<1, 64, 0, (hipStream_t)stream_>>>(const_cast<int *>(step));
+    GHIPCHK(hipGetLastError());
 }
 
 void Mlp::adam_step(double lr, double b1, double b2, double eps) {
@@ -518,25 +549,73 @@ double Guess::fit(int n, const double *angles, const void *B, const void *X, con
     auto net = std::make_unique<Mlp>(std::vector<int>{nf, o.hidden, o.hidden, no}, stream_);
     net->init_uniform(o.seed);
     float *dF = nullptr, *dY = nullptr;
+    int *dstep = nullptr;
     GHIPCHK(hipMalloc(&dF, sizeof(float) * F.size()));
     GHIPCHK(hipMalloc(&dY, sizeof(float) * Y.size()));
+    GHIPCHK(hipMalloc(&dstep, sizeof(int)));
     double loss = 0;
     try {
         GHIPCHK(hipMemcpyAsync(dF, F.data(), sizeof(float) * F.size(), hipMemcpyHostToDevice, (hipStream_t)stream_));
         GHIPCHK(hipMemcpyAsync(dY, Y.data(), sizeof(float) * Y.size(), hipMemcpyHostToDevice, (hipStream_t)stream_));
-        const double pi = 3.14159265358979323846;
-        for (int e = 0; e < o.epochs; ++e) {
-            net->loss_grad(n, dF, dY, false);
-            net->adam_step(o.lr * 0.5 * (1.0 + std::cos(pi * e / o.epochs)));
+        // one epoch (forward, backward, Adam with the device-side step count)
+        // is captured once into a HIP graph and replayed
+        GHIPCHK(hipMemsetAsync(dstep, 0, sizeof(int), (hipStream_t)stream_));
+        net->ensure_batch(n);
+        hipStream_t st = (hipStream_t)stream_;
+        bool graphed = false;
+        if (st && o.epochs > 1) {
+            hipGraph_t g = nullptr;
+            // EPG epochs per graph launch
+            constexpr int EPG = 25;
+            const int per = std::min(EPG, o.epochs);
+            GHIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            try {
+                for (int k = 0; k < per; ++k) {
+                    net->loss_grad(n, dF, dY, false);
+                    net->adam_scheduled(dstep, o.lr, o.epochs);
+                }
+            } catch (...) {
+                hipGraph_t broken = nullptr;
+                (void)hipStreamEndCapture(st, &broken);
+                if (broken) (void)hipGraphDestroy(broken);
+                throw;
+            }
+            GHIPCHK(hipStreamEndCapture(st, &g));
+            hipGraphExec_t ex = nullptr;
+            const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            GHIPCHK(e);
+            int done = 0;
+            for (; done + per <= o.epochs; done += per) {
+                const hipError_t le = hipGraphLaunch(ex, st);
+                if (le != hipSuccess) {
+                    (void)hipGraphExecDestroy(ex);
+                    GHIPCHK(le);
+                }
+            }
+            GHIPCHK(hipStreamSynchronize(st));
+            (void)hipGraphExecDestroy(ex);
+            for (; done < o.epochs; ++done) {   // the remainder, launched directly
+                net->loss_grad(n, dF, dY, false);
+                net->adam_scheduled(dstep, o.lr, o.epochs);
+            }
+            graphed = true;
         }
+        if (!graphed)
+            for (int ep = 0; ep < o.epochs; ++ep) {
+                net->loss_grad(n, dF, dY, false);
+                net->adam_scheduled(dstep, o.lr, o.epochs);
+            }
         loss = net->loss_grad(n, dF, dY, true);
     } catch (...) {
         (void)hipFree(dF);
         (void)hipFree(dY);
+        (void)hipFree(dstep);
         throw;
     }
     (void)hipFree(dF);
     (void)hipFree(dY);
+    (void)hipFree(dstep);
     net_ = std::move(net);
     return loss;
 }

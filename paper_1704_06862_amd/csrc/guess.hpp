@@ -36,9 +36,15 @@ class Mlp {
     // and NaN is returned
     double loss_grad(int B, const float *X, const float *Y, bool want_loss = true);
     void adam_step(double lr, double b1 = 0.9, double b2 = 0.999, double eps = 1e-8);
+    // Adam step with the step count *step on the device (incremented after
+    // the update) and the cosine schedule lr0 (1 + cos(pi (t-1)/epochs)) / 2;
+    // launches only kernels, so it can be captured into a graph
+    void adam_scheduled(const int *step, double lr0, int epochs, double b1 = 0.9, double b2 = 0.999,
+                        double eps = 1e-8);
+    // activation buffers for batches up to B (allocates; call before capture)
+    void ensure_batch(int B);
 
   private:
-    void ensure(int B);
     std::vector<int> sizes_;
     void *stream_;
     int64_t np_ = 0;

@@ -28,7 +28,7 @@ EXPORTED = ["sfmm_default_options", "sfmm_setup", "sfmm_destroy", "sfmm_last_err
             "sfmm_num_unknowns", "sfmm_edges", "sfmm_matvec", "sfmm_precond", "sfmm_planewave_rhs",
             "sfmm_solve", "sfmm_rcs", "sfmm_near_rows", "sfmm_describe", "sfmm_profile",
             "sfmm_guess_default_options", "sfmm_guess_fit", "sfmm_guess_predict", "sfmm_mlp_train",
-            "sfmm_solve_bodies"]
+            "sfmm_solve_bodies", "sfmm_set_solver"]
 
 
 class sfmm_body(ctypes.Structure):
@@ -100,6 +100,7 @@ def load():
     lib.sfmm_guess_predict.argtypes = [P, I32, I32, P, P, P, I32]
     lib.sfmm_mlp_train.argtypes = [I32, I32, P, P, I32, P, P, I32, D, P, P, P]
     lib.sfmm_solve_bodies.argtypes = [P, I32, P, P, P, P, P, I32]
+    lib.sfmm_set_solver.argtypes = [P, I32, I32, D]
     for name in EXPORTED:
         if name not in ("sfmm_default_options", "sfmm_destroy", "sfmm_last_error", "sfmm_guess_default_options"):
             getattr(lib, name).restype = ctypes.c_int
@@ -265,6 +266,9 @@ class Context:
         return [dict(converged=bool(i.converged), iterations=i.iterations, restarts=i.restarts,
                      guess_used=bool(i.guess_used), true_residual=i.true_residual,
                      initial_residual=i.initial_residual, seconds=i.seconds) for i in info]
+
+    def sfmm_set_solver(self, gmres_restart=0, max_iters=0, tol=0.0):
+        _check(lib().sfmm_set_solver(self.ctx, gmres_restart, max_iters, tol), self.ctx)
 
     def sfmm_solve_bodies(self, problems, raise_on_nonconvergence=False):
         """problems: list of (body, b, x); all host or all device arrays.
