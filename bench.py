@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes of one k_near launch at this size from rocprofv3 --pmc: FETCH_SIZE
 # (KiB) x 2.0 + WRITE_SIZE (KiB) x 1.0, the factors being what the counters
 # read for a plain 256 MiB device copy (profiles/near_product_sphere61440_pmc_traffic.md)
-NEAR_TRAFFIC_BYTES = int((154590 * 2.0 + 524) * 1024)
+NEAR_TRAFFIC_BYTES = int((154369 * 2.0 + 523) * 1024)
 
 
 def parse():
@@ -49,7 +49,7 @@ def parse():
     p.add_argument("--batch", type=str, default="8,64",
                    help="extra right-hand-side batch sizes measured outside the timed region")
     p.add_argument("--sweep", type=int, default=64, help="angles of the theta sweep (0 = skip)")
-    p.add_argument("--train-every", type=int, default=4,
+    p.add_argument("--train-every", type=int, default=2,
                    help="learned-guess sweep: solve every n-th angle loosely first and train on those")
     p.add_argument("--copy-calibration", type=int, default=0,
                    help="MiB of a plain device copy run after the measurements, to scale HBM byte counters")
@@ -93,7 +93,9 @@ def sweep(ctx, ctx_mixed, torch, n_ang, every):
                        loose solves, training and prediction are timed);
       learned_pretrained bf16-split, network trained beforehand on a coarse
                        sweep at the mid-points (reported apart): prediction and
-                       one batched solve of all angles from it are timed.
+                       one batched solve of all angles from it are timed;
+      span_projection  the same training solutions without the network: the
+                       minimal-residual guess in their POD span (baseline).
     """
     from workloads import theta_sweep
 
@@ -111,7 +113,8 @@ def sweep(ctx, ctx_mixed, torch, n_ang, every):
         return out, time.perf_counter() - t0
 
     def its(infos):
-        return float(np.mean([i["iterations"] for i in infos]))
+        # mean and, since a batch iterates in lockstep, the maximum
+        return [round(float(np.mean([i["iterations"] for i in infos])), 1), max(i["iterations"] for i in infos)]
 
     x = torch.zeros_like(b)
     i_plain, t_plain = timed(lambda: [ctx.sfmm_solve(b[i:i + 1], x[i:i + 1])[0] for i in range(n_ang)])
@@ -134,7 +137,7 @@ def sweep(ctx, ctx_mixed, torch, n_ang, every):
         i_tr = ctx_mixed.sfmm_solve(b_tr, x_tr)
         ctx_mixed.sfmm_set_solver(tol=1e-4)
         t_fit = time.perf_counter()
-        loss = ctx_mixed.sfmm_guess_fit(ang[tr], x_tr, rank=len(tr))
+        loss = ctx_mixed.sfmm_guess_fit(ang[tr], x_tr)
         x0 = torch.zeros_like(b)
         ctx_mixed.sfmm_guess_predict(ang, x0)
         torch.cuda.synchronize()
@@ -154,7 +157,7 @@ def sweep(ctx, ctx_mixed, torch, n_ang, every):
 
     def pretrain():
         i_mid = ctx_mixed.sfmm_solve(b_mid, x_mid)
-        loss = ctx_mixed.sfmm_guess_fit(mid, x_mid, rank=len(mid))
+        loss = ctx_mixed.sfmm_guess_fit(mid, x_mid)
         return i_mid, loss
 
     (i_mid, loss_pre), t_pre = timed(pretrain)
@@ -167,29 +170,44 @@ def sweep(ctx, ctx_mixed, torch, n_ang, every):
 
     i_am, t_am = timed(amortized)
 
+    def span_baseline():
+        x0 = torch.zeros_like(b)
+        ctx_mixed.sfmm_span_predict(ang, x0)
+        xs = torch.zeros_like(b)
+        return ctx_mixed.sfmm_solve(b, xs, x0=x0)
+
+    span_baseline()   # the first call forms Z U (reported with the training cost)
+    i_sp, t_sp = timed(span_baseline)
+
     (i_tr, i_te, loss, t_fit), t_learn = timed(learned)
-    ok = all(i["converged"] for i in i_plain + i_batch + i_mixed + i_tr + i_te + i_mid + i_am)
+    ok = all(i["converged"] for i in i_plain + i_batch + i_mixed + i_tr + i_te + i_mid + i_am + i_sp)
     assert len(i_te) == n_ang
     ms = lambda t: round(1e3 * t / n_ang, 2)  # noqa: E731
     return {
         "angles": n_ang, "tol": 1e-4,
         "ms_per_angle": {"plain_fp32": ms(t_plain), "batched_fp32": ms(t_batch), "batched_bf16split": ms(t_mixed),
                          "batched_bf16split_learned_in_sweep": ms(t_learn),
-                         "batched_bf16split_learned_pretrained": ms(t_am)},
+                         "batched_bf16split_learned_pretrained": ms(t_am),
+                         "batched_bf16split_span_projection_pretrained": ms(t_sp)},
         "speedup_vs_plain": {"batched_fp32": round(t_plain / t_batch, 2),
                              "batched_bf16split": round(t_plain / t_mixed, 2),
                              "batched_bf16split_learned_in_sweep": round(t_plain / t_learn, 2),
-                             "batched_bf16split_learned_pretrained": round(t_plain / t_am, 2)},
-        "iterations_mean": {"plain_fp32": its(i_plain), "batched_fp32": its(i_batch),
+                             "batched_bf16split_learned_pretrained": round(t_plain / t_am, 2),
+                             "batched_bf16split_span_projection_pretrained": round(t_plain / t_sp, 2)},
+        "iterations_mean_max": {"plain_fp32": its(i_plain), "batched_fp32": its(i_batch),
                             "batched_bf16split": its(i_mixed), "in_sweep_training_solves_1e-2": its(i_tr),
-                            "in_sweep_all_angles_from_guess": its(i_te), "pretrained": its(i_am)},
-        "true_residual_max": max(i["true_residual"] for i in i_plain + i_batch + i_mixed + i_te + i_am),
+                            "in_sweep_all_angles_from_guess": its(i_te), "pretrained": its(i_am),
+                            "span_projection_pretrained": its(i_sp)},
+        "true_residual_max": max(i["true_residual"] for i in i_plain + i_batch + i_mixed + i_te + i_am + i_sp),
         "guess_in_sweep": {"trained_on": len(tr), "fit_and_predict_s": round(t_fit, 3), "loss": loss,
                            "initial_residual_median": float(np.median([i["initial_residual"] for i in i_te])),
                            "used": int(sum(i["guess_used"] for i in i_te))},
         "guess_pretrained": {"trained_on": len(mid), "coarse_solve_and_fit_s": round(t_pre, 3), "loss": loss_pre,
                              "initial_residual_median": float(np.median([i["initial_residual"] for i in i_am])),
                              "used": int(sum(i["guess_used"] for i in i_am))},
+        "span_projection_pretrained": {
+            "initial_residual_median": float(np.median([i["initial_residual"] for i in i_sp])),
+            "used": int(sum(i["guess_used"] for i in i_sp))},
         "all_converged": bool(ok),
     }
 

@@ -251,6 +251,13 @@ sfmm_status sfmm_guess_fit(sfmm_ctx *ctx, int32_t body, int32_t n, const double 
 sfmm_status sfmm_guess_predict(sfmm_ctx *ctx, int32_t body, int32_t n, const double *angles, const double *pol,
                                void *x0, int32_t on_device);
 
+/* Baseline for the learned guess, without the network: the guess in the span
+ * of the POD basis U of the last sfmm_guess_fit that minimises the residual,
+ * x0 = U c, c = argmin ||b - Z U c|| (normal equations of W = Z U; W costs r
+ * products on the first call after a fit).  Arguments as sfmm_guess_predict. */
+sfmm_status sfmm_span_predict(sfmm_ctx *ctx, int32_t body, int32_t n, const double *angles, const double *pol,
+                              void *x0, int32_t on_device);
+
 /* The network kernels of the learned guess on their own, for checking: an
  * MLP with layer sizes sizes[0..n_sizes-1] (tanh hidden layers, linear
  * output) and parameters params (host; per layer W [in][out] row-major then

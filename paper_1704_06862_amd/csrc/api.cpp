@@ -509,6 +509,28 @@ sfmm_status sfmm_guess_predict(sfmm_ctx *ctx, int32_t body, int32_t n, const dou
     });
 }
 
+sfmm_status sfmm_span_predict(sfmm_ctx *ctx, int32_t body, int32_t n, const double *angles, const double *pol,
+                              void *x0, int32_t on_device) {
+    return guarded(ctx, [&] {
+        DeviceBody &d = dev_of(ctx, body);
+        if (n <= 0 || !angles || !x0) throw Error(SFMM_E_INVALID_ARG, "bad arguments");
+        if ((int)ctx->guess.size() <= body || !ctx->guess[body])
+            throw Error(SFMM_E_INVALID_ARG, "no training solutions for this body (call sfmm_guess_fit)");
+        const int N = 2 * ctx->bodies[body]->mesh.ne;
+        const size_t bytes = (size_t)n * N * 2 * sizeof(double);
+        Staged db(bytes);
+        d.planewave_rhs(n, angles, pol, db.p);
+        auto product = [&](int r, const void *in, void *out) { d.matvec(r, in, out, SFMM_PART_ALL); };
+        if (on_device) {
+            ctx->guess[body]->span_predict(n, db.p, x0, product);
+        } else {
+            Staged dx(bytes);
+            ctx->guess[body]->span_predict(n, db.p, dx.p, product);
+            copy_d2h(x0, dx.p, bytes, d.stream());
+        }
+    });
+}
+
 sfmm_status sfmm_mlp_train(int32_t device, int32_t n_sizes, const int32_t *sizes, float *params, int32_t batch,
                            const float *X, const float *Y, int32_t steps, double lr, double *loss, float *grads,
                            float *out) {

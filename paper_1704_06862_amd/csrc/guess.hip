@@ -448,7 +448,51 @@ void lincomb(const void *vecs, int64_t ld, int nv, const cd *coef_host, int ns, 
 
 namespace sfmm {
 
-Guess::~Guess() { (void)hipFree(U_); }
+Guess::~Guess() {
+    (void)hipFree(U_);
+    (void)hipFree(W_);
+}
+
+void Guess::span_predict(int n, const void *B, void *X0,
+                         const std::function<void(int, const void *, void *)> &product) {
+    if (!U_) throw Error(SFMM_E_INVALID_ARG, "learned guess is not trained (call sfmm_guess_fit first)");
+    if (n < 1) throw Error(SFMM_E_INVALID_ARG, "n must be positive");
+    const int r = r_;
+    if (!W_) {
+        GHIPCHK(hipMalloc(&W_, sizeof(double2) * (size_t)r * N_));
+        product(r, U_, W_);
+        gram_.assign((size_t)r * r, 0.0);
+        cross_dots(W_, N_, r, W_, N_, r, N_, gram_.data(), stream_);
+    }
+    // c_s = (W^H W)^-1 W^H b_s: Gaussian elimination with partial pivoting
+    std::vector<cd> h((size_t)r * n);
+    cross_dots(W_, N_, r, B, N_, n, N_, h.data(), stream_);   // h[k][s] = w_k^H b_s
+    std::vector<cd> A = gram_, coef((size_t)n * r);
+    std::vector<cd> rhs(h);
+    for (int k = 0; k < r; ++k) {
+        int piv = k;
+        for (int i = k + 1; i < r; ++i)
+            if (std::abs(A[(size_t)i * r + k]) > std::abs(A[(size_t)piv * r + k])) piv = i;
+        if (piv != k) {
+            for (int j = 0; j < r; ++j) std::swap(A[(size_t)k * r + j], A[(size_t)piv * r + j]);
+            for (int s2 = 0; s2 < n; ++s2) std::swap(rhs[(size_t)k * n + s2], rhs[(size_t)piv * n + s2]);
+        }
+        const cd p = A[(size_t)k * r + k];
+        if (!(std::abs(p) > 0)) throw Error(SFMM_E_BREAKDOWN, "singular reduced system in the span guess");
+        for (int i = k + 1; i < r; ++i) {
+            const cd f = A[(size_t)i * r + k] / p;
+            for (int j = k; j < r; ++j) A[(size_t)i * r + j] -= f * A[(size_t)k * r + j];
+            for (int s2 = 0; s2 < n; ++s2) rhs[(size_t)i * n + s2] -= f * rhs[(size_t)k * n + s2];
+        }
+    }
+    for (int s2 = 0; s2 < n; ++s2)
+        for (int i = r - 1; i >= 0; --i) {
+            cd v = rhs[(size_t)i * n + s2];
+            for (int j = i + 1; j < r; ++j) v -= A[(size_t)i * r + j] * coef[(size_t)s2 * r + j];
+            coef[(size_t)s2 * r + i] = v / A[(size_t)i * r + i];
+        }
+    lincomb(U_, N_, r, coef.data(), n, N_, X0, N_, stream_);
+}
 
 void Guess::set_stream(void *s) {
     stream_ = s;
@@ -486,6 +530,9 @@ double Guess::fit(int n, const double *angles, const void *B, const void *X, con
         throw Error(SFMM_E_INVALID_ARG, "learned guess: bad options");
     o_ = o;
     net_.reset();
+    (void)hipFree(W_);
+    W_ = nullptr;
+    gram_.clear();
     // POD basis: Gram matrix G[i][j] = <x_i, x_j>, G = V diag(w) V^H,
     // u_k = sum_i x_i V[i][k] / sqrt(w_k) for the r largest w_k
     std::vector<cd> G((size_t)n * n), V;

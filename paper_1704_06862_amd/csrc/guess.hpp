@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <memory>
 #include <vector>
 
@@ -73,7 +74,7 @@ struct GuessOptions {
     int rank = 16;        // POD basis size r (clamped to the training count)
     int harmonics = 4;    // M angle harmonics
     int hidden = 64;      // width of both tanh hidden layers
-    int epochs = 6000;    // full-batch Adam steps
+    int epochs = 2000;    // full-batch Adam steps
     double lr = 3e-3;     // peak Adam step, cosine decay to zero
     uint64_t seed = 0;    // weight initialisation
 };
@@ -93,6 +94,11 @@ class Guess {
     double fit(int n, const double *angles, const void *B, const void *X, const GuessOptions &o);
     // X0 device [n][N] complex
     void predict(int n, const double *angles, const void *B, void *X0);
+    // Baseline without the network: the minimal-residual guess in span(U),
+    // c = argmin ||b - Z U c|| (normal equations of W = Z U, W formed once
+    // with `product`, which applies Z to r boundary-layout device vectors)
+    void span_predict(int n, const void *B, void *X0,
+                      const std::function<void(int, const void *, void *)> &product);
 
   private:
     void features(int n, const double *angles, const void *B, std::vector<float> &F, std::vector<double> &nb);
@@ -103,6 +109,8 @@ class Guess {
     void *U_ = nullptr;            // [r][N] complex FP64, orthonormal rows
     std::vector<double> mu_, sd_;  // target standardisation
     std::unique_ptr<Mlp> net_;
+    void *W_ = nullptr;            // Z U, [r][N], formed on the first span_predict
+    std::vector<cd> gram_;         // W^H W
 };
 
 }  // namespace sfmm

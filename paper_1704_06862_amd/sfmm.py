@@ -28,7 +28,7 @@ EXPORTED = ["sfmm_default_options", "sfmm_setup", "sfmm_destroy", "sfmm_last_err
             "sfmm_num_unknowns", "sfmm_edges", "sfmm_matvec", "sfmm_precond", "sfmm_planewave_rhs",
             "sfmm_solve", "sfmm_rcs", "sfmm_near_rows", "sfmm_describe", "sfmm_profile",
             "sfmm_guess_default_options", "sfmm_guess_fit", "sfmm_guess_predict", "sfmm_mlp_train",
-            "sfmm_solve_bodies", "sfmm_set_solver"]
+            "sfmm_solve_bodies", "sfmm_set_solver", "sfmm_span_predict"]
 
 
 class sfmm_body(ctypes.Structure):
@@ -101,6 +101,7 @@ def load():
     lib.sfmm_mlp_train.argtypes = [I32, I32, P, P, I32, P, P, I32, D, P, P, P]
     lib.sfmm_solve_bodies.argtypes = [P, I32, P, P, P, P, P, I32]
     lib.sfmm_set_solver.argtypes = [P, I32, I32, D]
+    lib.sfmm_span_predict.argtypes = [P, I32, I32, P, P, P, I32]
     for name in EXPORTED:
         if name not in ("sfmm_default_options", "sfmm_destroy", "sfmm_last_error", "sfmm_guess_default_options"):
             getattr(lib, name).restype = ctypes.c_int
@@ -308,6 +309,14 @@ class Context:
                                     None if polv is None else polv.ctypes.data, px, ctypes.byref(go),
                                     ctypes.byref(loss), dev), self.ctx)
         return loss.value
+
+    def sfmm_span_predict(self, angles, x0, pol=None, body=0):
+        angles = np.ascontiguousarray(angles, dtype=np.float64).reshape(-1, 2)
+        polv = None if pol is None else np.ascontiguousarray(pol, dtype=np.float64)
+        px, dev = _ptr(x0)
+        _check(lib().sfmm_span_predict(self.ctx, body, len(angles), angles.ctypes.data,
+                                       None if polv is None else polv.ctypes.data, px, dev), self.ctx)
+        return x0
 
     def sfmm_guess_predict(self, angles, x0, pol=None, body=0):
         angles = np.ascontiguousarray(angles, dtype=np.float64).reshape(-1, 2)

@@ -158,6 +158,16 @@ def test_learned_guess_cuts_iterations(ectx):
     assert its1.mean() < 0.75 * its0.mean()
     # both solutions agree to the solver tolerance
     assert rel(x_lrn, x_zero) < 1e-2
+    # the network-free baseline: minimal residual in the same POD span; it
+    # also lies in the span and its residual is no larger than the network's
+    xs = ectx.sfmm_span_predict(ang[te], np.zeros((len(te), n), dtype=complex))
+    coef = np.linalg.lstsq(x_tr.T, xs.T, rcond=None)[0]
+    assert rel(x_tr.T @ coef, xs.T) < 1e-6
+    info2 = ectx.sfmm_solve(b[te].copy(), np.zeros((len(te), n), dtype=complex), x0=xs)
+    r2 = np.array([i["initial_residual"] for i in info2])
+    print(f"span baseline: guess residual median {np.median(r2):.3e}, iterations "
+          f"{np.mean([i['iterations'] for i in info2]):.1f}")
+    assert np.median(r2) <= np.median(r0) * 1.05
 
 
 def test_judge_drops_a_bad_guess(ectx):
