@@ -104,6 +104,11 @@ class DeviceBodyT final : public DeviceBody {
         // cannot be captured; it is a blocking stream, so it stays ordered
         // with work on the default stream
         HIPCHK(hipStreamCreate(&own_stream_));
+        for (int i = 0; i < 2; ++i) {
+            HIPCHK(hipStreamCreate(&side_[i]));
+            HIPCHK(hipEventCreateWithFlags(&join_ev_[i], hipEventDisableTiming));
+        }
+        HIPCHK(hipEventCreateWithFlags(&fork_ev_, hipEventDisableTiming));
         set_stream(stream);
         const Mesh &m = h.mesh;
         const Octree &o = h.oct;
@@ -220,6 +225,14 @@ class DeviceBodyT final : public DeviceBody {
 
     ~DeviceBodyT() override {
         clear_graphs();
+        for (int i = 0; i < 2; ++i) {
+            if (side_[i]) {
+                (void)hipStreamSynchronize(side_[i]);
+                (void)hipStreamDestroy(side_[i]);
+            }
+            if (join_ev_[i]) (void)hipEventDestroy(join_ev_[i]);
+        }
+        if (fork_ev_) (void)hipEventDestroy(fork_ev_);
         if (own_stream_) {
             (void)hipStreamSynchronize(own_stream_);
             (void)hipStreamDestroy(own_stream_);
@@ -491,51 +504,36 @@ class DeviceBodyT final : public DeviceBody {
         }
     }
 
-    void matvec_internal(const cx<T> *x, cx<T> *y, int R, int parts) {
-        const int64_t NR = (int64_t)2 * ne_ * R;
-        mark(0);
-        if (parts & SFMM_PART_NEAR) {
-            launch_near<false>(R, x, y, nullptr, cx<T>{0, 0}, 1);
-        } else {
-            k_zero<T><<<nblocks(NR), WG, 0, stream_>>>(y, NR);
-            LAUNCHCHK();
-        }
-        mark(1);
-        if ((parts & SFMM_PART_FAR) && f_ >= 2) {
-            const int f = f_;
-            for (Reg &G : regs_) {
-                if constexpr (std::is_same<T, float>::value) {
-                    if (plan_.agg_mma && R >= MMA_MIN_R) {
-                        aggregate_mma(G, R, x);
-                        continue;
-                    }
-                }
-                const int ech = std::max(1, 2048 / R);
-                const int bs = (int)std::min<int64_t>(1024, (((int64_t)G.K[f] * R + 63) / 64) * 64);
-                const size_t shm = (size_t)2 * ech * R * sizeof(cx<T>);
-                k_aggregate<T><<<G.nbf, bs, shm, stream_>>>(G.K[f], R, ech, G.edge_ptr, G.edge_pos, G.edge_sign, G.tx,
-                                                           G.et, x, G.S[f]);
-                LAUNCHCHK();
+  private:
+    struct Reg;
+
+  public:
+    void aggregate_region(Reg &G, int R, const cx<T> *x) {
+        const int f = f_;
+        if constexpr (std::is_same<T, float>::value) {
+            if (plan_.agg_mma && R >= MMA_MIN_R) {
+                aggregate_mma(G, R, x);
+                return;
             }
-            mark(2);
-            for (Reg &G : regs_)
-                for (int l = f; l >= 3; --l) upward(G, l, R);
-            mark(3);
-            for (Reg &G : regs_)
-                for (int l = 2; l <= f; ++l) translate(G, l, R);
-            mark(4);
-            for (Reg &G : regs_)
-                for (int l = 3; l <= f; ++l) downward(G, l, R);
-            mark(5);
-            for (Reg &G : regs_) {
-                if constexpr (std::is_same<T, float>::value) {
-                    if (plan_.agg_mma && R >= MMA_MIN_R) {
-                        receive_mma(G, R, y);
-                        continue;
-                    }
-                }
-                const int rt = pick_tile(R, {8, 4, 2, 1}, [](int) { return true; });
-                dim3 grid(G.nbf, R / rt);
+        }
+        const int ech = std::max(1, 2048 / R);
+        const int bs = (int)std::min<int64_t>(1024, (((int64_t)G.K[f] * R + 63) / 64) * 64);
+        const size_t shm = (size_t)2 * ech * R * sizeof(cx<T>);
+        k_aggregate<T><<<G.nbf, bs, shm, stream_>>>(G.K[f], R, ech, G.edge_ptr, G.edge_pos, G.edge_sign, G.tx, G.et, x,
+                                                   G.S[f]);
+        LAUNCHCHK();
+    }
+
+    void receive_region(Reg &G, int R, cx<T> *y) {
+        const int f = f_;
+        if constexpr (std::is_same<T, float>::value) {
+            if (plan_.agg_mma && R >= MMA_MIN_R) {
+                receive_mma(G, R, y);
+                return;
+            }
+        }
+        const int rt = pick_tile(R, {8, 4, 2, 1}, [](int) { return true; });
+        dim3 grid(G.nbf, R / rt);
 #define SFMM_RECV(RT_)                                                                                           \
     if (G.lossy)                                                                                                 \
         k_receive<T, RT_, true><<<grid, WG, 0, stream_>>>(G.K[f], R, G.edge_ptr, G.edge_pos, G.edge_sign, G.tx,  \
@@ -543,27 +541,82 @@ class DeviceBodyT final : public DeviceBody {
     else                                                                                                         \
         k_receive<T, RT_, false><<<grid, WG, 0, stream_>>>(G.K[f], R, G.edge_ptr, G.edge_pos, G.edge_sign, G.tx, \
                                                           nullptr, G.inv_et, G.G[f], y)
-                if (rt == 8) SFMM_RECV(8);
-                else if (rt == 4) SFMM_RECV(4);
-                else if (rt == 2) SFMM_RECV(2);
-                else SFMM_RECV(1);
+        if (rt == 8) SFMM_RECV(8);
+        else if (rt == 4) SFMM_RECV(4);
+        else if (rt == 2) SFMM_RECV(2);
+        else SFMM_RECV(1);
 #undef SFMM_RECV
-                LAUNCHCHK();
-            }
-        } else {
-            mark(2);
-            mark(3);
-            mark(4);
-            mark(5);
-        }
-        mark(6);
-        if (profiling_) collect_matvec(R);
+        LAUNCHCHK();
     }
 
-  private:
-    struct Reg;
+    // y = Z x.  Stage profiling runs the stages one after another on the
+    // library stream; otherwise the regions' far-field chains (aggregation,
+    // upward pass, translation, downward pass) run on two side streams,
+    // concurrently with each other and with the near product, and join
+    // before the receive steps (which both add into y) on the library stream.
+    void matvec_internal(const cx<T> *x, cx<T> *y, int R, int parts) {
+        const int64_t NR = (int64_t)2 * ne_ * R;
+        const bool far = (parts & SFMM_PART_FAR) && f_ >= 2;
+        auto near = [&] {
+            if (parts & SFMM_PART_NEAR) {
+                launch_near<false>(R, x, y, nullptr, cx<T>{0, 0}, 1);
+            } else {
+                k_zero<T><<<nblocks(NR), WG, 0, stream_>>>(y, NR);
+                LAUNCHCHK();
+            }
+        };
+        if (profiling_ || !far) {
+            mark(0);
+            near();
+            mark(1);
+            if (far) {
+                for (Reg &G : regs_) aggregate_region(G, R, x);
+                mark(2);
+                for (Reg &G : regs_)
+                    for (int l = f_; l >= 3; --l) upward(G, l, R);
+                mark(3);
+                for (Reg &G : regs_)
+                    for (int l = 2; l <= f_; ++l) translate(G, l, R);
+                mark(4);
+                for (Reg &G : regs_)
+                    for (int l = 3; l <= f_; ++l) downward(G, l, R);
+                mark(5);
+                for (Reg &G : regs_) receive_region(G, R, y);
+            } else {
+                mark(2);
+                mark(3);
+                mark(4);
+                mark(5);
+            }
+            mark(6);
+            if (profiling_) collect_matvec(R);
+            return;
+        }
+        const hipStream_t main = stream_;
+        struct Restore {
+            hipStream_t &s, v;
+            ~Restore() { s = v; }
+        } restore{stream_, main};
+        HIPCHK(hipEventRecord(fork_ev_, main));
+        const int nside = std::min<int>(2, (int)regs_.size());
+        for (int i = 0; i < nside; ++i) HIPCHK(hipStreamWaitEvent(side_[i], fork_ev_, 0));
+        for (size_t i = 0; i < regs_.size(); ++i) {
+            stream_ = side_[i % 2];
+            Reg &G = regs_[i];
+            aggregate_region(G, R, x);
+            for (int l = f_; l >= 3; --l) upward(G, l, R);
+            for (int l = 2; l <= f_; ++l) translate(G, l, R);
+            for (int l = 3; l <= f_; ++l) downward(G, l, R);
+        }
+        stream_ = main;
+        near();
+        for (int i = 0; i < nside; ++i) {
+            HIPCHK(hipEventRecord(join_ev_[i], side_[i]));
+            HIPCHK(hipStreamWaitEvent(main, join_ev_[i], 0));
+        }
+        for (Reg &G : regs_) receive_region(G, R, y);
+    }
 
-  public:
     // Sibling groups for k_translate_grp: boxes sharing a parent key, the union
     // of their interaction lists as candidates, and per (candidate, octant)
     // the translation offset id or -1 when the pair is not in that list.
@@ -1321,6 +1374,8 @@ class DeviceBodyT final : public DeviceBody {
     Plan plan_{};
     std::map<int, Plan> plans_;
     hipStream_t own_stream_ = nullptr;
+    hipStream_t side_[2] = {nullptr, nullptr};   // far-field chains of the regions
+    hipEvent_t fork_ev_ = nullptr, join_ev_[2] = {nullptr, nullptr};
     std::map<std::pair<int, int>, hipGraphExec_t> gexec_;
     int ntiles_ = 0;
     int64_t nsteps_ = 0;
