@@ -284,13 +284,31 @@ sfmm_status sfmm_near_rows(const sfmm_ctx *ctx, int32_t body, int32_t n_rows, co
  * (0 <= r < n_regions, up to 8) trunc[r*16 + l] = truncation order at level l. */
 sfmm_status sfmm_describe(const sfmm_ctx *ctx, int32_t body, int64_t *info, int32_t *trunc);
 
+/* Algorithmic HBM bytes of one single-RHS product y = Z x of a body at the
+ * context's storage precision: the least traffic of this stored-table form,
+ * every array read or written once per use.  bytes[0] near-field values (three
+ * complex numbers per edge pair, the PMCHWT 2x2 block [[A, -B], [B, C]]) and
+ * column indices; bytes[1] x read and y written once; bytes[2] radiation
+ * patterns read for aggregation and again for receiving (Sec. 3: the
+ * aggregation and disaggregation steps of the MLFMM); bytes[3] level arrays,
+ * outgoing and incoming patterns each written and read once; bytes[4]
+ * translation operators for the offsets in use; bytes[5] interpolation and
+ * shift tables; bytes[6] the total; bytes[7] = 0.  `bytes` is a caller array
+ * of 8 int64. */
+sfmm_status sfmm_product_bytes(const sfmm_ctx *ctx, int32_t body, int64_t *bytes);
+
 /* Average GPU time in milliseconds of each stage over the products and
  * preconditioner applications since the last reset, measured with HIP events
  * on the context's stream: t[0] near product, t[1] aggregation, t[2] upward
  * interpolation, t[3] translation, t[4] downward anterpolation, t[5] receive,
  * t[6] ILU(0) solves, t[7] whole product; n[i] = number of samples.
  * Stage timing is enabled only between sfmm_profile(ctx, 1, ...) and
- * sfmm_profile(ctx, 0, ...); enabling resets the accumulators. */
+ * sfmm_profile(ctx, 0, ...); enabling resets the accumulators.  With
+ * enable = 1 the stages of a product run one after another on the context's
+ * stream (each stage timed alone); with enable = 2 products keep their
+ * concurrent form (far-field chains on side streams beside the near product)
+ * and only t[0] (the near product as it runs beside them) and t[7] are
+ * recorded.  Either way products run directly, not from captured graphs. */
 sfmm_status sfmm_profile(sfmm_ctx *ctx, int32_t enable, double *t, int64_t *n);
 
 #ifdef __cplusplus

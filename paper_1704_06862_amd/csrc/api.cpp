@@ -423,6 +423,45 @@ sfmm_status sfmm_describe(const sfmm_ctx *ctx, int32_t body, int64_t *info, int3
     });
 }
 
+sfmm_status sfmm_product_bytes(const sfmm_ctx *ctx, int32_t body, int64_t *bytes) {
+    return guarded(const_cast<sfmm_ctx *>(ctx), [&] {
+        if (!bytes) throw Error(SFMM_E_INVALID_ARG, "NULL output");
+        const BodyHost &b = body_of(ctx, body);
+        const int64_t cb = ctx->opt.precision == SFMM_PREC_FP64 ? 16 : 8;   // one stored complex number
+        const int64_t ne = b.mesh.ne;
+        int64_t col = 0;
+        for (int i = 0; i < b.oct.nb; ++i) col += b.near.col_ptr[i + 1] - b.near.col_ptr[i];
+        int64_t nearb = 3 * cb * b.oct.near_pairs + 4 * col, xy = 2 * (2 * ne) * cb, pat = 0, lev = 0, trans = 0,
+                interp = 0;
+        for (size_t r = 0; r < b.oct.regions.size(); ++r) {
+            const RegionTree &rt = b.oct.regions[r];
+            const RegionTables &tb = b.tables[r];
+            pat += cb * (int64_t)(tb.tx.size() + (tb.lossy ? tb.rx.size() : tb.tx.size()));
+            for (int l = 2; l <= b.oct.f; ++l) {
+                const LevelBoxes &lv = rt.lev[l];
+                const int64_t K = tb.samp[l].K;
+                lev += 4 * cb * 2 * K * (int64_t)lv.key.size();
+                std::vector<char> used(343, 0);
+                for (int o : lv.il_off) used[o] = 1;
+                int64_t nu = 0;
+                for (char u : used) nu += u;
+                trans += cb * K * nu;
+                if (l >= 3)
+                    interp += 4 * (int64_t)(tb.ipA[l].size() + tb.ipB[l].size() + tb.ipD[l].size()) +
+                              cb * (int64_t)(tb.shift_up[l].size() + tb.shift_dn[l].size());
+            }
+        }
+        bytes[0] = nearb;
+        bytes[1] = xy;
+        bytes[2] = pat;
+        bytes[3] = lev;
+        bytes[4] = trans;
+        bytes[5] = interp;
+        bytes[6] = nearb + xy + pat + lev + trans + interp;
+        bytes[7] = 0;
+    });
+}
+
 sfmm_status sfmm_profile(sfmm_ctx *ctx, int32_t enable, double *t, int64_t *n) {
     return guarded(ctx, [&] {
         if (!ctx) throw Error(SFMM_E_INVALID_ARG, "NULL context");
@@ -434,7 +473,7 @@ sfmm_status sfmm_profile(sfmm_ctx *ctx, int32_t enable, double *t, int64_t *n) {
                 acc.ms[i] += s.ms[i];
                 acc.n[i] += s.n[i];
             }
-            d->profile(enable != 0);
+            d->profile(enable == 2 ? 2 : enable != 0 ? 1 : 0);
         }
         for (int i = 0; i < 8; ++i) {
             if (t) t[i] = acc.n[i] ? acc.ms[i] / acc.n[i] : 0.0;

@@ -290,9 +290,9 @@ class DeviceBodyT final : public DeviceBody {
         }
         HIPCHK(hipGraphLaunch(it->second, stream_));
     }
-    void profile(bool enable) override {
-        profiling_ = enable;
-        if (enable) times_ = StageTimes();
+    void profile(int mode) override {
+        profiling_ = mode;
+        if (mode) times_ = StageTimes();
     }
     StageTimes times() const override { return times_; }
     int64_t device_bytes() const override { return bytes_; }
@@ -304,11 +304,13 @@ class DeviceBodyT final : public DeviceBody {
     // (one stage at a time, the others at their current best).
     struct Plan {
         bool near_mma = false, agg_mma = false, interp_mma = false, trans_grp = false;
+        bool interp_split = false;   // one RHS: theta and phi stages as separate whole-level launches
     };
     static Plan default_plan(int R) {
         Plan p;
         p.near_mma = p.agg_mma = p.interp_mma = R >= MMA_MIN_R && std::is_same<T, float>::value;
         p.trans_grp = R >= TRANS_GRP_MIN_R;
+        p.interp_split = R == 1;
         return p;
     }
     void use_plan(int R) {
@@ -337,17 +339,21 @@ class DeviceBodyT final : public DeviceBody {
     }
     Plan tune(int R) {
         ensure_batch(R);
-        const bool prof = profiling_;
-        profiling_ = false;
+        const int prof = profiling_;
+        profiling_ = 0;
         k_zero<T><<<nblocks((int64_t)2 * ne_ * R), WG, 0, stream_>>>(xi_, (int64_t)2 * ne_ * R);
         LAUNCHCHK();
         Plan best = default_plan(R);
         plan_ = best;
         float tbest = time_product(R);
-        bool Plan::*fields[4] = {&Plan::near_mma, &Plan::agg_mma, &Plan::interp_mma, &Plan::trans_grp};
+        bool Plan::*fields[5] = {&Plan::near_mma, &Plan::agg_mma, &Plan::interp_mma, &Plan::trans_grp,
+                                 &Plan::interp_split};
         for (bool Plan::*f : fields) {
-            if (f != &Plan::trans_grp && !std::is_same<T, float>::value) continue;
-            if (f != &Plan::trans_grp && R < MMA_MIN_R) continue;
+            if (f == &Plan::interp_split) {
+                if (R != 1) continue;
+            } else if (f != &Plan::trans_grp) {
+                if (!std::is_same<T, float>::value || R < MMA_MIN_R) continue;
+            }
             plan_ = best;
             plan_.*f = !(best.*f);
             const float t = time_product(R);
@@ -361,7 +367,8 @@ class DeviceBodyT final : public DeviceBody {
             std::fprintf(stderr, "sfmm autotune R=%d: near %s, aggregate/receive %s, interpolation %s, translation %s "
                                  "(%.3f ms)\n",
                          R, best.near_mma ? "mfma" : "vector", best.agg_mma ? "mfma" : "vector",
-                         best.interp_mma ? "mfma" : "vector", best.trans_grp ? "grouped" : "flat", tbest);
+                         best.interp_mma ? "mfma" : best.interp_split ? "vector, split stages" : "vector",
+                         best.trans_grp ? "grouped" : "flat", tbest);
         return best;
     }
 
@@ -532,6 +539,17 @@ class DeviceBodyT final : public DeviceBody {
                 return;
             }
         }
+        if (R == 1 && G.K[f] % 2 == 0 && (size_t)2 * G.K[f] * sizeof(cx<T>) <= LDS_LIMIT) {
+            const size_t shm = (size_t)2 * G.K[f] * sizeof(cx<T>);
+            if (G.lossy)
+                k_receive1<T, true><<<G.nbf, WG, shm, stream_>>>(G.K[f], G.edge_ptr, G.edge_pos, G.edge_sign, G.tx,
+                                                                 G.rx, G.inv_et, G.G[f], y);
+            else
+                k_receive1<T, false><<<G.nbf, WG, shm, stream_>>>(G.K[f], G.edge_ptr, G.edge_pos, G.edge_sign, G.tx,
+                                                                  nullptr, G.inv_et, G.G[f], y);
+            LAUNCHCHK();
+            return;
+        }
         const int rt = pick_tile(R, {8, 4, 2, 1}, [](int) { return true; });
         dim3 grid(G.nbf, R / rt);
 #define SFMM_RECV(RT_)                                                                                           \
@@ -565,7 +583,7 @@ class DeviceBodyT final : public DeviceBody {
                 LAUNCHCHK();
             }
         };
-        if (profiling_ || !far) {
+        if (profiling_ == 1 || !far) {
             mark(0);
             near();
             mark(1);
@@ -575,8 +593,7 @@ class DeviceBodyT final : public DeviceBody {
                 for (Reg &G : regs_)
                     for (int l = f_; l >= 3; --l) upward(G, l, R);
                 mark(3);
-                for (Reg &G : regs_)
-                    for (int l = 2; l <= f_; ++l) translate(G, l, R);
+                for (Reg &G : regs_) translate_levels(G, R);
                 mark(4);
                 for (Reg &G : regs_)
                     for (int l = 3; l <= f_; ++l) downward(G, l, R);
@@ -597,6 +614,7 @@ class DeviceBodyT final : public DeviceBody {
             hipStream_t &s, v;
             ~Restore() { s = v; }
         } restore{stream_, main};
+        mark(0);
         HIPCHK(hipEventRecord(fork_ev_, main));
         const int nside = std::min<int>(2, (int)regs_.size());
         for (int i = 0; i < nside; ++i) HIPCHK(hipStreamWaitEvent(side_[i], fork_ev_, 0));
@@ -605,16 +623,20 @@ class DeviceBodyT final : public DeviceBody {
             Reg &G = regs_[i];
             aggregate_region(G, R, x);
             for (int l = f_; l >= 3; --l) upward(G, l, R);
-            for (int l = 2; l <= f_; ++l) translate(G, l, R);
+            translate_levels(G, R);
             for (int l = 3; l <= f_; ++l) downward(G, l, R);
         }
         stream_ = main;
+        mark(1);
         near();
+        mark(2);
         for (int i = 0; i < nside; ++i) {
             HIPCHK(hipEventRecord(join_ev_[i], side_[i]));
             HIPCHK(hipStreamWaitEvent(main, join_ev_[i], 0));
         }
         for (Reg &G : regs_) receive_region(G, R, y);
+        mark(6);
+        if (profiling_) collect_concurrent(R);
     }
 
     // Sibling groups for k_translate_grp: boxes sharing a parent key, the union
@@ -699,6 +721,13 @@ class DeviceBodyT final : public DeviceBody {
     }
 
     // matrix-core interpolation: sizes within 4 tiles of 16 (theta pairs and phi)
+    // single-RHS split stages: the matrices of the transition l -> l - 1 fit in LDS
+    bool split_ok(const Reg &G, int l, int R) const {
+        const size_t th = (size_t)2 * G.nth[l - 1] * G.nth[l] * sizeof(T), ph = (size_t)G.nph[l - 1] * G.nph[l] * sizeof(T);
+        return plan_.interp_split && R == 1 && G.tmp && G.nph[l] % 2 == 0 && G.nph[l - 1] % 2 == 0 &&
+               th <= LDS_LIMIT && ph <= LDS_LIMIT;
+    }
+
     bool interp_mma_ok(const Reg &G, int l, int R) const {
         return plan_.interp_mma && R >= MMA_MIN_R && G.Dup[l] && 2 * G.nth[l - 1] <= 64 && 2 * G.nth[l] <= 64 && G.nph[l - 1] <= 64 &&
                G.nph[l] <= 64;
@@ -738,6 +767,37 @@ class DeviceBodyT final : public DeviceBody {
 #undef SFMM_DNM
     }
 
+    // all translation levels of a region
+    void translate_levels(Reg &G, int R) {
+        if (R == 1 && !plan_.trans_grp && f_ - 1 <= TRANS_MAXLEV) {
+            TransLevels<T> tl{};
+            tl.nlev = f_ - 1;
+            int nblk = 0;
+            for (int i = 0; i < tl.nlev; ++i) {
+                const int l = i + 2;
+                tl.blk0[i] = nblk;
+                tl.K[i] = G.K[l];
+                tl.nkc[i] = (G.K[l] + 63) / 64;
+                tl.il_ptr[i] = G.il_ptr[l];
+                tl.il_src[i] = G.il_src[l];
+                tl.il_off[i] = G.il_off[l];
+                tl.trans[i] = G.trans[l];
+                tl.S[i] = G.S[l];
+                tl.G[i] = G.G[l];
+                nblk += G.nbox[l] * tl.nkc[i];
+            }
+            tl.blk0[tl.nlev] = nblk;
+            tl.nblk = nblk;
+            if (nblk > 0) {
+                const unsigned grid = (unsigned)((nblk + 7) / 8 * 8);
+                k_translate1<T><<<grid, WG, 0, stream_>>>(tl);
+                LAUNCHCHK();
+            }
+            return;
+        }
+        for (int l = 2; l <= f_; ++l) translate(G, l, R);
+    }
+
     void translate(Reg &G, int l, int R) {
         if (!plan_.trans_grp) {
             k_translate<T><<<nblocks((int64_t)G.nbox[l] * G.K[l] * R), WG, 0, stream_>>>(
@@ -770,6 +830,18 @@ class DeviceBodyT final : public DeviceBody {
                 upward_mma(G, l, R);
                 return;
             }
+        }
+        if (split_ok(G, l, R)) {
+            const int64_t n1 = (int64_t)G.nbox[l] * 2 * ((nth_p + 1) / 2) * (nph_c / 2);
+            k_up_theta1<T><<<nblocks(n1), WG, (size_t)2 * nth_p * nth_c * sizeof(T), stream_>>>(
+                G.nbox[l] * 2, nth_c, nph_c, nth_p, G.ipA[l], G.ipB[l], G.S[l], G.tmp);
+            LAUNCHCHK();
+            const int64_t n2 = (int64_t)G.nbox[l - 1] * 2 * nth_p * (nph_p / 2);
+            k_up_phi1<T><<<nblocks(n2), WG, (size_t)nph_c * nph_p * sizeof(T), stream_>>>(
+                G.nbox[l - 1], nth_p, nph_p, nph_c, G.ipDt[l], G.child_ptr[l - 1], G.child_idx[l - 1], G.slot[l],
+                G.sup[l], G.tmp, G.S[l - 1]);
+            LAUNCHCHK();
+            return;
         }
         const int rt = pick_tile(R, {4, 2, 1}, [&](int t) {
             return ((size_t)G.K[l] + (size_t)UPR * nph_c) * t * sizeof(cx<T>) <= LDS_LIMIT &&
@@ -808,6 +880,17 @@ class DeviceBodyT final : public DeviceBody {
                 downward_mma(G, l, R);
                 return;
             }
+        }
+        if (split_ok(G, l, R)) {
+            const int64_t n1 = (int64_t)G.nbox[l] * 2 * nth_p * (nph_c / 2);
+            k_dn_phi1<T><<<nblocks(n1), WG, (size_t)nph_p * nph_c * sizeof(T), stream_>>>(
+                G.nbox[l], nth_p, nph_p, nph_c, G.ipD[l], G.parent[l], G.slot[l], G.sdn[l], G.G[l - 1], G.tmp);
+            LAUNCHCHK();
+            const int64_t n2 = (int64_t)G.nbox[l] * 2 * ((nth_c + 1) / 2) * (nph_c / 2);
+            k_dn_theta1<T><<<nblocks(n2), WG, (size_t)2 * nth_p * nth_c * sizeof(T), stream_>>>(
+                G.nbox[l] * 2, nth_c, nph_c, nth_p, G.ipA[l], G.ipB[l], G.tmp, G.G[l]);
+            LAUNCHCHK();
+            return;
         }
         const int rt = pick_tile(R, {4, 2, 1}, [&](int t) {
             return ((size_t)G.K[l - 1] + (size_t)nth_p * nph_c) * t * sizeof(cx<T>) <= LDS_LIMIT;
@@ -1345,6 +1428,18 @@ class DeviceBodyT final : public DeviceBody {
     void mark(int i) {
         if (profiling_) HIPCHK(hipEventRecord(evs_[i], stream_));
     }
+    // concurrent product: the near kernel as it runs beside the far-field
+    // chains (events around it on the library stream) and the whole product
+    void collect_concurrent(int R) {
+        HIPCHK(hipEventSynchronize(evs_[6]));
+        float ms;
+        HIPCHK(hipEventElapsedTime(&ms, evs_[1], evs_[2]));
+        times_.ms[0] += ms / R;
+        times_.n[0] += 1;
+        HIPCHK(hipEventElapsedTime(&ms, evs_[0], evs_[6]));
+        times_.ms[7] += ms / R;
+        times_.n[7] += 1;
+    }
     void collect_matvec(int R) {
         HIPCHK(hipEventSynchronize(evs_[6]));
         float ms;
@@ -1401,7 +1496,7 @@ class DeviceBodyT final : public DeviceBody {
     int *dact_ = nullptr, *dcnt_ = nullptr;
     std::vector<void *> allocs_, batch_allocs_, krylov_allocs_;
     int64_t bytes_ = 0;
-    bool profiling_ = false;
+    int profiling_ = 0;   // 0 off, 1 stage by stage, 2 concurrent product (near and total)
     hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
     hipEvent_t evs_[7] = {nullptr};
     StageTimes times_;

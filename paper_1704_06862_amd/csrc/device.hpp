@@ -40,7 +40,7 @@ class DeviceBody {
     // or a stream of the body's own when the context has none)
     virtual void *stream() const = 0;
     virtual void stream_synchronize() = 0;
-    virtual void profile(bool enable) = 0;
+    virtual void profile(int mode) = 0;
     virtual StageTimes times() const = 0;
     virtual int64_t device_bytes() const = 0;
 };

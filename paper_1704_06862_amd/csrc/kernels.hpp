@@ -622,6 +622,185 @@ __global__ void k_dn_theta(int R, int nchild, int nth_c, int nph_c, int nth_p, c
 }
 
 // ---------------------------------------------------------------------------
+// One right-hand side: the same two stages as the element-wise kernels above,
+// register-blocked, with the interpolation matrices staged in LDS.  In the
+// theta stages a thread computes two theta rows by the azimuthal pair
+// (j, j + h), h = nph_c / 2 (the two halves of the paired matrix
+// [[A, B], [B, A]] share every load); in the phi stages a thread computes two
+// adjacent azimuths of one theta row.
+
+// tmp[cc][I][j] = sum_i A/B[I][i] S[cc][i][j or j +- h], cc = 2 child + comp
+template <typename T>
+__global__ void __launch_bounds__(WG) k_up_theta1(int ncc, int nth_c, int nph_c, int nth_p, const T *__restrict__ A,
+                                                  const T *__restrict__ B, const cx<T> *__restrict__ S,
+                                                  cx<T> *__restrict__ tmp) {
+    extern __shared__ unsigned char lds_raw[];
+    T *As = reinterpret_cast<T *>(lds_raw);   // [nth_p][nth_c]
+    T *Bs = As + nth_p * nth_c;
+    for (int t = threadIdx.x; t < nth_p * nth_c; t += WG) {
+        As[t] = A[t];
+        Bs[t] = B[t];
+    }
+    __syncthreads();
+    const int h = nph_c / 2, np2 = (nth_p + 1) / 2;
+    const int64_t id = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (id >= (int64_t)ncc * np2 * h) return;
+    const int j = id % h;
+    const int I = 2 * (int)((id / h) % np2);
+    const int64_t cc = id / ((int64_t)h * np2);
+    const bool two = I + 1 < nth_p;
+    const int I1 = two ? I + 1 : I;
+    const cx<T> *f = S + cc * nth_c * nph_c;
+    cx<T> a0 = {0, 0}, a1 = {0, 0}, b0 = {0, 0}, b1 = {0, 0};   // rows I, I1; azimuths j, j + h
+    for (int i = 0; i < nth_c; ++i) {
+        const T p0 = As[I * nth_c + i], q0 = Bs[I * nth_c + i];
+        const T p1 = As[I1 * nth_c + i], q1 = Bs[I1 * nth_c + i];
+        const cx<T> f1 = f[i * nph_c + j], f2 = f[i * nph_c + j + h];
+        a0.x += p0 * f1.x + q0 * f2.x;
+        a0.y += p0 * f1.y + q0 * f2.y;
+        b0.x += q0 * f1.x + p0 * f2.x;
+        b0.y += q0 * f1.y + p0 * f2.y;
+        a1.x += p1 * f1.x + q1 * f2.x;
+        a1.y += p1 * f1.y + q1 * f2.y;
+        b1.x += q1 * f1.x + p1 * f2.x;
+        b1.y += q1 * f1.y + p1 * f2.y;
+    }
+    cx<T> *o = tmp + (cc * nth_p + I) * nph_c;
+    o[j] = a0;
+    o[j + h] = b0;
+    if (two) {
+        o[nph_c + j] = a1;
+        o[nph_c + j + h] = b1;
+    }
+}
+
+// Sp[P][comp][I][J] = sum_children shift[slot][I][J] sum_j Dt[j][J] tmp[c][comp][I][j]
+template <typename T>
+__global__ void __launch_bounds__(WG) k_up_phi1(int nparent, int nth_p, int nph_p, int nph_c,
+                                                const T *__restrict__ Dt, const int *__restrict__ child_ptr,
+                                                const int *__restrict__ child_idx, const int *__restrict__ child_slot,
+                                                const cx<T> *__restrict__ shift, const cx<T> *__restrict__ tmp,
+                                                cx<T> *__restrict__ Sp) {
+    extern __shared__ unsigned char lds_raw[];
+    T *Ds = reinterpret_cast<T *>(lds_raw);   // [nph_c][nph_p]
+    for (int t = threadIdx.x; t < nph_c * nph_p; t += WG) Ds[t] = Dt[t];
+    __syncthreads();
+    const int Kp = nth_p * nph_p, hp = nph_p / 2;
+    const int64_t id = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (id >= (int64_t)nparent * 2 * nth_p * hp) return;
+    const int J = 2 * (int)(id % hp);
+    int64_t q = id / hp;
+    const int I = q % nth_p;
+    q /= nth_p;
+    const int comp = q % 2;
+    const int P = q / 2;
+    cx<T> o0 = {0, 0}, o1 = {0, 0};
+    for (int qq = child_ptr[P]; qq < child_ptr[P + 1]; ++qq) {
+        const int c = child_idx[qq];
+        const cx<T> *g = tmp + (((int64_t)c * 2 + comp) * nth_p + I) * nph_c;
+        cx<T> v0 = {0, 0}, v1 = {0, 0};
+        for (int j = 0; j < nph_c; ++j) {
+            const T d0 = Ds[j * nph_p + J], d1 = Ds[j * nph_p + J + 1];
+            const cx<T> t = g[j];
+            v0.x += d0 * t.x;
+            v0.y += d0 * t.y;
+            v1.x += d1 * t.x;
+            v1.y += d1 * t.y;
+        }
+        const cx<T> *sh = shift + (size_t)child_slot[c] * Kp + I * nph_p + J;
+        cfma(o0, sh[0], v0);
+        cfma(o1, sh[1], v1);
+    }
+    cx<T> *out = Sp + ((int64_t)P * 2 + comp) * Kp + I * nph_p + J;
+    out[0] = o0;
+    out[1] = o1;
+}
+
+// tmp[c][comp][I][j] = sum_J D[J][j] shift_dn[slot][I][J] Gp[parent][comp][I][J]
+template <typename T>
+__global__ void __launch_bounds__(WG) k_dn_phi1(int nchild, int nth_p, int nph_p, int nph_c, const T *__restrict__ D,
+                                                const int *__restrict__ parent, const int *__restrict__ child_slot,
+                                                const cx<T> *__restrict__ shift, const cx<T> *__restrict__ Gp,
+                                                cx<T> *__restrict__ tmp) {
+    extern __shared__ unsigned char lds_raw[];
+    T *Ds = reinterpret_cast<T *>(lds_raw);   // [nph_p][nph_c]
+    for (int t = threadIdx.x; t < nph_p * nph_c; t += WG) Ds[t] = D[t];
+    __syncthreads();
+    const int Kp = nth_p * nph_p, hc = nph_c / 2;
+    const int64_t id = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (id >= (int64_t)nchild * 2 * nth_p * hc) return;
+    const int j = 2 * (int)(id % hc);
+    int64_t q = id / hc;
+    const int I = q % nth_p;
+    q /= nth_p;
+    const int comp = q % 2;
+    const int c = q / 2;
+    const cx<T> *g = Gp + ((int64_t)parent[c] * 2 + comp) * Kp + I * nph_p;
+    const cx<T> *sh = shift + (size_t)child_slot[c] * Kp + I * nph_p;
+    cx<T> a0 = {0, 0}, a1 = {0, 0};
+    for (int J = 0; J < nph_p; ++J) {
+        const cx<T> v = cmul(sh[J], g[J]);
+        const T d0 = Ds[J * nph_c + j], d1 = Ds[J * nph_c + j + 1];
+        a0.x += d0 * v.x;
+        a0.y += d0 * v.y;
+        a1.x += d1 * v.x;
+        a1.y += d1 * v.y;
+    }
+    cx<T> *o = tmp + (((int64_t)c * 2 + comp) * nth_p + I) * nph_c + j;
+    o[0] = a0;
+    o[1] = a1;
+}
+
+// Gc[cc][i][j] += sum_I A/B[I][i] tmp[cc][I][j or j +- h]
+template <typename T>
+__global__ void __launch_bounds__(WG) k_dn_theta1(int ncc, int nth_c, int nph_c, int nth_p, const T *__restrict__ A,
+                                                  const T *__restrict__ B, const cx<T> *__restrict__ tmp,
+                                                  cx<T> *__restrict__ Gc) {
+    extern __shared__ unsigned char lds_raw[];
+    T *As = reinterpret_cast<T *>(lds_raw);   // [nth_p][nth_c]
+    T *Bs = As + nth_p * nth_c;
+    for (int t = threadIdx.x; t < nth_p * nth_c; t += WG) {
+        As[t] = A[t];
+        Bs[t] = B[t];
+    }
+    __syncthreads();
+    const int h = nph_c / 2, nc2 = (nth_c + 1) / 2;
+    const int64_t id = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (id >= (int64_t)ncc * nc2 * h) return;
+    const int j = id % h;
+    const int i = 2 * (int)((id / h) % nc2);
+    const int64_t cc = id / ((int64_t)h * nc2);
+    const bool two = i + 1 < nth_c;
+    const int i1 = two ? i + 1 : i;
+    const cx<T> *g = tmp + cc * nth_p * nph_c;
+    cx<T> a0 = {0, 0}, a1 = {0, 0}, b0 = {0, 0}, b1 = {0, 0};   // rows i, i1; azimuths j, j + h
+    for (int I = 0; I < nth_p; ++I) {
+        const T p0 = As[I * nth_c + i], q0 = Bs[I * nth_c + i];
+        const T p1 = As[I * nth_c + i1], q1 = Bs[I * nth_c + i1];
+        const cx<T> g1 = g[I * nph_c + j], g2 = g[I * nph_c + j + h];
+        a0.x += p0 * g1.x + q0 * g2.x;
+        a0.y += p0 * g1.y + q0 * g2.y;
+        b0.x += q0 * g1.x + p0 * g2.x;
+        b0.y += q0 * g1.y + p0 * g2.y;
+        a1.x += p1 * g1.x + q1 * g2.x;
+        a1.y += p1 * g1.y + q1 * g2.y;
+        b1.x += q1 * g1.x + p1 * g2.x;
+        b1.y += q1 * g1.y + p1 * g2.y;
+    }
+    cx<T> *o = Gc + (cc * nth_c + i) * nph_c;
+    cx<T> v = o[j];
+    o[j] = {v.x + a0.x, v.y + a0.y};
+    v = o[j + h];
+    o[j + h] = {v.x + b0.x, v.y + b0.y};
+    if (two) {
+        v = o[nph_c + j];
+        o[nph_c + j] = {v.x + a1.x, v.y + a1.y};
+        v = o[nph_c + j + h];
+        o[nph_c + j + h] = {v.x + b1.x, v.y + b1.y};
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Diagonal translation over the interaction lists: G_b = sum T(X_bb') S_b'.
 // Threads are flattened over (box, direction, rhs), rhs fastest: the R
 // threads of a direction share every translation-table load.
@@ -657,6 +836,76 @@ __global__ void __launch_bounds__(WG) k_translate(int nbox, int K, int R, const 
     }
     G[(size_t)b * 2 * KR + kr] = gt;
     G[(size_t)b * 2 * KR + KR + kr] = gp;
+}
+
+// Translation for one right-hand side, every level of a region in one launch.
+// A workgroup takes one box and 64 directions; its four wavefronts split the
+// box's interaction list (entries q = w, w + 4, ...: the source and offset ids
+// are wave-uniform scalar loads) and are summed through LDS.  Workgroups are
+// numbered so that each of the 8 XCDs (which take workgroups round-robin)
+// receives a contiguous range of boxes in Morton order, whose source patterns
+// then stay in that XCD's L2.
+constexpr int TRANS_MAXLEV = 8;
+template <typename T>
+struct TransLevels {
+    int nlev, nblk;
+    int blk0[TRANS_MAXLEV + 1];   // first workgroup of each level
+    int K[TRANS_MAXLEV], nkc[TRANS_MAXLEV];
+    const int *il_ptr[TRANS_MAXLEV], *il_src[TRANS_MAXLEV], *il_off[TRANS_MAXLEV];
+    const cx<T> *trans[TRANS_MAXLEV], *S[TRANS_MAXLEV];
+    cx<T> *G[TRANS_MAXLEV];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(WG) k_translate1(const TransLevels<T> tl) {
+    __shared__ cx<T> part[WAVES][2][64];
+    const int per = (tl.nblk + 7) / 8;
+    const int id = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (id >= tl.nblk) return;   // whole workgroup: no barrier is reached
+    int L = 0;
+    while (L + 1 < tl.nlev && id >= tl.blk0[L + 1]) ++L;
+    const int local = id - tl.blk0[L];
+    const int K = tl.K[L];
+    const int b = local / tl.nkc[L];
+    const int k = (local % tl.nkc[L]) * 64 + (threadIdx.x & 63);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int *src = tl.il_src[L], *off = tl.il_off[L];
+    const cx<T> *S = tl.S[L], *tr = tl.trans[L];
+    const int kk = k < K ? k : K - 1;   // lanes past K load a valid sample, their sums are dropped
+    cx<T> gt = {0, 0}, gp = {0, 0}, ht = {0, 0}, hp = {0, 0};
+    const int q1 = tl.il_ptr[L][b + 1];
+    int q = tl.il_ptr[L][b] + w;
+    for (; q + WAVES < q1; q += 2 * WAVES) {
+        const int s0 = __builtin_amdgcn_readfirstlane(src[q]), s1 = __builtin_amdgcn_readfirstlane(src[q + WAVES]);
+        const int o0 = __builtin_amdgcn_readfirstlane(off[q]), o1 = __builtin_amdgcn_readfirstlane(off[q + WAVES]);
+        const cx<T> t0 = tr[(size_t)o0 * K + kk], t1 = tr[(size_t)o1 * K + kk];
+        const cx<T> a0 = S[(size_t)s0 * 2 * K + kk], b0 = S[(size_t)s0 * 2 * K + K + kk];
+        const cx<T> a1 = S[(size_t)s1 * 2 * K + kk], b1 = S[(size_t)s1 * 2 * K + K + kk];
+        cfma(gt, t0, a0);
+        cfma(gp, t0, b0);
+        cfma(ht, t1, a1);
+        cfma(hp, t1, b1);
+    }
+    if (q < q1) {
+        const int s0 = __builtin_amdgcn_readfirstlane(src[q]), o0 = __builtin_amdgcn_readfirstlane(off[q]);
+        const cx<T> t0 = tr[(size_t)o0 * K + kk];
+        cfma(gt, t0, S[(size_t)s0 * 2 * K + kk]);
+        cfma(gp, t0, S[(size_t)s0 * 2 * K + K + kk]);
+    }
+    const int lane = threadIdx.x & 63;
+    part[w][0][lane] = {gt.x + ht.x, gt.y + ht.y};
+    part[w][1][lane] = {gp.x + hp.x, gp.y + hp.y};
+    __syncthreads();
+    if (threadIdx.x < 128) {
+        const int comp = threadIdx.x >> 6;
+        cx<T> v = part[0][comp][lane];
+#pragma unroll
+        for (int i = 1; i < WAVES; ++i) {
+            v.x += part[i][comp][lane].x;
+            v.y += part[i][comp][lane].y;
+        }
+        if (k < K) tl.G[L][(size_t)b * 2 * K + comp * K + k] = v;
+    }
 }
 
 // Translation for batched right-hand sides, grouped by parent: the (up to 8)
@@ -769,6 +1018,74 @@ __global__ void __launch_bounds__(WG) k_receive(int K, int R, const int *__restr
             yh.y += s * hh.y;
             y[iE] = ye;
             y[iH] = yh;
+        }
+    }
+}
+
+// Receive at the finest level for one right-hand side.  One workgroup per
+// region box with the box's incoming pattern staged in LDS; every wavefront
+// takes eight edges at a time, eight lanes per edge, each lane two adjacent
+// directions per step (one 16-byte load per pattern component for FP32), and
+// the eight partial sums of an edge are combined by three shuffles.  K is
+// even (K = 2 (L + 1)^2), so the pairs never straddle the theta/phi halves.
+template <typename T, bool LOSSY>
+__global__ void __launch_bounds__(WG) k_receive1(int K, const int *__restrict__ edge_ptr,
+                                                 const int *__restrict__ edge_pos, const int *__restrict__ edge_sign,
+                                                 const cx<T> *__restrict__ tx, const cx<T> *__restrict__ rx,
+                                                 cx<T> inv_et, const cx<T> *__restrict__ G, cx<T> *__restrict__ y) {
+    extern __shared__ unsigned char lds_raw[];
+    cx<T> *gs = reinterpret_cast<cx<T> *>(lds_raw);   // [2][K]
+    const int b = blockIdx.x;
+    const cx<T> *g = G + (size_t)b * 2 * K;
+    for (int i = threadIdx.x; i < 2 * K; i += WG) gs[i] = g[i];
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int sub = lane & 7, slot = lane >> 3;
+    const int e1 = edge_ptr[b + 1];
+    const cx<T> *tab = LOSSY ? rx : tx;
+    for (int base = edge_ptr[b] + wave * 8; base < e1; base += WAVES * 8) {
+        const int ie = base + slot;
+        cx<T> aE = {0, 0}, aH = {0, 0};
+        if (ie < e1) {
+            const cx<T> *Rp = tab + (size_t)ie * 2 * K;
+#pragma unroll 3
+            for (int k = 2 * sub; k < K; k += 16) {
+                cx<T> rt0 = Rp[k], rt1 = Rp[k + 1], rp0 = Rp[K + k], rp1 = Rp[K + k + 1];
+                if (!LOSSY) {
+                    rt0 = cconj(rt0);
+                    rt1 = cconj(rt1);
+                    rp0 = cconj(rp0);
+                    rp1 = cconj(rp1);
+                }
+                const cx<T> gt0 = gs[k], gt1 = gs[k + 1], gp0 = gs[K + k], gp1 = gs[K + k + 1];
+                cfma(aE, rt0, gt0);
+                cfma(aE, rp0, gp0);
+                cfms(aH, rt0, gp0);
+                cfma(aH, rp0, gt0);
+                cfma(aE, rt1, gt1);
+                cfma(aE, rp1, gp1);
+                cfms(aH, rt1, gp1);
+                cfma(aH, rp1, gt1);
+            }
+        }
+#pragma unroll
+        for (int m = 1; m < 8; m <<= 1) {
+            aE.x += __shfl_xor(aE.x, m, 64);
+            aE.y += __shfl_xor(aE.y, m, 64);
+            aH.x += __shfl_xor(aH.x, m, 64);
+            aH.y += __shfl_xor(aH.y, m, 64);
+        }
+        if (ie < e1 && sub == 0) {
+            const int p = edge_pos[ie];
+            const T s = (T)edge_sign[ie];
+            const cx<T> hh = cmul(aH, inv_et);
+            cx<T> ye = y[2 * p], yh = y[2 * p + 1];
+            ye.x += s * aE.x;
+            ye.y += s * aE.y;
+            yh.x += s * hh.x;
+            yh.y += s * hh.y;
+            y[2 * p] = ye;
+            y[2 * p + 1] = yh;
         }
     }
 }

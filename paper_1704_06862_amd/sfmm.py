@@ -26,7 +26,7 @@ PRECOND_ILU0, PRECOND_NONE, PRECOND_BLOCK_JACOBI, PRECOND_POLY = 0, 1, 2, 3
 
 EXPORTED = ["sfmm_default_options", "sfmm_setup", "sfmm_destroy", "sfmm_last_error", "sfmm_set_stream",
             "sfmm_num_unknowns", "sfmm_edges", "sfmm_matvec", "sfmm_precond", "sfmm_planewave_rhs",
-            "sfmm_solve", "sfmm_rcs", "sfmm_near_rows", "sfmm_describe", "sfmm_profile",
+            "sfmm_solve", "sfmm_rcs", "sfmm_near_rows", "sfmm_describe", "sfmm_product_bytes", "sfmm_profile",
             "sfmm_guess_default_options", "sfmm_guess_fit", "sfmm_guess_predict", "sfmm_mlp_train",
             "sfmm_solve_bodies", "sfmm_set_solver", "sfmm_span_predict"]
 
@@ -94,6 +94,7 @@ def load():
     lib.sfmm_near_rows.argtypes = [P, I32, I32, P, P]
     lib.sfmm_describe.argtypes = [P, I32, P, P]
     lib.sfmm_profile.argtypes = [P, I32, P, P]
+    lib.sfmm_product_bytes.argtypes = [P, I32, P]
     lib.sfmm_guess_default_options.argtypes = [ctypes.POINTER(sfmm_guess_options)]
     lib.sfmm_guess_default_options.restype = None
     lib.sfmm_guess_fit.argtypes = [P, I32, I32, P, P, P, ctypes.POINTER(sfmm_guess_options), P, I32]
@@ -347,6 +348,12 @@ class Context:
         _check(lib().sfmm_describe(self.ctx, body, info.ctypes.data, trunc.ctypes.data), self.ctx)
         return dict(levels=int(info[0]), finest_boxes=int(info[1]), near_pairs=int(info[2]),
                     translation_pairs=int(info[3]), truncation=trunc)
+
+    def sfmm_product_bytes(self, body=0):
+        b = np.zeros(8, dtype=np.int64)
+        _check(lib().sfmm_product_bytes(self.ctx, body, b.ctypes.data), self.ctx)
+        keys = ["near", "x_y", "patterns", "levels", "translation", "interpolation", "total"]
+        return {k: int(v) for k, v in zip(keys, b)}
 
     def sfmm_profile(self, enable):
         t = np.zeros(8)
