@@ -103,7 +103,14 @@ typedef struct {
                                  the matrix-core / grouped variant of every stage that
                                  has both and keep the faster; 0 (default): fixed
                                  thresholds (matrix cores from 16 RHS, grouped
-                                 translation from 16 RHS)                               */
+                                 translation at 1 RHS and from 16 RHS)                  */
+    int32_t kernel_plan;      /* 0 (default): kernels chosen as `autotune` says; with
+                                 bit 0 set, bits 1..5 fix for every batch size: matrix-
+                                 core near product, matrix-core aggregation and receive,
+                                 matrix-core interpolation, grouped translation, split
+                                 single-RHS interpolation stages.  A variant whose
+                                 conditions do not hold (batch size, LDS) falls back to
+                                 the vector kernel.  For tests and measurement.         */
 } sfmm_options;
 
 /* Preconditioners of sfmm_solve, all built from the near-field matrix Z_near
@@ -303,12 +310,8 @@ sfmm_status sfmm_product_bytes(const sfmm_ctx *ctx, int32_t body, int64_t *bytes
  * interpolation, t[3] translation, t[4] downward anterpolation, t[5] receive,
  * t[6] ILU(0) solves, t[7] whole product; n[i] = number of samples.
  * Stage timing is enabled only between sfmm_profile(ctx, 1, ...) and
- * sfmm_profile(ctx, 0, ...); enabling resets the accumulators.  With
- * enable = 1 the stages of a product run one after another on the context's
- * stream (each stage timed alone); with enable = 2 products keep their
- * concurrent form (far-field chains on side streams beside the near product)
- * and only t[0] (the near product as it runs beside them) and t[7] are
- * recorded.  Either way products run directly, not from captured graphs. */
+ * sfmm_profile(ctx, 0, ...); enabling resets the accumulators.  While timing
+ * is on, products run kernel by kernel instead of from captured graphs. */
 sfmm_status sfmm_profile(sfmm_ctx *ctx, int32_t enable, double *t, int64_t *n);
 
 #ifdef __cplusplus

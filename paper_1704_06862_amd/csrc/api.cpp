@@ -122,6 +122,7 @@ void sfmm_default_options(sfmm_options *o) {
     o->poly_degree = 16;
     o->graphs = 1;
     o->autotune = 0;
+    o->kernel_plan = 0;
 }
 
 sfmm_status sfmm_setup(const sfmm_body *bodies, int32_t n_bodies, const sfmm_options *opt, sfmm_ctx **out) {
@@ -173,7 +174,7 @@ sfmm_status sfmm_setup(const sfmm_body *bodies, int32_t n_bodies, const sfmm_opt
         }
         if (o.device >= 0) {
             for (auto &bh : ctx->bodies) ctx->dev.push_back(make_device_body(*bh, o.precision, o.device, ctx->stream, o.graphs != 0,
-                                                                         o.autotune != 0, o.verbose));
+                                                                         o.autotune != 0, o.kernel_plan, o.verbose));
         }
         *out = ctx.release();
     });
@@ -473,7 +474,7 @@ sfmm_status sfmm_profile(sfmm_ctx *ctx, int32_t enable, double *t, int64_t *n) {
                 acc.ms[i] += s.ms[i];
                 acc.n[i] += s.n[i];
             }
-            d->profile(enable == 2 ? 2 : enable != 0 ? 1 : 0);
+            d->profile(enable != 0);
         }
         for (int i = 0; i < 8; ++i) {
             if (t) t[i] = acc.n[i] ? acc.ms[i] / acc.n[i] : 0.0;

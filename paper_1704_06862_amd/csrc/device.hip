@@ -97,18 +97,14 @@ int pick_tile(int R, std::initializer_list<int> cands, F fits) {
 template <typename T>
 class DeviceBodyT final : public DeviceBody {
   public:
-    DeviceBodyT(const BodyHost &h, int device, void *stream, bool split, bool graphs, bool autotune, int verbose)
-        : h_(h), split_(split), graphs_(graphs), autotune_(autotune), verbose_(verbose) {
+    DeviceBodyT(const BodyHost &h, int device, void *stream, bool split, bool graphs, bool autotune, int kernel_plan,
+                int verbose)
+        : h_(h), split_(split), graphs_(graphs), autotune_(autotune), kernel_plan_(kernel_plan), verbose_(verbose) {
         HIPCHK(hipSetDevice(device));
         // a stream of our own stands in for the legacy default stream, which
         // cannot be captured; it is a blocking stream, so it stays ordered
         // with work on the default stream
         HIPCHK(hipStreamCreate(&own_stream_));
-        for (int i = 0; i < 2; ++i) {
-            HIPCHK(hipStreamCreate(&side_[i]));
-            HIPCHK(hipEventCreateWithFlags(&join_ev_[i], hipEventDisableTiming));
-        }
-        HIPCHK(hipEventCreateWithFlags(&fork_ev_, hipEventDisableTiming));
         set_stream(stream);
         const Mesh &m = h.mesh;
         const Octree &o = h.oct;
@@ -225,14 +221,6 @@ class DeviceBodyT final : public DeviceBody {
 
     ~DeviceBodyT() override {
         clear_graphs();
-        for (int i = 0; i < 2; ++i) {
-            if (side_[i]) {
-                (void)hipStreamSynchronize(side_[i]);
-                (void)hipStreamDestroy(side_[i]);
-            }
-            if (join_ev_[i]) (void)hipEventDestroy(join_ev_[i]);
-        }
-        if (fork_ev_) (void)hipEventDestroy(fork_ev_);
         if (own_stream_) {
             (void)hipStreamSynchronize(own_stream_);
             (void)hipStreamDestroy(own_stream_);
@@ -290,9 +278,9 @@ class DeviceBodyT final : public DeviceBody {
         }
         HIPCHK(hipGraphLaunch(it->second, stream_));
     }
-    void profile(int mode) override {
-        profiling_ = mode;
-        if (mode) times_ = StageTimes();
+    void profile(bool enable) override {
+        profiling_ = enable;
+        if (enable) times_ = StageTimes();
     }
     StageTimes times() const override { return times_; }
     int64_t device_bytes() const override { return bytes_; }
@@ -309,11 +297,19 @@ class DeviceBodyT final : public DeviceBody {
     static Plan default_plan(int R) {
         Plan p;
         p.near_mma = p.agg_mma = p.interp_mma = R >= MMA_MIN_R && std::is_same<T, float>::value;
-        p.trans_grp = R >= TRANS_GRP_MIN_R;
+        p.trans_grp = R == 1 || R >= TRANS_GRP_MIN_R;
         p.interp_split = R == 1;
         return p;
     }
     void use_plan(int R) {
+        if (kernel_plan_ & 1) {
+            plan_.near_mma = (kernel_plan_ >> 1) & 1;
+            plan_.agg_mma = (kernel_plan_ >> 2) & 1;
+            plan_.interp_mma = (kernel_plan_ >> 3) & 1;
+            plan_.trans_grp = (kernel_plan_ >> 4) & 1;
+            plan_.interp_split = (kernel_plan_ >> 5) & 1;
+            return;
+        }
         if (!autotune_) {
             plan_ = default_plan(R);
             return;
@@ -339,8 +335,8 @@ class DeviceBodyT final : public DeviceBody {
     }
     Plan tune(int R) {
         ensure_batch(R);
-        const int prof = profiling_;
-        profiling_ = 0;
+        const bool prof = profiling_;
+        profiling_ = false;
         k_zero<T><<<nblocks((int64_t)2 * ne_ * R), WG, 0, stream_>>>(xi_, (int64_t)2 * ne_ * R);
         LAUNCHCHK();
         Plan best = default_plan(R);
@@ -567,76 +563,38 @@ class DeviceBodyT final : public DeviceBody {
         LAUNCHCHK();
     }
 
-    // y = Z x.  Stage profiling runs the stages one after another on the
-    // library stream; otherwise the regions' far-field chains (aggregation,
-    // upward pass, translation, downward pass) run on two side streams,
-    // concurrently with each other and with the near product, and join
-    // before the receive steps (which both add into y) on the library stream.
+    // y = Z x: the near product, then per stage every region's far-field
+    // work (aggregation, upward pass, translation, downward pass, receive),
+    // all on the library stream.
     void matvec_internal(const cx<T> *x, cx<T> *y, int R, int parts) {
         const int64_t NR = (int64_t)2 * ne_ * R;
         const bool far = (parts & SFMM_PART_FAR) && f_ >= 2;
-        auto near = [&] {
-            if (parts & SFMM_PART_NEAR) {
-                launch_near<false>(R, x, y, nullptr, cx<T>{0, 0}, 1);
-            } else {
-                k_zero<T><<<nblocks(NR), WG, 0, stream_>>>(y, NR);
-                LAUNCHCHK();
-            }
-        };
-        if (profiling_ == 1 || !far) {
-            mark(0);
-            near();
-            mark(1);
-            if (far) {
-                for (Reg &G : regs_) aggregate_region(G, R, x);
-                mark(2);
-                for (Reg &G : regs_)
-                    for (int l = f_; l >= 3; --l) upward(G, l, R);
-                mark(3);
-                for (Reg &G : regs_) translate_levels(G, R);
-                mark(4);
-                for (Reg &G : regs_)
-                    for (int l = 3; l <= f_; ++l) downward(G, l, R);
-                mark(5);
-                for (Reg &G : regs_) receive_region(G, R, y);
-            } else {
-                mark(2);
-                mark(3);
-                mark(4);
-                mark(5);
-            }
-            mark(6);
-            if (profiling_) collect_matvec(R);
-            return;
-        }
-        const hipStream_t main = stream_;
-        struct Restore {
-            hipStream_t &s, v;
-            ~Restore() { s = v; }
-        } restore{stream_, main};
         mark(0);
-        HIPCHK(hipEventRecord(fork_ev_, main));
-        const int nside = std::min<int>(2, (int)regs_.size());
-        for (int i = 0; i < nside; ++i) HIPCHK(hipStreamWaitEvent(side_[i], fork_ev_, 0));
-        for (size_t i = 0; i < regs_.size(); ++i) {
-            stream_ = side_[i % 2];
-            Reg &G = regs_[i];
-            aggregate_region(G, R, x);
-            for (int l = f_; l >= 3; --l) upward(G, l, R);
-            translate_levels(G, R);
-            for (int l = 3; l <= f_; ++l) downward(G, l, R);
+        if (parts & SFMM_PART_NEAR) {
+            launch_near<false>(R, x, y, nullptr, cx<T>{0, 0}, 1);
+        } else {
+            k_zero<T><<<nblocks(NR), WG, 0, stream_>>>(y, NR);
+            LAUNCHCHK();
         }
-        stream_ = main;
         mark(1);
-        near();
-        mark(2);
-        for (int i = 0; i < nside; ++i) {
-            HIPCHK(hipEventRecord(join_ev_[i], side_[i]));
-            HIPCHK(hipStreamWaitEvent(main, join_ev_[i], 0));
+        if (far) {
+            for (Reg &G : regs_) aggregate_region(G, R, x);
+            mark(2);
+            for (int l = f_; l >= 3; --l) upward_level(l, R);
+            mark(3);
+            translate_all(R);
+            mark(4);
+            for (int l = 3; l <= f_; ++l) downward_level(l, R);
+            mark(5);
+            for (Reg &G : regs_) receive_region(G, R, y);
+        } else {
+            mark(2);
+            mark(3);
+            mark(4);
+            mark(5);
         }
-        for (Reg &G : regs_) receive_region(G, R, y);
         mark(6);
-        if (profiling_) collect_concurrent(R);
+        if (profiling_) collect_matvec(R);
     }
 
     // Sibling groups for k_translate_grp: boxes sharing a parent key, the union
@@ -721,6 +679,9 @@ class DeviceBodyT final : public DeviceBody {
     }
 
     // matrix-core interpolation: sizes within 4 tiles of 16 (theta pairs and phi)
+    // fewer than four 256-thread workgroups per CU: launch 64-thread ones
+    static bool small_grid(int64_t items) { return nblocks(items) < 4 * 256; }
+
     // single-RHS split stages: the matrices of the transition l -> l - 1 fit in LDS
     bool split_ok(const Reg &G, int l, int R) const {
         const size_t th = (size_t)2 * G.nth[l - 1] * G.nth[l] * sizeof(T), ph = (size_t)G.nph[l - 1] * G.nph[l] * sizeof(T);
@@ -767,35 +728,63 @@ class DeviceBodyT final : public DeviceBody {
 #undef SFMM_DNM
     }
 
-    // all translation levels of a region
-    void translate_levels(Reg &G, int R) {
-        if (R == 1 && !plan_.trans_grp && f_ - 1 <= TRANS_MAXLEV) {
-            TransLevels<T> tl{};
-            tl.nlev = f_ - 1;
+    // every translation level of every region; one RHS: one launch
+    void translate_all(int R) {
+        const int nlev = f_ - 1;
+        if (R == 1 && nlev >= 1 && (int)regs_.size() * nlev <= TRANS_MAXJOB) {
             int nblk = 0;
-            for (int i = 0; i < tl.nlev; ++i) {
-                const int l = i + 2;
-                tl.blk0[i] = nblk;
-                tl.K[i] = G.K[l];
-                tl.nkc[i] = (G.K[l] + 63) / 64;
-                tl.il_ptr[i] = G.il_ptr[l];
-                tl.il_src[i] = G.il_src[l];
-                tl.il_off[i] = G.il_off[l];
-                tl.trans[i] = G.trans[l];
-                tl.S[i] = G.S[l];
-                tl.G[i] = G.G[l];
-                nblk += G.nbox[l] * tl.nkc[i];
-            }
-            tl.blk0[tl.nlev] = nblk;
-            tl.nblk = nblk;
-            if (nblk > 0) {
-                const unsigned grid = (unsigned)((nblk + 7) / 8 * 8);
-                k_translate1<T><<<grid, WG, 0, stream_>>>(tl);
-                LAUNCHCHK();
+            if (plan_.trans_grp) {
+                TransGroups<T> tg{};
+                int e = 0;
+                for (Reg &G : regs_)
+                    for (int l = 2; l <= f_; ++l, ++e) {
+                        tg.blk0[e] = nblk;
+                        tg.K[e] = G.K[l];
+                        tg.nkc[e] = (G.K[l] + 63) / 64;
+                        tg.grp_dst[e] = G.grp_dst[l];
+                        tg.cand_ptr[e] = G.cand_ptr[l];
+                        tg.cand_src[e] = G.cand_src[l];
+                        tg.cand_off[e] = G.cand_off[l];
+                        tg.trans[e] = G.trans[l];
+                        tg.S[e] = G.S[l];
+                        tg.G[e] = G.G[l];
+                        nblk += G.ngrp[l] * tg.nkc[e];
+                    }
+                tg.nlev = e;
+                tg.blk0[e] = nblk;
+                tg.nblk = nblk;
+                if (nblk > 0) {
+                    k_translate_grp1<T><<<(unsigned)((nblk + 7) / 8 * 8), WG, 0, stream_>>>(tg);
+                    LAUNCHCHK();
+                }
+            } else {
+                TransLevels<T> tl{};
+                int e = 0;
+                for (Reg &G : regs_)
+                    for (int l = 2; l <= f_; ++l, ++e) {
+                        tl.blk0[e] = nblk;
+                        tl.K[e] = G.K[l];
+                        tl.nkc[e] = (G.K[l] + 63) / 64;
+                        tl.il_ptr[e] = G.il_ptr[l];
+                        tl.il_src[e] = G.il_src[l];
+                        tl.il_off[e] = G.il_off[l];
+                        tl.trans[e] = G.trans[l];
+                        tl.S[e] = G.S[l];
+                        tl.G[e] = G.G[l];
+                        nblk += G.nbox[l] * tl.nkc[e];
+                    }
+                tl.nlev = e;
+                tl.blk0[e] = nblk;
+                tl.nblk = nblk;
+                if (nblk > 0) {
+                    k_translate1<T><<<(unsigned)((nblk + 7) / 8 * 8), WG, 0, stream_>>>(tl);
+                    LAUNCHCHK();
+                }
             }
             return;
         }
-        for (int l = 2; l <= f_; ++l) translate(G, l, R);
+        for (Reg &G : regs_)
+            for (int l = 2; l <= f_; ++l) translate(G, l, R);
     }
 
     void translate(Reg &G, int l, int R) {
@@ -823,6 +812,84 @@ class DeviceBodyT final : public DeviceBody {
         LAUNCHCHK();
     }
 
+    // Level transition l -> l - 1 (upward) or l - 1 -> l (downward) of every
+    // region: one RHS with the split stages of all regions in one launch per
+    // stage, otherwise region by region.
+    template <typename P>
+    static unsigned add_job(JobList<P> &jl, const P &p, int64_t items, int bs) {
+        jl.blk0[jl.n] = jl.n ? jl.blk0[jl.n] : 0;
+        jl.p[jl.n] = p;
+        const unsigned nb = nblocks(items, bs);
+        jl.blk0[jl.n + 1] = jl.blk0[jl.n] + (int)nb;
+        ++jl.n;
+        return nb;
+    }
+    bool split_all(int l, int R) const {
+        if ((int)regs_.size() > SPLIT_MAXJOB) return false;
+        for (const Reg &G : regs_)
+            if (!split_ok(G, l, R)) return false;
+        return true;
+    }
+    template <typename P, typename K64, typename K256>
+    void launch_jobs(const std::vector<P> &jobs, const std::vector<int64_t> &items, size_t shm, K64 k64,
+                     K256 k256) {
+        int64_t total = 0;
+        for (int64_t n : items) total += n;
+        const bool small = small_grid(total);
+        const int bs = small ? 64 : WG;
+        JobList<P> jl{};
+        for (size_t i = 0; i < jobs.size(); ++i) add_job(jl, jobs[i], items[i], bs);
+        const unsigned grid = (unsigned)jl.blk0[jl.n];
+        if (!grid) return;
+        if (small) k64<<<grid, 64, shm, stream_>>>(jl);
+        else k256<<<grid, WG, shm, stream_>>>(jl);
+        LAUNCHCHK();
+    }
+    void upward_level(int l, int R) {
+        if (!split_all(l, R)) {
+            for (Reg &G : regs_) upward(G, l, R);
+            return;
+        }
+        std::vector<ThetaJob<T>> th;
+        std::vector<UpPhiJob<T>> ph;
+        std::vector<int64_t> n1, n2;
+        size_t sh1 = 0, sh2 = 0;
+        for (Reg &G : regs_) {
+            const int nth_c = G.nth[l], nph_c = G.nph[l], nth_p = G.nth[l - 1], nph_p = G.nph[l - 1];
+            th.push_back({G.nbox[l] * 2, nth_c, nph_c, nth_p, G.ipA[l], G.ipB[l], G.S[l], G.tmp});
+            n1.push_back((int64_t)G.nbox[l] * 2 * ((nth_p + 1) / 2) * (nph_c / 2));
+            sh1 = std::max(sh1, (size_t)2 * nth_p * nth_c * sizeof(T));
+            ph.push_back({G.nbox[l - 1], nth_p, nph_p, nph_c, G.ipDt[l], G.child_ptr[l - 1], G.child_idx[l - 1],
+                          G.slot[l], G.sup[l], G.tmp, G.S[l - 1]});
+            n2.push_back((int64_t)G.nbox[l - 1] * 2 * nth_p * (nph_p / 2));
+            sh2 = std::max(sh2, (size_t)nph_c * nph_p * sizeof(T));
+        }
+        launch_jobs(th, n1, sh1, k_up_theta1<T, 64>, k_up_theta1<T, WG>);
+        launch_jobs(ph, n2, sh2, k_up_phi1<T, 64>, k_up_phi1<T, WG>);
+    }
+    void downward_level(int l, int R) {
+        if (!split_all(l, R)) {
+            for (Reg &G : regs_) downward(G, l, R);
+            return;
+        }
+        std::vector<DnPhiJob<T>> ph;
+        std::vector<ThetaJob<T>> th;
+        std::vector<int64_t> n1, n2;
+        size_t sh1 = 0, sh2 = 0;
+        for (Reg &G : regs_) {
+            const int nth_c = G.nth[l], nph_c = G.nph[l], nth_p = G.nth[l - 1], nph_p = G.nph[l - 1];
+            ph.push_back({G.nbox[l], nth_p, nph_p, nph_c, G.ipD[l], G.parent[l], G.slot[l], G.sdn[l], G.G[l - 1],
+                          G.tmp});
+            n1.push_back((int64_t)G.nbox[l] * 2 * nth_p * (nph_c / 2));
+            sh1 = std::max(sh1, (size_t)nph_p * nph_c * sizeof(T));
+            th.push_back({G.nbox[l] * 2, nth_c, nph_c, nth_p, G.ipA[l], G.ipB[l], G.tmp, G.G[l]});
+            n2.push_back((int64_t)G.nbox[l] * 2 * ((nth_c + 1) / 2) * (nph_c / 2));
+            sh2 = std::max(sh2, (size_t)2 * nth_p * nth_c * sizeof(T));
+        }
+        launch_jobs(ph, n1, sh1, k_dn_phi1<T, 64>, k_dn_phi1<T, WG>);
+        launch_jobs(th, n2, sh2, k_dn_theta1<T, 64>, k_dn_theta1<T, WG>);
+    }
+
     void upward(Reg &G, int l, int R) {
         const int nth_c = G.nth[l], nph_c = G.nph[l], nth_p = G.nth[l - 1], nph_p = G.nph[l - 1];
         if constexpr (std::is_same<T, float>::value) {
@@ -830,18 +897,6 @@ class DeviceBodyT final : public DeviceBody {
                 upward_mma(G, l, R);
                 return;
             }
-        }
-        if (split_ok(G, l, R)) {
-            const int64_t n1 = (int64_t)G.nbox[l] * 2 * ((nth_p + 1) / 2) * (nph_c / 2);
-            k_up_theta1<T><<<nblocks(n1), WG, (size_t)2 * nth_p * nth_c * sizeof(T), stream_>>>(
-                G.nbox[l] * 2, nth_c, nph_c, nth_p, G.ipA[l], G.ipB[l], G.S[l], G.tmp);
-            LAUNCHCHK();
-            const int64_t n2 = (int64_t)G.nbox[l - 1] * 2 * nth_p * (nph_p / 2);
-            k_up_phi1<T><<<nblocks(n2), WG, (size_t)nph_c * nph_p * sizeof(T), stream_>>>(
-                G.nbox[l - 1], nth_p, nph_p, nph_c, G.ipDt[l], G.child_ptr[l - 1], G.child_idx[l - 1], G.slot[l],
-                G.sup[l], G.tmp, G.S[l - 1]);
-            LAUNCHCHK();
-            return;
         }
         const int rt = pick_tile(R, {4, 2, 1}, [&](int t) {
             return ((size_t)G.K[l] + (size_t)UPR * nph_c) * t * sizeof(cx<T>) <= LDS_LIMIT &&
@@ -880,17 +935,6 @@ class DeviceBodyT final : public DeviceBody {
                 downward_mma(G, l, R);
                 return;
             }
-        }
-        if (split_ok(G, l, R)) {
-            const int64_t n1 = (int64_t)G.nbox[l] * 2 * nth_p * (nph_c / 2);
-            k_dn_phi1<T><<<nblocks(n1), WG, (size_t)nph_p * nph_c * sizeof(T), stream_>>>(
-                G.nbox[l], nth_p, nph_p, nph_c, G.ipD[l], G.parent[l], G.slot[l], G.sdn[l], G.G[l - 1], G.tmp);
-            LAUNCHCHK();
-            const int64_t n2 = (int64_t)G.nbox[l] * 2 * ((nth_c + 1) / 2) * (nph_c / 2);
-            k_dn_theta1<T><<<nblocks(n2), WG, (size_t)2 * nth_p * nth_c * sizeof(T), stream_>>>(
-                G.nbox[l] * 2, nth_c, nph_c, nth_p, G.ipA[l], G.ipB[l], G.tmp, G.G[l]);
-            LAUNCHCHK();
-            return;
         }
         const int rt = pick_tile(R, {4, 2, 1}, [&](int t) {
             return ((size_t)G.K[l - 1] + (size_t)nth_p * nph_c) * t * sizeof(cx<T>) <= LDS_LIMIT;
@@ -1428,18 +1472,6 @@ class DeviceBodyT final : public DeviceBody {
     void mark(int i) {
         if (profiling_) HIPCHK(hipEventRecord(evs_[i], stream_));
     }
-    // concurrent product: the near kernel as it runs beside the far-field
-    // chains (events around it on the library stream) and the whole product
-    void collect_concurrent(int R) {
-        HIPCHK(hipEventSynchronize(evs_[6]));
-        float ms;
-        HIPCHK(hipEventElapsedTime(&ms, evs_[1], evs_[2]));
-        times_.ms[0] += ms / R;
-        times_.n[0] += 1;
-        HIPCHK(hipEventElapsedTime(&ms, evs_[0], evs_[6]));
-        times_.ms[7] += ms / R;
-        times_.n[7] += 1;
-    }
     void collect_matvec(int R) {
         HIPCHK(hipEventSynchronize(evs_[6]));
         float ms;
@@ -1465,12 +1497,11 @@ class DeviceBodyT final : public DeviceBody {
     bool split_ = false;
     bool graphs_ = true;
     bool autotune_ = false;
+    int kernel_plan_ = 0;
     int verbose_ = 0;
     Plan plan_{};
     std::map<int, Plan> plans_;
     hipStream_t own_stream_ = nullptr;
-    hipStream_t side_[2] = {nullptr, nullptr};   // far-field chains of the regions
-    hipEvent_t fork_ev_ = nullptr, join_ev_[2] = {nullptr, nullptr};
     std::map<std::pair<int, int>, hipGraphExec_t> gexec_;
     int ntiles_ = 0;
     int64_t nsteps_ = 0;
@@ -1496,7 +1527,7 @@ class DeviceBodyT final : public DeviceBody {
     int *dact_ = nullptr, *dcnt_ = nullptr;
     std::vector<void *> allocs_, batch_allocs_, krylov_allocs_;
     int64_t bytes_ = 0;
-    int profiling_ = 0;   // 0 off, 1 stage by stage, 2 concurrent product (near and total)
+    bool profiling_ = false;
     hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
     hipEvent_t evs_[7] = {nullptr};
     StageTimes times_;
@@ -1505,14 +1536,14 @@ class DeviceBodyT final : public DeviceBody {
 }  // namespace
 
 std::unique_ptr<DeviceBody> make_device_body(const BodyHost &h, int precision, int device, void *stream,
-                                             bool graphs, bool autotune, int verbose) {
+                                             bool graphs, bool autotune, int kernel_plan, int verbose) {
     check_device(device);
     if (precision == SFMM_PREC_FP64)
-        return std::make_unique<DeviceBodyT<double>>(h, device, stream, false, graphs, autotune, verbose);
+        return std::make_unique<DeviceBodyT<double>>(h, device, stream, false, graphs, autotune, kernel_plan, verbose);
     if (precision == SFMM_PREC_FP32)
-        return std::make_unique<DeviceBodyT<float>>(h, device, stream, false, graphs, autotune, verbose);
+        return std::make_unique<DeviceBodyT<float>>(h, device, stream, false, graphs, autotune, kernel_plan, verbose);
     if (precision == SFMM_PREC_BF16_SPLIT)
-        return std::make_unique<DeviceBodyT<float>>(h, device, stream, true, graphs, autotune, verbose);
+        return std::make_unique<DeviceBodyT<float>>(h, device, stream, true, graphs, autotune, kernel_plan, verbose);
     throw Error(SFMM_E_UNSUPPORTED, "unknown precision mode");
 }
 

@@ -40,13 +40,13 @@ class DeviceBody {
     // or a stream of the body's own when the context has none)
     virtual void *stream() const = 0;
     virtual void stream_synchronize() = 0;
-    virtual void profile(int mode) = 0;
+    virtual void profile(bool enable) = 0;
     virtual StageTimes times() const = 0;
     virtual int64_t device_bytes() const = 0;
 };
 
 std::unique_ptr<DeviceBody> make_device_body(const BodyHost &h, int precision, int device, void *stream,
-                                             bool graphs, bool autotune, int verbose);
+                                             bool graphs, bool autotune, int kernel_plan, int verbose);
 
 // HIP helpers used by the C ABI for host <-> device staging.
 void *device_alloc(size_t bytes);

@@ -333,6 +333,32 @@ __global__ void __launch_bounds__(1024) k_aggregate(int K, int R, int ech, const
             if (q < KR) {
                 const cx<T> *F = tx + (size_t)c0 * 2 * K + k;
                 int t = 0;
+                for (; t + 3 < cnt; t += 4) {
+                    const cx<T> ft = F[(size_t)t * 2 * K], fp = F[(size_t)t * 2 * K + K];
+                    const cx<T> gt = F[(size_t)(t + 1) * 2 * K], gp = F[(size_t)(t + 1) * 2 * K + K];
+                    const cx<T> ut = F[(size_t)(t + 2) * 2 * K], up = F[(size_t)(t + 2) * 2 * K + K];
+                    const cx<T> vt = F[(size_t)(t + 3) * 2 * K], vp = F[(size_t)(t + 3) * 2 * K + K];
+                    const cx<T> j0 = js[t * R + r], m0 = ms[t * R + r];
+                    const cx<T> j1 = js[(t + 1) * R + r], m1 = ms[(t + 1) * R + r];
+                    const cx<T> j2 = js[(t + 2) * R + r], m2 = ms[(t + 2) * R + r];
+                    const cx<T> j3 = js[(t + 3) * R + r], m3 = ms[(t + 3) * R + r];
+                    cfma(st, ft, j0);
+                    cfma(st, fp, m0);
+                    cfma(sp, fp, j0);
+                    cfms(sp, ft, m0);
+                    cfma(st2, gt, j1);
+                    cfma(st2, gp, m1);
+                    cfma(sp2, gp, j1);
+                    cfms(sp2, gt, m1);
+                    cfma(st, ut, j2);
+                    cfma(st, up, m2);
+                    cfma(sp, up, j2);
+                    cfms(sp, ut, m2);
+                    cfma(st2, vt, j3);
+                    cfma(st2, vp, m3);
+                    cfma(sp2, vp, j3);
+                    cfms(sp2, vt, m3);
+                }
                 for (; t + 1 < cnt; t += 2) {
                     const cx<T> ft = F[(size_t)t * 2 * K], fp = F[(size_t)t * 2 * K + K];
                     const cx<T> gt = F[(size_t)(t + 1) * 2 * K], gp = F[(size_t)(t + 1) * 2 * K + K];
@@ -623,34 +649,79 @@ __global__ void k_dn_theta(int R, int nchild, int nth_c, int nph_c, int nth_p, c
 
 // ---------------------------------------------------------------------------
 // One right-hand side: the same two stages as the element-wise kernels above,
-// register-blocked, with the interpolation matrices staged in LDS.  In the
-// theta stages a thread computes two theta rows by the azimuthal pair
+// register-blocked, with the interpolation matrices staged in LDS, and one
+// launch for the same level transition of every region (a list of up to
+// SPLIT_MAXJOB jobs; the workgroups [blk0[i], blk0[i + 1]) serve job i).  In
+// the theta stages a thread computes two theta rows by the azimuthal pair
 // (j, j + h), h = nph_c / 2 (the two halves of the paired matrix
 // [[A, B], [B, A]] share every load); in the phi stages a thread computes two
-// adjacent azimuths of one theta row.
+// adjacent azimuths of one theta row.  BS threads per workgroup: transitions
+// with few items use 64 so the workgroups spread evenly over the CUs.
+constexpr int SPLIT_MAXJOB = 8;
+
+template <typename P>
+struct JobList {
+    int n;
+    int blk0[SPLIT_MAXJOB + 1];
+    P p[SPLIT_MAXJOB];
+};
+
+// the job of this workgroup (workgroup-uniform) and the workgroup's index in it
+template <typename P>
+__device__ __forceinline__ const P &job_of(const JobList<P> &jl, int &local) {
+    int i = 0;
+    while (i + 1 < jl.n && (int)blockIdx.x >= jl.blk0[i + 1]) ++i;
+    local = (int)blockIdx.x - jl.blk0[i];
+    return jl.p[i];
+}
+
+template <typename T>
+struct ThetaJob {   // up: tmp[cc][I][j] from S[cc][i][j]; down: Gc[cc][i][j] += from tmp[cc][I][j]
+    int ncc, nth_c, nph_c, nth_p;
+    const T *A, *B;
+    const cx<T> *in;
+    cx<T> *out;
+};
+template <typename T>
+struct UpPhiJob {
+    int nparent, nth_p, nph_p, nph_c;
+    const T *Dt;
+    const int *child_ptr, *child_idx, *child_slot;
+    const cx<T> *shift, *tmp;
+    cx<T> *Sp;
+};
+template <typename T>
+struct DnPhiJob {
+    int nchild, nth_p, nph_p, nph_c;
+    const T *D;
+    const int *parent, *child_slot;
+    const cx<T> *shift, *Gp;
+    cx<T> *tmp;
+};
 
 // tmp[cc][I][j] = sum_i A/B[I][i] S[cc][i][j or j +- h], cc = 2 child + comp
-template <typename T>
-__global__ void __launch_bounds__(WG) k_up_theta1(int ncc, int nth_c, int nph_c, int nth_p, const T *__restrict__ A,
-                                                  const T *__restrict__ B, const cx<T> *__restrict__ S,
-                                                  cx<T> *__restrict__ tmp) {
+template <typename T, int BS>
+__global__ void __launch_bounds__(BS) k_up_theta1(const JobList<ThetaJob<T>> jl) {
     extern __shared__ unsigned char lds_raw[];
+    int local;
+    const ThetaJob<T> &a = job_of(jl, local);
+    const int nth_c = a.nth_c, nph_c = a.nph_c, nth_p = a.nth_p;
     T *As = reinterpret_cast<T *>(lds_raw);   // [nth_p][nth_c]
     T *Bs = As + nth_p * nth_c;
-    for (int t = threadIdx.x; t < nth_p * nth_c; t += WG) {
-        As[t] = A[t];
-        Bs[t] = B[t];
+    for (int t = threadIdx.x; t < nth_p * nth_c; t += BS) {
+        As[t] = a.A[t];
+        Bs[t] = a.B[t];
     }
     __syncthreads();
     const int h = nph_c / 2, np2 = (nth_p + 1) / 2;
-    const int64_t id = (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (id >= (int64_t)ncc * np2 * h) return;
+    const int64_t id = (int64_t)local * BS + threadIdx.x;
+    if (id >= (int64_t)a.ncc * np2 * h) return;
     const int j = id % h;
     const int I = 2 * (int)((id / h) % np2);
     const int64_t cc = id / ((int64_t)h * np2);
     const bool two = I + 1 < nth_p;
     const int I1 = two ? I + 1 : I;
-    const cx<T> *f = S + cc * nth_c * nph_c;
+    const cx<T> *f = a.in + cc * nth_c * nph_c;
     cx<T> a0 = {0, 0}, a1 = {0, 0}, b0 = {0, 0}, b1 = {0, 0};   // rows I, I1; azimuths j, j + h
     for (int i = 0; i < nth_c; ++i) {
         const T p0 = As[I * nth_c + i], q0 = Bs[I * nth_c + i];
@@ -665,7 +736,7 @@ __global__ void __launch_bounds__(WG) k_up_theta1(int ncc, int nth_c, int nph_c,
         b1.x += q1 * f1.x + p1 * f2.x;
         b1.y += q1 * f1.y + p1 * f2.y;
     }
-    cx<T> *o = tmp + (cc * nth_p + I) * nph_c;
+    cx<T> *o = a.out + (cc * nth_p + I) * nph_c;
     o[j] = a0;
     o[j + h] = b0;
     if (two) {
@@ -675,19 +746,18 @@ __global__ void __launch_bounds__(WG) k_up_theta1(int ncc, int nth_c, int nph_c,
 }
 
 // Sp[P][comp][I][J] = sum_children shift[slot][I][J] sum_j Dt[j][J] tmp[c][comp][I][j]
-template <typename T>
-__global__ void __launch_bounds__(WG) k_up_phi1(int nparent, int nth_p, int nph_p, int nph_c,
-                                                const T *__restrict__ Dt, const int *__restrict__ child_ptr,
-                                                const int *__restrict__ child_idx, const int *__restrict__ child_slot,
-                                                const cx<T> *__restrict__ shift, const cx<T> *__restrict__ tmp,
-                                                cx<T> *__restrict__ Sp) {
+template <typename T, int BS>
+__global__ void __launch_bounds__(BS) k_up_phi1(const JobList<UpPhiJob<T>> jl) {
     extern __shared__ unsigned char lds_raw[];
+    int local;
+    const UpPhiJob<T> &a = job_of(jl, local);
+    const int nth_p = a.nth_p, nph_p = a.nph_p, nph_c = a.nph_c;
     T *Ds = reinterpret_cast<T *>(lds_raw);   // [nph_c][nph_p]
-    for (int t = threadIdx.x; t < nph_c * nph_p; t += WG) Ds[t] = Dt[t];
+    for (int t = threadIdx.x; t < nph_c * nph_p; t += BS) Ds[t] = a.Dt[t];
     __syncthreads();
     const int Kp = nth_p * nph_p, hp = nph_p / 2;
-    const int64_t id = (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (id >= (int64_t)nparent * 2 * nth_p * hp) return;
+    const int64_t id = (int64_t)local * BS + threadIdx.x;
+    if (id >= (int64_t)a.nparent * 2 * nth_p * hp) return;
     const int J = 2 * (int)(id % hp);
     int64_t q = id / hp;
     const int I = q % nth_p;
@@ -695,9 +765,9 @@ __global__ void __launch_bounds__(WG) k_up_phi1(int nparent, int nth_p, int nph_
     const int comp = q % 2;
     const int P = q / 2;
     cx<T> o0 = {0, 0}, o1 = {0, 0};
-    for (int qq = child_ptr[P]; qq < child_ptr[P + 1]; ++qq) {
-        const int c = child_idx[qq];
-        const cx<T> *g = tmp + (((int64_t)c * 2 + comp) * nth_p + I) * nph_c;
+    for (int qq = a.child_ptr[P]; qq < a.child_ptr[P + 1]; ++qq) {
+        const int c = a.child_idx[qq];
+        const cx<T> *g = a.tmp + (((int64_t)c * 2 + comp) * nth_p + I) * nph_c;
         cx<T> v0 = {0, 0}, v1 = {0, 0};
         for (int j = 0; j < nph_c; ++j) {
             const T d0 = Ds[j * nph_p + J], d1 = Ds[j * nph_p + J + 1];
@@ -707,36 +777,36 @@ __global__ void __launch_bounds__(WG) k_up_phi1(int nparent, int nth_p, int nph_
             v1.x += d1 * t.x;
             v1.y += d1 * t.y;
         }
-        const cx<T> *sh = shift + (size_t)child_slot[c] * Kp + I * nph_p + J;
+        const cx<T> *sh = a.shift + (size_t)a.child_slot[c] * Kp + I * nph_p + J;
         cfma(o0, sh[0], v0);
         cfma(o1, sh[1], v1);
     }
-    cx<T> *out = Sp + ((int64_t)P * 2 + comp) * Kp + I * nph_p + J;
+    cx<T> *out = a.Sp + ((int64_t)P * 2 + comp) * Kp + I * nph_p + J;
     out[0] = o0;
     out[1] = o1;
 }
 
 // tmp[c][comp][I][j] = sum_J D[J][j] shift_dn[slot][I][J] Gp[parent][comp][I][J]
-template <typename T>
-__global__ void __launch_bounds__(WG) k_dn_phi1(int nchild, int nth_p, int nph_p, int nph_c, const T *__restrict__ D,
-                                                const int *__restrict__ parent, const int *__restrict__ child_slot,
-                                                const cx<T> *__restrict__ shift, const cx<T> *__restrict__ Gp,
-                                                cx<T> *__restrict__ tmp) {
+template <typename T, int BS>
+__global__ void __launch_bounds__(BS) k_dn_phi1(const JobList<DnPhiJob<T>> jl) {
     extern __shared__ unsigned char lds_raw[];
+    int local;
+    const DnPhiJob<T> &a = job_of(jl, local);
+    const int nth_p = a.nth_p, nph_p = a.nph_p, nph_c = a.nph_c;
     T *Ds = reinterpret_cast<T *>(lds_raw);   // [nph_p][nph_c]
-    for (int t = threadIdx.x; t < nph_p * nph_c; t += WG) Ds[t] = D[t];
+    for (int t = threadIdx.x; t < nph_p * nph_c; t += BS) Ds[t] = a.D[t];
     __syncthreads();
     const int Kp = nth_p * nph_p, hc = nph_c / 2;
-    const int64_t id = (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (id >= (int64_t)nchild * 2 * nth_p * hc) return;
+    const int64_t id = (int64_t)local * BS + threadIdx.x;
+    if (id >= (int64_t)a.nchild * 2 * nth_p * hc) return;
     const int j = 2 * (int)(id % hc);
     int64_t q = id / hc;
     const int I = q % nth_p;
     q /= nth_p;
     const int comp = q % 2;
     const int c = q / 2;
-    const cx<T> *g = Gp + ((int64_t)parent[c] * 2 + comp) * Kp + I * nph_p;
-    const cx<T> *sh = shift + (size_t)child_slot[c] * Kp + I * nph_p;
+    const cx<T> *g = a.Gp + ((int64_t)a.parent[c] * 2 + comp) * Kp + I * nph_p;
+    const cx<T> *sh = a.shift + (size_t)a.child_slot[c] * Kp + I * nph_p;
     cx<T> a0 = {0, 0}, a1 = {0, 0};
     for (int J = 0; J < nph_p; ++J) {
         const cx<T> v = cmul(sh[J], g[J]);
@@ -746,33 +816,34 @@ __global__ void __launch_bounds__(WG) k_dn_phi1(int nchild, int nth_p, int nph_p
         a1.x += d1 * v.x;
         a1.y += d1 * v.y;
     }
-    cx<T> *o = tmp + (((int64_t)c * 2 + comp) * nth_p + I) * nph_c + j;
+    cx<T> *o = a.tmp + (((int64_t)c * 2 + comp) * nth_p + I) * nph_c + j;
     o[0] = a0;
     o[1] = a1;
 }
 
 // Gc[cc][i][j] += sum_I A/B[I][i] tmp[cc][I][j or j +- h]
-template <typename T>
-__global__ void __launch_bounds__(WG) k_dn_theta1(int ncc, int nth_c, int nph_c, int nth_p, const T *__restrict__ A,
-                                                  const T *__restrict__ B, const cx<T> *__restrict__ tmp,
-                                                  cx<T> *__restrict__ Gc) {
+template <typename T, int BS>
+__global__ void __launch_bounds__(BS) k_dn_theta1(const JobList<ThetaJob<T>> jl) {
     extern __shared__ unsigned char lds_raw[];
+    int local;
+    const ThetaJob<T> &a = job_of(jl, local);
+    const int nth_c = a.nth_c, nph_c = a.nph_c, nth_p = a.nth_p;
     T *As = reinterpret_cast<T *>(lds_raw);   // [nth_p][nth_c]
     T *Bs = As + nth_p * nth_c;
-    for (int t = threadIdx.x; t < nth_p * nth_c; t += WG) {
-        As[t] = A[t];
-        Bs[t] = B[t];
+    for (int t = threadIdx.x; t < nth_p * nth_c; t += BS) {
+        As[t] = a.A[t];
+        Bs[t] = a.B[t];
     }
     __syncthreads();
     const int h = nph_c / 2, nc2 = (nth_c + 1) / 2;
-    const int64_t id = (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (id >= (int64_t)ncc * nc2 * h) return;
+    const int64_t id = (int64_t)local * BS + threadIdx.x;
+    if (id >= (int64_t)a.ncc * nc2 * h) return;
     const int j = id % h;
     const int i = 2 * (int)((id / h) % nc2);
     const int64_t cc = id / ((int64_t)h * nc2);
     const bool two = i + 1 < nth_c;
     const int i1 = two ? i + 1 : i;
-    const cx<T> *g = tmp + cc * nth_p * nph_c;
+    const cx<T> *g = a.in + cc * nth_p * nph_c;
     cx<T> a0 = {0, 0}, a1 = {0, 0}, b0 = {0, 0}, b1 = {0, 0};   // rows i, i1; azimuths j, j + h
     for (int I = 0; I < nth_p; ++I) {
         const T p0 = As[I * nth_c + i], q0 = Bs[I * nth_c + i];
@@ -787,7 +858,7 @@ __global__ void __launch_bounds__(WG) k_dn_theta1(int ncc, int nth_c, int nph_c,
         b1.x += q1 * g1.x + p1 * g2.x;
         b1.y += q1 * g1.y + p1 * g2.y;
     }
-    cx<T> *o = Gc + (cc * nth_c + i) * nph_c;
+    cx<T> *o = a.out + (cc * nth_c + i) * nph_c;
     cx<T> v = o[j];
     o[j] = {v.x + a0.x, v.y + a0.y};
     v = o[j + h];
@@ -838,22 +909,23 @@ __global__ void __launch_bounds__(WG) k_translate(int nbox, int K, int R, const 
     G[(size_t)b * 2 * KR + KR + kr] = gp;
 }
 
-// Translation for one right-hand side, every level of a region in one launch.
+// Translation for one right-hand side, every level of every region in one
+// launch (the entries of TransLevels are (region, level) pairs).
 // A workgroup takes one box and 64 directions; its four wavefronts split the
 // box's interaction list (entries q = w, w + 4, ...: the source and offset ids
 // are wave-uniform scalar loads) and are summed through LDS.  Workgroups are
 // numbered so that each of the 8 XCDs (which take workgroups round-robin)
 // receives a contiguous range of boxes in Morton order, whose source patterns
 // then stay in that XCD's L2.
-constexpr int TRANS_MAXLEV = 8;
+constexpr int TRANS_MAXJOB = 16;   // (region, level) entries of one launch
 template <typename T>
 struct TransLevels {
     int nlev, nblk;
-    int blk0[TRANS_MAXLEV + 1];   // first workgroup of each level
-    int K[TRANS_MAXLEV], nkc[TRANS_MAXLEV];
-    const int *il_ptr[TRANS_MAXLEV], *il_src[TRANS_MAXLEV], *il_off[TRANS_MAXLEV];
-    const cx<T> *trans[TRANS_MAXLEV], *S[TRANS_MAXLEV];
-    cx<T> *G[TRANS_MAXLEV];
+    int blk0[TRANS_MAXJOB + 1];   // first workgroup of each level
+    int K[TRANS_MAXJOB], nkc[TRANS_MAXJOB];
+    const int *il_ptr[TRANS_MAXJOB], *il_src[TRANS_MAXJOB], *il_off[TRANS_MAXJOB];
+    const cx<T> *trans[TRANS_MAXJOB], *S[TRANS_MAXJOB];
+    cx<T> *G[TRANS_MAXJOB];
 };
 
 template <typename T>
@@ -905,6 +977,85 @@ __global__ void __launch_bounds__(WG) k_translate1(const TransLevels<T> tl) {
             v.y += part[i][comp][lane].y;
         }
         if (k < K) tl.G[L][(size_t)b * 2 * K + comp * K + k] = v;
+    }
+}
+
+// The same for one right-hand side with the boxes grouped by parent: the
+// siblings share most of their interaction lists, so a workgroup (one group,
+// 64 directions) loads every candidate source sample once and applies it to
+// each sibling whose list holds it.  The four wavefronts split the candidates;
+// a candidate's translation samples are all requested before they are used,
+// and the wavefronts' partial sums are added in LDS one wavefront at a time.
+template <typename T>
+struct TransGroups {
+    int nlev, nblk;
+    int blk0[TRANS_MAXJOB + 1];
+    int K[TRANS_MAXJOB], nkc[TRANS_MAXJOB];
+    const int *grp_dst[TRANS_MAXJOB], *cand_ptr[TRANS_MAXJOB], *cand_src[TRANS_MAXJOB], *cand_off[TRANS_MAXJOB];
+    const cx<T> *trans[TRANS_MAXJOB], *S[TRANS_MAXJOB];
+    cx<T> *G[TRANS_MAXJOB];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(WG) k_translate_grp1(const TransGroups<T> tg) {
+    __shared__ cx<T> red[8][2][64];
+    const int per = (tg.nblk + 7) / 8;
+    const int id = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (id >= tg.nblk) return;   // whole workgroup
+    int L = 0;
+    while (L + 1 < tg.nlev && id >= tg.blk0[L + 1]) ++L;
+    const int local = id - tg.blk0[L];
+    const int K = tg.K[L];
+    const int g = local / tg.nkc[L];
+    const int lane = threadIdx.x & 63;
+    const int k0 = (local % tg.nkc[L]) * 64;
+    const int kk = k0 + lane < K ? k0 + lane : K - 1;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int *cs = tg.cand_src[L], *co = tg.cand_off[L];
+    const cx<T> *S = tg.S[L], *tr = tg.trans[L];
+    cx<T> acc[8][2];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j][0] = acc[j][1] = cx<T>{0, 0};
+    const int c1 = tg.cand_ptr[L][g + 1];
+    for (int c = tg.cand_ptr[L][g] + w; c < c1; c += WAVES) {
+        const int s = __builtin_amdgcn_readfirstlane(cs[c]);
+        const cx<T> a = S[(size_t)s * 2 * K + kk], b = S[(size_t)s * 2 * K + K + kk];
+        int o[8];
+        cx<T> t[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            o[j] = __builtin_amdgcn_readfirstlane(co[(int64_t)c * 8 + j]);
+            t[j] = o[j] >= 0 ? tr[(size_t)o[j] * K + kk] : cx<T>{0, 0};
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (o[j] >= 0) {
+                cfma(acc[j][0], t[j], a);
+                cfma(acc[j][1], t[j], b);
+            }
+    }
+    for (int step = 0; step < WAVES; ++step) {
+        if (w == step) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    cx<T> v = acc[j][q];
+                    if (step > 0) {
+                        v.x += red[j][q][lane].x;
+                        v.y += red[j][q][lane].y;
+                    }
+                    red[j][q][lane] = v;
+                }
+        }
+        __syncthreads();
+    }
+    const int *dst = tg.grp_dst[L] + (int64_t)g * 8;
+    cx<T> *G = tg.G[L];
+    for (int t = threadIdx.x; t < 8 * 2 * 64; t += WG) {
+        const int j = t >> 7, q = (t >> 6) & 1, ln = t & 63;
+        const int d = dst[j];
+        if (d >= 0 && k0 + ln < K) G[(size_t)d * 2 * K + q * K + k0 + ln] = red[j][q][ln];
     }
 }
 

@@ -44,7 +44,8 @@ class sfmm_options(ctypes.Structure):
                 ("extra_multipoles", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("gmres_restart", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("device", ctypes.c_int32), ("verbose", ctypes.c_int32), ("preconditioner", ctypes.c_int32),
-                ("poly_degree", ctypes.c_int32), ("graphs", ctypes.c_int32), ("autotune", ctypes.c_int32)]
+                ("poly_degree", ctypes.c_int32), ("graphs", ctypes.c_int32), ("autotune", ctypes.c_int32),
+                ("kernel_plan", ctypes.c_int32)]
 
 
 class sfmm_solve_info(ctypes.Structure):

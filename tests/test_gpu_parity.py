@@ -302,6 +302,42 @@ def test_multilevel_product_sampled_rows():
         assert err < 1e-3
 
 
+# kernel_plan bits: 1 = fixed plan, 16 = grouped translation, 32 = split
+# single-RHS interpolation stages (otherwise the per-box kernels)
+SINGLE_RHS_PLANS = {"flat+split": 1 | 32, "grouped+split": 1 | 16 | 32, "flat+box": 1, "grouped+box": 1 | 16}
+
+
+def test_single_rhs_kernel_variants():
+    # every single-RHS variant of translation and interpolation on a 4-level
+    # tree, in FP64 and FP32: within the MLFMM tolerance of the oracle's rows;
+    # the FP64 variants equal to each other up to the rounding of a different
+    # summation order, the FP32 ones within their single-precision rounding
+    # (amplified by the translation operator) of the FP64 product
+    b = sphere_body(1.0, 2.56, 3)
+    m = rwg.from_body(b)
+    rng = np.random.default_rng(6)
+    test = np.sort(rng.choice(m.n_edges, 40, replace=False))
+    x = random_complex_vector(2 * m.n_edges, 1, seed=98)
+    ZE, ZH = mom.pmchwt_rows(m, b.eps_r, b.mu_r, b.frequency, test)
+    ref = np.concatenate([ZE @ x[0], ZH @ x[0]])
+    ys = {}
+    for prec in ("fp64", "fp32"):
+        p = sfmm.PREC_FP64 if prec == "fp64" else sfmm.PREC_FP32
+        for name, plan in SINGLE_RHS_PLANS.items():
+            print("single-RHS variant", prec, name, flush=True)
+            with sfmm.Context([b], precision=p, finest_box=0.25, extra_multipoles=2, kernel_plan=plan) as ctx:
+                y = ctx.sfmm_matvec(x, np.zeros_like(x))[0]
+            ys[prec, name] = y
+            got = np.concatenate([y[test], y[m.n_edges + test]])
+            print(prec, name, "sampled-row rel err", rel(got, ref))
+            assert rel(got, ref) < 1e-3
+    base = ys["fp64", "flat+box"]
+    for (prec, name), y in ys.items():
+        d = rel(y, base)
+        print(prec, name, "vs fp64 flat+box", d)
+        assert d < (1e-12 if prec == "fp64" else 1e-4)
+
+
 def _oracle_poly(cfg1, degree):
     Zn = np.where(cfg1["pat"], cfg1["Z"], 0)
     return krylov.near_poly_preconditioner(Zn, degree)
