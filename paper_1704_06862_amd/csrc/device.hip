@@ -156,6 +156,13 @@ class DeviceBodyT final : public DeviceBody {
             R.edge_ptr = upload(rt.edge_ptr);
             R.edge_pos = upload(rt.edge_pos);
             R.edge_sign = upload(rt.edge_sign);
+            {
+                std::vector<int> eb(rt.edge_pos.size());
+                for (int b = 0; b + 1 < (int)rt.edge_ptr.size(); ++b)
+                    for (int e = rt.edge_ptr[b]; e < rt.edge_ptr[b + 1]; ++e) eb[e] = b;
+                R.edge_box = upload(eb);
+                R.ne = (int)eb.size();
+            }
             for (int b = 0; b + 1 < (int)rt.edge_ptr.size(); ++b)
                 R.max_ebox = std::max(R.max_ebox, rt.edge_ptr[b + 1] - rt.edge_ptr[b]);
             if (f_ >= 2) {
@@ -535,14 +542,15 @@ class DeviceBodyT final : public DeviceBody {
                 return;
             }
         }
-        if (R == 1 && G.K[f] % 2 == 0 && (size_t)2 * G.K[f] * sizeof(cx<T>) <= LDS_LIMIT) {
-            const size_t shm = (size_t)2 * G.K[f] * sizeof(cx<T>);
+        if (R == 1 && G.K[f] % 2 == 0) {
+            const unsigned grid = nblocks(G.ne, 8 * WAVES);   // eight edges per wavefront
+            if (!grid) return;
             if (G.lossy)
-                k_receive1<T, true><<<G.nbf, WG, shm, stream_>>>(G.K[f], G.edge_ptr, G.edge_pos, G.edge_sign, G.tx,
-                                                                 G.rx, G.inv_et, G.G[f], y);
+                k_receive1<T, true><<<grid, WG, 0, stream_>>>(G.ne, G.K[f], G.edge_box, G.edge_pos, G.edge_sign, G.tx,
+                                                              G.rx, G.inv_et, G.G[f], y);
             else
-                k_receive1<T, false><<<G.nbf, WG, shm, stream_>>>(G.K[f], G.edge_ptr, G.edge_pos, G.edge_sign, G.tx,
-                                                                  nullptr, G.inv_et, G.G[f], y);
+                k_receive1<T, false><<<grid, WG, 0, stream_>>>(G.ne, G.K[f], G.edge_box, G.edge_pos, G.edge_sign,
+                                                               G.tx, nullptr, G.inv_et, G.G[f], y);
             LAUNCHCHK();
             return;
         }
@@ -1383,6 +1391,8 @@ class DeviceBodyT final : public DeviceBody {
         bool lossy = false;
         int nbf = 0, max_ebox = 0;
         int *edge_ptr = nullptr, *edge_pos = nullptr, *edge_sign = nullptr;
+        int *edge_box = nullptr;   // region box of every entry of the region's edge list
+        int ne = 0;                // entries of the region's edge list
         cx<T> *tx = nullptr, *rx = nullptr, *tmp = nullptr;
         int K[MAXLEV] = {0}, nth[MAXLEV] = {0}, nph[MAXLEV] = {0}, nbox[MAXLEV] = {0};
         cx<T> *S[MAXLEV] = {nullptr}, *G[MAXLEV] = {nullptr}, *trans[MAXLEV] = {nullptr};

@@ -1173,71 +1173,65 @@ __global__ void __launch_bounds__(WG) k_receive(int K, int R, const int *__restr
     }
 }
 
-// Receive at the finest level for one right-hand side.  One workgroup per
-// region box with the box's incoming pattern staged in LDS; every wavefront
-// takes eight edges at a time, eight lanes per edge, each lane two adjacent
-// directions per step (one 16-byte load per pattern component for FP32), and
-// the eight partial sums of an edge are combined by three shuffles.  K is
-// even (K = 2 (L + 1)^2), so the pairs never straddle the theta/phi halves.
+// Receive at the finest level for one right-hand side.  The region's edge
+// list (edges grouped by box) is cut into groups of eight consecutive edges,
+// one group per wavefront, so every wavefront has the same work whatever the
+// box sizes: eight lanes per edge, each lane two adjacent directions per step
+// (one 16-byte load per pattern component for FP32), the incoming pattern of
+// the edge's box read through the cache, and the eight partial sums of an edge
+// combined by three shuffles.  K is even (K = 2 (L + 1)^2), so the pairs
+// never straddle the theta/phi halves.
 template <typename T, bool LOSSY>
-__global__ void __launch_bounds__(WG) k_receive1(int K, const int *__restrict__ edge_ptr,
+__global__ void __launch_bounds__(WG) k_receive1(int ne, int K, const int *__restrict__ edge_box,
                                                  const int *__restrict__ edge_pos, const int *__restrict__ edge_sign,
                                                  const cx<T> *__restrict__ tx, const cx<T> *__restrict__ rx,
                                                  cx<T> inv_et, const cx<T> *__restrict__ G, cx<T> *__restrict__ y) {
-    extern __shared__ unsigned char lds_raw[];
-    cx<T> *gs = reinterpret_cast<cx<T> *>(lds_raw);   // [2][K]
-    const int b = blockIdx.x;
-    const cx<T> *g = G + (size_t)b * 2 * K;
-    for (int i = threadIdx.x; i < 2 * K; i += WG) gs[i] = g[i];
-    __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int sub = lane & 7, slot = lane >> 3;
-    const int e1 = edge_ptr[b + 1];
+    const int lane = threadIdx.x & 63;
+    const int sub = lane & 7;
+    const int ie = (blockIdx.x * WAVES + (threadIdx.x >> 6)) * 8 + (lane >> 3);
     const cx<T> *tab = LOSSY ? rx : tx;
-    for (int base = edge_ptr[b] + wave * 8; base < e1; base += WAVES * 8) {
-        const int ie = base + slot;
-        cx<T> aE = {0, 0}, aH = {0, 0};
-        if (ie < e1) {
-            const cx<T> *Rp = tab + (size_t)ie * 2 * K;
+    cx<T> aE = {0, 0}, aH = {0, 0};
+    if (ie < ne) {
+        const cx<T> *Rp = tab + (size_t)ie * 2 * K;
+        const cx<T> *g = G + (size_t)edge_box[ie] * 2 * K;
 #pragma unroll 3
-            for (int k = 2 * sub; k < K; k += 16) {
-                cx<T> rt0 = Rp[k], rt1 = Rp[k + 1], rp0 = Rp[K + k], rp1 = Rp[K + k + 1];
-                if (!LOSSY) {
-                    rt0 = cconj(rt0);
-                    rt1 = cconj(rt1);
-                    rp0 = cconj(rp0);
-                    rp1 = cconj(rp1);
-                }
-                const cx<T> gt0 = gs[k], gt1 = gs[k + 1], gp0 = gs[K + k], gp1 = gs[K + k + 1];
-                cfma(aE, rt0, gt0);
-                cfma(aE, rp0, gp0);
-                cfms(aH, rt0, gp0);
-                cfma(aH, rp0, gt0);
-                cfma(aE, rt1, gt1);
-                cfma(aE, rp1, gp1);
-                cfms(aH, rt1, gp1);
-                cfma(aH, rp1, gt1);
+        for (int k = 2 * sub; k < K; k += 16) {
+            cx<T> rt0 = Rp[k], rt1 = Rp[k + 1], rp0 = Rp[K + k], rp1 = Rp[K + k + 1];
+            if (!LOSSY) {
+                rt0 = cconj(rt0);
+                rt1 = cconj(rt1);
+                rp0 = cconj(rp0);
+                rp1 = cconj(rp1);
             }
+            const cx<T> gt0 = g[k], gt1 = g[k + 1], gp0 = g[K + k], gp1 = g[K + k + 1];
+            cfma(aE, rt0, gt0);
+            cfma(aE, rp0, gp0);
+            cfms(aH, rt0, gp0);
+            cfma(aH, rp0, gt0);
+            cfma(aE, rt1, gt1);
+            cfma(aE, rp1, gp1);
+            cfms(aH, rt1, gp1);
+            cfma(aH, rp1, gt1);
         }
+    }
 #pragma unroll
-        for (int m = 1; m < 8; m <<= 1) {
-            aE.x += __shfl_xor(aE.x, m, 64);
-            aE.y += __shfl_xor(aE.y, m, 64);
-            aH.x += __shfl_xor(aH.x, m, 64);
-            aH.y += __shfl_xor(aH.y, m, 64);
-        }
-        if (ie < e1 && sub == 0) {
-            const int p = edge_pos[ie];
-            const T s = (T)edge_sign[ie];
-            const cx<T> hh = cmul(aH, inv_et);
-            cx<T> ye = y[2 * p], yh = y[2 * p + 1];
-            ye.x += s * aE.x;
-            ye.y += s * aE.y;
-            yh.x += s * hh.x;
-            yh.y += s * hh.y;
-            y[2 * p] = ye;
-            y[2 * p + 1] = yh;
-        }
+    for (int m = 1; m < 8; m <<= 1) {
+        aE.x += __shfl_xor(aE.x, m, 64);
+        aE.y += __shfl_xor(aE.y, m, 64);
+        aH.x += __shfl_xor(aH.x, m, 64);
+        aH.y += __shfl_xor(aH.y, m, 64);
+    }
+    if (ie < ne && sub == 0) {
+        const int p = edge_pos[ie];
+        const T s = (T)edge_sign[ie];
+        const cx<T> hh = cmul(aH, inv_et);
+        cx<T> ye = y[2 * p], yh = y[2 * p + 1];
+        ye.x += s * aE.x;
+        ye.y += s * aE.y;
+        yh.x += s * hh.x;
+        yh.y += s * hh.y;
+        y[2 * p] = ye;
+        y[2 * p + 1] = yh;
     }
 }
 
