@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes of one k_near launch at this size from rocprofv3 --pmc: FETCH_SIZE
 # (KiB) x 2.0 + WRITE_SIZE (KiB) x 1.0, the factors being what the counters
 # read for a plain 256 MiB device copy (profiles/near_product_sphere61440_pmc_traffic.md)
-NEAR_TRAFFIC_BYTES = int((154369 * 2.0 + 523) * 1024)
+NEAR_TRAFFIC_BYTES = int((154601 * 2.0 + 525) * 1024)
 
 
 def parse():
@@ -89,8 +89,10 @@ def sweep(ctx, ctx_mixed, torch, n_ang, every):
       mixed            bf16-split matrix-core products, all angles at once;
       learned_in_sweep bf16-split: every `every`-th angle solved loosely
                        (1e-2) first, the network trained on those currents,
-                       then all angles solved from its predictions (the
-                       loose solves, training and prediction are timed);
+                       then all angles solved to the tolerance, the others
+                       from the network's predictions and the training angles
+                       from their loose solutions (the loose solves, training
+                       and prediction are timed);
       learned_pretrained bf16-split, network trained beforehand on a coarse
                        sweep at the mid-points (reported apart): prediction and
                        one batched solve of all angles from it are timed;
@@ -140,6 +142,7 @@ def sweep(ctx, ctx_mixed, torch, n_ang, every):
         loss = ctx_mixed.sfmm_guess_fit(ang[tr], x_tr)
         x0 = torch.zeros_like(b)
         ctx_mixed.sfmm_guess_predict(ang, x0)
+        x0.index_copy_(0, tr_t, x_tr)   # the training angles restart from their loose solutions
         torch.cuda.synchronize()
         t_fit = time.perf_counter() - t_fit
         x_all = torch.zeros_like(b)
@@ -196,11 +199,15 @@ def sweep(ctx, ctx_mixed, torch, n_ang, every):
                              "batched_bf16split_span_projection_pretrained": round(t_plain / t_sp, 2)},
         "iterations_mean_max": {"plain_fp32": its(i_plain), "batched_fp32": its(i_batch),
                             "batched_bf16split": its(i_mixed), "in_sweep_training_solves_1e-2": its(i_tr),
-                            "in_sweep_all_angles_from_guess": its(i_te), "pretrained": its(i_am),
+                            "in_sweep_all_angles_final": its(i_te),
+                            "in_sweep_predicted_angles": its([i_te[k] for k in te]),
+                            "in_sweep_training_angles_restarted": its([i_te[k] for k in tr]),
+                            "pretrained": its(i_am),
                             "span_projection_pretrained": its(i_sp)},
         "true_residual_max": max(i["true_residual"] for i in i_plain + i_batch + i_mixed + i_te + i_am + i_sp),
         "guess_in_sweep": {"trained_on": len(tr), "fit_and_predict_s": round(t_fit, 3), "loss": loss,
-                           "initial_residual_median": float(np.median([i["initial_residual"] for i in i_te])),
+                           "initial_residual_median_predicted": float(np.median([i_te[k]["initial_residual"]
+                                                                                 for k in te])),
                            "used": int(sum(i["guess_used"] for i in i_te))},
         "guess_pretrained": {"trained_on": len(mid), "coarse_solve_and_fit_s": round(t_pre, 3), "loss": loss_pre,
                              "initial_residual_median": float(np.median([i["initial_residual"] for i in i_am])),

@@ -102,3 +102,34 @@ def test_uneven_bodies_solved_concurrently():
         assert all(a["converged"] for a in conc[i])
         assert [a["iterations"] for a in conc[i]] == [a["iterations"] for a in seq[i]]
         assert float(torch.linalg.norm(xc[i] - xs[i]) / torch.linalg.norm(xs[i])) < 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_sphere_15360_rcs_vs_stored_oracle(prec):
+    # the bench's tree (r = 2 wavelengths, 0.25-wavelength boxes, 5 levels,
+    # 3 digits) on the s = 4 mesh, against the oracle's dense LU solution of
+    # the same mesh (tests/golden/sphere15360_rcs.txt, written by the oracle
+    # alone); bf16-split runs as a batch of 16 angles so the products go
+    # through the matrix cores, and the theta = 0 member is compared
+    import os
+    gold = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "sphere15360_rcs.txt"))
+    body = sphere_body(2.0, 2.56, 4)
+    p = sfmm.PREC_FP32 if prec == "fp32" else sfmm.PREC_BF16_SPLIT
+    nr = 1 if prec == "fp32" else 16
+    ang = np.zeros((nr, 2))
+    ang[:, 0] = np.linspace(0.0, np.pi, nr, endpoint=False)
+    print("setup 15,360-unknown sphere", prec, flush=True)
+    with sfmm.Context([body], finest_box=0.25, n_levels=5, digits=3.0, precision=p, gmres_restart=50,
+                      tol=1e-4) as ctx:
+        n = ctx.sfmm_num_unknowns()
+        assert n == 15360
+        b = ctx.sfmm_planewave_rhs(ang, np.zeros((nr, n), dtype=complex))
+        x = np.zeros_like(b)
+        info = ctx.sfmm_solve(b, x)
+        x0 = np.ascontiguousarray(x[:1])
+        sE = ctx.sfmm_rcs(x0, np.stack([THETA, 0 * THETA], 1))[0, :, 0]
+        sH = ctx.sfmm_rcs(x0, np.stack([THETA, 0 * THETA + np.pi / 2], 1))[0, :, 1]
+    assert all(i["converged"] and i["true_residual"] <= 1e-4 for i in info)
+    (rE, xE), (rH, xH) = db_stats(sE, gold[:, 1]), db_stats(sH, gold[:, 2])
+    print(prec, info[0], "vs oracle: E-plane RMS/max dB", rE, xE, "H-plane", rH, xH)
+    assert xE < 0.2 and xH < 0.2
