@@ -87,12 +87,11 @@ def sweep(ctx, ctx_mixed, torch, n_ang, every):
       plain            FP32, one right-hand side per solve, zero start;
       batched          FP32, all angles in one lockstep solve;
       mixed            bf16-split matrix-core products, all angles at once;
-      learned_in_sweep bf16-split: every `every`-th angle solved loosely
-                       (1e-2) first, the network trained on those currents,
-                       then all angles solved to the tolerance, the others
-                       from the network's predictions and the training angles
-                       from their loose solutions (the loose solves, training
-                       and prediction are timed);
+      learned_in_sweep bf16-split: every `every`-th angle solved first (to
+                       the tolerance: those angles are done), the network
+                       trained on their currents, then the other angles
+                       solved from its predictions (solves, training and
+                       prediction all timed);
       learned_pretrained bf16-split, network trained beforehand on a coarse
                        sweep at the mid-points (reported apart): prediction and
                        one batched solve of all angles from it are timed;
@@ -131,22 +130,20 @@ def sweep(ctx, ctx_mixed, torch, n_ang, every):
     te_t = torch.from_numpy(te).to("cuda")
 
     def learned():
-        # training currents from a loose solve (1e-2) of every `every`-th
-        # angle; then every angle is solved to the tolerance from its guess
+        # the training angles are solved to the tolerance (they are then
+        # done); the network learns their currents and starts the others
         b_tr = b.index_select(0, tr_t).contiguous()
         x_tr = torch.zeros_like(b_tr)
-        ctx_mixed.sfmm_set_solver(tol=1e-2)
         i_tr = ctx_mixed.sfmm_solve(b_tr, x_tr)
-        ctx_mixed.sfmm_set_solver(tol=1e-4)
         t_fit = time.perf_counter()
         loss = ctx_mixed.sfmm_guess_fit(ang[tr], x_tr)
-        x0 = torch.zeros_like(b)
-        ctx_mixed.sfmm_guess_predict(ang, x0)
-        x0.index_copy_(0, tr_t, x_tr)   # the training angles restart from their loose solutions
+        b_te = b.index_select(0, te_t).contiguous()
+        x0 = torch.zeros_like(b_te)
+        ctx_mixed.sfmm_guess_predict(ang[te], x0)
         torch.cuda.synchronize()
         t_fit = time.perf_counter() - t_fit
-        x_all = torch.zeros_like(b)
-        i_te = ctx_mixed.sfmm_solve(b, x_all, x0=x0)
+        x_te = torch.zeros_like(b_te)
+        i_te = ctx_mixed.sfmm_solve(b_te, x_te, x0=x0)
         return i_tr, i_te, loss, t_fit
 
     # a network trained beforehand on a coarse sweep (the mid-points of this
@@ -184,7 +181,7 @@ def sweep(ctx, ctx_mixed, torch, n_ang, every):
 
     (i_tr, i_te, loss, t_fit), t_learn = timed(learned)
     ok = all(i["converged"] for i in i_plain + i_batch + i_mixed + i_tr + i_te + i_mid + i_am + i_sp)
-    assert len(i_te) == n_ang
+    assert len(i_tr) + len(i_te) == n_ang
     ms = lambda t: round(1e3 * t / n_ang, 2)  # noqa: E731
     return {
         "angles": n_ang, "tol": 1e-4,
@@ -198,16 +195,13 @@ def sweep(ctx, ctx_mixed, torch, n_ang, every):
                              "batched_bf16split_learned_pretrained": round(t_plain / t_am, 2),
                              "batched_bf16split_span_projection_pretrained": round(t_plain / t_sp, 2)},
         "iterations_mean_max": {"plain_fp32": its(i_plain), "batched_fp32": its(i_batch),
-                            "batched_bf16split": its(i_mixed), "in_sweep_training_solves_1e-2": its(i_tr),
-                            "in_sweep_all_angles_final": its(i_te),
-                            "in_sweep_predicted_angles": its([i_te[k] for k in te]),
-                            "in_sweep_training_angles_restarted": its([i_te[k] for k in tr]),
+                            "batched_bf16split": its(i_mixed), "in_sweep_training_angles": its(i_tr),
+                            "in_sweep_predicted_angles": its(i_te),
                             "pretrained": its(i_am),
                             "span_projection_pretrained": its(i_sp)},
-        "true_residual_max": max(i["true_residual"] for i in i_plain + i_batch + i_mixed + i_te + i_am + i_sp),
+        "true_residual_max": max(i["true_residual"] for i in i_plain + i_batch + i_mixed + i_tr + i_te + i_am + i_sp),
         "guess_in_sweep": {"trained_on": len(tr), "fit_and_predict_s": round(t_fit, 3), "loss": loss,
-                           "initial_residual_median_predicted": float(np.median([i_te[k]["initial_residual"]
-                                                                                 for k in te])),
+                           "initial_residual_median": float(np.median([i["initial_residual"] for i in i_te])),
                            "used": int(sum(i["guess_used"] for i in i_te))},
         "guess_pretrained": {"trained_on": len(mid), "coarse_solve_and_fit_s": round(t_pre, 3), "loss": loss_pre,
                              "initial_residual_median": float(np.median([i["initial_residual"] for i in i_am])),
