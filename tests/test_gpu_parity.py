@@ -268,6 +268,25 @@ def test_solve_iterations_match_oracle_gmres(cfg1, ctx64):
     assert abs(info["iterations"] - oinfo.iterations) <= 3
 
 
+def test_product_bytes_follow_the_tables(cfg1, ctx32, ctx64):
+    # algorithmic bytes of one product, checked against the octree and
+    # sampling the library reports: three complex numbers per near edge pair,
+    # x and y once, the transmit table (2 K_f directions per edge and region,
+    # K = 2 (L + 1)^2) read twice for real wavenumbers, element size by precision
+    ne = cfg1["mesh"].n_edges
+    for ctx, cb in ((ctx32, 8), (ctx64, 16)):
+        d = ctx.sfmm_describe()
+        pb = ctx.sfmm_product_bytes()
+        f = d["levels"] - 1
+        assert pb["near"] >= 3 * cb * d["near_pairs"]
+        assert pb["near"] - 3 * cb * d["near_pairs"] <= 4 * d["near_pairs"]   # one int32 per (box, column)
+        assert pb["x_y"] == 2 * 2 * ne * cb
+        K = [2 * (int(d["truncation"][r, f]) + 1) ** 2 for r in range(2)]
+        assert pb["patterns"] == sum(2 * ne * 2 * k * cb for k in K)
+        assert pb["levels"] > 0 and pb["translation"] > 0
+        assert pb["total"] == sum(v for k, v in pb.items() if k != "total")
+
+
 def test_device_pointers_match_host_path(cfg1, ctx32):
     torch = pytest.importorskip("torch")
     x = cfg1["x"]
