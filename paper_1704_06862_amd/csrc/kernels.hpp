@@ -74,7 +74,7 @@ __device__ __forceinline__ void edge_block(const cx<T> *__restrict__ d, cx<T> &e
 
 constexpr int WG = 256;
 constexpr int WAVES = WG / 64;
-constexpr int RW = 16;              // rows (wavefronts) per near/ILU workgroup
+constexpr int RW = 8;               // rows (wavefronts) per near/ILU workgroup
 constexpr int RWG = RW * 64;
 constexpr int UPR = 4;              // parent theta rows per upward workgroup
 constexpr int UPMAX = 8;            // outputs per thread in the upward kernel
