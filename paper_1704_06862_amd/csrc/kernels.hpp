@@ -1074,10 +1074,14 @@ __global__ void __launch_bounds__(WG) k_translate_grp(int K, int R, const int *_
                                                       const cx<T> *__restrict__ trans, const cx<T> *__restrict__ S,
                                                       cx<T> *__restrict__ G) {
     constexpr int DPW = WG / RP;   // directions per workgroup
+    constexpr int DW = 64 / RP;    // directions per wavefront
     const int g = blockIdx.x;
     const int rr = threadIdx.x % RP;
     int k = blockIdx.y * DPW + threadIdx.x / RP;
     if (RP == 64) k = __builtin_amdgcn_readfirstlane(k);
+    // first direction of this wavefront (wave-uniform)
+    const int kw = __builtin_amdgcn_readfirstlane((int)(blockIdx.y * DPW + (threadIdx.x >> 6) * DW));
+    const int q = (threadIdx.x & 63) / RP;   // this lane's direction within the wavefront
     if (k >= K || rr >= R) return;
     const int64_t KR = (int64_t)K * R;
     const int64_t kr = (int64_t)k * R + rr;
@@ -1104,7 +1108,20 @@ __global__ void __launch_bounds__(WG) k_translate_grp(int K, int R, const int *_
         for (int j = 0; j < 8; ++j) {
             const int o = cand_off[(int64_t)c * 8 + j];
             if (o >= 0) {
-                const cx<T> t = trans[(int64_t)o * K + k];
+                cx<T> t;
+                if constexpr (RP >= 16 && RP < 64) {
+                    // two or four directions per wavefront: uniform loads of
+                    // their samples, each lane takes its own
+                    const cx<T> *row = trans + (int64_t)o * K + kw;
+                    t = row[0];
+#pragma unroll
+                    for (int d = 1; d < DW; ++d) {
+                        const cx<T> td = kw + d < K ? row[d] : cx<T>{0, 0};
+                        if (q == d) t = td;
+                    }
+                } else {
+                    t = trans[(int64_t)o * K + k];
+                }
                 cfma(acc[j][0], t, s0);
                 cfma(acc[j][1], t, s1);
             }
