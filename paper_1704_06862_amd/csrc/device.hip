@@ -834,8 +834,13 @@ class DeviceBodyT final : public DeviceBody {
     }
     bool split_all(int l, int R) const {
         if ((int)regs_.size() > SPLIT_MAXJOB) return false;
-        for (const Reg &G : regs_)
+        for (const Reg &G : regs_) {
             if (!split_ok(G, l, R)) return false;
+            // the kernels index their items in 32 bits
+            const int64_t up = (int64_t)G.nbox[l] * 2 * G.nth[l - 1] * G.nph[l],
+                          dn = (int64_t)std::max(G.nbox[l - 1], G.nbox[l]) * 2 * G.nth[l - 1] * G.nph[l - 1];
+            if (std::max(up, dn) + 1024 >= ((int64_t)1 << 31)) return false;
+        }
         return true;
     }
     template <typename P, typename K64, typename K256>

@@ -714,11 +714,11 @@ __global__ void __launch_bounds__(BS) k_up_theta1(const JobList<ThetaJob<T>> jl)
     }
     __syncthreads();
     const int h = nph_c / 2, np2 = (nth_p + 1) / 2;
-    const int64_t id = (int64_t)local * BS + threadIdx.x;
-    if (id >= (int64_t)a.ncc * np2 * h) return;
+    const int id = local * BS + (int)threadIdx.x;   // item counts fit in 32 bits (checked by the host)
+    if (id >= a.ncc * np2 * h) return;
     const int j = id % h;
-    const int I = 2 * (int)((id / h) % np2);
-    const int64_t cc = id / ((int64_t)h * np2);
+    const int I = 2 * ((id / h) % np2);
+    const int64_t cc = id / (h * np2);
     const bool two = I + 1 < nth_p;
     const int I1 = two ? I + 1 : I;
     const cx<T> *f = a.in + cc * nth_c * nph_c;
@@ -756,10 +756,10 @@ __global__ void __launch_bounds__(BS) k_up_phi1(const JobList<UpPhiJob<T>> jl) {
     for (int t = threadIdx.x; t < nph_c * nph_p; t += BS) Ds[t] = a.Dt[t];
     __syncthreads();
     const int Kp = nth_p * nph_p, hp = nph_p / 2;
-    const int64_t id = (int64_t)local * BS + threadIdx.x;
-    if (id >= (int64_t)a.nparent * 2 * nth_p * hp) return;
-    const int J = 2 * (int)(id % hp);
-    int64_t q = id / hp;
+    const int id = local * BS + (int)threadIdx.x;
+    if (id >= a.nparent * 2 * nth_p * hp) return;
+    const int J = 2 * (id % hp);
+    int q = id / hp;
     const int I = q % nth_p;
     q /= nth_p;
     const int comp = q % 2;
@@ -797,10 +797,10 @@ __global__ void __launch_bounds__(BS) k_dn_phi1(const JobList<DnPhiJob<T>> jl) {
     for (int t = threadIdx.x; t < nph_p * nph_c; t += BS) Ds[t] = a.D[t];
     __syncthreads();
     const int Kp = nth_p * nph_p, hc = nph_c / 2;
-    const int64_t id = (int64_t)local * BS + threadIdx.x;
-    if (id >= (int64_t)a.nchild * 2 * nth_p * hc) return;
-    const int j = 2 * (int)(id % hc);
-    int64_t q = id / hc;
+    const int id = local * BS + (int)threadIdx.x;
+    if (id >= a.nchild * 2 * nth_p * hc) return;
+    const int j = 2 * (id % hc);
+    int q = id / hc;
     const int I = q % nth_p;
     q /= nth_p;
     const int comp = q % 2;
@@ -836,11 +836,11 @@ __global__ void __launch_bounds__(BS) k_dn_theta1(const JobList<ThetaJob<T>> jl)
     }
     __syncthreads();
     const int h = nph_c / 2, nc2 = (nth_c + 1) / 2;
-    const int64_t id = (int64_t)local * BS + threadIdx.x;
-    if (id >= (int64_t)a.ncc * nc2 * h) return;
+    const int id = local * BS + (int)threadIdx.x;
+    if (id >= a.ncc * nc2 * h) return;
     const int j = id % h;
-    const int i = 2 * (int)((id / h) % nc2);
-    const int64_t cc = id / ((int64_t)h * nc2);
+    const int i = 2 * ((id / h) % nc2);
+    const int64_t cc = id / (h * nc2);
     const bool two = i + 1 < nth_c;
     const int i1 = two ? i + 1 : i;
     const cx<T> *g = a.in + cc * nth_p * nph_c;
