@@ -230,39 +230,65 @@ class Context:
         _check(lib().sfmm_edges(self.ctx, body, out.ctypes.data), self.ctx)
         return out
 
-    def _vec_args(self, x, y):
-        px, dx = _ptr(x)
-        py, dy = _ptr(y)
+    def _vec(self, a, n_rhs, body, name):
+        """Pointer and location of a block of n_rhs complex128 vectors of the
+        body's 2E unknowns; the library reads or writes exactly that many
+        numbers, so the size is checked here."""
+        if isinstance(a, np.ndarray):
+            ok = a.dtype == np.complex128
+            size = a.size
+        elif hasattr(a, "numel"):
+            ok = str(a.dtype) == "torch.complex128"
+            size = a.numel()
+        else:
+            raise TypeError(f"{name}: numpy array or torch tensor expected")
+        if not ok:
+            raise TypeError(f"{name} must be complex128")
+        n = self.sfmm_num_unknowns(body)
+        if size != n_rhs * n:
+            raise ValueError(f"{name} must hold {n_rhs} x {n} complex numbers, not {size}")
+        return _ptr(a)
+
+    @staticmethod
+    def _rows(a):
+        if a.ndim not in (1, 2):
+            raise ValueError("vectors are [n] or [n_rhs][n]")
+        return a.shape[0] if a.ndim == 2 else 1
+
+    def _vec_args(self, x, y, body):
+        n_rhs = self._rows(x)
+        px, dx = self._vec(x, n_rhs, body, "x")
+        py, dy = self._vec(y, n_rhs, body, "y")
         if dx != dy:
             raise ValueError("x and y must both be host or both be device arrays")
-        n = self.sfmm_num_unknowns(0)
-        return px, py, dx
+        return px, py, dx, n_rhs
 
     def sfmm_matvec(self, x, y, body=0, parts=PART_ALL):
-        px, py, dev = self._vec_args(x, y)
-        n_rhs = x.shape[0] if x.ndim == 2 else 1
+        px, py, dev, n_rhs = self._vec_args(x, y, body)
         _check(lib().sfmm_matvec(self.ctx, body, n_rhs, px, py, dev, parts), self.ctx)
         return y
 
     def sfmm_precond(self, x, y, body=0):
-        px, py, dev = self._vec_args(x, y)
-        n_rhs = x.shape[0] if x.ndim == 2 else 1
+        px, py, dev, n_rhs = self._vec_args(x, y, body)
         _check(lib().sfmm_precond(self.ctx, body, n_rhs, px, py, dev), self.ctx)
         return y
 
     def sfmm_planewave_rhs(self, angles, b, pol=None, body=0):
         angles = np.ascontiguousarray(angles, dtype=np.float64).reshape(-1, 2)
         polv = None if pol is None else np.ascontiguousarray(pol, dtype=np.float64)
-        pb, dev = _ptr(b)
+        pb, dev = self._vec(b, len(angles), body, "b")
         _check(lib().sfmm_planewave_rhs(self.ctx, body, len(angles), angles.ctypes.data,
                                         None if polv is None else polv.ctypes.data, pb, dev), self.ctx)
         return b
 
     def sfmm_solve(self, b, x, x0=None, body=0, raise_on_nonconvergence=False):
-        pb, px, dev = self._vec_args(b, x)
-        n_rhs = b.shape[0] if b.ndim == 2 else 1
+        pb, px, dev, n_rhs = self._vec_args(b, x, body)
         info = (sfmm_solve_info * n_rhs)()
-        p0 = None if x0 is None else _ptr(x0)[0]
+        p0 = None
+        if x0 is not None:
+            p0, d0 = self._vec(x0, n_rhs, body, "x0")
+            if d0 != dev:
+                raise ValueError("x0 must be where b and x are")
         st = lib().sfmm_solve(self.ctx, body, n_rhs, pb, px, p0, info, dev)
         if st != SFMM_OK and (st != 5 or raise_on_nonconvergence):
             _check(st, self.ctx)
@@ -278,12 +304,12 @@ class Context:
         Returns one list of info dicts per problem."""
         n = len(problems)
         bodies = np.array([p[0] for p in problems], dtype=np.int32)
-        n_rhs = np.array([p[1].shape[0] if p[1].ndim == 2 else 1 for p in problems], dtype=np.int32)
+        n_rhs = np.array([self._rows(p[1]) for p in problems], dtype=np.int32)
         devs = set()
         pb, px = (ctypes.c_void_p * n)(), (ctypes.c_void_p * n)()
-        for i, (_, b, x) in enumerate(problems):
-            pb[i], d1 = _ptr(b)
-            px[i], d2 = _ptr(x)
+        for i, (bi, b, x) in enumerate(problems):
+            pb[i], d1 = self._vec(b, int(n_rhs[i]), bi, "b")
+            px[i], d2 = self._vec(x, int(n_rhs[i]), bi, "x")
             devs.update((d1, d2))
         if len(devs) != 1:
             raise ValueError("all vectors must be host arrays or all device arrays")
@@ -304,7 +330,7 @@ class Context:
         incidences angles [n][2]; returns the final training loss."""
         angles = np.ascontiguousarray(angles, dtype=np.float64).reshape(-1, 2)
         polv = None if pol is None else np.ascontiguousarray(pol, dtype=np.float64)
-        px, dev = _ptr(x)
+        px, dev = self._vec(x, len(angles), body, "x")
         go = sfmm_guess_default_options(**options)
         loss = ctypes.c_double(0.0)
         _check(lib().sfmm_guess_fit(self.ctx, body, len(angles), angles.ctypes.data,
@@ -315,7 +341,7 @@ class Context:
     def sfmm_span_predict(self, angles, x0, pol=None, body=0):
         angles = np.ascontiguousarray(angles, dtype=np.float64).reshape(-1, 2)
         polv = None if pol is None else np.ascontiguousarray(pol, dtype=np.float64)
-        px, dev = _ptr(x0)
+        px, dev = self._vec(x0, len(angles), body, "x0")
         _check(lib().sfmm_span_predict(self.ctx, body, len(angles), angles.ctypes.data,
                                        None if polv is None else polv.ctypes.data, px, dev), self.ctx)
         return x0
@@ -323,15 +349,15 @@ class Context:
     def sfmm_guess_predict(self, angles, x0, pol=None, body=0):
         angles = np.ascontiguousarray(angles, dtype=np.float64).reshape(-1, 2)
         polv = None if pol is None else np.ascontiguousarray(pol, dtype=np.float64)
-        px, dev = _ptr(x0)
+        px, dev = self._vec(x0, len(angles), body, "x0")
         _check(lib().sfmm_guess_predict(self.ctx, body, len(angles), angles.ctypes.data,
                                         None if polv is None else polv.ctypes.data, px, dev), self.ctx)
         return x0
 
     def sfmm_rcs(self, x, theta_phi, body=0):
-        px, dev = _ptr(x)
+        n_rhs = self._rows(x)
+        px, dev = self._vec(x, n_rhs, body, "x")
         tp = np.ascontiguousarray(theta_phi, dtype=np.float64).reshape(-1, 2)
-        n_rhs = x.shape[0] if x.ndim == 2 else 1
         sigma = np.zeros((n_rhs, len(tp), 2))
         _check(lib().sfmm_rcs(self.ctx, body, n_rhs, px, len(tp), tp.ctypes.data, sigma.ctypes.data, dev), self.ctx)
         return sigma

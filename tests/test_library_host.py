@@ -40,6 +40,29 @@ def test_host_only_context_refuses_device_calls():
         assert e.value.status == 1
 
 
+def test_binding_checks_vector_sizes_and_types():
+    # the library reads and writes n_rhs x 2E complex numbers through plain
+    # pointers, so the binding refuses anything else before calling it
+    b = sphere_body(0.3, 4.0, 1)
+    with sfmm.Context([b], device=-1) as ctx:
+        n = ctx.sfmm_num_unknowns()
+        good = np.zeros((2, n), dtype=complex)
+        with pytest.raises(ValueError):
+            ctx.sfmm_matvec(good, np.zeros((2, n - 1), dtype=complex))
+        with pytest.raises(ValueError):
+            ctx.sfmm_solve(good, good.copy(), x0=np.zeros((1, n), dtype=complex))
+        with pytest.raises(TypeError):
+            ctx.sfmm_matvec(good.astype(np.complex64), good.copy())
+        with pytest.raises(ValueError):
+            ctx.sfmm_planewave_rhs(np.zeros((3, 2)), good)
+        with pytest.raises(ValueError):
+            ctx.sfmm_rcs(np.zeros((2, n + 2), dtype=complex), np.zeros((4, 2)))
+        with pytest.raises(ValueError):
+            ctx.sfmm_guess_predict(np.zeros((1, 2)), good)
+        with pytest.raises(ValueError):
+            ctx.sfmm_solve_bodies([(0, good, np.zeros((2, 3 * n), dtype=complex))])
+
+
 def test_canonical_edges_and_near_rows_match_oracle():
     b = sphere_body(0.3, 4.0, 2)
     m = rwg.from_body(b)
