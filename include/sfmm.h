@@ -87,7 +87,9 @@ typedef struct {
  * boxes (960-unknown sphere, eps_r = 4) one extra multipole keeps the FP32
  * product within 1.2e-3 of the dense matrix, while five give 0.12 (FP64:
  * 4e-4); at 0.25-wavelength boxes and above the excess-bandwidth order is safe
- * in FP32.  FP64 has no such limit at these sizes. */
+ * in FP32.  FP64 has no such limit at these sizes.  sfmm_setup refuses FP32
+ * and BF16_SPLIT (SFMM_E_UNSUPPORTED) where an estimate of this amplification
+ * at a level's closest translation offset times the FP32 rounding exceeds 5. */
 enum { SFMM_PREC_FP32 = 0, SFMM_PREC_BF16_SPLIT = 1, SFMM_PREC_FP64 = 2 };
 
 typedef struct {

@@ -63,6 +63,22 @@ def test_binding_checks_vector_sizes_and_types():
             ctx.sfmm_solve_bodies([(0, good, np.zeros((2, 3 * n), dtype=complex))])
 
 
+def test_fp32_refused_where_translations_amplify_rounding():
+    # 0.15-wavelength boxes with five extra multipoles: FP32 products would be
+    # 12 % off the dense matrix (FP64 4e-4), so single-precision setups are
+    # refused; one extra multipole, or FP64, is accepted
+    b = sphere_body(0.3, 4.0, 2)
+    opts = dict(device=-1, finest_box=0.15, n_levels=3)
+    for prec in (sfmm.PREC_FP32, sfmm.PREC_BF16_SPLIT):
+        with pytest.raises(sfmm.SfmmError) as e:
+            sfmm.Context([b], precision=prec, extra_multipoles=5, **opts)
+        assert e.value.status == 7 and "FP64" in str(e.value)
+        with sfmm.Context([b], precision=prec, extra_multipoles=1, **opts):
+            pass
+    with sfmm.Context([b], precision=sfmm.PREC_FP64, extra_multipoles=5, **opts):
+        pass
+
+
 def test_canonical_edges_and_near_rows_match_oracle():
     b = sphere_body(0.3, 4.0, 2)
     m = rwg.from_body(b)
