@@ -50,7 +50,11 @@ def parse():
                    help="extra right-hand-side batch sizes measured outside the timed region")
     p.add_argument("--sweep", type=int, default=64, help="angles of the theta sweep (0 = skip)")
     p.add_argument("--train-every", type=int, default=2,
-                   help="learned-guess sweep: solve every n-th angle loosely first and train on those")
+                   help="learned-guess sweep: solve every n-th angle first and train on those")
+    p.add_argument("--sweep-body", choices=["sphere", "coated"], default="sphere",
+                   help="body of the sweep: the benchmark sphere, or the two-layer coated sphere (lossy core "
+                        "r = 1.5, eps 6-0.5j, s = 5; shell r = 2.5, eps 2.56, s = 6; 307,200 unknowns; "
+                        "degree-48 polynomial preconditioner); the coated sweep takes several minutes")
     p.add_argument("--copy-calibration", type=int, default=0,
                    help="MiB of a plain device copy run after the measurements, to scale HBM byte counters")
     return p.parse_args()
@@ -117,8 +121,14 @@ def sweep(ctx, ctx_mixed, torch, n_ang, every):
         # mean and, since a batch iterates in lockstep, the maximum
         return [round(float(np.mean([i["iterations"] for i in infos])), 1), max(i["iterations"] for i in infos)]
 
+    def plain_one(i):
+        if i % 16 == 0:
+            print(f"sweep: plain single-RHS solve {i} of {n_ang}", file=sys.stderr, flush=True)
+        return ctx.sfmm_solve(b[i:i + 1], x[i:i + 1])[0]
+
     x = torch.zeros_like(b)
-    i_plain, t_plain = timed(lambda: [ctx.sfmm_solve(b[i:i + 1], x[i:i + 1])[0] for i in range(n_ang)])
+    i_plain, t_plain = timed(lambda: [plain_one(i) for i in range(n_ang)])
+    print("sweep: batched solves", file=sys.stderr, flush=True)
     x.zero_()
     i_batch, t_batch = timed(lambda: ctx.sfmm_solve(b, x))
     x.zero_()
@@ -329,11 +339,30 @@ def main():
                            "preconditioner": "near-field GMRES polynomial, degree 16"}
         print("gmres", result["gmres"], file=sys.stderr, flush=True)
 
-    if args.sweep > 0:
+    if args.sweep > 0 and args.sweep_body == "sphere":
         ctx_mixed = sfmm.Context([body], **dict(opts, precision=sfmm.PREC_BF16_SPLIT))
         ctx_mixed.sfmm_set_stream(stream.cuda_stream)
         result["sweep"] = sweep(ctx, ctx_mixed, torch, args.sweep, args.train_every)
         ctx_mixed.close()
+        print("sweep", result["sweep"], file=sys.stderr, flush=True)
+    elif args.sweep > 0:
+        from workloads import coated_sphere_body
+
+        ctx.close()
+        coated = coated_sphere_body(1.5, 6 - 0.5j, 5, 2.5, 2.56, 6)
+        copts = dict(opts, poly_degree=48, n_levels=0)   # the 2.5-wavelength shell needs a deeper tree
+        t0 = time.perf_counter()
+        ctx_c = sfmm.Context([coated], **copts)
+        ctx_cm = sfmm.Context([coated], **dict(copts, precision=sfmm.PREC_BF16_SPLIT))
+        for c in (ctx_c, ctx_cm):
+            c.sfmm_set_stream(stream.cuda_stream)
+        print(f"coated sphere setup {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        result["sweep"] = sweep(ctx_c, ctx_cm, torch, args.sweep, args.train_every)
+        result["sweep"]["body"] = ("two-layer coated sphere: core r=1.5 lambda0 eps_r 6-0.5j (s=5), shell r=2.5 "
+                                   "lambda0 eps_r 2.56 (s=6), 307,200 unknowns, 0.25 lambda0 boxes, polynomial "
+                                   "preconditioner degree 48")
+        ctx_c.close()
+        ctx_cm.close()
         print("sweep", result["sweep"], file=sys.stderr, flush=True)
 
     if args.copy_calibration > 0:
