@@ -1,8 +1,8 @@
 """FP64 reference of the learned initial guess for GMRES.
 
-The paper has no learned component; this is the reading adopted for the
-north-star addition "a small network predicts the GMRES initial guess for a new
-incidence angle", written as plain numpy:
+The paper has no learned component; this module is the reference for an
+addition to the method: a small network, trained on solved currents, that
+predicts the GMRES initial guess for a new incidence angle.  Plain numpy:
 
 * POD basis: U = the first r left singular vectors of the matrix of solved
   currents X = [x_1 .. x_n] (complex); coefficients c = U^H x.
