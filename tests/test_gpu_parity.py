@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 sfmm = pytest.importorskip("paper_1704_06862_amd.sfmm")
 
-CFG1 = dict(finest_box=0.15, n_levels=3, extra_multipoles=5, preconditioner=0)
+SPHERE960_OPTS = dict(finest_box=0.15, n_levels=3, extra_multipoles=5, preconditioner=0)
 THETA = np.deg2rad(np.arange(181.0))
 
 
@@ -26,7 +26,7 @@ def rel(a, b):
 
 
 @pytest.fixture(scope="module")
-def cfg1():
+def sphere960():
     b = sphere_body(0.3, 4.0, 2)
     m = rwg.from_body(b)
     Z = mom.pmchwt_dense(m, b.eps_r, b.mu_r, b.frequency)
@@ -37,40 +37,40 @@ def cfg1():
 
 
 @pytest.fixture(scope="module")
-def ctx64(cfg1):
-    print("setup cfg1 fp64", flush=True)
-    with sfmm.Context([cfg1["body"]], precision=sfmm.PREC_FP64, **CFG1) as c:
+def ctx64(sphere960):
+    print("setup sphere960 fp64", flush=True)
+    with sfmm.Context([sphere960["body"]], precision=sfmm.PREC_FP64, **SPHERE960_OPTS) as c:
         yield c
 
 
 @pytest.fixture(scope="module")
-def ctx32(cfg1):
-    print("setup cfg1 fp32", flush=True)
+def ctx32(sphere960):
+    print("setup sphere960 fp32", flush=True)
     # FP32 at 0.15-wavelength boxes: the diagonal translation grows like
     # h_L(kX) at small kX, so single-precision rounding is amplified; keep L
     # at the excess-bandwidth order + 1 here (the 1e-3 FP32 gate is on the
     # 0.25-wavelength multilevel case below)
     # (FP32 solves stop at 1e-4, the tolerance of the FP32 workloads; the
     # rounding noise of an FP32 product limits the attainable residual)
-    opts = dict(CFG1, extra_multipoles=1, tol=1e-4)
-    with sfmm.Context([cfg1["body"]], precision=sfmm.PREC_FP32, **opts) as c:
+    opts = dict(SPHERE960_OPTS, extra_multipoles=1, tol=1e-4)
+    with sfmm.Context([sphere960["body"]], precision=sfmm.PREC_FP32, **opts) as c:
         yield c
 
 
 @pytest.fixture(scope="module")
-def ctxbf(cfg1):
-    print("setup cfg1 bf16-split", flush=True)
-    opts = dict(CFG1, extra_multipoles=1, tol=1e-4)
-    with sfmm.Context([cfg1["body"]], precision=sfmm.PREC_BF16_SPLIT, **opts) as c:
+def ctxbf(sphere960):
+    print("setup sphere960 bf16-split", flush=True)
+    opts = dict(SPHERE960_OPTS, extra_multipoles=1, tol=1e-4)
+    with sfmm.Context([sphere960["body"]], precision=sfmm.PREC_BF16_SPLIT, **opts) as c:
         yield c
 
 
 @pytest.mark.parametrize("R", [16, 20, 64])
-def test_batched_near_on_matrix_cores(cfg1, ctx32, ctxbf, R):
+def test_batched_near_on_matrix_cores(sphere960, ctx32, ctxbf, R):
     # from 16 right-hand sides the near product runs on the matrix cores;
     # 20 leaves a ragged second block of 16
-    x = random_complex_vector(cfg1["x"].shape[1], R, seed=40 + R)
-    ref = x @ np.where(cfg1["pat"], cfg1["Z"], 0).T
+    x = random_complex_vector(sphere960["x"].shape[1], R, seed=40 + R)
+    ref = x @ np.where(sphere960["pat"], sphere960["Z"], 0).T
     for ctx, tol in ((ctx32, 1e-5), (ctxbf, 5e-5)):
         y = ctx.sfmm_matvec(x, np.zeros_like(x), parts=sfmm.PART_NEAR)
         err = max(rel(y[r], ref[r]) for r in range(R))
@@ -79,11 +79,11 @@ def test_batched_near_on_matrix_cores(cfg1, ctx32, ctxbf, R):
 
 
 @pytest.mark.parametrize("R", [16, 64])
-def test_batched_full_product_on_matrix_cores(cfg1, ctx32, ctxbf, R):
+def test_batched_full_product_on_matrix_cores(sphere960, ctx32, ctxbf, R):
     # aggregation, receive (and, from 33 RHS, the sibling-grouped translation)
     # switch to their batched kernels
-    x = random_complex_vector(cfg1["x"].shape[1], R, seed=60 + R)
-    ref = x @ cfg1["Z"].T
+    x = random_complex_vector(sphere960["x"].shape[1], R, seed=60 + R)
+    ref = x @ sphere960["Z"].T
     for ctx in (ctx32, ctxbf):
         y = ctx.sfmm_matvec(x, np.zeros_like(x))
         err = max(rel(y[r], ref[r]) for r in range(R))
@@ -131,26 +131,26 @@ def test_coated_lossy_sphere_product_and_rcs(coated, prec):
         assert _masked_db(sE, rE).max() < 0.2
 
 
-def test_near_product_fp64(cfg1, ctx64):
-    x = cfg1["x"]
+def test_near_product_fp64(sphere960, ctx64):
+    x = sphere960["x"]
     y = ctx64.sfmm_matvec(x, np.zeros_like(x), parts=sfmm.PART_NEAR)
-    ref = x @ np.where(cfg1["pat"], cfg1["Z"], 0).T
+    ref = x @ np.where(sphere960["pat"], sphere960["Z"], 0).T
     assert rel(y, ref) < 1e-11
 
 
-def test_near_product_fp32(cfg1, ctx32):
-    x = cfg1["x"]
+def test_near_product_fp32(sphere960, ctx32):
+    x = sphere960["x"]
     y = ctx32.sfmm_matvec(x, np.zeros_like(x), parts=sfmm.PART_NEAR)
-    ref = x @ np.where(cfg1["pat"], cfg1["Z"], 0).T
+    ref = x @ np.where(sphere960["pat"], sphere960["Z"], 0).T
     assert rel(y, ref) < 1e-5
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
-def test_full_product_matches_dense(cfg1, ctx64, ctx32, ctxbf, prec):
+def test_full_product_matches_dense(sphere960, ctx64, ctx32, ctxbf, prec):
     ctx = {"fp64": ctx64, "fp32": ctx32, "bf16": ctxbf}[prec]
-    x = cfg1["x"]
+    x = sphere960["x"]
     y = ctx.sfmm_matvec(x, np.zeros_like(x))
-    ref = x @ cfg1["Z"].T
+    ref = x @ sphere960["Z"].T
     err = rel(y, ref)
     print(prec, "matvec rel err", err)
     assert err < (1e-3 if prec == "fp64" else 3e-3)
@@ -159,13 +159,13 @@ def test_full_product_matches_dense(cfg1, ctx64, ctx32, ctxbf, prec):
     assert np.linalg.norm(yf) > 0.03 * np.linalg.norm(ref)
 
 
-def test_batched_rhs_equals_single(cfg1, ctx32, ctx64):
+def test_batched_rhs_equals_single(sphere960, ctx32, ctx64):
     # a batch runs the same arithmetic per right-hand side; only the order of
     # the partial sums across lanes differs; at these 0.15-wavelength boxes the
     # finest translations (h_L(kX) at small kX) amplify that reordering to
     # ~1e-5 in FP32 and ~2e-10 in FP64)
     rng = np.random.default_rng(3)
-    xb = random_complex_vector(cfg1["x"].shape[1], 8, seed=21)
+    xb = random_complex_vector(sphere960["x"].shape[1], 8, seed=21)
     for ctx, tol in ((ctx32, 3e-5), (ctx64, 1e-9)):
         yb = ctx.sfmm_matvec(xb, np.zeros_like(xb))
         zb = ctx.sfmm_precond(xb, np.zeros_like(xb))
@@ -175,8 +175,8 @@ def test_batched_rhs_equals_single(cfg1, ctx32, ctx64):
             assert rel(yb[r], y1) < tol and rel(zb[r], z1) < tol
 
 
-def test_batched_solve_matches_single_solves(cfg1, ctx64):
-    m, b = cfg1["mesh"], cfg1["body"]
+def test_batched_solve_matches_single_solves(sphere960, ctx64):
+    m, b = sphere960["mesh"], sphere960["body"]
     angles = np.array([[0.0, 0.0], [0.7, 0.3], [2.0, 1.0]])
     rhs = ctx64.sfmm_planewave_rhs(angles, np.zeros((3, 2 * m.n_edges), dtype=complex))
     xb = np.zeros_like(rhs)
@@ -188,29 +188,29 @@ def test_batched_solve_matches_single_solves(cfg1, ctx64):
         assert rel(xb[r], x1[0]) < 1e-5
 
 
-def test_ilu_preconditioner_fp64(cfg1, ctx64):
-    m = cfg1["mesh"]
-    p = octree.unknown_order(cfg1["keys"])
-    F = krylov.ilu0(cfg1["Z"][np.ix_(p, p)], cfg1["pat"][np.ix_(p, p)])
-    x = cfg1["x"][0]
+def test_ilu_preconditioner_fp64(sphere960, ctx64):
+    m = sphere960["mesh"]
+    p = octree.unknown_order(sphere960["keys"])
+    F = krylov.ilu0(sphere960["Z"][np.ix_(p, p)], sphere960["pat"][np.ix_(p, p)])
+    x = sphere960["x"][0]
     ref = np.empty_like(x)
     ref[p] = krylov.ilu_apply(F, x[p])
-    z = ctx64.sfmm_precond(cfg1["x"][:1].copy(), np.zeros_like(cfg1["x"][:1]))[0]
+    z = ctx64.sfmm_precond(sphere960["x"][:1].copy(), np.zeros_like(sphere960["x"][:1]))[0]
     assert rel(z, ref) < 1e-10
 
 
-def test_ilu_preconditioner_fp32(cfg1, ctx32):
-    p = octree.unknown_order(cfg1["keys"])
-    F = krylov.ilu0(cfg1["Z"][np.ix_(p, p)], cfg1["pat"][np.ix_(p, p)])
-    x = cfg1["x"][0]
+def test_ilu_preconditioner_fp32(sphere960, ctx32):
+    p = octree.unknown_order(sphere960["keys"])
+    F = krylov.ilu0(sphere960["Z"][np.ix_(p, p)], sphere960["pat"][np.ix_(p, p)])
+    x = sphere960["x"][0]
     ref = np.empty_like(x)
     ref[p] = krylov.ilu_apply(F, x[p])
-    z = ctx32.sfmm_precond(cfg1["x"][:1].copy(), np.zeros_like(cfg1["x"][:1]))[0]
+    z = ctx32.sfmm_precond(sphere960["x"][:1].copy(), np.zeros_like(sphere960["x"][:1]))[0]
     assert rel(z, ref) < 1e-4
 
 
-def test_planewave_rhs_matches_oracle(cfg1, ctx64):
-    m, b = cfg1["mesh"], cfg1["body"]
+def test_planewave_rhs_matches_oracle(sphere960, ctx64):
+    m, b = sphere960["mesh"], sphere960["body"]
     angles = np.array([[0.0, 0.0], [1.1, 0.4]])
     rhs = ctx64.sfmm_planewave_rhs(angles, np.zeros((2, 2 * m.n_edges), dtype=complex))
     for i, (th, ph) in enumerate(angles):
@@ -225,9 +225,9 @@ def _masked_db(s, ref):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
-def test_solve_and_rcs_match_oracle(cfg1, ctx64, ctx32, ctxbf, prec):
+def test_solve_and_rcs_match_oracle(sphere960, ctx64, ctx32, ctxbf, prec):
     ctx = {"fp64": ctx64, "fp32": ctx32, "bf16": ctxbf}[prec]
-    m, b, Z = cfg1["mesh"], cfg1["body"], cfg1["Z"]
+    m, b, Z = sphere960["mesh"], sphere960["body"], sphere960["Z"]
     kh, eh = mom.incidence(0.0, 0.0)
     rhs = mom.planewave_rhs(m, b.frequency, kh, eh)[None, :].copy()
     x = np.zeros_like(rhs)
@@ -248,9 +248,9 @@ def test_solve_and_rcs_match_oracle(cfg1, ctx64, ctx32, ctxbf, prec):
     assert _masked_db(sH, rH).max() < 0.2
 
 
-def test_solve_iterations_match_oracle_gmres(cfg1, ctx64):
-    m, b, Z, pat = cfg1["mesh"], cfg1["body"], cfg1["Z"], cfg1["pat"]
-    p = octree.unknown_order(cfg1["keys"])
+def test_solve_iterations_match_oracle_gmres(sphere960, ctx64):
+    m, b, Z, pat = sphere960["mesh"], sphere960["body"], sphere960["Z"], sphere960["pat"]
+    p = octree.unknown_order(sphere960["keys"])
     F = krylov.ilu0(Z[np.ix_(p, p)], pat[np.ix_(p, p)])
 
     def prec(v):
@@ -268,12 +268,12 @@ def test_solve_iterations_match_oracle_gmres(cfg1, ctx64):
     assert abs(info["iterations"] - oinfo.iterations) <= 3
 
 
-def test_product_bytes_follow_the_tables(cfg1, ctx32, ctx64):
+def test_product_bytes_follow_the_tables(sphere960, ctx32, ctx64):
     # algorithmic bytes of one product, checked against the octree and
     # sampling the library reports: three complex numbers per near edge pair,
     # x and y once, the transmit table (2 K_f directions per edge and region,
     # K = 2 (L + 1)^2) read twice for real wavenumbers, element size by precision
-    ne = cfg1["mesh"].n_edges
+    ne = sphere960["mesh"].n_edges
     for ctx, cb in ((ctx32, 8), (ctx64, 16)):
         d = ctx.sfmm_describe()
         pb = ctx.sfmm_product_bytes()
@@ -287,9 +287,9 @@ def test_product_bytes_follow_the_tables(cfg1, ctx32, ctx64):
         assert pb["total"] == sum(v for k, v in pb.items() if k != "total")
 
 
-def test_device_pointers_match_host_path(cfg1, ctx32):
+def test_device_pointers_match_host_path(sphere960, ctx32):
     torch = pytest.importorskip("torch")
-    x = cfg1["x"]
+    x = sphere960["x"]
     yh = ctx32.sfmm_matvec(x, np.zeros_like(x))
     xd = torch.from_numpy(x).to("cuda")
     yd = torch.zeros_like(xd)
@@ -357,25 +357,25 @@ def test_single_rhs_kernel_variants():
         assert d < (1e-12 if prec == "fp64" else 1e-4)
 
 
-def _oracle_poly(cfg1, degree):
-    Zn = np.where(cfg1["pat"], cfg1["Z"], 0)
+def _oracle_poly(sphere960, degree):
+    Zn = np.where(sphere960["pat"], sphere960["Z"], 0)
     return krylov.near_poly_preconditioner(Zn, degree)
 
 
-def test_polynomial_preconditioner_fp64(cfg1):
-    M = _oracle_poly(cfg1, 16)
-    x = cfg1["x"][:1].copy()
+def test_polynomial_preconditioner_fp64(sphere960):
+    M = _oracle_poly(sphere960, 16)
+    x = sphere960["x"][:1].copy()
     ref = M(x[0])
-    with sfmm.Context([cfg1["body"]], precision=sfmm.PREC_FP64, finest_box=0.15, n_levels=3,
+    with sfmm.Context([sphere960["body"]], precision=sfmm.PREC_FP64, finest_box=0.15, n_levels=3,
                       preconditioner=sfmm.PRECOND_POLY, poly_degree=16) as ctx:
         z = ctx.sfmm_precond(x, np.zeros_like(x))[0]
     print("poly precond rel err", rel(z, ref))
     assert rel(z, ref) < 1e-9
 
 
-def test_polynomial_preconditioned_solve_matches_oracle(cfg1):
-    M = _oracle_poly(cfg1, 16)
-    m, b, Z = cfg1["mesh"], cfg1["body"], cfg1["Z"]
+def test_polynomial_preconditioned_solve_matches_oracle(sphere960):
+    M = _oracle_poly(sphere960, 16)
+    m, b, Z = sphere960["mesh"], sphere960["body"], sphere960["Z"]
     kh, eh = mom.incidence(0.0, 0.0)
     rhs = mom.planewave_rhs(m, b.frequency, kh, eh)
     _, oinfo = krylov.gmres(lambda v: Z @ v, rhs, M, restart=30, tol=1e-6)
@@ -388,13 +388,13 @@ def test_polynomial_preconditioned_solve_matches_oracle(cfg1):
     assert rel(Z @ x[0], rhs) < 2e-3
 
 
-def test_graph_replays_match_eager(cfg1):
+def test_graph_replays_match_eager(sphere960):
     # products and preconditioner applications replayed from captured HIP
     # graphs must equal the kernel-by-kernel launches, replay after replay,
     # with other (eager) work and synchronisations in between
-    b = cfg1["body"]
-    opts = dict(CFG1, extra_multipoles=1, tol=1e-4, preconditioner=sfmm.PRECOND_POLY)
-    x = random_complex_vector(cfg1["x"].shape[1], 20, seed=123)
+    b = sphere960["body"]
+    opts = dict(SPHERE960_OPTS, extra_multipoles=1, tol=1e-4, preconditioner=sfmm.PRECOND_POLY)
+    x = random_complex_vector(sphere960["x"].shape[1], 20, seed=123)
     with sfmm.Context([b], precision=sfmm.PREC_FP32, graphs=0, **opts) as ce, \
             sfmm.Context([b], precision=sfmm.PREC_FP32, graphs=1, **opts) as cg:
         ye = ce.sfmm_matvec(x, np.zeros_like(x))
@@ -405,7 +405,7 @@ def test_graph_replays_match_eager(cfg1):
             assert rel(yg, ye) < 1e-12 and rel(zg, ze) < 1e-12, rep
             cg.sfmm_matvec(x[:3].copy(), np.zeros_like(x[:3]), parts=sfmm.PART_NEAR)
         kh, eh = mom.incidence(0.3, 0.2)
-        rhs = mom.planewave_rhs(cfg1["mesh"], b.frequency, kh, eh)[None, :].copy()
+        rhs = mom.planewave_rhs(sphere960["mesh"], b.frequency, kh, eh)[None, :].copy()
         xe, xg = np.zeros_like(rhs), np.zeros_like(rhs)
         ie = ce.sfmm_solve(rhs, xe)[0]
         ig = cg.sfmm_solve(rhs, xg)[0]
@@ -413,9 +413,9 @@ def test_graph_replays_match_eager(cfg1):
         assert rel(xg, xe) < 1e-10
 
 
-def test_planewave_rhs_kernel_polarisations(cfg1, ctx32):
+def test_planewave_rhs_kernel_polarisations(sphere960, ctx32):
     # the excitation kernel is FP64 in every precision mode
-    m, b = cfg1["mesh"], cfg1["body"]
+    m, b = sphere960["mesh"], sphere960["body"]
     angles = np.array([[0.0, 0.0], [0.4, 1.3], [2.2, -0.7], [np.pi, 0.5], [1.0, 2.0]])
     pol = np.array([1.0, 0.0, 1.0, 0.0, 0.3])
     rhs = ctx32.sfmm_planewave_rhs(angles, np.zeros((5, 2 * m.n_edges), dtype=complex), pol=pol)
@@ -426,10 +426,10 @@ def test_planewave_rhs_kernel_polarisations(cfg1, ctx32):
         assert rel(rhs[i], ref) < 1e-12, i
 
 
-def test_rcs_kernel_matches_oracle_far_field(cfg1, ctx32):
+def test_rcs_kernel_matches_oracle_far_field(sphere960, ctx32):
     # same currents on both sides: the oracle's dense solutions for 5
     # incidences (a full tile of 4 and a ragged one)
-    m, b, Z = cfg1["mesh"], cfg1["body"], cfg1["Z"]
+    m, b, Z = sphere960["mesh"], sphere960["body"], sphere960["Z"]
     cur = []
     for th in (0.0, 0.5, 1.1, 2.0, 3.0):
         kh, eh = mom.incidence(th, 0.3)
@@ -444,14 +444,14 @@ def test_rcs_kernel_matches_oracle_far_field(cfg1, ctx32):
             assert rel(s[r, :, 0], rE) < 1e-10 and rel(s[r, :, 1], rH) < 1e-10
 
 
-def test_autotuned_batched_product(cfg1):
+def test_autotuned_batched_product(sphere960):
     # whatever the autotuner picks per batch size, the products stay within
     # the MLFMM tolerance of the dense matrix
-    b = cfg1["body"]
-    opts = dict(CFG1, extra_multipoles=1, tol=1e-4, autotune=1)
+    b = sphere960["body"]
+    opts = dict(SPHERE960_OPTS, extra_multipoles=1, tol=1e-4, autotune=1)
     with sfmm.Context([b], precision=sfmm.PREC_FP32, **opts) as ctx:
         for R in (3, 24, 48):
-            x = random_complex_vector(cfg1["x"].shape[1], R, seed=200 + R)
+            x = random_complex_vector(sphere960["x"].shape[1], R, seed=200 + R)
             y = ctx.sfmm_matvec(x, np.zeros_like(x))
-            ref = x @ cfg1["Z"].T
+            ref = x @ sphere960["Z"].T
             assert max(rel(y[r], ref[r]) for r in range(R)) < 3e-3, R

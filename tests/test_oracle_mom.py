@@ -13,7 +13,7 @@ THETA = np.deg2rad(np.arange(181.0))
 
 
 @pytest.fixture(scope="module")
-def cfg1():
+def sphere960():
     b = sphere_body(0.3, 4.0, 2)
     m = rwg.from_body(b)
     Z = mom.pmchwt_dense(m, b.eps_r, b.mu_r, b.frequency)
@@ -32,10 +32,10 @@ def _far_pairs(m):
     return far
 
 
-def test_galerkin_symmetry_on_separated_pairs(cfg1):
+def test_galerkin_symmetry_on_separated_pairs(sphere960):
     # L and K are symmetric, so Z^T = D Z D with D = diag(I, -I); on pairs
     # computed with the plain 7x7 rule this holds to rounding.
-    b, m, Z = cfg1
+    b, m, Z = sphere960
     ne = m.n_edges
     far = np.tile(_far_pairs(m), (2, 2))
     D = np.r_[np.ones(ne), -np.ones(ne)]
@@ -82,8 +82,8 @@ def _refined_pair(m, P, Q, k, nsub):
     return -1j * k / (4 * AP * AQ) * L, K / (4 * AP * AQ)
 
 
-def test_touching_pair_symmetry_converges_under_refinement(cfg1):
-    b, m, _ = cfg1
+def test_touching_pair_symmetry_converges_under_refinement(sphere960):
+    b, m, _ = sphere960
     k = mom.wavenumber(b.frequency, 4.0, 1.0)
     e = 100
     P, Q = m.tri_p[e], m.tri_m[e]          # edge-adjacent pair
@@ -109,8 +109,8 @@ def _solve_rcs(b, m, Z, theta_i=0.0, phi_i=0.0):
     return x, sE, sH
 
 
-def test_oracle_matches_mie_on_the_small_sphere(cfg1):
-    b, m, Z = cfg1
+def test_oracle_matches_mie_on_the_small_sphere(sphere960):
+    b, m, Z = sphere960
     _, sE, sH = _solve_rcs(b, m, Z)
     mE, mH = mie.sphere_rcs(0.3, 4.0, THETA)
     dE = 10 * np.log10(sE / mE)
@@ -120,8 +120,8 @@ def test_oracle_matches_mie_on_the_small_sphere(cfg1):
     assert np.sqrt(np.mean(dH ** 2)) < 0.6 and np.abs(dH).max() < 1.6
 
 
-def test_transparent_sphere_scatters_nothing(cfg1):
-    b, m, Z = cfg1
+def test_transparent_sphere_scatters_nothing(sphere960):
+    b, m, Z = sphere960
     bt = sphere_body(0.3, 1.0, 2)
     Zt = mom.pmchwt_dense(m, bt.eps_r, bt.mu_r, bt.frequency)
     _, sE, sH = _solve_rcs(bt, m, Zt)
@@ -130,8 +130,8 @@ def test_transparent_sphere_scatters_nothing(cfg1):
     assert np.all(10 * np.log10(sH / sH4) < -30)
 
 
-def test_bistatic_reciprocity(cfg1):
-    b, m, Z = cfg1
+def test_bistatic_reciprocity(sphere960):
+    b, m, Z = sphere960
     ti, pi_, ts, ps = 0.3, 0.2, 1.9, 2.5
     ki, ei = mom.incidence(ti, pi_)
     ks, es = mom.incidence(ts, ps)
