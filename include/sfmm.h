@@ -114,10 +114,12 @@ typedef struct {
                                  thresholds (matrix cores from 16 RHS, grouped
                                  translation at 1 RHS and from 16 RHS)                  */
     int32_t kernel_plan;      /* 0 (default): kernels chosen as `autotune` says; with
-                                 bit 0 set, bits 1..5 fix for every batch size: matrix-
-                                 core near product, matrix-core aggregation and receive,
-                                 matrix-core interpolation, grouped translation, split
-                                 single-RHS interpolation stages.  A variant whose
+                                 bit 0 set, bits 1..5 and 7 fix for every batch size:
+                                 matrix-core near product, matrix-core aggregation and
+                                 receive, matrix-core interpolation, grouped translation,
+                                 split single-RHS interpolation stages; bit 7: single-RHS
+                                 coarsest upward phi stage in one launch with the finer
+                                 levels' translations.  A variant whose
                                  conditions do not hold (batch size, LDS) falls back to
                                  the vector kernel.  For tests and measurement.         */
 } sfmm_options;

@@ -300,12 +300,14 @@ class DeviceBodyT final : public DeviceBody {
     struct Plan {
         bool near_mma = false, agg_mma = false, interp_mma = false, trans_grp = false;
         bool interp_split = false;   // one RHS: theta and phi stages as separate whole-level launches
+        bool overlap_trans = false;  // one RHS: coarsest phi stage and finer translations in one launch
     };
     static Plan default_plan(int R) {
         Plan p;
         p.near_mma = p.agg_mma = p.interp_mma = R >= MMA_MIN_R && std::is_same<T, float>::value;
         p.trans_grp = R == 1 || R >= TRANS_GRP_MIN_R;
         p.interp_split = R == 1;
+        p.overlap_trans = R == 1;
         return p;
     }
     void use_plan(int R) {
@@ -315,6 +317,7 @@ class DeviceBodyT final : public DeviceBody {
             plan_.interp_mma = (kernel_plan_ >> 3) & 1;
             plan_.trans_grp = (kernel_plan_ >> 4) & 1;
             plan_.interp_split = (kernel_plan_ >> 5) & 1;
+            plan_.overlap_trans = (kernel_plan_ >> 7) & 1;
             return;
         }
         if (!autotune_) {
@@ -349,10 +352,10 @@ class DeviceBodyT final : public DeviceBody {
         Plan best = default_plan(R);
         plan_ = best;
         float tbest = time_product(R);
-        bool Plan::*fields[5] = {&Plan::near_mma, &Plan::agg_mma, &Plan::interp_mma, &Plan::trans_grp,
-                                 &Plan::interp_split};
+        bool Plan::*fields[6] = {&Plan::near_mma, &Plan::agg_mma, &Plan::interp_mma, &Plan::trans_grp,
+                                 &Plan::interp_split, &Plan::overlap_trans};
         for (bool Plan::*f : fields) {
-            if (f == &Plan::interp_split) {
+            if (f == &Plan::interp_split || f == &Plan::overlap_trans) {
                 if (R != 1) continue;
             } else if (f != &Plan::trans_grp) {
                 if (!std::is_same<T, float>::value || R < MMA_MIN_R) continue;
@@ -587,10 +590,15 @@ class DeviceBodyT final : public DeviceBody {
         mark(1);
         if (far) {
             for (Reg &G : regs_) aggregate_region(G, R, x);
-            mark(2);
-            for (int l = f_; l >= 3; --l) upward_level(l, R);
-            mark(3);
-            translate_all(R);
+            if (!profiling_ && overlap_ok(R)) {
+                // stage timing keeps the upward pass and the translation apart
+                up_and_translate_overlapped(R);
+            } else {
+                mark(2);
+                for (int l = f_; l >= 3; --l) upward_level(l, R);
+                mark(3);
+                translate_all(R);
+            }
             mark(4);
             for (int l = 3; l <= f_; ++l) downward_level(l, R);
             mark(5);
@@ -736,31 +744,83 @@ class DeviceBodyT final : public DeviceBody {
 #undef SFMM_DNM
     }
 
+    // job table of the grouped single-RHS translation: every region, levels
+    // lmin..lmax
+    TransGroups<T> trans_groups(int lmin, int lmax) const {
+        TransGroups<T> tg{};
+        int e = 0, nblk = 0;
+        for (const Reg &G : regs_)
+            for (int l = lmin; l <= lmax; ++l, ++e) {
+                tg.blk0[e] = nblk;
+                tg.K[e] = G.K[l];
+                tg.nkc[e] = (G.K[l] + 63) / 64;
+                tg.grp_dst[e] = G.grp_dst[l];
+                tg.cand_ptr[e] = G.cand_ptr[l];
+                tg.cand_src[e] = G.cand_src[l];
+                tg.cand_off[e] = G.cand_off[l];
+                tg.trans[e] = G.trans[l];
+                tg.S[e] = G.S[l];
+                tg.G[e] = G.G[l];
+                nblk += G.ngrp[l] * tg.nkc[e];
+            }
+        tg.nlev = e;
+        tg.blk0[e] = nblk;
+        tg.nblk = nblk;
+        return tg;
+    }
+
+    // One RHS, three or more levels: the coarsest upward phi stage shares a
+    // launch with the translations of the finer levels (which only need the
+    // finer levels' outgoing patterns); level 2 is translated after it.
+    bool overlap_ok(int R) const {
+        return R == 1 && plan_.trans_grp && plan_.overlap_trans && f_ >= 3 && split_all(3, R) &&
+               (int)regs_.size() * (f_ - 1) <= TRANS_MAXJOB;
+    }
+    void up_and_translate_overlapped(int R) {
+        for (int l = f_; l >= 4; --l) upward_level(l, R);
+        std::vector<UpPhiJob<T>> ph;
+        std::vector<int64_t> n2;
+        size_t sh = 8 * 2 * 64 * sizeof(cx<T>);
+        {
+            const int l = 3;
+            std::vector<ThetaJob<T>> th;
+            std::vector<int64_t> n1;
+            size_t sh1 = 0;
+            for (Reg &G : regs_) {
+                const int nth_c = G.nth[l], nph_c = G.nph[l], nth_p = G.nth[l - 1], nph_p = G.nph[l - 1];
+                th.push_back({G.nbox[l] * 2, nth_c, nph_c, nth_p, G.ipA[l], G.ipB[l], G.S[l], G.tmp});
+                n1.push_back((int64_t)G.nbox[l] * 2 * ((nth_p + 1) / 2) * (nph_c / 2));
+                sh1 = std::max(sh1, (size_t)2 * nth_p * nth_c * sizeof(T));
+                ph.push_back({G.nbox[l - 1], nth_p, nph_p, nph_c, G.ipDt[l], G.child_ptr[l - 1], G.child_idx[l - 1],
+                              G.slot[l], G.sup[l], G.tmp, G.S[l - 1]});
+                n2.push_back((int64_t)G.nbox[l - 1] * 2 * nth_p * (nph_p / 2));
+                sh = std::max(sh, (size_t)nph_c * nph_p * sizeof(T));
+            }
+            launch_jobs(th, n1, sh1, k_up_theta1<T, 64>, k_up_theta1<T, WG>);
+        }
+        JobList<UpPhiJob<T>> jl{};
+        for (size_t i = 0; i < ph.size(); ++i) add_job(jl, ph[i], n2[i], WG);
+        const TransGroups<T> tg = trans_groups(3, f_);
+        const unsigned grid = 8u * (unsigned)((jl.blk0[jl.n] + 7) / 8 + (tg.nblk + 7) / 8);
+        if (grid) {
+            k_up_phi1_translate1<T><<<grid, WG, sh, stream_>>>(jl, tg);
+            LAUNCHCHK();
+        }
+        const TransGroups<T> t2 = trans_groups(2, 2);
+        if (t2.nblk > 0) {
+            k_translate_grp1<T><<<(unsigned)((t2.nblk + 7) / 8 * 8), WG, 0, stream_>>>(t2);
+            LAUNCHCHK();
+        }
+    }
+
     // every translation level of every region; one RHS: one launch
     void translate_all(int R) {
         const int nlev = f_ - 1;
         if (R == 1 && nlev >= 1 && (int)regs_.size() * nlev <= TRANS_MAXJOB) {
             int nblk = 0;
             if (plan_.trans_grp) {
-                TransGroups<T> tg{};
-                int e = 0;
-                for (Reg &G : regs_)
-                    for (int l = 2; l <= f_; ++l, ++e) {
-                        tg.blk0[e] = nblk;
-                        tg.K[e] = G.K[l];
-                        tg.nkc[e] = (G.K[l] + 63) / 64;
-                        tg.grp_dst[e] = G.grp_dst[l];
-                        tg.cand_ptr[e] = G.cand_ptr[l];
-                        tg.cand_src[e] = G.cand_src[l];
-                        tg.cand_off[e] = G.cand_off[l];
-                        tg.trans[e] = G.trans[l];
-                        tg.S[e] = G.S[l];
-                        tg.G[e] = G.G[l];
-                        nblk += G.ngrp[l] * tg.nkc[e];
-                    }
-                tg.nlev = e;
-                tg.blk0[e] = nblk;
-                tg.nblk = nblk;
+                const TransGroups<T> tg = trans_groups(2, f_);
+                nblk = tg.nblk;
                 if (nblk > 0) {
                     k_translate_grp1<T><<<(unsigned)((nblk + 7) / 8 * 8), WG, 0, stream_>>>(tg);
                     LAUNCHCHK();

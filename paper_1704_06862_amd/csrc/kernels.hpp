@@ -668,11 +668,15 @@ struct JobList {
 
 // the job of this workgroup (workgroup-uniform) and the workgroup's index in it
 template <typename P>
-__device__ __forceinline__ const P &job_of(const JobList<P> &jl, int &local) {
+__device__ __forceinline__ const P &job_at(const JobList<P> &jl, int blk, int &local) {
     int i = 0;
-    while (i + 1 < jl.n && (int)blockIdx.x >= jl.blk0[i + 1]) ++i;
-    local = (int)blockIdx.x - jl.blk0[i];
+    while (i + 1 < jl.n && blk >= jl.blk0[i + 1]) ++i;
+    local = blk - jl.blk0[i];
     return jl.p[i];
+}
+template <typename P>
+__device__ __forceinline__ const P &job_of(const JobList<P> &jl, int &local) {
+    return job_at(jl, (int)blockIdx.x, local);
 }
 
 template <typename T>
@@ -747,10 +751,9 @@ __global__ void __launch_bounds__(BS) k_up_theta1(const JobList<ThetaJob<T>> jl)
 
 // Sp[P][comp][I][J] = sum_children shift[slot][I][J] sum_j Dt[j][J] tmp[c][comp][I][j]
 template <typename T, int BS>
-__global__ void __launch_bounds__(BS) k_up_phi1(const JobList<UpPhiJob<T>> jl) {
-    extern __shared__ unsigned char lds_raw[];
+__device__ __forceinline__ void up_phi1_block(const JobList<UpPhiJob<T>> &jl, int blk, unsigned char *lds_raw) {
     int local;
-    const UpPhiJob<T> &a = job_of(jl, local);
+    const UpPhiJob<T> &a = job_at(jl, blk, local);
     const int nth_p = a.nth_p, nph_p = a.nph_p, nph_c = a.nph_c;
     T *Ds = reinterpret_cast<T *>(lds_raw);   // [nph_c][nph_p]
     for (int t = threadIdx.x; t < nph_c * nph_p; t += BS) Ds[t] = a.Dt[t];
@@ -784,6 +787,12 @@ __global__ void __launch_bounds__(BS) k_up_phi1(const JobList<UpPhiJob<T>> jl) {
     cx<T> *out = a.Sp + ((int64_t)P * 2 + comp) * Kp + I * nph_p + J;
     out[0] = o0;
     out[1] = o1;
+}
+
+template <typename T, int BS>
+__global__ void __launch_bounds__(BS) k_up_phi1(const JobList<UpPhiJob<T>> jl) {
+    extern __shared__ unsigned char lds_raw[];
+    up_phi1_block<T, BS>(jl, (int)blockIdx.x, lds_raw);
 }
 
 // tmp[c][comp][I][j] = sum_J D[J][j] shift_dn[slot][I][J] Gp[parent][comp][I][J]
@@ -996,11 +1005,13 @@ struct TransGroups {
     cx<T> *G[TRANS_MAXJOB];
 };
 
+// One workgroup of the grouped single-RHS translation; `blk` is its index in
+// the launch's own numbering (XCD-contiguous renumbering applied here), `red`
+// an LDS buffer of 8 x 2 x 64 complex numbers.
 template <typename T>
-__global__ void __launch_bounds__(WG) k_translate_grp1(const TransGroups<T> tg) {
-    __shared__ cx<T> red[8][2][64];
+__device__ __forceinline__ void translate_grp1_block(const TransGroups<T> &tg, int blk, cx<T> (*red)[2][64]) {
     const int per = (tg.nblk + 7) / 8;
-    const int id = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    const int id = (blk % 8) * per + blk / 8;
     if (id >= tg.nblk) return;   // whole workgroup
     int L = 0;
     while (L + 1 < tg.nlev && id >= tg.blk0[L + 1]) ++L;
@@ -1056,6 +1067,41 @@ __global__ void __launch_bounds__(WG) k_translate_grp1(const TransGroups<T> tg) 
         const int j = t >> 7, q = (t >> 6) & 1, ln = t & 63;
         const int d = dst[j];
         if (d >= 0 && k0 + ln < K) G[(size_t)d * 2 * K + q * K + k0 + ln] = red[j][q][ln];
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(WG) k_translate_grp1(const TransGroups<T> tg) {
+    __shared__ cx<T> red[8][2][64];
+    translate_grp1_block(tg, (int)blockIdx.x, red);
+}
+
+// One right-hand side: the coarsest upward phi stage (parents at level 2)
+// and the translations that do not wait for it (every level but 2) in one
+// launch.  The phi stage alone leaves most of the chip idle; the translations'
+// workgroups fill it.  Workgroups alternate between the two kinds in runs of
+// eight (one per XCD); each kind keeps its own numbering.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_up_phi1_translate1(const JobList<UpPhiJob<T>> jl, const TransGroups<T> tg) {
+    extern __shared__ unsigned char lds_raw[];
+    const int nphi = jl.blk0[jl.n];
+    const int n8a = (nphi + 7) / 8, n8b = (tg.nblk + 7) / 8;
+    const int run = blockIdx.x / 8, within = blockIdx.x % 8;
+    const int both = n8a < n8b ? n8a : n8b;
+    bool phi;
+    int k;
+    if (run < 2 * both) {
+        phi = (run & 1) == 0;
+        k = run >> 1;
+    } else {
+        phi = n8a > n8b;
+        k = both + (run - 2 * both);
+    }
+    const int blk = 8 * k + within;
+    if (phi) {
+        if (blk < nphi) up_phi1_block<T, WG>(jl, blk, lds_raw);
+    } else {
+        if (blk < 8 * n8b) translate_grp1_block(tg, blk, reinterpret_cast<cx<T>(*)[2][64]>(lds_raw));
     }
 }
 

@@ -322,8 +322,10 @@ def test_multilevel_product_sampled_rows():
 
 
 # kernel_plan bits: 1 = fixed plan, 16 = grouped translation, 32 = split
-# single-RHS interpolation stages (otherwise the per-box kernels)
-SINGLE_RHS_PLANS = {"flat+split": 1 | 32, "grouped+split": 1 | 16 | 32, "flat+box": 1, "grouped+box": 1 | 16}
+# single-RHS interpolation stages (otherwise the per-box kernels), 128 = the
+# coarsest upward phi stage in one launch with the finer translations
+SINGLE_RHS_PLANS = {"flat+split": 1 | 32, "grouped+split": 1 | 16 | 32, "flat+box": 1, "grouped+box": 1 | 16,
+                    "grouped+split+overlap": 1 | 16 | 32 | 128}
 
 
 def test_single_rhs_kernel_variants():
