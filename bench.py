@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes of one k_near launch at this size from rocprofv3 --pmc: FETCH_SIZE
 # (KiB) x 2.0 + WRITE_SIZE (KiB) x 1.0, the factors being what the counters
 # read for a plain 256 MiB device copy (profiles/near_product_sphere61440_pmc_traffic.md)
-NEAR_TRAFFIC_BYTES = int((157344 * 2.0 + 566) * 1024)
+NEAR_TRAFFIC_BYTES = int((157493 * 2.0 + 568) * 1024)
 
 
 def parse():
