@@ -330,7 +330,9 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": NEAR_TRAFFIC_BYTES, "alg_bytes_per_launch": int(alg_bytes), "avg_ms": round(near_ms, 4),
                 "avg_ms_measured": "HIP events on the library stream around k_near in 10 products launched kernel by "
-                                   "kernel (the graph the timed steps replay runs the same kernels in the same order)",
+                                   "kernel; the graph the timed steps replay runs the same rows as the trailing "
+                                   "workgroups of the level-2 translation launch (k_near_up_phi1_translate1<float, "
+                                   "true>), overlapped with that level's translations",
                 "measured_copy_GBs": round(copy_gbs, 1),
                 "whole_product": {"alg_bytes": pb, "ms": round(ms, 4), "achieved": round(gbs(pb["total"], ms), 1),
                                   "frac": round(gbs(pb["total"], ms) / HBM_PEAK_GBS, 4)}}

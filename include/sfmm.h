@@ -114,12 +114,13 @@ typedef struct {
                                  thresholds (matrix cores from 16 RHS, grouped
                                  translation at 1 RHS and from 16 RHS)                  */
     int32_t kernel_plan;      /* 0 (default): kernels chosen as `autotune` says; with
-                                 bit 0 set, bits 1..5 and 7 fix for every batch size:
+                                 bit 0 set, bits 1..5, 7 and 8 fix for every batch size:
                                  matrix-core near product, matrix-core aggregation and
                                  receive, matrix-core interpolation, grouped translation,
                                  split single-RHS interpolation stages; bit 7: single-RHS
                                  coarsest upward phi stage in one launch with the finer
-                                 levels' translations.  A variant whose
+                                 levels' translations; bit 8 (with bit 7): the near-field
+                                 product in the level-2 translation launch.  A variant whose
                                  conditions do not hold (batch size, LDS) falls back to
                                  the vector kernel.  For tests and measurement.         */
 } sfmm_options;

@@ -127,6 +127,17 @@ class DeviceBodyT final : public DeviceBody {
             max_ncol_ = std::max(max_ncol_, h.near.col_ptr[b + 1] - h.near.col_ptr[b]);
             max_nrow_ = std::max(max_nrow_, o.bstart[b + 1] - o.bstart[b]);
         }
+        {
+            // (box, row group) of every non-empty group of WAVES rows
+            std::vector<int> grp;
+            for (int b = 0; b < nb_; ++b)
+                for (int rg = 0; rg * WAVES < o.bstart[b + 1] - o.bstart[b]; ++rg) {
+                    grp.push_back(b);
+                    grp.push_back(rg);
+                }
+            near_ngrp_ = (int)(grp.size() / 2);
+            if (near_ngrp_ > 0) near_grp_ = upload(grp);
+        }
         if constexpr (std::is_same<T, float>::value) build_mma_tiles(h);
         upload_edge_quadrature(m);
         if (!h.ilu.fwd_col_ptr.empty()) {
@@ -301,6 +312,7 @@ class DeviceBodyT final : public DeviceBody {
         bool near_mma = false, agg_mma = false, interp_mma = false, trans_grp = false;
         bool interp_split = false;   // one RHS: theta and phi stages as separate whole-level launches
         bool overlap_trans = false;  // one RHS: coarsest phi stage and finer translations in one launch
+        bool near_join = false;      // ... and the near product in the level-2 translation launch
     };
     static Plan default_plan(int R) {
         Plan p;
@@ -308,6 +320,7 @@ class DeviceBodyT final : public DeviceBody {
         p.trans_grp = R == 1 || R >= TRANS_GRP_MIN_R;
         p.interp_split = R == 1;
         p.overlap_trans = R == 1;
+        p.near_join = R == 1;
         return p;
     }
     void use_plan(int R) {
@@ -318,6 +331,7 @@ class DeviceBodyT final : public DeviceBody {
             plan_.trans_grp = (kernel_plan_ >> 4) & 1;
             plan_.interp_split = (kernel_plan_ >> 5) & 1;
             plan_.overlap_trans = (kernel_plan_ >> 7) & 1;
+            plan_.near_join = (kernel_plan_ >> 8) & 1;
             return;
         }
         if (!autotune_) {
@@ -352,10 +366,10 @@ class DeviceBodyT final : public DeviceBody {
         Plan best = default_plan(R);
         plan_ = best;
         float tbest = time_product(R);
-        bool Plan::*fields[6] = {&Plan::near_mma, &Plan::agg_mma, &Plan::interp_mma, &Plan::trans_grp,
-                                 &Plan::interp_split, &Plan::overlap_trans};
+        bool Plan::*fields[7] = {&Plan::near_mma,     &Plan::agg_mma,       &Plan::interp_mma, &Plan::trans_grp,
+                                 &Plan::interp_split, &Plan::overlap_trans, &Plan::near_join};
         for (bool Plan::*f : fields) {
-            if (f == &Plan::interp_split || f == &Plan::overlap_trans) {
+            if (f == &Plan::interp_split || f == &Plan::overlap_trans || f == &Plan::near_join) {
                 if (R != 1) continue;
             } else if (f != &Plan::trans_grp) {
                 if (!std::is_same<T, float>::value || R < MMA_MIN_R) continue;
@@ -580,9 +594,13 @@ class DeviceBodyT final : public DeviceBody {
     void matvec_internal(const cx<T> *x, cx<T> *y, int R, int parts) {
         const int64_t NR = (int64_t)2 * ne_ * R;
         const bool far = (parts & SFMM_PART_FAR) && f_ >= 2;
+        const bool overlap = far && !profiling_ && overlap_ok(R);
+        // the near product may wait for that shared launch: y is not touched
+        // before it, and the receive step adds to y after it
+        const bool near_joined = overlap && (parts & SFMM_PART_NEAR) && near_join_ok(R);
         mark(0);
         if (parts & SFMM_PART_NEAR) {
-            launch_near<false>(R, x, y, nullptr, cx<T>{0, 0}, 1);
+            if (!near_joined) launch_near<false>(R, x, y, nullptr, cx<T>{0, 0}, 1);
         } else {
             k_zero<T><<<nblocks(NR), WG, 0, stream_>>>(y, NR);
             LAUNCHCHK();
@@ -590,9 +608,9 @@ class DeviceBodyT final : public DeviceBody {
         mark(1);
         if (far) {
             for (Reg &G : regs_) aggregate_region(G, R, x);
-            if (!profiling_ && overlap_ok(R)) {
+            if (overlap) {
                 // stage timing keeps the upward pass and the translation apart
-                up_and_translate_overlapped(R);
+                up_and_translate_overlapped(R, near_joined ? x : nullptr, y);
             } else {
                 mark(2);
                 for (int l = f_; l >= 3; --l) upward_level(l, R);
@@ -776,7 +794,12 @@ class DeviceBodyT final : public DeviceBody {
         return R == 1 && plan_.trans_grp && plan_.overlap_trans && f_ >= 3 && split_all(3, R) &&
                (int)regs_.size() * (f_ - 1) <= TRANS_MAXJOB;
     }
-    void up_and_translate_overlapped(int R) {
+    bool near_join_ok(int R) const {
+        return R == 1 && plan_.near_join && near_ngrp_ > 0 &&
+               (size_t)max_ncol_ * 2 * sizeof(cx<T>) <= LDS_LIMIT;
+    }
+    // x != nullptr: the near product y = Z_near x joins the launch
+    void up_and_translate_overlapped(int R, const cx<T> *x, cx<T> *y) {
         for (int l = f_; l >= 4; --l) upward_level(l, R);
         std::vector<UpPhiJob<T>> ph;
         std::vector<int64_t> n2;
@@ -801,13 +824,25 @@ class DeviceBodyT final : public DeviceBody {
         JobList<UpPhiJob<T>> jl{};
         for (size_t i = 0; i < ph.size(); ++i) add_job(jl, ph[i], n2[i], WG);
         const TransGroups<T> tg = trans_groups(3, f_);
+        const NearRows<T> none{};
         const unsigned grid = 8u * (unsigned)((jl.blk0[jl.n] + 7) / 8 + (tg.nblk + 7) / 8);
         if (grid) {
-            k_up_phi1_translate1<T><<<grid, WG, sh, stream_>>>(jl, tg);
+            k_near_up_phi1_translate1<T, false><<<grid, WG, sh, stream_>>>(jl, tg, none);
             LAUNCHCHK();
         }
+        // level 2: a few hundred workgroups; the near product's follow them
         const TransGroups<T> t2 = trans_groups(2, 2);
-        if (t2.nblk > 0) {
+        if (x) {
+            NearRows<T> nr{};
+            nr.a = NearArgs<T>{R,  bstart_, near_col_ptr_, near_cols_, near_val_ptr_, nA_,    nB_,
+                               nC_, x,       y,             nullptr,    cx<T>{0, 0},   1,      nullptr};
+            nr.grp = near_grp_;
+            nr.ngrp = near_ngrp_;
+            const size_t sh2 = std::max((size_t)8 * 2 * 64 * sizeof(cx<T>), (size_t)max_ncol_ * 2 * sizeof(cx<T>));
+            const unsigned g2 = 8u * (unsigned)((t2.nblk + 7) / 8 + (nr.ngrp + 7) / 8);
+            k_near_up_phi1_translate1<T, true><<<g2, WG, sh2, stream_>>>(JobList<UpPhiJob<T>>{}, t2, nr);
+            LAUNCHCHK();
+        } else if (t2.nblk > 0) {
             k_translate_grp1<T><<<(unsigned)((t2.nblk + 7) / 8 * 8), WG, 0, stream_>>>(t2);
             LAUNCHCHK();
         }
@@ -1586,6 +1621,7 @@ class DeviceBodyT final : public DeviceBody {
     // edge quadrature for the plane-wave and far-field kernels
     int *gs0_ = nullptr;
     double *gqr_ = nullptr, *gqf_ = nullptr;
+    int *near_grp_ = nullptr, near_ngrp_ = 0;
     int max_ncol_ = 0, max_nrow_ = 0, max_ilu_nc_ = 0, precond_ = SFMM_PRECOND_ILU0;
     int *fcol_ptr_ = nullptr, *fcols_ = nullptr, *bcol_ptr_ = nullptr, *bcols_ = nullptr;
     int64_t *fptr_ = nullptr, *bptr_ = nullptr;

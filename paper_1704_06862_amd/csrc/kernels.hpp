@@ -149,55 +149,61 @@ __global__ void k_zero(cx<T> *__restrict__ a, int64_t n) {
 
 // ---------------------------------------------------------------------------
 // Near-field product Y = Z_near X for a tile of RT right-hand sides.
-// Grid: (finest boxes, row groups of RW rows, RHS tiles).  The box's input
+// The box's input
 // columns (both halves, RT right-hand sides) are staged in LDS; one wavefront
 // per row; lane = rr + RT * cg (cg: column group), so the RT lanes of a
 // column group share the matrix entries (one load serves RT products).
 // POLY = true fuses one product-form step of the polynomial preconditioner:
 // with Q = Z_near X,  acc += X / theta  and  Y = X - Q / theta.
-template <typename T, int RT, bool LDS, bool POLY>
-__global__ void __launch_bounds__(RWG) k_near(int R, const int *__restrict__ bstart, const int *__restrict__ col_ptr,
-                                              const int *__restrict__ cols, const int64_t *__restrict__ val_ptr,
-                                              const cx<T> *__restrict__ A, const cx<T> *__restrict__ B,
-                                              const cx<T> *__restrict__ C, const cx<T> *__restrict__ x,
-                                              cx<T> *__restrict__ y, cx<T> *__restrict__ acc, cx<T> inv_theta,
-                                              int write_y, const cx<T> *__restrict__ dinv) {
-    extern __shared__ unsigned char lds_raw[];
-    cx<T> *xs = reinterpret_cast<cx<T> *>(lds_raw);     // [ncol][2][RT]
+template <typename T>
+struct NearArgs {
+    int R;
+    const int *bstart, *col_ptr, *cols;
+    const int64_t *val_ptr;
+    const cx<T> *A, *B, *C, *x;
+    cx<T> *y, *acc;
+    cx<T> inv_theta;
+    int write_y;
+    const cx<T> *dinv;
+};
+
+// One workgroup of the near-field product: NRW rows (one wavefront each) of
+// box b from row NRW * rg on, right-hand sides rhs0 .. rhs0 + RT - 1; xs is
+// the LDS staging area of the box's input columns.
+template <typename T, int RT, bool LDS, bool POLY, int NRW>
+__device__ __forceinline__ void near_block(const NearArgs<T> &a, int b, int rg, int rhs0, cx<T> *xs) {
     constexpr int NCG = 64 / RT;
-    const int b = blockIdx.x;
-    const int r0 = bstart[b], nrow = bstart[b + 1] - r0;
-    if ((int)blockIdx.y * RW >= nrow) return;            // uniform over the workgroup
-    const int c0 = col_ptr[b], ncol = col_ptr[b + 1] - c0;
-    const int rhs0 = blockIdx.z * RT;
+    const int r0 = a.bstart[b], nrow = a.bstart[b + 1] - r0;
+    if (rg * NRW >= nrow) return;            // uniform over the workgroup
+    const int c0 = a.col_ptr[b], ncol = a.col_ptr[b + 1] - c0;
     if (LDS) {
-        for (int t = threadIdx.x; t < ncol * 2 * RT; t += RWG) {
+        for (int t = threadIdx.x; t < ncol * 2 * RT; t += NRW * 64) {
             const int c = t / (2 * RT), hr = t % (2 * RT);
-            const int p = cols[c0 + c];
-            xs[t] = x[(int64_t)(2 * p + hr / RT) * R + rhs0 + hr % RT];
+            const int p = a.cols[c0 + c];
+            xs[t] = a.x[(int64_t)(2 * p + hr / RT) * a.R + rhs0 + hr % RT];
         }
         __syncthreads();
     }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int row = blockIdx.y * RW + wave;
+    const int row = rg * NRW + wave;
     if (row >= nrow) return;
     const int rr = lane % RT, cg = lane / RT;
-    const int64_t rb = val_ptr[b] + (int64_t)row * ncol;
+    const int64_t rb = a.val_ptr[b] + (int64_t)row * ncol;
     auto xin = [&](int c, cx<T> &xj, cx<T> &xm) {
         if (LDS) {
             xj = xs[(2 * c) * RT + rr];
             xm = xs[(2 * c + 1) * RT + rr];
         } else {
-            const int p = cols[c0 + c];
-            xj = x[(int64_t)(2 * p) * R + rhs0 + rr];
-            xm = x[(int64_t)(2 * p + 1) * R + rhs0 + rr];
+            const int p = a.cols[c0 + c];
+            xj = a.x[(int64_t)(2 * p) * a.R + rhs0 + rr];
+            xm = a.x[(int64_t)(2 * p + 1) * a.R + rhs0 + rr];
         }
     };
     cx<T> aE = {0, 0}, aH = {0, 0}, bE = {0, 0}, bH = {0, 0};
     int c = cg;
     for (; c + NCG < ncol; c += 2 * NCG) {
-        const cx<T> a0 = A[rb + c], b0 = B[rb + c], c0v = C[rb + c];
-        const cx<T> a1 = A[rb + c + NCG], b1 = B[rb + c + NCG], c1v = C[rb + c + NCG];
+        const cx<T> a0 = a.A[rb + c], b0 = a.B[rb + c], c0v = a.C[rb + c];
+        const cx<T> a1 = a.A[rb + c + NCG], b1 = a.B[rb + c + NCG], c1v = a.C[rb + c + NCG];
         cx<T> xj0, xm0, xj1, xm1;
         xin(c, xj0, xm0);
         xin(c + NCG, xj1, xm1);
@@ -211,7 +217,7 @@ __global__ void __launch_bounds__(RWG) k_near(int R, const int *__restrict__ bst
         cfma(bH, c1v, xm1);
     }
     if (c < ncol) {
-        const cx<T> a0 = A[rb + c], b0 = B[rb + c], c0v = C[rb + c];
+        const cx<T> a0 = a.A[rb + c], b0 = a.B[rb + c], c0v = a.C[rb + c];
         cx<T> xj0, xm0;
         xin(c, xj0, xm0);
         cfma(aE, a0, xj0);
@@ -224,27 +230,41 @@ __global__ void __launch_bounds__(RWG) k_near(int R, const int *__restrict__ bst
     aH.x = group_sum<RT>(aH.x + bH.x);
     aH.y = group_sum<RT>(aH.y + bH.y);
     if (lane < RT) {
-        const int64_t iE = (int64_t)(2 * (r0 + row)) * R + rhs0 + rr;
-        const int64_t iH = iE + R;
+        const int64_t iE = (int64_t)(2 * (r0 + row)) * a.R + rhs0 + rr;
+        const int64_t iH = iE + a.R;
         if (POLY) {
-            cx<T> xe = x[iE], xh = x[iH];
-            cx<T> ae = acc[iE], ah = acc[iH];
-            cfma(ae, xe, inv_theta);
-            cfma(ah, xh, inv_theta);
-            acc[iE] = ae;
-            acc[iH] = ah;
-            if (write_y) {
-                if (dinv) edge_block(dinv + 4 * (int64_t)(r0 + row), aE, aH);
-                cfms(xe, aE, inv_theta);
-                cfms(xh, aH, inv_theta);
-                y[iE] = xe;
-                y[iH] = xh;
+            cx<T> xe = a.x[iE], xh = a.x[iH];
+            cx<T> ae = a.acc[iE], ah = a.acc[iH];
+            cfma(ae, xe, a.inv_theta);
+            cfma(ah, xh, a.inv_theta);
+            a.acc[iE] = ae;
+            a.acc[iH] = ah;
+            if (a.write_y) {
+                if (a.dinv) edge_block(a.dinv + 4 * (int64_t)(r0 + row), aE, aH);
+                cfms(xe, aE, a.inv_theta);
+                cfms(xh, aH, a.inv_theta);
+                a.y[iE] = xe;
+                a.y[iH] = xh;
             }
         } else {
-            y[iE] = aE;
-            y[iH] = aH;
+            a.y[iE] = aE;
+            a.y[iH] = aH;
         }
     }
+}
+
+// Grid: (finest boxes, row groups of RW rows, RHS tiles).
+template <typename T, int RT, bool LDS, bool POLY>
+__global__ void __launch_bounds__(RWG) k_near(int R, const int *__restrict__ bstart, const int *__restrict__ col_ptr,
+                                              const int *__restrict__ cols, const int64_t *__restrict__ val_ptr,
+                                              const cx<T> *__restrict__ A, const cx<T> *__restrict__ B,
+                                              const cx<T> *__restrict__ C, const cx<T> *__restrict__ x,
+                                              cx<T> *__restrict__ y, cx<T> *__restrict__ acc, cx<T> inv_theta,
+                                              int write_y, const cx<T> *__restrict__ dinv) {
+    extern __shared__ unsigned char lds_raw[];
+    const NearArgs<T> a{R, bstart, col_ptr, cols, val_ptr, A, B, C, x, y, acc, inv_theta, write_y, dinv};
+    near_block<T, RT, LDS, POLY, RW>(a, (int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z * RT,
+                                     reinterpret_cast<cx<T> *>(lds_raw));
 }
 
 // ---------------------------------------------------------------------------
@@ -1076,17 +1096,40 @@ __global__ void __launch_bounds__(WG) k_translate_grp1(const TransGroups<T> tg) 
     translate_grp1_block(tg, (int)blockIdx.x, red);
 }
 
-// One right-hand side: the coarsest upward phi stage (parents at level 2)
-// and the translations that do not wait for it (every level but 2) in one
-// launch.  The phi stage alone leaves most of the chip idle; the translations'
-// workgroups fill it.  Workgroups alternate between the two kinds in runs of
-// eight (one per XCD); each kind keeps its own numbering.
+// Rows of the single-RHS near product as workgroups of WAVES rows: grp holds
+// (box, row group) per workgroup, only groups with at least one row.
 template <typename T>
-__global__ void __launch_bounds__(WG) k_up_phi1_translate1(const JobList<UpPhiJob<T>> jl, const TransGroups<T> tg) {
+struct NearRows {
+    NearArgs<T> a;
+    const int *grp;
+    int ngrp;
+};
+
+// One right-hand side: up to three independent kinds of work in one launch,
+// each too small to fill the chip alone or able to fill what another leaves
+// idle: an upward phi stage (the coarsest: parents at level 2), translations
+// that do not wait for it, and the near-field product, which depends on
+// nothing in the far field.  Workgroups come in runs of eight (one per XCD);
+// phi and translation runs alternate, and the near runs follow all of them,
+// so the few workgroups of a small translation level start first and the
+// near product's fill the rest of the chip.  Each kind keeps its own
+// numbering; an empty kind takes no runs.  NEAR = false compiles the near
+// kind out.
+template <typename T, bool NEAR>
+__global__ void __launch_bounds__(WG) k_near_up_phi1_translate1(const JobList<UpPhiJob<T>> jl,
+                                                                const TransGroups<T> tg, const NearRows<T> nr) {
     extern __shared__ unsigned char lds_raw[];
     const int nphi = jl.blk0[jl.n];
-    const int n8a = (nphi + 7) / 8, n8b = (tg.nblk + 7) / 8;
-    const int run = blockIdx.x / 8, within = blockIdx.x % 8;
+    const int n8a = (nphi + 7) / 8, n8b = (tg.nblk + 7) / 8, n8n = (nr.ngrp + 7) / 8;
+    const int within = blockIdx.x % 8;
+    int run = blockIdx.x / 8;
+    if (NEAR && run >= n8a + n8b) {
+        const int g = 8 * (run - n8a - n8b) + within;
+        if (g < nr.ngrp)
+            near_block<T, 1, true, false, WAVES>(nr.a, nr.grp[2 * g], nr.grp[2 * g + 1], 0,
+                                                 reinterpret_cast<cx<T> *>(lds_raw));
+        return;
+    }
     const int both = n8a < n8b ? n8a : n8b;
     bool phi;
     int k;
