@@ -417,6 +417,41 @@ def test_graph_replays_match_eager(sphere960):
         assert rel(xg, xe) < 1e-10
 
 
+# kernel_plan bits for batched products: 2 = near product, 4 = aggregation
+# and receive, 8 = interpolation on the matrix cores, 16 = grouped translation
+BATCHED_PLANS = {"mfma": 1 | 2 | 4 | 8 | 16, "vector": 1 | 16}
+
+
+def test_batched_interpolation_variants():
+    # the batched products of a 4-level tree (two interpolation levels) on
+    # the matrix cores and with the vector kernels:
+    # within the MLFMM truncation error of the oracle's rows (about 1e-3 for
+    # this tree; the bound is on the worst of all right-hand sides) and within
+    # FP32 rounding of each other
+    b = sphere_body(1.0, 2.56, 3)
+    m = rwg.from_body(b)
+    rng = np.random.default_rng(8)
+    test = np.sort(rng.choice(m.n_edges, 24, replace=False))
+    ZE, ZH = mom.pmchwt_rows(m, b.eps_r, b.mu_r, b.frequency, test)
+    for R in (20, 64):
+        x = random_complex_vector(2 * m.n_edges, R, seed=300 + R)
+        ys = {}
+        for name, plan in BATCHED_PLANS.items():
+            print("batched variant", R, name, flush=True)
+            with sfmm.Context([b], precision=sfmm.PREC_FP32, finest_box=0.25, extra_multipoles=2,
+                              kernel_plan=plan) as ctx:
+                y = ctx.sfmm_matvec(x, np.zeros_like(x))
+            err = max(rel(np.concatenate([y[r][test], y[r][m.n_edges + test]]),
+                          np.concatenate([ZE @ x[r], ZH @ x[r]])) for r in range(R))
+            print(R, name, "sampled-row rel err", err)
+            assert err < 2e-3
+            ys[name] = y
+        for name, y in ys.items():
+            d = max(rel(y[r], ys["vector"][r]) for r in range(R))
+            print(R, name, "vs vector kernels", d)
+            assert d < 1e-4
+
+
 def test_planewave_rhs_kernel_polarisations(sphere960, ctx32):
     # the excitation kernel is FP64 in every precision mode
     m, b = sphere960["mesh"], sphere960["body"]
