@@ -424,10 +424,12 @@ class DeviceBodyT final : public DeviceBody {
     void launch_near_mma(int R, const cx<float> *x, cx<float> *y, cx<float> *acc, cx<float> inv_theta,
                          int write_y) {
         const int nt = (R + 15) / 16;
+        const unsigned ng = (unsigned)((ntiles_ + 7) / 8 * 8);
 #define SFMM_NMMA(NT_, S_)                                                                                          \
-    k_near_mma<NT_, S_, POLY><<<ntiles_, 64 * MMA_WAVES, 0, stream_>>>(R, tile_box_, tile_row0_, tile_step_, bstart_, \
-                                                                     near_col_ptr_, near_cols_, tvals_, nsteps_, x, y, \
-                                                                     acc, inv_theta, write_y, POLY ? dinv_ : nullptr)
+    k_near_mma<NT_, S_, POLY><<<ng, 64 * MMA_WAVES, 0, stream_>>>(R, tile_box_, tile_row0_, tile_step_, bstart_,      \
+                                                                near_col_ptr_, near_cols_, tvals_, nsteps_, x, y,      \
+                                                                acc, inv_theta, write_y, POLY ? dinv_ : nullptr,       \
+                                                                ntiles_)
         if (split_) {
             if (nt == 1) SFMM_NMMA(1, true);
             else if (nt == 2) SFMM_NMMA(2, true);
@@ -900,10 +902,11 @@ class DeviceBodyT final : public DeviceBody {
         int rp = 1;
         while (rp < R) rp <<= 1;
         const int dpw = WG / rp;
-        dim3 grid(G.ngrp[l], (G.K[l] + dpw - 1) / dpw);
+        dim3 grid((G.ngrp[l] + 7) / 8 * 8, (G.K[l] + dpw - 1) / dpw);
 #define SFMM_TG(RP_)                                                                                             \
     k_translate_grp<T, RP_><<<grid, WG, 0, stream_>>>(G.K[l], R, G.grp_dst[l], G.cand_ptr[l], G.cand_src[l], \
-                                                      G.cand_off[l], G.trans[l], G.S[l], G.G[l])
+                                                      G.cand_off[l], G.trans[l], G.S[l], G.G[l],             \
+                                                      G.ngrp[l])
         if (rp == 64) SFMM_TG(64);
         else if (rp == 32) SFMM_TG(32);
         else if (rp == 16) SFMM_TG(16);

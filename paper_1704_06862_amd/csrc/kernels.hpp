@@ -1161,10 +1161,14 @@ __global__ void __launch_bounds__(WG) k_translate_grp(int K, int R, const int *_
                                                       const int *__restrict__ cand_src,
                                                       const int *__restrict__ cand_off,
                                                       const cx<T> *__restrict__ trans, const cx<T> *__restrict__ S,
-                                                      cx<T> *__restrict__ G) {
+                                                      cx<T> *__restrict__ G, int ngrp) {
     constexpr int DPW = WG / RP;   // directions per workgroup
     constexpr int DW = 64 / RP;    // directions per wavefront
-    const int g = blockIdx.x;
+    // each XCD takes a contiguous range of groups (neighbouring groups share
+    // most candidates, whose samples then stay in that XCD's L2); grid.x is 8 per
+    const int per = (ngrp + 7) / 8;
+    const int g = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (g >= ngrp) return;
     const int rr = threadIdx.x % RP;
     int k = blockIdx.y * DPW + threadIdx.x / RP;
     if (RP == 64) k = __builtin_amdgcn_readfirstlane(k);

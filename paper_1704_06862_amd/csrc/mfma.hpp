@@ -55,7 +55,8 @@ __device__ __forceinline__ void mma_split(f32x4 &c, const bf16x8 &ah, const bf16
 }
 
 // Near-field product on the matrix cores for R <= 16 * NT right-hand sides.
-// One workgroup per tile (box b, 16-row block starting at row0); the 4 waves
+// One workgroup per tile (box b, 16-row block starting at row0), tiles
+// renumbered so that each XCD takes a contiguous range; the 4 waves
 // take every 4th K step and their partial sums are added through LDS.
 // vals: FP32: three planes (A, B, C) of cx<float>[nsteps][64];
 //       split: twelve planes (A, B, C) x (re hi, re lo, im hi, im lo) of
@@ -67,9 +68,13 @@ __global__ void __launch_bounds__(64 * MMA_WAVES)
                const int64_t *__restrict__ tile_step, const int *__restrict__ bstart, const int *__restrict__ col_ptr,
                const int *__restrict__ cols, const void *__restrict__ vals, int64_t nsteps,
                const cx<float> *__restrict__ x, cx<float> *__restrict__ y, cx<float> *__restrict__ acc,
-               cx<float> inv_theta, int write_y, const cx<float> *__restrict__ dinv) {
+               cx<float> inv_theta, int write_y, const cx<float> *__restrict__ dinv, int ntiles) {
     __shared__ f32x4 red[MMA_WAVES - 1][NT * 4][64];
-    const int t = blockIdx.x;
+    // each XCD takes a contiguous range of tiles (neighbouring boxes, whose
+    // column lists overlap, then share that XCD's L2); the grid is 8 per
+    const int per = (ntiles + 7) / 8;
+    const int t = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (t >= ntiles) return;
     const int b = tile_box[t], row0 = tile_row0[t];
     const int r0 = bstart[b], nrow = bstart[b + 1] - r0;
     const int c0 = col_ptr[b], ncol = col_ptr[b + 1] - c0;
