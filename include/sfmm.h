@@ -110,9 +110,12 @@ typedef struct {
                                  replayed; 0: launched kernel by kernel                 */
     int32_t autotune;         /* 1: on the first batch of each size, time the vector and
                                  the matrix-core / grouped variant of every stage that
-                                 has both and keep the faster; 0 (default): fixed
+                                 has both (for one RHS also the split interpolation
+                                 stages and the shared launches of kernel_plan bits 7
+                                 and 8) and keep the faster; 0 (default): fixed
                                  thresholds (matrix cores from 16 RHS, grouped
-                                 translation at 1 RHS and from 16 RHS)                  */
+                                 translation at 1 RHS and from 16 RHS, the split
+                                 stages and shared launches at 1 RHS)                   */
     int32_t kernel_plan;      /* 0 (default): kernels chosen as `autotune` says; with
                                  bit 0 set, bits 1..5, 7 and 8 fix for every batch size:
                                  matrix-core near product, matrix-core aggregation and
