@@ -1120,7 +1120,7 @@ __global__ void __launch_bounds__(WG) k_near_up_phi1_translate1(const JobList<Up
                                                                 const TransGroups<T> tg, const NearRows<T> nr) {
     extern __shared__ unsigned char lds_raw[];
     const int nphi = jl.blk0[jl.n];
-    const int n8a = (nphi + 7) / 8, n8b = (tg.nblk + 7) / 8, n8n = (nr.ngrp + 7) / 8;
+    const int n8a = (nphi + 7) / 8, n8b = (tg.nblk + 7) / 8;
     const int within = blockIdx.x % 8;
     int run = blockIdx.x / 8;
     if (NEAR && run >= n8a + n8b) {
@@ -1153,8 +1153,9 @@ __global__ void __launch_bounds__(WG) k_near_up_phi1_translate1(const JobList<Up
 // pattern sample is loaded once per group and applied to every sibling whose
 // list holds it (offset id >= 0 in cand_off[c][slot]).  Lanes: rr = lane % RP
 // (right-hand side, RP = R rounded up to a power of two), the rest of the
-// workgroup runs over directions; blockIdx.x = group, blockIdx.y = direction
-// chunk, so concurrent workgroups share a slab of directions in cache.
+// workgroup runs over directions; blockIdx.x = group (renumbered so that each
+// XCD takes a contiguous range), blockIdx.y = direction chunk, so concurrent
+// workgroups share a slab of directions in cache.
 template <typename T, int RP>
 __global__ void __launch_bounds__(WG) k_translate_grp(int K, int R, const int *__restrict__ grp_dst,
                                                       const int *__restrict__ cand_ptr,
