@@ -126,7 +126,24 @@ typedef struct {
                                  product in the level-2 translation launch.  A variant whose
                                  conditions do not hold (batch size, LDS) falls back to
                                  the vector kernel.  For tests and measurement.         */
+    int32_t formulation;      /* SFMM_FORM_*: integral equation; 0 = PMCHWT               */
+    int32_t quad_points;      /* points of the triangle rule for the outer and regular
+                                 inner integrals; 0 = 7 (degree 5), the only rule built;
+                                 other values: SFMM_E_UNSUPPORTED                         */
+    int32_t solver;           /* SFMM_SOLVER_*: Krylov method of sfmm_solve; 0 = GMRES     */
+    double ilu_pivot_tol;     /* ILU0 / BLOCK_JACOBI: a pivot whose modulus is at most this
+                                 times the largest entry of its diagonal box block counts
+                                 as zero (SFMM_E_BREAKDOWN at setup); 0 = 1e-13           */
 } sfmm_options;
+
+/* Integral equations (the paper's "Integral Equation Formulation" section):
+ *   PMCHWT  tangential EFIE and MFIE of both regions of every interface summed
+ *           (eqs. 10-13; several interfaces as in eq. 16). */
+enum { SFMM_FORM_PMCHWT = 0 };
+
+/* Krylov solvers of sfmm_solve:
+ *   GMRES   restarted flexible GMRES(m), see sfmm_solve. */
+enum { SFMM_SOLVER_GMRES = 0 };
 
 /* Preconditioners of sfmm_solve, all built from the near-field matrix Z_near
  * (the paper preconditions with an incomplete LU of it):
@@ -157,11 +174,19 @@ typedef struct {
 /* Fill *opt with the defaults listed above. */
 void sfmm_default_options(sfmm_options *opt);
 
-/* Validate the meshes, build RWG tables, octrees, the FP64 near-field matrix
- * (singular terms in closed form), its ILU(0) factors and the MLFMM tables,
- * and upload them to the device.  Bodies are independent scatterers.
- * Errors: SFMM_E_INVALID_ARG, SFMM_E_MESH, SFMM_E_OOM, SFMM_E_DEVICE,
- * SFMM_E_BREAKDOWN (zero ILU pivot).  On success *out owns all memory. */
+/* Problem set-up (the paper's problem statement: a body of homogeneous
+ * regions with their eps_r, mu_r at one frequency, "Integral Equation
+ * Formulation" section and eq. 16; RWG discretisation, eq. 22 and the
+ * "Discretization" section).  Validates the meshes, builds the RWG tables,
+ * the octrees, the FP64 near-field matrix of the PMCHWT operator (singular
+ * terms in closed form), the preconditioner chosen by opt->preconditioner
+ * (default: the near-field polynomial; ILU0 = the paper's incomplete LU) and
+ * the MLFMM tables, and uploads them to the device.  Bodies are independent
+ * scatterers.  opt = NULL takes sfmm_default_options.  Errors:
+ * SFMM_E_INVALID_ARG (NULL or non-finite inputs, bad options, a non-vacuum
+ * region 0), SFMM_E_MESH, SFMM_E_OOM, SFMM_E_DEVICE, SFMM_E_UNSUPPORTED,
+ * SFMM_E_BREAKDOWN (zero pivot, see ilu_pivot_tol).  On success *out owns all
+ * memory; on failure *out is NULL. */
 sfmm_status sfmm_setup(const sfmm_body *bodies, int32_t n_bodies, const sfmm_options *opt,
                        sfmm_ctx **out);
 
@@ -181,15 +206,24 @@ sfmm_status sfmm_num_unknowns(const sfmm_ctx *ctx, int32_t body, int64_t *n_unkn
 /* Canonical edge table: [E][2] vertex ids (smaller first). */
 sfmm_status sfmm_edges(const sfmm_ctx *ctx, int32_t body, int32_t *edge_vertices);
 
-/* y = Z x for n_rhs vectors (Z: scaled PMCHWT matrix, near part exact, far
- * part by MLFMM).  parts = 3 for the full product; 1 = near-field matrix only,
- * 2 = far-field (MLFMM) part only (for diagnostics). */
+/* y = Z x for n_rhs vectors: the product of the moment matrix of the
+ * PMCHWT equations (eqs. 10-13 and 16 tested with RWG functions, eqs. 22-26)
+ * that the paper's Krylov solver evaluates by the MLFMM ("Simulation
+ * Results": the multipole-accelerated product).  Near part exact (stored
+ * matrix), far part by aggregation, translation and disaggregation.
+ * x, y: [n_rhs][2E] complex in the boundary layout, host or device per
+ * on_device; y is overwritten.  parts = 3 for the full product; 1 =
+ * near-field matrix only, 2 = far-field (MLFMM) part only (for diagnostics).
+ * Errors: SFMM_E_INVALID_ARG (NULL pointers, n_rhs <= 0, parts), SFMM_E_OOM,
+ * SFMM_E_DEVICE. */
 enum { SFMM_PART_NEAR = 1, SFMM_PART_FAR = 2, SFMM_PART_ALL = 3 };
 sfmm_status sfmm_matvec(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void *x, void *y,
                         int32_t on_device, int32_t parts);
 
-/* y = M^-1 x with M the context's preconditioner (ILU(0) of the near-field
- * matrix in colour ordering by default; identity for SFMM_PRECOND_NONE). */
+/* y = M^-1 x with M the context's preconditioner (opt->preconditioner: the
+ * near-field polynomial by default, ILU(0) of the near-field matrix in colour
+ * ordering for SFMM_PRECOND_ILU0 - the paper's incomplete LU, "Simulation
+ * Results" - identity for SFMM_PRECOND_NONE).  Layout as sfmm_matvec. */
 sfmm_status sfmm_precond(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void *x, void *y,
                          int32_t on_device);
 
@@ -207,7 +241,12 @@ sfmm_status sfmm_planewave_rhs(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const
  * restart length (1..1000), iteration cap, relative tolerance. */
 sfmm_status sfmm_set_solver(sfmm_ctx *ctx, int32_t gmres_restart, int32_t max_iters, double tol);
 
-/* Solve Z x = b with restarted flexible GMRES(m) (Saad 1993): Arnoldi with
+/* Solve Z x = b, the discretised PMCHWT system of eqs. 10-13 / 16 with the
+ * plane-wave right-hand side of eqs. 20-21 and 30, by the preconditioned
+ * Krylov iteration the paper uses ("Simulation Results"; the solver is
+ * restarted GMRES here, see sfmm_options.solver).  b, x (and x0): [n_rhs][2E]
+ * complex, host or device per on_device.  Restarted flexible GMRES(m) (Saad
+ * 1993): Arnoldi with
  * classical Gram-Schmidt applied twice, Givens rotations and the
  * least-squares update in FP64, the preconditioner of sfmm_options applied on
  * the right in the product precision.  Right-hand sides are iterated in
@@ -311,8 +350,9 @@ sfmm_status sfmm_describe(const sfmm_ctx *ctx, int32_t body, int64_t *info, int3
  * every array read or written once per use.  bytes[0] near-field values (three
  * complex numbers per edge pair, the PMCHWT 2x2 block [[A, -B], [B, C]]) and
  * column indices; bytes[1] x read and y written once; bytes[2] radiation
- * patterns read for aggregation and again for receiving (Sec. 3: the
- * aggregation and disaggregation steps of the MLFMM); bytes[3] level arrays,
+ * patterns read for aggregation and again for receiving (the aggregation and
+ * disaggregation steps of the multipole method the paper's solver uses,
+ * "Simulation Results"); bytes[3] level arrays,
  * outgoing and incoming patterns each written and read once; bytes[4]
  * translation operators for the offsets in use; bytes[5] interpolation and
  * shift tables; bytes[6] the total; bytes[7] = 0.  `bytes` is a caller array

@@ -70,3 +70,15 @@ def near_pattern(keys):
     """[2 ne, 2 ne] bool near pattern in boundary layout."""
     m = near_mask(keys)
     return np.block([[m, m], [m, m]])
+
+
+def natural_order(keys):
+    """Permutation of the 2 ne unknowns into the natural (uncoloured) order:
+    boxes by Morton code, canonical edge index inside a box, J before M~.
+    Used only to measure what the colouring of unknown_order costs ILU(0)."""
+    ne = len(keys)
+    edges = np.lexsort((np.arange(ne), morton(keys)))
+    p = np.empty(2 * ne, dtype=np.int64)
+    p[0::2] = edges
+    p[1::2] = edges + ne
+    return p

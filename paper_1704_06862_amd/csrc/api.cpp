@@ -166,6 +166,10 @@ void sfmm_default_options(sfmm_options *o) {
     o->graphs = 1;
     o->autotune = 0;
     o->kernel_plan = 0;
+    o->formulation = SFMM_FORM_PMCHWT;
+    o->quad_points = 7;
+    o->solver = SFMM_SOLVER_GMRES;
+    o->ilu_pivot_tol = 1e-13;
 }
 
 sfmm_status sfmm_setup(const sfmm_body *bodies, int32_t n_bodies, const sfmm_options *opt, sfmm_ctx **out) {
@@ -186,6 +190,15 @@ sfmm_status sfmm_setup(const sfmm_body *bodies, int32_t n_bodies, const sfmm_opt
         if (o.preconditioner < 0 || o.preconditioner > 3) throw Error(SFMM_E_INVALID_ARG, "unknown preconditioner");
         if (o.poly_degree <= 0) o.poly_degree = 16;
         if (o.poly_degree > 64) throw Error(SFMM_E_INVALID_ARG, "poly_degree must be at most 64");
+        if (o.quad_points == 0) o.quad_points = 7;
+        if (o.quad_points != 7) throw Error(SFMM_E_UNSUPPORTED, "only the 7-point triangle rule is built");
+        if (o.formulation != SFMM_FORM_PMCHWT) throw Error(SFMM_E_UNSUPPORTED, "unknown formulation");
+        if (o.solver != SFMM_SOLVER_GMRES) throw Error(SFMM_E_UNSUPPORTED, "unknown solver");
+        if (o.ilu_pivot_tol == 0) o.ilu_pivot_tol = 1e-13;
+        if (!(o.ilu_pivot_tol > 0) || !std::isfinite(o.ilu_pivot_tol))
+            throw Error(SFMM_E_INVALID_ARG, "ilu_pivot_tol must be positive");
+        if (!std::isfinite(o.finest_box) || o.finest_box < 0 || !std::isfinite(o.digits) || o.digits < 0)
+            throw Error(SFMM_E_INVALID_ARG, "finest_box and digits must be finite and non-negative");
         if (o.device >= 0) check_device(o.device);
         for (int32_t i = 0; i < n_bodies; ++i) {
             auto t0 = std::chrono::steady_clock::now();
@@ -196,8 +209,8 @@ sfmm_status sfmm_setup(const sfmm_body *bodies, int32_t n_bodies, const sfmm_opt
             auto t1 = std::chrono::steady_clock::now();
             bh->near = fill_near(bh->mesh, bh->oct);
             auto t2 = std::chrono::steady_clock::now();
-            if (o.preconditioner == SFMM_PRECOND_ILU0) bh->ilu = factor_ilu(bh->mesh, bh->oct, bh->near);
-            else if (o.preconditioner == SFMM_PRECOND_BLOCK_JACOBI) bh->ilu = factor_block_jacobi(bh->mesh, bh->oct, bh->near);
+            if (o.preconditioner == SFMM_PRECOND_ILU0) bh->ilu = factor_ilu(bh->mesh, bh->oct, bh->near, o.ilu_pivot_tol);
+            else if (o.preconditioner == SFMM_PRECOND_BLOCK_JACOBI) bh->ilu = factor_block_jacobi(bh->mesh, bh->oct, bh->near, o.ilu_pivot_tol);
             else if (o.preconditioner == SFMM_PRECOND_POLY) {
                 bh->poly_dinv = edge_block_inverse(bh->oct, bh->near);
                 bh->poly = poly_roots(bh->mesh, bh->oct, bh->near, o.poly_degree, bh->poly_dinv);

@@ -142,10 +142,12 @@ struct IluFactors {
     std::vector<cd> fwd, bwd;                 // row-major [2n][2nc]
 };
 
-IluFactors factor_ilu(const Mesh &m, const Octree &o, const NearMatrix &Z);
+// A pivot of modulus at most pivot_tol times the largest entry of its
+// diagonal block counts as zero (SFMM_E_BREAKDOWN).
+IluFactors factor_ilu(const Mesh &m, const Octree &o, const NearMatrix &Z, double pivot_tol);
 // Block-Jacobi: forward rows hold the inverse of each same-box diagonal block
 // of the near matrix, backward rows the identity.
-IluFactors factor_block_jacobi(const Mesh &m, const Octree &o, const NearMatrix &Z);
+IluFactors factor_block_jacobi(const Mesh &m, const Octree &o, const NearMatrix &Z, double pivot_tol);
 
 // Roots (Leja-ordered harmonic Ritz values) of the near-field GMRES polynomial
 // preconditioner of the given degree.

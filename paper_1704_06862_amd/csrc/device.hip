@@ -1241,6 +1241,9 @@ class DeviceBodyT final : public DeviceBody {
             for (int s = 0; s < R; ++s) all[s] = s;
             upload_act(all);
             std::vector<double> nb = norms(kb_, R);
+            for (int s = 0; s < R; ++s)
+                if (!std::isfinite(nb[s]))
+                    throw Error(SFMM_E_INVALID_ARG, "right-hand side " + std::to_string(c0 + s) + " is not finite");
             std::vector<int> its(R, 0), restarts(R, 0), used(R, 0);
             std::vector<double> rel(R, 0.0), rel0(R, 1.0);
             std::vector<char> conv(R, 0);

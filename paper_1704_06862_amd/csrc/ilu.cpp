@@ -48,12 +48,12 @@ void gemm_sub(Mat &C, const Mat &A, const Mat &B, int r, int k, int c) {
     }
 }
 
-void lu_inplace(Mat &A, int n) {
+void lu_inplace(Mat &A, int n, double pivot_tol) {
     double scale = 0;
     for (const cd &v : A) scale = std::max(scale, std::abs(v));
     for (int k = 0; k < n; ++k) {
         cd piv = A[(size_t)k * n + k];
-        if (!(std::abs(piv) > 1e-13 * scale)) throw Error(SFMM_E_BREAKDOWN, "zero pivot in ILU(0)");
+        if (!(std::abs(piv) > pivot_tol * scale)) throw Error(SFMM_E_BREAKDOWN, "zero pivot in ILU(0)");
         for (int i = k + 1; i < n; ++i) {
             cd f = A[(size_t)i * n + k] / piv;
             A[(size_t)i * n + k] = f;
@@ -88,7 +88,7 @@ void left_solve_upper(Mat &W, int n, int c, const Mat &LU) {
 
 }  // namespace
 
-IluFactors factor_ilu(const Mesh &m, const Octree &o, const NearMatrix &Z) {
+IluFactors factor_ilu(const Mesh &m, const Octree &o, const NearMatrix &Z, double pivot_tol) {
     (void)m;
     const int nb = o.nb;
     auto nu = [&](int b) { return 2 * (o.bstart[b + 1] - o.bstart[b]); };
@@ -145,7 +145,7 @@ IluFactors factor_ilu(const Mesh &m, const Octree &o, const NearMatrix &Z) {
                         gemm_sub(blk[I][q2], blk[I][q], blk[K][s], nI, nK, nu(J));
                     }
                 }
-                lu_inplace(blk[I][qI], nI);
+                lu_inplace(blk[I][qI], nI, pivot_tol);
                 for (int q = qI + 1; q < nq; ++q) {
                     const int J = o.nbr_idx[o.nbr_ptr[I] + q];
                     left_solve_unit_lower(blk[I][q], nI, nu(J), blk[I][qI]);   // U_IJ
@@ -232,7 +232,7 @@ IluFactors factor_ilu(const Mesh &m, const Octree &o, const NearMatrix &Z) {
 
 namespace sfmm {
 
-IluFactors factor_block_jacobi(const Mesh &m, const Octree &o, const NearMatrix &Z) {
+IluFactors factor_block_jacobi(const Mesh &m, const Octree &o, const NearMatrix &Z, double pivot_tol) {
     (void)m;
     const int nb = o.nb;
     IluFactors F;
@@ -247,6 +247,9 @@ IluFactors factor_block_jacobi(const Mesh &m, const Octree &o, const NearMatrix 
     }
     F.fwd_cols.resize(F.fwd_col_ptr[nb]);
     F.fwd.assign(F.fwd_ptr[nb], 0.0);
+    // an exception must not leave an OpenMP region: flag the breakdown and
+    // throw after the loop
+    bool breakdown = false;
 #pragma omp parallel for schedule(dynamic, 4)
     for (int I = 0; I < nb; ++I) {
         const int n = o.bstart[I + 1] - o.bstart[I];
@@ -268,12 +271,19 @@ IluFactors factor_block_jacobi(const Mesh &m, const Octree &o, const NearMatrix 
                 A[(size_t)(2 * r + 1) * nu + 2 * c + 1] = Z.C[idx];
             }
         for (int i = 0; i < nu; ++i) Inv[(size_t)i * nu + i] = 1.0;
-        lu_inplace(A, nu);
+        try {
+            lu_inplace(A, nu, pivot_tol);
+        } catch (const Error &) {
+#pragma omp critical
+            breakdown = true;
+            continue;
+        }
         left_solve_unit_lower(Inv, nu, nu, A);
         left_solve_upper(Inv, nu, nu, A);
         for (int p = 0; p < n; ++p) F.fwd_cols[F.fwd_col_ptr[I] + p] = o.bstart[I] + p;
         std::copy(Inv.begin(), Inv.end(), F.fwd.begin() + F.fwd_ptr[I]);
     }
+    if (breakdown) throw Error(SFMM_E_BREAKDOWN, "zero pivot in a block-Jacobi diagonal block");
     return F;
 }
 

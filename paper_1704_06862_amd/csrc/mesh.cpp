@@ -35,7 +35,8 @@ Mesh build_mesh(const sfmm_body &b) {
     if (b.n_vertices < 4 || b.n_triangles < 4 || !b.vertices || !b.triangles || !b.tri_regions)
         throw Error(SFMM_E_INVALID_ARG, "body needs vertices, triangles and tri_regions");
     if (b.n_regions < 2 || !b.eps_r || !b.mu_r) throw Error(SFMM_E_INVALID_ARG, "body needs >= 2 regions with eps_r, mu_r");
-    if (!(b.frequency_hz > 0)) throw Error(SFMM_E_INVALID_ARG, "frequency must be positive");
+    if (!(b.frequency_hz > 0) || !std::isfinite(b.frequency_hz))
+        throw Error(SFMM_E_INVALID_ARG, "frequency must be positive and finite");
     m.nv = b.n_vertices;
     m.nt = b.n_triangles;
     m.nr = b.n_regions;
@@ -43,7 +44,10 @@ Mesh build_mesh(const sfmm_body &b) {
     m.k0 = 2 * PI * m.freq / C0;
     m.V.resize(m.nv);
     for (int i = 0; i < m.nv; ++i)
-        for (int j = 0; j < 3; ++j) m.V[i][j] = b.vertices[3 * i + j];
+        for (int j = 0; j < 3; ++j) {
+            m.V[i][j] = b.vertices[3 * i + j];
+            if (!std::isfinite(m.V[i][j])) throw Error(SFMM_E_INVALID_ARG, "non-finite vertex coordinate");
+        }
     m.T.resize(m.nt);
     m.TR.resize(m.nt);
     for (int t = 0; t < m.nt; ++t) {
@@ -68,7 +72,14 @@ Mesh build_mesh(const sfmm_body &b) {
     for (int r = 0; r < m.nr; ++r) {
         m.eps[r] = cd(b.eps_r[2 * r], b.eps_r[2 * r + 1]);
         m.mu[r] = cd(b.mu_r[2 * r], b.mu_r[2 * r + 1]);
+        if (!std::isfinite(m.eps[r].real()) || !std::isfinite(m.eps[r].imag()) || !std::isfinite(m.mu[r].real()) ||
+            !std::isfinite(m.mu[r].imag()))
+            throw Error(SFMM_E_INVALID_ARG, "non-finite eps_r or mu_r");
         if (std::abs(m.eps[r]) == 0 || std::abs(m.mu[r]) == 0) throw Error(SFMM_E_INVALID_ARG, "zero eps_r or mu_r");
+        // the plane wave (eq. 30) and the far field (eqs. 27-28) live in the
+        // unbounded region, taken as vacuum
+        if (r == 0 && (m.eps[0] != cd(1.0) || m.mu[0] != cd(1.0)))
+            throw Error(SFMM_E_INVALID_ARG, "region 0 (the unbounded exterior) must be vacuum: eps_r = mu_r = 1");
         // principal square roots: Im k <= 0 for passive media under exp(+j w t)
         m.k[r] = m.k0 * std::sqrt(m.eps[r] * m.mu[r]);
         m.eta[r] = std::sqrt(m.mu[r] / m.eps[r]);

@@ -23,6 +23,8 @@ STATUS = {0: "SFMM_OK", 1: "SFMM_E_INVALID_ARG", 2: "SFMM_E_MESH", 3: "SFMM_E_OO
 PREC_FP32, PREC_BF16_SPLIT, PREC_FP64 = 0, 1, 2
 PART_NEAR, PART_FAR, PART_ALL = 1, 2, 3
 PRECOND_ILU0, PRECOND_NONE, PRECOND_BLOCK_JACOBI, PRECOND_POLY = 0, 1, 2, 3
+FORM_PMCHWT = 0
+SOLVER_GMRES = 0
 
 EXPORTED = ["sfmm_default_options", "sfmm_setup", "sfmm_destroy", "sfmm_last_error", "sfmm_set_stream",
             "sfmm_num_unknowns", "sfmm_edges", "sfmm_matvec", "sfmm_precond", "sfmm_planewave_rhs",
@@ -45,7 +47,8 @@ class sfmm_options(ctypes.Structure):
                 ("gmres_restart", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("device", ctypes.c_int32), ("verbose", ctypes.c_int32), ("preconditioner", ctypes.c_int32),
                 ("poly_degree", ctypes.c_int32), ("graphs", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("kernel_plan", ctypes.c_int32)]
+                ("kernel_plan", ctypes.c_int32), ("formulation", ctypes.c_int32), ("quad_points", ctypes.c_int32),
+                ("solver", ctypes.c_int32), ("ilu_pivot_tol", ctypes.c_double)]
 
 
 class sfmm_solve_info(ctypes.Structure):

@@ -167,3 +167,46 @@ def test_guess_entry_points_refuse_bad_use():
         sfmm.sfmm_mlp_train([4, 2], np.zeros(10), np.zeros((1, 4)), np.zeros((1, 2)))
     o = sfmm.sfmm_guess_default_options()
     assert o.rank > 0 and o.hidden > 0 and o.epochs > 0 and o.lr > 0
+
+
+# --- input validation and failure injection (host set-up, no GPU) -----------
+
+def _status(fn):
+    with pytest.raises(sfmm.SfmmError) as e:
+        fn()
+    return e.value.status
+
+
+def test_non_finite_and_non_vacuum_inputs_are_rejected():
+    b = sphere_body(0.3, 4.0, 1)
+    bad = Body(b.vertices.copy(), b.triangles, b.tri_regions, b.eps_r, b.mu_r)
+    bad.vertices[3, 1] = np.nan
+    assert _status(lambda: sfmm.Context([bad], device=-1)) == 1
+    for eps in ([1.0, np.nan], [1.0, complex(4.0, np.inf)], [2.0, 4.0]):
+        nb = Body(b.vertices, b.triangles, b.tri_regions, np.array(eps, dtype=complex), b.mu_r)
+        assert _status(lambda: sfmm.Context([nb], device=-1)) == 1
+    nb = Body(b.vertices, b.triangles, b.tri_regions, b.eps_r, b.mu_r, frequency=float("nan"))
+    assert _status(lambda: sfmm.Context([nb], device=-1)) == 1
+    assert _status(lambda: sfmm.Context([b], device=-1, finest_box=float("nan"))) == 1
+
+
+def test_unbuilt_options_are_refused():
+    b = sphere_body(0.3, 4.0, 1)
+    assert _status(lambda: sfmm.Context([b], device=-1, quad_points=13)) == 7
+    assert _status(lambda: sfmm.Context([b], device=-1, formulation=9)) == 7
+    assert _status(lambda: sfmm.Context([b], device=-1, solver=9)) == 7
+    with sfmm.Context([b], device=-1, quad_points=7):
+        pass
+
+
+def test_zero_pivot_reports_breakdown():
+    # a pivot at most ilu_pivot_tol times its block's largest entry counts as
+    # zero; every pivot is at most the block's largest entry, so a tolerance
+    # above 1 turns the first one into a breakdown, for ILU(0) and for the
+    # block-Jacobi inverses alike
+    b = sphere_body(0.3, 4.0, 1)
+    for pc in (sfmm.PRECOND_ILU0, sfmm.PRECOND_BLOCK_JACOBI):
+        assert _status(lambda: sfmm.Context([b], device=-1, preconditioner=pc, ilu_pivot_tol=2.0)) == 6
+        with sfmm.Context([b], device=-1, preconditioner=pc):
+            pass
+    assert _status(lambda: sfmm.Context([b], device=-1, preconditioner=sfmm.PRECOND_ILU0, ilu_pivot_tol=-1.0)) == 1

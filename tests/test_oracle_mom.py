@@ -6,8 +6,8 @@ transparent-body limit and reciprocity."""
 import numpy as np
 import pytest
 
-from oracle import farfield, mie, mom, potentials, quadrature, rwg
-from workloads import sphere_body
+from oracle import farfield, mie, mom, octree, potentials, quadrature, rwg
+from workloads import coated_sphere_body, sphere_body
 
 THETA = np.deg2rad(np.arange(181.0))
 
@@ -143,3 +143,86 @@ def test_bistatic_reciprocity(sphere960):
     a1 = np.dot(es, Fi)
     a2 = np.dot(ei, Fs)
     assert abs(a1 - a2) < 5e-3 * abs(a1)
+
+
+# --- near-field matrix and several interfaces (eq. 16) -----------------------
+
+def _cuts(b, m, Z):
+    _, sE, sH = _solve_rcs(b, m, Z)
+    return sE, sH
+
+
+def _db_rms_max(s, ref):
+    floor = 1e-3 * ref.max()
+    d = np.abs(10 * np.log10((s + floor) / (ref + floor)))
+    return float(np.sqrt(np.mean(d ** 2))), float(d.max())
+
+
+def test_near_matrix_is_the_dense_matrix_on_the_near_pattern(sphere960):
+    # the near-field fill integrates only the triangle pairs of near edge
+    # pairs; every near entry must equal the dense fill's, every other be zero
+    b, m, Z = sphere960
+    keys = octree.finest_keys(m, 0.15, 3)
+    mask = octree.near_mask(keys)
+    Zn = mom.pmchwt_near(m, b.eps_r, b.mu_r, b.frequency, mask)
+    pat = octree.near_pattern(keys)
+    assert 0.05 < pat.mean() < 0.95
+    assert np.abs(Zn - np.where(pat, Z, 0)).max() <= 1e-14 * np.abs(Z).max()
+
+
+@pytest.fixture(scope="module")
+def coated1200():
+    b = coated_sphere_body(0.15, 6 - 0.5j, 1, 0.3, 2.56, 2)
+    m = rwg.from_body(b)
+    return b, m, mom.pmchwt_dense(m, b.eps_r, b.mu_r, b.frequency)
+
+
+def test_near_matrix_of_two_interfaces(coated1200):
+    b, m, Z = coated1200
+    keys = octree.finest_keys(m, 0.15, 3)
+    Zn = mom.pmchwt_near(m, b.eps_r, b.mu_r, b.frequency, octree.near_mask(keys))
+    pat = octree.near_pattern(keys)
+    # both interfaces and the pairs between them are in the pattern
+    inner = m.regions[:, 1] == 2
+    assert pat[:m.n_edges, :m.n_edges][np.ix_(inner, ~inner)].any()
+    assert np.abs(Zn - np.where(pat, Z, 0)).max() <= 1e-14 * np.abs(Z).max()
+
+
+def test_equal_media_across_the_inner_interface(coated1200):
+    # eq. 16 with the core made of the shell material: the inner interface
+    # separates identical media, so the body scatters like the homogeneous
+    # sphere of the outer mesh.  A wrong region sign on either interface, or a
+    # missing cross-interface block, breaks this by dBs.
+    b, m, _ = coated1200
+    be = coated_sphere_body(0.15, 2.56, 1, 0.3, 2.56, 2)
+    Ze = mom.pmchwt_dense(m, be.eps_r, be.mu_r, be.frequency)
+    bh = sphere_body(0.3, 2.56, 2)
+    mh = rwg.from_body(bh)
+    Zh = mom.pmchwt_dense(mh, bh.eps_r, bh.mu_r, bh.frequency)
+    eE, eH = _cuts(be, m, Ze)
+    hE, hH = _cuts(bh, mh, Zh)
+    for s, ref in ((eE, hE), (eH, hH)):
+        rms, mx = _db_rms_max(s, ref)
+        assert rms < 0.03 and mx < 0.1
+
+
+@pytest.mark.slow
+def test_coated_sphere_converges_to_the_coated_mie_series(coated1200):
+    # lossy core (eps 6 - 0.5j, r = 0.15) in a shell (eps 2.56, r = 0.3): the
+    # oracle's RCS approaches the Aden-Kerker series as both surfaces are
+    # refined (1,200 -> 4,800 unknowns)
+    mE, mH = mie.coated_sphere_rcs(0.15, 6 - 0.5j, 0.3, 2.56, THETA)
+    errs = []
+    for (cs, ss), pre in (((1, 2), coated1200), ((2, 3), None)):
+        if pre is None:
+            b = coated_sphere_body(0.15, 6 - 0.5j, cs, 0.3, 2.56, ss)
+            m = rwg.from_body(b)
+            Z = mom.pmchwt_dense(m, b.eps_r, b.mu_r, b.frequency)
+        else:
+            b, m, Z = pre
+        sE, sH = _cuts(b, m, Z)
+        errs.append(_db_rms_max(sE, mE) + _db_rms_max(sH, mH))
+    (e1, x1, h1, y1), (e2, x2, h2, y2) = errs
+    assert e1 < 0.6 and h1 < 0.7
+    assert e2 < 0.15 and h2 < 0.2 and x2 < 0.3 and y2 < 0.6
+    assert e2 < e1 / 3 and h2 < h1 / 3
