@@ -8,8 +8,8 @@ where G -> exp(-j k0 r)/(4 pi r) exp(+j k0 r_hat.r') and grad G -> -j k0 r_hat G
     F(r_hat) = (-j k0 / 4 pi) [ eta0 (I - r_hat r_hat) J_hat - r_hat x M_hat ]
     J_hat = int J(r') exp(+j k0 r_hat.r') dS'   (likewise M_hat)
 
-over the interfaces that face free space (each basis weighted by its region-0
-sign).  With M = eta0 M~ the bracket becomes eta0 [(I - r r) J_hat - r x M~_hat].
+over the interfaces that face free space (each half basis weighted by its
+triangle's region-0 sign).  With M = eta0 M~ the bracket becomes eta0 [(I - r r) J_hat - r x M~_hat].
 RCS (eq. 29): sigma_pp = 4 pi |p_hat . F|^2 / |E0|^2 in m^2.
 """
 
@@ -29,16 +29,19 @@ def spherical_units(theta, phi):
 
 
 def basis_transforms(mesh: RWGMesh, frequency, r_hat):
-    """T[d, n, 3] = int f_n(r') exp(+j k0 r_hat_d . r') dS' for every direction d."""
+    """T[d, n, 3] = int f_n(r') exp(+j k0 r_hat_d . r') dS' for every direction
+    d, f_n restricted to free space with its region-0 sign."""
     k0 = 2 * np.pi * frequency / C0
     r_hat = np.atleast_2d(r_hat)
     w = quadrature.WEIGHTS
     T = np.zeros((len(r_hat), mesh.n_edges, 3), dtype=complex)
-    for tri, free, sgn in ((mesh.tri_p, mesh.free_p, 1.0), (mesh.tri_m, mesh.free_m, -1.0)):
-        pts = mesh.qpts[tri]                                                     # [ne, 7, 3]
-        f = sgn * (mesh.length / (2 * mesh.area[tri]))[:, None, None] * (pts - mesh.vertices[free][:, None, :])
-        ph = np.exp(1j * k0 * np.einsum("dx,nqx->dnq", r_hat, pts))              # [d, ne, 7]
-        T += np.einsum("nq,dnq,nqx->dnx", w[None, :] * mesh.area[tri][:, None], ph, f)
+    e, tri, free, c = mesh.restricted_halves(0)
+    pts = mesh.qpts[tri]                                                         # [nh, 7, 3]
+    f = (c * mesh.length[e] / (2 * mesh.area[tri]))[:, None, None] * (pts - mesh.vertices[free][:, None, :])
+    ph = np.exp(1j * k0 * np.einsum("dx,nqx->dnq", r_hat, pts))                  # [d, nh, 7]
+    part = np.einsum("nq,dnq,nqx->dnx", w[None, :] * mesh.area[tri][:, None], ph, f)
+    for d in range(len(r_hat)):
+        np.add.at(T[d], e, part[d])
     return T
 
 
@@ -46,9 +49,8 @@ def far_field(mesh: RWGMesh, frequency, x, theta, phi):
     """F(theta, phi) [..., 3] for the scaled unknowns x = [J ; M~] (one RHS)."""
     k0 = 2 * np.pi * frequency / C0
     ne = mesh.n_edges
-    s0 = mesh.region_sign(0)
-    J = s0 * x[:ne]
-    Mt = s0 * x[ne:]
+    J = x[:ne]
+    Mt = x[ne:]
     r, th, ph = spherical_units(np.atleast_1d(theta), np.atleast_1d(phi))
     T = basis_transforms(mesh, frequency, r)
     Jh = np.einsum("dnx,n->dx", T, J)

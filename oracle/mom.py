@@ -23,6 +23,8 @@ acting on [J ; M~] with M~ = M / eta0 and et_r = eta_r / eta0 (the E-rows are
 divided by eta0, the H-rows are unchanged), so both unknowns and both rows
 carry A/m and A.  The right-hand side is b_i = -s_0i [<f, E_inc>/eta0 ;
 <f, H_inc>], non-zero only on interfaces that touch free space (region 0).
+The region signs are carried per triangle (rwg module), which also covers
+junction edges whose halves lie on different interfaces.
 The boundary layout is [J_1..J_E, M~_1..M~_E] in canonical edge order.
 
 Integration (the paper is silent): 7-point rule for outer and inner integrals.
@@ -145,56 +147,61 @@ def pair_interactions(mesh: RWGMesh, P: int, Qs: np.ndarray, k: complex):
 
 
 def operator_rows(mesh: RWGMesh, k: complex, region: int, test_edges):
-    """Rows ``test_edges`` of L_r and K_r over all basis functions (columns in
-    canonical order), using only triangles that border ``region``."""
+    """Rows ``test_edges`` of L_r and K_r between the basis functions
+    restricted to ``region`` (columns in canonical order): only triangles that
+    border the region take part, each half weighted by its triangle's region
+    sign, so the result already carries the sign products of eq. 16."""
     test_edges = np.asarray(test_edges, dtype=np.int64)
     ne = mesh.n_edges
     L = np.zeros((len(test_edges), ne), dtype=complex)
     K = np.zeros((len(test_edges), ne), dtype=complex)
-    border = np.nonzero((mesh.tri_regions[:, 0] == region) | (mesh.tri_regions[:, 1] == region))[0]
+    trs = mesh.tri_region_sign(region)
+    border = np.nonzero(trs)[0]
     edge_pos = {e: i for i, e in enumerate(test_edges)}
-    tris = sorted({int(t) for e in test_edges for t in (mesh.tri_p[e], mesh.tri_m[e])})
+    tris = sorted({int(t) for e in test_edges for t in mesh.side_tri[e] if t >= 0})
     for P in tris:
-        if P not in set(border.tolist()):
+        if trs[P] == 0:
             continue
         L_loc, K_loc = pair_interactions(mesh, P, border, k)
         for i in range(3):
             m = mesh.tri_edge[P, i]
             if m not in edge_pos:
                 continue
-            sm = mesh.tri_sign[P, i] * mesh.length[m]
+            sm = trs[P] * mesh.tri_sign[P, i] * mesh.length[m]
             row = edge_pos[m]
             for j in range(3):
                 n = mesh.tri_edge[border, j]
-                sn = mesh.tri_sign[border, j] * mesh.length[n]
+                sn = trs[border] * mesh.tri_sign[border, j] * mesh.length[n]
                 np.add.at(L[row], n, sm * sn * L_loc[:, i, j])
                 np.add.at(K[row], n, sm * sn * K_loc[:, i, j])
     return L, K
 
 
 def operator_near(mesh: RWGMesh, k: complex, region: int, near):
-    """L_r and K_r restricted to the boolean edge-pair pattern ``near``
-    ([ne, ne]); entries outside the pattern are zero.  Only the triangle pairs
-    that contribute to pattern entries are integrated."""
+    """As operator_rows for all rows, restricted to the boolean edge-pair
+    pattern ``near`` ([ne, ne]); entries outside the pattern are zero.  Only
+    the triangle pairs that contribute to pattern entries are integrated."""
     ne = mesh.n_edges
     L = np.zeros((ne, ne), dtype=complex)
     K = np.zeros((ne, ne), dtype=complex)
-    border = (mesh.tri_regions[:, 0] == region) | (mesh.tri_regions[:, 1] == region)
+    trs = mesh.tri_region_sign(region)
+    border = trs != 0
     for P in np.nonzero(border)[0]:
         edges_P = mesh.tri_edge[P]
         cols = np.nonzero(near[edges_P].any(axis=0))[0]
-        Qs = np.unique(np.concatenate([mesh.tri_p[cols], mesh.tri_m[cols]]))
+        Qs = mesh.side_tri[cols].ravel()
+        Qs = np.unique(Qs[Qs >= 0])
         Qs = Qs[border[Qs]]
         if len(Qs) == 0:
             continue
         L_loc, K_loc = pair_interactions(mesh, P, Qs, k)
         for i in range(3):
             m = edges_P[i]
-            sm = mesh.tri_sign[P, i] * mesh.length[m]
+            sm = trs[P] * mesh.tri_sign[P, i] * mesh.length[m]
             for j in range(3):
                 n = mesh.tri_edge[Qs, j]
                 keep = near[m, n]
-                sn = mesh.tri_sign[Qs, j] * mesh.length[n]
+                sn = trs[Qs] * mesh.tri_sign[Qs, j] * mesh.length[n]
                 np.add.at(L[m], n[keep], (sm * sn * L_loc[:, i, j])[keep])
                 np.add.at(K[m], n[keep], (sm * sn * K_loc[:, i, j])[keep])
     return L, K
@@ -206,17 +213,15 @@ def pmchwt_near(mesh: RWGMesh, eps_r, mu_r, frequency, near):
     ne = mesh.n_edges
     Z = np.zeros((2 * ne, 2 * ne), dtype=complex)
     for r in range(len(eps_r)):
-        s = mesh.region_sign(r)
-        if not np.any(s):
+        if not np.any(mesh.tri_region_sign(r)):
             continue
         k = wavenumber(frequency, eps_r[r], mu_r[r])
         et = rel_impedance(eps_r[r], mu_r[r])
         L, K = operator_near(mesh, k, r, near)
-        sign = s[:, None] * s[None, :]
-        Z[:ne, :ne] += sign * et * L
-        Z[:ne, ne:] += -sign * K
-        Z[ne:, :ne] += sign * K
-        Z[ne:, ne:] += sign * L / et
+        Z[:ne, :ne] += et * L
+        Z[:ne, ne:] += -K
+        Z[ne:, :ne] += K
+        Z[ne:, ne:] += L / et
     return Z
 
 
@@ -228,18 +233,17 @@ def pmchwt_rows(mesh: RWGMesh, eps_r, mu_r, frequency, test_edges):
     ZE = np.zeros((len(test_edges), 2 * ne), dtype=complex)
     ZH = np.zeros((len(test_edges), 2 * ne), dtype=complex)
     for r in range(len(eps_r)):
-        s = mesh.region_sign(r)
-        sm = s[test_edges]
-        if not np.any(sm) or not np.any(s):
+        trs = mesh.tri_region_sign(r)
+        touched = np.any(trs[mesh.side_tri[test_edges].clip(0)] * (mesh.side_tri[test_edges] >= 0))
+        if not touched:
             continue
         k = wavenumber(frequency, eps_r[r], mu_r[r])
         et = rel_impedance(eps_r[r], mu_r[r])
         L, K = operator_rows(mesh, k, r, test_edges)
-        sign = sm[:, None] * s[None, :]
-        ZE[:, :ne] += sign * et * L
-        ZE[:, ne:] += -sign * K
-        ZH[:, :ne] += sign * K
-        ZH[:, ne:] += sign * L / et
+        ZE[:, :ne] += et * L
+        ZE[:, ne:] += -K
+        ZH[:, :ne] += K
+        ZH[:, ne:] += L / et
     return ZE, ZH
 
 
@@ -271,13 +275,11 @@ def planewave_rhs(mesh: RWGMesh, frequency, k_hat, e_hat, E0=1.0):
     ne = mesh.n_edges
     bE = np.zeros(ne, dtype=complex)
     bH = np.zeros(ne, dtype=complex)
-    s0 = mesh.region_sign(0)
-    for side, (tri, free, sgn) in enumerate(((mesh.tri_p, mesh.free_p, 1.0), (mesh.tri_m, mesh.free_m, -1.0))):
-        pts = mesh.qpts[tri]                                           # [ne, 7, 3]
-        f = sgn * (mesh.length / (2 * mesh.area[tri]))[:, None, None] * (pts - mesh.vertices[free][:, None, :])
-        phase = E0 * np.exp(-1j * k0 * pts @ k_hat)                    # [ne, 7]
-        fe = f @ e_hat
-        fh = f @ h_hat
-        bE += mesh.area[tri] * np.sum(w * fe * phase, axis=1)
-        bH += mesh.area[tri] * np.sum(w * fh * phase, axis=1)
-    return np.concatenate([-s0 * bE / ETA0, -s0 * bH / ETA0])
+    # basis functions restricted to free space (region 0), region sign included
+    e, tri, free, c = mesh.restricted_halves(0)
+    pts = mesh.qpts[tri]                                               # [nh, 7, 3]
+    f = (c * mesh.length[e] / (2 * mesh.area[tri]))[:, None, None] * (pts - mesh.vertices[free][:, None, :])
+    phase = E0 * np.exp(-1j * k0 * pts @ k_hat)                        # [nh, 7]
+    np.add.at(bE, e, mesh.area[tri] * np.sum(w * (f @ e_hat) * phase, axis=1))
+    np.add.at(bH, e, mesh.area[tri] * np.sum(w * (f @ h_hat) * phase, axis=1))
+    return np.concatenate([-bE / ETA0, -bH / ETA0])

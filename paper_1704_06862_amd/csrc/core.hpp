@@ -56,16 +56,33 @@ struct Mesh {
     std::vector<double> area, maxedge;
     std::vector<V3> normal, centroid;
     std::vector<std::array<V3, 7>> qp;     // quadrature nodes
-    // edges, canonical order
+    // edges, canonical order.  An edge carries one half basis function
+    // h_t = l / (2 A_t) (r - v_t) (flux out of t across the edge) on each of
+    // its nside triangles: two on an interface, three where three regions
+    // meet (a junction edge).  Its coefficient there is +1 on a triangle that
+    // runs along the edge from the smaller to the larger vertex id (T+), -1
+    // otherwise, so f = h_T+ - h_T- on an interface edge.
     std::vector<std::array<int, 2>> ev;    // (min, max) vertex ids
-    std::vector<int> tp, tm, fp, fm;       // T+, T-, free vertices
+    std::vector<int> nside;
+    std::vector<std::array<int, 3>> etri, efree, ecoef;
     std::vector<double> len;
-    std::vector<std::array<int, 2>> ereg;  // (front, back) region of the interface
-    // per triangle and local vertex i: opposite edge and sign of its basis there
+    // per triangle and local vertex i: opposite edge and coefficient of its
+    // half basis there
     std::vector<std::array<int, 3>> tri_edge;
     std::vector<std::array<int, 3>> tri_sign;
-    int region_sign(int e, int r) const {
-        return ereg[e][0] == r ? 1 : (ereg[e][1] == r ? -1 : 0);
+    // region sign of triangle t for region r (eqs. 12-13, 16): +1 if its
+    // normal points into r, -1 if r lies behind it, 0 if t does not border r
+    int tri_region_sign(int t, int r) const { return TR[t][0] == r ? 1 : (TR[t][1] == r ? -1 : 0); }
+    // Restricted to region r, basis e is s * sum over its triangles t that
+    // border r of c_t h_t, with s = edge_region_sign(e, r) and
+    // c_t = s * tri_region_sign(t, r) * ecoef[e][t]; for an interface edge s
+    // is the interface's region sign and c_t = ecoef.  0 if e does not touch r.
+    int edge_region_sign(int e, int r) const {
+        for (int i = 0; i < nside[e]; ++i) {
+            const int s = tri_region_sign(etri[e][i], r);
+            if (s) return s;
+        }
+        return 0;
     }
 };
 

@@ -1443,18 +1443,25 @@ class DeviceBodyT final : public DeviceBody {
         device_free(da);
     }
 
+    // far field through device staging buffers dd [2 n_dirs] and
+    // ds [2 n_dirs n_rhs]; synchronous
+    void rcs_staged(int n_rhs, const void *x_dev, int n_dirs, const double *tp, double *sigma, double *dd,
+                    double *ds) {
+        HIPCHK(hipMemcpyAsync(dd, tp, sizeof(double) * 2 * n_dirs, hipMemcpyHostToDevice, stream_));
+        dim3 grid(n_dirs, (n_rhs + RCS_RT - 1) / RCS_RT);
+        k_far_field<<<grid, 256, 0, stream_>>>(ne_, n_rhs, gs0_, gqr_, gqf_, h_.mesh.k0, ETA0, dd,
+                                               (const double2 *)x_dev, ds, n_dirs);
+        LAUNCHCHK();
+        HIPCHK(hipMemcpyAsync(sigma, ds, sizeof(double) * 2 * (size_t)n_dirs * n_rhs, hipMemcpyDeviceToHost,
+                              stream_));
+        HIPCHK(hipStreamSynchronize(stream_));
+    }
+
     void rcs(int n_rhs, const void *x_dev, int n_dirs, const double *tp, double *sigma) override {
         double *dd = (double *)device_alloc(sizeof(double) * 2 * n_dirs);
         double *ds = (double *)device_alloc(sizeof(double) * 2 * (size_t)n_dirs * n_rhs);
         try {
-            HIPCHK(hipMemcpyAsync(dd, tp, sizeof(double) * 2 * n_dirs, hipMemcpyHostToDevice, stream_));
-            dim3 grid(n_dirs, (n_rhs + RCS_RT - 1) / RCS_RT);
-            k_far_field<<<grid, 256, 0, stream_>>>(ne_, n_rhs, gs0_, gqr_, gqf_, h_.mesh.k0, ETA0, dd,
-                                                   (const double2 *)x_dev, ds, n_dirs);
-            LAUNCHCHK();
-            HIPCHK(hipMemcpyAsync(sigma, ds, sizeof(double) * 2 * (size_t)n_dirs * n_rhs, hipMemcpyDeviceToHost,
-                                  stream_));
-            HIPCHK(hipStreamSynchronize(stream_));
+            rcs_staged(n_rhs, x_dev, n_dirs, tp, sigma, dd, ds);
         } catch (...) {
             device_free(dd);
             device_free(ds);
@@ -1471,10 +1478,15 @@ class DeviceBodyT final : public DeviceBody {
         std::vector<double> qr((size_t)14 * 3 * ne), qf(qr.size());
         std::vector<int> s0(ne);
         for (int e = 0; e < ne; ++e) {
-            s0[e] = m.region_sign(e, 0);
-            for (int side = 0; side < 2; ++side) {
-                const int tri = side ? m.tm[e] : m.tp[e], fv = side ? m.fm[e] : m.fp[e];
-                const double coef = (side ? -1.0 : 1.0) * m.len[e] / (2.0 * m.area[tri]);
+            // the basis restricted to the exterior region: its two triangles
+            // there (none if the edge does not touch the exterior)
+            s0[e] = m.edge_region_sign(e, 0);
+            int side = 0;
+            for (int i = 0; i < m.nside[e] && s0[e]; ++i) {
+                const int tri = m.etri[e][i], fv = m.efree[e][i];
+                const int rs = m.tri_region_sign(tri, 0);
+                if (!rs || side == 2) continue;
+                const double coef = s0[e] * rs * m.ecoef[e][i] * m.len[e] / (2.0 * m.area[tri]);
                 for (int a = 0; a < 7; ++a) {
                     const V3 &r = m.qp[tri][a];
                     const double w = q.w[a] * m.area[tri];
@@ -1484,6 +1496,7 @@ class DeviceBodyT final : public DeviceBody {
                         qf[((size_t)qi * 3 + c) * ne + e] = coef * (r[c] - m.V[fv][c]) * w;
                     }
                 }
+                ++side;
             }
         }
         gs0_ = upload(s0);

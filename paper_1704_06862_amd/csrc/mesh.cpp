@@ -3,6 +3,14 @@
 // Basis n on edge (a, b), a < b: f_n = +l/(2A+) (r - v+) on T+ (the triangle
 // whose CCW order runs a -> b), f_n = -l/(2A-) (r - v-) on T-.  Its divergence
 // is +l/A+ and -l/A-, so every basis function carries zero net charge.
+//
+// Junction edges (three regions meeting along a line, as between the layers
+// of a stacked body) carry one such half function on each of their three
+// triangles, with the same +1 / -1 rule.  Each region sees two of the three;
+// with the region signs of eq. 16 those two form an ordinary RWG function of
+// the region's closed boundary, so one J and one M unknown per junction edge
+// describe the tangential H and E along the junction line, which are shared
+// by all three regions.
 #include <algorithm>
 #include <cmath>
 #include <map>
@@ -105,49 +113,73 @@ Mesh build_mesh(const sfmm_body &b) {
     }
 
     // directed edges: local vertex i is free for the edge (i+1) -> (i+2)
-    struct Side { int tri = -1, free = -1, local = -1; };
-    std::map<std::pair<int, int>, std::pair<Side, Side>> edges;  // (plus, minus)
+    struct Side { int tri, free, local, dir; };
+    std::map<std::pair<int, int>, std::vector<Side>> edges;
     for (int t = 0; t < m.nt; ++t) {
         for (int i = 0; i < 3; ++i) {
             int x = m.T[t][(i + 1) % 3], y = m.T[t][(i + 2) % 3];
-            auto key = std::make_pair(std::min(x, y), std::max(x, y));
-            auto &e = edges[key];
-            Side &s = (x < y) ? e.first : e.second;
-            if (s.tri >= 0)
-                throw Error(SFMM_E_MESH, "edge traversed twice in one direction (non-manifold, mis-oriented "
-                                         "or a junction edge, which this build does not support)");
-            s.tri = t;
-            s.free = m.T[t][i];
-            s.local = i;
+            edges[{std::min(x, y), std::max(x, y)}].push_back({t, m.T[t][i], i, x < y ? 1 : -1});
         }
     }
     m.ne = (int)edges.size();
     m.ev.resize(m.ne);
-    m.tp.resize(m.ne);
-    m.tm.resize(m.ne);
-    m.fp.resize(m.ne);
-    m.fm.resize(m.ne);
+    m.nside.resize(m.ne);
+    m.etri.assign(m.ne, {-1, -1, -1});
+    m.efree.assign(m.ne, {-1, -1, -1});
+    m.ecoef.assign(m.ne, {0, 0, 0});
     m.len.resize(m.ne);
-    m.ereg.resize(m.ne);
     m.tri_edge.assign(m.nt, {-1, -1, -1});
     m.tri_sign.assign(m.nt, {0, 0, 0});
     int e = 0;
     for (auto &kv : edges) {  // std::map iterates in (min, max) order = canonical order
-        const Side &p = kv.second.first, &n = kv.second.second;
-        if (p.tri < 0 || n.tri < 0) throw Error(SFMM_E_MESH, "open surface or inconsistent orientation");
-        if (m.TR[p.tri] != m.TR[n.tri])
-            throw Error(SFMM_E_MESH, "edge between triangles of different interfaces");
+        std::vector<Side> &sd = kv.second;
+        if (sd.size() < 2) throw Error(SFMM_E_MESH, "open surface: an edge with a single triangle");
+        if (sd.size() > 3)
+            throw Error(SFMM_E_MESH, "an edge shared by more than three triangles (only junctions of three "
+                                     "regions are supported)");
+        // T+ sides first, each group by triangle index
+        std::sort(sd.begin(), sd.end(), [](const Side &a, const Side &b) {
+            return a.dir != b.dir ? a.dir > b.dir : a.tri < b.tri;
+        });
+        // every region that borders the edge sees exactly two of its
+        // triangles, and its closed boundary is consistently oriented there:
+        // seen from the region, the two run along the edge in opposite
+        // directions (sigma_t dir_t = -sigma_t' dir_t').  Then the half
+        // bases with coefficients dir restrict to a standard RWG function on
+        // every region's boundary (flux out of one triangle into the other).
+        std::vector<int> regs;
+        for (const Side &a : sd)
+            for (int j = 0; j < 2; ++j)
+                if (std::find(regs.begin(), regs.end(), m.TR[a.tri][j]) == regs.end()) regs.push_back(m.TR[a.tri][j]);
+        for (int r : regs) {
+            int cnt = 0, acc = 0;
+            for (const Side &a : sd) {
+                const int sg = m.tri_region_sign(a.tri, r);
+                if (!sg) continue;
+                ++cnt;
+                acc += sg * a.dir;
+            }
+            if (cnt != 2)
+                throw Error(SFMM_E_MESH, sd.size() == 2 ? "edge between triangles of different interfaces"
+                                                        : "junction edge where a region does not see exactly "
+                                                          "two of the three triangles");
+            if (acc != 0)
+                throw Error(SFMM_E_MESH, sd.size() == 2 ? "inconsistent orientation across an edge (or an open "
+                                                          "or non-manifold surface)"
+                                                        : "inconsistent orientation at a junction edge");
+        }
         m.ev[e] = {kv.first.first, kv.first.second};
-        m.tp[e] = p.tri;
-        m.tm[e] = n.tri;
-        m.fp[e] = p.free;
-        m.fm[e] = n.free;
+        m.nside[e] = (int)sd.size();
+        for (size_t i = 0; i < sd.size(); ++i) {
+            m.etri[e][i] = sd[i].tri;
+            m.efree[e][i] = sd[i].free;
+            m.ecoef[e][i] = sd[i].dir;
+            if (m.tri_edge[sd[i].tri][sd[i].local] >= 0)
+                throw Error(SFMM_E_MESH, "triangle with a repeated edge");
+            m.tri_edge[sd[i].tri][sd[i].local] = e;
+            m.tri_sign[sd[i].tri][sd[i].local] = sd[i].dir;
+        }
         m.len[e] = norm(m.V[kv.first.second] - m.V[kv.first.first]);
-        m.ereg[e] = m.TR[p.tri];
-        m.tri_edge[p.tri][p.local] = e;
-        m.tri_sign[p.tri][p.local] = 1;
-        m.tri_edge[n.tri][n.local] = e;
-        m.tri_sign[n.tri][n.local] = -1;
         ++e;
     }
     return m;

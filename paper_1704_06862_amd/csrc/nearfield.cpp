@@ -225,13 +225,17 @@ NearMatrix fill_near(const Mesh &m, const Octree &o) {
             sources.clear();
             for (int r = 0; r < nrow; ++r) {
                 int e = o.order[o.bstart[b] + r];
-                for (int t : {m.tp[e], m.tm[e]})
+                for (int i = 0; i < m.nside[e]; ++i) {
+                    const int t = m.etri[e][i];
                     if (!(seen[t] & 1)) { seen[t] |= 1; tests.push_back(t); }
+                }
             }
             for (int c = 0; c < ncol; ++c) {
                 int e = o.order[Z.cols[Z.col_ptr[b] + c]];
-                for (int t : {m.tp[e], m.tm[e]})
+                for (int i = 0; i < m.nside[e]; ++i) {
+                    const int t = m.etri[e][i];
                     if (!(seen[t] & 2)) { seen[t] |= 2; sources.push_back(t); }
+                }
             }
             for (int t : tests) seen[t] = 0;
             for (int t : sources) seen[t] = 0;
@@ -248,12 +252,12 @@ NearMatrix fill_near(const Mesh &m, const Octree &o) {
                             int em = m.tri_edge[P][i];
                             int row = rowmap[em];
                             if (row < 0) continue;
-                            double sm = m.region_sign(em, r) * m.tri_sign[P][i] * m.len[em];
+                            double sm = m.tri_region_sign(P, r) * m.tri_sign[P][i] * m.len[em];
                             for (int j = 0; j < 3; ++j) {
                                 int en = m.tri_edge[Q][j];
                                 int col = colmap[en];
                                 if (col < 0) continue;
-                                double sn = m.region_sign(en, r) * m.tri_sign[Q][j] * m.len[en];
+                                double sn = m.tri_region_sign(Q, r) * m.tri_sign[Q][j] * m.len[en];
                                 double f = sm * sn;
                                 int64_t idx = base + (int64_t)row * ncol + col;
                                 Z.A[idx] += f * et * L[i][j];

@@ -151,7 +151,7 @@ Octree build_octree(const Mesh &m, double finest_box, int n_levels, double digit
         for (int b = 0; b < o.nb; ++b) {
             int cnt = 0;
             for (int p = o.bstart[b]; p < o.bstart[b + 1]; ++p) {
-                int s = m.region_sign(o.order[p], r);
+                int s = m.edge_region_sign(o.order[p], r);
                 if (s) {
                     rt.edge_pos.push_back(p);
                     rt.edge_sign.push_back(s);

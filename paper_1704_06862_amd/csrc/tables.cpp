@@ -127,20 +127,26 @@ RegionTables build_tables(const Mesh &m, const Octree &o, const RegionTree &rt) 
         for (int d = 0; d < 3; ++d) c[d] = o.corner[d] + (o.bkey[b][d] + 0.5) * o.a_f;
         for (int ie = rt.edge_ptr[ib]; ie < rt.edge_ptr[ib + 1]; ++ie) {
             const int e = o.order[rt.edge_pos[ie]];
-            // 14 weighted vector samples of f_e
+            // 14 weighted vector samples of f_e restricted to the region (its
+            // two triangles there; the region sign stays in edge_sign)
             V3 fv[14], pts[14];
             double wq[14];
-            for (int side = 0; side < 2; ++side) {
-                int tri = side ? m.tm[e] : m.tp[e];
-                int fvtx = side ? m.fm[e] : m.fp[e];
-                double sg = side ? -1.0 : 1.0;
-                double coef = sg * m.len[e] / (2.0 * m.area[tri]);
+            const int es = rt.edge_sign[ie];
+            int side = 0;
+            for (int i = 0; i < m.nside[e]; ++i) {
+                const int tri = m.etri[e][i];
+                const int rs = m.tri_region_sign(tri, rt.region);
+                if (!rs) continue;
+                if (side == 2) throw Error(SFMM_E_MESH, "edge with more than two triangles in one region");
+                const double coef = es * rs * m.ecoef[e][i] * m.len[e] / (2.0 * m.area[tri]);
                 for (int a = 0; a < 7; ++a) {
                     pts[side * 7 + a] = m.qp[tri][a] - c;
-                    fv[side * 7 + a] = coef * (m.qp[tri][a] - m.V[fvtx]);
+                    fv[side * 7 + a] = coef * (m.qp[tri][a] - m.V[m.efree[e][i]]);
                     wq[side * 7 + a] = q.w[a] * m.area[tri];
                 }
+                ++side;
             }
+            if (side != 2) throw Error(SFMM_E_MESH, "region edge without two triangles in the region");
             cd *tx = &t.tx[(size_t)ie * 2 * Kf];
             cd *rx = t.lossy ? &t.rx[(size_t)ie * 2 * Kf] : nullptr;
             for (int kk = 0; kk < Kf; ++kk) {

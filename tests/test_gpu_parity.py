@@ -3,9 +3,18 @@
 Tolerances: FP64 near-field products and ILU(0) solves are exact up to
 rounding (1e-11 relative); FP32 ones carry single-precision rounding of
 sums over a few hundred terms (1e-5); the full MLFMM product approximates the
-dense Galerkin matrix to the stated 1e-3 relative 2-norm error; RCS agrees
-with the oracle's LU solution within 0.2 dB above a -30 dB floor (relative to
-the cut's maximum)."""
+dense Galerkin matrix to the stated 1e-3 relative 2-norm error, in every
+precision; RCS agrees with the oracle's LU solution within 0.2 dB above a
+-30 dB floor (relative to the cut's maximum).
+
+Trees: the 960-unknown sphere in FP64 uses 0.15-wavelength boxes with five
+extra multipoles (4e-4 from the dense matrix).  Single precision cannot reach
+1e-3 with 0.15-wavelength boxes: the diagonal translation there needs about
+five extra multipoles for it, and at that order it amplifies FP32 rounding
+about 276-fold (setup refuses it); with one or two extra multipoles FP32 and
+FP64 alike stay at 1.1e-3 to 1.5e-3, the truncation error.  The FP32 and
+bf16-split full products of the small spheres therefore use 0.2-wavelength
+boxes (one extra multipole: 1.4e-4 in every precision)."""
 
 import numpy as np
 import pytest
@@ -18,6 +27,8 @@ pytestmark = pytest.mark.gpu
 sfmm = pytest.importorskip("paper_1704_06862_amd.sfmm")
 
 SPHERE960_OPTS = dict(finest_box=0.15, n_levels=3, extra_multipoles=5, preconditioner=0)
+# single-precision products of the small spheres (see the module docstring)
+SPHERE960_F32 = dict(finest_box=0.2, n_levels=3, extra_multipoles=1, preconditioner=0, tol=1e-4)
 THETA = np.deg2rad(np.arange(181.0))
 
 
@@ -58,6 +69,20 @@ def ctx32(sphere960):
 
 
 @pytest.fixture(scope="module")
+def ctx32f(sphere960):
+    print("setup sphere960 fp32, 0.2-wavelength boxes", flush=True)
+    with sfmm.Context([sphere960["body"]], precision=sfmm.PREC_FP32, **SPHERE960_F32) as c:
+        yield c
+
+
+@pytest.fixture(scope="module")
+def ctxbff(sphere960):
+    print("setup sphere960 bf16-split, 0.2-wavelength boxes", flush=True)
+    with sfmm.Context([sphere960["body"]], precision=sfmm.PREC_BF16_SPLIT, **SPHERE960_F32) as c:
+        yield c
+
+
+@pytest.fixture(scope="module")
 def ctxbf(sphere960):
     print("setup sphere960 bf16-split", flush=True)
     opts = dict(SPHERE960_OPTS, extra_multipoles=1, tol=1e-4)
@@ -79,17 +104,17 @@ def test_batched_near_on_matrix_cores(sphere960, ctx32, ctxbf, R):
 
 
 @pytest.mark.parametrize("R", [16, 64])
-def test_batched_full_product_on_matrix_cores(sphere960, ctx32, ctxbf, R):
+def test_batched_full_product_on_matrix_cores(sphere960, ctx32f, ctxbff, R):
     # aggregation, receive (and, from 33 RHS, the sibling-grouped translation)
     # switch to their batched kernels
     x = random_complex_vector(sphere960["x"].shape[1], R, seed=60 + R)
     ref = x @ sphere960["Z"].T
-    for ctx in (ctx32, ctxbf):
+    for ctx in (ctx32f, ctxbff):
         y = ctx.sfmm_matvec(x, np.zeros_like(x))
         err = max(rel(y[r], ref[r]) for r in range(R))
         y1 = ctx.sfmm_matvec(np.ascontiguousarray(x[:1]), np.zeros_like(x[:1]))[0]
         print(R, "batched full rel err", err, "vs single", rel(y[0], y1))
-        assert err < 3e-3
+        assert err < 1e-3
         assert rel(y[0], y1) < 1e-4
 
 
@@ -107,7 +132,7 @@ def coated():
 def test_coated_lossy_sphere_product_and_rcs(coated, prec):
     b, m, Z = coated["body"], coated["mesh"], coated["Z"]
     p = sfmm.PREC_FP64 if prec == "fp64" else sfmm.PREC_FP32
-    opts = dict(finest_box=0.15, n_levels=3, extra_multipoles=5 if prec == "fp64" else 1,
+    opts = dict(finest_box=0.15 if prec == "fp64" else 0.2, n_levels=3, extra_multipoles=5 if prec == "fp64" else 1,
                 tol=1e-6 if prec == "fp64" else 1e-4)
     with sfmm.Context([b], precision=p, **opts) as ctx:
         assert ctx.sfmm_num_unknowns() == 2 * m.n_edges
@@ -117,7 +142,7 @@ def test_coated_lossy_sphere_product_and_rcs(coated, prec):
             ref = x @ Z.T
             err = max(rel(y[r], ref[r]) for r in range(R))
             print(prec, R, "coated product rel err", err)
-            assert err < (1e-3 if prec == "fp64" else 3e-3)
+            assert err < 1e-3
         kh, eh = mom.incidence(0.0, 0.0)
         rhs = mom.planewave_rhs(m, b.frequency, kh, eh)[None, :].copy()
         xs = np.zeros_like(rhs)
@@ -146,14 +171,14 @@ def test_near_product_fp32(sphere960, ctx32):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
-def test_full_product_matches_dense(sphere960, ctx64, ctx32, ctxbf, prec):
-    ctx = {"fp64": ctx64, "fp32": ctx32, "bf16": ctxbf}[prec]
+def test_full_product_matches_dense(sphere960, ctx64, ctx32f, ctxbff, prec):
+    ctx = {"fp64": ctx64, "fp32": ctx32f, "bf16": ctxbff}[prec]
     x = sphere960["x"]
     y = ctx.sfmm_matvec(x, np.zeros_like(x))
     ref = x @ sphere960["Z"].T
     err = rel(y, ref)
     print(prec, "matvec rel err", err)
-    assert err < (1e-3 if prec == "fp64" else 3e-3)
+    assert err < 1e-3
     # the far part alone is a sizeable share of the product
     yf = ctx.sfmm_matvec(x, np.zeros_like(x), parts=sfmm.PART_FAR)
     assert np.linalg.norm(yf) > 0.03 * np.linalg.norm(ref)
@@ -225,8 +250,8 @@ def _masked_db(s, ref):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
-def test_solve_and_rcs_match_oracle(sphere960, ctx64, ctx32, ctxbf, prec):
-    ctx = {"fp64": ctx64, "fp32": ctx32, "bf16": ctxbf}[prec]
+def test_solve_and_rcs_match_oracle(sphere960, ctx64, ctx32f, ctxbff, prec):
+    ctx = {"fp64": ctx64, "fp32": ctx32f, "bf16": ctxbff}[prec]
     m, b, Z = sphere960["mesh"], sphere960["body"], sphere960["Z"]
     kh, eh = mom.incidence(0.0, 0.0)
     rhs = mom.planewave_rhs(m, b.frequency, kh, eh)[None, :].copy()
@@ -236,7 +261,7 @@ def test_solve_and_rcs_match_oracle(sphere960, ctx64, ctx32, ctxbf, prec):
     tol = 1e-6 if prec == "fp64" else 1e-4
     assert info["converged"] and info["true_residual"] <= tol
     # residual of the exact (dense) system is bounded by the product error
-    assert rel(Z @ x[0], rhs[0]) < (2e-3 if prec == "fp64" else 4e-3)
+    assert rel(Z @ x[0], rhs[0]) < 1e-3
     xd = np.linalg.solve(Z, rhs[0])
     tp_e = np.stack([THETA, 0 * THETA], 1)
     tp_h = np.stack([THETA, 0 * THETA + np.pi / 2], 1)
@@ -389,7 +414,7 @@ def test_polynomial_preconditioned_solve_matches_oracle(sphere960):
         info = ctx.sfmm_solve(rhs[None, :].copy(), x)[0]
     print("poly solve", info, "oracle its", oinfo.iterations)
     assert info["converged"] and abs(info["iterations"] - oinfo.iterations) <= 2
-    assert rel(Z @ x[0], rhs) < 2e-3
+    assert rel(Z @ x[0], rhs) < 1e-3
 
 
 def test_graph_replays_match_eager(sphere960):
@@ -424,14 +449,14 @@ BATCHED_PLANS = {"mfma": 1 | 2 | 4 | 8 | 16, "vector": 1 | 16}
 
 def test_batched_interpolation_variants():
     # the batched products of a 4-level tree (two interpolation levels) on
-    # the matrix cores and with the vector kernels:
-    # within the MLFMM truncation error of the oracle's rows (about 1e-3 for
-    # this tree; the bound is on the worst of all right-hand sides) and within
-    # FP32 rounding of each other
+    # the matrix cores and with the vector kernels: within 1e-3 of the
+    # oracle's rows for the worst of all right-hand sides (two extra
+    # multipoles; the excess-bandwidth order alone gives up to 1.5e-3 on some
+    # right-hand sides of this tree) and within FP32 rounding of each other
     b = sphere_body(1.0, 2.56, 3)
     m = rwg.from_body(b)
     rng = np.random.default_rng(8)
-    test = np.sort(rng.choice(m.n_edges, 24, replace=False))
+    test = np.sort(rng.choice(m.n_edges, 60, replace=False))
     ZE, ZH = mom.pmchwt_rows(m, b.eps_r, b.mu_r, b.frequency, test)
     for R in (20, 64):
         x = random_complex_vector(2 * m.n_edges, R, seed=300 + R)
@@ -444,7 +469,7 @@ def test_batched_interpolation_variants():
             err = max(rel(np.concatenate([y[r][test], y[r][m.n_edges + test]]),
                           np.concatenate([ZE @ x[r], ZH @ x[r]])) for r in range(R))
             print(R, name, "sampled-row rel err", err)
-            assert err < 2e-3
+            assert err < 1e-3
             ys[name] = y
         for name, y in ys.items():
             d = max(rel(y[r], ys["vector"][r]) for r in range(R))
@@ -487,10 +512,10 @@ def test_autotuned_batched_product(sphere960):
     # whatever the autotuner picks per batch size, the products stay within
     # the MLFMM tolerance of the dense matrix
     b = sphere960["body"]
-    opts = dict(SPHERE960_OPTS, extra_multipoles=1, tol=1e-4, autotune=1)
+    opts = dict(SPHERE960_F32, autotune=1)
     with sfmm.Context([b], precision=sfmm.PREC_FP32, **opts) as ctx:
         for R in (3, 24, 48):
             x = random_complex_vector(sphere960["x"].shape[1], R, seed=200 + R)
             y = ctx.sfmm_matvec(x, np.zeros_like(x))
             ref = x @ sphere960["Z"].T
-            assert max(rel(y[r], ref[r]) for r in range(R)) < 3e-3, R
+            assert max(rel(y[r], ref[r]) for r in range(R)) < 1e-3, R

@@ -210,3 +210,30 @@ def test_zero_pivot_reports_breakdown():
         with sfmm.Context([b], device=-1, preconditioner=pc):
             pass
     assert _status(lambda: sfmm.Context([b], device=-1, preconditioner=sfmm.PRECOND_ILU0, ilu_pivot_tol=-1.0)) == 1
+
+
+def test_junction_body_tables_match_oracle():
+    # three regions along the rim of the internal disc: the library's edge
+    # table and near-field rows (junction rows included) equal the oracle's
+    from workloads import stacked_cylinder_body
+    b = stacked_cylinder_body(0.3, 0.6, (2.2, 4.4), 0.1)
+    m = rwg.from_body(b)
+    junction = np.nonzero(m.side_tri[:, 2] >= 0)[0]
+    with sfmm.Context([b], device=-1, finest_box=0.15, precision=2) as ctx:
+        assert np.array_equal(ctx.sfmm_edges(), m.edge_v)
+        d = ctx.sfmm_describe()
+        test = np.unique(np.concatenate([junction[::4], [0, 100, 300, m.n_edges - 1]]))
+        rows = ctx.sfmm_near_rows(test)
+    keys = octree.finest_keys(m, 0.15, d["levels"])
+    pat = np.tile(octree.near_mask(keys)[test], (1, 2))
+    ZE, ZH = mom.pmchwt_rows(m, b.eps_r, b.mu_r, b.frequency, test)
+    scale = np.abs(ZE).max()
+    assert np.abs(rows[:, 0] - np.where(pat, ZE, 0)).max() < 1e-12 * scale
+    assert np.abs(rows[:, 1] - np.where(pat, ZH, 0)).max() < 1e-12 * scale
+    # a junction where a region sees only one of the triangles is refused
+    t = b.triangles
+    disc = np.nonzero((b.tri_regions[:, 0] == 2) & (b.tri_regions[:, 1] == 1))[0]
+    bad = type(b)(b.vertices, np.delete(t, disc[:1], 0), np.delete(b.tri_regions, disc[:1], 0), b.eps_r, b.mu_r)
+    with pytest.raises(sfmm.SfmmError) as e:
+        sfmm.Context([bad], device=-1)
+    assert e.value.status == 2

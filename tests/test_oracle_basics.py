@@ -205,3 +205,48 @@ def test_octree_keys_near_and_colours():
     assert np.all(p[1::2] == p[0::2] + ne)
     c = colour[p[0::2]]
     assert np.all(np.diff(c) >= 0)
+
+
+# --- junction edges (three regions along a line) ------------------------------
+
+def test_junction_edges_restrict_to_rwg_functions_of_every_region():
+    from workloads import stacked_cylinder_body
+    b = stacked_cylinder_body(0.3, 0.6, (2.2, 4.4), 0.1)
+    m = rwg.from_body(b)
+    junction = np.nonzero(m.side_tri[:, 2] >= 0)[0]
+    assert len(junction) == 19                       # one ring of 19 edges
+    assert len(b.vertices) - m.n_edges + len(b.triangles) == 2 + 1   # two closed layers share a disc
+    for r in range(3):
+        e, tri, free, c = m.restricted_halves(r)
+        # every edge touching the region has exactly two halves there ...
+        cnt = np.bincount(e, minlength=m.n_edges)
+        assert set(np.unique(cnt)) <= {0, 2}
+        # ... and they form an RWG function of the region's closed boundary:
+        # flux +1 out of one half and +1 into the other, zero total charge
+        for k in np.nonzero(cnt == 2)[0][::3]:
+            sel = np.nonzero(e == k)[0]
+            assert sorted(c[sel]) == [-1.0, 1.0]
+            a, bb = m.vertices[m.edge_v[k]]
+            mid = 0.5 * (a + bb)
+            s_hat = (bb - a) / np.linalg.norm(bb - a)
+            flux = []
+            for h in sel:
+                cen = m.centroid[tri[h]]
+                out = (mid - cen) - np.dot(mid - cen, s_hat) * s_hat
+                out /= np.linalg.norm(out)
+                f = c[h] * m.length[k] / (2 * m.area[tri[h]]) * (mid - m.vertices[free[h]])
+                flux.append(np.dot(f, out))
+            assert abs(flux[0] + flux[1]) < 1e-12 and abs(abs(flux[0]) - 1) < 1e-12
+    # the merged body (no internal disc) has no junctions
+    mm = rwg.from_body(stacked_cylinder_body(0.3, 0.6, (2.2, 4.4), 0.1, merge_layers=True))
+    assert np.all(mm.side_tri[:, 2] < 0)
+
+
+def test_junction_orientation_errors_are_rejected():
+    from workloads import stacked_cylinder_body
+    b = stacked_cylinder_body(0.3, 0.6, (2.2, 4.4), 0.1)
+    t = b.triangles.copy()
+    disc = np.nonzero((b.tri_regions[:, 0] == 2) & (b.tri_regions[:, 1] == 1))[0]
+    t[disc] = t[disc][:, [0, 2, 1]]          # flip the internal disc only
+    with pytest.raises(rwg.MeshError):
+        rwg.build(b.vertices, t, b.tri_regions)

@@ -226,3 +226,33 @@ def test_coated_sphere_converges_to_the_coated_mie_series(coated1200):
     assert e1 < 0.6 and h1 < 0.7
     assert e2 < 0.15 and h2 < 0.2 and x2 < 0.3 and y2 < 0.6
     assert e2 < e1 / 3 and h2 < h1 / 3
+
+
+def test_equal_layers_of_a_stacked_cylinder_match_the_homogeneous_cylinder():
+    # junction edges (eq. 16 with three regions meeting along the rim of the
+    # internal disc): with both layers of one material the internal disc
+    # separates identical media and the stack must scatter like the same outer
+    # mesh without it.  A wrong sign on a junction half breaks this by dBs.
+    from workloads import stacked_cylinder_body
+    bs = stacked_cylinder_body(0.3, 0.6, (2.2, 2.2), 0.1)
+    bh = stacked_cylinder_body(0.3, 0.6, (2.2, 2.2), 0.1, merge_layers=True)
+    cuts = []
+    for b in (bs, bh):
+        m = rwg.from_body(b)
+        Z = mom.pmchwt_dense(m, b.eps_r, b.mu_r, b.frequency)
+        kh, eh = mom.incidence(0.6, 0.0)
+        x = np.linalg.solve(Z, mom.planewave_rhs(m, b.frequency, kh, eh))
+        sE, _ = farfield.rcs(m, b.frequency, x, THETA, 0 * THETA)
+        _, sH = farfield.rcs(m, b.frequency, x, THETA, 0 * THETA + np.pi / 2)
+        cuts.append((sE, sH))
+    for s, ref in zip(cuts[0], cuts[1]):
+        rms, mx = _db_rms_max(s, ref)
+        assert rms < 0.05 and mx < 0.2
+    # with different layers the stack scatters measurably differently
+    bd = stacked_cylinder_body(0.3, 0.6, (2.2, 10.2), 0.1)
+    m = rwg.from_body(bd)
+    Z = mom.pmchwt_dense(m, bd.eps_r, bd.mu_r, bd.frequency)
+    kh, eh = mom.incidence(0.6, 0.0)
+    x = np.linalg.solve(Z, mom.planewave_rhs(m, bd.frequency, kh, eh))
+    sE, _ = farfield.rcs(m, bd.frequency, x, THETA, 0 * THETA)
+    assert _db_rms_max(sE, cuts[1][0])[0] > 1.0

@@ -201,7 +201,7 @@ def _disc_mesh(radius: float, z: float, ring: np.ndarray, n_phi: int, target_edg
 
 
 def stacked_cylinder_body(radius: float = 1.0, height: float = 3.0, eps_layers=(2.2, 4.4, 10.2),
-                          target_edge: float = 0.05, name: str = "") -> Body:
+                          target_edge: float = 0.05, name: str = "", merge_layers: bool = False) -> Body:
     """Stack of equal-height dielectric cylinder layers (regions 1..n, bottom up).
 
     The side wall and the two end caps separate the layers from free space; the
@@ -209,6 +209,10 @@ def stacked_cylinder_body(radius: float = 1.0, height: float = 3.0, eps_layers=(
     the upper layer).  Every surface shares its boundary ring nodes, so the
     rings where a side wall meets an internal disc carry edges bordered by three
     triangles (junction edges).
+
+    merge_layers=True builds the same outer surface (identical vertices and
+    triangles) without the internal discs, as one homogeneous region of
+    permittivity eps_layers[0].
     """
     n_layers = len(eps_layers)
     n_phi = int(round(2 * np.pi * radius / target_edge))
@@ -253,6 +257,8 @@ def stacked_cylinder_body(radius: float = 1.0, height: float = 3.0, eps_layers=(
     nv = len(verts)
     # discs: bottom cap, internal interfaces, top cap
     for k in range(n_layers + 1):
+        if merge_layers and 0 < k < n_layers:
+            continue
         ring = ring_ids[k * n_z] if k < n_layers else ring_ids[-1]
         z = verts[ring[0], 2]
         dv, dt = _disc_mesh(radius, z, verts[ring], n_phi, target_edge)
@@ -275,6 +281,11 @@ def stacked_cylinder_body(radius: float = 1.0, height: float = 3.0, eps_layers=(
     v = np.concatenate(all_v)
     t = np.concatenate(all_t).astype(np.int32)
     rg = np.concatenate(all_r).astype(np.int32)
+    if merge_layers:
+        rg = np.minimum(rg, 1)
+        eps = np.array([1.0, eps_layers[0]], dtype=complex)
+        return Body(v, t, rg, eps, np.ones(2, dtype=complex),
+                    name=name or f"cylinder r={radius} h={height} eps={eps_layers[0]}")
     eps = np.array([1.0] + list(eps_layers), dtype=complex)
     return Body(v, t, rg, eps, np.ones(n_layers + 1, dtype=complex),
                 name=name or f"stacked cylinder r={radius} h={height} eps={list(eps_layers)}")
