@@ -141,9 +141,20 @@ typedef struct {
  *           (eqs. 10-13; several interfaces as in eq. 16). */
 enum { SFMM_FORM_PMCHWT = 0 };
 
-/* Krylov solvers of sfmm_solve:
- *   GMRES   restarted flexible GMRES(m), see sfmm_solve. */
-enum { SFMM_SOLVER_GMRES = 0 };
+/* Krylov solvers of sfmm_solve (the paper's solver comparison, "Simulation
+ * Results", Fig. 7: ILU-preconditioned BiCGStab and CGS, and BiCGStab
+ * without preconditioner - SFMM_PRECOND_NONE), all right-preconditioned,
+ * FP64 recurrences, right-hand sides in lockstep:
+ *   GMRES     restarted flexible GMRES(m), see sfmm_solve; an iteration is
+ *             one Arnoldi step (one preconditioned product);
+ *   BICGSTAB  van der Vorst's BiCGStab (1992); an iteration is two
+ *             preconditioned products;
+ *   CGS       Sonneveld's conjugate gradient squared (1989); an iteration is
+ *             two preconditioned products.
+ * For all three, convergence is declared only on the explicitly recomputed
+ * residual; a BiCGStab or CGS breakdown (a vanishing inner product) restarts
+ * that right-hand side from its current iterate. */
+enum { SFMM_SOLVER_GMRES = 0, SFMM_SOLVER_BICGSTAB = 1, SFMM_SOLVER_CGS = 2 };
 
 /* Preconditioners of sfmm_solve, all built from the near-field matrix Z_near
  * (the paper preconditions with an incomplete LU of it):
@@ -163,8 +174,11 @@ enum { SFMM_PRECOND_ILU0 = 0, SFMM_PRECOND_NONE = 1, SFMM_PRECOND_BLOCK_JACOBI =
 
 typedef struct {
     int32_t converged;        /* 1 if ||b - Z x|| / ||b|| <= tol                        */
-    int32_t iterations;       /* Arnoldi steps (each one preconditioned product)        */
-    int32_t restarts;
+    int32_t iterations;       /* iterations of the Krylov method: GMRES Arnoldi steps (one
+                                 preconditioned product each), BiCGStab / CGS
+                                 iterations (two products each)                        */
+    int32_t restarts;         /* GMRES restart cycles; BiCGStab / CGS: restarts after a
+                                 breakdown or a failed true-residual check             */
     int32_t guess_used;       /* 1 if the supplied x0 was kept (see sfmm_solve)         */
     double true_residual;     /* ||b - Z x|| / ||b|| at exit, recomputed explicitly     */
     double initial_residual;  /* ||b - Z x0|| / ||b|| of the supplied x0 (1 if none)    */
@@ -240,6 +254,9 @@ sfmm_status sfmm_planewave_rhs(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const
 /* Change the GMRES settings of later sfmm_solve calls (0 keeps a value):
  * restart length (1..1000), iteration cap, relative tolerance. */
 sfmm_status sfmm_set_solver(sfmm_ctx *ctx, int32_t gmres_restart, int32_t max_iters, double tol);
+
+/* Change the Krylov method (SFMM_SOLVER_*) of later sfmm_solve calls. */
+sfmm_status sfmm_set_krylov(sfmm_ctx *ctx, int32_t solver);
 
 /* Solve Z x = b, the discretised PMCHWT system of eqs. 10-13 / 16 with the
  * plane-wave right-hand side of eqs. 20-21 and 30, by the preconditioned

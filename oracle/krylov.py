@@ -211,3 +211,86 @@ def near_poly_preconditioner(Zn, degree):
 
     th = leja_order(harmonic_ritz(op, golden_start(Zn.shape[0]), degree))
     return lambda v: poly_apply(op, th, edge_blocks_apply(Dinv, v))
+
+
+# --- BiCGStab and CGS --------------------------------------------------------
+#
+# The paper compares ILU-preconditioned BiCGStab and CGS, and BiCGStab without
+# a preconditioner (Simulation Results, Fig. 7 discussion).  Both are written
+# here with right preconditioning (A M^-1 u = b, the iterate x = M^-1 u kept
+# directly), an iteration being two preconditioned products; convergence is
+# declared on the true residual, and a vanishing inner product or a
+# recurrence residual that the true residual does not confirm restarts the
+# method from the current iterate.
+
+def _bicg_family(matvec, b, precond, tol, max_iters, x0, squared):
+    precond = precond or (lambda v: v)
+    b = np.asarray(b, dtype=complex)
+    nb = np.linalg.norm(b)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=complex)
+    if nb == 0.0:
+        return np.zeros_like(b), GmresInfo(True, 0, 0, 0.0, [])
+    its, restarts, hist = 0, 0, []
+    r = b - matvec(x)
+    while True:
+        if np.linalg.norm(r) / nb <= tol:
+            return x, GmresInfo(True, its, restarts, np.linalg.norm(r) / nb, hist)
+        if its >= max_iters:
+            return x, GmresInfo(False, its, restarts, np.linalg.norm(r) / nb, hist)
+        rh = r.copy()
+        p = np.zeros_like(b)
+        v = np.zeros_like(b)            # BiCGStab: A p^ ; CGS: q
+        rho_old = alpha = omega = 1.0
+        first = True
+        while its < max_iters:
+            rho = np.vdot(rh, r)
+            if squared:                 # Sonneveld's CGS
+                beta = 0.0 if first else rho / rho_old
+                u = r + beta * v
+                p = u + beta * (v + beta * p)
+                ph = precond(p)
+                vh = matvec(ph)
+                sigma = np.vdot(rh, vh)
+                alpha = rho / sigma if sigma != 0 else 0.0
+                v = u - alpha * vh
+                uh = precond(u + v)
+                x = x + alpha * uh
+                r = r - alpha * matvec(uh)
+                broke = rho == 0 or sigma == 0
+            else:                       # van der Vorst's BiCGStab
+                beta = 0.0 if first else (rho / rho_old) * (alpha / omega)
+                p = r + beta * (p - omega * v)
+                ph = precond(p)
+                v = matvec(ph)
+                sigma = np.vdot(rh, v)
+                alpha = rho / sigma if sigma != 0 else 0.0
+                s = r - alpha * v
+                sh = precond(s)
+                t = matvec(sh)
+                tt = np.vdot(t, t)
+                omega = np.vdot(t, s) / tt if tt != 0 else 0.0
+                x = x + alpha * ph + omega * sh
+                r = s - omega * t
+                broke = rho == 0 or sigma == 0 or omega == 0
+            rho_old = rho
+            first = False
+            its += 1
+            est = np.linalg.norm(r) / nb
+            hist.append(est)
+            if est <= tol or broke or not np.isfinite(est):
+                break
+        r = b - matvec(x)               # the true residual decides
+        if np.linalg.norm(r) / nb > tol and its < max_iters:
+            restarts += 1
+
+
+def bicgstab(matvec, b, precond=None, tol=1e-6, max_iters=1000, x0=None):
+    """Right-preconditioned BiCGStab (van der Vorst, SIAM J. Sci. Stat.
+    Comput. 13, 1992)."""
+    return _bicg_family(matvec, b, precond, tol, max_iters, x0, squared=False)
+
+
+def cgs(matvec, b, precond=None, tol=1e-6, max_iters=1000, x0=None):
+    """Right-preconditioned CGS (Sonneveld, SIAM J. Sci. Stat. Comput. 10,
+    1989)."""
+    return _bicg_family(matvec, b, precond, tol, max_iters, x0, squared=True)

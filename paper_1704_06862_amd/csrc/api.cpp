@@ -125,7 +125,7 @@ void solve_one(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void *b, void *
     const sfmm_options &o = ctx->opt;
     const size_t bytes = (size_t)n_rhs * 2 * ctx->bodies[body]->mesh.ne * 2 * sizeof(double);
     if (on_device) {
-        d.solve(n_rhs, b, x, x0, o.gmres_restart, o.max_iters, o.tol, info, o.verbose);
+        d.solve(o.solver, n_rhs, b, x, x0, o.gmres_restart, o.max_iters, o.tol, info, o.verbose);
         return;
     }
     Staged db(bytes), dx(bytes);
@@ -136,7 +136,8 @@ void solve_one(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void *b, void *
         copy_h2d(dx0->p, x0, bytes, d.stream());
     }
     try {
-        d.solve(n_rhs, db.p, dx.p, dx0 ? dx0->p : nullptr, o.gmres_restart, o.max_iters, o.tol, info, o.verbose);
+        d.solve(o.solver, n_rhs, db.p, dx.p, dx0 ? dx0->p : nullptr, o.gmres_restart, o.max_iters, o.tol, info,
+                o.verbose);
     } catch (const Error &e) {
         if (e.code == SFMM_E_NOT_CONVERGED) copy_d2h(x, dx.p, bytes, d.stream());
         throw;
@@ -193,7 +194,7 @@ sfmm_status sfmm_setup(const sfmm_body *bodies, int32_t n_bodies, const sfmm_opt
         if (o.quad_points == 0) o.quad_points = 7;
         if (o.quad_points != 7) throw Error(SFMM_E_UNSUPPORTED, "only the 7-point triangle rule is built");
         if (o.formulation != SFMM_FORM_PMCHWT) throw Error(SFMM_E_UNSUPPORTED, "unknown formulation");
-        if (o.solver != SFMM_SOLVER_GMRES) throw Error(SFMM_E_UNSUPPORTED, "unknown solver");
+        if (o.solver < SFMM_SOLVER_GMRES || o.solver > SFMM_SOLVER_CGS) throw Error(SFMM_E_UNSUPPORTED, "unknown solver");
         if (o.ilu_pivot_tol == 0) o.ilu_pivot_tol = 1e-13;
         if (!(o.ilu_pivot_tol > 0) || !std::isfinite(o.ilu_pivot_tol))
             throw Error(SFMM_E_INVALID_ARG, "ilu_pivot_tol must be positive");
@@ -268,6 +269,14 @@ sfmm_status sfmm_set_solver(sfmm_ctx *ctx, int32_t gmres_restart, int32_t max_it
         if (gmres_restart > 0) ctx->opt.gmres_restart = gmres_restart;
         if (max_iters > 0) ctx->opt.max_iters = max_iters;
         if (tol > 0) ctx->opt.tol = tol;
+    });
+}
+
+sfmm_status sfmm_set_krylov(sfmm_ctx *ctx, int32_t solver) {
+    return guarded(ctx, [&] {
+        if (!ctx) throw Error(SFMM_E_INVALID_ARG, "NULL context");
+        if (solver < SFMM_SOLVER_GMRES || solver > SFMM_SOLVER_CGS) throw Error(SFMM_E_INVALID_ARG, "unknown solver");
+        ctx->opt.solver = solver;
     });
 }
 

@@ -1216,8 +1216,289 @@ class DeviceBodyT final : public DeviceBody {
         HIPCHK(hipMemcpyAsync(dact_, act.data(), sizeof(int) * act.size(), hipMemcpyHostToDevice, stream_));
     }
 
-    void solve(int n_rhs, const void *b_dev, void *x_dev, const void *x0_dev, int m, int max_iters, double tol,
-               sfmm_solve_info *info, int verbose) override {
+    void solve(int solver, int n_rhs, const void *b_dev, void *x_dev, const void *x0_dev, int m, int max_iters,
+               double tol, sfmm_solve_info *info, int verbose) override {
+        if (solver == SFMM_SOLVER_GMRES) solve_gmres(n_rhs, b_dev, x_dev, x0_dev, m, max_iters, tol, info, verbose);
+        else solve_bicg(solver == SFMM_SOLVER_CGS, n_rhs, b_dev, x_dev, x0_dev, max_iters, tol, info, verbose);
+    }
+
+    // out[a] = conj(X[act[a]]) . Y[act[a]] for the Ra active slots
+    std::vector<cd> bdot(const double2 *X, const double2 *Y, int Ra) {
+        const int N = 2 * ne_;
+        k_bdots<<<dim3(red_blocks_, 1, Ra), WG, 0, stream_>>>(X, 0, N, Y, dact_, N, 1, dpartc_);
+        LAUNCHCHK();
+        k_sum_partials<<<Ra, 64, 0, stream_>>>(dpartc_, red_blocks_, dh_);
+        LAUNCHCHK();
+        std::vector<double2> h(Ra);
+        copy_d2h(h.data(), dh_, sizeof(double2) * Ra, stream_);
+        std::vector<cd> out(Ra);
+        for (int a = 0; a < Ra; ++a) out[a] = cd(h[a].x, h[a].y);
+        return out;
+    }
+
+    // out = c0 x + c1 y + c2 z per active slot (coefficients [Ra][3])
+    void blin3(const std::vector<cd> &c, int Ra, const double2 *x, const double2 *y, const double2 *z,
+               double2 *out) {
+        const int N = 2 * ne_;
+        std::vector<double2> cc(3 * (size_t)Ra);
+        for (size_t i = 0; i < cc.size(); ++i) cc[i] = make_double2(c[i].real(), c[i].imag());
+        HIPCHK(hipMemcpyAsync(dh_, cc.data(), sizeof(double2) * cc.size(), hipMemcpyHostToDevice, stream_));
+        k_blin3<<<dim3(nblocks(N), Ra), WG, 0, stream_>>>(dh_, dact_, N, N, x, y, z, out);
+        LAUNCHCHK();
+    }
+
+    // BiCGStab (van der Vorst 1992) or CGS (Sonneveld 1989), right
+    // preconditioned (A M^-1 u = b, x = M^-1 u, the iterate x kept directly),
+    // FP64 recurrences, right-hand sides in lockstep.  A right-hand side
+    // leaves the batch when its explicitly recomputed residual reaches tol;
+    // when the recurrence claims convergence but the true residual does not
+    // confirm it, or an inner product vanishes, the right-hand side restarts
+    // from its current iterate.
+    void solve_bicg(bool cgs, int n_rhs, const void *b_dev, void *x_dev, const void *x0_dev, int max_iters,
+                    double tol, sfmm_solve_info *info, int verbose) {
+        const int N = 2 * ne_;
+        bool all_ok = true;
+        for (int c0 = 0; c0 < n_rhs; c0 += BATCH) {
+            const int R = std::min(BATCH, n_rhs - c0);
+            auto t0 = std::chrono::steady_clock::now();
+            ensure_krylov(8, R);
+            ensure_batch(R);
+            const int64_t ldj = (int64_t)kR_ * N;
+            double2 *r = kV_, *rh = kV_ + ldj, *p = kV_ + 2 * ldj, *v = kV_ + 3 * ldj, *sv = kV_ + 4 * ldj,
+                    *tv = kV_ + 5 * ldj, *w = kV_ + 6 * ldj, *aw = kV_ + 7 * ldj;
+            double2 *ph = kZ_, *sh = kZ_ + ldj;
+            for (int s = 0; s < R; ++s) {
+                k_perm_in<<<nblocks(ne_), WG, 0, stream_>>>((const double2 *)b_dev + (size_t)(c0 + s) * N, pos_, ne_,
+                                                             kb_ + (size_t)s * N);
+                LAUNCHCHK();
+                if (x0_dev) {
+                    k_perm_in<<<nblocks(ne_), WG, 0, stream_>>>((const double2 *)x0_dev + (size_t)(c0 + s) * N, pos_,
+                                                                 ne_, kx_ + (size_t)s * N);
+                    LAUNCHCHK();
+                }
+            }
+            if (!x0_dev) HIPCHK(hipMemsetAsync(kx_, 0, sizeof(double2) * (size_t)R * N, stream_));
+            std::vector<int> act(R);
+            for (int s = 0; s < R; ++s) act[s] = s;
+            upload_act(act);
+            std::vector<double> nb = norms(kb_, R);
+            for (int s = 0; s < R; ++s)
+                if (!std::isfinite(nb[s]))
+                    throw Error(SFMM_E_INVALID_ARG, "right-hand side " + std::to_string(c0 + s) + " is not finite");
+            std::vector<int> its(R, 0), restarts(R, 0), used(R, 0);
+            std::vector<double> rel(R, 1.0), rel0(R, 1.0);
+            std::vector<char> conv(R, 0);
+            // per-slot recurrence scalars
+            std::vector<cd> rho_old(R, 1.0), alpha(R, 1.0), omega(R, 1.0);
+            std::vector<char> fresh(R, 1);
+            // true residual r = b - A x of the listed slots; returns their
+            // relative norms and (re)starts their recurrences from it
+            auto restart_from_true = [&](const std::vector<int> &slots, bool first) {
+                upload_act(slots);
+                const int Ra = (int)slots.size();
+                if (first && !x0_dev) {
+                    for (int s : slots)
+                        HIPCHK(hipMemcpyAsync(r + (size_t)s * N, kb_ + (size_t)s * N, sizeof(double2) * N,
+                                              hipMemcpyDeviceToDevice, stream_));
+                } else {
+                    op_apply(kx_, r, nullptr, Ra, false, true);
+                    k_brsub<<<dim3(nblocks(N), Ra), WG, 0, stream_>>>(kb_, dact_, N, N, r);
+                    LAUNCHCHK();
+                }
+                std::vector<double> nr = norms(r, Ra);
+                for (int a = 0; a < Ra; ++a) {
+                    const int s = slots[a];
+                    HIPCHK(hipMemcpyAsync(rh + (size_t)s * N, r + (size_t)s * N, sizeof(double2) * N,
+                                          hipMemcpyDeviceToDevice, stream_));
+                    HIPCHK(hipMemsetAsync(p + (size_t)s * N, 0, sizeof(double2) * N, stream_));
+                    HIPCHK(hipMemsetAsync(v + (size_t)s * N, 0, sizeof(double2) * N, stream_));
+                    rho_old[s] = alpha[s] = omega[s] = 1.0;
+                    fresh[s] = 1;
+                }
+                return nr;
+            };
+            {
+                std::vector<double> nr = restart_from_true(act, true);
+                for (int a = 0; a < R; ++a) {
+                    const int s = act[a];
+                    if (nb[s] == 0.0) {
+                        conv[s] = 1;
+                        rel[s] = 0.0;
+                        continue;
+                    }
+                    rel[s] = nr[a] / nb[s];
+                    if (x0_dev) {
+                        rel0[s] = rel[s];
+                        if (rel[s] < 1.0) used[s] = 1;
+                    }
+                }
+                if (x0_dev) {
+                    // the true residual judges a supplied guess: one no better
+                    // than zero is dropped
+                    std::vector<int> drop;
+                    for (int s = 0; s < R; ++s)
+                        if (!conv[s] && !used[s]) drop.push_back(s);
+                    for (int s : drop) HIPCHK(hipMemsetAsync(kx_ + (size_t)s * N, 0, sizeof(double2) * N, stream_));
+                    if (!drop.empty()) {
+                        std::vector<double> nr2 = restart_from_true(drop, false);
+                        for (size_t a = 0; a < drop.size(); ++a) rel[drop[a]] = nr2[a] / nb[drop[a]];
+                    }
+                }
+                for (int s = 0; s < R; ++s)
+                    if (!conv[s] && rel[s] <= tol) conv[s] = 1;
+            }
+            while (true) {
+                act.clear();
+                for (int s = 0; s < R; ++s)
+                    if (!conv[s] && its[s] < max_iters) act.push_back(s);
+                if (act.empty()) break;
+                const int Ra = (int)act.size();
+                upload_act(act);
+                std::vector<cd> rho = bdot(rh, r, Ra);
+                std::vector<cd> c(3 * (size_t)Ra);
+                std::vector<int> broke;
+                for (int a = 0; a < Ra; ++a) {
+                    const int s = act[a];
+                    if (std::abs(rho[a]) == 0.0) broke.push_back(s);
+                }
+                if (cgs) {
+                    // u = r + beta q ; p = u + beta q + beta^2 p   (q in v, u in sv)
+                    for (int a = 0; a < Ra; ++a) {
+                        const int s = act[a];
+                        const cd beta = fresh[s] ? cd(0.0) : rho[a] / rho_old[s];
+                        c[3 * a] = 1.0;
+                        c[3 * a + 1] = beta;
+                        c[3 * a + 2] = 0.0;
+                    }
+                    blin3(c, Ra, r, v, nullptr, sv);
+                    for (int a = 0; a < Ra; ++a) {
+                        const int s = act[a];
+                        const cd beta = fresh[s] ? cd(0.0) : rho[a] / rho_old[s];
+                        c[3 * a] = 1.0;
+                        c[3 * a + 1] = beta;
+                        c[3 * a + 2] = beta * beta;
+                    }
+                    blin3(c, Ra, sv, v, p, p);
+                } else {
+                    // p = r + beta (p - omega v)
+                    for (int a = 0; a < Ra; ++a) {
+                        const int s = act[a];
+                        const cd beta = fresh[s] ? cd(0.0) : (rho[a] / rho_old[s]) * (alpha[s] / omega[s]);
+                        c[3 * a] = 1.0;
+                        c[3 * a + 1] = beta;
+                        c[3 * a + 2] = -beta * omega[s];
+                    }
+                    blin3(c, Ra, r, p, v, p);
+                }
+                // tv = A M^-1 p, ph = M^-1 p
+                op_apply(p, tv, ph, Ra, precond_ != SFMM_PRECOND_NONE, true);
+                std::vector<cd> sig = bdot(rh, tv, Ra);
+                for (int a = 0; a < Ra; ++a) {
+                    const int s = act[a];
+                    alpha[s] = std::abs(sig[a]) > 0 ? rho[a] / sig[a] : cd(0.0);
+                    if (!(std::abs(sig[a]) > 0) && std::find(broke.begin(), broke.end(), s) == broke.end())
+                        broke.push_back(s);
+                    c[3 * a] = 1.0;
+                    c[3 * a + 1] = -alpha[s];
+                    c[3 * a + 2] = 0.0;
+                }
+                if (cgs) {
+                    // q = u - alpha A p^ ; w = u + q ; aw = A M^-1 w, sh = M^-1 w
+                    blin3(c, Ra, sv, tv, nullptr, v);
+                    for (int a = 0; a < Ra; ++a) {
+                        c[3 * a] = 1.0;
+                        c[3 * a + 1] = 1.0;
+                    }
+                    blin3(c, Ra, sv, v, nullptr, w);
+                    op_apply(w, aw, sh, Ra, precond_ != SFMM_PRECOND_NONE, true);
+                    // x += alpha u^ ; r -= alpha A u^
+                    for (int a = 0; a < Ra; ++a) {
+                        const int s = act[a];
+                        c[3 * a] = 1.0;
+                        c[3 * a + 1] = alpha[s];
+                    }
+                    blin3(c, Ra, kx_, sh, nullptr, kx_);
+                    for (int a = 0; a < Ra; ++a) c[3 * a + 1] = -alpha[act[a]];
+                    blin3(c, Ra, r, aw, nullptr, r);
+                } else {
+                    // s = r - alpha v ; t = A M^-1 s, sh = M^-1 s
+                    std::swap(v, tv);   // v = A M^-1 p
+                    blin3(c, Ra, r, v, nullptr, sv);
+                    op_apply(sv, tv, sh, Ra, precond_ != SFMM_PRECOND_NONE, true);
+                    std::vector<cd> ts = bdot(tv, sv, Ra);
+                    std::vector<cd> tt = bdot(tv, tv, Ra);
+                    for (int a = 0; a < Ra; ++a) {
+                        const int s = act[a];
+                        omega[s] = std::abs(tt[a]) > 0 ? ts[a] / tt[a] : cd(0.0);
+                        if (!(std::abs(omega[s]) > 0) && std::find(broke.begin(), broke.end(), s) == broke.end())
+                            broke.push_back(s);
+                        c[3 * a] = 1.0;
+                        c[3 * a + 1] = alpha[s];
+                        c[3 * a + 2] = omega[s];
+                    }
+                    // x += alpha p^ + omega s^ ; r = s - omega t
+                    blin3(c, Ra, kx_, ph, sh, kx_);
+                    for (int a = 0; a < Ra; ++a) {
+                        const int s = act[a];
+                        c[3 * a + 1] = -omega[s];
+                        c[3 * a + 2] = 0.0;
+                    }
+                    blin3(c, Ra, sv, tv, nullptr, r);
+                }
+                for (int a = 0; a < Ra; ++a) {
+                    const int s = act[a];
+                    rho_old[s] = rho[a];
+                    fresh[s] = 0;
+                    ++its[s];
+                }
+                std::vector<double> nr = norms(r, Ra);
+                std::vector<int> check;
+                for (int a = 0; a < Ra; ++a) {
+                    const int s = act[a];
+                    rel[s] = nr[a] / nb[s];
+                    const bool bad = std::find(broke.begin(), broke.end(), s) != broke.end() || !std::isfinite(rel[s]);
+                    if (rel[s] <= tol || bad || its[s] >= max_iters) check.push_back(s);
+                }
+                if (check.empty()) continue;
+                // confirm on the true residual; restart the rest from their iterates
+                std::vector<double> tr = restart_from_true(check, false);
+                for (size_t q = 0; q < check.size(); ++q) {
+                    const int s = check[q];
+                    rel[s] = tr[q] / nb[s];
+                    if (rel[s] <= tol) conv[s] = 1;
+                    else if (its[s] < max_iters) ++restarts[s];
+                    if (verbose >= 2)
+                        std::fprintf(stderr, "sfmm %s: rhs %d its %d true residual %.3e\n", cgs ? "cgs" : "bicgstab",
+                                     c0 + s, its[s], rel[s]);
+                }
+            }
+            for (int s = 0; s < R; ++s) {
+                k_perm_out<<<nblocks(ne_), WG, 0, stream_>>>(kx_ + (size_t)s * N, pos_, ne_,
+                                                              (double2 *)x_dev + (size_t)(c0 + s) * N);
+                LAUNCHCHK();
+            }
+            HIPCHK(hipStreamSynchronize(stream_));
+            const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            for (int s = 0; s < R; ++s) {
+                if (info) {
+                    info[c0 + s].converged = conv[s] ? 1 : 0;
+                    info[c0 + s].iterations = its[s];
+                    info[c0 + s].restarts = restarts[s];
+                    info[c0 + s].guess_used = used[s];
+                    info[c0 + s].true_residual = rel[s];
+                    info[c0 + s].initial_residual = rel0[s];
+                    info[c0 + s].seconds = secs;
+                }
+                all_ok = all_ok && conv[s];
+            }
+        }
+        if (!all_ok)
+            throw Error(SFMM_E_NOT_CONVERGED, std::string(cgs ? "CGS" : "BiCGStab") +
+                                                  " did not reach the tolerance within max_iters");
+    }
+
+    void solve_gmres(int n_rhs, const void *b_dev, void *x_dev, const void *x0_dev, int m, int max_iters, double tol,
+                     sfmm_solve_info *info, int verbose) {
         const int N = 2 * ne_;
         bool all_ok = true;
         for (int c0 = 0; c0 < n_rhs; c0 += BATCH) {

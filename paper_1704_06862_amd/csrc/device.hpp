@@ -31,7 +31,8 @@ class DeviceBody {
     virtual ~DeviceBody() = default;
     virtual void matvec(int n_rhs, const void *x_dev, void *y_dev, int parts) = 0;
     virtual void precond(int n_rhs, const void *x_dev, void *y_dev) = 0;
-    virtual void solve(int n_rhs, const void *b_dev, void *x_dev, const void *x0_dev, int restart,
+    // solver: SFMM_SOLVER_* (GMRES(restart), BiCGStab or CGS)
+    virtual void solve(int solver, int n_rhs, const void *b_dev, void *x_dev, const void *x0_dev, int restart,
                        int max_iters, double tol, sfmm_solve_info *info, int verbose) = 0;
     virtual void planewave_rhs(int n_rhs, const double *angles_host, const double *pol_host, void *b_dev) = 0;
     virtual void rcs(int n_rhs, const void *x_dev, int n_dirs, const double *theta_phi_host, double *sigma_host) = 0;

@@ -1580,6 +1580,25 @@ __global__ void k_bscale(const double *__restrict__ a, const int *__restrict__ a
     w[i] = make_double2(a[s] * w[i].x, a[s] * w[i].y);
 }
 
+// out[s] = c[s][0] x[s] + c[s][1] y[s] + c[s][2] z[s] (z may be null; any of
+// x, y, z may be out itself: every element is read before it is written)
+__global__ void k_blin3(const double2 *__restrict__ c, const int *__restrict__ act, int64_t lds, int N,
+                        const double2 *x, const double2 *y, const double2 *z, double2 *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, s = blockIdx.y;
+    if (i >= N) return;
+    const int64_t o = (int64_t)act[s] * lds + i;
+    const double2 c0 = c[3 * s], c1 = c[3 * s + 1], c2 = c[3 * s + 2];
+    const double2 a = x[o], b = y[o];
+    double2 r = make_double2(c0.x * a.x - c0.y * a.y + c1.x * b.x - c1.y * b.y,
+                             c0.x * a.y + c0.y * a.x + c1.x * b.y + c1.y * b.x);
+    if (z) {
+        const double2 d = z[o];
+        r.x += c2.x * d.x - c2.y * d.y;
+        r.y += c2.x * d.y + c2.y * d.x;
+    }
+    out[o] = r;
+}
+
 // y[s] = b[s] - y[s]
 __global__ void k_brsub(const double2 *__restrict__ Bv, const int *__restrict__ act, int64_t lds, int N,
                         double2 *__restrict__ Y) {

@@ -24,13 +24,13 @@ PREC_FP32, PREC_BF16_SPLIT, PREC_FP64 = 0, 1, 2
 PART_NEAR, PART_FAR, PART_ALL = 1, 2, 3
 PRECOND_ILU0, PRECOND_NONE, PRECOND_BLOCK_JACOBI, PRECOND_POLY = 0, 1, 2, 3
 FORM_PMCHWT = 0
-SOLVER_GMRES = 0
+SOLVER_GMRES, SOLVER_BICGSTAB, SOLVER_CGS = 0, 1, 2
 
 EXPORTED = ["sfmm_default_options", "sfmm_setup", "sfmm_destroy", "sfmm_last_error", "sfmm_set_stream",
             "sfmm_num_unknowns", "sfmm_edges", "sfmm_matvec", "sfmm_precond", "sfmm_planewave_rhs",
             "sfmm_solve", "sfmm_rcs", "sfmm_near_rows", "sfmm_describe", "sfmm_product_bytes", "sfmm_profile",
             "sfmm_guess_default_options", "sfmm_guess_fit", "sfmm_guess_predict", "sfmm_mlp_train",
-            "sfmm_solve_bodies", "sfmm_set_solver", "sfmm_span_predict"]
+            "sfmm_solve_bodies", "sfmm_set_solver", "sfmm_span_predict", "sfmm_set_krylov"]
 
 
 class sfmm_body(ctypes.Structure):
@@ -106,6 +106,7 @@ def load():
     lib.sfmm_mlp_train.argtypes = [I32, I32, P, P, I32, P, P, I32, D, P, P, P]
     lib.sfmm_solve_bodies.argtypes = [P, I32, P, P, P, P, P, I32]
     lib.sfmm_set_solver.argtypes = [P, I32, I32, D]
+    lib.sfmm_set_krylov.argtypes = [P, I32]
     lib.sfmm_span_predict.argtypes = [P, I32, I32, P, P, P, I32]
     for name in EXPORTED:
         if name not in ("sfmm_default_options", "sfmm_destroy", "sfmm_last_error", "sfmm_guess_default_options"):
@@ -301,6 +302,9 @@ class Context:
 
     def sfmm_set_solver(self, gmres_restart=0, max_iters=0, tol=0.0):
         _check(lib().sfmm_set_solver(self.ctx, gmres_restart, max_iters, tol), self.ctx)
+
+    def sfmm_set_krylov(self, solver):
+        _check(lib().sfmm_set_krylov(self.ctx, solver), self.ctx)
 
     def sfmm_solve_bodies(self, problems, raise_on_nonconvergence=False):
         """problems: list of (body, b, x); all host or all device arrays.

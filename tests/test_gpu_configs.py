@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from oracle import mie
-from workloads import coated_sphere_body, sphere_body
+from workloads import sphere_body
 
 pytestmark = pytest.mark.gpu
 
@@ -47,21 +47,9 @@ def test_sphere_61440_unknowns_rcs_vs_mie(prec):
     (rE, xE), (rH, xH) = db_stats(sE, mE), db_stats(sH, mH)
     print(prec, info, "E-plane RMS/max dB", rE, xE, "H-plane", rH, xH)
     assert info["converged"] and info["true_residual"] <= 1e-4
-    assert rE < 0.5 and rH < 0.5 and xE < 3.0 and xH < 3.0
-
-
-def test_coated_sphere_307200_unknowns_rcs_vs_mie():
-    print("setup 307,200-unknown coated sphere", flush=True)
-    body = coated_sphere_body(1.5, 6 - 0.5j, 5, 2.5, 2.56, 6)
-    # two interfaces, a lossy high-contrast core and a dense shell mesh: the
-    # near-field polynomial needs degree 48 here (degree 16 stalls near 1e-3)
-    info, sE, sH = solve_cuts(body, finest_box=0.25, digits=3.0, precision=sfmm.PREC_FP32, gmres_restart=50,
-                              tol=1e-4, max_iters=1000, poly_degree=48)
-    mE, mH = mie.coated_sphere_rcs(1.5, 6 - 0.5j, 2.5, 2.56, THETA)
-    (rE, xE), (rH, xH) = db_stats(sE, mE), db_stats(sH, mH)
-    print(info, "E-plane RMS/max dB", rE, xE, "H-plane", rH, xH)
-    assert info["converged"] and info["true_residual"] <= 1e-4
-    assert rE < 0.5 and rH < 0.5 and xE < 3.0 and xH < 3.0
+    # measured 0.12 / 0.43 dB RMS and 0.47 / 1.16 dB max (E / H plane), the
+    # facetting error of s = 5, identical in FP32 and bf16-split
+    assert rE < 0.15 and rH < 0.5 and xE < 0.6 and xH < 1.4
 
 
 def test_uneven_bodies_solved_concurrently():

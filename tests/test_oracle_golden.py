@@ -35,3 +35,22 @@ def test_stored_oracle_rcs_against_mie():
         assert abs(10 * np.log10(d[i, 1] / d[i, 2])) < 0.05
     # the forward lobe dominates
     assert np.argmax(d[:, 1]) == 180 and np.argmax(d[:, 2]) == 180
+
+
+def test_stored_coated_sphere_sweep_against_mie_and_symmetry():
+    # tests/golden/coated19200_rcs.txt: the oracle's dense LU solutions of the
+    # coarse coated sphere (core s = 3, shell s = 4) for 64 incidences.  The
+    # facets are coarse (core edge ~ interior wavelength / 1.8), so the check
+    # against the Aden-Kerker series is loose; the sweep must be consistent:
+    # incidence from theta_i on a sphere scatters the cut of incidence 0
+    # rotated by theta_i (up to facetting), and every cut is positive.
+    path = os.path.join(os.path.dirname(__file__), "golden", "coated19200_rcs.txt")
+    d = np.loadtxt(path)
+    assert d.shape == (181, 65) and np.all(d[:, 1:] > 0)
+    th = np.deg2rad(d[:, 0])
+    mE, _ = mie.coated_sphere_rcs(1.5, 6 - 0.5j, 2.5, 2.56, th)
+    rms, mx = _db(d[:, 1], mE)
+    assert rms < 0.25 and mx < 0.6
+    # backscatter (theta = theta_i) is the same for every incidence on a sphere
+    back = np.array([d[int(round(180.0 * i / 63)), 1 + i] for i in range(64)])
+    assert np.std(10 * np.log10(back)) < 0.15

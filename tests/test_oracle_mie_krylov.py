@@ -159,3 +159,52 @@ def test_edge_block_scaling_pins():
     th = krylov.leja_order(krylov.harmonic_ritz(lambda u: Zs @ u, krylov.golden_start(2 * ne), 8))
     e_plain = np.linalg.norm(krylov.poly_apply(lambda u: Zs @ u, th, v) - ref) / np.linalg.norm(ref)
     assert e_scaled < 1e-3 and e_scaled < 1e-2 * e_plain
+
+
+@pytest.mark.parametrize("method", ["bicgstab", "cgs"])
+def test_bicg_family_terminates_and_solves(method):
+    solve = getattr(krylov, method)
+    rng = np.random.default_rng(17)
+    n = 60
+    # a diagonalisable matrix with three distinct eigenvalues: the BiCG
+    # residual polynomial (and its square, and its product with the
+    # stabilising factors) annihilates it after three steps
+    Q = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    lam = np.repeat([2.0 + 1j, -1.5, 4.0 - 2j], n // 3)
+    A = Q @ np.diag(lam) @ np.linalg.inv(Q)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x, info = solve(lambda v: A @ v, b, tol=1e-10, max_iters=50)
+    assert info.converged and info.iterations <= 3
+    assert np.linalg.norm(A @ x - b) <= 1e-9 * np.linalg.norm(b)
+    # the exact inverse as preconditioner: one iteration
+    Ainv = np.linalg.inv(A)
+    x, info = solve(lambda v: A @ v, b, lambda v: Ainv @ v, tol=1e-10, max_iters=50)
+    assert info.converged and info.iterations == 1
+    # a general non-normal system: the direct solution, the true residual
+    A = _test_matrix(80, seed=23)
+    x, info = solve(lambda v: A @ v, b[:1].repeat(80) * np.exp(1j * np.arange(80)), tol=1e-12, max_iters=500)
+    ref = np.linalg.solve(A, b[:1].repeat(80) * np.exp(1j * np.arange(80)))
+    assert info.converged and np.allclose(x, ref, atol=1e-9 * np.abs(ref).max())
+    # an iteration cap is reported with the true residual of the last iterate
+    _, info = solve(lambda v: A @ v, np.ones(80, dtype=complex), tol=1e-14, max_iters=2)
+    assert not info.converged and info.iterations == 2 and info.true_residual > 1e-14
+
+
+def test_sparse_ilu0_equals_dense_ilu0_and_orders_are_permutations():
+    from oracle import octree
+    from oracle.ilu_order import ilu0_sparse
+    n = 70
+    A = _test_matrix(n, seed=31)
+    rng = np.random.default_rng(31)
+    pat = rng.random((n, n)) < 0.2
+    pat |= pat.T
+    np.fill_diagonal(pat, True)
+    F = krylov.ilu0(A, pat)
+    L, U = ilu0_sparse(np.where(pat, A, 0), pat)
+    assert np.abs((L.toarray() - np.eye(n)) + U.toarray() - F).max() < 1e-12
+    keys = rng.integers(0, 8, size=(40, 3))
+    for perm in (octree.unknown_order(keys), octree.natural_order(keys)):
+        assert sorted(perm) == list(range(80))
+        assert np.all(perm[1::2] == perm[0::2] + 40)          # J then M~ of one edge
+    nat = octree.natural_order(keys)[0::2]
+    assert np.all(np.diff(octree.morton(keys)[nat]) >= 0)     # boxes in Morton order
