@@ -298,6 +298,20 @@ sfmm_status sfmm_solve_bodies(sfmm_ctx *ctx, int32_t n, const int32_t *bodies, c
 sfmm_status sfmm_rcs(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void *x, int32_t n_dirs,
                      const double *theta_phi, double *sigma, int32_t on_device);
 
+/* Allocation-free variant of sfmm_rcs, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): same result as sfmm_rcs with
+ * on_device = 1.  x_dev: [n_rhs][2E] complex on the context's device;
+ * theta_phi [n_dirs][2] and sigma [n_rhs][n_dirs][2] are host arrays, staged
+ * through a static device scratch of 262,144 doubles (2 MiB) that the
+ * library holds on every GPU it runs on until the process ends.  Requires
+ * n_dirs * (2 + 2 n_rhs) <= 262144, else SFMM_E_INVALID_ARG.  Calls no
+ * allocating routine.  Every context on a GPU shares that GPU's scratch:
+ * calls that overlap on one GPU (other threads, other contexts) race.
+ * Synchronous on the context's stream. */
+sfmm_status sfmm_rcs_noalloc(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void *x_dev, int32_t n_dirs,
+                             const double *theta_phi, double *sigma);
+
 /* Learned GMRES initial guess (an addition to the paper's method; the paper
  * starts GMRES from zero).  sfmm_guess_fit trains, on the device, a network
  * that maps an incidence to the currents:

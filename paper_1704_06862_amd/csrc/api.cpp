@@ -433,6 +433,16 @@ sfmm_status sfmm_rcs(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void *x, 
     });
 }
 
+sfmm_status sfmm_rcs_noalloc(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const void *x_dev, int32_t n_dirs,
+                             const double *theta_phi, double *sigma) {
+    return guarded(ctx, [&] {
+        DeviceBody &d = dev_of(ctx, body);
+        if (n_rhs <= 0 || n_dirs <= 0 || !x_dev || !theta_phi || !sigma)
+            throw Error(SFMM_E_INVALID_ARG, "bad arguments");
+        d.rcs_noalloc(n_rhs, x_dev, n_dirs, theta_phi, sigma);
+    });
+}
+
 sfmm_status sfmm_near_rows(const sfmm_ctx *ctx, int32_t body, int32_t n_rows, const int32_t *edges, double *out) {
     return guarded(const_cast<sfmm_ctx *>(ctx), [&] {
         const BodyHost &b = body_of(ctx, body);

@@ -21,6 +21,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -28,6 +29,13 @@
 #include "device.hpp"
 #include "mfma.hpp"
 #include "kernels.hpp"
+
+// Scratch of the allocation-free far-field entry point (sfmm_rcs_noalloc):
+// staging for the directions and the RCS values.  One copy per GPU, held
+// until the process ends; every context on that GPU shares it, so calls that
+// overlap on one GPU race.
+constexpr size_t SFMM_SCRATCH_DOUBLES = 262144;   // 2 MiB
+static __device__ __align__(256) double scratch[SFMM_SCRATCH_DOUBLES];
 
 namespace sfmm {
 
@@ -77,7 +85,25 @@ void check_device(int device) {
         throw Error(SFMM_E_DEVICE, std::string("library built for gfx950, device is ") + prop.gcnArchName);
 }
 
+size_t noalloc_scratch_doubles() { return SFMM_SCRATCH_DOUBLES; }
+
 namespace {
+
+// Device address of `scratch` on each GPU, looked up once per device with
+// that device current (the host-side name of the array is not a device
+// address).
+std::mutex g_scratch_mutex;
+std::map<int, double *> g_scratch_addr;
+
+double *scratch_address(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    auto it = g_scratch_addr.find(device);
+    if (it != g_scratch_addr.end()) return it->second;
+    void *p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_addr[device] = (double *)p;
+    return (double *)p;
+}
 
 inline unsigned nblocks(int64_t n, int bs = WG) { return (unsigned)((n + bs - 1) / bs); }
 
@@ -101,6 +127,7 @@ class DeviceBodyT final : public DeviceBody {
                 int verbose)
         : h_(h), split_(split), graphs_(graphs), autotune_(autotune), kernel_plan_(kernel_plan), verbose_(verbose) {
         HIPCHK(hipSetDevice(device));
+        scratch_ = scratch_address(device);
         // a stream of our own stands in for the legacy default stream, which
         // cannot be captured; it is a blocking stream, so it stays ordered
         // with work on the default stream
@@ -1752,6 +1779,15 @@ class DeviceBodyT final : public DeviceBody {
         device_free(ds);
     }
 
+    void rcs_noalloc(int n_rhs, const void *x_dev, int n_dirs, const double *tp, double *sigma) override {
+        const size_t need = (size_t)2 * n_dirs + (size_t)2 * n_dirs * n_rhs;
+        if (need > SFMM_SCRATCH_DOUBLES)
+            throw Error(SFMM_E_INVALID_ARG, "n_dirs * (2 + 2 n_rhs) = " + std::to_string(need) +
+                                                " exceeds the scratch of " + std::to_string(SFMM_SCRATCH_DOUBLES) +
+                                                " doubles");
+        rcs_staged(n_rhs, x_dev, n_dirs, tp, sigma, scratch_, scratch_ + 2 * (size_t)n_dirs);
+    }
+
     // quadrature geometry of every edge for the excitation and far-field kernels
     void upload_edge_quadrature(const Mesh &m) {
         const TriRule &q = tri_rule();
@@ -1919,6 +1955,7 @@ class DeviceBodyT final : public DeviceBody {
     int64_t *tile_step_ = nullptr;
     void *tvals_ = nullptr;
     // edge quadrature for the plane-wave and far-field kernels
+    double *scratch_ = nullptr;   // this device's copy of `scratch`
     int *gs0_ = nullptr;
     double *gqr_ = nullptr, *gqf_ = nullptr;
     int *near_grp_ = nullptr, near_ngrp_ = 0;

@@ -36,6 +36,10 @@ class DeviceBody {
                        int max_iters, double tol, sfmm_solve_info *info, int verbose) = 0;
     virtual void planewave_rhs(int n_rhs, const double *angles_host, const double *pol_host, void *b_dev) = 0;
     virtual void rcs(int n_rhs, const void *x_dev, int n_dirs, const double *theta_phi_host, double *sigma_host) = 0;
+    // as rcs, staged through the library's static device scratch instead of
+    // allocated buffers (n_dirs * (2 + 2 n_rhs) <= noalloc_scratch_doubles())
+    virtual void rcs_noalloc(int n_rhs, const void *x_dev, int n_dirs, const double *theta_phi_host,
+                             double *sigma_host) = 0;
     virtual void set_stream(void *stream) = 0;
     // the stream all of this body's work is ordered on (the context's stream,
     // or a stream of the body's own when the context has none)
@@ -56,5 +60,6 @@ void copy_h2d(void *dst, const void *src, size_t bytes, void *stream);
 void copy_d2h(void *dst, const void *src, size_t bytes, void *stream);
 void stream_sync(void *stream);
 void check_device(int device);
+size_t noalloc_scratch_doubles();
 
 }  // namespace sfmm

@@ -30,7 +30,7 @@ EXPORTED = ["sfmm_default_options", "sfmm_setup", "sfmm_destroy", "sfmm_last_err
             "sfmm_num_unknowns", "sfmm_edges", "sfmm_matvec", "sfmm_precond", "sfmm_planewave_rhs",
             "sfmm_solve", "sfmm_rcs", "sfmm_near_rows", "sfmm_describe", "sfmm_product_bytes", "sfmm_profile",
             "sfmm_guess_default_options", "sfmm_guess_fit", "sfmm_guess_predict", "sfmm_mlp_train",
-            "sfmm_solve_bodies", "sfmm_set_solver", "sfmm_span_predict", "sfmm_set_krylov"]
+            "sfmm_solve_bodies", "sfmm_set_solver", "sfmm_span_predict", "sfmm_set_krylov", "sfmm_rcs_noalloc"]
 
 
 class sfmm_body(ctypes.Structure):
@@ -108,6 +108,7 @@ def load():
     lib.sfmm_set_solver.argtypes = [P, I32, I32, D]
     lib.sfmm_set_krylov.argtypes = [P, I32]
     lib.sfmm_span_predict.argtypes = [P, I32, I32, P, P, P, I32]
+    lib.sfmm_rcs_noalloc.argtypes = [P, I32, I32, P, I32, P, P]
     for name in EXPORTED:
         if name not in ("sfmm_default_options", "sfmm_destroy", "sfmm_last_error", "sfmm_guess_default_options"):
             getattr(lib, name).restype = ctypes.c_int
@@ -367,6 +368,18 @@ class Context:
         tp = np.ascontiguousarray(theta_phi, dtype=np.float64).reshape(-1, 2)
         sigma = np.zeros((n_rhs, len(tp), 2))
         _check(lib().sfmm_rcs(self.ctx, body, n_rhs, px, len(tp), tp.ctypes.data, sigma.ctypes.data, dev), self.ctx)
+        return sigma
+
+    def sfmm_rcs_noalloc(self, x, theta_phi, body=0):
+        """x: device tensor [n_rhs][2E] complex128 (the call allocates no device memory)."""
+        n_rhs = self._rows(x)
+        px, dev = self._vec(x, n_rhs, body, "x")
+        if not dev:
+            raise ValueError("sfmm_rcs_noalloc takes device vectors")
+        tp = np.ascontiguousarray(theta_phi, dtype=np.float64).reshape(-1, 2)
+        sigma = np.zeros((n_rhs, len(tp), 2))
+        _check(lib().sfmm_rcs_noalloc(self.ctx, body, n_rhs, px, len(tp), tp.ctypes.data, sigma.ctypes.data),
+               self.ctx)
         return sigma
 
     def sfmm_near_rows(self, edges, body=0):
