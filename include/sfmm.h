@@ -123,7 +123,9 @@ typedef struct {
                                  split single-RHS interpolation stages; bit 7: single-RHS
                                  coarsest upward phi stage in one launch with the finer
                                  levels' translations; bit 8 (with bit 7): the near-field
-                                 product in the level-2 translation launch.  A variant whose
+                                 product in the level-2 translation launch; bit 9: single-RHS
+                                 downward level transitions with the phi and theta stages
+                                 fused in one kernel (the default at one RHS).  A variant whose
                                  conditions do not hold (batch size, LDS) falls back to
                                  the vector kernel.  For tests and measurement.         */
     int32_t formulation;      /* SFMM_FORM_*: integral equation; 0 = PMCHWT               */

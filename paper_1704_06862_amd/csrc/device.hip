@@ -340,6 +340,7 @@ class DeviceBodyT final : public DeviceBody {
         bool interp_split = false;   // one RHS: theta and phi stages as separate whole-level launches
         bool overlap_trans = false;  // one RHS: coarsest phi stage and finer translations in one launch
         bool near_join = false;      // ... and the near product in the level-2 translation launch
+        bool interp_fused = false;   // one RHS: downward phi and theta stages fused per level
     };
     static Plan default_plan(int R) {
         Plan p;
@@ -348,6 +349,7 @@ class DeviceBodyT final : public DeviceBody {
         p.interp_split = R == 1;
         p.overlap_trans = R == 1;
         p.near_join = R == 1;
+        p.interp_fused = R == 1;
         return p;
     }
     void use_plan(int R) {
@@ -359,6 +361,7 @@ class DeviceBodyT final : public DeviceBody {
             plan_.interp_split = (kernel_plan_ >> 5) & 1;
             plan_.overlap_trans = (kernel_plan_ >> 7) & 1;
             plan_.near_join = (kernel_plan_ >> 8) & 1;
+            plan_.interp_fused = (kernel_plan_ >> 9) & 1;
             return;
         }
         if (!autotune_) {
@@ -393,10 +396,11 @@ class DeviceBodyT final : public DeviceBody {
         Plan best = default_plan(R);
         plan_ = best;
         float tbest = time_product(R);
-        bool Plan::*fields[7] = {&Plan::near_mma,     &Plan::agg_mma,       &Plan::interp_mma, &Plan::trans_grp,
-                                 &Plan::interp_split, &Plan::overlap_trans, &Plan::near_join};
+        bool Plan::*fields[8] = {&Plan::near_mma,     &Plan::agg_mma,       &Plan::interp_mma, &Plan::trans_grp,
+                                 &Plan::interp_split, &Plan::overlap_trans, &Plan::near_join, &Plan::interp_fused};
         for (bool Plan::*f : fields) {
-            if (f == &Plan::interp_split || f == &Plan::overlap_trans || f == &Plan::near_join) {
+            if (f == &Plan::interp_split || f == &Plan::overlap_trans || f == &Plan::near_join ||
+                f == &Plan::interp_fused) {
                 if (R != 1) continue;
             } else if (f != &Plan::trans_grp) {
                 if (!std::is_same<T, float>::value || R < MMA_MIN_R) continue;
@@ -414,7 +418,10 @@ class DeviceBodyT final : public DeviceBody {
             std::fprintf(stderr, "sfmm autotune R=%d: near %s, aggregate/receive %s, interpolation %s, translation %s "
                                  "(%.3f ms)\n",
                          R, best.near_mma ? "mfma" : "vector", best.agg_mma ? "mfma" : "vector",
-                         best.interp_mma ? "mfma" : best.interp_split ? "vector, split stages" : "vector",
+                         best.interp_mma      ? "mfma"
+                         : best.interp_fused ? "vector, fused downward stages"
+                         : best.interp_split ? "vector, split stages"
+                                             : "vector",
                          best.trans_grp ? "grouped" : "flat", tbest);
         return best;
     }
@@ -752,6 +759,35 @@ class DeviceBodyT final : public DeviceBody {
                th <= LDS_LIMIT && ph <= LDS_LIMIT;
     }
 
+    // single-RHS fused downward transitions l - 1 -> l: one azimuth pair per
+    // workgroup must fit LDS
+    bool fused_ok(int l, int R) const {
+        if (!plan_.interp_fused || R != 1 || (int)regs_.size() > SPLIT_MAXJOB) return false;
+        for (const Reg &G : regs_)
+            if (G.nph[l] % 2 || fused_dn_lds<T>(G.nth[l], G.nth[l - 1], G.nph[l - 1], 1) > LDS_LIMIT) return false;
+        return true;
+    }
+    // azimuth-pair chunks per (child, component): about 2,048 workgroups per launch
+    JobList<FusedDnJob<T>> fused_dn_jobs(int l, size_t &shm) {
+        JobList<FusedDnJob<T>> jl{};
+        int64_t groups = 0;
+        for (Reg &G : regs_) groups += (int64_t)G.nbox[l] * 2;
+        const int want = (int)std::max<int64_t>(1, (2048 + groups - 1) / groups);
+        shm = 0;
+        for (Reg &G : regs_) {
+            const int nth_c = G.nth[l], nph_c = G.nph[l], nth_p = G.nth[l - 1], nph_p = G.nph[l - 1];
+            const int h = nph_c / 2;
+            int cols = (h + std::min(want, h) - 1) / std::min(want, h);
+            while (cols > 1 && fused_dn_lds<T>(nth_c, nth_p, nph_p, cols) > LDS_LIMIT) --cols;
+            const int nchunk = (h + cols - 1) / cols;
+            shm = std::max(shm, fused_dn_lds<T>(nth_c, nth_p, nph_p, cols));
+            add_job(jl, FusedDnJob<T>{G.nbox[l], nth_c, nph_c, nth_p, nph_p, cols, G.ipA[l], G.ipB[l], G.ipD[l],
+                                      G.parent[l], G.slot[l], G.sdn[l], G.G[l - 1], G.G[l]},
+                    (int64_t)G.nbox[l] * 2 * nchunk, 1);
+        }
+        return jl;
+    }
+
     bool interp_mma_ok(const Reg &G, int l, int R) const {
         return plan_.interp_mma && R >= MMA_MIN_R && G.Dup[l] && 2 * G.nth[l - 1] <= 64 && 2 * G.nth[l] <= 64 && G.nph[l - 1] <= 64 &&
                G.nph[l] <= 64;
@@ -859,7 +895,10 @@ class DeviceBodyT final : public DeviceBody {
             k_near_up_phi1_translate1<T, false><<<grid, WG, sh, stream_>>>(jl, tg, none);
             LAUNCHCHK();
         }
-        // level 2: a few hundred workgroups; the near product's follow them
+        translate_level2_and_near(R, x, y);
+    }
+    // level 2: a few hundred workgroups; the near product's follow them
+    void translate_level2_and_near(int R, const cx<T> *x, cx<T> *y) {
         const TransGroups<T> t2 = trans_groups(2, 2);
         if (x) {
             NearRows<T> nr{};
@@ -1006,6 +1045,15 @@ class DeviceBodyT final : public DeviceBody {
         launch_jobs(ph, n2, sh2, k_up_phi1<T, 64>, k_up_phi1<T, WG>);
     }
     void downward_level(int l, int R) {
+        if (fused_ok(l, R)) {
+            size_t sh = 0;
+            const JobList<FusedDnJob<T>> jl = fused_dn_jobs(l, sh);
+            if (jl.blk0[jl.n]) {
+                k_dn_fused1<T><<<(unsigned)jl.blk0[jl.n], WG, sh, stream_>>>(jl);
+                LAUNCHCHK();
+            }
+            return;
+        }
         if (!split_all(l, R)) {
             for (Reg &G : regs_) downward(G, l, R);
             return;

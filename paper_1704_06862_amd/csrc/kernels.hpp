@@ -901,6 +901,93 @@ __global__ void __launch_bounds__(BS) k_dn_theta1(const JobList<ThetaJob<T>> jl)
 }
 
 // ---------------------------------------------------------------------------
+// One right-hand side, a whole downward level transition per kernel: the phi
+// and theta stages fused, their intermediate kept in LDS (no round trip
+// through memory).  Both stages are independent across the azimuth pairs
+// (j, j + h) of the child, so a (child, component) is split into chunks of
+// azimuth pairs with no work repeated between chunks; the host picks the
+// chunk count so that a coarse level still yields enough workgroups to fill
+// the chip.  (Fusing the upward transition the same way measured slower than
+// its two separate stages: its phi stage sums over the eight children.)
+template <typename T>
+struct FusedDnJob {   // Gc[c][comp][i][j] += (A, B)^T D^T (shift_dn Gp)
+    int nchild, nth_c, nph_c, nth_p, nph_p, cols;    // cols: azimuth pairs per workgroup
+    const T *A, *B, *D;
+    const int *parent, *child_slot;
+    const cx<T> *shift, *Gp;
+    cx<T> *Gc;
+};
+
+// LDS bytes of one fused workgroup (the host checks them against the limit)
+template <typename T>
+__host__ __device__ inline size_t fused_dn_lds(int nth_c, int nth_p, int nph_p, int cols) {
+    const size_t nt = ((size_t)nph_p * 2 * cols + 2 * (size_t)nth_p * nth_c + 1) & ~(size_t)1;
+    return nt * sizeof(T) + ((size_t)nth_p * nph_p + (size_t)nth_p * 2 * cols) * 2 * sizeof(T);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(WG) k_dn_fused1(const JobList<FusedDnJob<T>> jl) {
+    extern __shared__ unsigned char lds_raw[];
+    int local;
+    const FusedDnJob<T> &a = job_of(jl, local);
+    const int nth_c = a.nth_c, nph_c = a.nph_c, nth_p = a.nth_p, nph_p = a.nph_p, cols = a.cols;
+    const int h = nph_c / 2;
+    const int nchunk = (h + cols - 1) / cols;
+    const int chunk = local % nchunk, cc = local / nchunk;   // cc = child * 2 + component
+    const int c = cc >> 1;
+    const int j0 = chunk * cols, nj = h - j0 < cols ? h - j0 : cols;
+    const int Kc = nth_c * nph_c, Kp = nth_p * nph_p, nj2 = 2 * nj;
+    T *Ds = reinterpret_cast<T *>(lds_raw);   // [nph_p][2 nj]: columns j0.. and j0 + h.. of D
+    T *As = Ds + nph_p * 2 * cols;            // [nth_p][nth_c]
+    T *Bs = As + nth_p * nth_c;
+    cx<T> *gs = reinterpret_cast<cx<T> *>(Ds + ((nph_p * 2 * cols + 2 * nth_p * nth_c + 1) & ~1));   // [nth_p][nph_p]
+    cx<T> *ts = gs + Kp;                                                                              // [nth_p][2 nj]
+    for (int t = threadIdx.x; t < nph_p * nj2; t += WG) {
+        const int J = t / nj2, jj = t - J * nj2;
+        Ds[t] = a.D[J * nph_c + (jj < nj ? j0 + jj : j0 + h + jj - nj)];
+    }
+    for (int t = threadIdx.x; t < nth_p * nth_c; t += WG) {
+        As[t] = a.A[t];
+        Bs[t] = a.B[t];
+    }
+    const cx<T> *g = a.Gp + ((int64_t)a.parent[c] * 2 + (cc & 1)) * Kp;
+    const cx<T> *sh = a.shift + (size_t)a.child_slot[c] * Kp;
+    for (int t = threadIdx.x; t < Kp; t += WG) gs[t] = cmul(sh[t], g[t]);
+    __syncthreads();
+    for (int t = threadIdx.x; t < nth_p * nj2; t += WG) {
+        const int I = t / nj2, jj = t - I * nj2;
+        const cx<T> *grow = gs + I * nph_p;
+        cx<T> v = {0, 0};
+        for (int J = 0; J < nph_p; ++J) {
+            const T d = Ds[J * nj2 + jj];
+            const cx<T> x = grow[J];
+            v.x = fmad(d, x.x, v.x);
+            v.y = fmad(d, x.y, v.y);
+        }
+        ts[t] = v;
+    }
+    __syncthreads();
+    cx<T> *o = a.Gc + (int64_t)cc * Kc;
+    for (int t = threadIdx.x; t < nth_c * nj; t += WG) {
+        const int i = t / nj, jl = t - i * nj;
+        cx<T> u = {0, 0}, v = {0, 0};   // azimuths j0 + jl and j0 + jl + h of row i
+        for (int I = 0; I < nth_p; ++I) {
+            const T pa = As[I * nth_c + i], pb = Bs[I * nth_c + i];
+            const cx<T> g1 = ts[I * nj2 + jl], g2 = ts[I * nj2 + nj + jl];
+            u.x = fmad(pa, g1.x, fmad(pb, g2.x, u.x));
+            u.y = fmad(pa, g1.y, fmad(pb, g2.y, u.y));
+            v.x = fmad(pb, g1.x, fmad(pa, g2.x, v.x));
+            v.y = fmad(pb, g1.y, fmad(pa, g2.y, v.y));
+        }
+        const int j = j0 + jl;
+        cx<T> w = o[i * nph_c + j];
+        o[i * nph_c + j] = {w.x + u.x, w.y + u.y};
+        w = o[i * nph_c + j + h];
+        o[i * nph_c + j + h] = {w.x + v.x, w.y + v.y};
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Diagonal translation over the interaction lists: G_b = sum T(X_bb') S_b'.
 // Threads are flattened over (box, direction, rhs), rhs fastest: the R
 // threads of a direction share every translation-table load.

@@ -345,11 +345,14 @@ def test_multilevel_product_sampled_rows():
 
 # kernel_plan bits: 1 = fixed plan, 16 = grouped translation, 32 = split
 # single-RHS interpolation stages (otherwise the per-box kernels), 128 = the
-# coarsest upward phi stage in one launch with the finer translations, 256 =
-# the near product in the level-2 translation launch
+# coarsest upward stage in one launch with the finer translations, 256 = the
+# near product in the level-2 translation launch, 512 = fused single-RHS
+# downward level transitions (phi and theta in one kernel, the default)
 SINGLE_RHS_PLANS = {"flat+split": 1 | 32, "grouped+split": 1 | 16 | 32, "flat+box": 1, "grouped+box": 1 | 16,
                     "grouped+split+overlap": 1 | 16 | 32 | 128,
-                    "grouped+split+overlap+near": 1 | 16 | 32 | 128 | 256}
+                    "grouped+split+overlap+near": 1 | 16 | 32 | 128 | 256,
+                    "flat+fused": 1 | 512, "grouped+fused+overlap": 1 | 16 | 128 | 512,
+                    "grouped+fused+overlap+near": 1 | 16 | 128 | 256 | 512}
 
 
 def test_single_rhs_kernel_variants():
