@@ -1,0 +1,156 @@
+"""Pins of the oracle's JMCFIE and CNF systems (eqs. 8-9, 14-16): the Gram
+matrix against an independent exact rule, the transparent-body limit (the
+normal-field operators of the two regions cancel, leaving the projection of
+the incident equivalent currents), the Mie series for a homogeneous and a
+coated sphere, and consistency with the independently pinned PMCHWT system
+(its solution satisfies both systems to discretisation level; a sign error
+in any normal-field term leaves a residual of order one)."""
+
+import numpy as np
+import pytest
+
+from oracle import farfield, mie, mom, rwg
+from workloads import coated_sphere_body, sphere_body
+
+THETA = np.deg2rad(np.arange(181.0))
+
+
+def _cuts(b, m, x):
+    sE, _ = farfield.rcs(m, b.frequency, x, THETA, 0 * THETA)
+    _, sH = farfield.rcs(m, b.frequency, x, THETA, 0 * THETA + np.pi / 2)
+    return sE, sH
+
+
+def _db(s, ref):
+    d = 10 * np.log10(s / ref)
+    return float(np.sqrt(np.mean(d ** 2))), float(np.abs(d).max())
+
+
+def _systems(b, m):
+    kh, eh = mom.incidence(0.0, 0.0)
+    out = {}
+    for name, tang in (("jmcfie", True), ("cnf", False)):
+        Z = mom.combined_dense(m, b.eps_r, b.mu_r, b.frequency, tang)
+        rhs = mom.combined_rhs(m, b.frequency, kh, eh, tang)
+        out[name] = (Z, rhs, np.linalg.solve(Z, rhs))
+    Zp = mom.pmchwt_dense(m, b.eps_r, b.mu_r, b.frequency)
+    out["pmchwt"] = (Zp, None, np.linalg.solve(Zp, mom.planewave_rhs(m, b.frequency, kh, eh)))
+    return out
+
+
+@pytest.fixture(scope="module")
+def sphere960_systems():
+    b = sphere_body(0.3, 4.0, 2)
+    m = rwg.from_body(b)
+    return b, m, _systems(b, m)
+
+
+def _rwg_at(m, x, P, pts):
+    """Current of coefficients x (one block of ne) at points of triangle P."""
+    v = m.vertices[m.triangles[P]]
+    out = np.zeros(pts.shape, dtype=complex)
+    for i in range(3):
+        e = m.tri_edge[P, i]
+        out += x[e] * m.tri_sign[P, i] * m.length[e] * (pts - v[i]) / (2 * m.area[P])
+    return out
+
+
+def test_gram_matrix_against_the_edge_midpoint_rule():
+    # the midpoint-of-edges rule (weights A/3) is exact for quadratics on a
+    # triangle, as is the 7-point rule the oracle uses; G = <f_m, f_n>
+    b = sphere_body(0.3, 4.0, 1)
+    m = rwg.from_body(b)
+    ne = m.n_edges
+    G, _, _ = mom.gram_rows(m, [1.0, 0.5], np.arange(ne))
+    ref = np.zeros((ne, ne))
+    for P in range(len(m.triangles)):
+        v = m.vertices[m.triangles[P]]
+        mids = 0.5 * (v + np.roll(v, -1, axis=0))
+        f = []
+        for i in range(3):
+            e = m.tri_edge[P, i]
+            f.append((e, m.tri_sign[P, i] * m.length[e] * (mids - v[i]) / (2 * m.area[P])))
+        for e1, f1 in f:
+            for e2, f2 in f:
+                ref[e1, e2] += m.area[P] / 3 * np.sum(f1 * f2)
+    assert np.abs(G - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_cnf_of_a_transparent_body_projects_the_incident_currents():
+    # eps_r = mu_r = 1: the normal-field operators of the two regions cancel
+    # term by term and the CNF matrix is the Gram matrix on both blocks; its
+    # solution is the projection of J = n x H_inc, M = -n x E_inc
+    b = sphere_body(0.3, 1.0, 2)
+    m = rwg.from_body(b)
+    ne = m.n_edges
+    Z = mom.combined_dense(m, b.eps_r, b.mu_r, b.frequency, tangential=False)
+    G, _, _ = mom.gram_rows(m, [1.0, 1.0], np.arange(ne))
+    blk = np.zeros_like(Z)
+    blk[:ne, :ne] = G
+    blk[ne:, ne:] = G
+    assert np.abs(Z - blk).max() <= 1e-10 * np.abs(G).max()
+    kh, eh = mom.incidence(0.0, 0.0)
+    x = np.linalg.solve(Z, mom.combined_rhs(m, b.frequency, kh, eh, tangential=False))
+    k0 = 2 * np.pi * b.frequency / mom.C0
+    hh = np.cross(kh, eh)
+    errJ, errM, nrm = 0.0, 0.0, 0.0
+    for P in range(len(m.triangles)):
+        c = m.centroid[P][None, :]
+        n = m.normal[P]
+        ph = np.exp(-1j * k0 * c @ kh)
+        Jx = np.cross(n, hh) / mom.ETA0 * ph[:, None]
+        Mx = -np.cross(n, eh) / mom.ETA0 * ph[:, None]
+        errJ += np.sum(np.abs(_rwg_at(m, x[:ne], P, c) - Jx) ** 2)
+        errM += np.sum(np.abs(_rwg_at(m, x[ne:], P, c) - Mx) ** 2)
+        nrm += np.sum(np.abs(Jx) ** 2)
+    # centroid values of a projection onto RWG functions on a 320-triangle
+    # sphere of radius 0.3 wavelengths: about 5 % RMS
+    assert np.sqrt(errJ / nrm) < 0.1 and np.sqrt(errM / nrm) < 0.1
+
+
+def test_jmcfie_and_cnf_match_mie_on_the_small_sphere(sphere960_systems):
+    b, m, sy = sphere960_systems
+    mE, mH = mie.sphere_rcs(0.3, 4.0, THETA)
+    # measured (E / H plane RMS, max dB): JMCFIE 0.14 / 0.66, 0.34 / 2.1;
+    # CNF 0.51 / 0.41, 0.85 / 0.85; PMCHWT on the same mesh 0.23 / 0.32
+    sE, sH = _cuts(b, m, sy["jmcfie"][2])
+    (rE, xE), (rH, xH) = _db(sE, mE), _db(sH, mH)
+    assert rE < 0.3 and xE < 0.6 and rH < 0.9 and xH < 2.6
+    sE, sH = _cuts(b, m, sy["cnf"][2])
+    (rE, xE), (rH, xH) = _db(sE, mE), _db(sH, mH)
+    assert rE < 0.7 and xE < 1.1 and rH < 0.6 and xH < 1.1
+
+
+def test_pmchwt_solution_satisfies_both_combined_systems(sphere960_systems):
+    b, m, sy = sphere960_systems
+    xp = sy["pmchwt"][2]
+    ne = m.n_edges
+    for name in ("jmcfie", "cnf"):
+        Z, rhs, _ = sy[name]
+        r = Z @ xp - rhs
+        # measured 0.023 (JMCFIE) and 0.032 (CNF), on both row blocks
+        assert np.linalg.norm(r[:ne]) < 0.06 * np.linalg.norm(rhs[:ne]), name
+        assert np.linalg.norm(r[ne:]) < 0.06 * np.linalg.norm(rhs[ne:]), name
+
+
+def test_cnf_is_better_conditioned_than_pmchwt(sphere960_systems):
+    # the second-kind normal equations: 2-norm condition 9.4 against 44
+    # (PMCHWT); the 1-norm condition numbers are compared
+    _, _, sy = sphere960_systems
+    assert np.linalg.cond(sy["cnf"][0], 1) < 0.5 * np.linalg.cond(sy["pmchwt"][0], 1)
+
+
+@pytest.mark.slow
+def test_jmcfie_on_the_coated_sphere_matches_the_coated_mie_series():
+    # two interfaces (eq. 16): lossy core eps 6 - 0.5j, r = 0.15, in a shell
+    # eps 2.56, r = 0.3; measured 0.18 / 0.39 dB (E plane RMS / max) and
+    # 0.31 / 1.3 dB (H plane), better than PMCHWT on the same mesh
+    b = coated_sphere_body(0.15, 6 - 0.5j, 1, 0.3, 2.56, 2)
+    m = rwg.from_body(b)
+    kh, eh = mom.incidence(0.0, 0.0)
+    Z = mom.combined_dense(m, b.eps_r, b.mu_r, b.frequency, True)
+    x = np.linalg.solve(Z, mom.combined_rhs(m, b.frequency, kh, eh, True))
+    mE, mH = mie.coated_sphere_rcs(0.15, 6 - 0.5j, 0.3, 2.56, THETA)
+    sE, sH = _cuts(b, m, x)
+    (rE, xE), (rH, xH) = _db(sE, mE), _db(sH, mH)
+    assert rE < 0.3 and xE < 0.6 and rH < 0.5 and xH < 1.8
