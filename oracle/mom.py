@@ -347,19 +347,27 @@ def planewave_rhs(mesh: RWGMesh, frequency, k_hat, e_hat, E0=1.0):
 #   N-EFIE(r): eta n x L J - n x K M + M / 2 = -n x E_inc   (eq. 8)
 #   N-MFIE(r): n x K J - J / 2 + n x L M / eta = -n x H_inc (eq. 9)
 # JMCFIE (eq. 14): J-row = sum_r T-EFIE(r) / eta_r + (-1)^r N-MFIE(r),
-# M-row = sum_r eta_r T-MFIE(r) - (-1)^r N-EFIE(r), (-1)^r = -1 on the side
-# the normal points into (the exterior of a single body) and +1 behind it.
+# M-row = sum_r eta_r T-MFIE(r) - (-1)^r N-EFIE(r).  The figure that numbers
+# the two media is not available; region 1 is taken as the one behind the
+# normal (the interior of a single body), so (-1)^r = +1 on the side the
+# normal points into and -1 behind it.  Both numberings give systems with
+# the same solution (the T and N parts hold separately); this one lets the
+# identity terms of the two parts reinforce each other (condition number 6.6
+# against 55 on a 960-unknown sphere of eps_r 4) and is the one for which
+# JMCFIE needs fewer iterations than the T parts alone and than PMCHWT, as
+# the paper reports.  The rows below are the combination times -1, so that
+# the Gram identity enters the diagonal blocks with a positive sign, as in
+# CNF: JMCFIE = (N parts) - (T parts).
 # The T parts are tested with the region-restricted basis (region sign on the
 # test half, as in PMCHWT); in the N parts the sign (-1)^r cancels the sign
 # of n_r, so the test halves carry no region sign and are rotated by the
 # triangle's own normal.  The code integrates the fields against the rotated
-# halves, <n x f, X> = -<f, n x X>, so the N parts enter with the opposite
-# sign of the rows above.  The identity terms become Gram matrices: J and M
-# (one half from each region) and, with the T parts' jump terms,
-# -(1/eta_o - 1/eta_p) <f, n x M> / 2 and +(eta_o - eta_p) <f, n x J> / 2
+# halves, <n x f, X> = -<f, n x X>.  The identity terms become Gram
+# matrices: J and M (one half from each region) and, with the T parts' jump
+# terms, -(1/eta_o - 1/eta_p) <f, n x M> / 2 and +(eta_o - eta_p) <f, n x J> / 2
 # per triangle between front region o and back region p.
 # Scaled as PMCHWT: unknowns [J ; M~ = M / eta0], J-row in A/m, M-row / eta0.
-# CNF (the normal equations alone): the same without the T parts.
+# CNF (the normal equations alone, eqs. 8-9): the N parts only.
 
 def operator_rows_n(mesh: RWGMesh, k: complex, region: int, test_edges):
     """Rows ``test_edges`` of n x L_r and n x K_r with unsigned test halves
@@ -441,16 +449,16 @@ def combined_rows(mesh: RWGMesh, eps_r, mu_r, frequency, test_edges, tangential=
         ZM[:, ne:] += KN
         if tangential:
             L, K = operator_rows(mesh, k, r, test_edges)
-            ZJ[:, :ne] += L
-            ZJ[:, ne:] += -K / eta[r]
-            ZM[:, :ne] += eta[r] * K
-            ZM[:, ne:] += L
+            ZJ[:, :ne] -= L
+            ZJ[:, ne:] -= -K / eta[r]
+            ZM[:, :ne] -= eta[r] * K
+            ZM[:, ne:] -= L
     G, GJ, GM = gram_rows(mesh, eta, test_edges)
     ZJ[:, :ne] += G
     ZM[:, ne:] += G
     if tangential:
-        ZJ[:, ne:] += GM
-        ZM[:, :ne] += GJ
+        ZJ[:, ne:] -= GM
+        ZM[:, :ne] -= GJ
     return ZJ, ZM
 
 
@@ -463,10 +471,10 @@ def combined_dense(mesh: RWGMesh, eps_r, mu_r, frequency, tangential=True):
 def combined_rhs(mesh: RWGMesh, frequency, k_hat, e_hat, tangential=True, E0=1.0):
     """Right-hand side of the scaled JMCFIE (or CNF) system for a plane wave
     in free space (region 0, eta_0 = 1):
-        J-row: -<f^0, E_inc>/eta0 - <n x f, H_inc>,  M-row: -<f^0, H_inc> + <n x f, E_inc>/eta0
+        J-row: -<n x f, H_inc> + <f^0, E_inc>/eta0,  M-row: <n x f, E_inc>/eta0 + <f^0, H_inc>
     (f^0: region-0-restricted basis; n x f: unsigned halves on the triangles
-    bordering free space, rotated by their normals); the T terms only for
-    JMCFIE."""
+    bordering free space, rotated by their normals); the T terms (those of
+    PMCHWT, entering JMCFIE with the sign -1) only for JMCFIE."""
     k0 = 2 * np.pi * frequency / C0
     k_hat = np.asarray(k_hat, dtype=float)
     e_hat = np.asarray(e_hat, dtype=complex)
@@ -486,6 +494,6 @@ def combined_rhs(mesh: RWGMesh, frequency, k_hat, e_hat, tangential=True, E0=1.0
     np.add.at(bM, e, np.sum(aw * (t @ e_hat) * phase, axis=1) / ETA0)
     if tangential:
         fr = c[:, None, None] * f
-        np.add.at(bJ, e, -np.sum(aw * (fr @ e_hat) * phase, axis=1) / ETA0)
-        np.add.at(bM, e, -np.sum(aw * (fr @ h_hat) * phase, axis=1) / ETA0)
+        np.add.at(bJ, e, np.sum(aw * (fr @ e_hat) * phase, axis=1) / ETA0)
+        np.add.at(bM, e, np.sum(aw * (fr @ h_hat) * phase, axis=1) / ETA0)
     return np.concatenate([bJ, bM])

@@ -4,7 +4,9 @@ normal-field operators of the two regions cancel, leaving the projection of
 the incident equivalent currents), the Mie series for a homogeneous and a
 coated sphere, and consistency with the independently pinned PMCHWT system
 (its solution satisfies both systems to discretisation level; a sign error
-in any normal-field term leaves a residual of order one)."""
+in any normal-field term leaves a residual of order one), and the iteration
+ordering JMCFIE < CTF < PMCHWT the paper reports, which fixes the relative
+sign of the normal and tangential parts (both signs give the same solution)."""
 
 import numpy as np
 import pytest
@@ -111,11 +113,12 @@ def test_cnf_of_a_transparent_body_projects_the_incident_currents():
 def test_jmcfie_and_cnf_match_mie_on_the_small_sphere(sphere960_systems):
     b, m, sy = sphere960_systems
     mE, mH = mie.sphere_rcs(0.3, 4.0, THETA)
-    # measured (E / H plane RMS, max dB): JMCFIE 0.14 / 0.66, 0.34 / 2.1;
-    # CNF 0.51 / 0.41, 0.85 / 0.85; PMCHWT on the same mesh 0.23 / 0.32
+    # measured (RMS / max dB, E plane then H plane): JMCFIE 0.32 / 0.40 and
+    # 0.33 / 0.88; CNF 0.51 / 0.85 and 0.41 / 0.85; PMCHWT on the same mesh
+    # 0.23 / 0.38 and 0.32 / 1.07
     sE, sH = _cuts(b, m, sy["jmcfie"][2])
     (rE, xE), (rH, xH) = _db(sE, mE), _db(sH, mH)
-    assert rE < 0.3 and xE < 0.6 and rH < 0.9 and xH < 2.6
+    assert rE < 0.5 and xE < 0.7 and rH < 0.6 and xH < 1.3
     sE, sH = _cuts(b, m, sy["cnf"][2])
     (rE, xE), (rH, xH) = _db(sE, mE), _db(sH, mH)
     assert rE < 0.7 and xE < 1.1 and rH < 0.6 and xH < 1.1
@@ -140,11 +143,37 @@ def test_cnf_is_better_conditioned_than_pmchwt(sphere960_systems):
     assert np.linalg.cond(sy["cnf"][0], 1) < 0.5 * np.linalg.cond(sy["pmchwt"][0], 1)
 
 
+def test_iteration_ordering_of_the_formulations(sphere960_systems):
+    # unpreconditioned full GMRES to 1e-6: JMCFIE needs fewer iterations than
+    # the tangential equations alone (CTF), which need fewer than PMCHWT, the
+    # ordering the paper reports (Fig. 6 discussion); measured 34, 69, 100.
+    # With the other numbering of the two media in eq. 14 (the N parts added
+    # to the T parts instead of subtracted) JMCFIE takes 59 iterations and
+    # its condition number rises from 6.6 to 55, above PMCHWT's 44.
+    import scipy.sparse.linalg as sla
+    b, m, sy = sphere960_systems
+    kh, eh = mom.incidence(0.0, 0.0)
+    Zj, bj, _ = sy["jmcfie"]
+    Zc, bc, _ = sy["cnf"]
+    systems = {"jmcfie": (Zj, bj), "ctf": (Zc - Zj, bc - bj),
+               "pmchwt": (sy["pmchwt"][0], mom.planewave_rhs(m, b.frequency, kh, eh))}
+    its = {}
+    for name, (Z, rhs) in systems.items():
+        n = [0]
+
+        def count(_):
+            n[0] += 1
+        sla.gmres(Z, rhs, rtol=1e-6, restart=400, maxiter=400, callback=count, callback_type="pr_norm")
+        its[name] = n[0]
+    assert its["jmcfie"] < 0.7 * its["ctf"] and its["ctf"] < 0.85 * its["pmchwt"], its
+
+
 @pytest.mark.slow
 def test_jmcfie_on_the_coated_sphere_matches_the_coated_mie_series():
     # two interfaces (eq. 16): lossy core eps 6 - 0.5j, r = 0.15, in a shell
-    # eps 2.56, r = 0.3; measured 0.18 / 0.39 dB (E plane RMS / max) and
-    # 0.31 / 1.3 dB (H plane), better than PMCHWT on the same mesh
+    # eps 2.56, r = 0.3; measured 0.51 / 0.94 dB (E plane RMS / max) and
+    # 0.84 / 2.7 dB (H plane); PMCHWT on the same mesh 0.44 / 0.78 and
+    # 0.69 / 2.4
     b = coated_sphere_body(0.15, 6 - 0.5j, 1, 0.3, 2.56, 2)
     m = rwg.from_body(b)
     kh, eh = mom.incidence(0.0, 0.0)
@@ -153,4 +182,4 @@ def test_jmcfie_on_the_coated_sphere_matches_the_coated_mie_series():
     mE, mH = mie.coated_sphere_rcs(0.15, 6 - 0.5j, 0.3, 2.56, THETA)
     sE, sH = _cuts(b, m, x)
     (rE, xE), (rH, xH) = _db(sE, mE), _db(sH, mH)
-    assert rE < 0.3 and xE < 0.6 and rH < 0.5 and xH < 1.8
+    assert rE < 0.7 and xE < 1.2 and rH < 1.1 and xH < 3.3
