@@ -1,13 +1,15 @@
 /*
  * sfmm.h - C interface of the MI355X (gfx950) MLFMM solver for dielectric
- * scattering with the PMCHWT surface integral equation discretised by RWG
- * functions in a Galerkin method of moments.
+ * scattering with the PMCHWT, JMCFIE or CNF surface integral equations
+ * discretised by RWG functions in a Galerkin method of moments.
  *
  * Method: H. T. Chorsi, "Surface Integral Formulation with Preconditioned,
  * Multipole-Accelerated Iterative Method Applied for the Analysis of RCS of
  * Single and Multi-Layer Dielectric Structures", arXiv:1704.06862.
  *   - equivalent currents J, M on every interface and their fields:   eqs. 1-7
+ *   - normal field equations N-EFIE / N-MFIE:                          eqs. 8-9
  *   - tangential field equations T-EFIE / T-MFIE and interface rules:  eqs. 10-13
+ *   - the JMCFIE combination:                                          eqs. 14-15
  *   - several interfaces / layered bodies:                              eq. 16
  *   - RWG basis functions, Galerkin testing:                            eq. 22, "Discretization" section
  *   - far field and RCS:                                                eqs. 27-29
@@ -128,7 +130,10 @@ typedef struct {
                                  fused in one kernel (the default at one RHS).  A variant whose
                                  conditions do not hold (batch size, LDS) falls back to
                                  the vector kernel.  For tests and measurement.         */
-    int32_t formulation;      /* SFMM_FORM_*: integral equation; 0 = PMCHWT               */
+    int32_t formulation;      /* SFMM_FORM_*: integral equation; 0 = PMCHWT.  JMCFIE and
+                                 CNF run the near-field and aggregation/receive products
+                                 on the vector kernels (kernel_plan bits 1, 2 and 8 are
+                                 ignored for them)                                        */
     int32_t quad_points;      /* points of the triangle rule for the outer and regular
                                  inner integrals; 0 = 7 (degree 5), the only rule built;
                                  other values: SFMM_E_UNSUPPORTED                         */
@@ -138,10 +143,25 @@ typedef struct {
                                  as zero (SFMM_E_BREAKDOWN at setup); 0 = 1e-13           */
 } sfmm_options;
 
-/* Integral equations (the paper's "Integral Equation Formulation" section):
+/* Integral equations (the paper's "Integral Equation Formulation" section).
+ * All three act on the same unknowns [J ; M~ = M / eta0] (RWG coefficients,
+ * boundary layout) and give the same currents up to discretisation error:
  *   PMCHWT  tangential EFIE and MFIE of both regions of every interface summed
- *           (eqs. 10-13; several interfaces as in eq. 16). */
-enum { SFMM_FORM_PMCHWT = 0 };
+ *           (eqs. 10-13; several interfaces as in eq. 16).
+ *   JMCFIE  the paper's mixed formulation (eqs. 8-9, 14-16): J-rows
+ *           sum_r T-EFIE(r) / eta_r + (-1)^r N-MFIE(r), M-rows
+ *           sum_r eta_r T-MFIE(r) - (-1)^r N-EFIE(r), Galerkin-tested with the
+ *           RWG functions; the N parts are the fields tested with n x f on
+ *           each triangle, the half-jump terms become sparse Gram blocks.
+ *           (-1)^r = +1 on the side the triangle normal points into, the
+ *           numbering of the media for which the identity terms of the N
+ *           and T parts reinforce; rows multiplied by -1 so the Gram
+ *           identity enters the diagonal blocks positively, as in CNF.
+ *           J-rows in A/m, M-rows divided by eta0 as for PMCHWT.
+ *   CNF     the normal equations alone (eqs. 8-9, the N parts of JMCFIE): a
+ *           second-kind system; its near-field matrix is dominated by the
+ *           Gram blocks. */
+enum { SFMM_FORM_PMCHWT = 0, SFMM_FORM_JMCFIE = 1, SFMM_FORM_CNF = 2 };
 
 /* Krylov solvers of sfmm_solve (the paper's solver comparison, "Simulation
  * Results", Fig. 7: ILU-preconditioned BiCGStab and CGS, and BiCGStab
@@ -194,7 +214,7 @@ void sfmm_default_options(sfmm_options *opt);
  * regions with their eps_r, mu_r at one frequency, "Integral Equation
  * Formulation" section and eq. 16; RWG discretisation, eq. 22 and the
  * "Discretization" section).  Validates the meshes, builds the RWG tables,
- * the octrees, the FP64 near-field matrix of the PMCHWT operator (singular
+ * the octrees, the FP64 near-field matrix of the chosen formulation (singular
  * terms in closed form), the preconditioner chosen by opt->preconditioner
  * (default: the near-field polynomial; ILU0 = the paper's incomplete LU) and
  * the MLFMM tables, and uploads them to the device.  Bodies are independent
@@ -223,7 +243,8 @@ sfmm_status sfmm_num_unknowns(const sfmm_ctx *ctx, int32_t body, int64_t *n_unkn
 sfmm_status sfmm_edges(const sfmm_ctx *ctx, int32_t body, int32_t *edge_vertices);
 
 /* y = Z x for n_rhs vectors: the product of the moment matrix of the
- * PMCHWT equations (eqs. 10-13 and 16 tested with RWG functions, eqs. 22-26)
+ * context's formulation (PMCHWT: eqs. 10-13 and 16; JMCFIE: eqs. 8-16; CNF:
+ * eqs. 8-9; tested with RWG functions, eqs. 22-26)
  * that the paper's Krylov solver evaluates by the MLFMM ("Simulation
  * Results": the multipole-accelerated product).  Near part exact (stored
  * matrix), far part by aggregation, translation and disaggregation.
@@ -260,7 +281,7 @@ sfmm_status sfmm_set_solver(sfmm_ctx *ctx, int32_t gmres_restart, int32_t max_it
 /* Change the Krylov method (SFMM_SOLVER_*) of later sfmm_solve calls. */
 sfmm_status sfmm_set_krylov(sfmm_ctx *ctx, int32_t solver);
 
-/* Solve Z x = b, the discretised PMCHWT system of eqs. 10-13 / 16 with the
+/* Solve Z x = b, the discretised system of the context's formulation with the
  * plane-wave right-hand side of eqs. 20-21 and 30, by the preconditioned
  * Krylov iteration the paper uses ("Simulation Results"; the solver is
  * restarted GMRES here, see sfmm_options.solver).  b, x (and x0): [n_rhs][2E]
@@ -381,7 +402,8 @@ sfmm_status sfmm_describe(const sfmm_ctx *ctx, int32_t body, int64_t *info, int3
 /* Algorithmic HBM bytes of one single-RHS product y = Z x of a body at the
  * context's storage precision: the least traffic of this stored-table form,
  * every array read or written once per use.  bytes[0] near-field values (three
- * complex numbers per edge pair, the PMCHWT 2x2 block [[A, -B], [B, C]]) and
+ * complex numbers per edge pair for the PMCHWT 2x2 block [[A, -B], [B, C]],
+ * four for JMCFIE / CNF) and
  * column indices; bytes[1] x read and y written once; bytes[2] radiation
  * patterns read for aggregation and again for receiving (the aggregation and
  * disaggregation steps of the multipole method the paper's solver uses,

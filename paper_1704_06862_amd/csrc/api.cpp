@@ -193,7 +193,8 @@ sfmm_status sfmm_setup(const sfmm_body *bodies, int32_t n_bodies, const sfmm_opt
         if (o.poly_degree > 64) throw Error(SFMM_E_INVALID_ARG, "poly_degree must be at most 64");
         if (o.quad_points == 0) o.quad_points = 7;
         if (o.quad_points != 7) throw Error(SFMM_E_UNSUPPORTED, "only the 7-point triangle rule is built");
-        if (o.formulation != SFMM_FORM_PMCHWT) throw Error(SFMM_E_UNSUPPORTED, "unknown formulation");
+        if (o.formulation < SFMM_FORM_PMCHWT || o.formulation > SFMM_FORM_CNF)
+            throw Error(SFMM_E_UNSUPPORTED, "unknown formulation");
         if (o.solver < SFMM_SOLVER_GMRES || o.solver > SFMM_SOLVER_CGS) throw Error(SFMM_E_UNSUPPORTED, "unknown solver");
         if (o.ilu_pivot_tol == 0) o.ilu_pivot_tol = 1e-13;
         if (!(o.ilu_pivot_tol > 0) || !std::isfinite(o.ilu_pivot_tol))
@@ -208,7 +209,8 @@ sfmm_status sfmm_setup(const sfmm_body *bodies, int32_t n_bodies, const sfmm_opt
             bh->oct = build_octree(bh->mesh, o.finest_box, o.n_levels, o.digits, o.extra_multipoles);
             if (o.precision != SFMM_PREC_FP64) check_fp32_translations(*bh);
             auto t1 = std::chrono::steady_clock::now();
-            bh->near = fill_near(bh->mesh, bh->oct);
+            bh->form = o.formulation;
+            bh->near = fill_near(bh->mesh, bh->oct, o.formulation);
             auto t2 = std::chrono::steady_clock::now();
             if (o.preconditioner == SFMM_PRECOND_ILU0) bh->ilu = factor_ilu(bh->mesh, bh->oct, bh->near, o.ilu_pivot_tol);
             else if (o.preconditioner == SFMM_PRECOND_BLOCK_JACOBI) bh->ilu = factor_block_jacobi(bh->mesh, bh->oct, bh->near, o.ilu_pivot_tol);
@@ -218,7 +220,7 @@ sfmm_status sfmm_setup(const sfmm_body *bodies, int32_t n_bodies, const sfmm_opt
             }
             bh->precond = o.preconditioner;
             auto t3 = std::chrono::steady_clock::now();
-            for (const RegionTree &rt : bh->oct.regions) bh->tables.push_back(build_tables(bh->mesh, bh->oct, rt));
+            for (const RegionTree &rt : bh->oct.regions) bh->tables.push_back(build_tables(bh->mesh, bh->oct, rt, o.formulation));
             auto t4 = std::chrono::steady_clock::now();
             if (o.verbose) {
                 auto s = [](auto a, auto b) { return std::chrono::duration<double>(b - a).count(); };
@@ -467,13 +469,13 @@ sfmm_status sfmm_near_rows(const sfmm_ctx *ctx, int32_t body, int32_t n_rows, co
             for (int c = 0; c < ncol; ++c) {
                 int n = o.order[b.near.cols[b.near.col_ptr[bx] + c]];
                 int64_t idx = b.near.val_ptr[bx] + (int64_t)row * ncol + c;
-                cd A = b.near.A[idx], B = b.near.B[idx], C = b.near.C[idx];
+                cd A = b.near.A[idx], B = b.near.B[idx], C = b.near.C[idx], D = b.near.d(idx);
                 rE[2 * n] = A.real();
                 rE[2 * n + 1] = A.imag();
                 rE[2 * (ne + n)] = -B.real();
                 rE[2 * (ne + n) + 1] = -B.imag();
-                rH[2 * n] = B.real();
-                rH[2 * n + 1] = B.imag();
+                rH[2 * n] = D.real();
+                rH[2 * n + 1] = D.imag();
                 rH[2 * (ne + n)] = C.real();
                 rH[2 * (ne + n) + 1] = C.imag();
             }
@@ -508,12 +510,13 @@ sfmm_status sfmm_product_bytes(const sfmm_ctx *ctx, int32_t body, int64_t *bytes
         const int64_t ne = b.mesh.ne;
         int64_t col = 0;
         for (int i = 0; i < b.oct.nb; ++i) col += b.near.col_ptr[i + 1] - b.near.col_ptr[i];
-        int64_t nearb = 3 * cb * b.oct.near_pairs + 4 * col, xy = 2 * (2 * ne) * cb, pat = 0, lev = 0, trans = 0,
+        const int64_t planes = b.near.D.empty() ? 3 : 4;
+        int64_t nearb = planes * cb * b.oct.near_pairs + 4 * col, xy = 2 * (2 * ne) * cb, pat = 0, lev = 0, trans = 0,
                 interp = 0;
         for (size_t r = 0; r < b.oct.regions.size(); ++r) {
             const RegionTree &rt = b.oct.regions[r];
             const RegionTables &tb = b.tables[r];
-            pat += cb * (int64_t)(tb.tx.size() + (tb.lossy ? tb.rx.size() : tb.tx.size()));
+            pat += cb * (int64_t)(tb.tx.size() + (tb.lossy ? tb.rx.size() : tb.tx.size()) + tb.nx.size());
             for (int l = 2; l <= b.oct.f; ++l) {
                 const LevelBoxes &lv = rt.lev[l];
                 const int64_t K = tb.samp[l].K;

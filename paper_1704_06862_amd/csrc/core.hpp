@@ -135,16 +135,18 @@ Octree build_octree(const Mesh &m, double finest_box, int n_levels, double digit
 // ---------------------------------------------------------------------------
 // Near-field matrix in box-ELL layout: the rows of finest box b are its edges
 // (n_b rows); its columns are the edges of its neighbour boxes in nbr order
-// (nc_b columns).  Each edge pair holds the three distinct complex entries of
-// the 2x2 PMCHWT block [[A, -B], [B, C]] (scaled system).
+// (nc_b columns).  Each edge pair holds the 2x2 block [[A, -B], [D, C]] of the
+// scaled system; for PMCHWT D = B and D is not stored.
 struct NearMatrix {
     std::vector<int64_t> val_ptr;   // [nb + 1] offset of box b's first entry
     std::vector<int> col_ptr;       // [nb + 1] offset into cols
     std::vector<int> cols;          // internal positions
-    std::vector<cd> A, B, C;
+    std::vector<cd> A, B, C, D;     // D empty: D = B
+    const cd &d(int64_t i) const { return D.empty() ? B[i] : D[i]; }
 };
 
-NearMatrix fill_near(const Mesh &m, const Octree &o);
+// form: SFMM_FORM_PMCHWT, SFMM_FORM_JMCFIE or SFMM_FORM_CNF
+NearMatrix fill_near(const Mesh &m, const Octree &o, int form);
 
 // ILU(0) of the near matrix in box-block form, folded for the solves:
 //   forward : z_I = Linv_II v_I - sum_{K<I} (Linv_II L_IK) z_K
@@ -191,11 +193,15 @@ struct RegionTables {
     std::vector<Sampling> samp;       // per level (2..f)
     std::vector<cd> tx;               // [n_region_edges][2][K_f] transmit patterns (theta, phi)
     std::vector<cd> rx;               // same for receive when lossy
+    // JMCFIE / CNF: patterns of the n x f test functions of every region edge
+    // (unsigned halves on the region's triangles, rotated by their normals),
+    // receive convention when lossy, transmit convention otherwise
+    std::vector<cd> nx;
     std::vector<std::vector<cd>> trans;     // per level: [343][K] C_r * w_k * T_L(k; X)
     std::vector<std::vector<double>> ipA, ipB, ipD;  // per level l (l -> l-1 transition, stored at child level l)
     std::vector<std::vector<cd>> shift_up, shift_dn; // per level l: [8][K_{l-1}]
 };
 
-RegionTables build_tables(const Mesh &m, const Octree &o, const RegionTree &rt);
+RegionTables build_tables(const Mesh &m, const Octree &o, const RegionTree &rt, int form);
 
 }  // namespace sfmm

@@ -147,6 +147,10 @@ class DeviceBodyT final : public DeviceBody {
         nA_ = upload_cx(h.near.A);
         nB_ = upload_cx(h.near.B);
         nC_ = upload_cx(h.near.C);
+        gen_ = h.form != SFMM_FORM_PMCHWT;
+        if (gen_) nD_ = upload_cx(h.near.D);
+        // weight of the tangential parts: JMCFIE = (N parts) - (T parts)
+        tang_ = h.form == SFMM_FORM_CNF ? cx<T>{0, 0} : cx<T>{-1, 0};
         precond_ = h.precond;
         for (const cd &t : h.poly) inv_theta_.push_back(to_cx<T>(1.0 / t));
         if (!h.poly_dinv.empty()) dinv_ = upload_cx(h.poly_dinv);
@@ -165,7 +169,9 @@ class DeviceBodyT final : public DeviceBody {
             near_ngrp_ = (int)(grp.size() / 2);
             if (near_ngrp_ > 0) near_grp_ = upload(grp);
         }
-        if constexpr (std::is_same<T, float>::value) build_mma_tiles(h);
+        if constexpr (std::is_same<T, float>::value) {
+            if (!gen_) build_mma_tiles(h);
+        }
         upload_edge_quadrature(m);
         if (!h.ilu.fwd_col_ptr.empty()) {
             fcol_ptr_ = upload(h.ilu.fwd_col_ptr);
@@ -206,6 +212,7 @@ class DeviceBodyT final : public DeviceBody {
             if (f_ >= 2) {
                 R.tx = upload_cx(tb.tx);
                 if (tb.lossy) R.rx = upload_cx(tb.rx);
+                if (!tb.nx.empty()) R.nx = upload_cx(tb.nx);
                 for (int l = 2; l <= f_; ++l) {
                     const Sampling &s = tb.samp[l];
                     const LevelBoxes &lv = rt.lev[l];
@@ -441,16 +448,22 @@ class DeviceBodyT final : public DeviceBody {
         const int t = lds ? rt : 1;
         dim3 grid(nb_, (max_nrow_ + RW - 1) / RW, R / t);
         const size_t shm = lds ? (size_t)max_ncol_ * 2 * t * sizeof(cx<T>) : 0;
-#define SFMM_NEAR(RT_, L_)                                                                                      \
-    k_near<T, RT_, L_, POLY><<<grid, RWG, shm, stream_>>>(R, bstart_, near_col_ptr_, near_cols_, near_val_ptr_, \
-                                                          nA_, nB_, nC_, x, y, acc, inv_theta, write_y,           \
-                                                          POLY ? dinv_ : nullptr)
+#define SFMM_NEAR_(RT_, L_, G_)                                                                                   \
+    k_near<T, RT_, L_, POLY, G_><<<grid, RWG, shm, stream_>>>(R, bstart_, near_col_ptr_, near_cols_, near_val_ptr_, \
+                                                              nA_, nB_, nC_, nD_, x, y, acc, inv_theta, write_y,    \
+                                                              POLY ? dinv_ : nullptr)
+#define SFMM_NEAR(RT_, L_)                  \
+    do {                                    \
+        if (gen_) SFMM_NEAR_(RT_, L_, true);  \
+        else SFMM_NEAR_(RT_, L_, false);      \
+    } while (0)
         if (!lds) SFMM_NEAR(1, false);
         else if (t == 8) SFMM_NEAR(8, true);
         else if (t == 4) SFMM_NEAR(4, true);
         else if (t == 2) SFMM_NEAR(2, true);
         else SFMM_NEAR(1, true);
 #undef SFMM_NEAR
+#undef SFMM_NEAR_
         LAUNCHCHK();
     }
 
@@ -590,37 +603,53 @@ class DeviceBodyT final : public DeviceBody {
     void receive_region(Reg &G, int R, cx<T> *y) {
         const int f = f_;
         if constexpr (std::is_same<T, float>::value) {
-            if (plan_.agg_mma && R >= MMA_MIN_R) {
+            if (plan_.agg_mma && R >= MMA_MIN_R && !gen_) {
                 receive_mma(G, R, y);
                 return;
             }
         }
+        const T tg = tang_.x;
         if (R == 1 && G.K[f] % 2 == 0) {
             const unsigned grid = nblocks(G.ne, 8 * WAVES);   // eight edges per wavefront
             if (!grid) return;
-            if (G.lossy)
-                k_receive1<T, true><<<grid, WG, 0, stream_>>>(G.ne, G.K[f], G.edge_box, G.edge_pos, G.edge_sign, G.tx,
-                                                              G.rx, G.inv_et, G.G[f], y);
-            else
-                k_receive1<T, false><<<grid, WG, 0, stream_>>>(G.ne, G.K[f], G.edge_box, G.edge_pos, G.edge_sign,
-                                                               G.tx, nullptr, G.inv_et, G.G[f], y);
+#define SFMM_RECV1(LO_, N_)                                                                                    \
+    k_receive1<T, LO_, N_><<<grid, WG, 0, stream_>>>(G.ne, G.K[f], G.edge_box, G.edge_pos, G.edge_sign, G.tx, \
+                                                     G.rx, G.nx, G.inv_et, tg, G.G[f], y)
+            if (G.lossy) {
+                if (gen_) SFMM_RECV1(true, true);
+                else SFMM_RECV1(true, false);
+            } else {
+                if (gen_) SFMM_RECV1(false, true);
+                else SFMM_RECV1(false, false);
+            }
+#undef SFMM_RECV1
             LAUNCHCHK();
             return;
         }
         const int rt = pick_tile(R, {8, 4, 2, 1}, [](int) { return true; });
         dim3 grid(G.nbf, R / rt);
-#define SFMM_RECV(RT_)                                                                                           \
-    if (G.lossy)                                                                                                 \
-        k_receive<T, RT_, true><<<grid, WG, 0, stream_>>>(G.K[f], R, G.edge_ptr, G.edge_pos, G.edge_sign, G.tx,  \
-                                                         G.rx, G.inv_et, G.G[f], y);                             \
-    else                                                                                                         \
-        k_receive<T, RT_, false><<<grid, WG, 0, stream_>>>(G.K[f], R, G.edge_ptr, G.edge_pos, G.edge_sign, G.tx, \
-                                                          nullptr, G.inv_et, G.G[f], y)
-        if (rt == 8) SFMM_RECV(8);
-        else if (rt == 4) SFMM_RECV(4);
-        else if (rt == 2) SFMM_RECV(2);
-        else SFMM_RECV(1);
+#define SFMM_RECV_(RT_, LO_, N_)                                                                              \
+    k_receive<T, RT_, LO_, N_><<<grid, WG, 0, stream_>>>(G.K[f], R, G.edge_ptr, G.edge_pos, G.edge_sign, G.tx, \
+                                                         G.rx, G.nx, G.inv_et, tg, G.G[f], y)
+#define SFMM_RECV(RT_)                       \
+    if (G.lossy) {                           \
+        if (gen_) SFMM_RECV_(RT_, true, true);   \
+        else SFMM_RECV_(RT_, true, false);       \
+    } else {                                 \
+        if (gen_) SFMM_RECV_(RT_, false, true);  \
+        else SFMM_RECV_(RT_, false, false);      \
+    }
+        if (rt == 8) {
+            SFMM_RECV(8)
+        } else if (rt == 4) {
+            SFMM_RECV(4)
+        } else if (rt == 2) {
+            SFMM_RECV(2)
+        } else {
+            SFMM_RECV(1)
+        }
 #undef SFMM_RECV
+#undef SFMM_RECV_
         LAUNCHCHK();
     }
 
@@ -860,7 +889,7 @@ class DeviceBodyT final : public DeviceBody {
                (int)regs_.size() * (f_ - 1) <= TRANS_MAXJOB;
     }
     bool near_join_ok(int R) const {
-        return R == 1 && plan_.near_join && near_ngrp_ > 0 &&
+        return R == 1 && plan_.near_join && near_ngrp_ > 0 && !gen_ &&
                (size_t)max_ncol_ * 2 * sizeof(cx<T>) <= LDS_LIMIT;
     }
     // x != nullptr: the near product y = Z_near x joins the launch
@@ -1788,8 +1817,8 @@ class DeviceBodyT final : public DeviceBody {
             HIPCHK(hipMemcpyAsync(da, angles, sizeof(double) * 2 * n_rhs, hipMemcpyHostToDevice, stream_));
             if (pol) HIPCHK(hipMemcpyAsync(da + 2 * n_rhs, pol, sizeof(double) * n_rhs, hipMemcpyHostToDevice, stream_));
             k_planewave_rhs<<<nblocks((int64_t)ne_ * n_rhs), WG, 0, stream_>>>(
-                ne_, n_rhs, gs0_, gqr_, gqf_, h_.mesh.k0, 1.0 / ETA0, da, pol ? da + 2 * n_rhs : nullptr,
-                (double2 *)b_dev);
+                ne_, n_rhs, gs0_, gqr_, gqf_, gqn_, (double)tang_.x, h_.mesh.k0, 1.0 / ETA0, da,
+                pol ? da + 2 * n_rhs : nullptr, (double2 *)b_dev);
             LAUNCHCHK();
             HIPCHK(hipStreamSynchronize(stream_));
         } catch (...) {
@@ -1841,6 +1870,8 @@ class DeviceBodyT final : public DeviceBody {
         const TriRule &q = tri_rule();
         const int ne = m.ne;
         std::vector<double> qr((size_t)14 * 3 * ne), qf(qr.size());
+        // JMCFIE / CNF: n x (unsigned half) at the same points, weighted
+        std::vector<double> qn(gen_ ? qr.size() : 0);
         std::vector<int> s0(ne);
         for (int e = 0; e < ne; ++e) {
             // the basis restricted to the exterior region: its two triangles
@@ -1860,6 +1891,14 @@ class DeviceBodyT final : public DeviceBody {
                         qr[((size_t)qi * 3 + c) * ne + e] = r[c];
                         qf[((size_t)qi * 3 + c) * ne + e] = coef * (r[c] - m.V[fv][c]) * w;
                     }
+                    if (gen_) {
+                        const double cu = m.ecoef[e][i] * m.len[e] / (2.0 * m.area[tri]) * w;
+                        const V3 h = m.qp[tri][a] - m.V[fv];
+                        const V3 &n = m.normal[tri];
+                        const double nh[3] = {n[1] * h[2] - n[2] * h[1], n[2] * h[0] - n[0] * h[2],
+                                              n[0] * h[1] - n[1] * h[0]};
+                        for (int c = 0; c < 3; ++c) qn[((size_t)qi * 3 + c) * ne + e] = cu * nh[c];
+                    }
                 }
                 ++side;
             }
@@ -1867,6 +1906,7 @@ class DeviceBodyT final : public DeviceBody {
         gs0_ = upload(s0);
         gqr_ = upload(qr);
         gqf_ = upload(qf);
+        if (gen_) gqn_ = upload(qn);
     }
 
   private:
@@ -1878,6 +1918,7 @@ class DeviceBodyT final : public DeviceBody {
         int *edge_box = nullptr;   // region box of every entry of the region's edge list
         int ne = 0;                // entries of the region's edge list
         cx<T> *tx = nullptr, *rx = nullptr, *tmp = nullptr;
+        cx<T> *nx = nullptr;       // patterns of the rotated test functions (JMCFIE / CNF)
         int K[MAXLEV] = {0}, nth[MAXLEV] = {0}, nph[MAXLEV] = {0}, nbox[MAXLEV] = {0};
         cx<T> *S[MAXLEV] = {nullptr}, *G[MAXLEV] = {nullptr}, *trans[MAXLEV] = {nullptr};
         int *il_ptr[MAXLEV] = {nullptr}, *il_src[MAXLEV] = {nullptr}, *il_off[MAXLEV] = {nullptr};
@@ -1987,6 +2028,9 @@ class DeviceBodyT final : public DeviceBody {
     int *near_col_ptr_ = nullptr, *near_cols_ = nullptr;
     int64_t *near_val_ptr_ = nullptr;
     cx<T> *nA_ = nullptr, *nB_ = nullptr, *nC_ = nullptr;
+    cx<T> *nD_ = nullptr;          // H-row J coefficient of the general block (JMCFIE / CNF)
+    bool gen_ = false;             // JMCFIE or CNF: general near blocks, rotated-test receive
+    cx<T> tang_{-1, 0};            // weight of the tangential parts (-1 JMCFIE, 0 CNF)
     // matrix-core tiles of the near matrix (FP32 / bf16-split modes)
     bool split_ = false;
     bool graphs_ = true;
@@ -2005,7 +2049,7 @@ class DeviceBodyT final : public DeviceBody {
     // edge quadrature for the plane-wave and far-field kernels
     double *scratch_ = nullptr;   // this device's copy of `scratch`
     int *gs0_ = nullptr;
-    double *gqr_ = nullptr, *gqf_ = nullptr;
+    double *gqr_ = nullptr, *gqf_ = nullptr, *gqn_ = nullptr;
     int *near_grp_ = nullptr, near_ngrp_ = 0;
     int max_ncol_ = 0, max_nrow_ = 0, max_ilu_nc_ = 0, precond_ = SFMM_PRECOND_ILU0;
     int *fcol_ptr_ = nullptr, *fcols_ = nullptr, *bcol_ptr_ = nullptr, *bcols_ = nullptr;

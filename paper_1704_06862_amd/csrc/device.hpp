@@ -15,6 +15,7 @@ struct BodyHost {
     IluFactors ilu;
     std::vector<RegionTables> tables;   // parallel to oct.regions
     int precond = SFMM_PRECOND_ILU0;
+    int form = SFMM_FORM_PMCHWT;        // integral equation (SFMM_FORM_*)
     std::vector<cd> poly;               // roots of the polynomial preconditioner
     std::vector<cd> poly_dinv;          // its edge-block scaling D^-1, [position][4]
 };

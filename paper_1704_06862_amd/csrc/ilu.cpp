@@ -112,7 +112,7 @@ IluFactors factor_ilu(const Mesh &m, const Octree &o, const NearMatrix &Z, doubl
                     int64_t idx = Z.val_ptr[I] + (int64_t)r * ncol + c0 + c;
                     W[(size_t)(2 * r) * ld + 2 * c] = Z.A[idx];
                     W[(size_t)(2 * r) * ld + 2 * c + 1] = -Z.B[idx];
-                    W[(size_t)(2 * r + 1) * ld + 2 * c] = Z.B[idx];
+                    W[(size_t)(2 * r + 1) * ld + 2 * c] = Z.d(idx);
                     W[(size_t)(2 * r + 1) * ld + 2 * c + 1] = Z.C[idx];
                 }
             c0 += nJ;
@@ -267,7 +267,7 @@ IluFactors factor_block_jacobi(const Mesh &m, const Octree &o, const NearMatrix 
                 int64_t idx = Z.val_ptr[I] + (int64_t)r * ncol + c0 + c;
                 A[(size_t)(2 * r) * nu + 2 * c] = Z.A[idx];
                 A[(size_t)(2 * r) * nu + 2 * c + 1] = -Z.B[idx];
-                A[(size_t)(2 * r + 1) * nu + 2 * c] = Z.B[idx];
+                A[(size_t)(2 * r + 1) * nu + 2 * c] = Z.d(idx);
                 A[(size_t)(2 * r + 1) * nu + 2 * c + 1] = Z.C[idx];
             }
         for (int i = 0; i < nu; ++i) Inv[(size_t)i * nu + i] = 1.0;

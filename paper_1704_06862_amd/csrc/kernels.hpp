@@ -165,12 +165,13 @@ struct NearArgs {
     cx<T> inv_theta;
     int write_y;
     const cx<T> *dinv;
+    const cx<T> *D = nullptr;   // general block [[A, -B], [D, C]] (GEN kernels)
 };
 
 // One workgroup of the near-field product: NRW rows (one wavefront each) of
 // box b from row NRW * rg on, right-hand sides rhs0 .. rhs0 + RT - 1; xs is
 // the LDS staging area of the box's input columns.
-template <typename T, int RT, bool LDS, bool POLY, int NRW>
+template <typename T, int RT, bool LDS, bool POLY, int NRW, bool GEN = false>
 __device__ __forceinline__ void near_block(const NearArgs<T> &a, int b, int rg, int rhs0, cx<T> *xs) {
     constexpr int NCG = 64 / RT;
     const int r0 = a.bstart[b], nrow = a.bstart[b + 1] - r0;
@@ -204,25 +205,27 @@ __device__ __forceinline__ void near_block(const NearArgs<T> &a, int b, int rg, 
     for (; c + NCG < ncol; c += 2 * NCG) {
         const cx<T> a0 = a.A[rb + c], b0 = a.B[rb + c], c0v = a.C[rb + c];
         const cx<T> a1 = a.A[rb + c + NCG], b1 = a.B[rb + c + NCG], c1v = a.C[rb + c + NCG];
+        const cx<T> d0 = GEN ? a.D[rb + c] : b0, d1 = GEN ? a.D[rb + c + NCG] : b1;
         cx<T> xj0, xm0, xj1, xm1;
         xin(c, xj0, xm0);
         xin(c + NCG, xj1, xm1);
         cfma(aE, a0, xj0);
         cfms(aE, b0, xm0);
-        cfma(aH, b0, xj0);
+        cfma(aH, d0, xj0);
         cfma(aH, c0v, xm0);
         cfma(bE, a1, xj1);
         cfms(bE, b1, xm1);
-        cfma(bH, b1, xj1);
+        cfma(bH, d1, xj1);
         cfma(bH, c1v, xm1);
     }
     if (c < ncol) {
         const cx<T> a0 = a.A[rb + c], b0 = a.B[rb + c], c0v = a.C[rb + c];
+        const cx<T> d0 = GEN ? a.D[rb + c] : b0;
         cx<T> xj0, xm0;
         xin(c, xj0, xm0);
         cfma(aE, a0, xj0);
         cfms(aE, b0, xm0);
-        cfma(aH, b0, xj0);
+        cfma(aH, d0, xj0);
         cfma(aH, c0v, xm0);
     }
     aE.x = group_sum<RT>(aE.x + bE.x);
@@ -253,18 +256,20 @@ __device__ __forceinline__ void near_block(const NearArgs<T> &a, int b, int rg, 
     }
 }
 
-// Grid: (finest boxes, row groups of RW rows, RHS tiles).
-template <typename T, int RT, bool LDS, bool POLY>
+// Grid: (finest boxes, row groups of RW rows, RHS tiles).  GEN: general
+// blocks [[A, -B], [D, C]] (JMCFIE / CNF); otherwise D = B (PMCHWT).
+template <typename T, int RT, bool LDS, bool POLY, bool GEN>
 __global__ void __launch_bounds__(RWG) k_near(int R, const int *__restrict__ bstart, const int *__restrict__ col_ptr,
                                               const int *__restrict__ cols, const int64_t *__restrict__ val_ptr,
                                               const cx<T> *__restrict__ A, const cx<T> *__restrict__ B,
-                                              const cx<T> *__restrict__ C, const cx<T> *__restrict__ x,
-                                              cx<T> *__restrict__ y, cx<T> *__restrict__ acc, cx<T> inv_theta,
-                                              int write_y, const cx<T> *__restrict__ dinv) {
+                                              const cx<T> *__restrict__ C, const cx<T> *__restrict__ D,
+                                              const cx<T> *__restrict__ x, cx<T> *__restrict__ y,
+                                              cx<T> *__restrict__ acc, cx<T> inv_theta, int write_y,
+                                              const cx<T> *__restrict__ dinv) {
     extern __shared__ unsigned char lds_raw[];
-    const NearArgs<T> a{R, bstart, col_ptr, cols, val_ptr, A, B, C, x, y, acc, inv_theta, write_y, dinv};
-    near_block<T, RT, LDS, POLY, RW>(a, (int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z * RT,
-                                     reinterpret_cast<cx<T> *>(lds_raw));
+    const NearArgs<T> a{R, bstart, col_ptr, cols, val_ptr, A, B, C, x, y, acc, inv_theta, write_y, dinv, D};
+    near_block<T, RT, LDS, POLY, RW, GEN>(a, (int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z * RT,
+                                          reinterpret_cast<cx<T> *>(lds_raw));
 }
 
 // ---------------------------------------------------------------------------
@@ -1324,11 +1329,39 @@ __global__ void __launch_bounds__(WG) k_translate_grp(int K, int R, const int *_
 // Receive at the finest level: y_E += s sum_k R.G, y_H += (s/et) sum_k R.(k x G)
 // for a tile of RT right-hand sides; one wavefront per edge, lane = rr + RT kg
 // (kg: direction group), reduction over the direction groups.
-template <typename T, int RT, bool LOSSY>
+// NRM (JMCFIE / CNF): with the rotated test functions' patterns N as well,
+// y_J += (c s R.G + N.(k x G)) / et and y_M += c s R.(k x G) - N.G, with
+// c = tang = -1 (JMCFIE) or 0 (CNF): the fields E ~ G, H ~ (k x G) / et
+// tested as the N-MFIE and N-EFIE rows minus the T-EFIE / et and et T-MFIE
+// rows.
+template <typename T, bool NRM>
+__device__ __forceinline__ void receive_store(cx<T> *y, int64_t iE, int64_t iH, T s, cx<T> aE, cx<T> aH, cx<T> nE,
+                                              cx<T> nH, cx<T> inv_et, T tang) {
+    cx<T> ye = y[iE], yh = y[iH];
+    if (!NRM) {
+        const cx<T> hh = cmul(aH, inv_et);
+        ye.x += s * aE.x;
+        ye.y += s * aE.y;
+        yh.x += s * hh.x;
+        yh.y += s * hh.y;
+    } else {
+        const T ts = tang * s;
+        const cx<T> jj = cmul(cx<T>{ts * aE.x + nH.x, ts * aE.y + nH.y}, inv_et);
+        ye.x += jj.x;
+        ye.y += jj.y;
+        yh.x += ts * aH.x - nE.x;
+        yh.y += ts * aH.y - nE.y;
+    }
+    y[iE] = ye;
+    y[iH] = yh;
+}
+
+template <typename T, int RT, bool LOSSY, bool NRM>
 __global__ void __launch_bounds__(WG) k_receive(int K, int R, const int *__restrict__ edge_ptr,
                                                 const int *__restrict__ edge_pos, const int *__restrict__ edge_sign,
                                                 const cx<T> *__restrict__ tx, const cx<T> *__restrict__ rx,
-                                                cx<T> inv_et, const cx<T> *__restrict__ G, cx<T> *__restrict__ y) {
+                                                const cx<T> *__restrict__ nx, cx<T> inv_et, T tang,
+                                                const cx<T> *__restrict__ G, cx<T> *__restrict__ y) {
     constexpr int NKG = 64 / RT;
     const int b = blockIdx.x;
     const int rhs0 = blockIdx.y * RT;
@@ -1338,7 +1371,8 @@ __global__ void __launch_bounds__(WG) k_receive(int K, int R, const int *__restr
     const cx<T> *g = G + (size_t)b * 2 * KR + rhs0 + rr;
     for (int ie = edge_ptr[b] + wave; ie < edge_ptr[b + 1]; ie += WAVES) {
         const cx<T> *Rp = (LOSSY ? rx : tx) + (size_t)ie * 2 * K;
-        cx<T> aE = {0, 0}, aH = {0, 0};
+        const cx<T> *Np = NRM ? nx + (size_t)ie * 2 * K : nullptr;
+        cx<T> aE = {0, 0}, aH = {0, 0}, nE = {0, 0}, nH = {0, 0};
         for (int k = kg; k < K; k += NKG) {
             cx<T> rt = Rp[k], rp = Rp[K + k];
             if (!LOSSY) {
@@ -1350,23 +1384,32 @@ __global__ void __launch_bounds__(WG) k_receive(int K, int R, const int *__restr
             cfma(aE, rp, gp);
             cfms(aH, rt, gp);
             cfma(aH, rp, gt);
+            if (NRM) {
+                cx<T> nt = Np[k], np = Np[K + k];
+                if (!LOSSY) {
+                    nt = cconj(nt);
+                    np = cconj(np);
+                }
+                cfma(nE, nt, gt);
+                cfma(nE, np, gp);
+                cfms(nH, nt, gp);
+                cfma(nH, np, gt);
+            }
         }
         aE.x = group_sum<RT>(aE.x);
         aE.y = group_sum<RT>(aE.y);
         aH.x = group_sum<RT>(aH.x);
         aH.y = group_sum<RT>(aH.y);
+        if (NRM) {
+            nE.x = group_sum<RT>(nE.x);
+            nE.y = group_sum<RT>(nE.y);
+            nH.x = group_sum<RT>(nH.x);
+            nH.y = group_sum<RT>(nH.y);
+        }
         if (lane < RT) {
             const int p = edge_pos[ie];
-            const T s = (T)edge_sign[ie];
-            const cx<T> hh = cmul(aH, inv_et);
             const int64_t iE = (int64_t)(2 * p) * R + rhs0 + rr, iH = iE + R;
-            cx<T> ye = y[iE], yh = y[iH];
-            ye.x += s * aE.x;
-            ye.y += s * aE.y;
-            yh.x += s * hh.x;
-            yh.y += s * hh.y;
-            y[iE] = ye;
-            y[iH] = yh;
+            receive_store<T, NRM>(y, iE, iH, (T)edge_sign[ie], aE, aH, nE, nH, inv_et, tang);
         }
     }
 }
@@ -1379,18 +1422,20 @@ __global__ void __launch_bounds__(WG) k_receive(int K, int R, const int *__restr
 // the edge's box read through the cache, and the eight partial sums of an edge
 // combined by three shuffles.  K is even (K = 2 (L + 1)^2), so the pairs
 // never straddle the theta/phi halves.
-template <typename T, bool LOSSY>
+template <typename T, bool LOSSY, bool NRM>
 __global__ void __launch_bounds__(WG) k_receive1(int ne, int K, const int *__restrict__ edge_box,
                                                  const int *__restrict__ edge_pos, const int *__restrict__ edge_sign,
                                                  const cx<T> *__restrict__ tx, const cx<T> *__restrict__ rx,
-                                                 cx<T> inv_et, const cx<T> *__restrict__ G, cx<T> *__restrict__ y) {
+                                                 const cx<T> *__restrict__ nx, cx<T> inv_et, T tang,
+                                                 const cx<T> *__restrict__ G, cx<T> *__restrict__ y) {
     const int lane = threadIdx.x & 63;
     const int sub = lane & 7;
     const int ie = (blockIdx.x * WAVES + (threadIdx.x >> 6)) * 8 + (lane >> 3);
     const cx<T> *tab = LOSSY ? rx : tx;
-    cx<T> aE = {0, 0}, aH = {0, 0};
+    cx<T> aE = {0, 0}, aH = {0, 0}, nE = {0, 0}, nH = {0, 0};
     if (ie < ne) {
         const cx<T> *Rp = tab + (size_t)ie * 2 * K;
+        const cx<T> *Np = NRM ? nx + (size_t)ie * 2 * K : nullptr;
         const cx<T> *g = G + (size_t)edge_box[ie] * 2 * K;
 #pragma unroll 3
         for (int k = 2 * sub; k < K; k += 16) {
@@ -1410,6 +1455,23 @@ __global__ void __launch_bounds__(WG) k_receive1(int ne, int K, const int *__res
             cfma(aE, rp1, gp1);
             cfms(aH, rt1, gp1);
             cfma(aH, rp1, gt1);
+            if (NRM) {
+                cx<T> nt0 = Np[k], nt1 = Np[k + 1], np0 = Np[K + k], np1 = Np[K + k + 1];
+                if (!LOSSY) {
+                    nt0 = cconj(nt0);
+                    nt1 = cconj(nt1);
+                    np0 = cconj(np0);
+                    np1 = cconj(np1);
+                }
+                cfma(nE, nt0, gt0);
+                cfma(nE, np0, gp0);
+                cfms(nH, nt0, gp0);
+                cfma(nH, np0, gt0);
+                cfma(nE, nt1, gt1);
+                cfma(nE, np1, gp1);
+                cfms(nH, nt1, gp1);
+                cfma(nH, np1, gt1);
+            }
         }
     }
 #pragma unroll
@@ -1418,18 +1480,16 @@ __global__ void __launch_bounds__(WG) k_receive1(int ne, int K, const int *__res
         aE.y += __shfl_xor(aE.y, m, 64);
         aH.x += __shfl_xor(aH.x, m, 64);
         aH.y += __shfl_xor(aH.y, m, 64);
+        if (NRM) {
+            nE.x += __shfl_xor(nE.x, m, 64);
+            nE.y += __shfl_xor(nE.y, m, 64);
+            nH.x += __shfl_xor(nH.x, m, 64);
+            nH.y += __shfl_xor(nH.y, m, 64);
+        }
     }
     if (ie < ne && sub == 0) {
         const int p = edge_pos[ie];
-        const T s = (T)edge_sign[ie];
-        const cx<T> hh = cmul(aH, inv_et);
-        cx<T> ye = y[2 * p], yh = y[2 * p + 1];
-        ye.x += s * aE.x;
-        ye.y += s * aE.y;
-        yh.x += s * hh.x;
-        yh.y += s * hh.y;
-        y[2 * p] = ye;
-        y[2 * p + 1] = yh;
+        receive_store<T, NRM>(y, 2 * p, 2 * p + 1, (T)edge_sign[ie], aE, aH, nE, nH, inv_et, tang);
     }
 }
 
@@ -1441,14 +1501,18 @@ __global__ void __launch_bounds__(WG) k_receive1(int ne, int K, const int *__res
 
 // b[r][e] = -s0 <f_e, E_inc> / eta0, b[r][ne + e] = -s0 <f_e, H_inc> eta0 / eta0
 // for the wave arriving from angles[r] = (theta, phi), polarisation pol[r].
+// With qn (JMCFIE / CNF: weighted n x f samples of the unsigned halves on the
+// region-0 triangles), the tangential part is weighted by tang (-1 or 0) and
+// the normal parts -<n x f, H_inc> (J-rows) and +<n x f, E_inc> / eta0
+// (M-rows) are added.
 __global__ void k_planewave_rhs(int ne, int R, const int *__restrict__ s0, const double *__restrict__ qr,
-                                const double *__restrict__ qf, double k0, double inv_eta0,
-                                const double *__restrict__ angles, const double *__restrict__ pol,
+                                const double *__restrict__ qf, const double *__restrict__ qn, double tang, double k0,
+                                double inv_eta0, const double *__restrict__ angles, const double *__restrict__ pol,
                                 double2 *__restrict__ b) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= (int64_t)ne * R) return;
     const int e = (int)(id % ne), r = (int)(id / ne);
-    double2 bE = make_double2(0, 0), bH = make_double2(0, 0);
+    double2 bE = make_double2(0, 0), bH = make_double2(0, 0), nE = make_double2(0, 0), nH = make_double2(0, 0);
     const int sg = s0[e];
     if (sg != 0) {
         double st, ct, sp, cp;
@@ -1472,11 +1536,21 @@ __global__ void k_planewave_rhs(int ne, int R, const int *__restrict__ s0, const
             bE.y += fe * sn;
             bH.x += fh * cs;
             bH.y += fh * sn;
+            if (qn) {
+                const double tx = qn[(q * 3 + 0) * (int64_t)ne + e], ty = qn[(q * 3 + 1) * (int64_t)ne + e],
+                             tz = qn[(q * 3 + 2) * (int64_t)ne + e];
+                const double te = tx * ev[0] + ty * ev[1] + tz * ev[2];
+                const double th = tx * hv[0] + ty * hv[1] + tz * hv[2];
+                nE.x += te * cs;
+                nE.y += te * sn;
+                nH.x += th * cs;
+                nH.y += th * sn;
+            }
         }
     }
-    const double c = -(double)sg * inv_eta0;
-    b[(int64_t)r * 2 * ne + e] = make_double2(c * bE.x, c * bE.y);
-    b[(int64_t)r * 2 * ne + ne + e] = make_double2(c * bH.x, c * bH.y);
+    const double c = -(double)sg * inv_eta0 * (qn ? tang : 1.0);
+    b[(int64_t)r * 2 * ne + e] = make_double2(c * bE.x - inv_eta0 * nH.x, c * bE.y - inv_eta0 * nH.y);
+    b[(int64_t)r * 2 * ne + ne + e] = make_double2(c * bH.x + inv_eta0 * nE.x, c * bH.y + inv_eta0 * nE.y);
 }
 
 // Bistatic RCS: for direction d (theta, phi) and the FP64 currents x[r]

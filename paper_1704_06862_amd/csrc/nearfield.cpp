@@ -97,8 +97,15 @@ inline cd expmj(cd k, double R) {  // exp(-j k R)
 }  // namespace
 
 // Local 3x3 interactions of the half-basis functions (r - v_i)/(2A) of test
-// triangle P and source triangle Q for wavenumber k.
-void pair_local(const Mesh &m, int P, int Q, cd k, bool close, cd L[3][3], cd K[3][3]) {
+// triangle P and source triangle Q for wavenumber k:
+//   L[i][j] = <h_i, L h_j>, K[i][j] = <h_i, K h_j> (principal value)
+// and, when LN != nullptr, the same fields tested with the rotated halves
+// t_i = n_P x h_i (eqs. 8-9):
+//   LN[i][j] = <t_i, L h_j>, with L h = -j k int h G - (j / k) grad int (div' h) G
+//              (t is not divergence-conforming, so the gradient stays on G)
+//   KN[i][j] = <t_i, K h_j>  (0 for Q = P: the field of P lies in its plane)
+void pair_local(const Mesh &m, int P, int Q, cd k, bool close, cd L[3][3], cd K[3][3], cd (*LN)[3] = nullptr,
+                cd (*KN)[3] = nullptr) {
     const TriRule &q = tri_rule();
     const double AP = m.area[P], AQ = m.area[Q];
     const V3 pv[3] = {m.V[m.T[P][0]], m.V[m.T[P][1]], m.V[m.T[P][2]]};
@@ -106,7 +113,8 @@ void pair_local(const Mesh &m, int P, int Q, cd k, bool close, cd L[3][3], cd K[
     const bool same = (P == Q);
     const cd jk(0.0, 1.0);
     const double inv4pi = 1.0 / (4.0 * PI);
-    cd Lacc[3][3] = {}, Kacc[3][3] = {};
+    cd Lacc[3][3] = {}, Kacc[3][3] = {}, LNacc[3][3] = {}, KNacc[3][3] = {};
+    const V3 &np = m.normal[P];
     for (int a = 0; a < 7; ++a) {
         const V3 &ra = m.qp[P][a];
         cd Isc = 0;
@@ -161,6 +169,17 @@ void pair_local(const Mesh &m, int P, int Q, cd k, bool close, cd L[3][3], cd K[
                 cd cy = g[2] * rj[0] - g[0] * rj[2];
                 cd cz = g[0] * rj[1] - g[1] * rj[0];
                 Kacc[i][jj] += wa * (ri[0] * cx + ri[1] * cy + ri[2] * cz);
+                if (LN) {
+                    // t_i = n_P x (r - p_i) (times 2 A_P);
+                    // A_Q L h_j = (-j k / 2)(Ivec - q_j Isc) - (j / k) g
+                    const double tx = np[1] * ri[2] - np[2] * ri[1], ty = np[2] * ri[0] - np[0] * ri[2],
+                                 tz = np[0] * ri[1] - np[1] * ri[0];
+                    const cd lx = (-0.5 * jk * k) * (Ivec[0] - qv[jj][0] * Isc) - (jk / k) * g[0];
+                    const cd ly = (-0.5 * jk * k) * (Ivec[1] - qv[jj][1] * Isc) - (jk / k) * g[1];
+                    const cd lz = (-0.5 * jk * k) * (Ivec[2] - qv[jj][2] * Isc) - (jk / k) * g[2];
+                    LNacc[i][jj] += wa * (tx * lx + ty * ly + tz * lz);
+                    KNacc[i][jj] += wa * (tx * cx + ty * cy + tz * cz);
+                }
             }
         }
     }
@@ -170,7 +189,35 @@ void pair_local(const Mesh &m, int P, int Q, cd k, bool close, cd L[3][3], cd K[
         for (int j = 0; j < 3; ++j) {
             L[i][j] = lf * Lacc[i][j];
             K[i][j] = same ? cd(0.0) : kf * Kacc[i][j];
+            if (LN) {
+                LN[i][j] = LNacc[i][j] / (2.0 * AP * AQ);
+                KN[i][j] = same ? cd(0.0) : kf * KNacc[i][j];
+            }
         }
+}
+
+// Gram blocks of triangle P's half-bases (the 7-point rule is exact for these
+// quadratics): G[i][j] = int_P h_i . h_j, GN[i][j] = int_P h_i . (n_P x h_j).
+static void gram_local(const Mesh &m, int P, double G[3][3], double GN[3][3]) {
+    const TriRule &q = tri_rule();
+    const double A = m.area[P];
+    const V3 pv[3] = {m.V[m.T[P][0]], m.V[m.T[P][1]], m.V[m.T[P][2]]};
+    const V3 &n = m.normal[P];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) G[i][j] = GN[i][j] = 0.0;
+    for (int a = 0; a < 7; ++a) {
+        const double w = q.w[a] * A / (4.0 * A * A);
+        V3 h[3], nh[3];
+        for (int i = 0; i < 3; ++i) {
+            h[i] = m.qp[P][a] - pv[i];
+            nh[i] = V3{n[1] * h[i][2] - n[2] * h[i][1], n[2] * h[i][0] - n[0] * h[i][2], n[0] * h[i][1] - n[1] * h[i][0]};
+        }
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                G[i][j] += w * dot(h[i], h[j]);
+                GN[i][j] += w * dot(h[i], nh[j]);
+            }
+    }
 }
 
 static bool close_pair(const Mesh &m, int P, int Q) {
@@ -181,7 +228,21 @@ static bool close_pair(const Mesh &m, int P, int Q) {
     return d < 2.0 * std::max(m.maxedge[P], m.maxedge[Q]);
 }
 
-NearMatrix fill_near(const Mesh &m, const Octree &o) {
+// PMCHWT: per region r bordering both triangles, with region-signed test and
+// source halves (factor f), A += f et L, B += f K, C += f L / et.
+// JMCFIE / CNF (block [[A, -B], [D, C]], scaled as PMCHWT; JMCFIE is the N
+// parts minus the T parts, the sign that lets their identity terms
+// reinforce): the N parts with unsigned rotated test halves (factor fn,
+// source region-signed), A += fn KN, B -= fn LN / et, D -= fn et LN,
+// C += fn KN; the T parts (JMCFIE only, weight ts = -1) with region-signed
+// halves, A += ts f L, B += ts f K / et, D += ts f et K, C += ts f L; on
+// every triangle the identity terms, A += G, C += G and (JMCFIE)
+// B -= ts GM, D += ts GJ with GJ = (et_o - et_p) GN / 2 and
+// GM = -(1/et_o - 1/et_p) GN / 2 between front region o and back region p.
+NearMatrix fill_near(const Mesh &m, const Octree &o, int form) {
+    const bool gen = form != SFMM_FORM_PMCHWT;
+    const bool tang = form != SFMM_FORM_CNF;
+    const double ts = -1.0;   // weight of the T parts in JMCFIE
     NearMatrix Z;
     Z.val_ptr.assign(o.nb + 1, 0);
     Z.col_ptr.assign(o.nb + 1, 0);
@@ -207,6 +268,7 @@ NearMatrix fill_near(const Mesh &m, const Octree &o) {
     Z.A.assign(nnz, 0.0);
     Z.B.assign(nnz, 0.0);
     Z.C.assign(nnz, 0.0);
+    if (gen) Z.D.assign(nnz, 0.0);
 
 #pragma omp parallel
     {
@@ -239,20 +301,21 @@ NearMatrix fill_near(const Mesh &m, const Octree &o) {
             }
             for (int t : tests) seen[t] = 0;
             for (int t : sources) seen[t] = 0;
-            cd L[3][3], K[3][3];
+            cd L[3][3], K[3][3], LN[3][3], KN[3][3];
             for (int P : tests) {
                 for (int Q : sources) {
                     bool close = close_pair(m, P, Q);
                     for (int rr = 0; rr < 2; ++rr) {
                         int r = m.TR[P][rr];
                         if (m.TR[Q][0] != r && m.TR[Q][1] != r) continue;
-                        pair_local(m, P, Q, m.k[r], close, L, K);
+                        pair_local(m, P, Q, m.k[r], close, L, K, gen ? LN : nullptr, gen ? KN : nullptr);
                         const cd et = m.eta[r];
                         for (int i = 0; i < 3; ++i) {
                             int em = m.tri_edge[P][i];
                             int row = rowmap[em];
                             if (row < 0) continue;
                             double sm = m.tri_region_sign(P, r) * m.tri_sign[P][i] * m.len[em];
+                            double smn = m.tri_sign[P][i] * m.len[em];
                             for (int j = 0; j < 3; ++j) {
                                 int en = m.tri_edge[Q][j];
                                 int col = colmap[en];
@@ -260,9 +323,47 @@ NearMatrix fill_near(const Mesh &m, const Octree &o) {
                                 double sn = m.tri_region_sign(Q, r) * m.tri_sign[Q][j] * m.len[en];
                                 double f = sm * sn;
                                 int64_t idx = base + (int64_t)row * ncol + col;
-                                Z.A[idx] += f * et * L[i][j];
-                                Z.B[idx] += f * K[i][j];
-                                Z.C[idx] += f * L[i][j] / et;
+                                if (!gen) {
+                                    Z.A[idx] += f * et * L[i][j];
+                                    Z.B[idx] += f * K[i][j];
+                                    Z.C[idx] += f * L[i][j] / et;
+                                    continue;
+                                }
+                                const double fn = smn * sn;
+                                cd a = fn * KN[i][j], b = -fn * LN[i][j] / et, d = -fn * et * LN[i][j];
+                                if (tang) {
+                                    a += ts * f * L[i][j];
+                                    b += ts * f * K[i][j] / et;
+                                    d += ts * f * et * K[i][j];
+                                }
+                                Z.A[idx] += a;
+                                Z.B[idx] += b;
+                                Z.C[idx] += a;
+                                Z.D[idx] += d;
+                            }
+                        }
+                    }
+                    if (gen && Q == P) {
+                        double G[3][3], GN[3][3];
+                        gram_local(m, P, G, GN);
+                        const cd eo = m.eta[m.TR[P][0]], ep = m.eta[m.TR[P][1]];
+                        const cd wj = tang ? ts * 0.5 * (eo - ep) : cd(0.0);
+                        const cd wm = tang ? -ts * 0.5 * (1.0 / eo - 1.0 / ep) : cd(0.0);
+                        for (int i = 0; i < 3; ++i) {
+                            int em = m.tri_edge[P][i];
+                            int row = rowmap[em];
+                            if (row < 0) continue;
+                            double sm = m.tri_sign[P][i] * m.len[em];
+                            for (int j = 0; j < 3; ++j) {
+                                int en = m.tri_edge[P][j];
+                                int col = colmap[en];
+                                if (col < 0) continue;
+                                double f = sm * m.tri_sign[P][j] * m.len[en];
+                                int64_t idx = base + (int64_t)row * ncol + col;
+                                Z.A[idx] += f * G[i][j];
+                                Z.C[idx] += f * G[i][j];
+                                Z.B[idx] -= f * wm * GN[i][j];
+                                Z.D[idx] += f * wj * GN[i][j];
                             }
                         }
                     }

@@ -43,7 +43,7 @@ void near_apply(const Octree &o, const NearMatrix &Z, const std::vector<cd> &x, 
                 const int p = Z.cols[Z.col_ptr[b] + c];
                 const cd xj = x[2 * p], xm = x[2 * p + 1];
                 e += Z.A[base + c] * xj - Z.B[base + c] * xm;
-                h += Z.B[base + c] * xj + Z.C[base + c] * xm;
+                h += Z.d(base + c) * xj + Z.C[base + c] * xm;
             }
             y[2 * (o.bstart[b] + r)] = e;
             y[2 * (o.bstart[b] + r) + 1] = h;
@@ -153,13 +153,13 @@ std::vector<cd> edge_block_inverse(const Octree &o, const NearMatrix &Z) {
                 if (Z.cols[Z.col_ptr[b] + q] == p) c = q;
             if (c < 0) throw Error(SFMM_E_BREAKDOWN, "edge missing from its own near-field row");
             const int64_t idx = Z.val_ptr[b] + (int64_t)r * ncol + c;
-            const cd A = Z.A[idx], B = Z.B[idx], C = Z.C[idx];
-            // [[A, -B], [B, C]]^-1 = [[C, B], [-B, A]] / (A C + B^2)
-            const cd det = A * C + B * B;
+            const cd A = Z.A[idx], B = Z.B[idx], C = Z.C[idx], D = Z.d(idx);
+            // [[A, -B], [D, C]]^-1 = [[C, B], [-D, A]] / (A C + B D)
+            const cd det = A * C + B * D;
             if (!(std::abs(det) > 0)) throw Error(SFMM_E_BREAKDOWN, "singular edge self block");
             dinv[4 * (size_t)p] = C / det;
             dinv[4 * (size_t)p + 1] = B / det;
-            dinv[4 * (size_t)p + 2] = -B / det;
+            dinv[4 * (size_t)p + 2] = -D / det;
             dinv[4 * (size_t)p + 3] = A / det;
         }
     }

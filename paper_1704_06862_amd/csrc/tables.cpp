@@ -98,7 +98,7 @@ Sampling make_sampling(int L) {
     return s;
 }
 
-RegionTables build_tables(const Mesh &m, const Octree &o, const RegionTree &rt) {
+RegionTables build_tables(const Mesh &m, const Octree &o, const RegionTree &rt, int form) {
     RegionTables t;
     const int r = rt.region;
     t.k = m.k[r];
@@ -118,6 +118,8 @@ RegionTables build_tables(const Mesh &m, const Octree &o, const RegionTree &rt) 
     const int Kf = sf.K;
     t.tx.assign((size_t)ned * 2 * Kf, 0.0);
     if (t.lossy) t.rx.assign((size_t)ned * 2 * Kf, 0.0);
+    const bool ntest = form != SFMM_FORM_PMCHWT;
+    if (ntest) t.nx.assign((size_t)ned * 2 * Kf, 0.0);
     const TriRule &q = tri_rule();
     const int nrb = (int)rt.fbox.size();
 #pragma omp parallel for schedule(dynamic, 4)
@@ -129,7 +131,7 @@ RegionTables build_tables(const Mesh &m, const Octree &o, const RegionTree &rt) 
             const int e = o.order[rt.edge_pos[ie]];
             // 14 weighted vector samples of f_e restricted to the region (its
             // two triangles there; the region sign stays in edge_sign)
-            V3 fv[14], pts[14];
+            V3 fv[14], pts[14], nv[14];
             double wq[14];
             const int es = rt.edge_sign[ie];
             int side = 0;
@@ -142,6 +144,10 @@ RegionTables build_tables(const Mesh &m, const Octree &o, const RegionTree &rt) 
                 for (int a = 0; a < 7; ++a) {
                     pts[side * 7 + a] = m.qp[tri][a] - c;
                     fv[side * 7 + a] = coef * (m.qp[tri][a] - m.V[m.efree[e][i]]);
+                    // n x f with the unsigned half (no region or edge sign)
+                    const V3 h = (m.ecoef[e][i] * m.len[e] / (2.0 * m.area[tri])) * (m.qp[tri][a] - m.V[m.efree[e][i]]);
+                    const V3 &n = m.normal[tri];
+                    nv[side * 7 + a] = V3{n[1] * h[2] - n[2] * h[1], n[2] * h[0] - n[0] * h[2], n[0] * h[1] - n[1] * h[0]};
                     wq[side * 7 + a] = q.w[a] * m.area[tri];
                 }
                 ++side;
@@ -167,6 +173,20 @@ RegionTables build_tables(const Mesh &m, const Octree &o, const RegionTree &rt) 
                 if (rx) {
                     rx[kk] = Rt;
                     rx[Kf + kk] = Rp;
+                }
+            }
+            if (ntest) {
+                cd *nx = &t.nx[(size_t)ie * 2 * Kf];
+                const double sg = t.lossy ? -1.0 : 1.0;   // receive: exp(-j k khat.r)
+                for (int kk = 0; kk < Kf; ++kk) {
+                    cd Nt = 0, Np = 0;
+                    for (int s = 0; s < 14; ++s) {
+                        cd ph = std::exp(sg * j * k * dot(sf.khat[kk], pts[s]));
+                        Nt += dot(sf.th[kk], nv[s]) * wq[s] * ph;
+                        Np += dot(sf.ph[kk], nv[s]) * wq[s] * ph;
+                    }
+                    nx[kk] = Nt;
+                    nx[Kf + kk] = Np;
                 }
             }
         }

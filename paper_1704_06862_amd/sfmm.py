@@ -23,7 +23,7 @@ STATUS = {0: "SFMM_OK", 1: "SFMM_E_INVALID_ARG", 2: "SFMM_E_MESH", 3: "SFMM_E_OO
 PREC_FP32, PREC_BF16_SPLIT, PREC_FP64 = 0, 1, 2
 PART_NEAR, PART_FAR, PART_ALL = 1, 2, 3
 PRECOND_ILU0, PRECOND_NONE, PRECOND_BLOCK_JACOBI, PRECOND_POLY = 0, 1, 2, 3
-FORM_PMCHWT = 0
+FORM_PMCHWT, FORM_JMCFIE, FORM_CNF = 0, 1, 2
 SOLVER_GMRES, SOLVER_BICGSTAB, SOLVER_CGS = 0, 1, 2
 
 EXPORTED = ["sfmm_default_options", "sfmm_setup", "sfmm_destroy", "sfmm_last_error", "sfmm_set_stream",

@@ -194,6 +194,7 @@ def test_unbuilt_options_are_refused():
     b = sphere_body(0.3, 4.0, 1)
     assert _status(lambda: sfmm.Context([b], device=-1, quad_points=13)) == 7
     assert _status(lambda: sfmm.Context([b], device=-1, formulation=9)) == 7
+    assert _status(lambda: sfmm.Context([b], device=-1, formulation=-1)) == 7
     assert _status(lambda: sfmm.Context([b], device=-1, solver=9)) == 7
     with sfmm.Context([b], device=-1, quad_points=7):
         pass
@@ -237,3 +238,33 @@ def test_junction_body_tables_match_oracle():
     with pytest.raises(sfmm.SfmmError) as e:
         sfmm.Context([bad], device=-1)
     assert e.value.status == 2
+
+
+@pytest.mark.parametrize("form", ["jmcfie", "cnf"])
+@pytest.mark.parametrize("body", ["sphere", "coated", "junction"])
+def test_combined_formulation_near_rows_match_oracle(form, body):
+    # the FP64 near-field rows of JMCFIE / CNF (normal-field integrals, Gram
+    # blocks, four distinct entries per edge pair) equal the oracle's rows on
+    # the near pattern, for one interface, two interfaces (a lossy core) and
+    # junction edges
+    from workloads import stacked_cylinder_body
+    if body == "sphere":
+        b, box, test = sphere_body(0.3, 4.0, 2), 0.15, [0, 7, 123, 250, 479]
+    elif body == "coated":
+        b, box, test = coated_sphere_body(0.25, 6 - 0.5j, 1, 0.45, 2.56, 2), 0.2, [3, 200, 480, 560, 599]
+    else:
+        b, box = stacked_cylinder_body(0.3, 0.6, (2.2, 4.4), 0.1), 0.15
+        m0 = rwg.from_body(b)
+        junction = np.nonzero(m0.side_tri[:, 2] >= 0)[0]
+        test = list(np.unique(np.concatenate([junction[::6], [0, 300]])))
+    m = rwg.from_body(b)
+    f = sfmm.FORM_JMCFIE if form == "jmcfie" else sfmm.FORM_CNF
+    with sfmm.Context([b], device=-1, finest_box=box, precision=2, formulation=f) as ctx:
+        rows = ctx.sfmm_near_rows(np.array(test))
+        d = ctx.sfmm_describe()
+    keys = octree.finest_keys(m, box, d["levels"])
+    pat = np.tile(octree.near_mask(keys)[test], (1, 2))
+    ZJ, ZM = mom.combined_rows(m, b.eps_r, b.mu_r, b.frequency, np.array(test), tangential=form == "jmcfie")
+    scale = np.abs(ZJ).max()
+    assert np.abs(rows[:, 0] - np.where(pat, ZJ, 0)).max() < 1e-12 * scale
+    assert np.abs(rows[:, 1] - np.where(pat, ZM, 0)).max() < 1e-12 * scale
