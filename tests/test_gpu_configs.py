@@ -4,7 +4,9 @@ the oracle's Mie series (homogeneous and coated spheres) as the reference.
 The dense oracle cannot solve these sizes; the Mie series is exact for the
 sphere, so the agreement is limited by the facetted surface and the MLFMM
 accuracy, and the bounds are set accordingly (RMS and max dB above a -30 dB
-floor of each cut's maximum)."""
+floor of each cut's maximum).  Bodies without a series (the ellipsoid batch,
+the stacked cylinder) are checked on sampled oracle rows and by convergence
+of the whole solve."""
 
 import numpy as np
 import pytest
@@ -153,3 +155,48 @@ def test_high_contrast_bodies_converge_under_jmcfie():
             assert all(a["converged"] and a["true_residual"] <= 1e-4 for a in info)
             worst = max(worst, max(its))
     assert worst <= 200
+
+
+def test_stacked_cylinder_82080_unknowns_under_jmcfie():
+    # the three-layer stacked cylinder (radius 1, height 3 wavelengths, layers
+    # eps_r 2.2 / 4.4 / 10.2, mean edge 1/20 wavelength: 82,080 unknowns, 252
+    # junction edges on the two rims where the internal discs meet the side
+    # wall).  Sampled rows of the FP32 product (junction rows among them)
+    # against the oracle's JMCFIE rows, and 8 monostatic angles solved to
+    # 1e-4 with ILU(0): measured 97-157 iterations, where PMCHWT with ILU(0)
+    # does not converge in 1,500
+    from oracle import mom, rwg
+    from workloads import random_complex_vector, stacked_cylinder_body
+
+    torch = pytest.importorskip("torch")
+    b = stacked_cylinder_body(1.0, 3.0, (2.2, 4.4, 10.2), 0.05)
+    m = rwg.from_body(b)
+    ne = m.n_edges
+    assert 2 * ne == 82080
+    junction = np.nonzero(m.side_tri[:, 2] >= 0)[0]
+    assert len(junction) == 252
+    rng = np.random.default_rng(11)
+    test = np.unique(np.concatenate([junction[::32], rng.choice(ne, 12, replace=False)]))
+    print("oracle rows of the stacked cylinder", len(test), flush=True)
+    ZJ, ZM = mom.combined_rows(m, b.eps_r, b.mu_r, b.frequency, test, True)
+    print("setup stacked cylinder jmcfie", flush=True)
+    with sfmm.Context([b], formulation=sfmm.FORM_JMCFIE, preconditioner=sfmm.PRECOND_ILU0, finest_box=0.25,
+                      digits=3.0, precision=sfmm.PREC_FP32, gmres_restart=50, tol=1e-4, max_iters=600) as ctx:
+        x = random_complex_vector(2 * ne, 2, seed=3)
+        y = ctx.sfmm_matvec(x, np.zeros_like(x))
+        for r in range(2):
+            ref = np.concatenate([ZJ @ x[r], ZM @ x[r]])
+            got = np.concatenate([y[r, test], y[r, ne + test]])
+            err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+            print("sampled rows rel err", err, flush=True)
+            assert err < 1e-3
+        ang = np.zeros((8, 2))
+        ang[:, 0] = np.linspace(0.0, np.pi, 8)
+        rhs = torch.zeros((8, 2 * ne), dtype=torch.complex128, device="cuda")
+        ctx.sfmm_planewave_rhs(ang, rhs)
+        xs = torch.zeros_like(rhs)
+        info = ctx.sfmm_solve(rhs, xs)
+    its = [a["iterations"] for a in info]
+    print("stacked cylinder jmcfie iterations", its, flush=True)
+    assert all(a["converged"] and a["true_residual"] <= 1e-4 for a in info)
+    assert max(its) <= 300
