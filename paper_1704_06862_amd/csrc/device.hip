@@ -105,6 +105,8 @@ double *scratch_address(int device) {
     return (double *)p;
 }
 
+std::mutex g_capture_mutex;
+
 inline unsigned nblocks(int64_t n, int bs = WG) { return (unsigned)((n + bs - 1) / bs); }
 
 template <typename T>
@@ -311,6 +313,9 @@ class DeviceBodyT final : public DeviceBody {
         const std::pair<int, int> key(kind, R);
         auto it = gexec_.find(key);
         if (it == gexec_.end()) {
+            // first-time captures and instantiations run one at a time in the
+            // process (bodies solved concurrently capture from several threads)
+            std::lock_guard<std::mutex> lock(g_capture_mutex);
             HIPCHK(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
             try {
                 body();
