@@ -147,6 +147,8 @@ struct NearMatrix {
 
 // form: SFMM_FORM_PMCHWT, SFMM_FORM_JMCFIE or SFMM_FORM_CNF
 NearMatrix fill_near(const Mesh &m, const Octree &o, int form);
+// The box-ELL structure alone (pointers and columns, no values).
+NearMatrix near_structure(const Octree &o);
 
 // ILU(0) of the near matrix in box-block form, folded for the solves:
 //   forward : z_I = Linv_II v_I - sum_{K<I} (Linv_II L_IK) z_K

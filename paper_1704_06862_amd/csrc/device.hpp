@@ -54,6 +54,10 @@ class DeviceBody {
 std::unique_ptr<DeviceBody> make_device_body(const BodyHost &h, int precision, int device, void *stream,
                                              bool graphs, bool autotune, int kernel_plan, int verbose);
 
+// The near-field matrix of fill_near computed on the device (one thread per
+// stored edge pair) and copied back to the host.
+NearMatrix fill_near_device(const Mesh &m, const Octree &o, int form, int device);
+
 // HIP helpers used by the C ABI for host <-> device staging.
 void *device_alloc(size_t bytes);
 void device_free(void *p);

@@ -228,21 +228,7 @@ static bool close_pair(const Mesh &m, int P, int Q) {
     return d < 2.0 * std::max(m.maxedge[P], m.maxedge[Q]);
 }
 
-// PMCHWT: per region r bordering both triangles, with region-signed test and
-// source halves (factor f), A += f et L, B += f K, C += f L / et.
-// JMCFIE / CNF (block [[A, -B], [D, C]], scaled as PMCHWT; JMCFIE is the N
-// parts minus the T parts, the sign that lets their identity terms
-// reinforce): the N parts with unsigned rotated test halves (factor fn,
-// source region-signed), A += fn KN, B -= fn LN / et, D -= fn et LN,
-// C += fn KN; the T parts (JMCFIE only, weight ts = -1) with region-signed
-// halves, A += ts f L, B += ts f K / et, D += ts f et K, C += ts f L; on
-// every triangle the identity terms, A += G, C += G and (JMCFIE)
-// B -= ts GM, D += ts GJ with GJ = (et_o - et_p) GN / 2 and
-// GM = -(1/et_o - 1/et_p) GN / 2 between front region o and back region p.
-NearMatrix fill_near(const Mesh &m, const Octree &o, int form) {
-    const bool gen = form != SFMM_FORM_PMCHWT;
-    const bool tang = form != SFMM_FORM_CNF;
-    const double ts = -1.0;   // weight of the T parts in JMCFIE
+NearMatrix near_structure(const Octree &o) {
     NearMatrix Z;
     Z.val_ptr.assign(o.nb + 1, 0);
     Z.col_ptr.assign(o.nb + 1, 0);
@@ -264,6 +250,25 @@ NearMatrix fill_near(const Mesh &m, const Octree &o, int form) {
             for (int p = o.bstart[j]; p < o.bstart[j + 1]; ++p) Z.cols[c++] = p;
         }
     }
+    return Z;
+}
+
+// PMCHWT: per region r bordering both triangles, with region-signed test and
+// source halves (factor f), A += f et L, B += f K, C += f L / et.
+// JMCFIE / CNF (block [[A, -B], [D, C]], scaled as PMCHWT; JMCFIE is the N
+// parts minus the T parts, the sign that lets their identity terms
+// reinforce): the N parts with unsigned rotated test halves (factor fn,
+// source region-signed), A += fn KN, B -= fn LN / et, D -= fn et LN,
+// C += fn KN; the T parts (JMCFIE only, weight ts = -1) with region-signed
+// halves, A += ts f L, B += ts f K / et, D += ts f et K, C += ts f L; on
+// every triangle the identity terms, A += G, C += G and (JMCFIE)
+// B -= ts GM, D += ts GJ with GJ = (et_o - et_p) GN / 2 and
+// GM = -(1/et_o - 1/et_p) GN / 2 between front region o and back region p.
+NearMatrix fill_near(const Mesh &m, const Octree &o, int form) {
+    const bool gen = form != SFMM_FORM_PMCHWT;
+    const bool tang = form != SFMM_FORM_CNF;
+    const double ts = -1.0;   // weight of the T parts in JMCFIE
+    NearMatrix Z = near_structure(o);
     const int64_t nnz = Z.val_ptr[o.nb];
     Z.A.assign(nnz, 0.0);
     Z.B.assign(nnz, 0.0);

@@ -48,7 +48,8 @@ class sfmm_options(ctypes.Structure):
                 ("device", ctypes.c_int32), ("verbose", ctypes.c_int32), ("preconditioner", ctypes.c_int32),
                 ("poly_degree", ctypes.c_int32), ("graphs", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("kernel_plan", ctypes.c_int32), ("formulation", ctypes.c_int32), ("quad_points", ctypes.c_int32),
-                ("solver", ctypes.c_int32), ("ilu_pivot_tol", ctypes.c_double)]
+                ("solver", ctypes.c_int32), ("ilu_pivot_tol", ctypes.c_double),
+                ("near_fill_on_device", ctypes.c_int32)]
 
 
 class sfmm_solve_info(ctypes.Structure):

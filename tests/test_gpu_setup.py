@@ -1,0 +1,64 @@
+"""The near-field fill on the device (sfmm_options.near_fill_on_device, the
+default for device contexts) against the host fill and the oracle: the same FP64 integrals, so the rows
+agree to rounding (1e-12 of the largest entry) for PMCHWT, JMCFIE and CNF, on
+one interface, two interfaces with a lossy core, and junction edges; and the
+solve on a device-filled context matches the host-filled one."""
+
+import numpy as np
+import pytest
+
+from oracle import mom, octree, rwg
+from workloads import coated_sphere_body, sphere_body, stacked_cylinder_body
+
+pytestmark = pytest.mark.gpu
+
+sfmm = pytest.importorskip("paper_1704_06862_amd.sfmm")
+
+BODIES = {
+    "sphere": (lambda: sphere_body(0.3, 4.0, 2), 0.15),
+    "coated": (lambda: coated_sphere_body(0.25, 6 - 0.5j, 1, 0.45, 2.56, 2), 0.2),
+    "junction": (lambda: stacked_cylinder_body(0.3, 0.6, (2.2, 4.4), 0.1), 0.15),
+}
+
+
+@pytest.mark.parametrize("form", [0, 1, 2])
+@pytest.mark.parametrize("name", ["sphere", "coated", "junction"])
+def test_device_near_fill_matches_host_and_oracle(name, form):
+    make, box = BODIES[name]
+    b = make()
+    m = rwg.from_body(b)
+    rng = np.random.default_rng(17)
+    test = np.unique(np.concatenate([rng.choice(m.n_edges, 12, replace=False),
+                                     np.nonzero(m.side_tri[:, 2] >= 0)[0][::8]]))
+    print("setup", name, "formulation", form, flush=True)
+    with sfmm.Context([b], near_fill_on_device=0, finest_box=box, precision=2, formulation=form) as ch:
+        rows_h = ch.sfmm_near_rows(test)
+        levels = ch.sfmm_describe()["levels"]
+    with sfmm.Context([b], finest_box=box, precision=2, formulation=form, near_fill_on_device=1) as cd:
+        rows_d = cd.sfmm_near_rows(test)
+    scale = np.abs(rows_h).max()
+    assert np.abs(rows_d - rows_h).max() < 1e-12 * scale
+    pat = np.tile(octree.near_mask(octree.finest_keys(m, box, levels))[test], (1, 2))
+    if form == 0:
+        R1, R2 = mom.pmchwt_rows(m, b.eps_r, b.mu_r, b.frequency, test)
+    else:
+        R1, R2 = mom.combined_rows(m, b.eps_r, b.mu_r, b.frequency, test, tangential=form == 1)
+    assert np.abs(rows_d[:, 0] - np.where(pat, R1, 0)).max() < 1e-12 * scale
+    assert np.abs(rows_d[:, 1] - np.where(pat, R2, 0)).max() < 1e-12 * scale
+
+
+def test_solve_on_a_device_filled_context():
+    b = sphere_body(0.3, 4.0, 2)
+    opts = dict(precision=2, finest_box=0.2, n_levels=3, extra_multipoles=2, preconditioner=0, tol=1e-6)
+    rhs = None
+    out = []
+    for dev in (0, 1):
+        with sfmm.Context([b], near_fill_on_device=dev, **opts) as ctx:
+            n = ctx.sfmm_num_unknowns()
+            if rhs is None:
+                rhs = ctx.sfmm_planewave_rhs(np.zeros((1, 2)), np.zeros((1, n), dtype=complex))
+            x = np.zeros_like(rhs)
+            info = ctx.sfmm_solve(rhs, x)[0]
+            out.append((x, info["iterations"]))
+    assert out[0][1] == out[1][1]
+    assert np.linalg.norm(out[0][0] - out[1][0]) < 1e-10 * np.linalg.norm(out[0][0])

@@ -268,3 +268,11 @@ def test_combined_formulation_near_rows_match_oracle(form, body):
     scale = np.abs(ZJ).max()
     assert np.abs(rows[:, 0] - np.where(pat, ZJ, 0)).max() < 1e-12 * scale
     assert np.abs(rows[:, 1] - np.where(pat, ZM, 0)).max() < 1e-12 * scale
+
+
+def test_device_near_fill_needs_a_device():
+    b = sphere_body(0.3, 4.0, 1)
+    assert _status(lambda: sfmm.Context([b], device=-1, near_fill_on_device=1)) == 1
+    assert _status(lambda: sfmm.Context([b], device=-1, near_fill_on_device=2)) == 1
+    with sfmm.Context([b], device=-1, near_fill_on_device=-1):
+        pass
