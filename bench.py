@@ -98,6 +98,13 @@ def parse():
                    help="skip the 307,200-unknown coated-sphere leg (64-RHS products and 64-angle sweep)")
     p.add_argument("--coated-plain-stride", type=int, default=8,
                    help="coated sweep: the plain single-RHS path is timed on every n-th angle")
+    p.add_argument("--cylinder-sweep", type=int, default=0,
+                   help="angles of the stacked-cylinder monostatic sweep under JMCFIE (0 = skip; 721 is the "
+                        "three-layer workload's sweep)")
+    p.add_argument("--cylinder-train-every", type=int, default=10,
+                   help="stacked-cylinder sweep: the learned guess trains on every n-th angle")
+    p.add_argument("--cylinder-plain-stride", type=int, default=8,
+                   help="stacked-cylinder sweep: the plain single-RHS path is timed on every n-th angle")
     return p.parse_args()
 
 
@@ -390,6 +397,34 @@ def coated_leg(sfmm, torch, stream, opts, n_ang, every, plain_stride):
     return out
 
 
+def cylinder_leg(sfmm, torch, stream, n_ang, every, plain_stride):
+    """The three-layer stacked cylinder (junction edges, eps_r 2.2 / 4.4 /
+    10.2, 82,080 unknowns) under JMCFIE with ILU(0): a monostatic theta sweep
+    to 1e-4, plain single-RHS FP32 solves against batched FP32 and
+    bf16-split solves and the learned guess trained on every `every`-th
+    angle (zero-guess GMRES is the batched bf16-split solve)."""
+    from workloads import stacked_cylinder_body
+
+    body = stacked_cylinder_body(1.0, 3.0, (2.2, 4.4, 10.2), 0.05)
+    opts = dict(formulation=sfmm.FORM_JMCFIE, preconditioner=sfmm.PRECOND_ILU0, finest_box=0.25, digits=3.0,
+                gmres_restart=50, tol=1e-4, max_iters=1000)
+    t0 = time.perf_counter()
+    ctx = sfmm.Context([body], precision=sfmm.PREC_FP32, **opts)
+    ctx_mixed = sfmm.Context([body], precision=sfmm.PREC_BF16_SPLIT, **opts)
+    setup_s = time.perf_counter() - t0
+    for c in (ctx, ctx_mixed):
+        c.sfmm_set_stream(stream.cuda_stream)
+    out = {"body": "three-layer stacked cylinder r=1 lambda0, h=3 lambda0, eps_r 2.2/4.4/10.2, mean edge "
+                   "0.05 lambda0, 82,080 unknowns (252 junction edges), JMCFIE, ILU(0), 0.25 lambda0 boxes, "
+                   "3 digits", "setup_s_both_contexts": round(setup_s, 1)}
+    print(f"cylinder setup {setup_s:.1f} s", file=sys.stderr, flush=True)
+    out["sweep"] = sweep(ctx, ctx_mixed, torch, n_ang, every, plain_stride=plain_stride, batched_fp32=True,
+                         pretrained=False)
+    ctx_mixed.close()
+    ctx.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -545,6 +580,11 @@ def main():
         result["coated"] = coated_leg(sfmm, torch, stream, opts, args.sweep, args.train_every,
                                       args.coated_plain_stride)
         print("coated", result["coated"], file=sys.stderr, flush=True)
+
+    if args.cylinder_sweep > 0:
+        result["cylinder"] = cylinder_leg(sfmm, torch, stream, args.cylinder_sweep, args.cylinder_train_every,
+                                          args.cylinder_plain_stride)
+        print("cylinder", result["cylinder"], file=sys.stderr, flush=True)
 
     if args.copy_calibration > 0:
         a = torch.ones(args.copy_calibration * (1 << 18), dtype=torch.float32, device="cuda")
