@@ -171,9 +171,7 @@ class DeviceBodyT final : public DeviceBody {
             near_ngrp_ = (int)(grp.size() / 2);
             if (near_ngrp_ > 0) near_grp_ = upload(grp);
         }
-        if constexpr (std::is_same<T, float>::value) {
-            if (!gen_) build_mma_tiles(h);
-        }
+        if constexpr (std::is_same<T, float>::value) build_mma_tiles(h);
         upload_edge_quadrature(m);
         if (!h.ilu.fwd_col_ptr.empty()) {
             fcol_ptr_ = upload(h.ilu.fwd_col_ptr);
@@ -477,11 +475,16 @@ class DeviceBodyT final : public DeviceBody {
                          int write_y) {
         const int nt = (R + 15) / 16;
         const unsigned ng = (unsigned)((ntiles_ + 7) / 8 * 8);
-#define SFMM_NMMA(NT_, S_)                                                                                          \
-    k_near_mma<NT_, S_, POLY><<<ng, 64 * MMA_WAVES, 0, stream_>>>(R, tile_box_, tile_row0_, tile_step_, bstart_,      \
-                                                                near_col_ptr_, near_cols_, tvals_, nsteps_, x, y,      \
-                                                                acc, inv_theta, write_y, POLY ? dinv_ : nullptr,       \
-                                                                ntiles_)
+#define SFMM_NMMA_(NT_, S_, G_)                                                                                 \
+    k_near_mma<NT_, S_, POLY, G_><<<ng, 64 * MMA_WAVES, 0, stream_>>>(R, tile_box_, tile_row0_, tile_step_, bstart_, \
+                                                                    near_col_ptr_, near_cols_, tvals_, nsteps_, x,  \
+                                                                    y, acc, inv_theta, write_y,                    \
+                                                                    POLY ? dinv_ : nullptr, ntiles_)
+#define SFMM_NMMA(NT_, S_)                  \
+    do {                                    \
+        if (gen_) SFMM_NMMA_(NT_, S_, true);  \
+        else SFMM_NMMA_(NT_, S_, false);      \
+    } while (0)
         if (split_) {
             if (nt == 1) SFMM_NMMA(1, true);
             else if (nt == 2) SFMM_NMMA(2, true);
@@ -494,6 +497,7 @@ class DeviceBodyT final : public DeviceBody {
             else SFMM_NMMA(4, false);
         }
 #undef SFMM_NMMA
+#undef SFMM_NMMA_
         LAUNCHCHK();
     }
 
@@ -523,9 +527,10 @@ class DeviceBodyT final : public DeviceBody {
         tile_box_ = upload(tbox);
         tile_row0_ = upload(trow0);
         tile_step_ = upload(tstep);
-        const std::vector<cd> *mats[3] = {&Z.A, &Z.B, &Z.C};
+        const std::vector<cd> *mats[4] = {&Z.A, &Z.B, &Z.C, &Z.D};
+        const int np = Z.D.empty() ? 3 : 4;   // planes: the general block adds D
         if (!split_) {
-            std::vector<cx<float>> V((size_t)3 * nsteps_ * 64, cx<float>{0, 0});
+            std::vector<cx<float>> V((size_t)np * nsteps_ * 64, cx<float>{0, 0});
             for (int t = 0; t < ntiles_; ++t) {
                 const int b = tbox[t], row0 = trow0[t];
                 const int nrow = o.bstart[b + 1] - o.bstart[b], ncol = Z.col_ptr[b + 1] - Z.col_ptr[b];
@@ -535,15 +540,15 @@ class DeviceBodyT final : public DeviceBody {
                         const int row = row0 + lane % 16, col = 4 * s + lane / 16;
                         if (row >= nrow || col >= ncol) continue;
                         const int64_t idx = Z.val_ptr[b] + (int64_t)row * ncol + col;
-                        for (int m = 0; m < 3; ++m)
+                        for (int m = 0; m < np; ++m)
                             V[((size_t)m * nsteps_ + st) * 64 + lane] = to_cx<float>((*mats[m])[idx]);
                     }
                 }
             }
             tvals_ = upload(V);
         } else {
-            // twelve planes (A, B, C) x (re hi, re lo, im hi, im lo), 8 bf16 per lane
-            std::vector<uint16_t> V((size_t)12 * nsteps_ * 64 * 8, 0);
+            // twelve (or sixteen) planes (A, B, C[, D]) x (re hi, re lo, im hi, im lo), 8 bf16 per lane
+            std::vector<uint16_t> V((size_t)4 * np * nsteps_ * 64 * 8, 0);
             auto bf = [](double v, uint16_t &hi, uint16_t &lo) {
                 auto rne = [](float f) {
                     uint32_t u;
@@ -570,7 +575,7 @@ class DeviceBodyT final : public DeviceBody {
                             const int row = row0 + lane % 16, col = 32 * s + 8 * (lane / 16) + e;
                             if (row >= nrow || col >= ncol) continue;
                             const int64_t idx = Z.val_ptr[b] + (int64_t)row * ncol + col;
-                            for (int m = 0; m < 3; ++m) {
+                            for (int m = 0; m < np; ++m) {
                                 const cd v = (*mats[m])[idx];
                                 uint16_t q[4];
                                 bf(v.real(), q[0], q[1]);
@@ -608,7 +613,7 @@ class DeviceBodyT final : public DeviceBody {
     void receive_region(Reg &G, int R, cx<T> *y) {
         const int f = f_;
         if constexpr (std::is_same<T, float>::value) {
-            if (plan_.agg_mma && R >= MMA_MIN_R && !gen_) {
+            if (plan_.agg_mma && R >= MMA_MIN_R) {
                 receive_mma(G, R, y);
                 return;
             }
@@ -761,24 +766,37 @@ class DeviceBodyT final : public DeviceBody {
         LAUNCHCHK();
     }
 
+    // PMCHWT: one pass (MODE 0).  JMCFIE: the RWG pass (MODE 1) and the pass
+    // of the rotated test functions (MODE 2, their table given as the
+    // transmit table for real k, as the receive table otherwise); CNF: MODE 2.
     void receive_mma(Reg &G, int R, cx<float> *y) {
         const int f = f_, K = G.K[f], nt = (R + 15) / 16;
         dim3 grid(G.nbf, (G.max_ebox + 15) / 16);
-#define SFMM_RCV(NT_, L_)                                                                                              \
-    k_receive_mma<NT_, L_><<<grid, 64 * MMA_WAVES, 0, stream_>>>(K, R, G.edge_ptr, G.edge_pos, G.edge_sign, G.tx, G.rx, \
-                                                                 G.inv_et, G.G[f], y)
-        if (G.lossy) {
-            if (nt == 1) SFMM_RCV(1, true);
-            else if (nt == 2) SFMM_RCV(2, true);
-            else if (nt == 3) SFMM_RCV(3, true);
-            else SFMM_RCV(4, true);
+        const float tg = tang_.x;
+#define SFMM_RCV_(NT_, L_, MD_, TX_, RX_)                                                                          \
+    k_receive_mma<NT_, L_, MD_><<<grid, 64 * MMA_WAVES, 0, stream_>>>(K, R, G.edge_ptr, G.edge_pos, G.edge_sign,  \
+                                                                      TX_, RX_, G.inv_et, tg, G.G[f], y)
+#define SFMM_RCV(L_, MD_, TX_, RX_)                     \
+    do {                                                \
+        if (nt == 1) SFMM_RCV_(1, L_, MD_, TX_, RX_);   \
+        else if (nt == 2) SFMM_RCV_(2, L_, MD_, TX_, RX_); \
+        else if (nt == 3) SFMM_RCV_(3, L_, MD_, TX_, RX_); \
+        else SFMM_RCV_(4, L_, MD_, TX_, RX_);           \
+    } while (0)
+        if (!gen_) {
+            if (G.lossy) SFMM_RCV(true, 0, G.tx, G.rx);
+            else SFMM_RCV(false, 0, G.tx, G.rx);
         } else {
-            if (nt == 1) SFMM_RCV(1, false);
-            else if (nt == 2) SFMM_RCV(2, false);
-            else if (nt == 3) SFMM_RCV(3, false);
-            else SFMM_RCV(4, false);
+            if (tg != 0.f) {
+                if (G.lossy) SFMM_RCV(true, 1, G.tx, G.rx);
+                else SFMM_RCV(false, 1, G.tx, G.rx);
+                LAUNCHCHK();
+            }
+            if (G.lossy) SFMM_RCV(true, 2, nullptr, G.nx);
+            else SFMM_RCV(false, 2, G.nx, nullptr);
         }
 #undef SFMM_RCV
+#undef SFMM_RCV_
         LAUNCHCHK();
     }
 

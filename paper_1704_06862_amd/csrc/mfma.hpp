@@ -61,8 +61,10 @@ __device__ __forceinline__ void mma_split(f32x4 &c, const bf16x8 &ah, const bf16
 // vals: FP32: three planes (A, B, C) of cx<float>[nsteps][64];
 //       split: twelve planes (A, B, C) x (re hi, re lo, im hi, im lo) of
 //       bf16x8[nsteps][64].
+// GEN (JMCFIE / CNF): a fourth plane D (or four more split planes) holds
+// the H-row J coefficient of the block [[A, -B], [D, C]]; otherwise D = B.
 // POLY as in k_near: with Q = Z_near X, acc += X / theta, Y = X - Q / theta.
-template <int NT, bool SPLIT, bool POLY>
+template <int NT, bool SPLIT, bool POLY, bool GEN>
 __global__ void __launch_bounds__(64 * MMA_WAVES)
     k_near_mma(int R, const int *__restrict__ tile_box, const int *__restrict__ tile_row0,
                const int64_t *__restrict__ tile_step, const int *__restrict__ bstart, const int *__restrict__ col_ptr,
@@ -91,9 +93,10 @@ __global__ void __launch_bounds__(64 * MMA_WAVES)
         if constexpr (!SPLIT) {
             const cx<float> *V = reinterpret_cast<const cx<float> *>(vals);
             const cx<float> a = V[vi], bb = V[nsteps * 64 + vi], c = V[2 * nsteps * 64 + vi];
+            const cx<float> d = GEN ? V[3 * nsteps * 64 + vi] : bb;
             const int col = 4 * s + lg;
             const int p = col < ncol ? cols[c0 + col] : -1;
-            const float nay = -a.y, nbx = -bb.x, nby = -bb.y, ncy = -c.y;
+            const float nay = -a.y, nbx = -bb.x, nby = -bb.y, ncy = -c.y, ndy = -d.y;
 #pragma unroll
             for (int n = 0; n < NT; ++n) {
                 const int rhs = 16 * n + lr;
@@ -102,7 +105,7 @@ __global__ void __launch_bounds__(64 * MMA_WAVES)
                     xj = x[(int64_t)(2 * p) * R + rhs];
                     xm = x[(int64_t)(2 * p + 1) * R + rhs];
                 }
-                // E = A xJ - B xM ; H = B xJ + C xM
+                // E = A xJ - B xM ; H = D xJ + C xM
                 mma_f32(aEr[n], a.x, xj.x);
                 mma_f32(aEr[n], nay, xj.y);
                 mma_f32(aEr[n], nbx, xm.x);
@@ -111,12 +114,12 @@ __global__ void __launch_bounds__(64 * MMA_WAVES)
                 mma_f32(aEi[n], a.y, xj.x);
                 mma_f32(aEi[n], nbx, xm.y);
                 mma_f32(aEi[n], nby, xm.x);
-                mma_f32(aHr[n], bb.x, xj.x);
-                mma_f32(aHr[n], nby, xj.y);
+                mma_f32(aHr[n], d.x, xj.x);
+                mma_f32(aHr[n], ndy, xj.y);
                 mma_f32(aHr[n], c.x, xm.x);
                 mma_f32(aHr[n], ncy, xm.y);
-                mma_f32(aHi[n], bb.x, xj.y);
-                mma_f32(aHi[n], bb.y, xj.x);
+                mma_f32(aHi[n], d.x, xj.y);
+                mma_f32(aHi[n], d.y, xj.x);
                 mma_f32(aHi[n], c.x, xm.y);
                 mma_f32(aHi[n], c.y, xm.x);
             }
@@ -126,8 +129,11 @@ __global__ void __launch_bounds__(64 * MMA_WAVES)
             const bf16x8 arh = V[vi], arl = V[pl + vi], aih = V[2 * pl + vi], ail = V[3 * pl + vi];
             const bf16x8 brh = V[4 * pl + vi], brl = V[5 * pl + vi], bih = V[6 * pl + vi], bil = V[7 * pl + vi];
             const bf16x8 crh = V[8 * pl + vi], crl = V[9 * pl + vi], cih = V[10 * pl + vi], cil = V[11 * pl + vi];
+            const bf16x8 drh = GEN ? V[12 * pl + vi] : brh, drl = GEN ? V[13 * pl + vi] : brl;
+            const bf16x8 dih = GEN ? V[14 * pl + vi] : bih, dil = GEN ? V[15 * pl + vi] : bil;
             const bf16x8 naih = neg8(aih), nail = neg8(ail), nbrh = neg8(brh), nbrl = neg8(brl);
             const bf16x8 nbih = neg8(bih), nbil = neg8(bil), ncih = neg8(cih), ncil = neg8(cil);
+            const bf16x8 ndih = neg8(dih), ndil = neg8(dil);
             const int colb = 32 * s + 8 * lg;
             int p[8];
 #pragma unroll
@@ -165,12 +171,12 @@ __global__ void __launch_bounds__(64 * MMA_WAVES)
                 mma_split(aEi[n], aih, ail, jrh, jrl);
                 mma_split(aEi[n], nbrh, nbrl, mih, mil);
                 mma_split(aEi[n], nbih, nbil, mrh, mrl);
-                mma_split(aHr[n], brh, brl, jrh, jrl);
-                mma_split(aHr[n], nbih, nbil, jih, jil);
+                mma_split(aHr[n], drh, drl, jrh, jrl);
+                mma_split(aHr[n], ndih, ndil, jih, jil);
                 mma_split(aHr[n], crh, crl, mrh, mrl);
                 mma_split(aHr[n], ncih, ncil, mih, mil);
-                mma_split(aHi[n], brh, brl, jih, jil);
-                mma_split(aHi[n], bih, bil, jrh, jrl);
+                mma_split(aHi[n], drh, drl, jih, jil);
+                mma_split(aHi[n], dih, dil, jrh, jrl);
                 mma_split(aHi[n], crh, crl, mih, mil);
                 mma_split(aHi[n], cih, cil, mrh, mrl);
             }
@@ -310,11 +316,15 @@ __global__ void __launch_bounds__(256) k_aggregate_mma(int K, int R, int nmt, co
 // with R = conj(F) (real wavenumber) or the separate receive table.  Rows are
 // the box's edges (16 per tile), K runs over directions (4 waves take every
 // 4th step, partial sums added through LDS), N over right-hand sides.
-template <int NT, bool LOSSY>
+// MODE 0 (PMCHWT) adds the sums as above.  JMCFIE / CNF run two passes:
+// MODE 1 with the RWG table, y_E += c s R.G / et, y_H += c s R.(k x G)
+// (c = tang, the weight of the tangential parts), and MODE 2 with the table
+// of the rotated test functions N, y_E += N.(k x G) / et, y_H -= N.G.
+template <int NT, bool LOSSY, int MODE>
 __global__ void __launch_bounds__(64 * MMA_WAVES)
     k_receive_mma(int K, int R, const int *__restrict__ edge_ptr, const int *__restrict__ edge_pos,
                   const int *__restrict__ edge_sign, const cx<float> *__restrict__ tx,
-                  const cx<float> *__restrict__ rx, cx<float> inv_et, const cx<float> *__restrict__ G,
+                  const cx<float> *__restrict__ rx, cx<float> inv_et, float tang, const cx<float> *__restrict__ G,
                   cx<float> *__restrict__ y) {
     __shared__ f32x4 red[MMA_WAVES - 1][NT * 4][64];
     const int b = blockIdx.x, mt = blockIdx.y;
@@ -395,13 +405,28 @@ __global__ void __launch_bounds__(64 * MMA_WAVES)
             if (ed >= n) continue;
             const int p = edge_pos[e0 + ed];
             const float sg = (float)edge_sign[e0 + ed];
-            const cx<float> hh = cmul(cx<float>{hr[q][v], hi[q][v]}, inv_et);
             const int64_t iE = (int64_t)(2 * p) * R + rhs, iH = iE + R;
             cx<float> ye = y[iE], yh = y[iH];
-            ye.x += sg * er[q][v];
-            ye.y += sg * ei[q][v];
-            yh.x += sg * hh.x;
-            yh.y += sg * hh.y;
+            if (MODE == 0) {
+                const cx<float> hh = cmul(cx<float>{hr[q][v], hi[q][v]}, inv_et);
+                ye.x += sg * er[q][v];
+                ye.y += sg * ei[q][v];
+                yh.x += sg * hh.x;
+                yh.y += sg * hh.y;
+            } else if (MODE == 1) {
+                const float c = tang * sg;
+                const cx<float> ee = cmul(cx<float>{c * er[q][v], c * ei[q][v]}, inv_et);
+                ye.x += ee.x;
+                ye.y += ee.y;
+                yh.x += c * hr[q][v];
+                yh.y += c * hi[q][v];
+            } else {
+                const cx<float> hh = cmul(cx<float>{hr[q][v], hi[q][v]}, inv_et);
+                ye.x += hh.x;
+                ye.y += hh.y;
+                yh.x -= er[q][v];
+                yh.y -= ei[q][v];
+            }
             y[iE] = ye;
             y[iH] = yh;
         }

@@ -108,19 +108,28 @@ def test_general_blocks_in_the_other_preconditioners(sphere, pc):
     assert rel(xs[0], np.linalg.solve(Z, rhs[0])) < 2e-3
 
 
-def test_jmcfie_on_a_lossy_coated_sphere():
-    # complex wavenumber in the core: separate receive tables for the RWG and
-    # the rotated test functions; two interfaces (eq. 16)
+@pytest.fixture(scope="module")
+def coated_jm():
     b = coated_sphere_body(0.15, 6 - 0.5j, 1, 0.3, 2.56, 2)
     m = rwg.from_body(b)
     print("oracle dense coated sphere jmcfie", flush=True)
-    Z = mom.combined_dense(m, b.eps_r, b.mu_r, b.frequency, True)
-    with sfmm.Context([b], formulation=sfmm.FORM_JMCFIE, **OPTS64) as ctx:
+    return b, m, mom.combined_dense(m, b.eps_r, b.mu_r, b.frequency, True)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_jmcfie_on_a_lossy_coated_sphere(coated_jm, prec):
+    # complex wavenumber in the core: separate receive tables for the RWG and
+    # the rotated test functions; two interfaces (eq. 16); at 16 RHS the
+    # FP32 and bf16-split contexts run the matrix-core near product (four
+    # planes) and the two-pass matrix-core receive
+    b, m, Z = coated_jm
+    opts = OPTS64 if prec == "fp64" else dict(OPTS32, precision=0 if prec == "fp32" else 1)
+    with sfmm.Context([b], formulation=sfmm.FORM_JMCFIE, **opts) as ctx:
         for R in (1, 16):
             x = random_complex_vector(2 * m.n_edges, R, seed=95 + R)
             y = ctx.sfmm_matvec(x, np.zeros_like(x))
             err = max(rel(y[r], (x @ Z.T)[r]) for r in range(R))
-            print(R, "coated jmcfie product rel err", err, flush=True)
+            print(prec, R, "coated jmcfie product rel err", err, flush=True)
             assert err < 1e-3
         kh, eh = mom.incidence(0.0, 0.0)
         rhs = ctx.sfmm_planewave_rhs(np.zeros((1, 2)), np.zeros((1, 2 * m.n_edges), dtype=complex))
