@@ -141,11 +141,15 @@ typedef struct {
     double ilu_pivot_tol;     /* ILU0 / BLOCK_JACOBI: a pivot whose modulus is at most this
                                  times the largest entry of its diagonal box block counts
                                  as zero (SFMM_E_BREAKDOWN at setup); 0 = 1e-13           */
-    int32_t near_fill_on_device; /* where the FP64 near-field matrix is computed: 1 on the
-                                 device (same integrals, one thread per stored edge pair,
-                                 copied back for the preconditioner set-up; needs
-                                 device >= 0, SFMM_E_INVALID_ARG otherwise), 0 on the host
-                                 (OpenMP), -1 (default) on the device when there is one */
+    int32_t setup_on_device;  /* where the FP64 near-field matrix and the ILU(0)
+                                 factorisation are computed: 1 on the device (the same
+                                 arithmetic: one thread per stored edge pair for the
+                                 fill, one workgroup per box row and one launch per
+                                 colour for ILU(0); needs device >= 0,
+                                 SFMM_E_INVALID_ARG otherwise), 0 on the host (OpenMP),
+                                 -1 (default) on the device when there is one.  The
+                                 block-Jacobi inverses and the polynomial's roots are
+                                 always computed on the host                              */
 } sfmm_options;
 
 /* Integral equations (the paper's "Integral Equation Formulation" section).

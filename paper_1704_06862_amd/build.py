@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libsfmm.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HOST_SOURCES = ["mesh.cpp", "octree.cpp", "nearfield.cpp", "ilu.cpp", "poly.cpp", "tables.cpp", "api.cpp"]
-DEVICE_SOURCES = ["device.hip", "guess.hip", "nearfill.hip"]
+DEVICE_SOURCES = ["device.hip", "guess.hip", "nearfill.hip", "ilufactor.hip"]
 
 HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-fopenmp", "-ffp-contract=off", "-fcx-limited-range",
               "-Wall", "-Wno-unused-function"]

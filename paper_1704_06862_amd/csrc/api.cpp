@@ -171,7 +171,7 @@ void sfmm_default_options(sfmm_options *o) {
     o->quad_points = 7;
     o->solver = SFMM_SOLVER_GMRES;
     o->ilu_pivot_tol = 1e-13;
-    o->near_fill_on_device = -1;
+    o->setup_on_device = -1;
 }
 
 sfmm_status sfmm_setup(const sfmm_body *bodies, int32_t n_bodies, const sfmm_options *opt, sfmm_ctx **out) {
@@ -202,11 +202,11 @@ sfmm_status sfmm_setup(const sfmm_body *bodies, int32_t n_bodies, const sfmm_opt
             throw Error(SFMM_E_INVALID_ARG, "ilu_pivot_tol must be positive");
         if (!std::isfinite(o.finest_box) || o.finest_box < 0 || !std::isfinite(o.digits) || o.digits < 0)
             throw Error(SFMM_E_INVALID_ARG, "finest_box and digits must be finite and non-negative");
-        if (o.near_fill_on_device < -1 || o.near_fill_on_device > 1)
-            throw Error(SFMM_E_INVALID_ARG, "near_fill_on_device must be -1, 0 or 1");
-        if (o.near_fill_on_device == 1 && o.device < 0)
-            throw Error(SFMM_E_INVALID_ARG, "near_fill_on_device needs a device");
-        if (o.near_fill_on_device == -1) o.near_fill_on_device = o.device >= 0 ? 1 : 0;
+        if (o.setup_on_device < -1 || o.setup_on_device > 1)
+            throw Error(SFMM_E_INVALID_ARG, "setup_on_device must be -1, 0 or 1");
+        if (o.setup_on_device == 1 && o.device < 0)
+            throw Error(SFMM_E_INVALID_ARG, "setup_on_device needs a device");
+        if (o.setup_on_device == -1) o.setup_on_device = o.device >= 0 ? 1 : 0;
         if (o.device >= 0) check_device(o.device);
         for (int32_t i = 0; i < n_bodies; ++i) {
             auto t0 = std::chrono::steady_clock::now();
@@ -216,10 +216,12 @@ sfmm_status sfmm_setup(const sfmm_body *bodies, int32_t n_bodies, const sfmm_opt
             if (o.precision != SFMM_PREC_FP64) check_fp32_translations(*bh);
             auto t1 = std::chrono::steady_clock::now();
             bh->form = o.formulation;
-            bh->near = o.near_fill_on_device ? fill_near_device(bh->mesh, bh->oct, o.formulation, o.device)
+            bh->near = o.setup_on_device ? fill_near_device(bh->mesh, bh->oct, o.formulation, o.device)
                                              : fill_near(bh->mesh, bh->oct, o.formulation);
             auto t2 = std::chrono::steady_clock::now();
-            if (o.preconditioner == SFMM_PRECOND_ILU0) bh->ilu = factor_ilu(bh->mesh, bh->oct, bh->near, o.ilu_pivot_tol);
+            if (o.preconditioner == SFMM_PRECOND_ILU0)
+                bh->ilu = o.setup_on_device ? factor_ilu_device(bh->oct, bh->near, o.ilu_pivot_tol, o.device)
+                                            : factor_ilu(bh->mesh, bh->oct, bh->near, o.ilu_pivot_tol);
             else if (o.preconditioner == SFMM_PRECOND_BLOCK_JACOBI) bh->ilu = factor_block_jacobi(bh->mesh, bh->oct, bh->near, o.ilu_pivot_tol);
             else if (o.preconditioner == SFMM_PRECOND_POLY) {
                 bh->poly_dinv = edge_block_inverse(bh->oct, bh->near);

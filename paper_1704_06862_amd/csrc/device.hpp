@@ -57,6 +57,8 @@ std::unique_ptr<DeviceBody> make_device_body(const BodyHost &h, int precision, i
 // The near-field matrix of fill_near computed on the device (one thread per
 // stored edge pair) and copied back to the host.
 NearMatrix fill_near_device(const Mesh &m, const Octree &o, int form, int device);
+// factor_ilu on the device (the same block factorisation and folded form).
+IluFactors factor_ilu_device(const Octree &o, const NearMatrix &Z, double pivot_tol, int device);
 
 // HIP helpers used by the C ABI for host <-> device staging.
 void *device_alloc(size_t bytes);

@@ -49,7 +49,7 @@ class sfmm_options(ctypes.Structure):
                 ("poly_degree", ctypes.c_int32), ("graphs", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("kernel_plan", ctypes.c_int32), ("formulation", ctypes.c_int32), ("quad_points", ctypes.c_int32),
                 ("solver", ctypes.c_int32), ("ilu_pivot_tol", ctypes.c_double),
-                ("near_fill_on_device", ctypes.c_int32)]
+                ("setup_on_device", ctypes.c_int32)]
 
 
 class sfmm_solve_info(ctypes.Structure):
@@ -145,20 +145,25 @@ def _ptr(a):
     raise TypeError(type(a))
 
 
+def _override(o, overrides):
+    names = {f[0] for f in type(o)._fields_}
+    for k, v in overrides.items():
+        if k not in names:
+            raise TypeError(f"unknown option {k!r} for {type(o).__name__}")
+        setattr(o, k, v)
+    return o
+
+
 def sfmm_default_options(**overrides):
     o = sfmm_options()
     lib().sfmm_default_options(ctypes.byref(o))
-    for k, v in overrides.items():
-        setattr(o, k, v)
-    return o
+    return _override(o, overrides)
 
 
 def sfmm_guess_default_options(**overrides):
     o = sfmm_guess_options()
     lib().sfmm_guess_default_options(ctypes.byref(o))
-    for k, v in overrides.items():
-        setattr(o, k, v)
-    return o
+    return _override(o, overrides)
 
 
 def sfmm_mlp_train(sizes, params, X, Y, steps=0, lr=1e-3, device=0):

@@ -1,4 +1,4 @@
-"""The near-field fill on the device (sfmm_options.near_fill_on_device, the
+"""The near-field fill on the device (sfmm_options.setup_on_device, the
 default for device contexts) against the host fill and the oracle: the same FP64 integrals, so the rows
 agree to rounding (1e-12 of the largest entry) for PMCHWT, JMCFIE and CNF, on
 one interface, two interfaces with a lossy core, and junction edges; and the
@@ -31,10 +31,10 @@ def test_device_near_fill_matches_host_and_oracle(name, form):
     test = np.unique(np.concatenate([rng.choice(m.n_edges, 12, replace=False),
                                      np.nonzero(m.side_tri[:, 2] >= 0)[0][::8]]))
     print("setup", name, "formulation", form, flush=True)
-    with sfmm.Context([b], near_fill_on_device=0, finest_box=box, precision=2, formulation=form) as ch:
+    with sfmm.Context([b], setup_on_device=0, finest_box=box, precision=2, formulation=form) as ch:
         rows_h = ch.sfmm_near_rows(test)
         levels = ch.sfmm_describe()["levels"]
-    with sfmm.Context([b], finest_box=box, precision=2, formulation=form, near_fill_on_device=1) as cd:
+    with sfmm.Context([b], finest_box=box, precision=2, formulation=form, setup_on_device=1) as cd:
         rows_d = cd.sfmm_near_rows(test)
     scale = np.abs(rows_h).max()
     assert np.abs(rows_d - rows_h).max() < 1e-12 * scale
@@ -53,7 +53,7 @@ def test_solve_on_a_device_filled_context():
     rhs = None
     out = []
     for dev in (0, 1):
-        with sfmm.Context([b], near_fill_on_device=dev, **opts) as ctx:
+        with sfmm.Context([b], setup_on_device=dev, **opts) as ctx:
             n = ctx.sfmm_num_unknowns()
             if rhs is None:
                 rhs = ctx.sfmm_planewave_rhs(np.zeros((1, 2)), np.zeros((1, n), dtype=complex))
@@ -62,3 +62,34 @@ def test_solve_on_a_device_filled_context():
             out.append((x, info["iterations"]))
     assert out[0][1] == out[1][1]
     assert np.linalg.norm(out[0][0] - out[1][0]) < 1e-10 * np.linalg.norm(out[0][0])
+
+
+@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("name", ["sphere", "coated", "junction"])
+def test_device_ilu_factorisation_matches_host(name, form):
+    # ILU(0) factored on the device (one launch per colour) and on the host:
+    # the FP64 preconditioner applications agree to rounding
+    from workloads import random_complex_vector
+    make, box = BODIES[name]
+    b = make()
+    x = None
+    out = []
+    for dev in (0, 1):
+        with sfmm.Context([b], setup_on_device=dev, finest_box=box, precision=2, formulation=form,
+                          preconditioner=sfmm.PRECOND_ILU0) as ctx:
+            n = ctx.sfmm_num_unknowns()
+            if x is None:
+                x = random_complex_vector(n, 2, seed=23)
+            out.append(ctx.sfmm_precond(x, np.zeros_like(x)))
+    err = np.linalg.norm(out[1] - out[0]) / np.linalg.norm(out[0])
+    print(name, form, "device vs host ILU(0) application", err)
+    assert err < 1e-10
+
+
+def test_device_ilu_reports_a_zero_pivot():
+    # every pivot is at most its block's largest entry, so a tolerance above
+    # 1 turns the first one into a breakdown
+    b = sphere_body(0.3, 4.0, 1)
+    with pytest.raises(sfmm.SfmmError) as e:
+        sfmm.Context([b], setup_on_device=1, preconditioner=sfmm.PRECOND_ILU0, ilu_pivot_tol=2.0)
+    assert e.value.status == 6

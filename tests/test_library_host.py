@@ -272,7 +272,13 @@ def test_combined_formulation_near_rows_match_oracle(form, body):
 
 def test_device_near_fill_needs_a_device():
     b = sphere_body(0.3, 4.0, 1)
-    assert _status(lambda: sfmm.Context([b], device=-1, near_fill_on_device=1)) == 1
-    assert _status(lambda: sfmm.Context([b], device=-1, near_fill_on_device=2)) == 1
-    with sfmm.Context([b], device=-1, near_fill_on_device=-1):
+    assert _status(lambda: sfmm.Context([b], device=-1, setup_on_device=1)) == 1
+    assert _status(lambda: sfmm.Context([b], device=-1, setup_on_device=2)) == 1
+    with sfmm.Context([b], device=-1, setup_on_device=-1):
         pass
+
+
+def test_unknown_option_names_are_refused():
+    b = sphere_body(0.3, 4.0, 1)
+    with pytest.raises(TypeError):
+        sfmm.Context([b], device=-1, no_such_option=1)
