@@ -282,11 +282,42 @@ class DeviceBodyT final : public DeviceBody {
         for (void *p : allocs_) device_free(p);
         if (ev0_) (void)hipEventDestroy(ev0_);
         if (ev1_) (void)hipEventDestroy(ev1_);
+        if (pin_) (void)hipHostFree(pin_);
         for (auto &e : evs_)
             if (e) (void)hipEventDestroy(e);
     }
 
-    void set_stream(void *s) override { stream_ = s ? (hipStream_t)s : own_stream_; }
+    void set_stream(void *s) override {
+        const hipStream_t next = s ? (hipStream_t)s : own_stream_;
+        if (next != stream_ && pin_off_ > 0 && stream_) {
+            // the staging arena may still feed copies on the old stream
+            HIPCHK(hipStreamSynchronize(stream_));
+            pin_off_ = 0;
+        }
+        stream_ = next;
+    }
+
+    // Host -> device copy of a small host array (Krylov coefficients, active
+    // lists) through a pinned staging arena, so the copy runs asynchronously
+    // in stream order and the caller's array may change or go away as soon
+    // as this returns.  The arena is reused from its start only after the
+    // stream has drained.
+    void stage_h2d(void *dst, const void *src, size_t bytes) {
+        const size_t need = (bytes + 255) & ~(size_t)255;
+        if (pin_off_ + need > pin_cap_) {
+            HIPCHK(hipStreamSynchronize(stream_));
+            pin_off_ = 0;
+            if (need > pin_cap_) {
+                if (pin_) HIPCHK(hipHostFree(pin_));
+                pin_ = nullptr;
+                pin_cap_ = std::max<size_t>(need, (size_t)1 << 20);
+                HIPCHK(hipHostMalloc((void **)&pin_, pin_cap_, hipHostMallocDefault));
+            }
+        }
+        std::memcpy(pin_ + pin_off_, src, bytes);
+        HIPCHK(hipMemcpyAsync(dst, pin_ + pin_off_, bytes, hipMemcpyHostToDevice, stream_));
+        pin_off_ += need;
+    }
     void *stream() const override { return stream_; }
     void stream_synchronize() override { HIPCHK(hipStreamSynchronize(stream_)); }
 
@@ -602,14 +633,64 @@ class DeviceBodyT final : public DeviceBody {
                 return;
             }
         }
+        launch_aggregate(agg(G), AggRegion<T>{}, R, x);
+    }
+    AggRegion<T> agg(const Reg &G) const {
+        return AggRegion<T>{G.K[f_], G.nbf, G.edge_ptr, G.edge_pos, G.edge_sign, G.tx, G.et, G.S[f_]};
+    }
+    void launch_aggregate(const AggRegion<T> &a, const AggRegion<T> &b, int R, const cx<T> *x) {
+        const int nwg = a.nbf + b.nbf;
+        if (nwg <= 0) return;
         const int ech = std::max(1, 2048 / R);
-        const int bs = (int)std::min<int64_t>(1024, (((int64_t)G.K[f] * R + 63) / 64) * 64);
+        const int kmax = std::max(a.K, b.nbf > 0 ? b.K : 0);
+        const int bs = (int)std::min<int64_t>(1024, (((int64_t)kmax * R + 63) / 64) * 64);
         const size_t shm = (size_t)2 * ech * R * sizeof(cx<T>);
-        k_aggregate<T><<<G.nbf, bs, shm, stream_>>>(G.K[f], R, ech, G.edge_ptr, G.edge_pos, G.edge_sign, G.tx, G.et, x,
-                                                   G.S[f]);
+        k_aggregate<T><<<nwg, bs, shm, stream_>>>(a, b, R, ech, x);
         LAUNCHCHK();
     }
+    // Aggregation of every region: with the vector kernel, two regions per
+    // launch (the larger-K region first).
+    void aggregate_all(int R, const cx<T> *x) {
+        bool mma = false;
+        if constexpr (std::is_same<T, float>::value) mma = plan_.agg_mma && R >= MMA_MIN_R;
+        if (mma) {
+            for (Reg &G : regs_) aggregate_region(G, R, x);
+            return;
+        }
+        for (size_t i = 0; i < regs_.size(); i += 2) {
+            AggRegion<T> a = agg(regs_[i]), b = i + 1 < regs_.size() ? agg(regs_[i + 1]) : AggRegion<T>{};
+            if (b.nbf > 0 && b.K > a.K) std::swap(a, b);
+            launch_aggregate(a, b, R, x);
+        }
+    }
 
+    Rcv1Region<T> rcv1(const Reg &G) const {
+        Rcv1Region<T> r{};
+        r.ne = G.ne;
+        r.K = G.K[f_];
+        r.nwaves = (G.ne + 7) / 8;
+        r.edge_box = G.edge_box;
+        r.edge_pos = G.edge_pos;
+        r.edge_sign = G.edge_sign;
+        r.tab = G.lossy ? G.rx : G.tx;
+        r.nx = G.nx;
+        r.conj = G.lossy ? 0 : 1;
+        r.inv_et = G.inv_et;
+        r.G = G.G[f_];
+        return r;
+    }
+    void launch_receive1(const Rcv1Region<T> &a, cx<T> *y) {
+        if (a.nwaves <= 0) return;
+        const unsigned grid = nblocks(a.nwaves, WAVES);
+        if (gen_) k_receive1<T, true><<<grid, WG, 0, stream_>>>(a, tang_.x, y);
+        else k_receive1<T, false><<<grid, WG, 0, stream_>>>(a, tang_.x, y);
+        LAUNCHCHK();
+    }
+    // Receive of every region, one launch each: they add into the same
+    // entries of y.
+    void receive_all(int R, cx<T> *y) {
+        for (Reg &G : regs_) receive_region(G, R, y);
+    }
     void receive_region(Reg &G, int R, cx<T> *y) {
         const int f = f_;
         if constexpr (std::is_same<T, float>::value) {
@@ -620,20 +701,7 @@ class DeviceBodyT final : public DeviceBody {
         }
         const T tg = tang_.x;
         if (R == 1 && G.K[f] % 2 == 0) {
-            const unsigned grid = nblocks(G.ne, 8 * WAVES);   // eight edges per wavefront
-            if (!grid) return;
-#define SFMM_RECV1(LO_, N_)                                                                                    \
-    k_receive1<T, LO_, N_><<<grid, WG, 0, stream_>>>(G.ne, G.K[f], G.edge_box, G.edge_pos, G.edge_sign, G.tx, \
-                                                     G.rx, G.nx, G.inv_et, tg, G.G[f], y)
-            if (G.lossy) {
-                if (gen_) SFMM_RECV1(true, true);
-                else SFMM_RECV1(true, false);
-            } else {
-                if (gen_) SFMM_RECV1(false, true);
-                else SFMM_RECV1(false, false);
-            }
-#undef SFMM_RECV1
-            LAUNCHCHK();
+            launch_receive1(rcv1(G), y);
             return;
         }
         const int rt = pick_tile(R, {8, 4, 2, 1}, [](int) { return true; });
@@ -682,7 +750,7 @@ class DeviceBodyT final : public DeviceBody {
         }
         mark(1);
         if (far) {
-            for (Reg &G : regs_) aggregate_region(G, R, x);
+            aggregate_all(R, x);
             if (overlap) {
                 // stage timing keeps the upward pass and the translation apart
                 up_and_translate_overlapped(R, near_joined ? x : nullptr, y);
@@ -695,7 +763,7 @@ class DeviceBodyT final : public DeviceBody {
             mark(4);
             for (int l = 3; l <= f_; ++l) downward_level(l, R);
             mark(5);
-            for (Reg &G : regs_) receive_region(G, R, y);
+            receive_all(R, y);
         } else {
             mark(2);
             mark(3);
@@ -1340,7 +1408,7 @@ class DeviceBodyT final : public DeviceBody {
     }
 
     void upload_act(const std::vector<int> &act) {
-        HIPCHK(hipMemcpyAsync(dact_, act.data(), sizeof(int) * act.size(), hipMemcpyHostToDevice, stream_));
+        stage_h2d(dact_, act.data(), sizeof(int) * act.size());
     }
 
     void solve(int solver, int n_rhs, const void *b_dev, void *x_dev, const void *x0_dev, int m, int max_iters,
@@ -1369,7 +1437,7 @@ class DeviceBodyT final : public DeviceBody {
         const int N = 2 * ne_;
         std::vector<double2> cc(3 * (size_t)Ra);
         for (size_t i = 0; i < cc.size(); ++i) cc[i] = make_double2(c[i].real(), c[i].imag());
-        HIPCHK(hipMemcpyAsync(dh_, cc.data(), sizeof(double2) * cc.size(), hipMemcpyHostToDevice, stream_));
+        stage_h2d(dh_, cc.data(), sizeof(double2) * cc.size());
         k_blin3<<<dim3(nblocks(N), Ra), WG, 0, stream_>>>(dh_, dact_, N, N, x, y, z, out);
         LAUNCHCHK();
     }
@@ -1718,7 +1786,7 @@ class DeviceBodyT final : public DeviceBody {
                 act = act2;
                 Ra = (int)act.size();
                 upload_act(act);
-                HIPCHK(hipMemcpyAsync(dscal_, inv_beta.data(), sizeof(double) * Ra, hipMemcpyHostToDevice, stream_));
+                stage_h2d(dscal_, inv_beta.data(), sizeof(double) * Ra);
                 k_bscale<<<dim3(nblocks(N), Ra), WG, 0, stream_>>>(dscal_, dact_, N, N, V0);
                 LAUNCHCHK();
                 std::vector<cd> H((size_t)Ra * (m + 1) * m, 0.0), g((size_t)Ra * (m + 1), 0.0), sn((size_t)Ra * m);
@@ -1788,7 +1856,7 @@ class DeviceBodyT final : public DeviceBody {
                             if (est <= tol || its[act[a]] >= max_iters || breakdown) done[a] = 1;
                         }
                     }
-                    HIPCHK(hipMemcpyAsync(dscal_, sc.data(), sizeof(double) * Ra, hipMemcpyHostToDevice, stream_));
+                    stage_h2d(dscal_, sc.data(), sizeof(double) * Ra);
                     k_bscale<<<dim3(nblocks(N), Ra), WG, 0, stream_>>>(dscal_, dact_, N, N, W);
                     LAUNCHCHK();
                     if (std::all_of(done.begin(), done.end(), [](char d) { return d != 0; })) break;
@@ -1806,8 +1874,8 @@ class DeviceBodyT final : public DeviceBody {
                     for (int i = 0; i < n; ++i) ys[(size_t)a * m + i] = make_double2(y[i].real(), y[i].imag());
                     ++restarts[act[a]];
                 }
-                HIPCHK(hipMemcpyAsync(dh_, ys.data(), sizeof(double2) * ys.size(), hipMemcpyHostToDevice, stream_));
-                HIPCHK(hipMemcpyAsync(dcnt_, cnt.data(), sizeof(int) * Ra, hipMemcpyHostToDevice, stream_));
+                stage_h2d(dh_, ys.data(), sizeof(double2) * ys.size());
+                stage_h2d(dcnt_, cnt.data(), sizeof(int) * Ra);
                 k_bupdate<<<dim3(nblocks(N), Ra), WG, 0, stream_>>>(kZ_, ldj, N, m, dcnt_, dact_, N, dh_, kx_);
                 LAUNCHCHK();
             }
@@ -2052,6 +2120,8 @@ class DeviceBodyT final : public DeviceBody {
     int64_t *near_val_ptr_ = nullptr;
     cx<T> *nA_ = nullptr, *nB_ = nullptr, *nC_ = nullptr;
     cx<T> *nD_ = nullptr;          // H-row J coefficient of the general block (JMCFIE / CNF)
+    char *pin_ = nullptr;          // pinned staging arena of stage_h2d
+    size_t pin_cap_ = 0, pin_off_ = 0;
     bool gen_ = false;             // JMCFIE or CNF: general near blocks, rotated-test receive
     cx<T> tang_{-1, 0};            // weight of the tangential parts (-1 JMCFIE, 0 CNF)
     // matrix-core tiles of the near matrix (FP32 / bf16-split modes)

@@ -328,14 +328,39 @@ __global__ void __launch_bounds__(RWG) k_ilu(int R, int box0, const int *__restr
 // fastest, so the R threads of a direction share each pattern load; the
 // box's scaled excitations are staged in LDS in chunks of ech edges.
 template <typename T>
-__global__ void __launch_bounds__(1024) k_aggregate(int K, int R, int ech, const int *__restrict__ edge_ptr,
-                                                    const int *__restrict__ edge_pos,
-                                                    const int *__restrict__ edge_sign, const cx<T> *__restrict__ tx,
-                                                    cx<T> et, const cx<T> *__restrict__ x, cx<T> *__restrict__ S) {
+struct AggRegion {
+    int K, nbf;                          // directions, region boxes
+    const int *edge_ptr, *edge_pos, *edge_sign;
+    const cx<T> *tx;
+    cx<T> et;
+    cx<T> *S;
+};
+
+template <typename T>
+__device__ __forceinline__ void aggregate_box(int K, int R, int ech, const int *__restrict__ edge_ptr,
+                                              const int *__restrict__ edge_pos, const int *__restrict__ edge_sign,
+                                              const cx<T> *__restrict__ tx, cx<T> et, const cx<T> *__restrict__ x,
+                                              cx<T> *__restrict__ S, int b);
+
+// Up to two regions per launch: workgroups 0 .. r0.nbf - 1 take region r0's
+// boxes, the next r1.nbf those of r1.
+template <typename T>
+__global__ void __launch_bounds__(1024) k_aggregate(const AggRegion<T> r0, const AggRegion<T> r1, int R, int ech,
+                                                    const cx<T> *__restrict__ x) {
+    const bool second = (int)blockIdx.x >= r0.nbf;
+    const AggRegion<T> &rg = second ? r1 : r0;
+    const int b = second ? (int)blockIdx.x - r0.nbf : (int)blockIdx.x;
+    aggregate_box<T>(rg.K, R, ech, rg.edge_ptr, rg.edge_pos, rg.edge_sign, rg.tx, rg.et, x, rg.S, b);
+}
+
+template <typename T>
+__device__ __forceinline__ void aggregate_box(int K, int R, int ech, const int *__restrict__ edge_ptr,
+                                              const int *__restrict__ edge_pos, const int *__restrict__ edge_sign,
+                                              const cx<T> *__restrict__ tx, cx<T> et, const cx<T> *__restrict__ x,
+                                              cx<T> *__restrict__ S, int b) {
     extern __shared__ unsigned char lds_raw[];
     cx<T> *js = reinterpret_cast<cx<T> *>(lds_raw);      // [ech][R]
     cx<T> *ms = js + (size_t)ech * R;
-    const int b = blockIdx.x;
     const int e0 = edge_ptr[b], e1 = edge_ptr[b + 1];
     const int KR = K * R;
     for (int q0 = 0; q0 < KR; q0 += blockDim.x) {
@@ -1422,25 +1447,36 @@ __global__ void __launch_bounds__(WG) k_receive(int K, int R, const int *__restr
 // the edge's box read through the cache, and the eight partial sums of an edge
 // combined by three shuffles.  K is even (K = 2 (L + 1)^2), so the pairs
 // never straddle the theta/phi halves.
-template <typename T, bool LOSSY, bool NRM>
-__global__ void __launch_bounds__(WG) k_receive1(int ne, int K, const int *__restrict__ edge_box,
-                                                 const int *__restrict__ edge_pos, const int *__restrict__ edge_sign,
-                                                 const cx<T> *__restrict__ tx, const cx<T> *__restrict__ rx,
-                                                 const cx<T> *__restrict__ nx, cx<T> inv_et, T tang,
-                                                 const cx<T> *__restrict__ G, cx<T> *__restrict__ y) {
+template <typename T>
+struct Rcv1Region {
+    int ne, K, nwaves;                   // region edge list entries, directions, ceil(ne / 8)
+    const int *edge_box, *edge_pos, *edge_sign;
+    const cx<T> *tab, *nx;               // receive table; rotated-test table (NRM)
+    int conj;                            // 1: the tables are in transmit form (real k)
+    cx<T> inv_et;
+    const cx<T> *G;
+};
+
+// One region per launch: the regions' receives add into the same entries
+// of y, so they stay ordered launches.
+template <typename T, bool NRM>
+__global__ void __launch_bounds__(WG) k_receive1(const Rcv1Region<T> rg, T tang, cx<T> *__restrict__ y) {
     const int lane = threadIdx.x & 63;
     const int sub = lane & 7;
-    const int ie = (blockIdx.x * WAVES + (threadIdx.x >> 6)) * 8 + (lane >> 3);
-    const cx<T> *tab = LOSSY ? rx : tx;
+    const int w = blockIdx.x * WAVES + (threadIdx.x >> 6);
+    if (w >= rg.nwaves) return;          // uniform over the wavefront
+    const int ne = rg.ne, K = rg.K;
+    const int ie = w * 8 + (lane >> 3);
     cx<T> aE = {0, 0}, aH = {0, 0}, nE = {0, 0}, nH = {0, 0};
     if (ie < ne) {
-        const cx<T> *Rp = tab + (size_t)ie * 2 * K;
-        const cx<T> *Np = NRM ? nx + (size_t)ie * 2 * K : nullptr;
-        const cx<T> *g = G + (size_t)edge_box[ie] * 2 * K;
+        const cx<T> *Rp = rg.tab + (size_t)ie * 2 * K;
+        const cx<T> *Np = NRM ? rg.nx + (size_t)ie * 2 * K : nullptr;
+        const cx<T> *g = rg.G + (size_t)rg.edge_box[ie] * 2 * K;
+        const bool cj = rg.conj != 0;
 #pragma unroll 3
         for (int k = 2 * sub; k < K; k += 16) {
             cx<T> rt0 = Rp[k], rt1 = Rp[k + 1], rp0 = Rp[K + k], rp1 = Rp[K + k + 1];
-            if (!LOSSY) {
+            if (cj) {
                 rt0 = cconj(rt0);
                 rt1 = cconj(rt1);
                 rp0 = cconj(rp0);
@@ -1457,7 +1493,7 @@ __global__ void __launch_bounds__(WG) k_receive1(int ne, int K, const int *__res
             cfma(aH, rp1, gt1);
             if (NRM) {
                 cx<T> nt0 = Np[k], nt1 = Np[k + 1], np0 = Np[K + k], np1 = Np[K + k + 1];
-                if (!LOSSY) {
+                if (cj) {
                     nt0 = cconj(nt0);
                     nt1 = cconj(nt1);
                     np0 = cconj(np0);
@@ -1488,8 +1524,8 @@ __global__ void __launch_bounds__(WG) k_receive1(int ne, int K, const int *__res
         }
     }
     if (ie < ne && sub == 0) {
-        const int p = edge_pos[ie];
-        receive_store<T, NRM>(y, 2 * p, 2 * p + 1, (T)edge_sign[ie], aE, aH, nE, nH, inv_et, tang);
+        const int p = rg.edge_pos[ie];
+        receive_store<T, NRM>(y, 2 * p, 2 * p + 1, (T)rg.edge_sign[ie], aE, aH, nE, nH, rg.inv_et, tang);
     }
 }
 
