@@ -131,9 +131,8 @@ typedef struct {
                                  conditions do not hold (batch size, LDS) falls back to
                                  the vector kernel.  For tests and measurement.         */
     int32_t formulation;      /* SFMM_FORM_*: integral equation; 0 = PMCHWT.  JMCFIE and
-                                 CNF run the near-field and aggregation/receive products
-                                 on the vector kernels (kernel_plan bits 1, 2 and 8 are
-                                 ignored for them)                                        */
+                                 CNF use the same kernels with a fourth near-field plane
+                                 and a second receive table                               */
     int32_t quad_points;      /* points of the triangle rule for the outer and regular
                                  inner integrals; 0 = 7 (degree 5), the only rule built;
                                  other values: SFMM_E_UNSUPPORTED                         */

@@ -980,7 +980,7 @@ class DeviceBodyT final : public DeviceBody {
                (int)regs_.size() * (f_ - 1) <= TRANS_MAXJOB;
     }
     bool near_join_ok(int R) const {
-        return R == 1 && plan_.near_join && near_ngrp_ > 0 && !gen_ &&
+        return R == 1 && plan_.near_join && near_ngrp_ > 0 &&
                (size_t)max_ncol_ * 2 * sizeof(cx<T>) <= LDS_LIMIT;
     }
     // x != nullptr: the near product y = Z_near x joins the launch
@@ -1023,12 +1023,13 @@ class DeviceBodyT final : public DeviceBody {
         if (x) {
             NearRows<T> nr{};
             nr.a = NearArgs<T>{R,  bstart_, near_col_ptr_, near_cols_, near_val_ptr_, nA_,    nB_,
-                               nC_, x,       y,             nullptr,    cx<T>{0, 0},   1,      nullptr};
+                               nC_, x,       y,             nullptr,    cx<T>{0, 0},   1,      nullptr, nD_};
             nr.grp = near_grp_;
             nr.ngrp = near_ngrp_;
             const size_t sh2 = std::max((size_t)8 * 2 * 64 * sizeof(cx<T>), (size_t)max_ncol_ * 2 * sizeof(cx<T>));
             const unsigned g2 = 8u * (unsigned)((t2.nblk + 7) / 8 + (nr.ngrp + 7) / 8);
-            k_near_up_phi1_translate1<T, true><<<g2, WG, sh2, stream_>>>(JobList<UpPhiJob<T>>{}, t2, nr);
+            if (gen_) k_near_up_phi1_translate1<T, true, true><<<g2, WG, sh2, stream_>>>(JobList<UpPhiJob<T>>{}, t2, nr);
+            else k_near_up_phi1_translate1<T, true><<<g2, WG, sh2, stream_>>>(JobList<UpPhiJob<T>>{}, t2, nr);
             LAUNCHCHK();
         } else if (t2.nblk > 0) {
             k_translate_grp1<T><<<(unsigned)((t2.nblk + 7) / 8 * 8), WG, 0, stream_>>>(t2);

@@ -1231,8 +1231,8 @@ struct NearRows {
 // so the few workgroups of a small translation level start first and the
 // near product's fill the rest of the chip.  Each kind keeps its own
 // numbering; an empty kind takes no runs.  NEAR = false compiles the near
-// kind out.
-template <typename T, bool NEAR>
+// kind out; GEN: the near rows are general blocks [[A, -B], [D, C]].
+template <typename T, bool NEAR, bool GEN = false>
 __global__ void __launch_bounds__(WG) k_near_up_phi1_translate1(const JobList<UpPhiJob<T>> jl,
                                                                 const TransGroups<T> tg, const NearRows<T> nr) {
     extern __shared__ unsigned char lds_raw[];
@@ -1243,8 +1243,8 @@ __global__ void __launch_bounds__(WG) k_near_up_phi1_translate1(const JobList<Up
     if (NEAR && run >= n8a + n8b) {
         const int g = 8 * (run - n8a - n8b) + within;
         if (g < nr.ngrp)
-            near_block<T, 1, true, false, WAVES>(nr.a, nr.grp[2 * g], nr.grp[2 * g + 1], 0,
-                                                 reinterpret_cast<cx<T> *>(lds_raw));
+            near_block<T, 1, true, false, WAVES, GEN>(nr.a, nr.grp[2 * g], nr.grp[2 * g + 1], 0,
+                                                      reinterpret_cast<cx<T> *>(lds_raw));
         return;
     }
     const int both = n8a < n8b ? n8a : n8b;
