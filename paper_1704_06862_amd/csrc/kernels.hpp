@@ -823,7 +823,9 @@ __device__ __forceinline__ void up_phi1_block(const JobList<UpPhiJob<T>> &jl, in
         const cx<T> *g = a.tmp + (((int64_t)c * 2 + comp) * nth_p + I) * nph_c;
         cx<T> v0 = {0, 0}, v1 = {0, 0};
         for (int j = 0; j < nph_c; ++j) {
-            const T d0 = Ds[j * nph_p + J], d1 = Ds[j * nph_p + J + 1];
+            // one paired LDS read of (J, J + 1): J and nph_p are even
+            const cx<T> dd = *reinterpret_cast<const cx<T> *>(Ds + j * nph_p + J);
+            const T d0 = dd.x, d1 = dd.y;
             const cx<T> t = g[j];
             v0.x += d0 * t.x;
             v0.y += d0 * t.y;

@@ -200,3 +200,31 @@ def test_stacked_cylinder_82080_unknowns_under_jmcfie():
     print("stacked cylinder jmcfie iterations", its, flush=True)
     assert all(a["converged"] and a["true_residual"] <= 1e-4 for a in info)
     assert max(its) <= 300
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_ellipsoid_batch_body_sampled_oracle_rows(form):
+    # body 20 of the seeded 48-ellipsoid batch (semi-axes 0.785 x 0.538 x
+    # 0.409, eps_r 8.21, 15,360 unknowns) in the batch's tree: 16 seeded rows
+    # of the FP32 product against the oracle's PMCHWT or JMCFIE rows
+    # (measured 4.3e-5 and 8.5e-5)
+    from oracle import mom, rwg
+    from workloads import ellipsoid_batch, random_complex_vector
+
+    b = ellipsoid_batch(48)[20]
+    m = rwg.from_body(b)
+    ne = m.n_edges
+    test = np.sort(np.random.default_rng(5).choice(ne, 16, replace=False))
+    print("oracle rows of ellipsoid 20, formulation", form, flush=True)
+    if form == 0:
+        R1, R2 = mom.pmchwt_rows(m, b.eps_r, b.mu_r, b.frequency, test)
+    else:
+        R1, R2 = mom.combined_rows(m, b.eps_r, b.mu_r, b.frequency, test, True)
+    x = random_complex_vector(2 * ne, 1, seed=7)
+    with sfmm.Context([b], formulation=form, finest_box=0.25, digits=3.0, precision=sfmm.PREC_FP32) as ctx:
+        y = ctx.sfmm_matvec(x, np.zeros_like(x))[0]
+    ref = np.concatenate([R1 @ x[0], R2 @ x[0]])
+    got = np.concatenate([y[test], y[ne + test]])
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print("sampled rows rel err", err)
+    assert err < 1e-3
