@@ -45,14 +45,16 @@ def basis_transforms(mesh: RWGMesh, frequency, r_hat):
     return T
 
 
-def far_field(mesh: RWGMesh, frequency, x, theta, phi):
-    """F(theta, phi) [..., 3] for the scaled unknowns x = [J ; M~] (one RHS)."""
+def far_field(mesh: RWGMesh, frequency, x, theta, phi, T=None):
+    """F(theta, phi) [..., 3] for the scaled unknowns x = [J ; M~] (one RHS);
+    T: basis_transforms of these directions if already computed."""
     k0 = 2 * np.pi * frequency / C0
     ne = mesh.n_edges
     J = x[:ne]
     Mt = x[ne:]
     r, th, ph = spherical_units(np.atleast_1d(theta), np.atleast_1d(phi))
-    T = basis_transforms(mesh, frequency, r)
+    if T is None:
+        T = basis_transforms(mesh, frequency, r)
     Jh = np.einsum("dnx,n->dx", T, J)
     Mh = np.einsum("dnx,n->dx", T, Mt)
     Jt = Jh - r * np.sum(r * Jh, axis=-1, keepdims=True)
