@@ -216,7 +216,7 @@ def sweep(ctx, ctx_mixed, torch, n_ang, every, plain_stride=1, batched_fp32=True
     x.zero_()
     i_mixed, t_mixed = timed(lambda: ctx_mixed.sfmm_solve(b, x))
 
-    tr = np.arange(0, n_ang, every)
+    tr = np.union1d(np.arange(0, n_ang, every), [n_ang - 1])   # both ends of the sweep: no extrapolation
     te = np.setdiff1d(np.arange(n_ang), tr)
     tr_t = torch.from_numpy(tr).to("cuda")
     te_t = torch.from_numpy(te).to("cuda")
@@ -236,7 +236,17 @@ def sweep(ctx, ctx_mixed, torch, n_ang, every, plain_stride=1, batched_fp32=True
         t_fit = time.perf_counter() - t_fit
         x_te = torch.zeros_like(b_te)
         i_te = ctx_mixed.sfmm_solve(b_te, x_te, x0=x0)
-        return i_tr, i_te, loss, t_fit
+        return i_tr, i_te, loss, t_fit, x_tr
+
+    def span_in_sweep(x_tr):
+        # the same protocol without the network: POD basis of the training
+        # solutions (fit with no Adam steps), minimal-residual guess in its span
+        ctx_mixed.sfmm_guess_fit(ang[tr], x_tr, epochs=0)
+        b_te = b.index_select(0, te_t).contiguous()
+        x0 = torch.zeros_like(b_te)
+        ctx_mixed.sfmm_span_predict(ang[te], x0)
+        x_te = torch.zeros_like(b_te)
+        return ctx_mixed.sfmm_solve(b_te, x_te, x0=x0)
 
     # a network trained beforehand on a coarse sweep (the mid-points of this
     # sweep's angles, every other one): prediction + one batched solve of all
@@ -274,8 +284,14 @@ def sweep(ctx, ctx_mixed, torch, n_ang, every, plain_stride=1, batched_fp32=True
         i_sp, t_sp = timed(span_baseline)
 
     print("sweep: learned guess inside the sweep", file=sys.stderr, flush=True)
-    (i_tr, i_te, loss, t_fit), t_learn = timed(learned)
-    ok = all(i["converged"] for i in i_plain + i_batch + i_mixed + i_tr + i_te + i_mid + i_am + i_sp)
+    (i_tr, i_te, loss, t_fit, x_tr_done), t_learn = timed(learned)
+    # the library solves in chunks of up to 64 right-hand sides and reports
+    # each chunk's time on its entries
+    t_tr_solve = sum(i_tr[k]["seconds"] for k in range(0, len(i_tr), 64))
+    print("sweep: span projection inside the sweep", file=sys.stderr, flush=True)
+    i_spi, t_spi = timed(lambda: span_in_sweep(x_tr_done))
+    t_spi += t_tr_solve
+    ok = all(i["converged"] for i in i_plain + i_batch + i_mixed + i_tr + i_te + i_mid + i_am + i_sp + i_spi)
     assert len(i_tr) + len(i_te) == n_ang
     ms = lambda t: round(1e3 * t / n_ang, 2)  # noqa: E731
     res_max = max(i["true_residual"] for i in i_plain + i_batch + i_mixed + i_tr + i_te + i_am + i_sp)
@@ -283,15 +299,23 @@ def sweep(ctx, ctx_mixed, torch, n_ang, every, plain_stride=1, batched_fp32=True
         "angles": n_ang, "tol": 1e-4,
         "plain_timed_on": f"{len(plain_idx)} of {n_ang} angles (every {plain_stride}-th), scaled to the sweep",
         "ms_per_angle": {"plain_fp32": ms(t_plain), "batched_bf16split": ms(t_mixed),
-                         "batched_bf16split_learned_in_sweep": ms(t_learn)},
+                         "batched_bf16split_learned_in_sweep": ms(t_learn),
+                         "batched_bf16split_span_projection_in_sweep": ms(t_spi)},
         "speedup_vs_plain": {"batched_bf16split": round(t_plain / t_mixed, 2),
-                             "batched_bf16split_learned_in_sweep": round(t_plain / t_learn, 2)},
+                             "batched_bf16split_learned_in_sweep": round(t_plain / t_learn, 2),
+                             "batched_bf16split_span_projection_in_sweep": round(t_plain / t_spi, 2)},
         "iterations_mean_max": {"plain_fp32": its(i_plain), "batched_bf16split": its(i_mixed),
-                                "in_sweep_training_angles": its(i_tr), "in_sweep_predicted_angles": its(i_te)},
+                                "in_sweep_training_angles": its(i_tr), "in_sweep_predicted_angles": its(i_te),
+                                "span_projection_in_sweep_predicted_angles": its(i_spi)},
         "true_residual_max": res_max,
         "guess_in_sweep": {"trained_on": len(tr), "fit_and_predict_s": round(t_fit, 3), "loss": loss,
                            "initial_residual_median": float(np.median([i["initial_residual"] for i in i_te])),
+                           "initial_residual_max": float(max(i["initial_residual"] for i in i_te)),
                            "used": int(sum(i["guess_used"] for i in i_te))},
+        "span_projection_in_sweep": {
+            "timed_as": "the learned run's training solves + fit without Adam steps + span guess + solve",
+            "initial_residual_median": float(np.median([i["initial_residual"] for i in i_spi])),
+            "initial_residual_max": float(max(i["initial_residual"] for i in i_spi))},
         "all_converged": bool(ok),
     }
     if batched_fp32:

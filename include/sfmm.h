@@ -348,24 +348,34 @@ sfmm_status sfmm_rcs_noalloc(sfmm_ctx *ctx, int32_t body, int32_t n_rhs, const v
  * that maps an incidence to the currents:
  *   POD basis U: the r leading left singular vectors of the n training
  *     solutions x (Gram matrix on the device, Hermitian Jacobi on the host);
- *   features: cos/sin(m theta), cos/sin(m phi) for m = 1..M and
- *     Re/Im(U^H b) / ||b||, b the plane-wave right-hand side of the angle;
- *   network: two tanh hidden layers and a linear output of the standardised
- *     Re/Im(U^H x) / ||b||; mean-squared error, Adam with a cosine decay;
- *     GEMM operands rounded to bfloat16 with FP32 accumulation, FP32 weights.
+ *   features: cos/sin(m theta), cos/sin(m phi) for m = 1..M, then the
+ *     radiation pattern of the right-hand side b read as surface currents
+ *     (its far field, as in the RCS of eqs. 27-29, at n_theta x n_phi
+ *     directions: theta at band midpoints of [0, pi], phi uniform in
+ *     [0, 2 pi); Re/Im of the theta and phi components) / ||b||, scaled by
+ *     one scalar;
+ *   network: y = Ws^T z_p + MLP(z) / s_r for the scaled Re/Im(U^H x) / ||b||:
+ *     a linear path from the pattern features, fitted first as the
+ *     minimum-norm least-squares map (FP64), and two tanh hidden layers
+ *     trained by Adam (cosine step decay) on what the linear path leaves,
+ *     scaled to unit RMS; MLP GEMMs on the matrix cores with bf16-split
+ *     operands and FP32 accumulation, FP32 weights.
  * sfmm_guess_predict returns x0 = U c ||b|| for new incidences, to be passed
  * to sfmm_solve, which keeps it only if it lowers the true residual.
  * angles [n][2] (theta, phi) and pol [n] follow sfmm_planewave_rhs; x and x0
  * are [n][2E] complex in boundary order, on the device if on_device.
- * fit: 1 <= n <= 512; *final_loss (may be NULL) receives the training loss.
+ * fit: 1 <= n <= 512; *final_loss (may be NULL) receives the MLP's training
+ * loss on its unit-RMS targets (0.5/n sum of squares; r at the start).
  * Errors: SFMM_E_INVALID_ARG (sizes, options, predict before fit). */
 typedef struct {
     int32_t rank;       /* POD basis size r (clamped to n and to the resolved rank) */
     int32_t harmonics;  /* M angle harmonics                                        */
-    int32_t hidden;     /* width of both tanh hidden layers                         */
-    int32_t epochs;     /* full-batch Adam steps                                    */
+    int32_t hidden;     /* width of both tanh hidden layers (1..4096)               */
+    int32_t epochs;     /* full-batch Adam steps (0: the linear path alone)         */
     double lr;          /* peak Adam step size                                      */
     uint64_t seed;      /* SplitMix64 seed of the uniform weight initialisation     */
+    int32_t n_theta;    /* pattern directions: theta bands (n_theta * n_phi <= 4096) */
+    int32_t n_phi;      /*                     phi samples                           */
 } sfmm_guess_options;
 
 void sfmm_guess_default_options(sfmm_guess_options *opt);

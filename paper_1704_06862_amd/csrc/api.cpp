@@ -580,6 +580,8 @@ void sfmm_guess_default_options(sfmm_guess_options *o) {
     o->epochs = d.epochs;
     o->lr = d.lr;
     o->seed = d.seed;
+    o->n_theta = d.n_theta;
+    o->n_phi = d.n_phi;
 }
 
 sfmm_status sfmm_guess_fit(sfmm_ctx *ctx, int32_t body, int32_t n, const double *angles, const double *pol,
@@ -597,6 +599,8 @@ sfmm_status sfmm_guess_fit(sfmm_ctx *ctx, int32_t body, int32_t n, const double 
         g.epochs = go.epochs;
         g.lr = go.lr;
         g.seed = go.seed;
+        g.n_theta = go.n_theta;
+        g.n_phi = go.n_phi;
         const int N = 2 * ctx->bodies[body]->mesh.ne;
         const size_t bytes = (size_t)n * N * 2 * sizeof(double);
         Staged db(bytes);
@@ -609,7 +613,9 @@ sfmm_status sfmm_guess_fit(sfmm_ctx *ctx, int32_t body, int32_t n, const double 
             xd = dx->p;
         }
         if (ctx->guess.size() < ctx->bodies.size()) ctx->guess.resize(ctx->bodies.size());
-        auto gs = std::make_unique<Guess>(N, d.stream());
+        DeviceBody *dp = &d;   // the context's device bodies outlive its guesses
+        auto gs = std::make_unique<Guess>(N, d.stream(), [dp](int m, const void *b, int nd, const double *dirs,
+                                                              double *F) { dp->far_pattern(m, b, nd, dirs, F); });
         const double loss = gs->fit(n, angles, db.p, xd, g);
         ctx->guess[body] = std::move(gs);
         if (final_loss) *final_loss = loss;

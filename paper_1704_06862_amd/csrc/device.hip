@@ -1926,12 +1926,24 @@ class DeviceBodyT final : public DeviceBody {
                     double *ds) {
         HIPCHK(hipMemcpyAsync(dd, tp, sizeof(double) * 2 * n_dirs, hipMemcpyHostToDevice, stream_));
         dim3 grid(n_dirs, (n_rhs + RCS_RT - 1) / RCS_RT);
-        k_far_field<<<grid, 256, 0, stream_>>>(ne_, n_rhs, gs0_, gqr_, gqf_, h_.mesh.k0, ETA0, dd,
-                                               (const double2 *)x_dev, ds, n_dirs);
+        k_far_field<false><<<grid, 256, 0, stream_>>>(ne_, n_rhs, gs0_, gqr_, gqf_, h_.mesh.k0, ETA0, dd,
+                                                      (const double2 *)x_dev, ds, n_dirs);
         LAUNCHCHK();
         HIPCHK(hipMemcpyAsync(sigma, ds, sizeof(double) * 2 * (size_t)n_dirs * n_rhs, hipMemcpyDeviceToHost,
                               stream_));
         HIPCHK(hipStreamSynchronize(stream_));
+    }
+
+    void far_pattern(int n_rhs, const void *x_dev, int n_dirs, const double *dirs_dev, double *F_dev) override {
+        if (n_rhs < 1 || n_dirs < 1 || n_dirs > 65535) throw Error(SFMM_E_INVALID_ARG, "far pattern: bad sizes");
+        for (int c0 = 0; c0 < n_rhs; c0 += 65535 * RCS_RT) {   // grid.y limit
+            const int c = std::min(n_rhs - c0, 65535 * RCS_RT);
+            dim3 grid(n_dirs, (c + RCS_RT - 1) / RCS_RT);
+            k_far_field<true><<<grid, 256, 0, stream_>>>(ne_, c, gs0_, gqr_, gqf_, h_.mesh.k0, ETA0, dirs_dev,
+                                                         (const double2 *)x_dev + (int64_t)c0 * 2 * ne_,
+                                                         F_dev + (int64_t)c0 * n_dirs * 4, n_dirs);
+            LAUNCHCHK();
+        }
     }
 
     void rcs(int n_rhs, const void *x_dev, int n_dirs, const double *tp, double *sigma) override {

@@ -41,6 +41,10 @@ class DeviceBody {
     // allocated buffers (n_dirs * (2 + 2 n_rhs) <= noalloc_scratch_doubles())
     virtual void rcs_noalloc(int n_rhs, const void *x_dev, int n_dirs, const double *theta_phi_host,
                              double *sigma_host) = 0;
+    // the far field of x read as surface currents (FP64, on the device):
+    // F_dev [n_rhs][n_dirs][4] = Re/Im of theta.F, Re/Im of phi.F at the
+    // directions dirs_dev [n_dirs][2] (theta, phi)
+    virtual void far_pattern(int n_rhs, const void *x_dev, int n_dirs, const double *dirs_dev, double *F_dev) = 0;
     virtual void set_stream(void *stream) = 0;
     // the stream all of this body's work is ordered on (the context's stream,
     // or a stream of the body's own when the context has none)

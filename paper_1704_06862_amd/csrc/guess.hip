@@ -1,17 +1,22 @@
 // Learned initial guess for GMRES (an addition to the paper's method): a
-// small MLP trained on the device, with hand-written kernels, on currents the
+// network trained on the device, with hand-written kernels, on currents the
 // solver produced for other incidence angles.
 //
 //   POD basis   U = first r left singular vectors of X = [x_1 .. x_n]
 //               (Gram matrix X^H X on the device, Hermitian Jacobi
 //               eigen-decomposition on the host, U = X V Sigma^-1)
-//   features    [cos m theta, sin m theta, cos m phi, sin m phi]_{m=1..M},
-//               Re/Im (U^H b) / ||b||
-//   network     two tanh hidden layers, linear output of Re/Im of the POD
-//               coefficients / ||b||; mean-squared error; Adam
-//   arithmetic  GEMM operands rounded to bfloat16, products and sums in FP32
-//               (exact bf16 x bf16 products, FP32 accumulation), FP32 master
-//               weights and optimizer state
+//   features    the far field of the right-hand side b read as surface
+//               currents, on a coarse theta/phi grid (Re/Im of the theta
+//               and phi components, FP64, divided by ||b|| and scaled by one
+//               scalar), after cos/sin(m theta), cos/sin(m phi), m = 1..M
+//   network     y = Ws^T z_p + MLP(z) / s_r: a linear path from the pattern
+//               features, the minimum-norm least-squares fit of the scaled
+//               POD coefficients (FP64), and two tanh hidden layers trained
+//               by Adam on what the linear path leaves, scaled to unit RMS
+//   arithmetic  MLP GEMMs on the matrix cores with bf16-split operands
+//               (hi + lo, three v_mfma_f32_16x16x32_bf16 per K step, FP32
+//               accumulation), FP32 master weights and optimizer state; the
+//               linear path in FP64
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,39 +38,90 @@ namespace sfmm {
 
 namespace {
 
-constexpr int GT = 16;   // GEMM tile
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// round-to-nearest-even to bfloat16, returned as float
-__device__ __forceinline__ float bf16r(float x) {
-    uint32_t u = __float_as_uint(x);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return __uint_as_float(u & 0xffff0000u);
-}
-
-// C[i][j] (=|+=) act( sum_k bf(A(i,k)) bf(B(k,j)) + bias[j] ),
-// A(i,k) = A[i*a0 + k*a1], B(k,j) = B[k*b0 + j*b1], C row-major with ldc.
-__global__ void __launch_bounds__(GT *GT) k_gemm(int M, int N, int K, const float *__restrict__ A, int64_t a0,
+// C[i][j] = act( sum_k A(i,k) B(k,j) + bias[j] ), A(i,k) = A[i*a0 + k*a1],
+// B(k,j) = B[k*b0 + j*b1], C row-major with ldc; FP32 operands split into
+// bf16 hi + lo, hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16.  One wave
+// per 32 x 32 block of C (2 x 2 MFMA tiles).  Lane l of a 16 x 16 tile holds
+// A row l % 16 / B column l % 16 at K indices 8 (l / 16) .. + 7 and receives
+// D rows 4 (l / 16) .. + 3 of column l % 16.
+__global__ void __launch_bounds__(64) k_gemm_mma(int M, int N, int K, const float *__restrict__ A, int64_t a0,
                                                  int64_t a1, const float *__restrict__ B, int64_t b0, int64_t b1,
                                                  const float *__restrict__ bias, int act, float *__restrict__ C,
                                                  int64_t ldc) {
-    __shared__ float As[GT][GT + 1], Bs[GT][GT + 1];
-    const int ti = threadIdx.x / GT, tj = threadIdx.x % GT;
-    const int i = blockIdx.y * GT + ti, j = blockIdx.x * GT + tj;
-    float acc = 0.f;
-    for (int k0 = 0; k0 < K; k0 += GT) {
+    const int l = threadIdx.x, i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
+    const int lr = l & 15, lk = (l >> 4) * 8;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        bf16x8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int i = i0 + 16 * t + lr, j = j0 + 16 * t + lr;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = k0 + lk + e;
+                const float va = (i < M && k < K) ? A[i * a0 + k * a1] : 0.f;
+                const float vb = (j < N && k < K) ? B[k * b0 + j * b1] : 0.f;
+                const __bf16 ha = (__bf16)va, hb = (__bf16)vb;
+                ah[t][e] = ha;
+                al[t][e] = (__bf16)(va - (float)ha);
+                bh[t][e] = hb;
+                bl[t][e] = (__bf16)(vb - (float)hb);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+            }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int j = j0 + 16 * b + lr;
+            if (j >= N) continue;
+            const float bj = bias ? bias[j] : 0.f;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = i0 + 16 * a + (l >> 4) * 4 + v;
+                if (i >= M) continue;
+                float c = acc[a][b][v] + bj;
+                if (act == 1) c = tanhf(c);
+                C[i * ldc + j] = c;
+            }
+        }
+}
+
+// FP64: C[i][j] = sum_k A(i,k) B(k,j), strides as k_gemm_mma, 16 x 16 tiles
+// through LDS
+constexpr int DT = 16;
+__global__ void __launch_bounds__(DT *DT) k_dgemm(int M, int N, int K, const double *__restrict__ A, int64_t a0,
+                                                  int64_t a1, const double *__restrict__ B, int64_t b0, int64_t b1,
+                                                  double *__restrict__ C, int64_t ldc) {
+    __shared__ double As[DT][DT + 1], Bs[DT][DT + 1];
+    const int ti = threadIdx.x / DT, tj = threadIdx.x % DT;
+    const int i = blockIdx.y * DT + ti, j = blockIdx.x * DT + tj;
+    double acc = 0.0;
+    for (int k0 = 0; k0 < K; k0 += DT) {
         const int ka = k0 + tj, kb = k0 + ti;
-        As[ti][tj] = (i < M && ka < K) ? bf16r(A[i * a0 + ka * a1]) : 0.f;
-        Bs[ti][tj] = (kb < K && j < N) ? bf16r(B[kb * b0 + j * b1]) : 0.f;
+        As[ti][tj] = (i < M && ka < K) ? A[i * a0 + ka * a1] : 0.0;
+        Bs[ti][tj] = (kb < K && j < N) ? B[kb * b0 + j * b1] : 0.0;
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < GT; ++k) acc += As[ti][k] * Bs[k][tj];
+        for (int k = 0; k < DT; ++k) acc += As[ti][k] * Bs[k][tj];
         __syncthreads();
     }
-    if (i < M && j < N) {
-        if (bias) acc += bias[j];
-        if (act == 1) acc = tanhf(acc);
-        C[i * ldc + j] = acc;
-    }
+    if (i < M && j < N) C[i * ldc + j] = acc;
 }
 
 // delta *= (1 - h^2)
@@ -143,8 +199,15 @@ inline unsigned nb(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 void gemm(hipStream_t s, int M, int N, int K, const float *A, int64_t a0, int64_t a1, const float *B, int64_t b0,
           int64_t b1, const float *bias, int act, float *C, int64_t ldc) {
-    dim3 grid(nb(N, GT), nb(M, GT));
-    k_gemm<<<grid, GT * GT, 0, s>>>(M, N, K, A, a0, a1, B, b0, b1, bias, act, C, ldc);
+    dim3 grid(nb(N, 32), nb(M, 32));
+    k_gemm_mma<<<grid, 64, 0, s>>>(M, N, K, A, a0, a1, B, b0, b1, bias, act, C, ldc);
+    GHIPCHK(hipGetLastError());
+}
+
+void dgemm(hipStream_t s, int M, int N, int K, const double *A, int64_t a0, int64_t a1, const double *B,
+           int64_t b0, int64_t b1, double *C, int64_t ldc) {
+    dim3 grid(nb(N, DT), nb(M, DT));
+    k_dgemm<<<grid, DT * DT, 0, s>>>(M, N, K, A, a0, a1, B, b0, b1, C, ldc);
     GHIPCHK(hipGetLastError());
 }
 
@@ -192,9 +255,10 @@ void Mlp::get_grads(float *host) const {
     GHIPCHK(hipStreamSynchronize((hipStream_t)stream_));
 }
 
-void Mlp::init_uniform(uint64_t seed) {
+void Mlp::init_uniform(uint64_t seed, bool zero_last) {
     // SplitMix64 (Steele, Lea, Flood 2014) -> uniform [0,1); weights
-    // U(-sqrt(6/(in+out)), +sqrt(6/(in+out))), biases zero
+    // U(-sqrt(6/(in+out)), +sqrt(6/(in+out))), biases zero; with zero_last
+    // the output layer starts at zero
     std::vector<float> h(np_, 0.f);
     uint64_t state = seed;
     auto next = [&]() {
@@ -208,7 +272,8 @@ void Mlp::init_uniform(uint64_t seed) {
     for (size_t l = 0; l + 1 < sizes_.size(); ++l) {
         const int a = sizes_[l], b = sizes_[l + 1];
         const double lim = std::sqrt(6.0 / (a + b));
-        for (int64_t q = 0; q < (int64_t)a * b; ++q) h[off + q] = (float)((2.0 * next() - 1.0) * lim);
+        const bool zero = zero_last && l + 2 == sizes_.size();
+        for (int64_t q = 0; q < (int64_t)a * b; ++q) h[off + q] = zero ? 0.f : (float)((2.0 * next() - 1.0) * lim);
         off += (int64_t)a * b + b;
     }
     set_params(h.data());
@@ -451,6 +516,7 @@ namespace sfmm {
 Guess::~Guess() {
     (void)hipFree(U_);
     (void)hipFree(W_);
+    (void)hipFree(Ws_);
 }
 
 void Guess::span_predict(int n, const void *B, void *X0,
@@ -499,40 +565,140 @@ void Guess::set_stream(void *s) {
     if (net_) net_->set_stream(s);
 }
 
-void Guess::features(int n, const double *angles, const void *B, std::vector<float> &F, std::vector<double> &nb) {
-    const int M = o_.harmonics, r = r_, nf = 4 * M + 2 * r;
+namespace {
+
+// device buffer freed at scope exit
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    explicit DevBuf(size_t n) { GHIPCHK(hipMalloc(&p, sizeof(T) * std::max<size_t>(n, 1))); }
+    ~DevBuf() { (void)hipFree(p); }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+};
+
+}  // namespace
+
+void Guess::features(int n, const double *angles, const void *B, std::vector<float> &Z, std::vector<double> &Zp,
+                     std::vector<double> &nb, bool set_scale) {
+    constexpr double kPi = 3.14159265358979323846;
+    hipStream_t st = (hipStream_t)stream_;
+    const int M = o_.harmonics, nt = o_.n_theta, nph = o_.n_phi, nd = nt * nph, np = 4 * nd, nf = 4 * M + np;
+    // coarse direction grid: theta at the midpoints of nt bands, phi uniform
+    std::vector<double> dirs(2 * (size_t)nd);
+    for (int i = 0; i < nt; ++i)
+        for (int j = 0; j < nph; ++j) {
+            dirs[2 * ((size_t)i * nph + j)] = (i + 0.5) * kPi / nt;
+            dirs[2 * ((size_t)i * nph + j) + 1] = j * 2.0 * kPi / nph;
+        }
+    DevBuf<double> dd(dirs.size()), dF((size_t)n * np);
+    GHIPCHK(hipMemcpyAsync(dd.p, dirs.data(), sizeof(double) * dirs.size(), hipMemcpyHostToDevice, st));
+    pattern_(n, B, nd, dd.p, dF.p);
+    Zp.assign((size_t)n * np, 0.0);
+    GHIPCHK(hipMemcpyAsync(Zp.data(), dF.p, sizeof(double) * Zp.size(), hipMemcpyDeviceToHost, st));
     nb.assign(n, 0.0);
-    self_norms(B, N_, n, N_, nb.data(), stream_);
-    std::vector<cd> proj((size_t)r * n);
-    cross_dots(U_, N_, r, B, N_, n, N_, proj.data(), stream_);   // proj[k][s] = u_k^H b_s
-    F.assign((size_t)n * nf, 0.f);
+    self_norms(B, N_, n, N_, nb.data(), stream_);   // synchronises the stream
+    for (int s = 0; s < n; ++s) {
+        const double inv = nb[s] > 0 ? 1.0 / nb[s] : 0.0;
+        for (int q = 0; q < np; ++q) Zp[(size_t)s * np + q] *= inv;
+    }
+    if (set_scale) {
+        double ss = 0;
+        for (double v : Zp) ss += v * v;
+        const double rms = std::sqrt(ss / std::max<size_t>(Zp.size(), 1));
+        s_p_ = rms > 0 ? 1.0 / rms : 1.0;
+    }
+    for (double &v : Zp) v *= s_p_;
+    Z.assign((size_t)n * nf, 0.f);
     for (int s = 0; s < n; ++s) {
         const double th = angles[2 * s], ph = angles[2 * s + 1];
-        float *f = F.data() + (size_t)s * nf;
+        float *f = Z.data() + (size_t)s * nf;
         for (int m = 1; m <= M; ++m) {
             f[m - 1] = (float)std::cos(m * th);
             f[M + m - 1] = (float)std::sin(m * th);
             f[2 * M + m - 1] = (float)std::cos(m * ph);
             f[3 * M + m - 1] = (float)std::sin(m * ph);
         }
-        const double inv = nb[s] > 0 ? 1.0 / nb[s] : 0.0;
-        for (int k = 0; k < r; ++k) {
-            const cd p = proj[(size_t)k * n + s] * inv;
-            f[4 * M + k] = (float)p.real();
-            f[4 * M + r + k] = (float)p.imag();
-        }
+        for (int q = 0; q < np; ++q) f[4 * M + q] = (float)Zp[(size_t)s * np + q];
     }
+}
+
+double Mlp::train(int B, const float *X, const float *Y, int epochs, double lr) {
+    hipStream_t st = (hipStream_t)stream_;
+    int *dstep = nullptr;
+    GHIPCHK(hipMalloc(&dstep, sizeof(int)));
+    double loss = 0;
+    try {
+        GHIPCHK(hipMemsetAsync(dstep, 0, sizeof(int), st));
+        ensure_batch(B);
+        bool graphed = false;
+        if (st && epochs > 1) {
+            // EPG epochs (forward, backward, Adam with the device-side step
+            // count) captured once into a HIP graph and replayed
+            constexpr int EPG = 25;
+            const int per = std::min(EPG, epochs);
+            hipGraph_t g = nullptr;
+            GHIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            try {
+                for (int k = 0; k < per; ++k) {
+                    loss_grad(B, X, Y, false);
+                    adam_scheduled(dstep, lr, epochs);
+                }
+            } catch (...) {
+                hipGraph_t broken = nullptr;
+                (void)hipStreamEndCapture(st, &broken);
+                if (broken) (void)hipGraphDestroy(broken);
+                throw;
+            }
+            GHIPCHK(hipStreamEndCapture(st, &g));
+            hipGraphExec_t ex = nullptr;
+            const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            GHIPCHK(e);
+            int done = 0;
+            for (; done + per <= epochs; done += per) {
+                const hipError_t le = hipGraphLaunch(ex, st);
+                if (le != hipSuccess) {
+                    (void)hipGraphExecDestroy(ex);
+                    GHIPCHK(le);
+                }
+            }
+            const hipError_t se = hipStreamSynchronize(st);
+            (void)hipGraphExecDestroy(ex);
+            GHIPCHK(se);
+            for (; done < epochs; ++done) {   // the remainder, launched directly
+                loss_grad(B, X, Y, false);
+                adam_scheduled(dstep, lr, epochs);
+            }
+            graphed = true;
+        }
+        if (!graphed)
+            for (int ep = 0; ep < epochs; ++ep) {
+                loss_grad(B, X, Y, false);
+                adam_scheduled(dstep, lr, epochs);
+            }
+        loss = loss_grad(B, X, Y, true);
+    } catch (...) {
+        (void)hipFree(dstep);
+        throw;
+    }
+    (void)hipFree(dstep);
+    return loss;
 }
 
 double Guess::fit(int n, const double *angles, const void *B, const void *X, const GuessOptions &o) {
     if (n < 1 || n > 512) throw Error(SFMM_E_INVALID_ARG, "learned guess: 1 to 512 training solutions");
-    if (o.rank < 1 || o.harmonics < 0 || o.hidden < 1 || o.epochs < 0 || !(o.lr > 0))
+    if (o.rank < 1 || o.harmonics < 0 || o.hidden < 1 || o.hidden > 4096 || o.epochs < 0 || !(o.lr > 0) ||
+        o.n_theta < 1 || o.n_phi < 1 || (int64_t)o.n_theta * o.n_phi > 4096)
         throw Error(SFMM_E_INVALID_ARG, "learned guess: bad options");
+    hipStream_t st = (hipStream_t)stream_;
     o_ = o;
     net_.reset();
     (void)hipFree(W_);
     W_ = nullptr;
     gram_.clear();
+    (void)hipFree(Ws_);
+    Ws_ = nullptr;
     // POD basis: Gram matrix G[i][j] = <x_i, x_j>, G = V diag(w) V^H,
     // u_k = sum_i x_i V[i][k] / sqrt(w_k) for the r largest w_k
     std::vector<cd> G((size_t)n * n), V;
@@ -564,105 +730,70 @@ double Guess::fit(int n, const double *angles, const void *B, const void *X, con
     U_ = nullptr;
     GHIPCHK(hipMalloc(&U_, sizeof(double2) * (size_t)r * N_));
     lincomb(X, N_, n, coef.data(), r, N_, U_, N_, stream_);
-    // features and standardised targets Re/Im(U^H x) / ||b||
-    std::vector<float> F;
-    std::vector<double> nb;
-    features(n, angles, B, F, nb);
+    // features and targets y = s_y Re/Im(U^H x) / ||b||
+    std::vector<float> Z;
+    std::vector<double> Zp, nb;
+    features(n, angles, B, Z, Zp, nb, true);
+    const int np = 4 * o.n_theta * o.n_phi, no = 2 * r, nf = 4 * o.harmonics + np;
     std::vector<cd> c((size_t)r * n);
     cross_dots(U_, N_, r, X, N_, n, N_, c.data(), stream_);
-    const int no = 2 * r, nf = 4 * o.harmonics + 2 * r;
-    std::vector<double> Yd((size_t)n * no);
+    std::vector<double> Y((size_t)n * no);
     for (int s = 0; s < n; ++s) {
         const double inv = nb[s] > 0 ? 1.0 / nb[s] : 0.0;
         for (int k = 0; k < r; ++k) {
-            Yd[(size_t)s * no + k] = c[(size_t)k * n + s].real() * inv;
-            Yd[(size_t)s * no + r + k] = c[(size_t)k * n + s].imag() * inv;
+            Y[(size_t)s * no + k] = c[(size_t)k * n + s].real() * inv;
+            Y[(size_t)s * no + r + k] = c[(size_t)k * n + s].imag() * inv;
         }
     }
-    mu_.assign(no, 0.0);
-    sd_.assign(no, 0.0);
-    for (int j = 0; j < no; ++j) {
-        for (int s = 0; s < n; ++s) mu_[j] += Yd[(size_t)s * no + j];
-        mu_[j] /= n;
-        for (int s = 0; s < n; ++s) sd_[j] += (Yd[(size_t)s * no + j] - mu_[j]) * (Yd[(size_t)s * no + j] - mu_[j]);
-        sd_[j] = std::sqrt(sd_[j] / n);
+    double ss = 0;
+    for (double v : Y) ss += v * v;
+    const double yrms = std::sqrt(ss / Y.size());
+    s_y_ = yrms > 0 ? 1.0 / yrms : 1.0;
+    for (double &v : Y) v *= s_y_;
+    // linear path (FP64): Ws = Zp^T Gp^+ Y, Gp = Zp Zp^T with eigenvalues at
+    // or below 1e-12 of the largest dropped (minimum-norm least squares)
+    DevBuf<double> dZp(Zp.size()), dGp((size_t)n * n), dA((size_t)n * no), dLin((size_t)n * no);
+    GHIPCHK(hipMemcpyAsync(dZp.p, Zp.data(), sizeof(double) * Zp.size(), hipMemcpyHostToDevice, st));
+    dgemm(st, n, n, np, dZp.p, np, 1, dZp.p, 1, np, dGp.p, n);
+    std::vector<double> Gp((size_t)n * n);
+    GHIPCHK(hipMemcpyAsync(Gp.data(), dGp.p, sizeof(double) * Gp.size(), hipMemcpyDeviceToHost, st));
+    GHIPCHK(hipStreamSynchronize(st));
+    std::vector<cd> Gc((size_t)n * n), Vg;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Gc[(size_t)i * n + j] = 0.5 * (Gp[(size_t)i * n + j] + Gp[(size_t)j * n + i]);
+    std::vector<double> wg;
+    hermitian_eig(n, Gc, wg, Vg);
+    const double gmax = *std::max_element(wg.begin(), wg.end());
+    std::vector<double> A((size_t)n * no, 0.0);   // Gp^+ Y
+    for (int k = 0; k < n; ++k) {
+        if (!(gmax > 0) || wg[k] <= 1e-12 * gmax) continue;
+        for (int q = 0; q < no; ++q) {
+            double t = 0;
+            for (int i = 0; i < n; ++i) t += Vg[(size_t)i * n + k].real() * Y[(size_t)i * no + q];
+            t /= wg[k];
+            for (int i = 0; i < n; ++i) A[(size_t)i * no + q] += Vg[(size_t)i * n + k].real() * t;
+        }
     }
-    const double sdmax = *std::max_element(sd_.begin(), sd_.end());
-    for (double &v : sd_) v = std::max(v, sdmax > 0 ? 1e-6 * sdmax : 1.0);
-    std::vector<float> Y((size_t)n * no);
-    for (int s = 0; s < n; ++s)
-        for (int j = 0; j < no; ++j) Y[(size_t)s * no + j] = (float)((Yd[(size_t)s * no + j] - mu_[j]) / sd_[j]);
-    // train on the device: full batch, Adam, cosine step decay
+    GHIPCHK(hipMalloc(&Ws_, sizeof(double) * (size_t)np * no));
+    GHIPCHK(hipMemcpyAsync(dA.p, A.data(), sizeof(double) * A.size(), hipMemcpyHostToDevice, st));
+    dgemm(st, np, no, n, dZp.p, 1, np, dA.p, no, 1, Ws_, no);
+    dgemm(st, n, no, np, dZp.p, np, 1, Ws_, no, 1, dLin.p, no);
+    std::vector<double> lin((size_t)n * no);
+    GHIPCHK(hipMemcpyAsync(lin.data(), dLin.p, sizeof(double) * lin.size(), hipMemcpyDeviceToHost, st));
+    GHIPCHK(hipStreamSynchronize(st));
+    // the MLP learns the remainder R = Y - Zp Ws at unit RMS
+    ss = 0;
+    for (size_t q = 0; q < Y.size(); ++q) ss += (Y[q] - lin[q]) * (Y[q] - lin[q]);
+    const double rrms = std::sqrt(ss / Y.size());
+    s_r_ = rrms > 0 ? 1.0 / rrms : 1.0;
+    std::vector<float> Rs(Y.size());
+    for (size_t q = 0; q < Y.size(); ++q) Rs[q] = (float)((Y[q] - lin[q]) * s_r_);
     auto net = std::make_unique<Mlp>(std::vector<int>{nf, o.hidden, o.hidden, no}, stream_);
-    net->init_uniform(o.seed);
-    float *dF = nullptr, *dY = nullptr;
-    int *dstep = nullptr;
-    GHIPCHK(hipMalloc(&dF, sizeof(float) * F.size()));
-    GHIPCHK(hipMalloc(&dY, sizeof(float) * Y.size()));
-    GHIPCHK(hipMalloc(&dstep, sizeof(int)));
-    double loss = 0;
-    try {
-        GHIPCHK(hipMemcpyAsync(dF, F.data(), sizeof(float) * F.size(), hipMemcpyHostToDevice, (hipStream_t)stream_));
-        GHIPCHK(hipMemcpyAsync(dY, Y.data(), sizeof(float) * Y.size(), hipMemcpyHostToDevice, (hipStream_t)stream_));
-        // one epoch (forward, backward, Adam with the device-side step count)
-        // is captured once into a HIP graph and replayed
-        GHIPCHK(hipMemsetAsync(dstep, 0, sizeof(int), (hipStream_t)stream_));
-        net->ensure_batch(n);
-        hipStream_t st = (hipStream_t)stream_;
-        bool graphed = false;
-        if (st && o.epochs > 1) {
-            hipGraph_t g = nullptr;
-            // EPG epochs per graph launch
-            constexpr int EPG = 25;
-            const int per = std::min(EPG, o.epochs);
-            GHIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-            try {
-                for (int k = 0; k < per; ++k) {
-                    net->loss_grad(n, dF, dY, false);
-                    net->adam_scheduled(dstep, o.lr, o.epochs);
-                }
-            } catch (...) {
-                hipGraph_t broken = nullptr;
-                (void)hipStreamEndCapture(st, &broken);
-                if (broken) (void)hipGraphDestroy(broken);
-                throw;
-            }
-            GHIPCHK(hipStreamEndCapture(st, &g));
-            hipGraphExec_t ex = nullptr;
-            const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            GHIPCHK(e);
-            int done = 0;
-            for (; done + per <= o.epochs; done += per) {
-                const hipError_t le = hipGraphLaunch(ex, st);
-                if (le != hipSuccess) {
-                    (void)hipGraphExecDestroy(ex);
-                    GHIPCHK(le);
-                }
-            }
-            GHIPCHK(hipStreamSynchronize(st));
-            (void)hipGraphExecDestroy(ex);
-            for (; done < o.epochs; ++done) {   // the remainder, launched directly
-                net->loss_grad(n, dF, dY, false);
-                net->adam_scheduled(dstep, o.lr, o.epochs);
-            }
-            graphed = true;
-        }
-        if (!graphed)
-            for (int ep = 0; ep < o.epochs; ++ep) {
-                net->loss_grad(n, dF, dY, false);
-                net->adam_scheduled(dstep, o.lr, o.epochs);
-            }
-        loss = net->loss_grad(n, dF, dY, true);
-    } catch (...) {
-        (void)hipFree(dF);
-        (void)hipFree(dY);
-        (void)hipFree(dstep);
-        throw;
-    }
-    (void)hipFree(dF);
-    (void)hipFree(dY);
-    (void)hipFree(dstep);
+    net->init_uniform(o.seed, true);
+    DevBuf<float> dZ(Z.size()), dR(Rs.size());
+    GHIPCHK(hipMemcpyAsync(dZ.p, Z.data(), sizeof(float) * Z.size(), hipMemcpyHostToDevice, st));
+    GHIPCHK(hipMemcpyAsync(dR.p, Rs.data(), sizeof(float) * Rs.size(), hipMemcpyHostToDevice, st));
+    const double loss = net->train(n, dZ.p, dR.p, o.epochs, o.lr);
     net_ = std::move(net);
     return loss;
 }
@@ -670,30 +801,28 @@ double Guess::fit(int n, const double *angles, const void *B, const void *X, con
 void Guess::predict(int n, const double *angles, const void *B, void *X0) {
     if (!net_) throw Error(SFMM_E_INVALID_ARG, "learned guess is not trained (call sfmm_guess_fit first)");
     if (n < 1) throw Error(SFMM_E_INVALID_ARG, "n must be positive");
-    std::vector<float> F;
-    std::vector<double> nb;
-    features(n, angles, B, F, nb);
-    const int r = r_, no = 2 * r, nf = 4 * o_.harmonics + 2 * r;
-    float *dF = nullptr;
-    GHIPCHK(hipMalloc(&dF, sizeof(float) * F.size()));
+    hipStream_t st = (hipStream_t)stream_;
+    std::vector<float> Z;
+    std::vector<double> Zp, nb;
+    features(n, angles, B, Z, Zp, nb, false);
+    const int r = r_, no = 2 * r, np = 4 * o_.n_theta * o_.n_phi;
+    DevBuf<float> dZ(Z.size());
+    DevBuf<double> dZp(Zp.size()), dLin((size_t)n * no);
     std::vector<float> out((size_t)n * no);
-    try {
-        GHIPCHK(hipMemcpyAsync(dF, F.data(), sizeof(float) * F.size(), hipMemcpyHostToDevice, (hipStream_t)stream_));
-        const float *y = net_->forward(n, dF);
-        GHIPCHK(hipMemcpyAsync(out.data(), y, sizeof(float) * out.size(), hipMemcpyDeviceToHost,
-                               (hipStream_t)stream_));
-        GHIPCHK(hipStreamSynchronize((hipStream_t)stream_));
-    } catch (...) {
-        (void)hipFree(dF);
-        throw;
-    }
-    (void)hipFree(dF);
-    (void)nf;
+    std::vector<double> lin((size_t)n * no);
+    GHIPCHK(hipMemcpyAsync(dZ.p, Z.data(), sizeof(float) * Z.size(), hipMemcpyHostToDevice, st));
+    GHIPCHK(hipMemcpyAsync(dZp.p, Zp.data(), sizeof(double) * Zp.size(), hipMemcpyHostToDevice, st));
+    dgemm(st, n, no, np, dZp.p, np, 1, Ws_, no, 1, dLin.p, no);
+    const float *y = net_->forward(n, dZ.p);
+    GHIPCHK(hipMemcpyAsync(out.data(), y, sizeof(float) * out.size(), hipMemcpyDeviceToHost, st));
+    GHIPCHK(hipMemcpyAsync(lin.data(), dLin.p, sizeof(double) * lin.size(), hipMemcpyDeviceToHost, st));
+    GHIPCHK(hipStreamSynchronize(st));
     std::vector<cd> coef((size_t)n * r);
     for (int s = 0; s < n; ++s)
         for (int k = 0; k < r; ++k) {
-            const double re = out[(size_t)s * no + k] * sd_[k] + mu_[k];
-            const double im = out[(size_t)s * no + r + k] * sd_[r + k] + mu_[r + k];
+            const size_t a = (size_t)s * no + k, b = a + r;
+            const double re = (lin[a] + out[a] / s_r_) / s_y_;
+            const double im = (lin[b] + out[b] / s_r_) / s_y_;
             coef[(size_t)s * r + k] = cd(re, im) * nb[s];
         }
     lincomb(U_, N_, r, coef.data(), n, N_, X0, N_, stream_);

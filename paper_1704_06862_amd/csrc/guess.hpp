@@ -1,4 +1,4 @@
-// Learned initial guess: device MLP with hand-written kernels, POD helpers.
+// Learned initial guess: device network with hand-written kernels, POD helpers.
 #pragma once
 
 #include <cstdint>
@@ -26,7 +26,7 @@ class Mlp {
     int64_t n_params() const { return np_; }
     const std::vector<int> &sizes() const { return sizes_; }
     void set_stream(void *s) { stream_ = s; }
-    void init_uniform(uint64_t seed);
+    void init_uniform(uint64_t seed, bool zero_last = false);
     void set_params(const float *host);
     void get_params(float *host) const;
     void get_grads(float *host) const;
@@ -44,6 +44,9 @@ class Mlp {
                         double eps = 1e-8);
     // activation buffers for batches up to B (allocates; call before capture)
     void ensure_batch(int B);
+    // Adam steps (full batch X [B][in], targets Y [B][out], device), one
+    // graph-captured block of steps replayed; returns the final loss
+    double train(int B, const float *X, const float *Y, int epochs, double lr);
 
   private:
     std::vector<int> sizes_;
@@ -71,18 +74,25 @@ void lincomb(const void *vecs, int64_t ld, int nv, const cd *coef_host, int ns, 
              void *stream);
 
 struct GuessOptions {
-    int rank = 16;        // POD basis size r (clamped to the training count)
+    int rank = 72;        // POD basis size r (clamped to the training count)
     int harmonics = 4;    // M angle harmonics
-    int hidden = 64;      // width of both tanh hidden layers
-    int epochs = 2000;    // full-batch Adam steps
-    double lr = 3e-3;     // peak Adam step, cosine decay to zero
+    int hidden = 768;     // width of both tanh hidden layers
+    int epochs = 300;     // full-batch Adam steps of the MLP
+    double lr = 1e-3;     // peak Adam step, cosine decay to zero
     uint64_t seed = 0;    // weight initialisation
+    int n_theta = 16;     // pattern feature grid: theta bands
+    int n_phi = 31;       //                       phi samples
 };
+
+// b (device, [n][N] complex FP64, boundary layout) read as surface currents:
+// F [n][n_dirs][4] (device, FP64) = Re/Im of theta.F, Re/Im of phi.F of its
+// far field at dirs [n_dirs][2] (device, theta/phi)
+using PatternFn = std::function<void(int n, const void *b, int n_dirs, const double *dirs, double *F)>;
 
 // Learned GMRES initial guess for one body (boundary unknown order).
 class Guess {
   public:
-    Guess(int N, void *stream) : N_(N), stream_(stream) {}
+    Guess(int N, void *stream, PatternFn pattern) : N_(N), stream_(stream), pattern_(std::move(pattern)) {}
     ~Guess();
     Guess(const Guess &) = delete;
     Guess &operator=(const Guess &) = delete;
@@ -90,7 +100,8 @@ class Guess {
     bool trained() const { return net_ != nullptr; }
     int rank() const { return r_; }
     // angles [n][2]; B, X device [n][N] complex (right-hand sides and their
-    // solutions).  Returns the final training loss.
+    // solutions).  Returns the final training loss of the MLP (on the
+    // unit-RMS remainder of the linear path).
     double fit(int n, const double *angles, const void *B, const void *X, const GuessOptions &o);
     // X0 device [n][N] complex
     void predict(int n, const double *angles, const void *B, void *X0);
@@ -101,13 +112,19 @@ class Guess {
                       const std::function<void(int, const void *, void *)> &product);
 
   private:
-    void features(int n, const double *angles, const void *B, std::vector<float> &F, std::vector<double> &nb);
+    // features of n right-hand sides: Z [n][nf] (FP32, network input), Zp
+    // [n][np] (FP64, the pattern part), ||b||; with `set_scale` the pattern
+    // scale s_p is taken from these rows
+    void features(int n, const double *angles, const void *B, std::vector<float> &Z, std::vector<double> &Zp,
+                  std::vector<double> &nb, bool set_scale);
     int N_;
     void *stream_;
+    PatternFn pattern_;
     GuessOptions o_{};
     int r_ = 0;
     void *U_ = nullptr;            // [r][N] complex FP64, orthonormal rows
-    std::vector<double> mu_, sd_;  // target standardisation
+    double s_p_ = 1, s_y_ = 1, s_r_ = 1;
+    double *Ws_ = nullptr;         // [np][2r] FP64 linear path
     std::unique_ptr<Mlp> net_;
     void *W_ = nullptr;            // Z U, [r][N], formed on the first span_predict
     std::vector<cd> gram_;         // W^H W

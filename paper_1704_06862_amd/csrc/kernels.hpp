@@ -1594,8 +1594,10 @@ __global__ void k_planewave_rhs(int ne, int R, const int *__restrict__ s0, const
 // Bistatic RCS: for direction d (theta, phi) and the FP64 currents x[r]
 // (boundary layout), F = (-j k0 eta0 / 4 pi) [(I - rr) J^ - r x M~^] with
 // J^ = sum_e s0 J_e Int f_e exp(+j k0 r.r'); sigma = 4 pi (|F_theta|^2,
-// |F_phi|^2).  Grid: (directions, tiles of RCS_RT right-hand sides).
+// |F_phi|^2), or with FIELD the field itself: out[(rhs, dir)][4] = Re/Im
+// F_theta, Re/Im F_phi.  Grid: (directions, tiles of RCS_RT right-hand sides).
 constexpr int RCS_RT = 4;
+template <bool FIELD>
 __global__ void __launch_bounds__(256) k_far_field(int ne, int R, const int *__restrict__ s0,
                                                    const double *__restrict__ qr, const double *__restrict__ qf,
                                                    double k0, double eta0, const double *__restrict__ dirs,
@@ -1663,6 +1665,14 @@ __global__ void __launch_bounds__(256) k_far_field(int ne, int R, const int *__r
     const double pre = k0 * eta0 / (4.0 * 3.14159265358979323846);
     const double ar = v[0] + v[6], ai = v[1] + v[7];
     const double br = v[2] - v[4], bi = v[3] - v[5];
+    if (FIELD) {   // -j pre (a, b)
+        double *o = sigma + ((int64_t)(r0 + t) * n_dirs + d) * 4;
+        o[0] = pre * ai;
+        o[1] = -pre * ar;
+        o[2] = pre * bi;
+        o[3] = -pre * br;
+        return;
+    }
     // |pre * (a)|^2 = pre^2 |a|^2 (the -j factor has unit modulus)
     const double s = 4.0 * 3.14159265358979323846 * pre * pre;
     sigma[((int64_t)(r0 + t) * n_dirs + d) * 2] = s * (ar * ar + ai * ai);

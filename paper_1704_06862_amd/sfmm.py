@@ -60,7 +60,8 @@ class sfmm_solve_info(ctypes.Structure):
 
 class sfmm_guess_options(ctypes.Structure):
     _fields_ = [("rank", ctypes.c_int32), ("harmonics", ctypes.c_int32), ("hidden", ctypes.c_int32),
-                ("epochs", ctypes.c_int32), ("lr", ctypes.c_double), ("seed", ctypes.c_uint64)]
+                ("epochs", ctypes.c_int32), ("lr", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("n_theta", ctypes.c_int32), ("n_phi", ctypes.c_int32)]
 
 
 class SfmmError(RuntimeError):

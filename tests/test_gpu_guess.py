@@ -1,19 +1,25 @@
 """GPU checks of the learned initial guess.
 
-* The network kernels (bfloat16-rounded GEMM operands, FP32 accumulation)
-  against the FP64 oracle MLP on the same parameters: outputs and loss within
-  1e-2 relative, gradients per tensor with cosine >= 0.999 and relative error
-  <= 2e-2; Adam steps and a short training run follow the oracle's.
+* The network kernels (matrix-core GEMMs with bf16-split operands, FP32
+  accumulation) against the FP64 oracle MLP on the same parameters: outputs,
+  loss and gradients within 1e-4 relative (bf16-split keeps about 16
+  significant bits per operand); Adam steps and a short training run follow
+  the oracle's.
+* The whole fit/predict pipeline with the linear path alone (no Adam steps:
+  deterministic) against the oracle's on the same angles and the same seeded
+  training currents: radiation-pattern features, POD basis, minimum-norm
+  least squares and the decode, within 1e-6.
 * The trained guess on a theta sweep of a dielectric ellipsoid: it lies in the
-  span of the training solutions, it cuts GMRES iterations against the zero
-  start, and every solve still meets the tolerance on its true residual.
+  span of the training solutions, it reproduces them, it starts GMRES near
+  the tolerance between the training angles, and every solve still meets the
+  tolerance on its true residual.
 * The solver's judge: a guess worse than zero is dropped.
 """
 
 import numpy as np
 import pytest
 
-from oracle import mlp
+from oracle import mlp, rwg
 from workloads import Body, icosphere, random_complex_vector, theta_sweep
 
 pytestmark = pytest.mark.gpu
@@ -59,15 +65,13 @@ def test_forward_and_gradients_match_oracle():
     ref_params = unflatten(p32, SIZES)
     ref_out, _ = mlp.forward(ref_params, X.astype(np.float64))
     ref_loss, ref_grads = mlp.loss_and_grads(ref_params, X.astype(np.float64), Y.astype(np.float64))
-    assert rel(out, ref_out) < 1e-2
-    assert abs(loss[0] - ref_loss) < 1e-2 * ref_loss
+    assert rel(out, ref_out) < 1e-4, rel(out, ref_out)
+    assert abs(loss[0] - ref_loss) < 1e-4 * ref_loss
     g = unflatten(grads, SIZES)
     for li in range(len(g)):
         for k in range(2):
             a, b = g[li][k].ravel(), ref_grads[li][k].ravel()
-            cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b))
-            assert cos >= 0.999, (li, k, cos)
-            assert rel(a, b) <= 2e-2, (li, k, rel(a, b))
+            assert rel(a, b) <= 1e-4, (li, k, rel(a, b))
 
 
 def test_adam_steps_follow_oracle():
@@ -85,8 +89,8 @@ def test_adam_steps_follow_oracle():
     d_gpu = p.astype(np.float64) - p32
     d_ref = flatten(ref).astype(np.float64) - p32
     cos = d_gpu @ d_ref / (np.linalg.norm(d_gpu) * np.linalg.norm(d_ref))
-    assert cos >= 0.99, cos
-    assert np.allclose(loss, ref_loss, rtol=2e-2)
+    assert cos >= 0.999, cos
+    assert np.allclose(loss, ref_loss, rtol=1e-3)
 
 
 def test_training_reduces_loss_like_oracle():
@@ -122,25 +126,68 @@ def ectx():
         yield c
 
 
+def test_fit_and_predict_match_oracle_on_the_linear_path(ectx):
+    print("learned guess pipeline parity (linear path)", flush=True)
+    body = ellipsoid()
+    m = rwg.from_body(body)
+    n = ectx.sfmm_num_unknowns()
+    tr = theta_sweep(7, phi=0.2)                               # 30 degree steps
+    te = tr[:-1] + np.array([np.deg2rad(15.0), 0.0])           # the midpoints
+    # seeded training currents with a smooth angle dependence (any data serve
+    # the pipeline; both sides build their own right-hand sides)
+    V = random_complex_vector(n, 4, seed=11)
+    th = tr[:, 0][:, None]
+    X = np.cos(th) * V[0] + np.sin(th) * V[1] + np.cos(2 * th) * V[2] + np.sin(2 * th) * V[3]
+    ectx.sfmm_guess_fit(tr, X, epochs=0, n_theta=6, n_phi=11)
+    x0 = ectx.sfmm_guess_predict(te, np.zeros((len(te), n), dtype=complex))
+    B_tr = ectx.sfmm_planewave_rhs(tr, np.zeros((len(tr), n), dtype=complex))
+    B_te = ectx.sfmm_planewave_rhs(te, np.zeros((len(te), n), dtype=complex))
+    model = mlp.fit_guess(m, body.frequency, tr, _oracle_rhs(m, body, tr), X, hidden=4, epochs=0,
+                          n_theta=6, n_phi=11)
+    ref = mlp.predict_guess(model, te, _oracle_rhs(m, body, te))
+    err = rel(x0, ref)
+    print(f"pipeline parity {err:.2e} (rank {model['U'].shape[1]})", flush=True)
+    assert err < 1e-6
+    # the library's right-hand sides are the oracle's (the features read them)
+    assert rel(B_te, _oracle_rhs(m, body, te)) < 1e-10 and rel(B_tr, _oracle_rhs(m, body, tr)) < 1e-10
+
+
+def _oracle_rhs(m, body, ang):
+    from oracle import mom
+    return np.array([mom.planewave_rhs(m, body.frequency, *mom.incidence(t, p)) for t, p in ang])
+
+
+def test_guess_options_are_checked(ectx):
+    n = ectx.sfmm_num_unknowns()
+    x = np.zeros((2, n), dtype=complex)
+    x[:, 0] = 1.0
+    with pytest.raises(sfmm.SfmmError):
+        ectx.sfmm_guess_fit(theta_sweep(2), x, n_theta=64, n_phi=65)
+    with pytest.raises(sfmm.SfmmError):
+        ectx.sfmm_guess_fit(theta_sweep(2), x, hidden=0)
+
+
 def test_learned_guess_cuts_iterations(ectx):
     print("learned guess sweep", flush=True)
     n = ectx.sfmm_num_unknowns()
     ang = theta_sweep(91)
-    tr = np.arange(0, 91, 3)
+    tr = np.arange(0, 91, 3)                                   # both ends included
     te = np.setdiff1d(np.arange(91), tr)
     b = ectx.sfmm_planewave_rhs(ang, np.zeros((91, n), dtype=complex))
     x_tr = np.zeros((len(tr), n), dtype=complex)
     info_tr = ectx.sfmm_solve(b[tr].copy(), x_tr)
     assert all(i["converged"] for i in info_tr)
     loss = ectx.sfmm_guess_fit(ang[tr], x_tr)
-    assert np.isfinite(loss)
+    r = len(tr)
+    # the MLP starts at zero on unit-RMS targets (loss r); Adam lowers it
+    assert np.isfinite(loss) and loss < 0.9 * r, loss
     x0 = ectx.sfmm_guess_predict(ang[te], np.zeros((len(te), n), dtype=complex))
     # x0 = U c lies in the span of the training solutions
     coef = np.linalg.lstsq(x_tr.T, x0.T, rcond=None)[0]
     assert rel(x_tr.T @ coef, x0.T) < 1e-6
-    # at the training angles the guess is close to the training solutions
+    # at the training angles the guess reproduces the training solutions
     x0_tr = ectx.sfmm_guess_predict(ang[tr], np.zeros((len(tr), n), dtype=complex))
-    assert rel(x0_tr, x_tr) < 0.1
+    assert rel(x0_tr, x_tr) < 1e-3, rel(x0_tr, x_tr)
     x_zero = np.zeros((len(te), n), dtype=complex)
     x_lrn = np.zeros((len(te), n), dtype=complex)
     info0 = ectx.sfmm_solve(b[te].copy(), x_zero)
@@ -148,18 +195,18 @@ def test_learned_guess_cuts_iterations(ectx):
     its0 = np.array([i["iterations"] for i in info0])
     its1 = np.array([i["iterations"] for i in info1])
     r0 = np.array([i["initial_residual"] for i in info1])
-    print(f"zero-guess iterations {its0.mean():.1f}, learned {its1.mean():.1f}, "
+    print(f"zero-guess iterations {its0.mean():.1f}, learned {its1.mean():.1f} (max {its1.max()}), "
           f"guess residual median {np.median(r0):.3e} max {r0.max():.3e}, loss {loss:.3e}", flush=True)
     for i0, i1 in zip(info0, info1):
         assert i0["converged"] and i1["converged"]
         assert i0["true_residual"] <= 1e-4 and i1["true_residual"] <= 1e-4
     assert np.mean([i["guess_used"] for i in info1]) >= 0.9
-    assert np.median(r0) < 0.1
-    assert its1.mean() < 0.75 * its0.mean()
+    assert np.median(r0) < 1e-3
+    assert its1.mean() < 0.5 * its0.mean()
     # both solutions agree to the solver tolerance
     assert rel(x_lrn, x_zero) < 1e-2
     # the network-free baseline: minimal residual in the same POD span; it
-    # also lies in the span and its residual is no larger than the network's
+    # also lies in the span, and its residual is about the network's
     xs = ectx.sfmm_span_predict(ang[te], np.zeros((len(te), n), dtype=complex))
     coef = np.linalg.lstsq(x_tr.T, xs.T, rcond=None)[0]
     assert rel(x_tr.T @ coef, xs.T) < 1e-6
@@ -167,7 +214,7 @@ def test_learned_guess_cuts_iterations(ectx):
     r2 = np.array([i["initial_residual"] for i in info2])
     print(f"span baseline: guess residual median {np.median(r2):.3e}, iterations "
           f"{np.mean([i['iterations'] for i in info2]):.1f}")
-    assert np.median(r2) <= np.median(r0) * 1.05
+    assert np.median(r2) <= 2.0 * np.median(r0) + 1e-4
 
 
 def test_judge_drops_a_bad_guess(ectx):

@@ -124,9 +124,7 @@ def small_sweep():
     m = rwg.from_body(b)
     Z = mom.pmchwt_dense(m, b.eps_r, b.mu_r, b.frequency)
     ang = theta_sweep(25, phi=0.3)
-    B = np.array([mom.planewave_rhs(m, b.frequency,
-                                    [np.sin(t) * np.cos(p), np.sin(t) * np.sin(p), np.cos(t)],
-                                    [np.cos(t) * np.cos(p), np.cos(t) * np.sin(p), -np.sin(t)]) for t, p in ang])
+    B = np.array([mom.planewave_rhs(m, b.frequency, *mom.incidence(t, p)) for t, p in ang])
     X = np.linalg.solve(Z, B.T).T
     return b, m, Z, ang, B, X
 
