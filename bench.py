@@ -241,12 +241,14 @@ def sweep(ctx, ctx_mixed, torch, n_ang, every, plain_stride=1, batched_fp32=True
     def span_in_sweep(x_tr):
         # the same protocol without the network: POD basis of the training
         # solutions (fit with no Adam steps), minimal-residual guess in its span
-        ctx_mixed.sfmm_guess_fit(ang[tr], x_tr, epochs=0)
+        parts = {}
+        _, parts["fit_s"] = timed(lambda: ctx_mixed.sfmm_guess_fit(ang[tr], x_tr, epochs=0))
         b_te = b.index_select(0, te_t).contiguous()
         x0 = torch.zeros_like(b_te)
-        ctx_mixed.sfmm_span_predict(ang[te], x0)
+        _, parts["span_guess_s"] = timed(lambda: ctx_mixed.sfmm_span_predict(ang[te], x0))
         x_te = torch.zeros_like(b_te)
-        return ctx_mixed.sfmm_solve(b_te, x_te, x0=x0)
+        info, parts["solve_s"] = timed(lambda: ctx_mixed.sfmm_solve(b_te, x_te, x0=x0))
+        return info, {k: round(v, 3) for k, v in parts.items()}
 
     # a network trained beforehand on a coarse sweep (the mid-points of this
     # sweep's angles, every other one): prediction + one batched solve of all
@@ -285,11 +287,13 @@ def sweep(ctx, ctx_mixed, torch, n_ang, every, plain_stride=1, batched_fp32=True
 
     print("sweep: learned guess inside the sweep", file=sys.stderr, flush=True)
     (i_tr, i_te, loss, t_fit, x_tr_done), t_learn = timed(learned)
+    t_learn_te = sum(i_te[k]["seconds"] for k in range(0, len(i_te), 64))
     # the library solves in chunks of up to 64 right-hand sides and reports
     # each chunk's time on its entries
     t_tr_solve = sum(i_tr[k]["seconds"] for k in range(0, len(i_tr), 64))
     print("sweep: span projection inside the sweep", file=sys.stderr, flush=True)
-    i_spi, t_spi = timed(lambda: span_in_sweep(x_tr_done))
+    (i_spi, spi_parts), t_spi = timed(lambda: span_in_sweep(x_tr_done))
+    spi_parts["training_solve_s"] = round(t_tr_solve, 3)
     t_spi += t_tr_solve
     ok = all(i["converged"] for i in i_plain + i_batch + i_mixed + i_tr + i_te + i_mid + i_am + i_sp + i_spi)
     assert len(i_tr) + len(i_te) == n_ang
@@ -309,11 +313,14 @@ def sweep(ctx, ctx_mixed, torch, n_ang, every, plain_stride=1, batched_fp32=True
                                 "span_projection_in_sweep_predicted_angles": its(i_spi)},
         "true_residual_max": res_max,
         "guess_in_sweep": {"trained_on": len(tr), "fit_and_predict_s": round(t_fit, 3), "loss": loss,
+                           "training_solve_s": round(sum(i_tr[k]["seconds"] for k in range(0, len(i_tr), 64)), 3),
+                           "predicted_solve_s": round(t_learn_te, 3),
                            "initial_residual_median": float(np.median([i["initial_residual"] for i in i_te])),
                            "initial_residual_max": float(max(i["initial_residual"] for i in i_te)),
                            "used": int(sum(i["guess_used"] for i in i_te))},
         "span_projection_in_sweep": {
             "timed_as": "the learned run's training solves + fit without Adam steps + span guess + solve",
+            "parts_s": spi_parts,
             "initial_residual_median": float(np.median([i["initial_residual"] for i in i_spi])),
             "initial_residual_max": float(max(i["initial_residual"] for i in i_spi))},
         "all_converged": bool(ok),

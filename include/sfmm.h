@@ -115,9 +115,11 @@ typedef struct {
                                  has both (for one RHS also the split interpolation
                                  stages and the shared launches of kernel_plan bits 7
                                  and 8) and keep the faster; 0 (default): fixed
-                                 thresholds (matrix cores from 16 RHS, grouped
-                                 translation at 1 RHS and from 16 RHS, the split
-                                 stages and shared launches at 1 RHS)                   */
+                                 thresholds (matrix-core near product from 4 RHS,
+                                 matrix-core aggregation, interpolation and receive
+                                 from 6 RHS, grouped translation at 1 RHS and from
+                                 16 RHS, the split stages and shared launches at
+                                 1 RHS)                                                  */
     int32_t kernel_plan;      /* 0 (default): kernels chosen as `autotune` says; with
                                  bit 0 set, bits 1..5, 7 and 8 fix for every batch size:
                                  matrix-core near product, matrix-core aggregation and

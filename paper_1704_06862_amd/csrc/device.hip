@@ -52,7 +52,14 @@ constexpr int MAXLEV = 21;
 constexpr size_t LDS_LIMIT = 64 * 1024;
 constexpr int BATCH = 64;        // right-hand sides per batched chunk
 constexpr int TRANS_GRP_MIN_R = 16;  // sibling-grouped translation from this many RHS
-constexpr int MMA_MIN_R = 16;    // batched near products from this many RHS run on the matrix cores
+// default plan: the batched near product (also inside the polynomial
+// preconditioner) runs on the matrix cores from NEAR_MMA_MIN_R right-hand
+// sides, aggregation, interpolation and receive from MMA_MIN_R (measured
+// crossovers against the vector kernels on the 61,440- and 307,200-unknown
+// spheres; below them the vector kernels are as fast or faster)
+constexpr int NEAR_MMA_MIN_R = 4;
+constexpr int MMA_MIN_R = 6;
+constexpr int MMA_GATE_R = 2;    // the matrix-core kernels take any batch of at least this many RHS
 
 void *device_alloc(size_t bytes) {
     void *p = nullptr;
@@ -385,7 +392,8 @@ class DeviceBodyT final : public DeviceBody {
     };
     static Plan default_plan(int R) {
         Plan p;
-        p.near_mma = p.agg_mma = p.interp_mma = R >= MMA_MIN_R && std::is_same<T, float>::value;
+        p.near_mma = R >= NEAR_MMA_MIN_R && std::is_same<T, float>::value;
+        p.agg_mma = p.interp_mma = R >= MMA_MIN_R && std::is_same<T, float>::value;
         p.trans_grp = R == 1 || R >= TRANS_GRP_MIN_R;
         p.interp_split = R == 1;
         p.overlap_trans = R == 1;
@@ -444,7 +452,7 @@ class DeviceBodyT final : public DeviceBody {
                 f == &Plan::interp_fused) {
                 if (R != 1) continue;
             } else if (f != &Plan::trans_grp) {
-                if (!std::is_same<T, float>::value || R < MMA_MIN_R) continue;
+                if (!std::is_same<T, float>::value || R < MMA_GATE_R) continue;
             }
             plan_ = best;
             plan_.*f = !(best.*f);
@@ -471,7 +479,7 @@ class DeviceBodyT final : public DeviceBody {
     template <bool POLY>
     void launch_near(int R, const cx<T> *x, cx<T> *y, cx<T> *acc, cx<T> inv_theta, int write_y) {
         if constexpr (std::is_same<T, float>::value) {
-            if (plan_.near_mma && R >= MMA_MIN_R && ntiles_ > 0) {
+            if (plan_.near_mma && R >= MMA_GATE_R && ntiles_ > 0) {
                 launch_near_mma<POLY>(R, x, y, acc, inv_theta, write_y);
                 return;
             }
@@ -628,7 +636,7 @@ class DeviceBodyT final : public DeviceBody {
     void aggregate_region(Reg &G, int R, const cx<T> *x) {
         const int f = f_;
         if constexpr (std::is_same<T, float>::value) {
-            if (plan_.agg_mma && R >= MMA_MIN_R) {
+            if (plan_.agg_mma && R >= MMA_GATE_R) {
                 aggregate_mma(G, R, x);
                 return;
             }
@@ -652,7 +660,7 @@ class DeviceBodyT final : public DeviceBody {
     // launch (the larger-K region first).
     void aggregate_all(int R, const cx<T> *x) {
         bool mma = false;
-        if constexpr (std::is_same<T, float>::value) mma = plan_.agg_mma && R >= MMA_MIN_R;
+        if constexpr (std::is_same<T, float>::value) mma = plan_.agg_mma && R >= MMA_GATE_R;
         if (mma) {
             for (Reg &G : regs_) aggregate_region(G, R, x);
             return;
@@ -694,7 +702,7 @@ class DeviceBodyT final : public DeviceBody {
     void receive_region(Reg &G, int R, cx<T> *y) {
         const int f = f_;
         if constexpr (std::is_same<T, float>::value) {
-            if (plan_.agg_mma && R >= MMA_MIN_R) {
+            if (plan_.agg_mma && R >= MMA_GATE_R) {
                 receive_mma(G, R, y);
                 return;
             }
@@ -909,7 +917,7 @@ class DeviceBodyT final : public DeviceBody {
     }
 
     bool interp_mma_ok(const Reg &G, int l, int R) const {
-        return plan_.interp_mma && R >= MMA_MIN_R && G.Dup[l] && 2 * G.nth[l - 1] <= 64 && 2 * G.nth[l] <= 64 && G.nph[l - 1] <= 64 &&
+        return plan_.interp_mma && R >= MMA_GATE_R && G.Dup[l] && 2 * G.nth[l - 1] <= 64 && 2 * G.nth[l] <= 64 && G.nph[l - 1] <= 64 &&
                G.nph[l] <= 64;
     }
 

@@ -87,10 +87,10 @@ def ctxbf(sphere960):
         yield c
 
 
-@pytest.mark.parametrize("R", [16, 20, 64])
+@pytest.mark.parametrize("R", [4, 7, 16, 20, 64])
 def test_batched_near_on_matrix_cores(sphere960, ctx32, ctxbf, R):
-    # from 16 right-hand sides the near product runs on the matrix cores;
-    # 20 leaves a ragged second block of 16
+    # from 4 right-hand sides the near product runs on the matrix cores;
+    # 4 and 7 fill part of one block of 16, 20 leaves a ragged second block
     x = random_complex_vector(sphere960["x"].shape[1], R, seed=40 + R)
     ref = x @ np.where(sphere960["pat"], sphere960["Z"], 0).T
     for ctx, tol in ((ctx32, 1e-5), (ctxbf, 5e-5)):
@@ -100,10 +100,10 @@ def test_batched_near_on_matrix_cores(sphere960, ctx32, ctxbf, R):
         assert err < tol
 
 
-@pytest.mark.parametrize("R", [16, 64])
+@pytest.mark.parametrize("R", [5, 7, 16, 64])
 def test_batched_full_product_on_matrix_cores(sphere960, ctx32f, ctxbff, R):
-    # aggregation, receive (and, from 33 RHS, the sibling-grouped translation)
-    # switch to their batched kernels
+    # aggregation, interpolation and receive run on the matrix cores from 6
+    # RHS (5: near product only), the sibling-grouped translation from 16
     x = random_complex_vector(sphere960["x"].shape[1], R, seed=60 + R)
     ref = x @ sphere960["Z"].T
     for ctx in (ctx32f, ctxbff):
