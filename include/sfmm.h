@@ -115,7 +115,7 @@ typedef struct {
                                  has both (for one RHS also the split interpolation
                                  stages and the shared launches of kernel_plan bits 7
                                  and 8) and keep the faster; 0 (default): fixed
-                                 thresholds (matrix-core near product from 4 RHS,
+                                 thresholds (matrix-core near product from 3 RHS,
                                  matrix-core aggregation, interpolation and receive
                                  from 6 RHS, grouped translation at 1 RHS and from
                                  16 RHS, the split stages and shared launches at

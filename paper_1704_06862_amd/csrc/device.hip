@@ -57,7 +57,7 @@ constexpr int TRANS_GRP_MIN_R = 16;  // sibling-grouped translation from this ma
 // sides, aggregation, interpolation and receive from MMA_MIN_R (measured
 // crossovers against the vector kernels on the 61,440- and 307,200-unknown
 // spheres; below them the vector kernels are as fast or faster)
-constexpr int NEAR_MMA_MIN_R = 4;
+constexpr int NEAR_MMA_MIN_R = 3;
 constexpr int MMA_MIN_R = 6;
 constexpr int MMA_GATE_R = 2;    // the matrix-core kernels take any batch of at least this many RHS
 
@@ -1804,32 +1804,50 @@ class DeviceBodyT final : public DeviceBody {
                 std::vector<char> done(Ra, 0);
                 for (int a = 0; a < Ra; ++a) g[(size_t)a * (m + 1)] = g0[a];
                 auto Hs = [&](int a, int i, int j) -> cd & { return H[((size_t)a * (m + 1) + i) * m + j]; };
+                // positions of the cycle still iterating: a slot whose residual
+                // estimate has met the tolerance leaves the batch at once (its
+                // Arnoldi relation is complete at cnt steps), so the products
+                // of the rest of the cycle run on the smaller batch
+                std::vector<int> cur(Ra);
+                for (int a = 0; a < Ra; ++a) cur[a] = a;
                 for (int j = 0; j < m; ++j) {
                     double2 *Vj = kV_ + (size_t)j * ldj;
                     double2 *W = kV_ + (size_t)(j + 1) * ldj;
-                    op_apply(Vj, W, kZ_ + (size_t)j * ldj, Ra, prec, true);
-                    for (int a = 0; a < Ra; ++a)
-                        if (!done[a]) ++its[act[a]];
-                    std::vector<cd> hsum((size_t)Ra * (j + 1), 0.0);
+                    {
+                        std::vector<int> nc;
+                        for (int a : cur)
+                            if (!done[a]) nc.push_back(a);
+                        if (nc.size() != cur.size() || j == 0) {
+                            cur = nc;
+                            std::vector<int> sub;
+                            for (int a : cur) sub.push_back(act[a]);
+                            upload_act(sub);
+                        }
+                    }
+                    const int Rc = (int)cur.size();
+                    op_apply(Vj, W, kZ_ + (size_t)j * ldj, Rc, prec, true);
+                    for (int a : cur) ++its[act[a]];
+                    std::vector<cd> hsum((size_t)Rc * (j + 1), 0.0);
                     for (int pass = 0; pass < 2; ++pass) {
-                        k_bdots<<<dim3(red_blocks_, j + 1, Ra), WG, 0, stream_>>>(kV_, ldj, N, W, dact_, N, j + 1,
+                        k_bdots<<<dim3(red_blocks_, j + 1, Rc), WG, 0, stream_>>>(kV_, ldj, N, W, dact_, N, j + 1,
                                                                                   dpartc_);
                         LAUNCHCHK();
-                        k_sum_partials<<<Ra * (j + 1), 64, 0, stream_>>>(dpartc_, red_blocks_, dh_);
+                        k_sum_partials<<<Rc * (j + 1), 64, 0, stream_>>>(dpartc_, red_blocks_, dh_);
                         LAUNCHCHK();
-                        k_bsub<<<dim3(nblocks(N), Ra), WG, 0, stream_>>>(kV_, ldj, N, j + 1, dact_, N, dh_, W);
+                        k_bsub<<<dim3(nblocks(N), Rc), WG, 0, stream_>>>(kV_, ldj, N, j + 1, dact_, N, dh_, W);
                         LAUNCHCHK();
-                        std::vector<double2> hh((size_t)Ra * (j + 1));
+                        std::vector<double2> hh((size_t)Rc * (j + 1));
                         copy_d2h(hh.data(), dh_, sizeof(double2) * hh.size(), stream_);
                         for (size_t q = 0; q < hh.size(); ++q) hsum[q] += cd(hh[q].x, hh[q].y);
                     }
-                    std::vector<double> hn = norms(W, Ra);
-                    std::vector<double> sc(Ra);
-                    for (int a = 0; a < Ra; ++a) {
-                        for (int i = 0; i <= j; ++i) Hs(a, i, j) = hsum[(size_t)a * (j + 1) + i];
-                        Hs(a, j + 1, j) = hn[a];
-                        const bool breakdown = !(hn[a] > 0);
-                        sc[a] = breakdown ? 0.0 : 1.0 / hn[a];
+                    std::vector<double> hn = norms(W, Rc);
+                    std::vector<double> sc(Rc);
+                    for (int q = 0; q < Rc; ++q) {
+                        const int a = cur[q];
+                        for (int i = 0; i <= j; ++i) Hs(a, i, j) = hsum[(size_t)q * (j + 1) + i];
+                        Hs(a, j + 1, j) = hn[q];
+                        const bool breakdown = !(hn[q] > 0);
+                        sc[q] = breakdown ? 0.0 : 1.0 / hn[q];
                         for (int i = 0; i < j; ++i) {
                             const cd x1 = Hs(a, i, j), x2 = Hs(a, i + 1, j);
                             const double c = cs[(size_t)a * m + i];
@@ -1859,17 +1877,16 @@ class DeviceBodyT final : public DeviceBody {
                         cd &gj = g[(size_t)a * (m + 1) + j];
                         g[(size_t)a * (m + 1) + j + 1] = -std::conj(sv) * gj;
                         gj = c * gj;
-                        if (!done[a]) {
-                            cnt[a] = j + 1;
-                            const double est = std::abs(g[(size_t)a * (m + 1) + j + 1]) / nb[act[a]];
-                            if (est <= tol || its[act[a]] >= max_iters || breakdown) done[a] = 1;
-                        }
+                        cnt[a] = j + 1;
+                        const double est = std::abs(g[(size_t)a * (m + 1) + j + 1]) / nb[act[a]];
+                        if (est <= tol || its[act[a]] >= max_iters || breakdown) done[a] = 1;
                     }
-                    stage_h2d(dscal_, sc.data(), sizeof(double) * Ra);
-                    k_bscale<<<dim3(nblocks(N), Ra), WG, 0, stream_>>>(dscal_, dact_, N, N, W);
+                    stage_h2d(dscal_, sc.data(), sizeof(double) * Rc);
+                    k_bscale<<<dim3(nblocks(N), Rc), WG, 0, stream_>>>(dscal_, dact_, N, N, W);
                     LAUNCHCHK();
                     if (std::all_of(done.begin(), done.end(), [](char d) { return d != 0; })) break;
                 }
+                upload_act(act);   // the update below covers every slot of the cycle
                 // x += Z y with y = H^-1 g over each slot's own step count
                 std::vector<double2> ys((size_t)Ra * m, make_double2(0, 0));
                 for (int a = 0; a < Ra; ++a) {

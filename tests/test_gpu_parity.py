@@ -87,10 +87,10 @@ def ctxbf(sphere960):
         yield c
 
 
-@pytest.mark.parametrize("R", [4, 7, 16, 20, 64])
+@pytest.mark.parametrize("R", [3, 7, 16, 20, 64])
 def test_batched_near_on_matrix_cores(sphere960, ctx32, ctxbf, R):
-    # from 4 right-hand sides the near product runs on the matrix cores;
-    # 4 and 7 fill part of one block of 16, 20 leaves a ragged second block
+    # from 3 right-hand sides the near product runs on the matrix cores;
+    # 3 and 7 fill part of one block of 16, 20 leaves a ragged second block
     x = random_complex_vector(sphere960["x"].shape[1], R, seed=40 + R)
     ref = x @ np.where(sphere960["pat"], sphere960["Z"], 0).T
     for ctx, tol in ((ctx32, 1e-5), (ctxbf, 5e-5)):
