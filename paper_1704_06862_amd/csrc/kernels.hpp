@@ -177,11 +177,13 @@ __device__ __forceinline__ void near_block(const NearArgs<T> &a, int b, int rg, 
     const int r0 = a.bstart[b], nrow = a.bstart[b + 1] - r0;
     if (rg * NRW >= nrow) return;            // uniform over the workgroup
     const int c0 = a.col_ptr[b], ncol = a.col_ptr[b + 1] - c0;
+    // LDS: the J inputs of all columns, then the M inputs ([2][ncol][RT]), so
+    // that lanes reading consecutive columns touch consecutive 8-byte words
     if (LDS) {
         for (int t = threadIdx.x; t < ncol * 2 * RT; t += NRW * 64) {
-            const int c = t / (2 * RT), hr = t % (2 * RT);
+            const int c = t / (2 * RT), hr = t % (2 * RT), h = hr / RT, r = hr % RT;
             const int p = a.cols[c0 + c];
-            xs[t] = a.x[(int64_t)(2 * p + hr / RT) * a.R + rhs0 + hr % RT];
+            xs[(h * ncol + c) * RT + r] = a.x[(int64_t)(2 * p + h) * a.R + rhs0 + r];
         }
         __syncthreads();
     }
@@ -192,8 +194,8 @@ __device__ __forceinline__ void near_block(const NearArgs<T> &a, int b, int rg, 
     const int64_t rb = a.val_ptr[b] + (int64_t)row * ncol;
     auto xin = [&](int c, cx<T> &xj, cx<T> &xm) {
         if (LDS) {
-            xj = xs[(2 * c) * RT + rr];
-            xm = xs[(2 * c + 1) * RT + rr];
+            xj = xs[c * RT + rr];
+            xm = xs[(ncol + c) * RT + rr];
         } else {
             const int p = a.cols[c0 + c];
             xj = a.x[(int64_t)(2 * p) * a.R + rhs0 + rr];
