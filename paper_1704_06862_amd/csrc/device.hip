@@ -161,6 +161,17 @@ class DeviceBodyT final : public DeviceBody {
         // weight of the tangential parts: JMCFIE = (N parts) - (T parts)
         tang_ = h.form == SFMM_FORM_CNF ? cx<T>{0, 0} : cx<T>{-1, 0};
         precond_ = h.precond;
+        if constexpr (std::is_same<T, float>::value) {
+            if (precond_ == SFMM_PRECOND_POLY) {
+                // bfloat16 copy of the blocks for the polynomial preconditioner
+                // (a fixed approximation of the near-field inverse: half the
+                // bytes of its products; GMRES still converges on Z itself)
+                h16A_ = upload_bf16x2(h.near.A);
+                h16B_ = upload_bf16x2(h.near.B);
+                h16C_ = upload_bf16x2(h.near.C);
+                if (gen_) h16D_ = upload_bf16x2(h.near.D);
+            }
+        }
         for (const cd &t : h.poly) inv_theta_.push_back(to_cx<T>(1.0 / t));
         if (!h.poly_dinv.empty()) dinv_ = upload_cx(h.poly_dinv);
         for (int b = 0; b < nb_; ++b) {
@@ -490,10 +501,22 @@ class DeviceBodyT final : public DeviceBody {
         const int t = lds ? rt : 1;
         dim3 grid(nb_, (max_nrow_ + RW - 1) / RW, R / t);
         const size_t shm = lds ? (size_t)max_ncol_ * 2 * t * sizeof(cx<T>) : 0;
-#define SFMM_NEAR_(RT_, L_, G_)                                                                                   \
-    k_near<T, RT_, L_, POLY, G_><<<grid, RWG, shm, stream_>>>(R, bstart_, near_col_ptr_, near_cols_, near_val_ptr_, \
-                                                              nA_, nB_, nC_, nD_, x, y, acc, inv_theta, write_y,    \
-                                                              POLY ? dinv_ : nullptr)
+        // the polynomial preconditioner reads the bfloat16 copy of the blocks
+        const bool h16 = POLY && h16A_ != nullptr;
+#define SFMM_NEAR_H(RT_, L_, G_, H_)                                                                                 \
+    k_near<T, RT_, L_, POLY, G_, H_><<<grid, RWG, shm, stream_>>>(R, bstart_, near_col_ptr_, near_cols_,              \
+                                                                  near_val_ptr_, nA_, nB_, nC_, nD_, x, y, acc,     \
+                                                                  inv_theta, write_y, POLY ? dinv_ : nullptr,       \
+                                                                  h16A_, h16B_, h16C_, h16D_)
+#define SFMM_NEAR_(RT_, L_, G_)                                    \
+    do {                                                           \
+        if constexpr (POLY && std::is_same<T, float>::value) {    \
+            if (h16) SFMM_NEAR_H(RT_, L_, G_, true);               \
+            else SFMM_NEAR_H(RT_, L_, G_, false);                  \
+        } else {                                                   \
+            SFMM_NEAR_H(RT_, L_, G_, false);                       \
+        }                                                          \
+    } while (0)
 #define SFMM_NEAR(RT_, L_)                  \
     do {                                    \
         if (gen_) SFMM_NEAR_(RT_, L_, true);  \
@@ -506,6 +529,7 @@ class DeviceBodyT final : public DeviceBody {
         else SFMM_NEAR(1, true);
 #undef SFMM_NEAR
 #undef SFMM_NEAR_
+#undef SFMM_NEAR_H
         LAUNCHCHK();
     }
 
@@ -2075,6 +2099,21 @@ class DeviceBodyT final : public DeviceBody {
         for (size_t i = 0; i < v.size(); ++i) t[i] = to_cx<T>(v[i]);
         return upload(t);
     }
+    // (re, im) rounded to bfloat16 (to nearest even, through FP32), packed
+    // low/high in 32 bits
+    uint32_t *upload_bf16x2(const std::vector<cd> &v) {
+        auto bf = [](double d) -> uint32_t {
+            const float f = (float)d;
+            uint32_t u;
+            std::memcpy(&u, &f, 4);
+            if ((u & 0x7f800000u) == 0x7f800000u) return u >> 16;   // inf / nan kept
+            u += 0x7fffu + ((u >> 16) & 1u);
+            return u >> 16;
+        };
+        std::vector<uint32_t> t(v.size());
+        for (size_t i = 0; i < v.size(); ++i) t[i] = bf(v[i].real()) | (bf(v[i].imag()) << 16);
+        return upload(t);
+    }
     T *upload_real(const std::vector<double> &v) {
         std::vector<T> t(v.begin(), v.end());
         return upload(t);
@@ -2157,6 +2196,7 @@ class DeviceBodyT final : public DeviceBody {
     int *near_col_ptr_ = nullptr, *near_cols_ = nullptr;
     int64_t *near_val_ptr_ = nullptr;
     cx<T> *nA_ = nullptr, *nB_ = nullptr, *nC_ = nullptr;
+    uint32_t *h16A_ = nullptr, *h16B_ = nullptr, *h16C_ = nullptr, *h16D_ = nullptr;
     cx<T> *nD_ = nullptr;          // H-row J coefficient of the general block (JMCFIE / CNF)
     char *pin_ = nullptr;          // pinned staging arena of stage_h2d
     size_t pin_cap_ = 0, pin_off_ = 0;

@@ -166,13 +166,21 @@ struct NearArgs {
     int write_y;
     const cx<T> *dinv;
     const cx<T> *D = nullptr;   // general block [[A, -B], [D, C]] (GEN kernels)
+    // the same blocks rounded to bfloat16, (re, im) packed low/high in 32 bits
+    // (H16 kernels: the polynomial preconditioner's products)
+    const uint32_t *A16 = nullptr, *B16 = nullptr, *C16 = nullptr, *D16 = nullptr;
 };
+
+__device__ __forceinline__ cx<float> unpack_bf16x2(uint32_t u) {
+    return cx<float>{__uint_as_float(u << 16), __uint_as_float(u & 0xffff0000u)};
+}
 
 // One workgroup of the near-field product: NRW rows (one wavefront each) of
 // box b from row NRW * rg on, right-hand sides rhs0 .. rhs0 + RT - 1; xs is
 // the LDS staging area of the box's input columns.
-template <typename T, int RT, bool LDS, bool POLY, int NRW, bool GEN = false>
+template <typename T, int RT, bool LDS, bool POLY, int NRW, bool GEN = false, bool H16 = false>
 __device__ __forceinline__ void near_block(const NearArgs<T> &a, int b, int rg, int rhs0, cx<T> *xs) {
+    static_assert(!H16 || std::is_same<T, float>::value, "bfloat16 blocks are read into FP32");
     constexpr int NCG = 64 / RT;
     const int r0 = a.bstart[b], nrow = a.bstart[b + 1] - r0;
     if (rg * NRW >= nrow) return;            // uniform over the workgroup
@@ -202,12 +210,22 @@ __device__ __forceinline__ void near_block(const NearArgs<T> &a, int b, int rg, 
             xm = a.x[(int64_t)(2 * p + 1) * a.R + rhs0 + rr];
         }
     };
+    // block entry i of plane P (FP32/FP64 or bfloat16 storage)
+    auto ld = [&](const cx<T> *P, const uint32_t *P16, int64_t i) -> cx<T> {
+        if constexpr (H16) {
+            const cx<float> v = unpack_bf16x2(P16[i]);
+            return cx<T>{v.x, v.y};
+        } else {
+            return P[i];
+        }
+    };
     cx<T> aE = {0, 0}, aH = {0, 0}, bE = {0, 0}, bH = {0, 0};
     int c = cg;
     for (; c + NCG < ncol; c += 2 * NCG) {
-        const cx<T> a0 = a.A[rb + c], b0 = a.B[rb + c], c0v = a.C[rb + c];
-        const cx<T> a1 = a.A[rb + c + NCG], b1 = a.B[rb + c + NCG], c1v = a.C[rb + c + NCG];
-        const cx<T> d0 = GEN ? a.D[rb + c] : b0, d1 = GEN ? a.D[rb + c + NCG] : b1;
+        const cx<T> a0 = ld(a.A, a.A16, rb + c), b0 = ld(a.B, a.B16, rb + c), c0v = ld(a.C, a.C16, rb + c);
+        const cx<T> a1 = ld(a.A, a.A16, rb + c + NCG), b1 = ld(a.B, a.B16, rb + c + NCG),
+                    c1v = ld(a.C, a.C16, rb + c + NCG);
+        const cx<T> d0 = GEN ? ld(a.D, a.D16, rb + c) : b0, d1 = GEN ? ld(a.D, a.D16, rb + c + NCG) : b1;
         cx<T> xj0, xm0, xj1, xm1;
         xin(c, xj0, xm0);
         xin(c + NCG, xj1, xm1);
@@ -221,8 +239,8 @@ __device__ __forceinline__ void near_block(const NearArgs<T> &a, int b, int rg, 
         cfma(bH, c1v, xm1);
     }
     if (c < ncol) {
-        const cx<T> a0 = a.A[rb + c], b0 = a.B[rb + c], c0v = a.C[rb + c];
-        const cx<T> d0 = GEN ? a.D[rb + c] : b0;
+        const cx<T> a0 = ld(a.A, a.A16, rb + c), b0 = ld(a.B, a.B16, rb + c), c0v = ld(a.C, a.C16, rb + c);
+        const cx<T> d0 = GEN ? ld(a.D, a.D16, rb + c) : b0;
         cx<T> xj0, xm0;
         xin(c, xj0, xm0);
         cfma(aE, a0, xj0);
@@ -260,18 +278,25 @@ __device__ __forceinline__ void near_block(const NearArgs<T> &a, int b, int rg, 
 
 // Grid: (finest boxes, row groups of RW rows, RHS tiles).  GEN: general
 // blocks [[A, -B], [D, C]] (JMCFIE / CNF); otherwise D = B (PMCHWT).
-template <typename T, int RT, bool LDS, bool POLY, bool GEN>
+// H16: the blocks are read from their bfloat16 copies A16 .. D16.
+template <typename T, int RT, bool LDS, bool POLY, bool GEN, bool H16 = false>
 __global__ void __launch_bounds__(RWG) k_near(int R, const int *__restrict__ bstart, const int *__restrict__ col_ptr,
                                               const int *__restrict__ cols, const int64_t *__restrict__ val_ptr,
                                               const cx<T> *__restrict__ A, const cx<T> *__restrict__ B,
                                               const cx<T> *__restrict__ C, const cx<T> *__restrict__ D,
                                               const cx<T> *__restrict__ x, cx<T> *__restrict__ y,
                                               cx<T> *__restrict__ acc, cx<T> inv_theta, int write_y,
-                                              const cx<T> *__restrict__ dinv) {
+                                              const cx<T> *__restrict__ dinv, const uint32_t *__restrict__ A16,
+                                              const uint32_t *__restrict__ B16, const uint32_t *__restrict__ C16,
+                                              const uint32_t *__restrict__ D16) {
     extern __shared__ unsigned char lds_raw[];
-    const NearArgs<T> a{R, bstart, col_ptr, cols, val_ptr, A, B, C, x, y, acc, inv_theta, write_y, dinv, D};
-    near_block<T, RT, LDS, POLY, RW, GEN>(a, (int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z * RT,
-                                          reinterpret_cast<cx<T> *>(lds_raw));
+    NearArgs<T> a{R, bstart, col_ptr, cols, val_ptr, A, B, C, x, y, acc, inv_theta, write_y, dinv, D};
+    a.A16 = A16;
+    a.B16 = B16;
+    a.C16 = C16;
+    a.D16 = D16;
+    near_block<T, RT, LDS, POLY, RW, GEN, H16>(a, (int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z * RT,
+                                               reinterpret_cast<cx<T> *>(lds_raw));
 }
 
 // ---------------------------------------------------------------------------

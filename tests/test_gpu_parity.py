@@ -402,6 +402,51 @@ def test_polynomial_preconditioner_fp64(sphere960):
     assert rel(z, ref) < 1e-9
 
 
+def _bf16(a):
+    # FP64 -> FP32 -> bfloat16 (nearest even) per real component
+    def r(v):
+        u = v.astype(np.float32).view(np.uint32).astype(np.uint64)
+        u = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+        return u.view(np.float32).astype(np.float64)
+    return r(a.real) + 1j * r(a.imag)
+
+
+@pytest.mark.parametrize("R", [1, 2])
+def test_polynomial_preconditioner_bf16_blocks(sphere960, R):
+    # FP32 contexts apply the polynomial at one and two right-hand sides with
+    # bfloat16 copies of the near blocks: the oracle's polynomial (roots of
+    # the exact near matrix) applied with the bfloat16-rounded blocks is the
+    # reference (measured within 1e-5), the unrounded one within 2e-2, and
+    # the preconditioned solve needs at most 2 more iterations than FP64's
+    Zn = np.where(sphere960["pat"], sphere960["Z"], 0)
+    Dinv = krylov.edge_blocks_inverse(Zn)
+    th = krylov.leja_order(krylov.harmonic_ritz(lambda u: krylov.edge_blocks_apply(Dinv, Zn @ u),
+                                                krylov.golden_start(Zn.shape[0]), 16))
+    Zh = _bf16(Zn)
+    x = sphere960["x"][:R].copy()
+    opts = dict(finest_box=0.2, n_levels=3, preconditioner=sfmm.PRECOND_POLY, poly_degree=16, tol=1e-4)
+    with sfmm.Context([sphere960["body"]], precision=sfmm.PREC_FP32, **opts) as ctx:
+        z = ctx.sfmm_precond(x, np.zeros_like(x))
+        ref_h = np.array([krylov.poly_apply(lambda u: krylov.edge_blocks_apply(Dinv, Zh @ u), th,
+                                            krylov.edge_blocks_apply(Dinv, v)) for v in x])
+        ref = np.array([krylov.poly_apply(lambda u: krylov.edge_blocks_apply(Dinv, Zn @ u), th,
+                                          krylov.edge_blocks_apply(Dinv, v)) for v in x])
+        e_h, e = rel(z, ref_h), rel(z, ref)
+        print(R, "bf16-block poly vs rounded reference", e_h, "vs exact", e)
+        assert e_h < 1e-4 and e < 2e-2
+        m, b = sphere960["mesh"], sphere960["body"]
+        kh, eh = mom.incidence(0.0, 0.0)
+        rhs = mom.planewave_rhs(m, b.frequency, kh, eh)[None, :].copy()
+        xs = np.zeros_like(rhs)
+        info = ctx.sfmm_solve(rhs, xs)[0]
+    with sfmm.Context([sphere960["body"]], precision=sfmm.PREC_FP64, **opts) as c64:
+        x64 = np.zeros_like(rhs)
+        i64 = c64.sfmm_solve(rhs, x64)[0]
+    print("poly solve fp32 bf16 blocks", info["iterations"], "fp64", i64["iterations"])
+    assert info["converged"] and i64["converged"]
+    assert info["iterations"] <= i64["iterations"] + 2
+
+
 def test_polynomial_preconditioned_solve_matches_oracle(sphere960):
     M = _oracle_poly(sphere960, 16)
     m, b, Z = sphere960["mesh"], sphere960["body"], sphere960["Z"]
