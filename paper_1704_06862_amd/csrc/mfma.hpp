@@ -124,13 +124,28 @@ __global__ void __launch_bounds__(64 * MMA_WAVES)
                 mma_f32(aHi[n], c.y, xm.x);
             }
         } else {
+            // the polynomial preconditioner reads only the hi (bfloat16) part
+            // of the blocks: two matrix-core products per step instead of three
+            constexpr bool AHI = POLY;
             const bf16x8 *V = reinterpret_cast<const bf16x8 *>(vals);
             const int64_t pl = nsteps * 64;
-            const bf16x8 arh = V[vi], arl = V[pl + vi], aih = V[2 * pl + vi], ail = V[3 * pl + vi];
-            const bf16x8 brh = V[4 * pl + vi], brl = V[5 * pl + vi], bih = V[6 * pl + vi], bil = V[7 * pl + vi];
-            const bf16x8 crh = V[8 * pl + vi], crl = V[9 * pl + vi], cih = V[10 * pl + vi], cil = V[11 * pl + vi];
-            const bf16x8 drh = GEN ? V[12 * pl + vi] : brh, drl = GEN ? V[13 * pl + vi] : brl;
-            const bf16x8 dih = GEN ? V[14 * pl + vi] : bih, dil = GEN ? V[15 * pl + vi] : bil;
+            const bf16x8 z8 = {};
+            const bf16x8 arh = V[vi], aih = V[2 * pl + vi], brh = V[4 * pl + vi], bih = V[6 * pl + vi];
+            const bf16x8 crh = V[8 * pl + vi], cih = V[10 * pl + vi];
+            const bf16x8 arl = AHI ? z8 : V[pl + vi], ail = AHI ? z8 : V[3 * pl + vi];
+            const bf16x8 brl = AHI ? z8 : V[5 * pl + vi], bil = AHI ? z8 : V[7 * pl + vi];
+            const bf16x8 crl = AHI ? z8 : V[9 * pl + vi], cil = AHI ? z8 : V[11 * pl + vi];
+            const bf16x8 drh = GEN ? V[12 * pl + vi] : brh, drl = GEN ? (AHI ? z8 : V[13 * pl + vi]) : brl;
+            const bf16x8 dih = GEN ? V[14 * pl + vi] : bih, dil = GEN ? (AHI ? z8 : V[15 * pl + vi]) : bil;
+            auto mma_split = [](f32x4 &c, const bf16x8 &ah, const bf16x8 &al, const bf16x8 &bh, const bf16x8 &bl) {
+                if constexpr (AHI) {
+                    (void)al;
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+                } else {
+                    sfmm::mma_split(c, ah, al, bh, bl);
+                }
+            };
             const bf16x8 naih = neg8(aih), nail = neg8(ail), nbrh = neg8(brh), nbrl = neg8(brl);
             const bf16x8 nbih = neg8(bih), nbil = neg8(bil), ncih = neg8(cih), ncil = neg8(cil);
             const bf16x8 ndih = neg8(dih), ndil = neg8(dil);
