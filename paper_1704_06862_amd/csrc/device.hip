@@ -1851,20 +1851,32 @@ class DeviceBodyT final : public DeviceBody {
                     const int Rc = (int)cur.size();
                     op_apply(Vj, W, kZ_ + (size_t)j * ldj, Rc, prec, true);
                     for (int a : cur) ++its[act[a]];
-                    std::vector<cd> hsum((size_t)Rc * (j + 1), 0.0);
+                    // classical Gram-Schmidt, twice; both passes' coefficients
+                    // and the new vector's norm come back in one read-back
+                    const size_t nh = (size_t)Rc * (j + 1);
                     for (int pass = 0; pass < 2; ++pass) {
                         k_bdots<<<dim3(red_blocks_, j + 1, Rc), WG, 0, stream_>>>(kV_, ldj, N, W, dact_, N, j + 1,
                                                                                   dpartc_);
                         LAUNCHCHK();
-                        k_sum_partials<<<Rc * (j + 1), 64, 0, stream_>>>(dpartc_, red_blocks_, dh_);
+                        k_sum_partials<<<Rc * (j + 1), 64, 0, stream_>>>(dpartc_, red_blocks_, dh2_ + pass * nh);
                         LAUNCHCHK();
-                        k_bsub<<<dim3(nblocks(N), Rc), WG, 0, stream_>>>(kV_, ldj, N, j + 1, dact_, N, dh_, W);
+                        k_bsub<<<dim3(nblocks(N), Rc), WG, 0, stream_>>>(kV_, ldj, N, j + 1, dact_, N,
+                                                                          dh2_ + pass * nh, W);
                         LAUNCHCHK();
-                        std::vector<double2> hh((size_t)Rc * (j + 1));
-                        copy_d2h(hh.data(), dh_, sizeof(double2) * hh.size(), stream_);
-                        for (size_t q = 0; q < hh.size(); ++q) hsum[q] += cd(hh[q].x, hh[q].y);
                     }
-                    std::vector<double> hn = norms(W, Rc);
+                    k_bnorm2<<<dim3(red_blocks_, Rc), WG, 0, stream_>>>(W, N, dact_, N, dpart_);
+                    LAUNCHCHK();
+                    k_sum_real<<<Rc, 64, 0, stream_>>>(dpart_, red_blocks_, dscal_);
+                    LAUNCHCHK();
+                    std::vector<double2> hh(2 * nh);
+                    std::vector<double> hn(Rc);
+                    HIPCHK(hipMemcpyAsync(hh.data(), dh2_, sizeof(double2) * hh.size(), hipMemcpyDeviceToHost,
+                                          stream_));
+                    HIPCHK(hipMemcpyAsync(hn.data(), dscal_, sizeof(double) * Rc, hipMemcpyDeviceToHost, stream_));
+                    HIPCHK(hipStreamSynchronize(stream_));
+                    std::vector<cd> hsum(nh);
+                    for (size_t q = 0; q < nh; ++q) hsum[q] = cd(hh[q].x + hh[nh + q].x, hh[q].y + hh[nh + q].y);
+                    for (double &v : hn) v = std::sqrt(v);
                     std::vector<double> sc(Rc);
                     for (int q = 0; q < Rc; ++q) {
                         const int a = cur[q];
@@ -2167,6 +2179,7 @@ class DeviceBodyT final : public DeviceBody {
         dpartc_ = alloc_in<double2>(krylov_allocs_, (size_t)(kM_ + 1) * kR_ * red_blocks_);
         dpart_ = alloc_in<double>(krylov_allocs_, (size_t)kR_ * red_blocks_);
         dh_ = alloc_in<double2>(krylov_allocs_, (size_t)(kM_ + 1) * kR_);
+        dh2_ = alloc_in<double2>(krylov_allocs_, (size_t)2 * (kM_ + 1) * kR_);
         dscal_ = alloc_in<double>(krylov_allocs_, kR_);
         dact_ = alloc_in<int>(krylov_allocs_, kR_);
         dcnt_ = alloc_in<int>(krylov_allocs_, kR_);
@@ -2233,7 +2246,7 @@ class DeviceBodyT final : public DeviceBody {
     cx<T> *xi_ = nullptr, *yi_ = nullptr, *zi_ = nullptr, *wi_ = nullptr, *pt_ = nullptr;
     int kM_ = 0, kR_ = 0, red_blocks_ = 1;
     double2 *kV_ = nullptr, *kZ_ = nullptr, *kb_ = nullptr, *kx_ = nullptr;
-    double2 *dpartc_ = nullptr, *dh_ = nullptr;
+    double2 *dpartc_ = nullptr, *dh_ = nullptr, *dh2_ = nullptr;
     double *dpart_ = nullptr, *dscal_ = nullptr;
     int *dact_ = nullptr, *dcnt_ = nullptr;
     std::vector<void *> allocs_, batch_allocs_, krylov_allocs_;
