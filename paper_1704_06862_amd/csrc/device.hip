@@ -548,7 +548,27 @@ class DeviceBodyT final : public DeviceBody {
         if (gen_) SFMM_NMMA_(NT_, S_, true);  \
         else SFMM_NMMA_(NT_, S_, false);      \
     } while (0)
-        if (split_) {
+        if (POLY && !ptvals_) throw Error(SFMM_E_DEVICE, "polynomial preconditioner tiles missing");
+        if (POLY) {
+            // the polynomial preconditioner: bfloat16 tiles of its own
+            const unsigned pg = (unsigned)((pntiles_ + 7) / 8 * 8);
+#define SFMM_PMMA_(NT_, G_)                                                                                        \
+    k_near_mma<NT_, true, true, G_><<<pg, 64 * MMA_WAVES, 0, stream_>>>(R, ptile_box_, ptile_row0_, ptile_step_,  \
+                                                                        bstart_, near_col_ptr_, near_cols_,       \
+                                                                        ptvals_, pnsteps_, x, y, acc, inv_theta,  \
+                                                                        write_y, dinv_, pntiles_)
+#define SFMM_PMMA(NT_)                  \
+    do {                                \
+        if (gen_) SFMM_PMMA_(NT_, true);  \
+        else SFMM_PMMA_(NT_, false);      \
+    } while (0)
+            if (nt == 1) SFMM_PMMA(1);
+            else if (nt == 2) SFMM_PMMA(2);
+            else if (nt == 3) SFMM_PMMA(3);
+            else SFMM_PMMA(4);
+#undef SFMM_PMMA
+#undef SFMM_PMMA_
+        } else if (split_) {
             if (nt == 1) SFMM_NMMA(1, true);
             else if (nt == 2) SFMM_NMMA(2, true);
             else if (nt == 3) SFMM_NMMA(3, true);
@@ -567,6 +587,66 @@ class DeviceBodyT final : public DeviceBody {
     // Near-field matrix in matrix-core tile order (see k_near_mma): tiles of
     // 16 rows of one box, K steps of 4 (FP32) or 32 (bf16 split) columns.
     void build_mma_tiles(const BodyHost &h) {
+        build_product_tiles(h);
+        if (precond_ == SFMM_PRECOND_POLY) build_poly_tiles(h);
+    }
+
+    // bfloat16 tiles of the blocks for the polynomial preconditioner's
+    // matrix-core products: K steps of 32 columns, eight (PMCHWT: six)
+    // compact planes (A, B, C[, D]) x (re, im), 8 bf16 per lane, each value
+    // rounded to nearest even through FP32
+    void build_poly_tiles(const BodyHost &h) {
+        const Octree &o = h.oct;
+        const NearMatrix &Z = h.near;
+        std::vector<int> tbox, trow0;
+        std::vector<int64_t> tstep{0};
+        for (int b = 0; b < nb_; ++b) {
+            const int nrow = o.bstart[b + 1] - o.bstart[b], ncol = Z.col_ptr[b + 1] - Z.col_ptr[b];
+            const int nks = (ncol + 31) / 32;
+            for (int row0 = 0; row0 < nrow; row0 += 16) {
+                tbox.push_back(b);
+                trow0.push_back(row0);
+                tstep.push_back(tstep.back() + nks);
+            }
+        }
+        if (tbox.empty() || tstep.back() == 0) return;
+        pntiles_ = (int)tbox.size();
+        pnsteps_ = tstep.back();
+        const std::vector<cd> *mats[4] = {&Z.A, &Z.B, &Z.C, &Z.D};
+        const int np = Z.D.empty() ? 3 : 4;
+        auto rne = [](double v) {
+            const float f = (float)v;
+            uint32_t u;
+            std::memcpy(&u, &f, 4);
+            u += 0x7fffu + ((u >> 16) & 1u);
+            return (uint16_t)(u >> 16);
+        };
+        std::vector<uint16_t> V((size_t)2 * np * pnsteps_ * 64 * 8, 0);
+        for (int t = 0; t < pntiles_; ++t) {
+            const int b = tbox[t], row0 = trow0[t];
+            const int nrow = o.bstart[b + 1] - o.bstart[b], ncol = Z.col_ptr[b + 1] - Z.col_ptr[b];
+            for (int64_t st = tstep[t]; st < tstep[t + 1]; ++st) {
+                const int s = (int)(st - tstep[t]);
+                for (int lane = 0; lane < 64; ++lane)
+                    for (int e = 0; e < 8; ++e) {
+                        const int row = row0 + lane % 16, col = 32 * s + 8 * (lane / 16) + e;
+                        if (row >= nrow || col >= ncol) continue;
+                        const int64_t idx = Z.val_ptr[b] + (int64_t)row * ncol + col;
+                        for (int m = 0; m < np; ++m) {
+                            const cd v = (*mats[m])[idx];
+                            V[((((size_t)(2 * m) * pnsteps_ + st) * 64) + lane) * 8 + e] = rne(v.real());
+                            V[((((size_t)(2 * m + 1) * pnsteps_ + st) * 64) + lane) * 8 + e] = rne(v.imag());
+                        }
+                    }
+            }
+        }
+        ptile_box_ = upload(tbox);
+        ptile_row0_ = upload(trow0);
+        ptile_step_ = upload(tstep);
+        ptvals_ = upload(V);
+    }
+
+    void build_product_tiles(const BodyHost &h) {
         const Octree &o = h.oct;
         const NearMatrix &Z = h.near;
         const int KS = split_ ? 32 : 4;
@@ -2210,6 +2290,12 @@ class DeviceBodyT final : public DeviceBody {
     int64_t *near_val_ptr_ = nullptr;
     cx<T> *nA_ = nullptr, *nB_ = nullptr, *nC_ = nullptr;
     uint32_t *h16A_ = nullptr, *h16B_ = nullptr, *h16C_ = nullptr, *h16D_ = nullptr;
+    // bfloat16 tiles of the polynomial preconditioner (build_poly_tiles)
+    int pntiles_ = 0;
+    int64_t pnsteps_ = 0;
+    int *ptile_box_ = nullptr, *ptile_row0_ = nullptr;
+    int64_t *ptile_step_ = nullptr;
+    uint16_t *ptvals_ = nullptr;
     cx<T> *nD_ = nullptr;          // H-row J coefficient of the general block (JMCFIE / CNF)
     char *pin_ = nullptr;          // pinned staging arena of stage_h2d
     size_t pin_cap_ = 0, pin_off_ = 0;

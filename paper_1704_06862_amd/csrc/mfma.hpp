@@ -124,19 +124,21 @@ __global__ void __launch_bounds__(64 * MMA_WAVES)
                 mma_f32(aHi[n], c.y, xm.x);
             }
         } else {
-            // the polynomial preconditioner reads only the hi (bfloat16) part
-            // of the blocks: two matrix-core products per step instead of three
+            // POLY (the polynomial preconditioner): vals holds only the
+            // bfloat16 values, compact planes (A, B, C[, D]) x (re, im), and
+            // each step takes two matrix-core products instead of three
             constexpr bool AHI = POLY;
             const bf16x8 *V = reinterpret_cast<const bf16x8 *>(vals);
             const int64_t pl = nsteps * 64;
             const bf16x8 z8 = {};
-            const bf16x8 arh = V[vi], aih = V[2 * pl + vi], brh = V[4 * pl + vi], bih = V[6 * pl + vi];
-            const bf16x8 crh = V[8 * pl + vi], cih = V[10 * pl + vi];
+            constexpr int H = AHI ? 1 : 2;   // plane stride of the hi parts
+            const bf16x8 arh = V[vi], aih = V[H * pl + vi], brh = V[2 * H * pl + vi], bih = V[3 * H * pl + vi];
+            const bf16x8 crh = V[4 * H * pl + vi], cih = V[5 * H * pl + vi];
             const bf16x8 arl = AHI ? z8 : V[pl + vi], ail = AHI ? z8 : V[3 * pl + vi];
             const bf16x8 brl = AHI ? z8 : V[5 * pl + vi], bil = AHI ? z8 : V[7 * pl + vi];
             const bf16x8 crl = AHI ? z8 : V[9 * pl + vi], cil = AHI ? z8 : V[11 * pl + vi];
-            const bf16x8 drh = GEN ? V[12 * pl + vi] : brh, drl = GEN ? (AHI ? z8 : V[13 * pl + vi]) : brl;
-            const bf16x8 dih = GEN ? V[14 * pl + vi] : bih, dil = GEN ? (AHI ? z8 : V[15 * pl + vi]) : bil;
+            const bf16x8 drh = GEN ? V[6 * H * pl + vi] : brh, drl = GEN ? (AHI ? z8 : V[13 * pl + vi]) : brl;
+            const bf16x8 dih = GEN ? V[7 * H * pl + vi] : bih, dil = GEN ? (AHI ? z8 : V[15 * pl + vi]) : bil;
             auto mma_split = [](f32x4 &c, const bf16x8 &ah, const bf16x8 &al, const bf16x8 &bh, const bf16x8 &bl) {
                 if constexpr (AHI) {
                     (void)al;

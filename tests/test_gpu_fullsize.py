@@ -109,7 +109,7 @@ def test_polynomial_preconditioner_multilevel_fp64():
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_polynomial_preconditioner_batched(prec):
     # 64 right-hand sides: every near product of the polynomial runs on the
-    # matrix cores (FP32 or bf16-split operands, FP32 accumulation)
+    # matrix cores (bfloat16 blocks, bf16-split vectors, FP32 accumulation)
     body = sphere_body(1.0, 2.56, 3)
     mesh = rwg.from_body(body)
     keys = octree.finest_keys(mesh, 0.25, 4)
@@ -123,24 +123,21 @@ def test_polynomial_preconditioner_batched(prec):
         z = ctx.sfmm_precond(x, np.zeros_like(x))
     err = max(rel(z[r], M(x[r])) for r in range(0, 64, 9))
     print(prec, "batched poly rel err", err)
-    if prec == "fp32":
-        assert err < 1e-4
-    else:
-        # bf16-split contexts apply the polynomial with the bfloat16 (hi) part
-        # of the blocks: the reference is the oracle's polynomial applied with
-        # the rounded blocks
-        def bf16(a):
-            def r(v):
-                u = v.astype(np.float32).view(np.uint32).astype(np.uint64)
-                u = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
-                return u.view(np.float32).astype(np.float64)
-            return r(a.real) + 1j * r(a.imag)
-        Dinv = krylov.edge_blocks_inverse(Zn)
-        th = krylov.leja_order(krylov.harmonic_ritz(lambda u: krylov.edge_blocks_apply(Dinv, Zn @ u),
-                                                    krylov.golden_start(Zn.shape[0]), 16))
-        Zh = bf16(Zn)
-        Mh = lambda v: krylov.poly_apply(lambda u: krylov.edge_blocks_apply(Dinv, Zh @ u), th,  # noqa: E731
-                                         krylov.edge_blocks_apply(Dinv, v))
-        err_h = max(rel(z[r], Mh(x[r])) for r in range(0, 64, 9))
-        print("vs the polynomial with rounded blocks", err_h)
-        assert err_h < 1e-4 and err < 2e-2
+    # FP32 and bf16-split contexts apply the polynomial with bfloat16
+    # copies of the blocks: the reference is the oracle's polynomial
+    # applied with the rounded blocks
+    def bf16(a):
+        def r(v):
+            u = v.astype(np.float32).view(np.uint32).astype(np.uint64)
+            u = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+            return u.view(np.float32).astype(np.float64)
+        return r(a.real) + 1j * r(a.imag)
+    Dinv = krylov.edge_blocks_inverse(Zn)
+    th = krylov.leja_order(krylov.harmonic_ritz(lambda u: krylov.edge_blocks_apply(Dinv, Zn @ u),
+                                                krylov.golden_start(Zn.shape[0]), 16))
+    Zh = bf16(Zn)
+    Mh = lambda v: krylov.poly_apply(lambda u: krylov.edge_blocks_apply(Dinv, Zh @ u), th,  # noqa: E731
+                                     krylov.edge_blocks_apply(Dinv, v))
+    err_h = max(rel(z[r], Mh(x[r])) for r in range(0, 64, 9))
+    print("vs the polynomial with rounded blocks", err_h)
+    assert err_h < 1e-4 and err < 2e-2
