@@ -199,9 +199,13 @@ enum { SFMM_SOLVER_GMRES = 0, SFMM_SOLVER_BICGSTAB = 1, SFMM_SOLVER_CGS = 2 };
  *                 values from d FP64 Arnoldi steps from v0[i] =
  *                 exp(2 pi j frac(i (sqrt5-1)/2)), Leja order, product form);
  *                 d near-field products per application (D^-1 fused into
- *                 their epilogue), no reductions.  Default; several
- *                 interfaces with high-contrast or lossy media may need a
- *                 higher degree (poly_degree). */
+ *                 their epilogue), no reductions.  In FP32 and bf16-split
+ *                 contexts these products read the blocks of Z_near rounded
+ *                 to bfloat16 (roots and D^-1 from the FP64 blocks): a fixed
+ *                 operator within about 1e-2 of the FP64 polynomial, half the
+ *                 bytes; the solve still converges on the product itself.
+ *                 Default; several interfaces with high-contrast or lossy
+ *                 media may need a higher degree (poly_degree). */
 enum { SFMM_PRECOND_ILU0 = 0, SFMM_PRECOND_NONE = 1, SFMM_PRECOND_BLOCK_JACOBI = 2, SFMM_PRECOND_POLY = 3 };
 
 typedef struct {
