@@ -283,6 +283,7 @@ class DeviceBodyT final : public DeviceBody {
             }
             regs_.push_back(R);
         }
+        build_receive_all(o);
         HIPCHK(hipEventCreate(&ev0_));
         HIPCHK(hipEventCreate(&ev1_));
         for (auto &e : evs_) HIPCHK(hipEventCreate(&e));
@@ -791,6 +792,38 @@ class DeviceBodyT final : public DeviceBody {
         r.G = G.G[f_];
         return r;
     }
+    // The single-RHS receive of all regions as one launch: every internal
+    // position's contributions (region, entry), region order.  Left unset
+    // (one launch per region) for more than RCV_MAXREG regions or an odd
+    // direction count.
+    void build_receive_all(const Octree &o) {
+        if (f_ < 2 || regs_.empty() || regs_.size() > (size_t)RCV_MAXREG) return;
+        for (const Reg &G : regs_)
+            if (G.K[f_] % 2 || G.ne >= (1 << RCV_REG_SHIFT)) return;
+        std::vector<int> ptr(ne_ + 1, 0);
+        for (const RegionTree &rt : o.regions)
+            for (int p : rt.edge_pos) ++ptr[p + 1];
+        int maxc = 0;
+        for (int p = 0; p < ne_; ++p) {
+            maxc = std::max(maxc, ptr[p + 1]);
+            ptr[p + 1] += ptr[p];
+        }
+        std::vector<int> ent(ptr[ne_]), fill(ptr.begin(), ptr.end() - 1);
+        for (size_t ri = 0; ri < o.regions.size(); ++ri) {
+            const std::vector<int> &pos = o.regions[ri].edge_pos;
+            for (size_t ie = 0; ie < pos.size(); ++ie) ent[fill[pos[ie]]++] = (int)ri << RCV_REG_SHIFT | (int)ie;
+        }
+        std::vector<Rcv1Region<T>> desc;
+        for (const Reg &G : regs_) {
+            desc.push_back(rcv1(G));
+            desc.back().G = nullptr;   // per-batch buffer: passed at launch
+        }
+        rcv_all_.npos = ne_;
+        rcv_all_.maxc = maxc;
+        rcv_all_.ptr = upload(ptr);
+        rcv_all_.ent = upload(ent);
+        rcv_all_.reg = upload(desc);
+    }
     void launch_receive1(const Rcv1Region<T> &a, cx<T> *y) {
         if (a.nwaves <= 0) return;
         const unsigned grid = nblocks(a.nwaves, WAVES);
@@ -801,6 +834,15 @@ class DeviceBodyT final : public DeviceBody {
     // Receive of every region, one launch each: they add into the same
     // entries of y.
     void receive_all(int R, cx<T> *y) {
+        if (R == 1 && rcv_all_.reg) {
+            Rcv1All<T> ra = rcv_all_;
+            for (size_t i = 0; i < regs_.size(); ++i) ra.G[i] = regs_[i].G[f_];
+            const unsigned grid = nblocks((ra.npos + 7) / 8, WAVES);
+            if (gen_) k_receive1_all<T, true><<<grid, WG, 0, stream_>>>(ra, tang_.x, y);
+            else k_receive1_all<T, false><<<grid, WG, 0, stream_>>>(ra, tang_.x, y);
+            LAUNCHCHK();
+            return;
+        }
         for (Reg &G : regs_) receive_region(G, R, y);
     }
     void receive_region(Reg &G, int R, cx<T> *y) {
@@ -2283,6 +2325,7 @@ class DeviceBodyT final : public DeviceBody {
 
     const BodyHost &h_;
     hipStream_t stream_;
+    Rcv1All<T> rcv_all_{};   // single-RHS receive of all regions in one launch
     int ne_ = 0, nb_ = 0, f_ = 0;
     std::array<int, 9> colour_ptr_{};
     int *pos_ = nullptr, *bstart_ = nullptr;

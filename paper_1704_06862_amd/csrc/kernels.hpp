@@ -1389,9 +1389,8 @@ __global__ void __launch_bounds__(WG) k_translate_grp(int K, int R, const int *_
 // tested as the N-MFIE and N-EFIE rows minus the T-EFIE / et and et T-MFIE
 // rows.
 template <typename T, bool NRM>
-__device__ __forceinline__ void receive_store(cx<T> *y, int64_t iE, int64_t iH, T s, cx<T> aE, cx<T> aH, cx<T> nE,
-                                              cx<T> nH, cx<T> inv_et, T tang) {
-    cx<T> ye = y[iE], yh = y[iH];
+__device__ __forceinline__ void receive_add(cx<T> &ye, cx<T> &yh, T s, cx<T> aE, cx<T> aH, cx<T> nE, cx<T> nH,
+                                            cx<T> inv_et, T tang) {
     if (!NRM) {
         const cx<T> hh = cmul(aH, inv_et);
         ye.x += s * aE.x;
@@ -1406,6 +1405,12 @@ __device__ __forceinline__ void receive_store(cx<T> *y, int64_t iE, int64_t iH, 
         yh.x += ts * aH.x - nE.x;
         yh.y += ts * aH.y - nE.y;
     }
+}
+template <typename T, bool NRM>
+__device__ __forceinline__ void receive_store(cx<T> *y, int64_t iE, int64_t iH, T s, cx<T> aE, cx<T> aH, cx<T> nE,
+                                              cx<T> nH, cx<T> inv_et, T tang) {
+    cx<T> ye = y[iE], yh = y[iH];
+    receive_add<T, NRM>(ye, yh, s, aE, aH, nE, nH, inv_et, tang);
     y[iE] = ye;
     y[iH] = yh;
 }
@@ -1486,21 +1491,17 @@ struct Rcv1Region {
     const cx<T> *G;
 };
 
-// One region per launch: the regions' receives add into the same entries
-// of y, so they stay ordered launches.
+// This lane's share (directions 2 sub, 2 sub + 1, + 16 ...) of the receive
+// sums of entry ie of a region's edge list.
+// Gf: the region's incoming patterns at the finest level.
 template <typename T, bool NRM>
-__global__ void __launch_bounds__(WG) k_receive1(const Rcv1Region<T> rg, T tang, cx<T> *__restrict__ y) {
-    const int lane = threadIdx.x & 63;
-    const int sub = lane & 7;
-    const int w = blockIdx.x * WAVES + (threadIdx.x >> 6);
-    if (w >= rg.nwaves) return;          // uniform over the wavefront
-    const int ne = rg.ne, K = rg.K;
-    const int ie = w * 8 + (lane >> 3);
-    cx<T> aE = {0, 0}, aH = {0, 0}, nE = {0, 0}, nH = {0, 0};
-    if (ie < ne) {
+__device__ __forceinline__ void receive1_sums(const Rcv1Region<T> &rg, const cx<T> *Gf, int ie, int sub, cx<T> &aE,
+                                              cx<T> &aH, cx<T> &nE, cx<T> &nH) {
+    const int K = rg.K;
+    {
         const cx<T> *Rp = rg.tab + (size_t)ie * 2 * K;
         const cx<T> *Np = NRM ? rg.nx + (size_t)ie * 2 * K : nullptr;
-        const cx<T> *g = rg.G + (size_t)rg.edge_box[ie] * 2 * K;
+        const cx<T> *g = Gf + (size_t)rg.edge_box[ie] * 2 * K;
         const bool cj = rg.conj != 0;
 #pragma unroll 3
         for (int k = 2 * sub; k < K; k += 16) {
@@ -1539,6 +1540,11 @@ __global__ void __launch_bounds__(WG) k_receive1(const Rcv1Region<T> rg, T tang,
             }
         }
     }
+}
+
+// the eight lanes' partial sums of an entry combined by three shuffles
+template <typename T, bool NRM>
+__device__ __forceinline__ void receive1_reduce(cx<T> &aE, cx<T> &aH, cx<T> &nE, cx<T> &nH) {
 #pragma unroll
     for (int m = 1; m < 8; m <<= 1) {
         aE.x += __shfl_xor(aE.x, m, 64);
@@ -1552,9 +1558,72 @@ __global__ void __launch_bounds__(WG) k_receive1(const Rcv1Region<T> rg, T tang,
             nH.y += __shfl_xor(nH.y, m, 64);
         }
     }
-    if (ie < ne && sub == 0) {
+}
+
+// One region per launch (regions that add into the same entries of y run as
+// ordered launches; k_receive1_all takes all of them in one).
+template <typename T, bool NRM>
+__global__ void __launch_bounds__(WG) k_receive1(const Rcv1Region<T> rg, T tang, cx<T> *__restrict__ y) {
+    const int lane = threadIdx.x & 63;
+    const int sub = lane & 7;
+    const int w = blockIdx.x * WAVES + (threadIdx.x >> 6);
+    if (w >= rg.nwaves) return;          // uniform over the wavefront
+    const int ie = w * 8 + (lane >> 3);
+    cx<T> aE = {0, 0}, aH = {0, 0}, nE = {0, 0}, nH = {0, 0};
+    if (ie < rg.ne) receive1_sums<T, NRM>(rg, rg.G, ie, sub, aE, aH, nE, nH);
+    receive1_reduce<T, NRM>(aE, aH, nE, nH);
+    if (ie < rg.ne && sub == 0) {
         const int p = rg.edge_pos[ie];
         receive_store<T, NRM>(y, 2 * p, 2 * p + 1, (T)rg.edge_sign[ie], aE, aH, nE, nH, rg.inv_et, tang);
+    }
+}
+
+// Receive of every region in one launch (one RHS).  Eight lanes per internal
+// position p, as above; the position's contributions (one per region whose
+// edge list holds its edge, in region order) are added to y[p] in registers,
+// in the same order and arithmetic as one launch per region, and y is read
+// and written once.
+constexpr int RCV_MAXREG = 8;          // regions the single launch takes
+constexpr int RCV_REG_SHIFT = 28;      // ent = region << RCV_REG_SHIFT | entry
+template <typename T>
+struct Rcv1All {
+    int npos, maxc;                      // positions; most contributions of one position
+    const int *ptr, *ent;                // [npos + 1] CSR of contributions; region and entry
+    const Rcv1Region<T> *reg;            // region descriptors (device memory; their G is unset)
+    const cx<T> *G[RCV_MAXREG];          // incoming finest-level patterns of each region (per batch
+                                         // buffers, so set at every launch)
+};
+
+template <typename T, bool NRM>
+__global__ void __launch_bounds__(WG) k_receive1_all(const Rcv1All<T> ra, T tang, cx<T> *__restrict__ y) {
+    const int lane = threadIdx.x & 63;
+    const int sub = lane & 7;
+    const int w = blockIdx.x * WAVES + (threadIdx.x >> 6);
+    if (w * 8 >= ra.npos) return;        // uniform over the wavefront
+    const int p = w * 8 + (lane >> 3);
+    const bool live = p < ra.npos;
+    const int q0 = live ? ra.ptr[p] : 0, nq = live ? ra.ptr[p + 1] - q0 : 0;
+    cx<T> ye = {0, 0}, yh = {0, 0};
+    if (live) {
+        ye = y[2 * (int64_t)p];
+        yh = y[2 * (int64_t)p + 1];
+    }
+    for (int c = 0; c < ra.maxc; ++c) {  // uniform trip count: the shuffles see every lane
+        cx<T> aE = {0, 0}, aH = {0, 0}, nE = {0, 0}, nH = {0, 0};
+        const int e = c < nq ? ra.ent[q0 + c] : 0;
+        const int r = e >> RCV_REG_SHIFT, ie = e & ((1 << RCV_REG_SHIFT) - 1);
+        const cx<T> *Gr = ra.G[0];
+#pragma unroll
+        for (int i = 1; i < RCV_MAXREG; ++i)
+            if (r == i) Gr = ra.G[i];
+        if (c < nq) receive1_sums<T, NRM>(ra.reg[r], Gr, ie, sub, aE, aH, nE, nH);
+        receive1_reduce<T, NRM>(aE, aH, nE, nH);
+        if (c < nq)
+            receive_add<T, NRM>(ye, yh, (T)ra.reg[r].edge_sign[ie], aE, aH, nE, nH, ra.reg[r].inv_et, tang);
+    }
+    if (live && sub == 0) {
+        y[2 * (int64_t)p] = ye;
+        y[2 * (int64_t)p + 1] = yh;
     }
 }
 
