@@ -149,6 +149,31 @@ def test_invalid_arguments():
             ctx.sfmm_near_rows([10 ** 6])
 
 
+def test_empty_and_negative_batches_are_refused():
+    # the C ABI itself (below the binding's shape checks): a batch of zero or
+    # a negative count of right-hand sides is SFMM_E_INVALID_ARG, before any
+    # device work is looked for
+    import ctypes
+    b = sphere_body(0.3, 4.0, 1)
+    L = sfmm.lib()
+    with sfmm.Context([b], device=-1) as ctx:
+        n = ctx.sfmm_num_unknowns()
+        x = np.zeros((1, n), complex)
+        y = np.zeros_like(x)
+        px, py = x.ctypes.data_as(ctypes.c_void_p), y.ctypes.data_as(ctypes.c_void_p)
+        ang = np.zeros((1, 2))
+        pa = ang.ctypes.data_as(ctypes.c_void_p)
+        sig = np.zeros((1, 1, 2))
+        ps = sig.ctypes.data_as(ctypes.c_void_p)
+        for nr in (0, -1):
+            assert L.sfmm_matvec(ctx.ctx, 0, nr, px, py, 0, sfmm.PART_ALL) == 1
+            assert L.sfmm_precond(ctx.ctx, 0, nr, px, py, 0) == 1
+            assert L.sfmm_solve(ctx.ctx, 0, nr, px, py, None, None, 0) == 1
+            assert L.sfmm_planewave_rhs(ctx.ctx, 0, nr, pa, None, px, 0) == 1
+            assert L.sfmm_rcs(ctx.ctx, 0, nr, px, 1, pa, ps, 0) == 1
+            assert L.sfmm_rcs(ctx.ctx, 0, 1, px, nr, pa, ps, 0) == 1
+
+
 def test_guess_entry_points_refuse_bad_use():
     b = sphere_body(0.3, 4.0, 1)
     with sfmm.Context([b], device=-1) as ctx:
