@@ -831,8 +831,9 @@ class DeviceBodyT final : public DeviceBody {
         else k_receive1<T, false><<<grid, WG, 0, stream_>>>(a, tang_.x, y);
         LAUNCHCHK();
     }
-    // Receive of every region, one launch each: they add into the same
-    // entries of y.
+    // Receive of every region: one launch for all of them at one RHS (when
+    // the merged table was built), otherwise one launch each, in region
+    // order (they add into the same entries of y).
     void receive_all(int R, cx<T> *y) {
         if (R == 1 && rcv_all_.reg) {
             Rcv1All<T> ra = rcv_all_;
