@@ -1071,7 +1071,8 @@ class DeviceBodyT final : public DeviceBody {
     void upward_mma(Reg &G, int l, int R) {
         const int nt = (R + 15) / 16;
         const int nth_c = G.nth[l], nph_c = G.nph[l], nth_p = G.nth[l - 1], nph_p = G.nph[l - 1];
-        const unsigned g1 = (unsigned)G.nbox[l] * 2, g2 = (unsigned)G.nbox[l - 1] * 2 * nth_p;
+        const int ipb = mma_rows_per_wg(nph_p);
+        const unsigned g1 = (unsigned)G.nbox[l] * 2, g2 = (unsigned)G.nbox[l - 1] * 2 * ((nth_p + ipb - 1) / ipb);
 #define SFMM_UPM(NT_)                                                                                                \
     k_up_theta_mma<NT_><<<g1, 256, 0, stream_>>>(R, nth_c, nph_c, nth_p, G.ipA[l], G.ipB[l], G.S[l], G.tmp);         \
     LAUNCHCHK();                                                                                                     \
@@ -1088,7 +1089,8 @@ class DeviceBodyT final : public DeviceBody {
     void downward_mma(Reg &G, int l, int R) {
         const int nt = (R + 15) / 16;
         const int nth_c = G.nth[l], nph_c = G.nph[l], nth_p = G.nth[l - 1], nph_p = G.nph[l - 1];
-        const unsigned g1 = (unsigned)G.nbox[l] * 2 * nth_p, g2 = (unsigned)G.nbox[l] * 2;
+        const int ipb = mma_rows_per_wg(nph_c);
+        const unsigned g1 = (unsigned)G.nbox[l] * 2 * ((nth_p + ipb - 1) / ipb), g2 = (unsigned)G.nbox[l] * 2;
 #define SFMM_DNM(NT_)                                                                                              \
     k_dn_phi_mma<NT_><<<g1, 256, 0, stream_>>>(R, nth_p, nph_p, nph_c, G.Ddn[l], G.parent[l], G.slot[l],            \
                                                G.G[l - 1], G.tmp);                                                 \

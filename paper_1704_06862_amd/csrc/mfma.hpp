@@ -531,6 +531,14 @@ __global__ void __launch_bounds__(256) k_up_theta_mma(int R, int nth_c, int nph_
 // tile of parent phi samples J; K runs over the children's phi samples, so
 // the sum over children accumulates inside the matrix-core accumulators.
 // Dsh[slot][I][J][j] = D[J][j] shift_up[slot][I nph_p + J] (complex).
+// With one or two 16-row tiles of J per theta row, a workgroup takes
+// mma_rows_per_wg(nph) theta rows (one per group of waves), so that all four
+// waves work.
+__host__ __device__ inline int mma_rows_per_wg(int nph) {
+    const int ntl = (nph + 15) / 16;
+    return ntl == 1 ? 4 : ntl == 2 ? 2 : 1;
+}
+
 template <int NT>
 __global__ void __launch_bounds__(256) k_up_phi_mma(int R, int nth_p, int nph_p, int nph_c,
                                                     const cx<float> *__restrict__ Dsh,
@@ -538,12 +546,14 @@ __global__ void __launch_bounds__(256) k_up_phi_mma(int R, int nth_p, int nph_p,
                                                     const int *__restrict__ child_idx,
                                                     const int *__restrict__ child_slot,
                                                     const cx<float> *__restrict__ tmp, cx<float> *__restrict__ Sp) {
+    const int ipb = mma_rows_per_wg(nph_p), nib = (nth_p + ipb - 1) / ipb, tpw = 4 / ipb;
     int bid = blockIdx.x;
-    const int I = bid % nth_p;
-    bid /= nth_p;
+    const int ib = bid % nib;
+    bid /= nib;
     const int comp = bid % 2, P = bid / 2;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
-    if (16 * wave >= nph_p) return;
+    const int wave0 = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+    const int wave = wave0 % tpw, I = ib * ipb + wave0 / tpw;   // tile of J, theta row
+    if (16 * wave >= nph_p || I >= nth_p) return;
     const int J = 16 * wave + lr;
     f32x4 re[NT], im[NT];
 #pragma unroll
@@ -591,12 +601,14 @@ __global__ void __launch_bounds__(256) k_dn_phi_mma(int R, int nth_p, int nph_p,
                                                     const int *__restrict__ parent,
                                                     const int *__restrict__ child_slot,
                                                     const cx<float> *__restrict__ Gp, cx<float> *__restrict__ tmp) {
+    const int ipb = mma_rows_per_wg(nph_c), nib = (nth_p + ipb - 1) / ipb, tpw = 4 / ipb;
     int bid = blockIdx.x;
-    const int I = bid % nth_p;
-    bid /= nth_p;
+    const int ib = bid % nib;
+    bid /= nib;
     const int comp = bid % 2, c = bid / 2;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
-    if (16 * wave >= nph_c) return;
+    const int wave0 = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+    const int wave = wave0 % tpw, I = ib * ipb + wave0 / tpw;   // tile of j, theta row
+    if (16 * wave >= nph_c || I >= nth_p) return;
     const int j = 16 * wave + lr;
     const cx<float> *a_row = Dsh + (((int64_t)child_slot[c] * nth_p + I) * nph_c + j) * nph_p;
     const cx<float> *g = Gp + (((int64_t)parent[c] * 2 + comp) * nth_p * nph_p + (int64_t)I * nph_p) * R;
