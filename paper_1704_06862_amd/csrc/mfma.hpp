@@ -485,7 +485,7 @@ __global__ void __launch_bounds__(256) k_up_theta_mma(int R, int nth_c, int nph_
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
     const int h = nph_c / 2, Kc = nth_c * nph_c;
     const int nmt = (2 * nth_p + 15) / 16, nks = (2 * nth_c + 3) / 4;
-    for (int t = threadIdx.x; t < IMT * IKS * 64; t += 256) {
+    for (int t = threadIdx.x; t < nmt * IKS * 64; t += 256) {   // only the row tiles in use are read
         const int l = t & 63, ms = t >> 6, mt = ms / IKS, st = ms % IKS;
         Wop[t] = theta_w(A, B, 16 * mt + (l & 15), 4 * st + (l >> 4), nth_p, nth_c, nth_c, false);
     }
@@ -655,7 +655,7 @@ __global__ void __launch_bounds__(256) k_dn_theta_mma(int R, int nth_c, int nph_
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
     const int h = nph_c / 2, Kc = nth_c * nph_c;
     const int nmt = (2 * nth_c + 15) / 16, nks = (2 * nth_p + 3) / 4;
-    for (int t = threadIdx.x; t < IMT * IKS * 64; t += 256) {
+    for (int t = threadIdx.x; t < nmt * IKS * 64; t += 256) {   // only the row tiles in use are read
         const int l = t & 63, ms = t >> 6, mt = ms / IKS, st = ms % IKS;
         Wop[t] = theta_w(A, B, 16 * mt + (l & 15), 4 * st + (l >> 4), nth_c, nth_p, nth_c, true);
     }
