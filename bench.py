@@ -92,6 +92,9 @@ def parse():
                    help="MiB of a plain device copy run after the measurements, to scale HBM byte counters")
     p.add_argument("--product-only", action="store_true",
                    help="only the timed single-RHS products (for counter runs)")
+    p.add_argument("--product-rhs", type=int, default=1,
+                   help="with --product-only: right-hand sides per timed product (1-64; counter runs of "
+                        "the batched kernels)")
     p.add_argument("--no-graphs", action="store_true",
                    help="launch the products kernel by kernel instead of replaying captured graphs")
     p.add_argument("--no-coated", action="store_true",
@@ -487,6 +490,10 @@ def main():
     stream = torch.cuda.current_stream()
     ctx.sfmm_set_stream(stream.cuda_stream)
     assert xh.shape[1] == n
+    if args.product_rhs != 1:
+        if not args.product_only or not 1 <= args.product_rhs <= 64:
+            sys.exit("--product-rhs takes 1..64 and goes with --product-only")
+        xh = random_complex_vector(n, args.product_rhs, seed=99)
     x = torch.from_numpy(xh).to("cuda")
     y = torch.zeros_like(x)
     for _ in range(args.warmup):
@@ -513,7 +520,8 @@ def main():
             for _ in range(3):
                 c.copy_(a)
             torch.cuda.synchronize()
-        print(json.dumps({"ms_per_step": ms, "hip_event_ms": ev_ms, "steps": args.steps, "warmup": args.warmup}))
+        print(json.dumps({"ms_per_step": ms, "hip_event_ms": ev_ms, "steps": args.steps, "warmup": args.warmup,
+                          "rhs": args.product_rhs}))
         return
 
     # batched products (outside the timed region): unknowns x RHS per second
