@@ -464,6 +464,8 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.product_rhs != 1 and (not args.product_only or not 1 <= args.product_rhs <= 64):
+        sys.exit("--product-rhs takes 1..64 and goes with --product-only")
     import torch
 
     from paper_1704_06862_amd import sfmm
@@ -491,8 +493,6 @@ def main():
     ctx.sfmm_set_stream(stream.cuda_stream)
     assert xh.shape[1] == n
     if args.product_rhs != 1:
-        if not args.product_only or not 1 <= args.product_rhs <= 64:
-            sys.exit("--product-rhs takes 1..64 and goes with --product-only")
         xh = random_complex_vector(n, args.product_rhs, seed=99)
     x = torch.from_numpy(xh).to("cuda")
     y = torch.zeros_like(x)
