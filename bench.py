@@ -462,7 +462,7 @@ def cylinder_leg(sfmm, torch, stream, n_ang, every, plain_stride):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "one GPU only: the path runs on a single MI355X, --gpus must be 1"}))
         sys.exit(2)
     if args.product_rhs != 1 and (not args.product_only or not 1 <= args.product_rhs <= 64):
         sys.exit("--product-rhs takes 1..64 and goes with --product-only")
