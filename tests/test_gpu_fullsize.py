@@ -7,6 +7,8 @@ by one and the test compares those entries of the GPU product, in the launch
 configuration that bench.py times (FP32, 0.25-wavelength boxes, 5 levels,
 3-digit excess-bandwidth truncation)."""
 
+import os
+
 import numpy as np
 import pytest
 
@@ -18,6 +20,7 @@ pytestmark = pytest.mark.gpu
 sfmm = pytest.importorskip("paper_1704_06862_amd.sfmm")
 
 BENCH_OPTS = dict(finest_box=0.25, n_levels=5, digits=3.0, extra_multipoles=0, precision=0)
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def rel(a, b):
@@ -69,6 +72,36 @@ def test_bench_configuration_sampled_rows(bench_rows, prec):
     assert eb_near < (1e-5 if prec == "fp32" else 5e-5)
     assert eb_full < 1e-3
     assert e_bs < (1e-5 if prec == "fp32" else 5e-5)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_bench_configuration_stored_oracle_rows(prec):
+    # 200 stored oracle rows (E and H rows of 100 seeded edges, written by
+    # tests/golden/make_sphere_rows.py) applied to the benchmark's single
+    # right-hand side and to a 64-RHS batch: the product in the launch
+    # configuration bench.py times, within 1e-3 for every right-hand side
+    path = os.path.join(GOLDEN, "sphere61440_rows.txt")
+    with open(path) as f:
+        f.readline()
+        edges = np.array([int(v) for v in f.readline().split()[2:]])
+    d = np.loadtxt(path)
+    ref = d[:, 0::2] + 1j * d[:, 1::2]                  # [2 * n_edges, 65]
+    body = sphere_body(2.0, 2.56, 5)
+    opts = dict(BENCH_OPTS, precision=sfmm.PREC_FP32 if prec == "fp32" else sfmm.PREC_BF16_SPLIT)
+    print("setup bench configuration", prec, flush=True)
+    with sfmm.Context([body], **opts) as ctx:
+        n = ctx.sfmm_num_unknowns()
+        ne = n // 2
+        assert n == 61440 and len(edges) == 100 and ref.shape == (200, 65)
+        x = np.concatenate([random_complex_vector(n, 1, seed=1234), random_complex_vector(n, 64, seed=77)])
+        y1 = ctx.sfmm_matvec(x[:1].copy(), np.zeros_like(x[:1]))
+        yb = ctx.sfmm_matvec(x[1:].copy(), np.zeros_like(x[1:]))
+    y = np.concatenate([y1, yb])
+    pick = np.concatenate([edges, ne + edges])
+    err = [rel(y[r][pick], ref[:, r]) for r in range(65)]
+    print(prec, "stored oracle rows: single RHS", err[0], "| 64 RHS max", max(err[1:]), "median",
+          np.median(err[1:]))
+    assert max(err) < 1e-3
 
 
 def test_ilu_preconditioner_multilevel_fp64():
