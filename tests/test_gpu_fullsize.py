@@ -104,6 +104,37 @@ def test_bench_configuration_stored_oracle_rows(prec):
     assert max(err) < 1e-3
 
 
+@pytest.mark.parametrize("form", ["jmcfie", "cnf"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_bench_sphere_combined_formulations_stored_oracle_rows(form, prec):
+    # the JMCFIE and CNF products of the benchmark's sphere and tree: 100
+    # stored oracle rows each (J and M test rows of 50 seeded edges, written
+    # by tests/golden/make_sphere_combined_rows.py) applied to the single
+    # right-hand side and to a 64-RHS batch, within 1e-3 for every one
+    path = os.path.join(GOLDEN, f"sphere61440_{form}_rows.txt")
+    with open(path) as f:
+        f.readline()
+        edges = np.array([int(v) for v in f.readline().split()[2:]])
+    d = np.loadtxt(path)
+    ref = d[:, 0::2] + 1j * d[:, 1::2]                  # [2 * n_edges, 65]
+    body = sphere_body(2.0, 2.56, 5)
+    opts = dict(BENCH_OPTS, precision=sfmm.PREC_FP32 if prec == "fp32" else sfmm.PREC_BF16_SPLIT,
+                formulation=sfmm.FORM_JMCFIE if form == "jmcfie" else sfmm.FORM_CNF)
+    print("setup bench configuration", form, prec, flush=True)
+    with sfmm.Context([body], **opts) as ctx:
+        n = ctx.sfmm_num_unknowns()
+        ne = n // 2
+        assert n == 61440 and len(edges) == 50 and ref.shape == (100, 65)
+        x = np.concatenate([random_complex_vector(n, 1, seed=1234), random_complex_vector(n, 64, seed=77)])
+        y1 = ctx.sfmm_matvec(x[:1].copy(), np.zeros_like(x[:1]))
+        yb = ctx.sfmm_matvec(x[1:].copy(), np.zeros_like(x[1:]))
+    y = np.concatenate([y1, yb])
+    pick = np.concatenate([edges, ne + edges])
+    err = [rel(y[r][pick], ref[:, r]) for r in range(65)]
+    print(form, prec, "stored oracle rows: single RHS", err[0], "| 64 RHS max", max(err[1:]))
+    assert max(err) < 1e-3
+
+
 def test_ilu_preconditioner_multilevel_fp64():
     body = sphere_body(1.0, 2.56, 3)
     mesh = rwg.from_body(body)
