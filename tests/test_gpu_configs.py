@@ -228,3 +228,34 @@ def test_ellipsoid_batch_body_sampled_oracle_rows(form):
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     print("sampled rows rel err", err)
     assert err < 1e-3
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_ellipsoid_batch_body_rcs_vs_stored_oracle(prec):
+    # body 20 of the seeded 48-ellipsoid batch (eps_r 8.21, 15,360 unknowns)
+    # with the batch's 8 incidences (theta_i = 180 deg * i / 7, phi = 0) as
+    # one batch under JMCFIE in the batch's tree, GMRES(50) to 1e-4: every
+    # bistatic theta-theta cut within 0.2 dB of the oracle's dense-LU JMCFIE
+    # solution (tests/golden/ellipsoid20_rcs.txt, written by the oracle alone)
+    import os
+    from workloads import ellipsoid_batch
+
+    gold = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "ellipsoid20_rcs.txt"))
+    assert gold.shape == (181, 9)
+    b = ellipsoid_batch(48)[20]
+    ang = np.stack([np.deg2rad(180.0 * np.arange(8) / 7), np.zeros(8)], 1)
+    p = sfmm.PREC_FP32 if prec == "fp32" else sfmm.PREC_BF16_SPLIT
+    print("setup ellipsoid 20 jmcfie", prec, flush=True)
+    with sfmm.Context([b], formulation=sfmm.FORM_JMCFIE, finest_box=0.25, digits=3.0, precision=p,
+                      gmres_restart=50, tol=1e-4, max_iters=1000) as ctx:
+        n = ctx.sfmm_num_unknowns()
+        assert n == 15360
+        rhs = ctx.sfmm_planewave_rhs(ang, np.zeros((8, n), dtype=complex))
+        x = np.zeros_like(rhs)
+        info = ctx.sfmm_solve(rhs, x)
+        s = ctx.sfmm_rcs(x, np.stack([THETA, 0 * THETA], 1))[:, :, 0]
+    assert all(i["converged"] and i["true_residual"] <= 1e-4 for i in info)
+    stats = [db_stats(s[i], gold[:, 1 + i]) for i in range(8)]
+    print(prec, "iterations", [i["iterations"] for i in info], "RMS / max dB per incidence",
+          [(round(r, 3), round(m, 3)) for r, m in stats])
+    assert max(m for _, m in stats) < 0.2
