@@ -1,8 +1,10 @@
-"""Pins of the stored oracle reference tests/golden/sphere15360_rcs.txt (written
-by tests/golden/make_sphere_rcs.py from the oracle alone): the dense FP64
-PMCHWT solution of the 15,360-unknown sphere scatters like the Mie series of
-the same sphere within the discretisation error of an s = 4 icosphere, and the
-cuts meet where they must (theta = 0 and 180 deg lie on both planes)."""
+"""Pins of the stored oracle references under tests/golden (each written from
+the oracle alone by the script beside it): the dense FP64 PMCHWT solution of
+the 15,360-unknown sphere scatters like the Mie series of the same sphere
+within the discretisation error of an s = 4 icosphere, and its cuts meet where
+they must (theta = 0 and 180 deg lie on both planes); the coated-sphere sweep
+against the coated series and its symmetry; the ellipsoid's cuts against the
+body's mirror symmetry."""
 
 import os
 
@@ -54,3 +56,22 @@ def test_stored_coated_sphere_sweep_against_mie_and_symmetry():
     # backscatter (theta = theta_i) is the same for every incidence on a sphere
     back = np.array([d[int(round(180.0 * i / 63)), 1 + i] for i in range(64)])
     assert np.std(10 * np.log10(back)) < 0.15
+
+
+def test_stored_ellipsoid_rcs_symmetry_and_forward_lobe():
+    # tests/golden/ellipsoid20_rcs.txt (dense-LU JMCFIE solutions of ellipsoid
+    # 20 of the batch, written by tests/golden/make_ellipsoid_rcs.py from the
+    # oracle alone).  The ellipsoid is symmetric under z -> -z, so the cut of
+    # the incidence from theta equals, mirrored in theta, the cut of the
+    # incidence from 180 deg - theta; and for incidence along -z the
+    # forward direction (theta = 180 deg) carries the largest lobe
+    d = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "ellipsoid20_rcs.txt"))
+    assert d.shape == (181, 9)
+    assert np.allclose(d[:, 0], np.arange(181.0))
+    cuts = d[:, 1:]
+    assert np.all(np.isfinite(cuts)) and np.all(cuts > 0)
+    for i in range(4):
+        assert np.allclose(cuts[:, i], cuts[::-1, 7 - i], rtol=1e-8, atol=0)
+    assert np.argmax(cuts[:, 0]) == 180 and np.argmax(cuts[:, 7]) == 0
+    # incidences at different angles scatter differently (no repeated column)
+    assert np.min([np.abs(cuts[:, i] - cuts[:, i + 1]).max() / cuts[:, i].max() for i in range(7)]) > 1e-2
